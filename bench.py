@@ -1,0 +1,290 @@
+"""Benchmark: pressure-Poisson solve to 1e-8 and matrix-free apply throughput
+on one MI355X, for the 3D uniform level-7 workload (128^3 trilinear hexes,
+2,146,689 nodes, phase field of 8 seeded tanh drops, Cn = 0.01, density ratio
+1000, right-hand side b = M f with f a seeded sum of 8 cosine modes).
+
+One step = set the phase field and solve the pressure system to a relative
+residual of 1e-8 from x0 = 0 (exact-diagonal set-up, Jacobi-PCG iterations,
+FP64 true-residual check), all inputs resident in HBM.
+
+Prints one JSON line.  `python bench.py --profile-run` runs a short, fixed
+sequence (a copy of known size, applies, one solve) meant to be wrapped by
+rocprofv3.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import chns_inputs as ci  # noqa: E402
+
+LEVEL = 7
+CN = 0.01
+RHO_P, RHO_M = 1.0, 1e-3
+METRIC = "pressure-solve time to 1e-8 rel. residual & GDoF/s apply, plain vs learned+mixed"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (fma) x 2.4 GHz
+FP32_PEAK_TFLOPS = 78.6   # same lane count without packed FP32 (packed math is not used)
+# algorithmic work of one trilinear-hex pressure-Poisson leaf, sum-factorised:
+# phase field to 8 Gauss points (72), 8 x (clamp 2 + fma 2 + reciprocal 9),
+# 3 x (differences 4 + 2 transforms 24 + coefficient sums/products 8 + 2
+# transforms 24 + scatter 8)
+PP_FLOPS_PER_LEAF = 72 + 8 * 13 + 3 * (4 + 24 + 8 + 24 + 8)
+PP_BYTES_PER_DOF = {8: 24, 4: 12}   # x and phi~ read once, y written once
+
+
+def src_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("apply.hip",):
+        with open(os.path.join(ROOT, "paper_2107_05123_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def setup(torch):
+    from paper_2107_05123_amd import Context, Mesh
+    t0 = time.time()
+    mesh = Mesh(dim=3, min_level=LEVEL, max_level=LEVEL, rule="uniform")
+    t_mesh = time.time() - t0
+    x_unit = ci.unit_coords(mesh.node_coords(), LEVEL)
+    c, r = ci.drops(0)
+    phi = ci.phi_drops(x_unit, c, r, CN)
+    amps, waves = ci.rhs_modes(1)
+    f = ci.rhs_field(x_unit, amps, waves)
+    ctx = Context(mesh, Cn=CN, rho_plus=RHO_P, rho_minus=RHO_M)
+    dev = lambda a, dt=torch.float64: torch.tensor(a, dtype=dt, device="cuda")
+    phi_d = dev(phi)
+    ctx.set_phase_field(phi_d)
+    b = ctx.apply(ctx.MASS, dev(f))
+    torch.cuda.synchronize()
+    return mesh, ctx, phi_d, b, x_unit, phi, f, t_mesh
+
+
+def time_applies(torch, ctx, x, n_warm=10, n_rep=100):
+    """Median wall time of one apply from HIP events on the current stream."""
+    for _ in range(n_warm):
+        ctx.apply(ctx.PRESSURE, x)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_rep)]
+    y = torch.empty_like(x)
+    for a, b in ev:
+        a.record()
+        ctx.apply(ctx.PRESSURE, x, y)
+        b.record()
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+
+def kernel_avg_ms(torch, ctx, x, tag, n_rep=50):
+    """Average duration of one tagged launch group measured with HIP events
+    that the library records on the stream it launches on."""
+    y = torch.empty_like(x)
+    ctx.apply(ctx.PRESSURE, x, y)
+    torch.cuda.synchronize()
+    ctx.profile_reset()
+    ctx.profile(True)
+    for _ in range(n_rep):
+        ctx.apply(ctx.PRESSURE, x, y)
+    torch.cuda.synchronize()
+    ms, n = ctx.profile_read(tag)
+    comb_ms, comb_n = ctx.profile_read("combine")
+    ctx.profile(False)
+    ctx.profile_reset()
+    return ms / max(n, 1), comb_ms / max(comb_n, 1)
+
+
+def solve_once(torch, ctx, phi_d, b, **kw):
+    ctx.set_phase_field(phi_d)
+    x = torch.zeros_like(b)
+    x, st = ctx.solve_pressure(b, x, rtol=1e-8, **kw)
+    return x, st
+
+
+def cpu_baseline(phi_nodes_lex, f_nodes_lex, gpu_iters):
+    """Oracle timed on this host: mesh + CSR assembly + a bounded number of
+    Jacobi-PCG iterations on the same 128^3 problem, scaled to the iteration
+    count of the full solve."""
+    from oracle import fem, krylov, mesh as om
+    t0 = time.time()
+    m = om.uniform(3, LEVEL)
+    side = 1 << LEVEL
+    oc = m.indep_coords()
+    # oracle node order -> lexicographic index (x fastest), the order of the inputs
+    lex = oc[:, 0] + (side + 1) * (oc[:, 1] + (side + 1) * oc[:, 2])
+    phi_o = phi_nodes_lex[lex]
+    A = fem.pp_matrix(m, phi_o, RHO_P, RHO_M)
+    M = fem.mass_matrix(m)
+    b = M @ f_nodes_lex[lex]
+    t_asm = time.time() - t0
+    k_it = 20
+    t1 = time.time()
+    dinv = 1.0 / A.diagonal()
+    x, it, hist = krylov.pcg(A, b, rtol=1e-30, max_it=k_it, M_inv_diag=dinv, singular=True)
+    t_it = (time.time() - t1) / k_it
+    t_spmv0 = time.time()
+    for _ in range(5):
+        A @ b
+    t_spmv = (time.time() - t_spmv0) / 5
+    est = t_asm + t_it * gpu_iters
+    return {
+        "value": est, "unit": "s", "cores": 1, "kind": "oracle",
+        "sample": (f"oracle mesh + CSR assembly ({t_asm:.1f} s) and {k_it} Jacobi-PCG iterations "
+                   f"({t_it * 1e3:.0f} ms each) on the full 128^3 problem, scaled to the {gpu_iters} iterations "
+                   f"the solve needs; CSR SpMV {m.n_indep / t_spmv / 1e9:.4f} GDoF/s single-threaded scipy"),
+        "spmv_gdof_s": m.n_indep / t_spmv / 1e9,
+        "assembly_s": t_asm,
+        "pcg_iter_s": t_it,
+    }
+
+
+def load_traffic(tag, launches_ms):
+    """HBM traffic per launch from a stored rocprofv3 PMC summary, only if it
+    was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{tag}_pmc.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("src_hash") != src_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def profile_run(torch, with_solve=True):
+    """Fixed sequence for rocprofv3: copy of known size, FP64/FP32 applies, one solve."""
+    mesh, ctx, phi_d, b, *_ = setup(torch)
+    big = torch.empty(1 << 25, dtype=torch.float64, device="cuda")  # 256 MiB
+    big2 = torch.empty_like(big)
+    for _ in range(3):
+        big2.copy_(big)
+    x = torch.randn(mesh.n_nodes, dtype=torch.float64, device="cuda")
+    for _ in range(20):
+        ctx.apply(ctx.PRESSURE, x)
+    x32 = x.float()
+    for _ in range(20):
+        ctx.apply(ctx.PRESSURE, x32)
+    torch.cuda.synchronize()
+    it = 0
+    if with_solve:
+        _, st = solve_once(torch, ctx, phi_d, b)
+        it = st.iterations
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_run": "done", "iterations": it, "copy_bytes": 2 * big.numel() * 8}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-run", nargs="?", const="full", default=None,
+                    help="fixed sequence for rocprofv3; 'applies' skips the solve (for counter passes)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    torch.cuda.set_device(0)
+    if args.profile_run:
+        profile_run(torch, with_solve=args.profile_run != "applies")
+        return
+    mesh, ctx, phi_d, b, x_unit, phi, f, t_mesh = setup(torch)
+    n = mesh.n_nodes
+
+    # ---- warm-up and timed steps (plain FP64 Jacobi-PCG)
+    for _ in range(args.warmup):
+        solve_once(torch, ctx, phi_d, b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for _ in range(args.steps):
+        _, st = solve_once(torch, ctx, phi_d, b)
+        stats.append(st)
+    torch.cuda.synchronize()
+    t_steps = time.perf_counter() - t0
+    ms_per_step = 1e3 * t_steps / args.steps
+    st = stats[-1]
+
+    # ---- variants (each timed once after one warm-up)
+    variants = {"jacobi_pcg_fp64": {"s": ms_per_step / 1e3, "iterations": st.iterations,
+                                   "rel_residual": st.rel_residual, "setup_ms": st.ms_setup}}
+    for name, kw in (("jacobi_pcg_mixed_ir", dict(mode="mixed", inner_rtol=1e-4)),):
+        solve_once(torch, ctx, phi_d, b, **kw)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, sv = solve_once(torch, ctx, phi_d, b, **kw)
+        torch.cuda.synchronize()
+        variants[name] = {"s": time.perf_counter() - t1, "iterations": sv.iterations,
+                          "outer": sv.outer_iterations, "rel_residual": sv.rel_residual,
+                          "setup_ms": sv.ms_setup}
+
+    # ---- apply throughput and the dominant kernel's roofline
+    xr = torch.tensor(ci.normal_vector(0, n), dtype=torch.float64, device="cuda")
+    ms64 = time_applies(torch, ctx, xr)
+    ms32 = time_applies(torch, ctx, xr.float())
+    k64, comb64 = kernel_avg_ms(torch, ctx, xr, "pp_brick_fp64")
+    k32, comb32 = kernel_avg_ms(torch, ctx, xr.float(), "pp_brick_fp32")
+    E = mesh.n_elems
+    flops = PP_FLOPS_PER_LEAF * E
+    bytes64 = PP_BYTES_PER_DOF[8] * n
+    ach_flops = flops / (k64 * 1e-3) / 1e12
+    ach_gbs = bytes64 / (k64 * 1e-3) / 1e9
+    frac_alu = ach_flops / FP64_PEAK_TFLOPS
+    frac_hbm = ach_gbs / HBM_PEAK_GBS
+    traffic = load_traffic("pp_brick_fp64_l7", k64)
+    if frac_alu >= frac_hbm:
+        roof = {"bound": "alu", "achieved": ach_flops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": frac_alu, "traffic": traffic}
+    else:
+        roof = {"bound": "hbm", "achieved": ach_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": frac_hbm, "traffic": traffic}
+    roof.update({"kernel": "k_brick<3,8,double,PP>", "kernel_ms": k64,
+                 "algorithmic_bytes_per_launch": bytes64, "algorithmic_flops_per_launch": flops,
+                 "hbm_frac_algorithmic": frac_hbm, "alu_frac": frac_alu})
+
+    out = {
+        "metric": METRIC,
+        "value": ms_per_step / 1e3,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "3D uniform octree level 7 (128^3 Q1 hex, 2,146,689 nodes), pressure Poisson "
+                               "-div((1/rho(phi)) grad p), 8 seeded tanh drops (Cn 0.01), density ratio 1000, "
+                               "Jacobi-PCG to 1e-8 from x0 = 0",
+                   "n_dof": n, "n_elems": E},
+        "apply_gdof_s": {"fp64": n / (ms64 * 1e-3) / 1e9, "fp32": n / (ms32 * 1e-3) / 1e9,
+                         "fp64_ms": ms64, "fp32_ms": ms32,
+                         "brick_fp64_ms": k64, "combine_fp64_ms": comb64,
+                         "brick_fp32_ms": k32, "combine_fp32_ms": comb32},
+        "roofline": roof,
+        "variants": variants,
+        "iterations": st.iterations,
+        "rel_residual": st.rel_residual,
+        "host_mesh_build_s": t_mesh,
+    }
+    if not args.no_cpu_baseline:
+        lex = np.arange(n)  # uniform meshes are numbered lexicographically, x fastest
+        out["cpu_baseline"] = cpu_baseline(phi[lex], f[lex], st.iterations)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

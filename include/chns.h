@@ -1,0 +1,209 @@
+/*
+ * chns.h - C ABI of libchns: the matrix-free hot path of the projection-based
+ * semi-implicit Cahn-Hilliard Navier-Stokes (CHNS) solver on adaptive
+ * 2:1-balanced octrees, for one AMD MI355X (gfx950).
+ *
+ * Conventions for every call:
+ *   - Return value: CHNS_OK (0) or a negative error code; no call aborts or
+ *     throws across the ABI.  chns_last_error() returns a thread-local message.
+ *   - Handles (chns_mesh, chns_ctx) are opaque, owned by the library and freed
+ *     with their *_destroy call.
+ *   - Vector arguments named x, y, b, phi ... are caller-owned, contiguous
+ *     DEVICE memory on the context's device, in the mesh's independent-node
+ *     order (chns_mesh_node_coords).  The library never keeps such a pointer
+ *     after the call returns.  FP64 vectors are double*, FP32 vectors float*.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls marked
+ *     "async" only enqueue work on it; the others synchronise it before
+ *     returning.
+ *   - A context must not be used by two threads at once.
+ *
+ * Citations refer to the paper "A projection-based, semi-implicit
+ * time-stepping approach for the Cahn-Hilliard Navier-Stokes equations on
+ * adaptive octree meshes" (Khanwale et al.): sections, definitions and
+ * equations by their names in the paper.
+ */
+#ifndef CHNS_H
+#define CHNS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  CHNS_OK = 0,
+  CHNS_EINVAL = -1,  /* bad argument, shape or state combination            */
+  CHNS_ENOMEM = -2,  /* host or device allocation failed                     */
+  CHNS_EHIP = -3,    /* a HIP runtime call failed (message has the HIP error) */
+  CHNS_ENOCONV = -4, /* solver stopped at max_it; outputs hold the last iterate */
+  CHNS_ESTATE = -5   /* call made before a required earlier call            */
+};
+
+/* ------------------------------------------------------------------ mesh */
+
+/* Refinement rules (paper Sec. 4.2: top-down refinement by a user predicate
+ * on the octant, followed by 2:1 balancing).                                */
+enum {
+  CHNS_RULE_UNIFORM = 0,           /* every leaf at max_level                  */
+  CHNS_RULE_SPHERE_BAND = 1,       /* refine to max_level every octant meeting
+                                      radius-band <= |x - centre| <= radius+band;
+                                      min_level everywhere                     */
+  CHNS_RULE_MULTI_SPHERE_BAND = 2, /* union over n_spheres of the above        */
+  CHNS_RULE_CALLBACK = 3           /* refine while refine(anchor, level, user) */
+};
+
+typedef struct chns_mesh_spec {
+  int dim;        /* 2 or 3                                                   */
+  int min_level;  /* every leaf is at least this deep                         */
+  int max_level;  /* no leaf is deeper; 1 <= max_level <= 16                  */
+  int rule;       /* CHNS_RULE_*                                              */
+  int n_spheres;  /* number of centres/radii (band rules)                     */
+  const double* centres; /* host, n_spheres * dim, unit-domain coordinates    */
+  const double* radii;   /* host, n_spheres                                   */
+  double band;           /* half width of the refined shell                   */
+  /* CALLBACK rule: anchor in integer units of 2^-max_level (unused entries 0);
+   * return nonzero to refine the octant further.                            */
+  int (*refine)(const int64_t anchor[3], int level, void* user);
+  void* user;
+} chns_mesh_spec;
+
+typedef struct chns_mesh chns_mesh;
+
+typedef struct chns_mesh_info {
+  int dim, max_level;
+  int node_order;        /* 0 = lexicographic (x fastest; uniform meshes), 1 = Morton */
+  int uniform;           /* 1 if every leaf has the same level               */
+  int64_t n_elems;       /* leaves                                           */
+  int64_t n_nodes;       /* independent nodes = vector length                */
+  int64_t n_hanging;     /* hanging (constrained) nodes                      */
+  int64_t n_bricks[4];   /* bricks of 8^d, 4^d, 2^d and single elements      */
+  int64_t elems_in_bricks[4];
+  int64_t n_slots;       /* brick-boundary partial sums per field            */
+  int64_t n_shared;      /* nodes completed by the deterministic combine pass */
+  int n_colors;          /* node colours used to probe the exact diagonal    */
+  int64_t level_counts[17];
+} chns_mesh_info;
+
+/* Build a 2:1 vertex-balanced octree on the unit cube/square, enumerate its
+ * independent nodes and hanging-node constraints (paper Sec. 4.2-4.3), and
+ * group its leaves into bricks.  Host-only: needs no GPU.  EINVAL on a bad
+ * spec; *out is owned by the caller and freed with chns_mesh_destroy.      */
+int chns_octree_build(const chns_mesh_spec* spec, chns_mesh** out);
+int chns_mesh_destroy(chns_mesh* mesh);
+int chns_mesh_info_get(const chns_mesh* mesh, chns_mesh_info* out);
+/* Integer coordinates (units 2^-max_level) of the independent nodes in vector
+ * order: host buffer of n_nodes * dim int64.                                */
+int chns_mesh_node_coords(const chns_mesh* mesh, int64_t* ijk);
+/* Leaves in Morton order: host buffers level[n_elems], anchor[n_elems*dim]. */
+int chns_mesh_leaves(const chns_mesh* mesh, int32_t* level, int64_t* anchor);
+/* Hanging nodes: coords[n_hanging*dim] and parent indices parents[n_hanging*4]
+ * (independent-node indices, -1 padded), host buffers.                     */
+int chns_mesh_hanging(const chns_mesh* mesh, int64_t* coords, int32_t* parents);
+
+/* --------------------------------------------------------------- context */
+
+/* Non-dimensional parameters (paper Sec. 2 and its non-dimensionalisation
+ * subsection).  Pe <= 0 selects 1/Pe = 3 Cn^2.  C_I <= 0 selects 6.        */
+typedef struct chns_params {
+  double Re, We, Cn, Pe, Fr;
+  double rho_plus, rho_minus;  /* specific densities; rho(phi) = alpha phi + beta */
+  double eta_plus, eta_minus;  /* specific viscosities                           */
+  double dt;                   /* time step                                      */
+  double C_I;                  /* VMS constant                                   */
+  int gravity_axis;            /* gravity is -e_axis (default 1 = y)             */
+} chns_params;
+
+typedef struct chns_ctx chns_ctx;
+
+/* Upload the mesh to the current HIP device and allocate work buffers.
+ * The mesh must outlive the context.                                       */
+int chns_context_create(chns_mesh* mesh, const chns_params* params, chns_ctx** out);
+int chns_context_destroy(chns_ctx* ctx);
+
+/* Phase field used by the variable-coefficient operators: the context keeps
+ * its own FP64 and FP32 copies of phi~ = (phi + phi_prev)/2, or of phi when
+ * phi_prev is NULL (paper Sec. 3, time averages).  Async.                   */
+int chns_set_phase_field(chns_ctx* ctx, const double* phi, const double* phi_prev, void* stream);
+
+/* ------------------------------------------------------------- operators */
+
+enum {
+  CHNS_OP_PRESSURE = 0,    /* y = A x,  A = -div((1/rho(phi*~)) grad .): pressure
+                              Poisson of Def. 2 / VMS pressure Poisson, natural BCs;
+                              1 field                                           */
+  CHNS_OP_MOMENTUM = 1,    /* VMS velocity prediction (Def. 3), dim fields,
+                              component-blocked; wall rows are identity        */
+  CHNS_OP_CH_JACOBIAN = 2, /* Newton Jacobian of the discrete CH system (Def. 6):
+                              2 fields (phi block then mu block)                */
+  CHNS_OP_MASS_RHO = 3,    /* (w, rho(phi*~) u): velocity update (Def. 5), dim
+                              fields, wall rows identity                        */
+  CHNS_OP_MASS = 4         /* (q, u): plain Q1 mass, 1 field                    */
+};
+enum { CHNS_FP64 = 0, CHNS_FP32 = 1 };
+
+/* y = Op x, matrix-free: per leaf, gather (with hanging-node interpolation),
+ * 2-point Gauss quadrature, and a conflict-free deterministic scatter-add
+ * (transpose interpolation).  x and y: device, n_fields * n_nodes of the
+ * precision's type; x and y must not alias.  Async.                         */
+int chns_apply_operator(chns_ctx* ctx, int op, int prec, const void* x, void* y, void* stream);
+
+/* Exact diagonal of the constrained operator diag(P^T (sum_e K_e) P),
+ * including the cross terms that hanging nodes create.  d: device,
+ * n_fields * n_nodes.  Async.                                              */
+int chns_operator_diagonal(chns_ctx* ctx, int op, int prec, void* d, void* stream);
+
+/* ---------------------------------------------------------------- solves */
+
+enum { CHNS_PC_JACOBI = 0, CHNS_PC_GMG = 1, CHNS_PC_LEARNED = 2, CHNS_PC_NONE = 3 };
+enum { CHNS_MODE_FP64 = 0, CHNS_MODE_MIXED_IR = 1 };
+
+typedef struct chns_solve_opts {
+  double rtol;        /* stop when |b - A x|_2 / |b|_2 <= rtol (FP64); default 1e-8 */
+  int max_it;         /* Krylov iterations (inner ones in MIXED_IR); default 20000   */
+  int pc;             /* CHNS_PC_*                                                   */
+  int mode;           /* CHNS_MODE_*                                                 */
+  double inner_rtol;  /* MIXED_IR inner tolerance; default 1e-4                      */
+  int check_every;    /* host convergence poll period in iterations; default 16      */
+  int max_outer;      /* MIXED_IR refinement steps; default 30                       */
+} chns_solve_opts;
+
+typedef struct chns_solve_stats {
+  int iterations;        /* total Krylov iterations (all inner ones in MIXED_IR)  */
+  int outer_iterations;  /* FP64 refinement steps (MIXED_IR), else 1               */
+  double rel_residual;   /* FP64 true |b - A x|/|b| at exit, recomputed            */
+  double ms_setup;       /* diagonal / hierarchy / network set-up                  */
+  double ms_solve;       /* iterations + final residual                            */
+  int fallback;          /* 1 if the learned preconditioner was abandoned          */
+} chns_solve_stats;
+
+/* Solve the pressure Poisson system A x = b for the current phase field.
+ * A is singular (constants); b is projected to 1^T b = 0 first and x is
+ * returned with 1^T x = 0.  b, x: device FP64, n_nodes; x holds x0 on entry
+ * (use zeros for the standard start).  Synchronises `stream`.  ENOCONV if
+ * rtol was not reached; x and stats then describe the last iterate.       */
+int chns_solve_pressure(chns_ctx* ctx, const double* b, double* x, const chns_solve_opts* opts,
+                        chns_solve_stats* stats, void* stream);
+
+/* ------------------------------------------------------------ profiling */
+
+/* Per-kernel timers (paper Sec. 6 reports per-solver time breakdowns; these
+ * are the device analogue).  When enabled, the context records HIP events
+ * on the caller's stream around each tagged launch group: "pp_brick_fp64",
+ * "pp_brick_fp32", "mass_brick_fp64", "massrho_brick_fp64", "combine", ...
+ * chns_profile_read synchronises the pending events and returns the summed
+ * milliseconds and number of launch groups for `tag` since the last reset. */
+int chns_profile_enable(chns_ctx* ctx, int enable);
+int chns_profile_read(chns_ctx* ctx, const char* tag, double* ms, int64_t* launches);
+int chns_profile_reset(chns_ctx* ctx);
+
+/* Last error message of the calling thread ("" if none). */
+const char* chns_last_error(void);
+/* Library version string. */
+const char* chns_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHNS_H */

@@ -1,0 +1,221 @@
+"""MI355X-native matrix-free hot path of the projection-based semi-implicit
+Cahn-Hilliard Navier-Stokes solver on adaptive octrees.
+
+Thin Python binding over libchns (include/chns.h): argument marshalling only.
+Every step of the hot path runs in the library's HIP kernels; PyTorch provides
+device memory and the current stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib as L
+from ._lib import ChnsError  # noqa: F401
+
+__all__ = ["Mesh", "Context", "ChnsError", "octree_build"]
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t, dtype, numel=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"expected dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"expected {numel} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+class Mesh:
+    """A 2:1-balanced octree on the unit cube (or square) with its independent
+    nodes, hanging constraints and brick decomposition (built on the host)."""
+
+    def __init__(self, dim=3, min_level=0, max_level=5, rule="uniform", centres=None, radii=None,
+                 band=0.0, refine=None):
+        lib = L.lib()
+        spec = L.MeshSpec()
+        spec.dim, spec.min_level, spec.max_level = dim, min_level, max_level
+        rules = {"uniform": L.RULE_UNIFORM, "sphere_band": L.RULE_SPHERE_BAND,
+                 "multi_sphere_band": L.RULE_MULTI_SPHERE_BAND, "callback": L.RULE_CALLBACK}
+        spec.rule = rules[rule]
+        self._keep = []
+        if centres is not None:
+            c = np.ascontiguousarray(np.asarray(centres, dtype=np.float64).reshape(-1, dim))
+            r = np.ascontiguousarray(np.asarray(radii, dtype=np.float64).reshape(-1))
+            self._keep += [c, r]
+            spec.n_spheres = r.shape[0]
+            spec.centres = c.ctypes.data_as(C.POINTER(C.c_double))
+            spec.radii = r.ctypes.data_as(C.POINTER(C.c_double))
+        spec.band = band
+        if refine is not None:
+            def _cb(anchor, level, user):
+                return int(bool(refine([anchor[i] for i in range(3)], level)))
+            cb = L.REFINE_CB(_cb)
+            self._keep.append(cb)
+            spec.refine = cb
+        else:
+            spec.refine = L.REFINE_CB()
+        h = C.c_void_p()
+        L.check(lib.chns_octree_build(C.byref(spec), C.byref(h)))
+        self._h = h
+        self.dim = dim
+        self.info = self._info()
+
+    def _info(self):
+        info = L.MeshInfo()
+        L.check(L.lib().chns_mesh_info_get(self._h, C.byref(info)))
+        return info
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.info.n_nodes)
+
+    @property
+    def n_elems(self) -> int:
+        return int(self.info.n_elems)
+
+    @property
+    def max_level(self) -> int:
+        return int(self.info.max_level)
+
+    def node_coords(self) -> np.ndarray:
+        out = np.empty((self.n_nodes, self.dim), dtype=np.int64)
+        L.check(L.lib().chns_mesh_node_coords(self._h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def leaves(self):
+        lev = np.empty(self.n_elems, dtype=np.int32)
+        anc = np.empty((self.n_elems, self.dim), dtype=np.int64)
+        L.check(L.lib().chns_mesh_leaves(self._h, lev.ctypes.data_as(C.c_void_p), anc.ctypes.data_as(C.c_void_p)))
+        return lev, anc
+
+    def hanging(self):
+        n = int(self.info.n_hanging)
+        coords = np.empty((n, self.dim), dtype=np.int64)
+        par = np.empty((n, 4), dtype=np.int32)
+        if n:
+            L.check(L.lib().chns_mesh_hanging(self._h, coords.ctypes.data_as(C.c_void_p),
+                                              par.ctypes.data_as(C.c_void_p)))
+        return coords, par
+
+    def summary(self) -> dict:
+        i = self.info
+        return {"dim": i.dim, "max_level": i.max_level, "uniform": bool(i.uniform), "n_elems": i.n_elems,
+                "n_nodes": i.n_nodes, "n_hanging": i.n_hanging, "n_bricks": list(i.n_bricks),
+                "elems_in_bricks": list(i.elems_in_bricks), "n_slots": i.n_slots, "n_shared": i.n_shared,
+                "n_colors": i.n_colors, "level_counts": {l: c for l, c in enumerate(i.level_counts) if c}}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            L.lib().chns_mesh_destroy(h)
+            self._h = C.c_void_p()
+
+
+def octree_build(**kw) -> Mesh:
+    return Mesh(**kw)
+
+
+@dataclass
+class SolveStats:
+    iterations: int
+    outer_iterations: int
+    rel_residual: float
+    ms_setup: float
+    ms_solve: float
+    fallback: int
+    status: int
+
+
+class Context:
+    """Device state for one mesh and parameter set (uploads the mesh to the
+    current device)."""
+
+    PRESSURE, MOMENTUM, CH_JACOBIAN, MASS_RHO, MASS = (L.OP_PRESSURE, L.OP_MOMENTUM, L.OP_CH_JACOBIAN,
+                                                       L.OP_MASS_RHO, L.OP_MASS)
+
+    def __init__(self, mesh: Mesh, Re=100.0, We=1.0, Cn=0.01, Pe=0.0, Fr=1.0, rho_plus=1.0, rho_minus=1.0,
+                 eta_plus=1.0, eta_minus=1.0, dt=1e-3, C_I=6.0, gravity_axis=1):
+        self.mesh = mesh
+        p = L.Params(Re, We, Cn, Pe, Fr, rho_plus, rho_minus, eta_plus, eta_minus, dt, C_I, gravity_axis)
+        self.params = p
+        h = C.c_void_p()
+        L.check(L.lib().chns_context_create(mesh._h, C.byref(p), C.byref(h)))
+        self._h = h
+        self.n = mesh.n_nodes
+        self.dim = mesh.dim
+
+    def fields(self, op: int) -> int:
+        return {L.OP_PRESSURE: 1, L.OP_MASS: 1, L.OP_MASS_RHO: self.dim, L.OP_MOMENTUM: self.dim,
+                L.OP_CH_JACOBIAN: 2}[op]
+
+    def set_phase_field(self, phi, phi_prev=None, stream=None):
+        import torch
+        pp = _dev_ptr(phi_prev, torch.float64, self.n) if phi_prev is not None else C.c_void_p()
+        L.check(L.lib().chns_set_phase_field(self._h, _dev_ptr(phi, torch.float64, self.n), pp,
+                                             _stream_ptr(stream)))
+
+    def apply(self, op, x, y=None, prec=None, stream=None):
+        import torch
+        dt = x.dtype
+        if prec is None:
+            prec = L.FP64 if dt == torch.float64 else L.FP32
+        want = torch.float64 if prec == L.FP64 else torch.float32
+        nf = self.fields(op)
+        if y is None:
+            y = torch.empty(nf * self.n, dtype=want, device=x.device)
+        L.check(L.lib().chns_apply_operator(self._h, op, prec, _dev_ptr(x, want, nf * self.n),
+                                            _dev_ptr(y, want, nf * self.n), _stream_ptr(stream)))
+        return y
+
+    def diagonal(self, op, prec=L.FP64, stream=None):
+        import torch
+        want = torch.float64 if prec == L.FP64 else torch.float32
+        d = torch.empty(self.fields(op) * self.n, dtype=want, device="cuda")
+        L.check(L.lib().chns_operator_diagonal(self._h, op, prec, _dev_ptr(d, want), _stream_ptr(stream)))
+        return d
+
+    def solve_pressure(self, b, x=None, rtol=1e-8, max_it=20000, pc="jacobi", mode="fp64", inner_rtol=1e-4,
+                       check_every=16, max_outer=30, stream=None, raise_on_noconv=True):
+        import torch
+        if x is None:
+            x = torch.zeros_like(b)
+        o = L.SolveOpts(rtol, max_it, {"jacobi": L.PC_JACOBI, "gmg": L.PC_GMG, "learned": L.PC_LEARNED,
+                                       "none": L.PC_NONE}[pc],
+                        {"fp64": L.MODE_FP64, "mixed": L.MODE_MIXED_IR}[mode], inner_rtol, check_every, max_outer)
+        st = L.SolveStats()
+        rc = L.lib().chns_solve_pressure(self._h, _dev_ptr(b, torch.float64, self.n),
+                                         _dev_ptr(x, torch.float64, self.n), C.byref(o), C.byref(st),
+                                         _stream_ptr(stream))
+        L.check(rc, allow=() if raise_on_noconv else (L.ENOCONV,))
+        return x, SolveStats(st.iterations, st.outer_iterations, st.rel_residual, st.ms_setup, st.ms_solve,
+                             st.fallback, rc)
+
+    def profile(self, enable=True):
+        L.check(L.lib().chns_profile_enable(self._h, int(enable)))
+
+    def profile_reset(self):
+        L.check(L.lib().chns_profile_reset(self._h))
+
+    def profile_read(self, tag):
+        ms = C.c_double()
+        n = C.c_int64()
+        L.check(L.lib().chns_profile_read(self._h, tag.encode(), C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            L.lib().chns_context_destroy(h)
+            self._h = C.c_void_p()

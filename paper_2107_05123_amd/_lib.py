@@ -1,0 +1,109 @@
+"""ctypes declarations of libchns (include/chns.h).  Argument marshalling only."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libchns.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOCONV, ESTATE = 0, -1, -2, -3, -4, -5
+RULE_UNIFORM, RULE_SPHERE_BAND, RULE_MULTI_SPHERE_BAND, RULE_CALLBACK = 0, 1, 2, 3
+OP_PRESSURE, OP_MOMENTUM, OP_CH_JACOBIAN, OP_MASS_RHO, OP_MASS = 0, 1, 2, 3, 4
+FP64, FP32 = 0, 1
+PC_JACOBI, PC_GMG, PC_LEARNED, PC_NONE = 0, 1, 2, 3
+MODE_FP64, MODE_MIXED_IR = 0, 1
+
+REFINE_CB = C.CFUNCTYPE(C.c_int, C.POINTER(C.c_int64), C.c_int, C.c_void_p)
+
+
+class MeshSpec(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int), ("min_level", C.c_int), ("max_level", C.c_int), ("rule", C.c_int),
+        ("n_spheres", C.c_int), ("centres", C.POINTER(C.c_double)), ("radii", C.POINTER(C.c_double)),
+        ("band", C.c_double), ("refine", REFINE_CB), ("user", C.c_void_p),
+    ]
+
+
+class MeshInfo(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int), ("max_level", C.c_int), ("node_order", C.c_int), ("uniform", C.c_int),
+        ("n_elems", C.c_int64), ("n_nodes", C.c_int64), ("n_hanging", C.c_int64),
+        ("n_bricks", C.c_int64 * 4), ("elems_in_bricks", C.c_int64 * 4), ("n_slots", C.c_int64),
+        ("n_shared", C.c_int64), ("n_colors", C.c_int), ("level_counts", C.c_int64 * 17),
+    ]
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("Re", C.c_double), ("We", C.c_double), ("Cn", C.c_double), ("Pe", C.c_double), ("Fr", C.c_double),
+        ("rho_plus", C.c_double), ("rho_minus", C.c_double), ("eta_plus", C.c_double), ("eta_minus", C.c_double),
+        ("dt", C.c_double), ("C_I", C.c_double), ("gravity_axis", C.c_int),
+    ]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [
+        ("rtol", C.c_double), ("max_it", C.c_int), ("pc", C.c_int), ("mode", C.c_int),
+        ("inner_rtol", C.c_double), ("check_every", C.c_int), ("max_outer", C.c_int),
+    ]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [
+        ("iterations", C.c_int), ("outer_iterations", C.c_int), ("rel_residual", C.c_double),
+        ("ms_setup", C.c_double), ("ms_solve", C.c_double), ("fallback", C.c_int),
+    ]
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "chns_last_error": (C.c_char_p, []),
+    "chns_version": (C.c_char_p, []),
+    "chns_octree_build": (C.c_int, [C.POINTER(MeshSpec), C.POINTER(C.c_void_p)]),
+    "chns_mesh_destroy": (C.c_int, [C.c_void_p]),
+    "chns_mesh_info_get": (C.c_int, [C.c_void_p, C.POINTER(MeshInfo)]),
+    "chns_mesh_node_coords": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "chns_mesh_leaves": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "chns_mesh_hanging": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "chns_context_create": (C.c_int, [C.c_void_p, C.POINTER(Params), C.POINTER(C.c_void_p)]),
+    "chns_context_destroy": (C.c_int, [C.c_void_p]),
+    "chns_set_phase_field": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "chns_apply_operator": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "chns_operator_diagonal": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p]),
+    "chns_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
+    "chns_profile_read": (C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "chns_profile_reset": (C.c_int, [C.c_void_p]),
+    "chns_solve_pressure": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(SolveOpts),
+                                      C.POINTER(SolveStats), C.c_void_p]),
+}
+
+
+class ChnsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libchns error {code}: {msg}")
+        self.code = code
+
+
+def lib():
+    """Load libchns.so; raises if it has not been built (no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() or "
+                              "python -m paper_2107_05123_amd.build")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(rc: int, allow=()) -> int:
+    if rc != OK and rc not in allow:
+        raise ChnsError(rc, lib().chns_last_error().decode())
+    return rc

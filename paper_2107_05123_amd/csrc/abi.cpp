@@ -1,0 +1,397 @@
+// C ABI entry points of libchns (declared in include/chns.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "chns_internal.h"
+
+namespace chns {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+int hip_fail(hipError_t e, const char* what) {
+  g_err = std::string("HIP error in ") + what + ": " + hipGetErrorString(e);
+  return CHNS_EHIP;
+}
+
+void* Ctx::dalloc(size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 8;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    set_error("hipMalloc failed (" + std::to_string(bytes) + " bytes)");
+    return nullptr;
+  }
+  allocs.push_back(p);
+  return p;
+}
+
+hipEvent_t Ctx::prof_event() {
+  if (!prof_pool.empty()) {
+    hipEvent_t e = prof_pool.back();
+    prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void Ctx::prof_begin(const char* tag, hipStream_t s, hipEvent_t* start) {
+  *start = nullptr;
+  if (!prof) return;
+  *start = prof_event();
+  if (*start) (void)hipEventRecord(*start, s);
+}
+
+void Ctx::prof_end(const char* tag, hipStream_t s, hipEvent_t start) {
+  if (!prof || !start) return;
+  hipEvent_t stop = prof_event();
+  if (!stop) return;
+  (void)hipEventRecord(stop, s);
+  prof_pending.push_back({tag, start, stop});
+}
+
+Ctx::~Ctx() {
+  for (auto& r : prof_pending) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : prof_pool) (void)hipEventDestroy(e);
+  for (void* p : allocs) (void)hipFree(p);
+  if (sc_host) (void)hipHostFree(sc_host);
+}
+
+template <typename T>
+static int upload(Ctx& c, T** dst, const std::vector<T>& src) {
+  *dst = (T*)c.dalloc(sizeof(T) * (src.empty() ? 1 : src.size()));
+  if (!*dst) return CHNS_ENOMEM;
+  if (!src.empty()) CHNS_HIP(hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice));
+  return CHNS_OK;
+}
+
+static int upload_mesh(Ctx& c) {
+  const HostMesh& m = *c.host;
+  DevMesh& d = c.dm;
+  d.dim = m.dim;
+  d.max_level = m.max_level;
+  d.n = m.n_indep;
+  d.n_hanging = m.n_hanging;
+  d.n_slots = m.n_slots;
+  d.n_colors = m.n_colors;
+  d.side = 1 << m.max_level;
+  d.structured = m.uniform && m.node_order == 0 && m.n_hanging == 0;
+  int rc;
+  for (int k = 0; k < kBrickClasses; ++k) {
+    const BrickClass& h = m.cls[k];
+    DevBrickClass& b = d.cls[k];
+    b.B = h.B;
+    b.count = h.count;
+    b.npb = h.nodes_per_brick;
+    b.nbnd = h.bnd_per_brick;
+    b.slot_base = h.slot_base;
+    if ((rc = upload(c, &b.table, h.table))) return rc;
+    if ((rc = upload(c, &b.level, h.level))) return rc;
+    std::vector<int16_t> r(h.rank.begin(), h.rank.end());
+    if ((rc = upload(c, &b.rank, r))) return rc;
+    if ((rc = upload(c, &b.anchor, h.anchor))) return rc;
+  }
+  if ((rc = upload(c, &d.hang_par, m.hang_parents))) return rc;
+  d.n_comb = (int64_t)m.comb_node.size();
+  if ((rc = upload(c, &d.comb_node, m.comb_node))) return rc;
+  if ((rc = upload(c, &d.comb_ptr, m.comb_ptr))) return rc;
+  if ((rc = upload(c, &d.comb_ent, m.comb_ent))) return rc;
+  if ((rc = upload(c, &d.color, m.color))) return rc;
+  if ((rc = upload(c, &d.wall, m.wall))) return rc;
+  return CHNS_OK;
+}
+
+}  // namespace chns
+
+using namespace chns;
+
+#define CHNS_GUARD_BEGIN try {
+#define CHNS_GUARD_END                                  \
+  }                                                     \
+  catch (const std::bad_alloc&) {                       \
+    set_error("host allocation failed");                \
+    return CHNS_ENOMEM;                                 \
+  }                                                     \
+  catch (...) {                                         \
+    set_error("unexpected internal exception");         \
+    return CHNS_EINVAL;                                 \
+  }
+
+extern "C" {
+
+const char* chns_last_error(void) { return g_err.c_str(); }
+const char* chns_version(void) { return "libchns 0.1 (gfx950)"; }
+
+int chns_octree_build(const chns_mesh_spec* spec, chns_mesh** out) {
+  CHNS_GUARD_BEGIN
+  if (!spec || !out) {
+    set_error("null argument");
+    return CHNS_EINVAL;
+  }
+  *out = nullptr;
+  auto* m = new chns_mesh();
+  std::string msg;
+  int rc = build_host_mesh(*spec, m->m, msg);
+  if (rc) {
+    set_error(msg);
+    delete m;
+    return rc;
+  }
+  *out = m;
+  return CHNS_OK;
+  CHNS_GUARD_END
+}
+
+int chns_mesh_destroy(chns_mesh* mesh) {
+  delete mesh;
+  return CHNS_OK;
+}
+
+int chns_mesh_info_get(const chns_mesh* mesh, chns_mesh_info* out) {
+  if (!mesh || !out) {
+    set_error("null argument");
+    return CHNS_EINVAL;
+  }
+  const HostMesh& m = mesh->m;
+  std::memset(out, 0, sizeof(*out));
+  out->dim = m.dim;
+  out->max_level = m.max_level;
+  out->node_order = m.node_order;
+  out->uniform = m.uniform ? 1 : 0;
+  out->n_elems = m.n_elems();
+  out->n_nodes = m.n_indep;
+  out->n_hanging = m.n_hanging;
+  for (int k = 0; k < kBrickClasses; ++k) {
+    out->n_bricks[k] = m.cls[k].count;
+    int64_t per = 1;
+    for (int d = 0; d < m.dim; ++d) per *= m.cls[k].B;
+    out->elems_in_bricks[k] = m.cls[k].count * per;
+  }
+  out->n_slots = m.n_slots;
+  out->n_shared = (int64_t)m.comb_node.size();
+  out->n_colors = m.n_colors;
+  for (auto l : m.leaf_level)
+    if (l >= 0 && l <= 16) out->level_counts[(int)l]++;
+  return CHNS_OK;
+}
+
+int chns_mesh_node_coords(const chns_mesh* mesh, int64_t* ijk) {
+  if (!mesh || !ijk) {
+    set_error("null argument");
+    return CHNS_EINVAL;
+  }
+  const HostMesh& m = mesh->m;
+  for (int64_t i = 0; i < m.n_indep; ++i)
+    for (int d = 0; d < m.dim; ++d) ijk[i * m.dim + d] = m.indep_coords[3 * i + d];
+  return CHNS_OK;
+}
+
+int chns_mesh_leaves(const chns_mesh* mesh, int32_t* level, int64_t* anchor) {
+  if (!mesh || !level || !anchor) {
+    set_error("null argument");
+    return CHNS_EINVAL;
+  }
+  const HostMesh& m = mesh->m;
+  for (int64_t e = 0; e < m.n_elems(); ++e) {
+    level[e] = m.leaf_level[e];
+    for (int d = 0; d < m.dim; ++d) anchor[e * m.dim + d] = m.leaf_anchor[3 * e + d];
+  }
+  return CHNS_OK;
+}
+
+int chns_mesh_hanging(const chns_mesh* mesh, int64_t* coords, int32_t* parents) {
+  if (!mesh || !coords || !parents) {
+    set_error("null argument");
+    return CHNS_EINVAL;
+  }
+  const HostMesh& m = mesh->m;
+  for (int64_t h = 0; h < m.n_hanging; ++h) {
+    for (int d = 0; d < m.dim; ++d) coords[h * m.dim + d] = m.hang_coords[3 * h + d];
+    for (int q = 0; q < 4; ++q) parents[4 * h + q] = m.hang_parents[4 * h + q];
+  }
+  return CHNS_OK;
+}
+
+int chns_context_create(chns_mesh* mesh, const chns_params* params, chns_ctx** out) {
+  CHNS_GUARD_BEGIN
+  if (!mesh || !params || !out) {
+    set_error("null argument");
+    return CHNS_EINVAL;
+  }
+  *out = nullptr;
+  if (!(params->rho_plus > 0.0) || !(params->rho_minus > 0.0)) {
+    set_error("densities must be positive");
+    return CHNS_EINVAL;
+  }
+  auto* h = new chns_ctx();
+  Ctx& c = h->c;
+  c.mesh_handle = mesh;
+  c.host = &mesh->m;
+  c.prm = *params;
+  if (c.prm.Pe <= 0.0) c.prm.Pe = 1.0 / (3.0 * c.prm.Cn * c.prm.Cn);
+  if (c.prm.C_I <= 0.0) c.prm.C_I = 6.0;
+  int rc = CHNS_OK;
+  if (hipGetDevice(&c.device) != hipSuccess) {
+    set_error("no HIP device available");
+    delete h;
+    return CHNS_EHIP;
+  }
+  rc = upload_mesh(c);
+  const int64_t n = c.dm.n;
+  if (!rc) {
+    c.phi64 = (double*)c.dalloc(sizeof(double) * n);
+    c.phi32 = (float*)c.dalloc(sizeof(float) * n);
+    c.slots_bytes = sizeof(double) * (size_t)(c.dm.n_slots > 0 ? c.dm.n_slots : 1) * 3;
+    c.slots = c.dalloc(c.slots_bytes);
+    c.partials = (double*)c.dalloc(sizeof(double) * kMaxPartials);
+    c.counter = (unsigned*)c.dalloc(sizeof(unsigned) * 16);
+    c.sc = (DevScalars*)c.dalloc(sizeof(DevScalars));
+    if (!c.phi64 || !c.phi32 || !c.slots || !c.partials || !c.counter || !c.sc) rc = CHNS_ENOMEM;
+  }
+  if (!rc && hipMemset(c.counter, 0, sizeof(unsigned) * 16) != hipSuccess) rc = hip_fail(hipErrorUnknown, "memset");
+  if (!rc && hipMemset(c.sc, 0, sizeof(DevScalars)) != hipSuccess) rc = hip_fail(hipErrorUnknown, "memset");
+  if (!rc && hipHostMalloc((void**)&c.sc_host, sizeof(DevScalars), hipHostMallocDefault) != hipSuccess)
+    rc = hip_fail(hipErrorOutOfMemory, "hipHostMalloc");
+  if (rc) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return CHNS_OK;
+  CHNS_GUARD_END
+}
+
+int chns_context_destroy(chns_ctx* ctx) {
+  if (ctx) {
+    (void)hipDeviceSynchronize();
+    delete ctx;
+  }
+  return CHNS_OK;
+}
+
+int chns_set_phase_field(chns_ctx* ctx, const double* phi, const double* phi_prev, void* stream) {
+  if (!ctx || !phi) {
+    set_error("null argument");
+    return CHNS_EINVAL;
+  }
+  return launch_set_phase(ctx->c, phi, phi_prev, (hipStream_t)stream);
+}
+
+int chns_apply_operator(chns_ctx* ctx, int op, int prec, const void* x, void* y, void* stream) {
+  CHNS_GUARD_BEGIN
+  if (!ctx || !x || !y) {
+    set_error("null argument");
+    return CHNS_EINVAL;
+  }
+  if (x == y) {
+    set_error("x and y must not alias");
+    return CHNS_EINVAL;
+  }
+  ApplyOut o{};
+  return launch_apply(ctx->c, op, prec, x, y, (hipStream_t)stream, o);
+  CHNS_GUARD_END
+}
+
+int chns_operator_diagonal(chns_ctx* ctx, int op, int prec, void* d, void* stream) {
+  CHNS_GUARD_BEGIN
+  if (!ctx || !d) {
+    set_error("null argument");
+    return CHNS_EINVAL;
+  }
+  return launch_diagonal(ctx->c, op, prec, d, false, (hipStream_t)stream);
+  CHNS_GUARD_END
+}
+
+int chns_solve_pressure(chns_ctx* ctx, const double* b, double* x, const chns_solve_opts* opts,
+                        chns_solve_stats* stats, void* stream) {
+  CHNS_GUARD_BEGIN
+  if (!ctx || !b || !x) {
+    set_error("null argument");
+    return CHNS_EINVAL;
+  }
+  chns_solve_opts o{};
+  o.rtol = 1e-8;
+  o.max_it = 20000;
+  o.pc = CHNS_PC_JACOBI;
+  o.mode = CHNS_MODE_FP64;
+  o.inner_rtol = 1e-4;
+  o.check_every = 16;
+  o.max_outer = 30;
+  if (opts) {
+    o = *opts;
+    if (!(o.rtol > 0.0)) o.rtol = 1e-8;
+    if (o.max_it <= 0) o.max_it = 20000;
+    if (!(o.inner_rtol > 0.0)) o.inner_rtol = 1e-4;
+    if (o.check_every <= 0) o.check_every = 16;
+    if (o.max_outer <= 0) o.max_outer = 30;
+  }
+  chns_solve_stats st{};
+  int rc = solve_pressure_impl(ctx->c, b, x, o, st, (hipStream_t)stream);
+  if (stats) *stats = st;
+  return rc;
+  CHNS_GUARD_END
+}
+
+int chns_profile_enable(chns_ctx* ctx, int enable) {
+  if (!ctx) {
+    set_error("null argument");
+    return CHNS_EINVAL;
+  }
+  ctx->c.prof = enable != 0;
+  return CHNS_OK;
+}
+
+int chns_profile_read(chns_ctx* ctx, const char* tag, double* ms, int64_t* launches) {
+  if (!ctx || !tag || !ms || !launches) {
+    set_error("null argument");
+    return CHNS_EINVAL;
+  }
+  Ctx& c = ctx->c;
+  for (auto& r : c.prof_pending) {
+    CHNS_HIP(hipEventSynchronize(r.b));
+    float t = 0.0f;
+    CHNS_HIP(hipEventElapsedTime(&t, r.a, r.b));
+    bool found = false;
+    for (auto& acc : c.prof_acc)
+      if (acc.tag == r.tag) {
+        acc.ms += t;
+        acc.launches += 1;
+        found = true;
+      }
+    if (!found) c.prof_acc.push_back({r.tag, (double)t, 1});
+    c.prof_pool.push_back(r.a);
+    c.prof_pool.push_back(r.b);
+  }
+  c.prof_pending.clear();
+  *ms = 0.0;
+  *launches = 0;
+  for (auto& acc : c.prof_acc)
+    if (acc.tag == tag) {
+      *ms = acc.ms;
+      *launches = acc.launches;
+    }
+  return CHNS_OK;
+}
+
+int chns_profile_reset(chns_ctx* ctx) {
+  if (!ctx) {
+    set_error("null argument");
+    return CHNS_EINVAL;
+  }
+  double ms;
+  int64_t n;
+  chns_profile_read(ctx, "", &ms, &n);
+  ctx->c.prof_acc.clear();
+  return CHNS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,139 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+
+#include "chns.h"
+#include "mesh_host.h"
+
+namespace chns {
+
+void set_error(const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define CHNS_HIP(call)                                  \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return ::chns::hip_fail(e_, #call); \
+  } while (0)
+
+// Device copy of one brick class.
+struct DevBrickClass {
+  int B = 0;
+  int64_t count = 0;
+  int npb = 0;            // nodes per brick
+  int nbnd = 0;           // boundary positions per brick
+  int64_t slot_base = 0;
+  int32_t* table = nullptr;
+  int8_t* level = nullptr;
+  int16_t* rank = nullptr;  // npb entries
+  int32_t* anchor = nullptr;  // 3 per brick (integer node coordinates)
+};
+
+struct DevMesh {
+  int dim = 3;
+  int max_level = 0;
+  int64_t n = 0;           // independent nodes
+  int64_t n_hanging = 0;
+  int64_t n_slots = 0;
+  DevBrickClass cls[kBrickClasses];
+  int32_t* hang_par = nullptr;  // n_hanging * 4, -1 padded
+  int64_t n_comb = 0;
+  int32_t* comb_node = nullptr;
+  int32_t* comb_ptr = nullptr;
+  uint32_t* comb_ent = nullptr;
+  uint8_t* color = nullptr;
+  uint8_t* wall = nullptr;
+  int n_colors = 0;
+  bool structured = false;  // uniform mesh, lexicographic node numbers
+  int32_t side = 0;         // 2^max_level
+};
+
+// Scalars of one Krylov solve kept on the device.
+struct DevScalars {
+  double pq, rz, rz_old, rr, bb, alpha, beta, sum;
+  double tol2;        // (rtol |b|)^2
+  int it, done, max_it, pad;
+};
+
+struct Ctx {
+  chns_mesh* mesh_handle = nullptr;
+  const HostMesh* host = nullptr;
+  DevMesh dm;
+  chns_params prm{};
+  int device = 0;
+  std::vector<void*> allocs;
+
+  // phase field phi~ in both precisions
+  double* phi64 = nullptr;
+  float* phi32 = nullptr;
+  bool phi_set = false;
+
+  // slot buffers (largest field count * n_slots), both precisions share storage
+  void* slots = nullptr;
+  size_t slots_bytes = 0;
+
+  // reduction scratch
+  double* partials = nullptr;   // kMaxPartials
+  unsigned* counter = nullptr;  // ticket counters
+  DevScalars* sc = nullptr;     // device scalars
+  DevScalars* sc_host = nullptr;  // pinned mirror
+
+  // work vectors (lazily allocated)
+  double* w64[8] = {};
+  float* w32[8] = {};
+  double* diag64 = nullptr;  // inverse diagonal of the pressure operator
+  float* diag32 = nullptr;
+  bool diag_valid = false;
+
+  // optional per-kernel HIP-event timers (tagged launch groups)
+  bool prof = false;
+  struct ProfRec {
+    std::string tag;
+    hipEvent_t a, b;
+  };
+  std::vector<ProfRec> prof_pending;
+  std::vector<hipEvent_t> prof_pool;
+  struct ProfAcc {
+    std::string tag;
+    double ms;
+    int64_t launches;
+  };
+  std::vector<ProfAcc> prof_acc;
+  hipEvent_t prof_event();
+  void prof_begin(const char* tag, hipStream_t s, hipEvent_t* start);
+  void prof_end(const char* tag, hipStream_t s, hipEvent_t start);
+
+  void* dalloc(size_t bytes);
+  ~Ctx();
+};
+
+constexpr int kMaxPartials = 1 << 16;
+
+// ---- apply (apply.hip)
+struct ApplyOut {
+  // optional fused reduction: sum_i x_i * y_i over written nodes into sc->pq
+  bool fuse_dot = false;
+  const int* done = nullptr;  // skip all work when *done != 0
+};
+int launch_apply(Ctx& c, int op, int prec, const void* x, void* y, hipStream_t s, const ApplyOut& o);
+int launch_diagonal(Ctx& c, int op, int prec, void* dinv_or_d, bool invert, hipStream_t s);
+int op_fields(int op, int dim);
+
+// ---- krylov (krylov.hip)
+int launch_set_phase(Ctx& c, const double* phi, const double* prev, hipStream_t s);
+int solve_pressure_impl(Ctx& c, const double* b, double* x, const chns_solve_opts& o, chns_solve_stats& st,
+                        hipStream_t s);
+
+}  // namespace chns
+
+struct chns_mesh {
+  chns::HostMesh m;
+};
+struct chns_ctx {
+  chns::Ctx c;
+};

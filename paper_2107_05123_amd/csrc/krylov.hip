@@ -1,0 +1,448 @@
+// Device-resident Krylov solvers for the pressure Poisson system.
+//
+// All scalars (dot products, step lengths, iteration count, convergence flag)
+// live in device memory; the host only enqueues kernels and polls the flag
+// every few iterations.  Dot products are accumulated in FP64 with a
+// wavefront + block tree and a last-block finalisation over the per-block
+// partials in a fixed order, so every reduction is deterministic.
+//
+// Solvers:
+//   * Jacobi-preconditioned CG (FP64, or FP32 vectors with FP64 dots);
+//   * FP64 iterative refinement around FP32 inner CG solves (mixed mode);
+// the paper solves the pressure Poisson system with PETSc Krylov methods
+// (appendix on solver options); CG is the natural choice for the symmetric
+// positive semi-definite operator.
+#include <chrono>
+#include <cmath>
+
+#include "chns_internal.h"
+
+namespace chns {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Per-block partial sums of NV doubles: partials[k * kStride + block].  The
+// totals are formed by a one-block finalisation kernel launched next on the
+// same stream (kernel boundaries order the writes; no per-block fences).
+constexpr int kStride = kMaxPartials / 4;
+template <int NV>
+__device__ void block_partials(double (&v)[NV], double* partials) {
+  __shared__ double sh[NV][4];
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double t = wsum(v[k]);
+    if ((threadIdx.x & 63) == 0) sh[k][w] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) partials[k * kStride + blockIdx.x] = (sh[k][0] + sh[k][1]) + (sh[k][2] + sh[k][3]);
+  }
+}
+
+enum FinMode { FIN_STORE = 0, FIN_CG_INIT = 1, FIN_CG_UPDATE = 2 };
+
+// Fixed-order totals of nv partial arrays, then the scalar update of `mode`.
+// 1024 threads, each with four independent running sums, so the few thousand
+// partials are read with many loads in flight.
+constexpr int kFinThreads = 1024;
+__global__ __launch_bounds__(kFinThreads) void k_finalize(const double* partials, int nparts, int nv, int mode,
+                                                          DevScalars* sc, double* out, int respect_done) {
+  __shared__ double sh[kFinThreads / 64];
+  if (respect_done && sc->done) return;
+  double tot[2] = {0.0, 0.0};
+  for (int k = 0; k < nv; ++k) {
+    const double* pk = partials + k * kStride;
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+    int b = threadIdx.x;
+    for (; b + 3 * kFinThreads < nparts; b += 4 * kFinThreads) {
+      v0 += pk[b];
+      v1 += pk[b + kFinThreads];
+      v2 += pk[b + 2 * kFinThreads];
+      v3 += pk[b + 3 * kFinThreads];
+    }
+    for (; b < nparts; b += kFinThreads) v0 += pk[b];
+    double v = (v0 + v1) + (v2 + v3);
+    v = wsum(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < kFinThreads / 64; ++i) t += sh[i];
+    tot[k] = t;
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  if (mode == FIN_STORE) {
+    *out = tot[0];
+  } else if (mode == FIN_CG_INIT) {
+    sc->rz = tot[0];
+    sc->rr = tot[1];
+    sc->it = 0;
+    sc->done = (tot[1] <= sc->tol2) ? 1 : 0;
+  } else {
+    sc->rz_old = sc->rz;
+    sc->rz = tot[0];
+    sc->rr = tot[1];
+    sc->beta = tot[0] / sc->rz_old;
+    sc->it = sc->it + 1;
+    sc->done = (tot[1] <= sc->tol2 || sc->it >= sc->max_it || !(tot[1] == tot[1])) ? 1 : 0;
+  }
+}
+
+inline unsigned grid_for(int64_t n) {
+  int64_t g = (n + kThreads - 1) / kThreads;
+  if (g > 2048) g = 2048;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+// --- plain reductions
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_sum(const T* x, int64_t n, double* partials, unsigned* counter,
+                                                  double* out) {
+  double v[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+    v[0] += (double)x[i];
+  block_partials<1>(v, partials);
+}
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_dot(const T* x, const T* y, int64_t n, double* partials,
+                                                  unsigned* counter, double* out) {
+  double v[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+    v[0] += (double)x[i] * (double)y[i];
+  block_partials<1>(v, partials);
+}
+
+// y = x - sum/n (projection onto 1^T y = 0)
+template <typename T>
+__global__ void k_sub_mean(const T* x, T* y, int64_t n, const double* sum) {
+  const double m = *sum / (double)n;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+    y[i] = (T)((double)x[i] - m);
+}
+
+__global__ void k_phase(const double* phi, const double* prev, double* p64, float* p32, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+    double v = prev ? 0.5 * (phi[i] + prev[i]) : phi[i];
+    p64[i] = v;
+    // FP32 copy holds 1 + phi: near phi = -1 (the light phase) this keeps the
+    // relative accuracy of rho = (beta - alpha) + alpha (1 + phi) at high
+    // density ratios, where alpha phi + beta would cancel.
+    p32[i] = (float)(1.0 + v);
+  }
+}
+
+template <typename T>
+__global__ void k_fill(T* x, T v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) x[i] = v;
+}
+
+__global__ void k_init_scalars(DevScalars* sc, double tol2, int max_it) {
+  sc->tol2 = tol2;
+  sc->max_it = max_it;
+  sc->it = 0;
+  sc->done = 0;
+  sc->rz = sc->rr = sc->pq = sc->alpha = sc->beta = 0.0;
+}
+
+// --- CG kernels
+// r = b - q; z = dinv r; p = z; rz, rr
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_cg_init(const T* b, const T* q, T* r, T* z, T* p, const T* dinv,
+                                                      int64_t n, DevScalars* sc, double* partials,
+                                                      unsigned* counter) {
+  double v[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+    T ri = b[i] - q[i];
+    T zi = dinv ? dinv[i] * ri : ri;
+    r[i] = ri;
+    z[i] = zi;
+    p[i] = zi;
+    v[0] += (double)ri * (double)zi;
+    v[1] += (double)ri * (double)ri;
+  }
+  block_partials<2>(v, partials);
+}
+
+// alpha = rz/pq; x += alpha p; r -= alpha q; z = dinv r; new rz, rr; beta
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_cg_update(T* x, T* r, T* z, const T* p, const T* q, const T* dinv,
+                                                        int64_t n, DevScalars* sc, double* partials,
+                                                        unsigned* counter) {
+  if (sc->done) return;
+  const double alpha = sc->rz / sc->pq;
+  const T a = (T)alpha;
+  double v[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+    T xi = x[i] + a * p[i];
+    T ri = r[i] - a * q[i];
+    T zi = dinv ? dinv[i] * ri : ri;
+    x[i] = xi;
+    r[i] = ri;
+    z[i] = zi;
+    v[0] += (double)ri * (double)zi;
+    v[1] += (double)ri * (double)ri;
+  }
+  block_partials<2>(v, partials);
+}
+
+template <typename T>
+__global__ void k_cg_p(T* p, const T* z, int64_t n, const DevScalars* sc, int check_done) {
+  if (check_done && sc->done) return;
+  const T beta = (T)sc->beta;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+    p[i] = z[i] + beta * p[i];
+}
+
+// x64 += scale * d32 ; r32 = (r64 - ...) handled separately
+__global__ void k_ir_correct(double* x, const float* d, double scale, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+    x[i] += scale * (double)d[i];
+}
+// r = b - q (FP64) and rr
+__global__ __launch_bounds__(kThreads) void k_residual(const double* b, const double* q, double* r, int64_t n,
+                                                       double* partials, unsigned* counter, double* out) {
+  double v[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+    double ri = b[i] - q[i];
+    r[i] = ri;
+    v[0] += ri * ri;
+  }
+  block_partials<1>(v, partials);
+}
+// r32 = r64 * s
+__global__ void k_demote(const double* r, float* r32, double s, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+    r32[i] = (float)(r[i] * s);
+}
+__global__ void k_promote(const float* a, double* b, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+    b[i] = (double)a[i];
+}
+
+int fin(Ctx& c, hipStream_t s, unsigned nparts, int nv, int mode, double* out, int respect_done) {
+  k_finalize<<<1, kFinThreads, 0, s>>>(c.partials, (int)nparts, nv, mode, c.sc, out, respect_done);
+  CHNS_HIP(hipGetLastError());
+  return CHNS_OK;
+}
+
+struct Timer {
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  double ms() const {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
+template <typename T>
+T** work(Ctx& c);
+template <>
+double** work<double>(Ctx& c) {
+  return c.w64;
+}
+template <>
+float** work<float>(Ctx& c) {
+  return c.w32;
+}
+
+template <typename T>
+int ensure_work(Ctx& c, int k) {
+  T** w = work<T>(c);
+  if (!w[k]) w[k] = (T*)c.dalloc(sizeof(T) * c.dm.n * 3);
+  return w[k] ? CHNS_OK : CHNS_ENOMEM;
+}
+
+int read_scalars(Ctx& c, hipStream_t s) {
+  CHNS_HIP(hipMemcpyAsync(c.sc_host, c.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+  CHNS_HIP(hipStreamSynchronize(s));
+  return CHNS_OK;
+}
+
+// Jacobi-PCG on A x = b with b already in range(A) (1^T b = 0).  Precision T
+// for vectors and the operator; dots in FP64.  Stops when |r|^2 <= tol2.
+template <typename T>
+int pcg(Ctx& c, const T* b, T* x, const T* dinv, double tol2, int max_it, int check_every, hipStream_t s,
+        int* iters, double* rr_out) {
+  const int64_t n = c.dm.n;
+  const int prec = sizeof(T) == 8 ? CHNS_FP64 : CHNS_FP32;
+  for (int k = 0; k < 4; ++k)
+    if (ensure_work<T>(c, k)) return CHNS_ENOMEM;
+  T** w = work<T>(c);
+  T *r = w[0], *z = w[1], *p = w[2], *q = w[3];
+  const unsigned g = grid_for(n);
+  k_init_scalars<<<1, 1, 0, s>>>(c.sc, tol2, max_it);
+  ApplyOut plain{};
+  int rc = launch_apply(c, CHNS_OP_PRESSURE, prec, x, q, s, plain);
+  if (rc) return rc;
+  k_cg_init<T><<<g, kThreads, 0, s>>>(b, q, r, z, p, dinv, n, c.sc, c.partials, c.counter);
+  CHNS_HIP(hipGetLastError());
+  if ((rc = fin(c, s, g, 2, FIN_CG_INIT, nullptr, 0))) return rc;
+  ApplyOut fused{};
+  fused.fuse_dot = true;
+  fused.done = &c.sc->done;
+  int it = 0;
+  while (true) {
+    rc = launch_apply(c, CHNS_OP_PRESSURE, prec, p, q, s, fused);
+    if (rc) return rc;
+    k_cg_update<T><<<g, kThreads, 0, s>>>(x, r, z, p, q, dinv, n, c.sc, c.partials, c.counter);
+    if ((rc = fin(c, s, g, 2, FIN_CG_UPDATE, nullptr, 1))) return rc;
+    k_cg_p<T><<<g, kThreads, 0, s>>>(p, z, n, c.sc, 1);
+    CHNS_HIP(hipGetLastError());
+    ++it;
+    if (it % check_every == 0 || it >= max_it) {
+      rc = read_scalars(c, s);
+      if (rc) return rc;
+      if (c.sc_host->done || it >= max_it) break;
+    }
+  }
+  *iters = c.sc_host->it;
+  *rr_out = c.sc_host->rr;
+  return CHNS_OK;
+}
+
+}  // namespace
+
+int launch_set_phase(Ctx& c, const double* phi, const double* prev, hipStream_t s) {
+  k_phase<<<grid_for(c.dm.n), kThreads, 0, s>>>(phi, prev, c.phi64, c.phi32, c.dm.n);
+  CHNS_HIP(hipGetLastError());
+  c.phi_set = true;
+  c.diag_valid = false;
+  return CHNS_OK;
+}
+
+int solve_pressure_impl(Ctx& c, const double* b_in, double* x, const chns_solve_opts& o, chns_solve_stats& st,
+                        hipStream_t s) {
+  const int64_t n = c.dm.n;
+  const unsigned g = grid_for(n);
+  if (!c.phi_set) {
+    set_error("set_phase_field must be called before solve_pressure");
+    return CHNS_ESTATE;
+  }
+  if (o.pc != CHNS_PC_JACOBI && o.pc != CHNS_PC_NONE) {
+    set_error("requested preconditioner is not available in this build");
+    return CHNS_EINVAL;
+  }
+  Timer t_setup;
+  // projected right-hand side kept in w64[4]
+  for (int k = 0; k < 6; ++k)
+    if (ensure_work<double>(c, k)) return CHNS_ENOMEM;
+  double* b = c.w64[4];
+  double* sums = &c.sc->sum;
+  int rc;
+  k_sum<double><<<g, kThreads, 0, s>>>(b_in, n, c.partials, c.counter, sums);
+  if ((rc = fin(c, s, g, 1, FIN_STORE, sums, 0))) return rc;
+  k_sub_mean<double><<<g, kThreads, 0, s>>>(b_in, b, n, sums);
+  k_dot<double><<<g, kThreads, 0, s>>>(b, b, n, c.partials, c.counter, &c.sc->bb);
+  if ((rc = fin(c, s, g, 1, FIN_STORE, &c.sc->bb, 0))) return rc;
+  CHNS_HIP(hipGetLastError());
+  const bool mixed = o.mode == CHNS_MODE_MIXED_IR;
+  if (o.pc == CHNS_PC_JACOBI) {
+    if (!c.diag_valid) {
+      if (!c.diag64) c.diag64 = (double*)c.dalloc(sizeof(double) * n);
+      if (!c.diag32) c.diag32 = (float*)c.dalloc(sizeof(float) * n);
+      if (!c.diag64 || !c.diag32) return CHNS_ENOMEM;
+      rc = launch_diagonal(c, CHNS_OP_PRESSURE, CHNS_FP64, c.diag64, true, s);
+      if (rc) return rc;
+      rc = launch_diagonal(c, CHNS_OP_PRESSURE, CHNS_FP32, c.diag32, true, s);
+      if (rc) return rc;
+      c.diag_valid = true;
+    }
+  }
+  rc = read_scalars(c, s);
+  if (rc) return rc;
+  const double bb = c.sc_host->bb;
+  st.ms_setup = t_setup.ms();
+  Timer t_solve;
+  st.iterations = 0;
+  st.outer_iterations = 0;
+  st.fallback = 0;
+  if (bb == 0.0) {
+    k_fill<double><<<g, kThreads, 0, s>>>(x, 0.0, n);
+    CHNS_HIP(hipStreamSynchronize(s));
+    st.rel_residual = 0.0;
+    st.ms_solve = t_solve.ms();
+    return CHNS_OK;
+  }
+  const double tol2 = o.rtol * o.rtol * bb;
+  double* q64 = c.w64[5];
+  double* r64 = c.w64[0];
+  ApplyOut plain{};
+  if (!mixed) {
+    int it = 0;
+    double rr = 0;
+    rc = pcg<double>(c, b, x, o.pc == CHNS_PC_JACOBI ? c.diag64 : nullptr, tol2, o.max_it, o.check_every, s, &it,
+                     &rr);
+    if (rc) return rc;
+    st.iterations = it;
+    st.outer_iterations = 1;
+  } else {
+    // FP64 iterative refinement: r = b - A x (FP64), inner FP32 CG on A d = r/|r|
+    for (int k = 0; k < 5; ++k)
+      if (ensure_work<float>(c, k)) return CHNS_ENOMEM;
+    if (ensure_work<float>(c, 5)) return CHNS_ENOMEM;
+    float* r32 = c.w32[4];
+    float* d32 = c.w32[5];
+    int total = 0;
+    for (int outer = 0; outer < o.max_outer; ++outer) {
+      rc = launch_apply(c, CHNS_OP_PRESSURE, CHNS_FP64, x, q64, s, plain);
+      if (rc) return rc;
+      k_residual<<<g, kThreads, 0, s>>>(b, q64, r64, n, c.partials, c.counter, &c.sc->rr);
+      CHNS_HIP(hipGetLastError());
+      if ((rc = fin(c, s, g, 1, FIN_STORE, &c.sc->rr, 0))) return rc;
+      rc = read_scalars(c, s);
+      if (rc) return rc;
+      const double rr = c.sc_host->rr;
+      st.outer_iterations = outer;
+      if (rr <= tol2 || total >= o.max_it) break;
+      const double rn = std::sqrt(rr);
+      k_demote<<<g, kThreads, 0, s>>>(r64, r32, 1.0 / rn, n);
+      // keep the inner right-hand side in range(A) after rounding
+      k_sum<float><<<g, kThreads, 0, s>>>(r32, n, c.partials, c.counter, sums);
+      if ((rc = fin(c, s, g, 1, FIN_STORE, sums, 0))) return rc;
+      k_sub_mean<float><<<g, kThreads, 0, s>>>(r32, r32, n, sums);
+      k_fill<float><<<g, kThreads, 0, s>>>(d32, 0.0f, n);
+      CHNS_HIP(hipGetLastError());
+      int it = 0;
+      double rri = 0;
+      const double itol = o.inner_rtol;
+      rc = pcg<float>(c, r32, d32, o.pc == CHNS_PC_JACOBI ? c.diag32 : nullptr, itol * itol, o.max_it - total,
+                      o.check_every, s, &it, &rri);
+      if (rc) return rc;
+      total += it;
+      k_ir_correct<<<g, kThreads, 0, s>>>(x, d32, rn, n);
+      CHNS_HIP(hipGetLastError());
+      st.outer_iterations = outer + 1;
+    }
+    st.iterations = total;
+  }
+  // x -> mean zero, then the FP64 true residual
+  k_sum<double><<<g, kThreads, 0, s>>>(x, n, c.partials, c.counter, sums);
+  if ((rc = fin(c, s, g, 1, FIN_STORE, sums, 0))) return rc;
+  k_sub_mean<double><<<g, kThreads, 0, s>>>(x, x, n, sums);
+  rc = launch_apply(c, CHNS_OP_PRESSURE, CHNS_FP64, x, q64, s, plain);
+  if (rc) return rc;
+  k_residual<<<g, kThreads, 0, s>>>(b, q64, r64, n, c.partials, c.counter, &c.sc->rr);
+  CHNS_HIP(hipGetLastError());
+  if ((rc = fin(c, s, g, 1, FIN_STORE, &c.sc->rr, 0))) return rc;
+  rc = read_scalars(c, s);
+  if (rc) return rc;
+  st.rel_residual = std::sqrt(c.sc_host->rr / bb);
+  st.ms_solve = t_solve.ms();
+  if (!(st.rel_residual <= o.rtol)) {
+    set_error("pressure solve did not reach rtol");
+    return CHNS_ENOCONV;
+  }
+  return CHNS_OK;
+}
+
+}  // namespace chns

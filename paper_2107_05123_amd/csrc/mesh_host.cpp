@@ -1,0 +1,771 @@
+// Host octree construction for the device hot path.
+//
+// Paper Sec. 4.2: the tree is refined top-down from the root by a predicate on
+// each octant and then 2:1 balanced.  Paper Sec. 4.3: independent nodes are
+// found from the leaf corners; a corner that coincides with a point one level
+// below the corners of a coarser touching leaf (the paper's "cancellation
+// nodes") is hanging and is re-expressed through that leaf's face or edge
+// corners (Fig. 1 caption: hanging values come from the immediate parent).
+//
+// Single-process design: leaves live in an open-addressing hash set keyed by
+// (level, Morton code); balancing walks the levels from finest to coarsest and
+// splits any leaf that is more than one level coarser than the parent
+// neighbourhood of a finer leaf, which yields the unique coarsest vertex-
+// balanced refinement in one sweep.  Node de-duplication uses a radix sort of
+// corner keys.  Leaves are then grouped into bricks (aligned cubes of 8^d,
+// 4^d, 2^d leaves of one level, then single leaves) that the device kernels
+// stream over without any per-leaf index map.
+#include "mesh_host.h"
+
+#include "brick_geom.h"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <stdexcept>
+
+namespace chns {
+namespace {
+
+inline uint64_t spread3(uint64_t x) {
+  x &= 0x1fffffull;
+  x = (x | x << 32) & 0x1f00000000ffffull;
+  x = (x | x << 16) & 0x1f0000ff0000ffull;
+  x = (x | x << 8) & 0x100f00f00f00f00full;
+  x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+  x = (x | x << 2) & 0x1249249249249249ull;
+  return x;
+}
+inline uint64_t spread2(uint64_t x) {
+  x &= 0xffffffffull;
+  x = (x | x << 16) & 0x0000ffff0000ffffull;
+  x = (x | x << 8) & 0x00ff00ff00ff00ffull;
+  x = (x | x << 4) & 0x0f0f0f0f0f0f0f0full;
+  x = (x | x << 2) & 0x3333333333333333ull;
+  x = (x | x << 1) & 0x5555555555555555ull;
+  return x;
+}
+inline uint64_t morton(int dim, const int32_t* c) {
+  if (dim == 3) return spread3(c[0]) | spread3(c[1]) << 1 | spread3(c[2]) << 2;
+  return spread2(c[0]) | spread2(c[1]) << 1;
+}
+inline uint64_t leaf_key(int dim, int level, const int32_t* a) {
+  return ((uint64_t)level << 58) | morton(dim, a);
+}
+inline uint64_t mix(uint64_t z) {
+  z += 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+// Open-addressing hash set of 64-bit keys (erase by tombstone).
+class KeySet {
+ public:
+  explicit KeySet(size_t expect) { rehash(std::max<size_t>(64, expect * 2)); }
+  bool contains(uint64_t k) const {
+    size_t i = mix(k) & mask_;
+    while (true) {
+      uint64_t v = slots_[i];
+      if (v == kEmpty) return false;
+      if (v == k) return true;
+      i = (i + 1) & mask_;
+    }
+  }
+  void insert(uint64_t k) {
+    if ((used_ + 1) * 2 > slots_.size()) rehash(slots_.size() * 2);
+    size_t i = mix(k) & mask_;
+    size_t tomb = SIZE_MAX;
+    while (true) {
+      uint64_t v = slots_[i];
+      if (v == k) return;
+      if (v == kTomb && tomb == SIZE_MAX) tomb = i;
+      if (v == kEmpty) break;
+      i = (i + 1) & mask_;
+    }
+    if (tomb != SIZE_MAX) {
+      slots_[tomb] = k;
+    } else {
+      slots_[i] = k;
+      ++used_;
+    }
+  }
+  void erase(uint64_t k) {
+    size_t i = mix(k) & mask_;
+    while (true) {
+      uint64_t v = slots_[i];
+      if (v == kEmpty) return;
+      if (v == k) {
+        slots_[i] = kTomb;
+        return;
+      }
+      i = (i + 1) & mask_;
+    }
+  }
+
+ private:
+  static constexpr uint64_t kEmpty = ~0ull;
+  static constexpr uint64_t kTomb = ~0ull - 1;
+  void rehash(size_t cap) {
+    size_t c = 64;
+    while (c < cap) c <<= 1;
+    std::vector<uint64_t> old;
+    old.swap(slots_);
+    slots_.assign(c, kEmpty);
+    mask_ = c - 1;
+    used_ = 0;
+    for (uint64_t v : old)
+      if (v != kEmpty && v != kTomb) insert(v);
+  }
+  std::vector<uint64_t> slots_;
+  size_t mask_ = 0;
+  size_t used_ = 0;
+};
+
+bool box_meets_shell(const double* lo, const double* hi, const double* c, int dim, double r_in,
+                     double r_out) {
+  double dmin2 = 0.0, dmax2 = 0.0;
+  for (int d = 0; d < dim; ++d) {
+    double nearest = std::min(std::max(c[d], lo[d]), hi[d]);
+    dmin2 += (nearest - c[d]) * (nearest - c[d]);
+    double far = std::max(std::fabs(lo[d] - c[d]), std::fabs(hi[d] - c[d]));
+    dmax2 += far * far;
+  }
+  if (dmin2 > r_out * r_out) return false;
+  if (r_in > 0.0 && dmax2 < r_in * r_in) return false;
+  return true;
+}
+
+// LSD radix sort of (key, payload) pairs.
+void radix_sort_pairs(std::vector<uint64_t>& key, std::vector<uint32_t>& val, int key_bits) {
+  const size_t n = key.size();
+  std::vector<uint64_t> k2(n);
+  std::vector<uint32_t> v2(n);
+  const int R = 11, NB = 1 << R;
+  for (int shift = 0; shift < key_bits; shift += R) {
+    std::vector<size_t> cnt(NB + 1, 0);
+    for (size_t i = 0; i < n; ++i) ++cnt[((key[i] >> shift) & (NB - 1)) + 1];
+    for (int b = 0; b < NB; ++b) cnt[b + 1] += cnt[b];
+    for (size_t i = 0; i < n; ++i) {
+      size_t p = cnt[(key[i] >> shift) & (NB - 1)]++;
+      k2[p] = key[i];
+      v2[p] = val[i];
+    }
+    key.swap(k2);
+    val.swap(v2);
+  }
+}
+
+struct Builder {
+  const chns_mesh_spec& sp;
+  HostMesh& m;
+  std::string& msg;
+  int dim, L;
+  int32_t side;
+  int nc;  // corners per leaf
+
+  Builder(const chns_mesh_spec& s, HostMesh& mm, std::string& e)
+      : sp(s), m(mm), msg(e), dim(s.dim), L(s.max_level), side(1 << s.max_level), nc(1 << s.dim) {}
+
+  int32_t size_at(int lev) const { return side >> lev; }
+
+  bool predicate(int lev, const int32_t* anc) {
+    if (lev < sp.min_level) return true;
+    if (lev >= L) return false;
+    switch (sp.rule) {
+      case CHNS_RULE_UNIFORM:
+        return true;
+      case CHNS_RULE_SPHERE_BAND:
+      case CHNS_RULE_MULTI_SPHERE_BAND: {
+        double lo[3], hi[3];
+        for (int d = 0; d < dim; ++d) {
+          lo[d] = (double)anc[d] / side;
+          hi[d] = ((double)anc[d] + size_at(lev)) / side;
+        }
+        int ns = sp.rule == CHNS_RULE_SPHERE_BAND ? 1 : sp.n_spheres;
+        for (int k = 0; k < ns; ++k) {
+          double r = sp.radii[k];
+          if (box_meets_shell(lo, hi, sp.centres + k * dim, dim, r - sp.band, r + sp.band)) return true;
+        }
+        return false;
+      }
+      case CHNS_RULE_CALLBACK: {
+        int64_t a[3] = {anc[0], anc[1], dim == 3 ? anc[2] : 0};
+        return sp.refine(a, lev, sp.user) != 0;
+      }
+    }
+    return false;
+  }
+
+  // ---------------------------------------------------------------- refine
+  void refine(std::vector<int8_t>& lev_out, std::vector<int32_t>& anc_out) {
+    struct Item {
+      int lev;
+      int32_t a[3];
+    };
+    std::vector<Item> stack;
+    stack.push_back({0, {0, 0, 0}});
+    while (!stack.empty()) {
+      Item it = stack.back();
+      stack.pop_back();
+      if (predicate(it.lev, it.a)) {
+        int32_t h = size_at(it.lev + 1);
+        // push children in reverse Morton order so that they pop in Morton order
+        for (int c = nc - 1; c >= 0; --c) {
+          Item ch{it.lev + 1, {0, 0, 0}};
+          for (int d = 0; d < dim; ++d) ch.a[d] = it.a[d] + ((c >> d) & 1) * h;
+          stack.push_back(ch);
+        }
+      } else {
+        lev_out.push_back((int8_t)it.lev);
+        for (int d = 0; d < 3; ++d) anc_out.push_back(it.a[d]);
+      }
+    }
+  }
+
+  // --------------------------------------------------------------- balance
+  void balance(std::vector<int8_t>& lev, std::vector<int32_t>& anc) {
+    const size_t n0 = lev.size();
+    KeySet S(n0 * 2);
+    std::vector<std::vector<std::array<int32_t, 3>>> bylev(L + 1);
+    for (size_t i = 0; i < n0; ++i) {
+      S.insert(leaf_key(dim, lev[i], &anc[3 * i]));
+      bylev[lev[i]].push_back({anc[3 * i], anc[3 * i + 1], anc[3 * i + 2]});
+    }
+    auto align = [&](const int32_t* p, int l, int32_t* out) {
+      int32_t s = size_at(l);
+      for (int d = 0; d < 3; ++d) out[d] = d < dim ? (p[d] / s) * s : 0;
+    };
+    int ndir = 1;
+    for (int d = 0; d < dim; ++d) ndir *= 3;
+    for (int l = L; l >= 2; --l) {
+      for (size_t idx = 0; idx < bylev[l].size(); ++idx) {
+        std::array<int32_t, 3> a = bylev[l][idx];
+        if (!S.contains(leaf_key(dim, l, a.data()))) continue;
+        int32_t P[3];
+        align(a.data(), l - 1, P);
+        int32_t sP = size_at(l - 1);
+        for (int t = 0; t < ndir; ++t) {
+          int dir[3] = {0, 0, 0};
+          int tt = t;
+          bool zero = true, inside = true;
+          int32_t N[3] = {0, 0, 0};
+          for (int d = 0; d < dim; ++d) {
+            dir[d] = tt % 3 - 1;
+            tt /= 3;
+            if (dir[d]) zero = false;
+            N[d] = P[d] + dir[d] * sP;
+            if (N[d] < 0 || N[d] >= side) inside = false;
+          }
+          if (zero || !inside) continue;
+          // level of the leaf covering N (aligned at l-1), -1 if covered finer
+          int cover = -1;
+          int32_t am[3];
+          for (int mlev = l - 1; mlev >= 0; --mlev) {
+            align(N, mlev, am);
+            if (S.contains(leaf_key(dim, mlev, am))) {
+              cover = mlev;
+              break;
+            }
+          }
+          if (cover < 0 || cover >= l - 1) continue;
+          for (int mlev = cover; mlev < l - 1; ++mlev) {
+            align(N, mlev, am);
+            S.erase(leaf_key(dim, mlev, am));
+            int32_t h = size_at(mlev + 1);
+            for (int c = 0; c < nc; ++c) {
+              std::array<int32_t, 3> ch = {0, 0, 0};
+              for (int d = 0; d < dim; ++d) ch[d] = am[d] + ((c >> d) & 1) * h;
+              S.insert(leaf_key(dim, mlev + 1, ch.data()));
+              bylev[mlev + 1].push_back(ch);
+            }
+          }
+        }
+      }
+    }
+    // collect and sort by Morton key of the anchor (= depth-first order)
+    std::vector<uint64_t> keys;
+    std::vector<uint32_t> ids;
+    std::vector<int8_t> lv;
+    std::vector<int32_t> an;
+    for (int l = 0; l <= L; ++l)
+      for (auto& a : bylev[l])
+        if (S.contains(leaf_key(dim, l, a.data()))) {
+          S.erase(leaf_key(dim, l, a.data()));  // guards against duplicates
+          keys.push_back(morton(dim, a.data()));
+          ids.push_back((uint32_t)lv.size());
+          lv.push_back((int8_t)l);
+          an.insert(an.end(), a.begin(), a.end());
+        }
+    radix_sort_pairs(keys, ids, dim * (L + 1));
+    lev.resize(lv.size());
+    anc.resize(an.size());
+    for (size_t i = 0; i < ids.size(); ++i) {
+      lev[i] = lv[ids[i]];
+      std::memcpy(&anc[3 * i], &an[3 * (size_t)ids[i]], 3 * sizeof(int32_t));
+    }
+  }
+
+  uint64_t node_key(const int32_t* c) const {
+    if (m.node_order == 1) return morton(dim, c);
+    uint64_t s1 = (uint64_t)side + 1;
+    uint64_t k = 0;
+    for (int d = dim - 1; d >= 0; --d) k = k * s1 + (uint64_t)c[d];
+    return k;
+  }
+  int node_key_bits() const {
+    if (m.node_order == 1) return dim * (L + 1);
+    double b = dim * std::log2((double)side + 1.0);
+    return (int)std::ceil(b) + 1;
+  }
+
+  // ----------------------------------------------------------------- nodes
+  int nodes(std::vector<int32_t>& elem_corner, std::vector<int32_t>& all_entry,
+            std::vector<int32_t>& all_coords) {
+    const int64_t E = m.n_elems();
+    if ((uint64_t)E * nc >= (1ull << 32)) {
+      msg = "mesh too large for 32-bit corner ids";
+      return CHNS_EINVAL;
+    }
+    std::vector<uint64_t> key((size_t)E * nc);
+    std::vector<uint32_t> pay((size_t)E * nc);
+    for (int64_t e = 0; e < E; ++e) {
+      int32_t s = size_at(m.leaf_level[e]);
+      for (int a = 0; a < nc; ++a) {
+        int32_t c[3] = {0, 0, 0};
+        for (int d = 0; d < dim; ++d) c[d] = m.leaf_anchor[3 * e + d] + ((a >> d) & 1) * s;
+        key[e * nc + a] = node_key(c);
+        pay[e * nc + a] = (uint32_t)(e * nc + a);
+      }
+    }
+    radix_sort_pairs(key, pay, node_key_bits());
+    elem_corner.assign((size_t)E * nc, -1);
+    std::vector<uint64_t> ukey;
+    std::vector<int8_t> maxlev;
+    for (size_t i = 0; i < key.size(); ++i) {
+      if (i == 0 || key[i] != key[i - 1]) {
+        ukey.push_back(key[i]);
+        uint32_t p = pay[i];
+        int64_t e = p / nc;
+        int a = p % nc;
+        int32_t s = size_at(m.leaf_level[e]);
+        for (int d = 0; d < 3; ++d)
+          all_coords.push_back(d < dim ? m.leaf_anchor[3 * e + d] + ((a >> d) & 1) * s : 0);
+        maxlev.push_back(m.leaf_level[e]);
+      }
+      int64_t id = (int64_t)ukey.size() - 1;
+      elem_corner[pay[i]] = (int32_t)id;
+      int8_t lv = m.leaf_level[pay[i] / nc];
+      if (lv > maxlev[id]) maxlev[id] = lv;
+    }
+    key.clear();
+    key.shrink_to_fit();
+    pay.clear();
+    pay.shrink_to_fit();
+    const int64_t NA = (int64_t)ukey.size();
+
+    // hanging detection: a corner that is not on the level-(lmax-1) grid and
+    // that sits on the boundary of a level-(lmax-1) leaf is hanging.
+    KeySet S((size_t)E * 2);
+    for (int64_t e = 0; e < E; ++e) S.insert(leaf_key(dim, m.leaf_level[e], &m.leaf_anchor[3 * e]));
+    std::vector<int32_t> hang_of(NA, -1);
+    std::vector<std::array<int32_t, 3>> hang_leaf_anchor;
+    std::vector<int8_t> hang_leaf_level;
+    for (int64_t n = 0; n < NA; ++n) {
+      int lm = maxlev[n];
+      if (lm < 1) continue;
+      const int32_t* c = &all_coords[3 * n];
+      int32_t S2 = size_at(lm - 1);
+      bool odd = false;
+      for (int d = 0; d < dim; ++d)
+        if (c[d] % S2) odd = true;
+      if (!odd) continue;
+      for (int o = 0; o < nc; ++o) {
+        int32_t a[3] = {0, 0, 0};
+        bool ok = true;
+        for (int d = 0; d < dim; ++d) {
+          if ((o >> d) & 1) {
+            if (c[d] >= side) ok = false;
+            a[d] = (c[d] / S2) * S2;
+          } else {
+            if (c[d] <= 0) ok = false;
+            a[d] = ((c[d] - 1) / S2) * S2;
+          }
+        }
+        if (!ok) continue;
+        if (S.contains(leaf_key(dim, lm - 1, a))) {
+          hang_of[n] = (int32_t)hang_leaf_level.size();
+          hang_leaf_level.push_back((int8_t)(lm - 1));
+          hang_leaf_anchor.push_back({a[0], a[1], a[2]});
+          break;
+        }
+      }
+    }
+    // independent numbering in key order
+    all_entry.assign(NA, 0);
+    int64_t ni = 0, nh = 0;
+    for (int64_t n = 0; n < NA; ++n) {
+      if (hang_of[n] >= 0) {
+        all_entry[n] = -(int32_t)(++nh);
+      } else {
+        all_entry[n] = (int32_t)ni++;
+        for (int d = 0; d < 3; ++d) m.indep_coords.push_back(all_coords[3 * n + d]);
+      }
+    }
+    m.n_indep = ni;
+    m.n_hanging = nh;
+    m.hang_parents.assign(nh * 4, -1);
+    m.hang_npar.assign(nh, 0);
+    m.hang_coords.resize(nh * 3);
+    for (int64_t n = 0; n < NA; ++n) {
+      if (hang_of[n] < 0) continue;
+      int64_t h = -all_entry[n] - 1;
+      const int32_t* c = &all_coords[3 * n];
+      for (int d = 0; d < 3; ++d) m.hang_coords[3 * h + d] = c[d];
+      auto& A = hang_leaf_anchor[hang_of[n]];
+      int32_t s = size_at(hang_leaf_level[hang_of[n]]);
+      int nfree = 0;
+      int fixedbit[3] = {0, 0, 0};
+      bool isfree[3] = {false, false, false};
+      for (int d = 0; d < dim; ++d) {
+        int32_t r = c[d] - A[d];
+        if (r == 0) fixedbit[d] = 0;
+        else if (r == s) fixedbit[d] = 1;
+        else {
+          isfree[d] = true;
+          ++nfree;
+        }
+      }
+      int np = 0;
+      for (int comb = 0; comb < (1 << nfree); ++comb) {
+        int32_t pc[3] = {0, 0, 0};
+        int k = 0;
+        for (int d = 0; d < dim; ++d) {
+          int bit = isfree[d] ? ((comb >> k++) & 1) : fixedbit[d];
+          pc[d] = A[d] + bit * s;
+        }
+        uint64_t pk = node_key(pc);
+        auto it = std::lower_bound(ukey.begin(), ukey.end(), pk);
+        if (it == ukey.end() || *it != pk) {
+          msg = "hanging-node parent is not a leaf corner";
+          return CHNS_EINVAL;
+        }
+        int32_t pe = all_entry[it - ukey.begin()];
+        if (pe < 0) {
+          msg = "hanging-node parent is itself hanging (tree not 2:1 balanced)";
+          return CHNS_EINVAL;
+        }
+        m.hang_parents[4 * h + np++] = pe;
+      }
+      m.hang_npar[h] = (int8_t)np;
+    }
+    return CHNS_OK;
+  }
+
+  // ---------------------------------------------------------------- bricks
+  void bricks(const std::vector<int32_t>& elem_corner, const std::vector<int32_t>& all_entry,
+              std::vector<std::vector<int32_t>>& brick_elems) {
+    const int64_t E = m.n_elems();
+    std::vector<uint8_t> taken(E, 0);
+    for (int c = 0; c < kBrickClasses; ++c) {
+      BrickClass& bc = m.cls[c];
+      int B = brick_side(c);
+      int b = 3 - c;
+      bc.B = B;
+      int n = 1, np = 1;
+      for (int d = 0; d < dim; ++d) {
+        n *= B;
+        np *= (B + 1);
+      }
+      bc.nodes_per_brick = np;
+      // boundary ranks in lexicographic order of brick-local positions
+      bc.rank.assign(np, -1);
+      int nb = 0;
+      for (int p = 0; p < np; ++p) {
+        int t = p;
+        bool bnd = false;
+        for (int d = 0; d < dim; ++d) {
+          int pd = t % (B + 1);
+          t /= (B + 1);
+          if (pd == 0 || pd == B) bnd = true;
+        }
+        if (bnd) bc.rank[p] = nb++;
+      }
+      bc.bnd_per_brick = nb;
+      // the kernels compute ranks arithmetically; they must match this table
+      if (nb != brick_boundary_count(dim, B)) throw std::logic_error("brick boundary count");
+      for (int p = 0; p < np; ++p) {
+        if (bc.rank[p] < 0) continue;
+        int jx = p % (B + 1), rest = p / (B + 1);
+        int jy = dim == 3 ? rest % (B + 1) : 0, z = dim == 3 ? rest / (B + 1) : rest;
+        if (brick_rank(dim, B, jx, jy, z) != bc.rank[p]) throw std::logic_error("brick rank formula");
+      }
+      std::vector<int32_t>& elist = brick_elems[c];
+      int64_t i = 0;
+      while (i < E) {
+        if (taken[i]) {
+          ++i;
+          continue;
+        }
+        int l = m.leaf_level[i];
+        if (c == kBrickClasses - 1) {
+          elist.push_back((int32_t)i);
+          taken[i] = 1;
+          ++bc.count;
+          ++i;
+          continue;
+        }
+        int32_t s = size_at(l);
+        bool ok = l >= b && i + n <= E;
+        for (int d = 0; ok && d < dim; ++d)
+          if (m.leaf_anchor[3 * i + d] % (B * s)) ok = false;
+        for (int64_t j = i; ok && j < i + n; ++j)
+          if (taken[j] || m.leaf_level[j] != l) ok = false;
+        for (int d = 0; ok && d < dim; ++d)
+          if (m.leaf_anchor[3 * (i + n - 1) + d] != m.leaf_anchor[3 * i + d] + (B - 1) * s) ok = false;
+        if (!ok) {
+          ++i;
+          continue;
+        }
+        // record the brick's leaves ordered by local lexicographic position
+        std::vector<int32_t> loc(n, -1);
+        for (int64_t j = i; j < i + n; ++j) {
+          int lp = 0, mul = 1;
+          for (int d = 0; d < dim; ++d) {
+            lp += ((m.leaf_anchor[3 * j + d] - m.leaf_anchor[3 * i + d]) / s) * mul;
+            mul *= B;
+          }
+          loc[lp] = (int32_t)j;
+          taken[j] = 1;
+        }
+        elist.insert(elist.end(), loc.begin(), loc.end());
+        ++bc.count;
+        i += n;
+      }
+      // tables
+      bc.table.resize((size_t)bc.count * np);
+      bc.level.resize(bc.count);
+      bc.anchor.resize((size_t)bc.count * 3);
+      for (int64_t k = 0; k < bc.count; ++k) {
+        const int32_t* els = &elist[(size_t)k * n];
+        bc.level[k] = m.leaf_level[els[0]];
+        for (int d = 0; d < 3; ++d) bc.anchor[3 * k + d] = m.leaf_anchor[3 * (size_t)els[0] + d];
+        for (int p = 0; p < np; ++p) {
+          int t = p, le = 0, mul = 1, a = 0;
+          for (int d = 0; d < dim; ++d) {
+            int pd = t % (B + 1);
+            t /= (B + 1);
+            int ed = pd < B ? pd : B - 1;
+            le += ed * mul;
+            mul *= B;
+            a |= (pd - ed) << d;
+          }
+          bc.table[(size_t)k * np + p] = all_entry[elem_corner[(size_t)els[le] * nc + a]];
+        }
+      }
+    }
+    int64_t base = 0;
+    for (int c = 0; c < kBrickClasses; ++c) {
+      m.cls[c].slot_base = base;
+      base += m.cls[c].count * m.cls[c].bnd_per_brick;
+    }
+    m.n_slots = base;
+  }
+
+  int combine() {
+    const int64_t N = m.n_indep;
+    if (m.n_slots >= (1ll << 30)) {
+      msg = "too many brick-boundary slots";
+      return CHNS_EINVAL;
+    }
+    std::vector<int32_t> interior(N, 0);
+    std::vector<int32_t> cnt(N + 1, 0);
+    struct Push {
+      int32_t node;
+      uint32_t ent;
+    };
+    std::vector<Push> pushes;
+    for (int c = 0; c < kBrickClasses; ++c) {
+      BrickClass& bc = m.cls[c];
+      for (int64_t k = 0; k < bc.count; ++k) {
+        for (int p = 0; p < bc.nodes_per_brick; ++p) {
+          int32_t e = bc.table[(size_t)k * bc.nodes_per_brick + p];
+          int r = bc.rank[p];
+          if (r < 0) {
+            if (e < 0) {
+              msg = "hanging node inside a brick";
+              return CHNS_EINVAL;
+            }
+            ++interior[e];
+            continue;
+          }
+          uint32_t slot = (uint32_t)(bc.slot_base + k * bc.bnd_per_brick + r);
+          if (e >= 0) {
+            pushes.push_back({e, slot});
+          } else {
+            int64_t h = -e - 1;
+            int np = m.hang_npar[h];
+            uint32_t code = np == 2 ? 1u : (np == 4 ? 2u : 0u);
+            for (int q = 0; q < np; ++q) pushes.push_back({m.hang_parents[4 * h + q], slot | (code << 30)});
+          }
+        }
+      }
+    }
+    for (auto& p : pushes) ++cnt[p.node + 1];
+    for (int64_t i = 0; i < N; ++i) {
+      bool in = interior[i] > 0, sh = cnt[i + 1] > 0;
+      if (interior[i] > 1 || in == sh) {
+        msg = "node ownership is inconsistent";
+        return CHNS_EINVAL;
+      }
+    }
+    std::vector<int32_t> start(N + 1, 0);
+    for (int64_t i = 0; i < N; ++i) start[i + 1] = start[i] + cnt[i + 1];
+    std::vector<uint32_t> ent(pushes.size());
+    std::vector<int32_t> fill(start.begin(), start.end() - 1);
+    for (auto& p : pushes) ent[fill[p.node]++] = p.ent;  // stable: push order kept
+    m.comb_ptr.push_back(0);
+    for (int64_t i = 0; i < N; ++i) {
+      if (cnt[i + 1] == 0) continue;
+      m.comb_node.push_back((int32_t)i);
+      for (int32_t j = start[i]; j < start[i + 1]; ++j) m.comb_ent.push_back(ent[j]);
+      m.comb_ptr.push_back((int32_t)m.comb_ent.size());
+    }
+    return CHNS_OK;
+  }
+
+  // colouring such that no two nodes of one colour are coupled by any leaf
+  int colour(const std::vector<int32_t>& elem_corner, const std::vector<int32_t>& all_entry) {
+    const int64_t N = m.n_indep, E = m.n_elems();
+    m.color.assign(N, 0);
+    if (m.uniform) {
+      int32_t s = size_at(L);
+      for (int64_t i = 0; i < N; ++i) {
+        int c = 0;
+        for (int d = 0; d < dim; ++d) c |= ((m.indep_coords[3 * i + d] / s) & 1) << d;
+        m.color[i] = (uint8_t)c;
+      }
+      m.n_colors = 1 << dim;
+      return CHNS_OK;
+    }
+    auto expand = [&](int64_t e, int32_t* out) {
+      int k = 0;
+      for (int a = 0; a < nc; ++a) {
+        int32_t v = all_entry[elem_corner[e * nc + a]];
+        if (v >= 0) {
+          out[k++] = v;
+        } else {
+          int64_t h = -v - 1;
+          for (int q = 0; q < m.hang_npar[h]; ++q) out[k++] = m.hang_parents[4 * h + q];
+        }
+      }
+      std::sort(out, out + k);
+      return (int)(std::unique(out, out + k) - out);
+    };
+    std::vector<int32_t> cnt(N + 1, 0);
+    int32_t buf[64];
+    for (int64_t e = 0; e < E; ++e) {
+      int k = expand(e, buf);
+      for (int j = 0; j < k; ++j) ++cnt[buf[j] + 1];
+    }
+    for (int64_t i = 0; i < N; ++i) cnt[i + 1] += cnt[i];
+    std::vector<int32_t> inc(cnt[N]);
+    std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int64_t e = 0; e < E; ++e) {
+      int k = expand(e, buf);
+      for (int j = 0; j < k; ++j) inc[fill[buf[j]]++] = (int32_t)e;
+    }
+    std::vector<int16_t> col(N, -1);
+    int maxc = 0;
+    for (int64_t i = 0; i < N; ++i) {
+      uint64_t used[4] = {0, 0, 0, 0};
+      for (int32_t t = cnt[i]; t < cnt[i + 1]; ++t) {
+        int k = expand(inc[t], buf);
+        for (int j = 0; j < k; ++j) {
+          int16_t cj = col[buf[j]];
+          if (cj >= 0) used[cj >> 6] |= 1ull << (cj & 63);
+        }
+      }
+      int c = 0;
+      while (c < 256 && ((used[c >> 6] >> (c & 63)) & 1)) ++c;
+      if (c >= 256) {
+        msg = "node colouring needs more than 256 colours";
+        return CHNS_EINVAL;
+      }
+      col[i] = (int16_t)c;
+      maxc = std::max(maxc, c + 1);
+    }
+    for (int64_t i = 0; i < N; ++i) m.color[i] = (uint8_t)col[i];
+    m.n_colors = maxc;
+    return CHNS_OK;
+  }
+
+  int run() {
+    if (dim != 2 && dim != 3) {
+      msg = "dim must be 2 or 3";
+      return CHNS_EINVAL;
+    }
+    if (L < 1 || L > 16 || sp.min_level < 0 || sp.min_level > L) {
+      msg = "need 0 <= min_level <= max_level, 1 <= max_level <= 16";
+      return CHNS_EINVAL;
+    }
+    if ((sp.rule == CHNS_RULE_SPHERE_BAND || sp.rule == CHNS_RULE_MULTI_SPHERE_BAND) &&
+        (!sp.centres || !sp.radii || (sp.rule == CHNS_RULE_MULTI_SPHERE_BAND && sp.n_spheres < 1))) {
+      msg = "band rules need centres and radii";
+      return CHNS_EINVAL;
+    }
+    if (sp.rule == CHNS_RULE_CALLBACK && !sp.refine) {
+      msg = "callback rule needs refine()";
+      return CHNS_EINVAL;
+    }
+    if (sp.rule < 0 || sp.rule > 3) {
+      msg = "unknown rule";
+      return CHNS_EINVAL;
+    }
+    m.dim = dim;
+    m.max_level = L;
+    refine(m.leaf_level, m.leaf_anchor);
+    balance(m.leaf_level, m.leaf_anchor);
+    int lmin = 99, lmax = -1;
+    for (auto l : m.leaf_level) {
+      lmin = std::min<int>(lmin, l);
+      lmax = std::max<int>(lmax, l);
+    }
+    m.uniform = lmin == lmax;
+    m.node_order = m.uniform ? 0 : 1;
+    std::vector<int32_t> elem_corner, all_entry, all_coords;
+    int rc = nodes(elem_corner, all_entry, all_coords);
+    if (rc) return rc;
+    std::vector<std::vector<int32_t>> brick_elems(kBrickClasses);
+    bricks(elem_corner, all_entry, brick_elems);
+    rc = combine();
+    if (rc) return rc;
+    rc = colour(elem_corner, all_entry);
+    if (rc) return rc;
+    m.wall.assign(m.n_indep, 0);
+    for (int64_t i = 0; i < m.n_indep; ++i)
+      for (int d = 0; d < dim; ++d) {
+        int32_t c = m.indep_coords[3 * i + d];
+        if (c == 0 || c == side) m.wall[i] = 1;
+      }
+    return CHNS_OK;
+  }
+};
+
+}  // namespace
+
+int build_host_mesh(const chns_mesh_spec& spec, HostMesh& m, std::string& msg) {
+  try {
+    Builder b(spec, m, msg);
+    return b.run();
+  } catch (const std::bad_alloc&) {
+    msg = "host allocation failed while building the mesh";
+    return CHNS_ENOMEM;
+  } catch (const std::logic_error& e) {
+    msg = std::string("internal consistency check failed: ") + e.what();
+    return CHNS_EINVAL;
+  }
+}
+
+}  // namespace chns

@@ -1,0 +1,69 @@
+// Host-side octree mesh: leaves, independent nodes, hanging constraints and
+// the brick decomposition that the device kernels stream over.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "chns.h"
+
+namespace chns {
+
+// Bricks are aligned cubes of B^d leaves of one level.  Class c holds
+// bricks with B = 8 >> c (c = 3: single leaves).
+constexpr int kBrickClasses = 4;
+inline int brick_side(int c) { return 8 >> c; }
+
+struct BrickClass {
+  int B = 0;                    // leaves per brick edge
+  int64_t count = 0;            // number of bricks
+  int nodes_per_brick = 0;      // (B+1)^d
+  int bnd_per_brick = 0;        // brick-boundary node positions
+  int64_t slot_base = 0;        // first slot of this class
+  std::vector<int32_t> table;   // count * nodes_per_brick gather entries
+  std::vector<int8_t> level;    // count
+  std::vector<int32_t> anchor;  // count * 3 (integer lower corner)
+  std::vector<int32_t> rank;    // nodes_per_brick: boundary rank or -1 (interior)
+};
+
+struct HostMesh {
+  int dim = 3;
+  int max_level = 0;
+  bool uniform = false;
+  int node_order = 0;  // 0 lexicographic, 1 Morton
+
+  // leaves in Morton order
+  std::vector<int8_t> leaf_level;
+  std::vector<int32_t> leaf_anchor;  // E * 3
+
+  // independent nodes in vector order
+  int64_t n_indep = 0;
+  std::vector<int32_t> indep_coords;  // n_indep * 3
+
+  // hanging nodes: coordinates and up to 4 parents (independent ids, -1 pad)
+  int64_t n_hanging = 0;
+  std::vector<int32_t> hang_coords;   // n_hanging * 3
+  std::vector<int32_t> hang_parents;  // n_hanging * 4
+  std::vector<int8_t> hang_npar;      // n_hanging
+
+  BrickClass cls[kBrickClasses];
+  int64_t n_slots = 0;
+
+  // deterministic combine: shared node -> (slot | weight code) list
+  std::vector<int32_t> comb_node;   // rows
+  std::vector<int32_t> comb_ptr;    // rows + 1
+  std::vector<uint32_t> comb_ent;   // slot (30 bits) | code << 30 (0: 1, 1: 1/2, 2: 1/4)
+  // every independent node is either interior to exactly one brick or a combine row
+  // node colours for probing the exact diagonal
+  int n_colors = 0;
+  std::vector<uint8_t> color;  // n_indep
+  // Dirichlet wall mask (1 on the domain boundary)
+  std::vector<uint8_t> wall;   // n_indep
+
+  int64_t n_elems() const { return (int64_t)leaf_level.size(); }
+};
+
+// Build everything from a spec; returns CHNS_OK or an error with msg set.
+int build_host_mesh(const chns_mesh_spec& spec, HostMesh& m, std::string& msg);
+
+}  // namespace chns
