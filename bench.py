@@ -219,7 +219,9 @@ def main():
     # ---- variants (each timed once after one warm-up)
     variants = {"jacobi_pcg_fp64": {"s": ms_per_step / 1e3, "iterations": st.iterations,
                                    "rel_residual": st.rel_residual, "setup_ms": st.ms_setup}}
-    for name, kw in (("jacobi_pcg_mixed_ir", dict(mode="mixed", inner_rtol=1e-4)),):
+    for name, kw in (("jacobi_pcg_mixed_ir", dict(mode="mixed", inner_rtol=1e-4)),
+                     ("gmg_pcg_fp64", dict(pc="gmg")),
+                     ("gmg_pcg_mixed_ir", dict(pc="gmg", mode="mixed", inner_rtol=1e-4))):
         solve_once(torch, ctx, phi_d, b, **kw)
         torch.cuda.synchronize()
         t1 = time.perf_counter()

@@ -67,6 +67,9 @@ typedef struct chns_mesh_spec {
    * return nonzero to refine the octant further.                            */
   int (*refine)(const int64_t anchor[3], int level, void* user);
   void* user;
+  /* largest brick edge (8, 4, 2 or 1 leaves); 0 = automatic: the largest
+   * edge that still gives >= 1024 bricks, so small meshes keep the GPU busy */
+  int brick_max;
 } chns_mesh_spec;
 
 typedef struct chns_mesh chns_mesh;
@@ -167,6 +170,8 @@ typedef struct chns_solve_opts {
   double inner_rtol;  /* MIXED_IR inner tolerance; default 1e-4                      */
   int check_every;    /* host convergence poll period in iterations; default 16      */
   int max_outer;      /* MIXED_IR refinement steps; default 30                       */
+  int no_graphs;      /* 1: launch every kernel eagerly instead of replaying one HIP
+                         graph per Krylov iteration (same arithmetic, same result)  */
 } chns_solve_opts;
 
 typedef struct chns_solve_stats {

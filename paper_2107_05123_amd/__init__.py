@@ -42,7 +42,7 @@ class Mesh:
     nodes, hanging constraints and brick decomposition (built on the host)."""
 
     def __init__(self, dim=3, min_level=0, max_level=5, rule="uniform", centres=None, radii=None,
-                 band=0.0, refine=None):
+                 band=0.0, refine=None, brick_max=0):
         lib = L.lib()
         spec = L.MeshSpec()
         spec.dim, spec.min_level, spec.max_level = dim, min_level, max_level
@@ -58,6 +58,7 @@ class Mesh:
             spec.centres = c.ctypes.data_as(C.POINTER(C.c_double))
             spec.radii = r.ctypes.data_as(C.POINTER(C.c_double))
         spec.band = band
+        spec.brick_max = int(brick_max)
         if refine is not None:
             def _cb(anchor, level, user):
                 return int(bool(refine([anchor[i] for i in range(3)], level)))
@@ -187,13 +188,14 @@ class Context:
         return d
 
     def solve_pressure(self, b, x=None, rtol=1e-8, max_it=20000, pc="jacobi", mode="fp64", inner_rtol=1e-4,
-                       check_every=16, max_outer=30, stream=None, raise_on_noconv=True):
+                       check_every=16, max_outer=30, graphs=True, stream=None, raise_on_noconv=True):
         import torch
         if x is None:
             x = torch.zeros_like(b)
         o = L.SolveOpts(rtol, max_it, {"jacobi": L.PC_JACOBI, "gmg": L.PC_GMG, "learned": L.PC_LEARNED,
                                        "none": L.PC_NONE}[pc],
-                        {"fp64": L.MODE_FP64, "mixed": L.MODE_MIXED_IR}[mode], inner_rtol, check_every, max_outer)
+                        {"fp64": L.MODE_FP64, "mixed": L.MODE_MIXED_IR}[mode], inner_rtol, check_every, max_outer,
+                        0 if graphs else 1)
         st = L.SolveStats()
         rc = L.lib().chns_solve_pressure(self._h, _dev_ptr(b, torch.float64, self.n),
                                          _dev_ptr(x, torch.float64, self.n), C.byref(o), C.byref(st),

@@ -21,7 +21,7 @@ class MeshSpec(C.Structure):
     _fields_ = [
         ("dim", C.c_int), ("min_level", C.c_int), ("max_level", C.c_int), ("rule", C.c_int),
         ("n_spheres", C.c_int), ("centres", C.POINTER(C.c_double)), ("radii", C.POINTER(C.c_double)),
-        ("band", C.c_double), ("refine", REFINE_CB), ("user", C.c_void_p),
+        ("band", C.c_double), ("refine", REFINE_CB), ("user", C.c_void_p), ("brick_max", C.c_int),
     ]
 
 
@@ -45,7 +45,7 @@ class Params(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [
         ("rtol", C.c_double), ("max_it", C.c_int), ("pc", C.c_int), ("mode", C.c_int),
-        ("inner_rtol", C.c_double), ("check_every", C.c_int), ("max_outer", C.c_int),
+        ("inner_rtol", C.c_double), ("check_every", C.c_int), ("max_outer", C.c_int), ("no_graphs", C.c_int),
     ]
 
 

@@ -57,6 +57,12 @@ void Ctx::prof_end(const char* tag, hipStream_t s, hipEvent_t start) {
 }
 
 Ctx::~Ctx() {
+  if (mg && mg->setup_exec) (void)hipGraphExecDestroy(mg->setup_exec);
+  if (diag_exec) (void)hipGraphExecDestroy(diag_exec);
+  delete mg;
+  for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+  if (ev_in) (void)hipEventDestroy(ev_in);
+  if (work) (void)hipStreamDestroy(work);
   for (auto& r : prof_pending) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -261,6 +267,10 @@ int chns_context_create(chns_mesh* mesh, const chns_params* params, chns_ctx** o
   if (!rc && hipMemset(c.sc, 0, sizeof(DevScalars)) != hipSuccess) rc = hip_fail(hipErrorUnknown, "memset");
   if (!rc && hipHostMalloc((void**)&c.sc_host, sizeof(DevScalars), hipHostMallocDefault) != hipSuccess)
     rc = hip_fail(hipErrorOutOfMemory, "hipHostMalloc");
+  if (!rc && hipStreamCreateWithFlags(&c.work, hipStreamNonBlocking) != hipSuccess)
+    rc = hip_fail(hipErrorUnknown, "hipStreamCreateWithFlags");
+  if (!rc && hipEventCreateWithFlags(&c.ev_in, hipEventDisableTiming) != hipSuccess)
+    rc = hip_fail(hipErrorUnknown, "hipEventCreateWithFlags");
   if (rc) {
     delete h;
     return rc;
@@ -326,6 +336,7 @@ int chns_solve_pressure(chns_ctx* ctx, const double* b, double* x, const chns_so
   o.inner_rtol = 1e-4;
   o.check_every = 16;
   o.max_outer = 30;
+  o.no_graphs = 0;
   if (opts) {
     o = *opts;
     if (!(o.rtol > 0.0)) o.rtol = 1e-8;

@@ -599,8 +599,7 @@ void launch_b(int B, int64_t grid, hipStream_t s, const BrickArgs<T>& a) {
 }
 
 template <int DIM, typename T, int OP>
-int launch_bricks(Ctx& c, BrickArgs<T> a, hipStream_t s, int& part_off) {
-  const DevMesh& dm = c.dm;
+int launch_bricks(const DevMesh& dm, BrickArgs<T> a, hipStream_t s, int& part_off) {
   for (int k = 0; k < kBrickClasses; ++k) {
     const DevBrickClass& bc = dm.cls[k];
     if (bc.count == 0) continue;
@@ -633,16 +632,16 @@ int launch_bricks(Ctx& c, BrickArgs<T> a, hipStream_t s, int& part_off) {
 int64_t combine_blocks(const DevMesh& dm) { return (dm.n_comb + 255) / 256; }
 
 template <int DIM, typename T, int OP>
-int apply_t(Ctx& c, const T* x, T* y, const T* phi, hipStream_t s, const ApplyOut& o) {
+int apply_t(Ctx& c, const LevelView& L, const T* x, T* y, const T* phi, hipStream_t s, const ApplyOut& o) {
   using TR = Traits<OP, DIM>;
-  const DevMesh& dm = c.dm;
+  const DevMesh& dm = *L.dm;
   BrickArgs<T> a{};
   a.n = dm.n;
   a.n_slots = dm.n_slots;
   a.x = x;
   a.coef = phi;
   a.y = y;
-  a.slots = (T*)c.slots;
+  a.slots = (T*)L.slots;
   a.hang = dm.hang_par;
   a.wall = dm.wall;
   a.alpha = (c.prm.rho_plus - c.prm.rho_minus) / (2.0 * c.prm.rho_plus);
@@ -659,7 +658,7 @@ int apply_t(Ctx& c, const T* x, T* y, const T* phi, hipStream_t s, const ApplyOu
   const char* tag = tags[OP][sizeof(T) == 8 ? 0 : 1];
   hipEvent_t ev;
   c.prof_begin(tag, s, &ev);
-  int rc = launch_bricks<DIM, T, OP>(c, a, s, part_off);
+  int rc = launch_bricks<DIM, T, OP>(dm, a, s, part_off);
   if (rc) return rc;
   c.prof_end(tag, s, ev);
   const int64_t cb = combine_blocks(dm);
@@ -672,7 +671,7 @@ int apply_t(Ctx& c, const T* x, T* y, const T* phi, hipStream_t s, const ApplyOu
     const unsigned g = (unsigned)(cb > 0 ? cb : 1);
     c.prof_begin("combine", s, &ev);
     k_combine<T, TR::NF, TR::MASK><<<dim3(g), dim3(256), 0, s>>>(
-        dm.comb_node, dm.comb_ptr, dm.comb_ent, dm.n_comb, (const T*)c.slots, dm.n_slots, y, x, dm.n, dm.wall,
+        dm.comb_node, dm.comb_ptr, dm.comb_ent, dm.n_comb, (const T*)L.slots, dm.n_slots, y, x, dm.n, dm.wall,
         o.fuse_dot ? c.partials + part_off : nullptr, o.done);
     CHNS_HIP(hipGetLastError());
     c.prof_end("combine", s, ev);
@@ -685,16 +684,17 @@ int apply_t(Ctx& c, const T* x, T* y, const T* phi, hipStream_t s, const ApplyOu
 }
 
 template <typename T>
-int apply_dispatch(Ctx& c, int op, const T* x, T* y, const T* phi, hipStream_t s, const ApplyOut& o) {
-  const int dim = c.dm.dim;
+int apply_dispatch(Ctx& c, const LevelView& L, int op, const T* x, T* y, const T* phi, hipStream_t s,
+                   const ApplyOut& o) {
+  const int dim = L.dm->dim;
   switch (op) {
     case CHNS_OP_PRESSURE:
-      return dim == 3 ? apply_t<3, T, K_PP>(c, x, y, phi, s, o) : apply_t<2, T, K_PP>(c, x, y, phi, s, o);
+      return dim == 3 ? apply_t<3, T, K_PP>(c, L, x, y, phi, s, o) : apply_t<2, T, K_PP>(c, L, x, y, phi, s, o);
     case CHNS_OP_MASS:
-      return dim == 3 ? apply_t<3, T, K_MASS>(c, x, y, phi, s, o) : apply_t<2, T, K_MASS>(c, x, y, phi, s, o);
+      return dim == 3 ? apply_t<3, T, K_MASS>(c, L, x, y, phi, s, o) : apply_t<2, T, K_MASS>(c, L, x, y, phi, s, o);
     case CHNS_OP_MASS_RHO:
-      return dim == 3 ? apply_t<3, T, K_MASS_RHO>(c, x, y, phi, s, o)
-                      : apply_t<2, T, K_MASS_RHO>(c, x, y, phi, s, o);
+      return dim == 3 ? apply_t<3, T, K_MASS_RHO>(c, L, x, y, phi, s, o)
+                      : apply_t<2, T, K_MASS_RHO>(c, L, x, y, phi, s, o);
   }
   set_error("operator not available");
   return CHNS_EINVAL;
@@ -716,50 +716,61 @@ int op_fields(int op, int dim) {
   return 0;
 }
 
-int launch_apply(Ctx& c, int op, int prec, const void* x, void* y, hipStream_t s, const ApplyOut& o) {
+LevelView fine_view(Ctx& c) { return LevelView{&c.dm, c.phi64, c.phi32, c.slots}; }
+
+int launch_apply_lv(Ctx& c, const LevelView& L, int op, int prec, const void* x, void* y, hipStream_t s,
+                    const ApplyOut& o) {
   if (op != CHNS_OP_MASS && !c.phi_set) {
     set_error("set_phase_field must be called before this operator");
     return CHNS_ESTATE;
   }
-  if (prec == CHNS_FP64) return apply_dispatch<double>(c, op, (const double*)x, (double*)y, c.phi64, s, o);
-  if (prec == CHNS_FP32) return apply_dispatch<float>(c, op, (const float*)x, (float*)y, c.phi32, s, o);
+  if (prec == CHNS_FP64) return apply_dispatch<double>(c, L, op, (const double*)x, (double*)y, L.phi64, s, o);
+  if (prec == CHNS_FP32) return apply_dispatch<float>(c, L, op, (const float*)x, (float*)y, L.phi32, s, o);
   set_error("prec must be CHNS_FP64 or CHNS_FP32");
   return CHNS_EINVAL;
 }
 
+int launch_apply(Ctx& c, int op, int prec, const void* x, void* y, hipStream_t s, const ApplyOut& o) {
+  return launch_apply_lv(c, fine_view(c), op, prec, x, y, s, o);
+}
+
 // Exact diagonal of P^T K P by probing: colour classes never share a leaf
 // (directly or through constraint parents), so y = A 1_c has y_i = A_ii on
-// colour c.  Uses work vectors 6 and 7 of the requested precision.
+// colour c.
+int launch_diagonal_lv(Ctx& c, const LevelView& L, int op, int prec, void* d, bool invert, void* xi, void* yi,
+                       hipStream_t s) {
+  const int64_t n = L.dm->n;
+  const int nf = op_fields(op, L.dm->dim);
+  const unsigned g = (unsigned)((n + 255) / 256);
+  ApplyOut o{};
+  for (int col = 0; col < L.dm->n_colors; ++col) {
+    if (prec == CHNS_FP64)
+      k_indicator<double><<<g, 256, 0, s>>>((double*)xi, L.dm->color, col, n, nf);
+    else
+      k_indicator<float><<<g, 256, 0, s>>>((float*)xi, L.dm->color, col, n, nf);
+    CHNS_HIP(hipGetLastError());
+    int rc = launch_apply_lv(c, L, op, prec, xi, yi, s, o);
+    if (rc) return rc;
+    if (prec == CHNS_FP64)
+      k_take_diag<double><<<g, 256, 0, s>>>((double*)d, (const double*)yi, L.dm->color, col, n, nf, invert);
+    else
+      k_take_diag<float><<<g, 256, 0, s>>>((float*)d, (const float*)yi, L.dm->color, col, n, nf, invert);
+    CHNS_HIP(hipGetLastError());
+  }
+  return CHNS_OK;
+}
+
 int launch_diagonal(Ctx& c, int op, int prec, void* d, bool invert, hipStream_t s) {
   const int64_t n = c.dm.n;
-  const int nf = op_fields(op, c.dm.dim);
-  const unsigned g = (unsigned)((n + 255) / 256);
-  void* xi;
-  void* yi;
   size_t es = prec == CHNS_FP64 ? 8 : 4;
   for (int k = 6; k < 8; ++k) {
     if (prec == CHNS_FP64 && !c.w64[k]) c.w64[k] = (double*)c.dalloc(es * n * 3);
     if (prec == CHNS_FP32 && !c.w32[k]) c.w32[k] = (float*)c.dalloc(es * n * 3);
     if ((prec == CHNS_FP64 && !c.w64[k]) || (prec == CHNS_FP32 && !c.w32[k])) return CHNS_ENOMEM;
   }
-  xi = prec == CHNS_FP64 ? (void*)c.w64[6] : (void*)c.w32[6];
-  yi = prec == CHNS_FP64 ? (void*)c.w64[7] : (void*)c.w32[7];
-  ApplyOut o{};
-  for (int col = 0; col < c.dm.n_colors; ++col) {
-    if (prec == CHNS_FP64)
-      k_indicator<double><<<g, 256, 0, s>>>((double*)xi, c.dm.color, col, n, nf);
-    else
-      k_indicator<float><<<g, 256, 0, s>>>((float*)xi, c.dm.color, col, n, nf);
-    CHNS_HIP(hipGetLastError());
-    int rc = launch_apply(c, op, prec, xi, yi, s, o);
-    if (rc) return rc;
-    if (prec == CHNS_FP64)
-      k_take_diag<double><<<g, 256, 0, s>>>((double*)d, (const double*)yi, c.dm.color, col, n, nf, invert);
-    else
-      k_take_diag<float><<<g, 256, 0, s>>>((float*)d, (const float*)yi, c.dm.color, col, n, nf, invert);
-    CHNS_HIP(hipGetLastError());
-  }
-  return CHNS_OK;
+  void* xi = prec == CHNS_FP64 ? (void*)c.w64[6] : (void*)c.w32[6];
+  void* yi = prec == CHNS_FP64 ? (void*)c.w64[7] : (void*)c.w32[7];
+  return launch_diagonal_lv(c, fine_view(c), op, prec, d, invert, xi, yi, s);
 }
 
 }  // namespace chns

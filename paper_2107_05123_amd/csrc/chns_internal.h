@@ -60,6 +60,47 @@ struct DevScalars {
   int it, done, max_it, pad;
 };
 
+// One coarse level of the geometric multigrid hierarchy (level 0 is the
+// context's own mesh and fields).
+struct MgLevel {
+  HostMesh host;
+  DevMesh dm;
+  double* phi64 = nullptr;
+  float* phi32 = nullptr;
+  void* slots = nullptr;
+  double* dinv64 = nullptr;
+  float* dinv32 = nullptr;
+  double* v64[4] = {};  // rhs, solution, temporary, probe output
+  float* v32[4] = {};
+  // rows on the next finer level: prolongation from this level
+  int64_t P_rows = 0;
+  int32_t *P_ptr = nullptr, *P_col = nullptr;
+  double* P_val64 = nullptr;
+  float* P_val32 = nullptr;
+  // rows on this level: restriction (P^T) and injection of nodal fields
+  int32_t *R_ptr = nullptr, *R_col = nullptr;
+  double* R_val64 = nullptr;
+  float* R_val32 = nullptr;
+  int32_t *I_ptr = nullptr, *I_col = nullptr;
+  double* I_val = nullptr;
+  // coarsest level: dense inverse of the rank-one regularised operator
+  double* inv64 = nullptr;
+  float* inv32 = nullptr;
+  double* dense = nullptr;
+};
+
+struct Multigrid {
+  std::vector<MgLevel> lv;  // lv[0] unused placeholder for the fine level
+  double* fine_dinv64 = nullptr;
+  float* fine_dinv32 = nullptr;
+  double* fine_t64 = nullptr;
+  float* fine_t32 = nullptr;
+  bool setup_valid = false;
+  hipGraphExec_t setup_exec = nullptr;  // captured device part of the set-up
+  int nu = 2;            // damped-Jacobi sweeps before and after the correction
+  double omega = 0.6;    // damping
+};
+
 struct Ctx {
   chns_mesh* mesh_handle = nullptr;
   const HostMesh* host = nullptr;
@@ -90,6 +131,20 @@ struct Ctx {
   float* diag32 = nullptr;
   bool diag_valid = false;
 
+  Multigrid* mg = nullptr;
+
+  // solves run on a context-owned stream (default priority) so that their
+  // iterations can be captured into HIP graphs, cached per configuration
+  hipStream_t work = nullptr;
+  hipEvent_t ev_in = nullptr;
+  struct GraphEntry {
+    int prec, pc, flexible;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  double* xw64 = nullptr;  // solution buffer of FP64 solves (fixed address for graphs)
+  hipGraphExec_t diag_exec = nullptr;  // captured Jacobi diagonal set-up
+
   // optional per-kernel HIP-event timers (tagged launch groups)
   bool prof = false;
   struct ProfRec {
@@ -114,6 +169,15 @@ struct Ctx {
 
 constexpr int kMaxPartials = 1 << 16;
 
+// A mesh level as seen by the apply kernels: the fine level of a context or
+// one level of its multigrid hierarchy.
+struct LevelView {
+  const DevMesh* dm;
+  const double* phi64;
+  const float* phi32;
+  void* slots;
+};
+
 // ---- apply (apply.hip)
 struct ApplyOut {
   // optional fused reduction: sum_i x_i * y_i over written nodes into sc->pq
@@ -121,8 +185,42 @@ struct ApplyOut {
   const int* done = nullptr;  // skip all work when *done != 0
 };
 int launch_apply(Ctx& c, int op, int prec, const void* x, void* y, hipStream_t s, const ApplyOut& o);
+int launch_apply_lv(Ctx& c, const LevelView& L, int op, int prec, const void* x, void* y, hipStream_t s,
+                    const ApplyOut& o);
 int launch_diagonal(Ctx& c, int op, int prec, void* dinv_or_d, bool invert, hipStream_t s);
+// probing with caller-provided work vectors xi, yi (n * fields each)
+int launch_diagonal_lv(Ctx& c, const LevelView& L, int op, int prec, void* d, bool invert, void* xi, void* yi,
+                       hipStream_t s);
+LevelView fine_view(Ctx& c);
 int op_fields(int op, int dim);
+
+// Run `enqueue(stream)` through a HIP graph captured on first use and cached
+// in *cache (eagerly when profiling).  The enqueued work must be kernels only.
+template <class F>
+int run_captured(Ctx& c, hipGraphExec_t* cache, hipStream_t s, F&& enqueue) {
+  if (c.prof) return enqueue(s);
+  if (!*cache) {
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    int rc = enqueue(s);
+    e = hipStreamEndCapture(s, &g);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(cache, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  }
+  hipError_t e = hipGraphLaunch(*cache, s);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return CHNS_OK;
+}
+
+// ---- geometric multigrid (gmg.hip)
+int mg_build(Ctx& c);
+int mg_setup(Ctx& c, hipStream_t s);
+int mg_vcycle64(Ctx& c, const double* r, double* z, hipStream_t s);
+int mg_vcycle32(Ctx& c, const float* r, float* z, hipStream_t s);
 
 // ---- krylov (krylov.hip)
 int launch_set_phase(Ctx& c, const double* phi, const double* prev, hipStream_t s);

@@ -1,0 +1,468 @@
+// Geometric multigrid V-cycle for the pressure Poisson operator on octree
+// levels.  The paper names geometric multigrid only as future work (its
+// conclusions); it solves with algebraic multigrid instead.  Here every level
+// is the octree truncated one level coarser (2:1 balance is kept), its
+// operator is the same variable-coefficient apply rediscretised with the
+// phase field injected from the finer level, the grid transfers are the
+// exact Q1 embedding (hanging constraints of both levels included) and its
+// transpose, smoothing is damped Jacobi with the exact diagonal, and the
+// coarsest level (level 1: 27 nodes in 3D, 9 in 2D) is solved with a dense inverse of the
+// operator regularised by (1/n) 1 1^T, which returns the mean-free solution
+// for a right-hand side in the range.  The cycle is symmetric, so it is a
+// fixed SPD preconditioner for CG.
+#include <cmath>
+#include <cstring>
+
+#include "chns_internal.h"
+
+namespace chns {
+namespace {
+
+constexpr int kT = 256;
+
+inline unsigned blocks(int64_t n) {
+  int64_t g = (n + kT - 1) / kT;
+  if (g > 4096) g = 4096;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+// y = A x (accumulate: y += A x) for a CSR matrix with values of type V
+template <typename T, typename V>
+__global__ void k_spmv(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                       const V* __restrict__ val, const T* __restrict__ x, T* __restrict__ y, int64_t rows,
+                       int accumulate) {
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < rows; i += (int64_t)gridDim.x * kT) {
+    T acc = T(0);
+    for (int32_t k = ptr[i]; k < ptr[i + 1]; ++k) acc += (T)val[k] * x[col[k]];
+    y[i] = accumulate ? y[i] + acc : acc;
+  }
+}
+
+// z = w dinv r
+template <typename T>
+__global__ void k_jacobi0(T* z, const T* r, const T* dinv, T w, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
+    z[i] = w * dinv[i] * r[i];
+}
+// z += w dinv (r - t)
+template <typename T>
+__global__ void k_jacobi(T* z, const T* r, const T* t, const T* dinv, T w, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
+    z[i] += w * dinv[i] * (r[i] - t[i]);
+}
+// t = r - t
+template <typename T>
+__global__ void k_resid(const T* r, T* t, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) t[i] = r[i] - t[i];
+}
+// z = M r with a dense n x n row-major M
+template <typename T>
+__global__ void k_dense(const T* M, const T* r, T* z, int n) {
+  for (int i = blockIdx.x * kT + threadIdx.x; i < n; i += gridDim.x * kT) {
+    T acc = T(0);
+    for (int j = 0; j < n; ++j) acc += M[(int64_t)i * n + j] * r[j];
+    z[i] = acc;
+  }
+}
+// Structured transfers between uniform lexicographically numbered levels
+// (fine side nf = 2 nc nodes per edge minus one): the Q1 embedding has weight
+// 1 at coincident nodes and 1/2 per direction at midpoints.
+//   restriction: coarse(I) = sum_{a in -1..1}^d w(a) (r - t)(2I + a)
+//   prolongation: z(i) += coarse field at i
+//   injection: coarse(I) = fine(2I)
+template <typename T>
+__global__ void k_restrict_s(const T* __restrict__ r, const T* __restrict__ t, T* __restrict__ out, int nc,
+                             int dim) {
+  const int nf = 2 * nc;
+  const int64_t s1 = nc + 1, f1 = nf + 1;
+  const int64_t ncount = dim == 3 ? s1 * s1 * s1 : s1 * s1;
+  for (int64_t c = (int64_t)blockIdx.x * kT + threadIdx.x; c < ncount; c += (int64_t)gridDim.x * kT) {
+    const int I = (int)(c % s1), J = (int)((c / s1) % s1), K = dim == 3 ? (int)(c / (s1 * s1)) : 0;
+    T acc = T(0);
+    for (int cz = (dim == 3 ? -1 : 0); cz <= (dim == 3 ? 1 : 0); ++cz) {
+      const int k = 2 * K + cz;
+      if (k < 0 || k > nf) continue;
+      const T wz = cz ? T(0.5) : T(1);
+      for (int cy = -1; cy <= 1; ++cy) {
+        const int j = 2 * J + cy;
+        if (j < 0 || j > nf) continue;
+        const T wy = cy ? wz * T(0.5) : wz;
+        const int64_t row = ((int64_t)k * f1 + j) * f1;
+        for (int cx = -1; cx <= 1; ++cx) {
+          const int i = 2 * I + cx;
+          if (i < 0 || i > nf) continue;
+          const T w = cx ? wy * T(0.5) : wy;
+          acc += w * (t ? r[row + i] - t[row + i] : r[row + i]);
+        }
+      }
+    }
+    out[c] = acc;
+  }
+}
+template <typename T>
+__global__ void k_prolong_s(const T* __restrict__ zc, T* __restrict__ z, int nc, int dim) {
+  const int nf = 2 * nc;
+  const int64_t s1 = nc + 1, f1 = nf + 1;
+  const int64_t fcount = dim == 3 ? f1 * f1 * f1 : f1 * f1;
+  for (int64_t f = (int64_t)blockIdx.x * kT + threadIdx.x; f < fcount; f += (int64_t)gridDim.x * kT) {
+    const int i = (int)(f % f1), j = (int)((f / f1) % f1), k = dim == 3 ? (int)(f / (f1 * f1)) : 0;
+    const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1, k0 = k >> 1, k1 = (k + 1) >> 1;
+    auto at = [&](int a, int b, int c) { return zc[((int64_t)c * s1 + b) * s1 + a]; };
+    T v;
+    if (dim == 3)
+      v = T(0.125) * ((at(i0, j0, k0) + at(i1, j0, k0)) + (at(i0, j1, k0) + at(i1, j1, k0)) +
+                      (at(i0, j0, k1) + at(i1, j0, k1)) + (at(i0, j1, k1) + at(i1, j1, k1)));
+    else
+      v = T(0.25) * ((at(i0, j0, 0) + at(i1, j0, 0)) + (at(i0, j1, 0) + at(i1, j1, 0)));
+    z[f] += v;
+  }
+}
+__global__ void k_inject_s(const double* __restrict__ fine, double* __restrict__ out, int nc, int dim) {
+  const int64_t s1 = nc + 1, f1 = 2 * nc + 1;
+  const int64_t ncount = dim == 3 ? s1 * s1 * s1 : s1 * s1;
+  for (int64_t c = (int64_t)blockIdx.x * kT + threadIdx.x; c < ncount; c += (int64_t)gridDim.x * kT) {
+    const int64_t I = c % s1, J = (c / s1) % s1, K = dim == 3 ? c / (s1 * s1) : 0;
+    out[c] = fine[((2 * K) * f1 + 2 * J) * f1 + 2 * I];
+  }
+}
+
+__global__ void k_unit(double* x, int j, int n) {
+  for (int i = blockIdx.x * kT + threadIdx.x; i < n; i += gridDim.x * kT) x[i] = (i == j) ? 1.0 : 0.0;
+}
+__global__ void k_copy_col(const double* y, double* M, int j, int n) {
+  for (int i = blockIdx.x * kT + threadIdx.x; i < n; i += gridDim.x * kT) M[(int64_t)j * n + i] = y[i];
+}
+__global__ void k_to32(const double* a, float* b, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) b[i] = (float)a[i];
+}
+__global__ void k_phase32(const double* a, float* b, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
+    b[i] = (float)(1.0 + a[i]);
+}
+
+template <typename T>
+int upload(Ctx& c, T** dst, const std::vector<T>& src) {
+  *dst = (T*)c.dalloc(sizeof(T) * (src.empty() ? 1 : src.size()));
+  if (!*dst) return CHNS_ENOMEM;
+  if (!src.empty()) CHNS_HIP(hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice));
+  return CHNS_OK;
+}
+template <typename T>
+int upload_as_float(Ctx& c, float** dst, const std::vector<T>& src) {
+  std::vector<float> f(src.begin(), src.end());
+  return upload(c, dst, f);
+}
+
+int upload_dm(Ctx& c, const HostMesh& m, DevMesh& d) {
+  d.dim = m.dim;
+  d.max_level = m.max_level;
+  d.n = m.n_indep;
+  d.n_hanging = m.n_hanging;
+  d.n_slots = m.n_slots;
+  d.n_colors = m.n_colors;
+  d.side = 1 << m.max_level;
+  d.structured = m.uniform && m.node_order == 0 && m.n_hanging == 0;
+  int rc;
+  for (int k = 0; k < kBrickClasses; ++k) {
+    const BrickClass& h = m.cls[k];
+    DevBrickClass& b = d.cls[k];
+    b.B = h.B;
+    b.count = h.count;
+    b.npb = h.nodes_per_brick;
+    b.nbnd = h.bnd_per_brick;
+    b.slot_base = h.slot_base;
+    if ((rc = upload(c, &b.table, h.table))) return rc;
+    if ((rc = upload(c, &b.level, h.level))) return rc;
+    std::vector<int16_t> r(h.rank.begin(), h.rank.end());
+    if ((rc = upload(c, &b.rank, r))) return rc;
+    if ((rc = upload(c, &b.anchor, h.anchor))) return rc;
+  }
+  if ((rc = upload(c, &d.hang_par, m.hang_parents))) return rc;
+  d.n_comb = (int64_t)m.comb_node.size();
+  if ((rc = upload(c, &d.comb_node, m.comb_node))) return rc;
+  if ((rc = upload(c, &d.comb_ptr, m.comb_ptr))) return rc;
+  if ((rc = upload(c, &d.comb_ent, m.comb_ent))) return rc;
+  if ((rc = upload(c, &d.color, m.color))) return rc;
+  if ((rc = upload(c, &d.wall, m.wall))) return rc;
+  return CHNS_OK;
+}
+
+LevelView view(MgLevel& L) { return LevelView{&L.dm, L.phi64, L.phi32, L.slots}; }
+
+// Host: regularised dense inverse (Cholesky of A + (1/n) 1 1^T).
+int dense_inverse(std::vector<double>& A, int n) {
+  double scale = 0.0;
+  for (int i = 0; i < n; ++i) scale = std::max(scale, A[(size_t)i * n + i]);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) A[(size_t)i * n + j] = 0.5 * (A[(size_t)i * n + j] + A[(size_t)j * n + i]);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) A[(size_t)i * n + j] += scale / n;
+  std::vector<double> Lc((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double d = A[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) d -= Lc[(size_t)j * n + k] * Lc[(size_t)j * n + k];
+    if (!(d > 0.0)) return CHNS_EINVAL;
+    d = std::sqrt(d);
+    Lc[(size_t)j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double v = A[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) v -= Lc[(size_t)i * n + k] * Lc[(size_t)j * n + k];
+      Lc[(size_t)i * n + j] = v / d;
+    }
+  }
+  // inverse column by column: L L^T x = e_j
+  std::vector<double> inv((size_t)n * n), y(n);
+  for (int j = 0; j < n; ++j) {
+    for (int i = 0; i < n; ++i) {
+      double v = (i == j) ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) v -= Lc[(size_t)i * n + k] * y[k];
+      y[i] = v / Lc[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double v = y[i];
+      for (int k = i + 1; k < n; ++k) v -= Lc[(size_t)k * n + i] * inv[(size_t)k * n + j];
+      inv[(size_t)i * n + j] = v / Lc[(size_t)i * n + i];
+    }
+  }
+  A.swap(inv);
+  return CHNS_OK;
+}
+
+template <typename T>
+struct Prec;
+template <>
+struct Prec<double> {
+  static constexpr int P = CHNS_FP64;
+  static double* v(MgLevel& L, int k) { return L.v64[k]; }
+  static double* dinv(MgLevel& L) { return L.dinv64; }
+  static const double* Pv(MgLevel& L) { return L.P_val64; }
+  static const double* Rv(MgLevel& L) { return L.R_val64; }
+  static const double* inv(MgLevel& L) { return L.inv64; }
+  static double* fine_dinv(Multigrid& m) { return m.fine_dinv64; }
+  static double* fine_t(Multigrid& m) { return m.fine_t64; }
+};
+template <>
+struct Prec<float> {
+  static constexpr int P = CHNS_FP32;
+  static float* v(MgLevel& L, int k) { return L.v32[k]; }
+  static float* dinv(MgLevel& L) { return L.dinv32; }
+  static const float* Pv(MgLevel& L) { return L.P_val32; }
+  static const float* Rv(MgLevel& L) { return L.R_val32; }
+  static const float* inv(MgLevel& L) { return L.inv32; }
+  static float* fine_dinv(Multigrid& m) { return m.fine_dinv32; }
+  static float* fine_t(Multigrid& m) { return m.fine_t32; }
+};
+
+// z = V(r) on level k (k = 0 is the context's mesh)
+template <typename T>
+int vcycle(Ctx& c, int k, const T* r, T* z, hipStream_t s) {
+  Multigrid& mg = *c.mg;
+  const int K = (int)mg.lv.size() - 1;
+  using PR = Prec<T>;
+  if (k == K) {
+    MgLevel& L = mg.lv[k];
+    k_dense<T><<<blocks(L.dm.n), kT, 0, s>>>(PR::inv(L), r, z, (int)L.dm.n);
+    CHNS_HIP(hipGetLastError());
+    return CHNS_OK;
+  }
+  const LevelView V = k == 0 ? fine_view(c) : view(mg.lv[k]);
+  const int64_t n = V.dm->n;
+  T* dinv = k == 0 ? PR::fine_dinv(mg) : PR::dinv(mg.lv[k]);
+  T* t = k == 0 ? PR::fine_t(mg) : PR::v(mg.lv[k], 2);
+  const T w = (T)mg.omega;
+  const unsigned g = blocks(n);
+  ApplyOut plain{};
+  int rc;
+  k_jacobi0<T><<<g, kT, 0, s>>>(z, r, dinv, w, n);
+  for (int it = 1; it < mg.nu; ++it) {
+    if ((rc = launch_apply_lv(c, V, CHNS_OP_PRESSURE, PR::P, z, t, s, plain))) return rc;
+    k_jacobi<T><<<g, kT, 0, s>>>(z, r, t, dinv, w, n);
+  }
+  if ((rc = launch_apply_lv(c, V, CHNS_OP_PRESSURE, PR::P, z, t, s, plain))) return rc;
+  MgLevel& C = mg.lv[k + 1];
+  T* rc_ = PR::v(C, 0);
+  T* zc = PR::v(C, 1);
+  const bool structured = V.dm->structured && C.dm.structured;
+  if (structured) {
+    k_restrict_s<T><<<blocks(C.dm.n), kT, 0, s>>>(r, t, rc_, C.dm.side, C.dm.dim);
+  } else {
+    k_resid<T><<<g, kT, 0, s>>>(r, t, n);
+    k_spmv<T, T><<<blocks(C.dm.n), kT, 0, s>>>(C.R_ptr, C.R_col, PR::Rv(C), t, rc_, C.dm.n, 0);
+  }
+  CHNS_HIP(hipGetLastError());
+  if ((rc = vcycle<T>(c, k + 1, rc_, zc, s))) return rc;
+  if (structured)
+    k_prolong_s<T><<<g, kT, 0, s>>>(zc, z, C.dm.side, C.dm.dim);
+  else
+    k_spmv<T, T><<<g, kT, 0, s>>>(C.P_ptr, C.P_col, PR::Pv(C), zc, z, n, 1);
+  for (int it = 0; it < mg.nu; ++it) {
+    if ((rc = launch_apply_lv(c, V, CHNS_OP_PRESSURE, PR::P, z, t, s, plain))) return rc;
+    k_jacobi<T><<<g, kT, 0, s>>>(z, r, t, dinv, w, n);
+  }
+  CHNS_HIP(hipGetLastError());
+  return CHNS_OK;
+}
+
+}  // namespace
+
+int mg_build(Ctx& c) {
+  if (c.mg) return CHNS_OK;
+  const HostMesh& f = *c.host;
+  const int coarsest = 1;
+  auto* mg = new Multigrid();
+  mg->lv.resize(1);
+  std::string msg;
+  const HostMesh* finer = &f;
+  for (int k = f.max_level - 1; k >= coarsest; --k) {
+    MgLevel L;
+    std::vector<int8_t> lev;
+    std::vector<int32_t> anc;
+    truncate_leaves(*finer, k, lev, anc);
+    int rc = build_host_mesh_from_leaves(f.dim, k, lev, anc, L.host, msg);
+    if (rc) {
+      delete mg;
+      set_error("multigrid level: " + msg);
+      return rc;
+    }
+    mg->lv.push_back(std::move(L));
+    finer = &mg->lv.back().host;
+  }
+  if (mg->lv.size() < 2) {
+    delete mg;
+    set_error("mesh too coarse for multigrid (needs max_level >= 3)");
+    return CHNS_EINVAL;
+  }
+  int rc;
+  for (size_t k = 1; k < mg->lv.size(); ++k) {
+    MgLevel& L = mg->lv[k];
+    const HostMesh& fine = k == 1 ? f : mg->lv[k - 1].host;
+    Transfer t;
+    if ((rc = build_transfer(fine, L.host, t, msg))) {
+      delete mg;
+      set_error("multigrid transfer: " + msg);
+      return rc;
+    }
+    if ((rc = upload_dm(c, L.host, L.dm))) goto fail;
+    L.P_rows = fine.n_indep;
+    if ((rc = upload(c, &L.P_ptr, t.P_ptr)) || (rc = upload(c, &L.P_col, t.P_col)) ||
+        (rc = upload(c, &L.P_val64, t.P_val)) || (rc = upload_as_float(c, &L.P_val32, t.P_val)) ||
+        (rc = upload(c, &L.R_ptr, t.R_ptr)) || (rc = upload(c, &L.R_col, t.R_col)) ||
+        (rc = upload(c, &L.R_val64, t.R_val)) || (rc = upload_as_float(c, &L.R_val32, t.R_val)) ||
+        (rc = upload(c, &L.I_ptr, t.I_ptr)) || (rc = upload(c, &L.I_col, t.I_col)) ||
+        (rc = upload(c, &L.I_val, t.I_val)))
+      goto fail;
+    {
+      const int64_t n = L.dm.n;
+      L.phi64 = (double*)c.dalloc(sizeof(double) * n);
+      L.phi32 = (float*)c.dalloc(sizeof(float) * n);
+      L.slots = c.dalloc(sizeof(double) * (size_t)(L.dm.n_slots > 0 ? L.dm.n_slots : 1) * 3);
+      L.dinv64 = (double*)c.dalloc(sizeof(double) * n);
+      L.dinv32 = (float*)c.dalloc(sizeof(float) * n);
+      for (int j = 0; j < 4; ++j) {
+        L.v64[j] = (double*)c.dalloc(sizeof(double) * n);
+        L.v32[j] = (float*)c.dalloc(sizeof(float) * n);
+        if (!L.v64[j] || !L.v32[j]) {
+          rc = CHNS_ENOMEM;
+          goto fail;
+        }
+      }
+      if (!L.phi64 || !L.phi32 || !L.slots || !L.dinv64 || !L.dinv32) {
+        rc = CHNS_ENOMEM;
+        goto fail;
+      }
+    }
+  }
+  {
+    MgLevel& B = mg->lv.back();
+    const int64_t n = B.dm.n;
+    B.dense = (double*)c.dalloc(sizeof(double) * n * n);
+    B.inv64 = (double*)c.dalloc(sizeof(double) * n * n);
+    B.inv32 = (float*)c.dalloc(sizeof(float) * n * n);
+    const int64_t nf = c.dm.n;
+    mg->fine_dinv64 = (double*)c.dalloc(sizeof(double) * nf);
+    mg->fine_dinv32 = (float*)c.dalloc(sizeof(float) * nf);
+    mg->fine_t64 = (double*)c.dalloc(sizeof(double) * nf);
+    mg->fine_t32 = (float*)c.dalloc(sizeof(float) * nf);
+    if (!B.dense || !B.inv64 || !B.inv32 || !mg->fine_dinv64 || !mg->fine_dinv32 || !mg->fine_t64 ||
+        !mg->fine_t32) {
+      rc = CHNS_ENOMEM;
+      goto fail;
+    }
+  }
+  c.mg = mg;
+  return CHNS_OK;
+fail:
+  delete mg;
+  return rc;
+}
+
+// Per phase field: inject phi~ down the levels, exact diagonals, coarse
+// operator columns (device part captured once into a graph), then the
+// regularised inverse of the coarsest operator on the host.
+int mg_setup(Ctx& c, hipStream_t s) {
+  Multigrid& mg = *c.mg;
+  int rc;
+  for (int k = 6; k < 8; ++k) {
+    if (!c.w64[k]) c.w64[k] = (double*)c.dalloc(sizeof(double) * c.dm.n * 3);
+    if (!c.w32[k]) c.w32[k] = (float*)c.dalloc(sizeof(float) * c.dm.n * 3);
+    if (!c.w64[k] || !c.w32[k]) return CHNS_ENOMEM;
+  }
+  MgLevel& B = mg.lv.back();
+  const int n = (int)B.dm.n;
+  auto device_part = [&](hipStream_t st) -> int {
+    int e;
+    if ((e = launch_diagonal_lv(c, fine_view(c), CHNS_OP_PRESSURE, CHNS_FP64, mg.fine_dinv64, true, c.w64[6],
+                                c.w64[7], st)))
+      return e;
+    if ((e = launch_diagonal_lv(c, fine_view(c), CHNS_OP_PRESSURE, CHNS_FP32, mg.fine_dinv32, true, c.w32[6],
+                                c.w32[7], st)))
+      return e;
+    const double* phi_f = c.phi64;
+    for (size_t k = 1; k < mg.lv.size(); ++k) {
+      MgLevel& L = mg.lv[k];
+      const int64_t nk = L.dm.n;
+      const DevMesh& F = k == 1 ? c.dm : mg.lv[k - 1].dm;
+      if (F.structured && L.dm.structured)
+        k_inject_s<<<blocks(nk), kT, 0, st>>>(phi_f, L.phi64, L.dm.side, L.dm.dim);
+      else
+        k_spmv<double, double><<<blocks(nk), kT, 0, st>>>(L.I_ptr, L.I_col, L.I_val, phi_f, L.phi64, nk, 0);
+      k_phase32<<<blocks(nk), kT, 0, st>>>(L.phi64, L.phi32, nk);
+      CHNS_HIP(hipGetLastError());
+      phi_f = L.phi64;
+      if (k + 1 < mg.lv.size()) {
+        if ((e = launch_diagonal_lv(c, view(L), CHNS_OP_PRESSURE, CHNS_FP64, L.dinv64, true, L.v64[0], L.v64[3],
+                                    st)))
+          return e;
+        if ((e = launch_diagonal_lv(c, view(L), CHNS_OP_PRESSURE, CHNS_FP32, L.dinv32, true, L.v32[0], L.v32[3],
+                                    st)))
+          return e;
+      }
+    }
+    ApplyOut plain{};
+    for (int j = 0; j < n; ++j) {
+      k_unit<<<blocks(n), kT, 0, st>>>(B.v64[0], j, n);
+      if ((e = launch_apply_lv(c, view(B), CHNS_OP_PRESSURE, CHNS_FP64, B.v64[0], B.v64[3], st, plain))) return e;
+      k_copy_col<<<blocks(n), kT, 0, st>>>(B.v64[3], B.dense, j, n);
+    }
+    CHNS_HIP(hipGetLastError());
+    return CHNS_OK;
+  };
+  if ((rc = run_captured(c, &mg.setup_exec, s, device_part))) return rc;
+  std::vector<double> A((size_t)n * n);
+  CHNS_HIP(hipMemcpyAsync(A.data(), B.dense, sizeof(double) * A.size(), hipMemcpyDeviceToHost, s));
+  CHNS_HIP(hipStreamSynchronize(s));
+  if ((rc = dense_inverse(A, n))) {
+    set_error("coarsest multigrid operator is not positive semi-definite");
+    return rc;
+  }
+  CHNS_HIP(hipMemcpy(B.inv64, A.data(), sizeof(double) * A.size(), hipMemcpyHostToDevice));
+  k_to32<<<blocks((int64_t)n * n), kT, 0, s>>>(B.inv64, B.inv32, (int64_t)n * n);
+  CHNS_HIP(hipGetLastError());
+  mg.setup_valid = true;
+  return CHNS_OK;
+}
+
+int mg_vcycle64(Ctx& c, const double* r, double* z, hipStream_t s) { return vcycle<double>(c, 0, r, z, s); }
+int mg_vcycle32(Ctx& c, const float* r, float* z, hipStream_t s) { return vcycle<float>(c, 0, r, z, s); }
+
+}  // namespace chns

@@ -48,7 +48,7 @@ __device__ void block_partials(double (&v)[NV], double* partials) {
   }
 }
 
-enum FinMode { FIN_STORE = 0, FIN_CG_INIT = 1, FIN_CG_UPDATE = 2 };
+enum FinMode { FIN_STORE = 0, FIN_CG_INIT = 1, FIN_CG_UPDATE = 2, FIN_FCG_UPDATE = 3 };
 
 // Fixed-order totals of nv partial arrays, then the scalar update of `mode`.
 // 1024 threads, each with four independent running sums, so the few thousand
@@ -58,7 +58,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const double* partials
                                                           DevScalars* sc, double* out, int respect_done) {
   __shared__ double sh[kFinThreads / 64];
   if (respect_done && sc->done) return;
-  double tot[2] = {0.0, 0.0};
+  double tot[3] = {0.0, 0.0, 0.0};
   for (int k = 0; k < nv; ++k) {
     const double* pk = partials + k * kStride;
     double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
@@ -90,10 +90,12 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const double* partials
     sc->it = 0;
     sc->done = (tot[1] <= sc->tol2) ? 1 : 0;
   } else {
+    // CG: beta = (r_new.z_new) / (r_old.z_old); flexible CG (Polak-Ribiere
+    // form): beta = z_new.(r_new - r_old) / (r_old.z_old)
     sc->rz_old = sc->rz;
     sc->rz = tot[0];
     sc->rr = tot[1];
-    sc->beta = tot[0] / sc->rz_old;
+    sc->beta = (mode == FIN_FCG_UPDATE ? tot[0] - tot[2] : tot[0]) / sc->rz_old;
     sc->it = sc->it + 1;
     sc->done = (tot[1] <= sc->tol2 || sc->it >= sc->max_it || !(tot[1] == tot[1])) ? 1 : 0;
   }
@@ -205,6 +207,65 @@ __global__ void k_cg_p(T* p, const T* z, int64_t n, const DevScalars* sc, int ch
     p[i] = z[i] + beta * p[i];
 }
 
+// r = b - q; partial r.r (slot 1)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_cg_init_nopc(const T* b, const T* q, T* r, int64_t n,
+                                                           double* partials) {
+  double v[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+    T ri = b[i] - q[i];
+    r[i] = ri;
+    v[1] += (double)ri * (double)ri;
+  }
+  block_partials<2>(v, partials);
+}
+// alpha = rz/pq; x += alpha p; (r_old = r); r -= alpha q; partial r.r (slot 1)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_cg_update_nopc(T* x, T* r, T* r_old, const T* p, const T* q, int64_t n,
+                                                             const DevScalars* sc, double* partials) {
+  if (sc->done) return;
+  const T a = (T)(sc->rz / sc->pq);
+  double v[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+    const T ri = r[i];
+    if (r_old) r_old[i] = ri;
+    x[i] += a * p[i];
+    const T rn = ri - a * q[i];
+    r[i] = rn;
+    v[1] += (double)rn * (double)rn;
+  }
+  block_partials<2>(v, partials);
+}
+// partial r.z (slot 0) and r_old.z (slot 2, flexible CG); slot 1 is left alone
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_dot_rz(const T* r, const T* z, const T* r_old, int64_t n,
+                                                     const DevScalars* sc, double* partials, int respect_done) {
+  __shared__ double sh[3][4];
+  if (respect_done && sc->done) return;
+  double a = 0.0, b = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+    a += (double)r[i] * (double)z[i];
+    if (r_old) b += (double)r_old[i] * (double)z[i];
+  }
+  a = wsum(a);
+  b = wsum(b);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][w] = a;
+    sh[2][w] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = (sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3]);
+    partials[2 * kStride + blockIdx.x] = (sh[2][0] + sh[2][1]) + (sh[2][2] + sh[2][3]);
+  }
+}
+template <typename T>
+__global__ void k_copy(T* dst, const T* src, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+    dst[i] = src[i];
+}
+
 // x64 += scale * d32 ; r32 = (r64 - ...) handled separately
 __global__ void k_ir_correct(double* x, const float* d, double scale, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
@@ -268,43 +329,147 @@ int read_scalars(Ctx& c, hipStream_t s) {
   return CHNS_OK;
 }
 
-// Jacobi-PCG on A x = b with b already in range(A) (1^T b = 0).  Precision T
-// for vectors and the operator; dots in FP64.  Stops when |r|^2 <= tol2.
+// Host-side convergence polling that keeps the device busy: after each
+// iteration the device scalars are copied (async) into a pinned ring slot and
+// an event is recorded; the host only waits for the iteration `depth - 1`
+// behind the one it has just enqueued.  Iterations enqueued after
+// convergence are no-ops for the CG kernels (they test the flag).
+struct Poller {
+  Ctx& c;
+  hipStream_t s;
+  int depth;
+  std::vector<hipEvent_t> ev;
+  DevScalars* ring = nullptr;
+  Poller(Ctx& cc, hipStream_t ss, int d) : c(cc), s(ss), depth(d), ev(d, nullptr) {}
+  ~Poller() {
+    for (auto e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (ring) (void)hipHostFree(ring);
+  }
+  int init() {
+    CHNS_HIP(hipHostMalloc((void**)&ring, sizeof(DevScalars) * depth, hipHostMallocDefault));
+    for (auto& e : ev) CHNS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return CHNS_OK;
+  }
+  int post(int it) {
+    const int k = it % depth;
+    CHNS_HIP(hipMemcpyAsync(&ring[k], c.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+    CHNS_HIP(hipEventRecord(ev[k], s));
+    return CHNS_OK;
+  }
+  // wait for iteration `it` (already posted); returns its scalars
+  int wait(int it, DevScalars* out) {
+    const int k = it % depth;
+    CHNS_HIP(hipEventSynchronize(ev[k]));
+    *out = ring[k];
+    return CHNS_OK;
+  }
+};
+
+enum PcKind { PCK_NONE = 0, PCK_JACOBI = 1, PCK_GMG = 2 };
+
 template <typename T>
-int pcg(Ctx& c, const T* b, T* x, const T* dinv, double tol2, int max_it, int check_every, hipStream_t s,
-        int* iters, double* rr_out) {
+int apply_pc(Ctx& c, int pc, const T* r, T* z, hipStream_t s) {
+  if (pc == PCK_GMG) {
+    if constexpr (sizeof(T) == 8) return mg_vcycle64(c, (const double*)r, (double*)z, s);
+    else return mg_vcycle32(c, (const float*)r, (float*)z, s);
+  }
+  set_error("unknown preconditioner");
+  return CHNS_EINVAL;
+}
+
+// Preconditioned CG on A x = b with b in range(A) (1^T b = 0).  Vectors and
+// the operator in precision T, dot products in FP64.  Jacobi (or none) is
+// fused into the vector update; other preconditioners run between the update
+// and the dot products.  flexible selects the Polak-Ribiere beta, which keeps
+// CG convergent for a preconditioner that varies between iterations.
+template <typename T>
+int pcg(Ctx& c, const T* b, T* x, int pc, const T* dinv, bool flexible, double tol2, int max_it, int depth,
+        bool graphs, hipStream_t s, int* iters, double* rr_out) {
   const int64_t n = c.dm.n;
   const int prec = sizeof(T) == 8 ? CHNS_FP64 : CHNS_FP32;
   for (int k = 0; k < 4; ++k)
     if (ensure_work<T>(c, k)) return CHNS_ENOMEM;
+  if (flexible && ensure_work<T>(c, 6)) return CHNS_ENOMEM;
   T** w = work<T>(c);
   T *r = w[0], *z = w[1], *p = w[2], *q = w[3];
+  T* r_old = flexible ? w[6] : nullptr;
+  const bool fused_pc = pc == PCK_NONE || pc == PCK_JACOBI;
   const unsigned g = grid_for(n);
+  Poller poll(c, s, std::max(1, depth));
+  int rc = poll.init();
+  if (rc) return rc;
   k_init_scalars<<<1, 1, 0, s>>>(c.sc, tol2, max_it);
   ApplyOut plain{};
-  int rc = launch_apply(c, CHNS_OP_PRESSURE, prec, x, q, s, plain);
-  if (rc) return rc;
-  k_cg_init<T><<<g, kThreads, 0, s>>>(b, q, r, z, p, dinv, n, c.sc, c.partials, c.counter);
+  if ((rc = launch_apply(c, CHNS_OP_PRESSURE, prec, x, q, s, plain))) return rc;
+  if (fused_pc) {
+    k_cg_init<T><<<g, kThreads, 0, s>>>(b, q, r, z, p, pc == PCK_JACOBI ? dinv : nullptr, n, c.sc, c.partials,
+                                        c.counter);
+  } else {
+    k_cg_init_nopc<T><<<g, kThreads, 0, s>>>(b, q, r, n, c.partials);
+    if ((rc = apply_pc<T>(c, pc, r, z, s))) return rc;
+    k_dot_rz<T><<<g, kThreads, 0, s>>>(r, z, nullptr, n, c.sc, c.partials, 0);
+    k_copy<T><<<g, kThreads, 0, s>>>(p, z, n);
+  }
   CHNS_HIP(hipGetLastError());
   if ((rc = fin(c, s, g, 2, FIN_CG_INIT, nullptr, 0))) return rc;
   ApplyOut fused{};
   fused.fuse_dot = true;
   fused.done = &c.sc->done;
-  int it = 0;
-  while (true) {
-    rc = launch_apply(c, CHNS_OP_PRESSURE, prec, p, q, s, fused);
-    if (rc) return rc;
-    k_cg_update<T><<<g, kThreads, 0, s>>>(x, r, z, p, q, dinv, n, c.sc, c.partials, c.counter);
-    if ((rc = fin(c, s, g, 2, FIN_CG_UPDATE, nullptr, 1))) return rc;
-    k_cg_p<T><<<g, kThreads, 0, s>>>(p, z, n, c.sc, 1);
+  auto iteration = [&](hipStream_t st) -> int {
+    int e;
+    if ((e = launch_apply(c, CHNS_OP_PRESSURE, prec, p, q, st, fused))) return e;
+    if (fused_pc) {
+      k_cg_update<T><<<g, kThreads, 0, st>>>(x, r, z, p, q, pc == PCK_JACOBI ? dinv : nullptr, n, c.sc,
+                                             c.partials, c.counter);
+      if ((e = fin(c, st, g, 2, FIN_CG_UPDATE, nullptr, 1))) return e;
+    } else {
+      k_cg_update_nopc<T><<<g, kThreads, 0, st>>>(x, r, r_old, p, q, n, c.sc, c.partials);
+      if ((e = apply_pc<T>(c, pc, r, z, st))) return e;
+      k_dot_rz<T><<<g, kThreads, 0, st>>>(r, z, r_old, n, c.sc, c.partials, 1);
+      if ((e = fin(c, st, g, flexible ? 3 : 2, flexible ? FIN_FCG_UPDATE : FIN_CG_UPDATE, nullptr, 1))) return e;
+    }
+    k_cg_p<T><<<g, kThreads, 0, st>>>(p, z, n, c.sc, 1);
     CHNS_HIP(hipGetLastError());
-    ++it;
-    if (it % check_every == 0 || it >= max_it) {
-      rc = read_scalars(c, s);
-      if (rc) return rc;
-      if (c.sc_host->done || it >= max_it) break;
+    return CHNS_OK;
+  };
+  // one HIP graph per (precision, preconditioner, variant); buffers are
+  // context-owned, so the graph stays valid across solves
+  hipGraphExec_t exec = nullptr;
+  if (graphs && !c.prof) {
+    for (auto& ge : c.graphs)
+      if (ge.prec == prec && ge.pc == pc && ge.flexible == (int)flexible) exec = ge.exec;
+    if (!exec) {
+      hipGraph_t graph = nullptr;
+      CHNS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+      int e = iteration(s);
+      hipError_t ce = hipStreamEndCapture(s, &graph);
+      if (e) return e;
+      if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+      hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ie != hipSuccess) return hip_fail(ie, "hipGraphInstantiate");
+      c.graphs.push_back({prec, pc, (int)flexible, exec});
     }
   }
+  DevScalars snap{};
+  int it = 0;
+  while (true) {
+    if (exec) {
+      CHNS_HIP(hipGraphLaunch(exec, s));
+    } else if ((rc = iteration(s))) {
+      return rc;
+    }
+    if ((rc = poll.post(it))) return rc;
+    ++it;
+    if (it >= max_it) break;
+    if (it >= depth) {
+      if ((rc = poll.wait(it - depth, &snap))) return rc;
+      if (snap.done) break;
+    }
+  }
+  CHNS_HIP(hipStreamSynchronize(s));
+  if ((rc = read_scalars(c, s))) return rc;
   *iters = c.sc_host->it;
   *rr_out = c.sc_host->rr;
   return CHNS_OK;
@@ -317,21 +482,34 @@ int launch_set_phase(Ctx& c, const double* phi, const double* prev, hipStream_t 
   CHNS_HIP(hipGetLastError());
   c.phi_set = true;
   c.diag_valid = false;
+  if (c.mg) c.mg->setup_valid = false;
   return CHNS_OK;
 }
 
-int solve_pressure_impl(Ctx& c, const double* b_in, double* x, const chns_solve_opts& o, chns_solve_stats& st,
-                        hipStream_t s) {
+int solve_pressure_impl(Ctx& c, const double* b_in, double* x_out, const chns_solve_opts& o,
+                        chns_solve_stats& st, hipStream_t caller) {
   const int64_t n = c.dm.n;
+  // work on the context stream after everything already queued on the caller's
+  CHNS_HIP(hipEventRecord(c.ev_in, caller));
+  CHNS_HIP(hipStreamWaitEvent(c.work, c.ev_in, 0));
+  hipStream_t s = c.work;
+  if (!c.xw64) c.xw64 = (double*)c.dalloc(sizeof(double) * n);
+  if (!c.xw64) return CHNS_ENOMEM;
+  double* x = c.xw64;
+  CHNS_HIP(hipMemcpyAsync(x, x_out, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  const bool graphs = o.no_graphs == 0;
   const unsigned g = grid_for(n);
   if (!c.phi_set) {
     set_error("set_phase_field must be called before solve_pressure");
     return CHNS_ESTATE;
   }
-  if (o.pc != CHNS_PC_JACOBI && o.pc != CHNS_PC_NONE) {
+  if (o.pc != CHNS_PC_JACOBI && o.pc != CHNS_PC_NONE && o.pc != CHNS_PC_GMG) {
     set_error("requested preconditioner is not available in this build");
     return CHNS_EINVAL;
   }
+  const int pck = o.pc == CHNS_PC_JACOBI ? PCK_JACOBI : (o.pc == CHNS_PC_GMG ? PCK_GMG : PCK_NONE);
+  // poll depth: cheap iterations can run far ahead, expensive ones not
+  const int depth = pck == PCK_GMG ? 2 : o.check_every;
   Timer t_setup;
   // projected right-hand side kept in w64[4]
   for (int k = 0; k < 6; ++k)
@@ -346,15 +524,26 @@ int solve_pressure_impl(Ctx& c, const double* b_in, double* x, const chns_solve_
   if ((rc = fin(c, s, g, 1, FIN_STORE, &c.sc->bb, 0))) return rc;
   CHNS_HIP(hipGetLastError());
   const bool mixed = o.mode == CHNS_MODE_MIXED_IR;
+  if (o.pc == CHNS_PC_GMG) {
+    if ((rc = mg_build(c))) return rc;
+    if (!c.mg->setup_valid && (rc = mg_setup(c, s))) return rc;
+  }
   if (o.pc == CHNS_PC_JACOBI) {
     if (!c.diag_valid) {
       if (!c.diag64) c.diag64 = (double*)c.dalloc(sizeof(double) * n);
       if (!c.diag32) c.diag32 = (float*)c.dalloc(sizeof(float) * n);
       if (!c.diag64 || !c.diag32) return CHNS_ENOMEM;
-      rc = launch_diagonal(c, CHNS_OP_PRESSURE, CHNS_FP64, c.diag64, true, s);
-      if (rc) return rc;
-      rc = launch_diagonal(c, CHNS_OP_PRESSURE, CHNS_FP32, c.diag32, true, s);
-      if (rc) return rc;
+      for (int k = 6; k < 8; ++k) {
+        if (!c.w64[k]) c.w64[k] = (double*)c.dalloc(sizeof(double) * n * 3);
+        if (!c.w32[k]) c.w32[k] = (float*)c.dalloc(sizeof(float) * n * 3);
+        if (!c.w64[k] || !c.w32[k]) return CHNS_ENOMEM;
+      }
+      auto diag_part = [&](hipStream_t st) -> int {
+        int e = launch_diagonal(c, CHNS_OP_PRESSURE, CHNS_FP64, c.diag64, true, st);
+        if (e) return e;
+        return launch_diagonal(c, CHNS_OP_PRESSURE, CHNS_FP32, c.diag32, true, st);
+      };
+      if ((rc = graphs ? run_captured(c, &c.diag_exec, s, diag_part) : diag_part(s))) return rc;
       c.diag_valid = true;
     }
   }
@@ -367,7 +556,7 @@ int solve_pressure_impl(Ctx& c, const double* b_in, double* x, const chns_solve_
   st.outer_iterations = 0;
   st.fallback = 0;
   if (bb == 0.0) {
-    k_fill<double><<<g, kThreads, 0, s>>>(x, 0.0, n);
+    k_fill<double><<<g, kThreads, 0, s>>>(x_out, 0.0, n);
     CHNS_HIP(hipStreamSynchronize(s));
     st.rel_residual = 0.0;
     st.ms_solve = t_solve.ms();
@@ -380,8 +569,7 @@ int solve_pressure_impl(Ctx& c, const double* b_in, double* x, const chns_solve_
   if (!mixed) {
     int it = 0;
     double rr = 0;
-    rc = pcg<double>(c, b, x, o.pc == CHNS_PC_JACOBI ? c.diag64 : nullptr, tol2, o.max_it, o.check_every, s, &it,
-                     &rr);
+    rc = pcg<double>(c, b, x, pck, c.diag64, false, tol2, o.max_it, depth, graphs, s, &it, &rr);
     if (rc) return rc;
     st.iterations = it;
     st.outer_iterations = 1;
@@ -415,8 +603,8 @@ int solve_pressure_impl(Ctx& c, const double* b_in, double* x, const chns_solve_
       int it = 0;
       double rri = 0;
       const double itol = o.inner_rtol;
-      rc = pcg<float>(c, r32, d32, o.pc == CHNS_PC_JACOBI ? c.diag32 : nullptr, itol * itol, o.max_it - total,
-                      o.check_every, s, &it, &rri);
+      rc = pcg<float>(c, r32, d32, pck, c.diag32, false, itol * itol, o.max_it - total, depth, graphs, s, &it,
+                      &rri);
       if (rc) return rc;
       total += it;
       k_ir_correct<<<g, kThreads, 0, s>>>(x, d32, rn, n);
@@ -434,6 +622,7 @@ int solve_pressure_impl(Ctx& c, const double* b_in, double* x, const chns_solve_
   k_residual<<<g, kThreads, 0, s>>>(b, q64, r64, n, c.partials, c.counter, &c.sc->rr);
   CHNS_HIP(hipGetLastError());
   if ((rc = fin(c, s, g, 1, FIN_STORE, &c.sc->rr, 0))) return rc;
+  CHNS_HIP(hipMemcpyAsync(x_out, x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   rc = read_scalars(c, s);
   if (rc) return rc;
   st.rel_residual = std::sqrt(c.sc_host->rr / bb);

@@ -468,6 +468,18 @@ struct Builder {
               std::vector<std::vector<int32_t>>& brick_elems) {
     const int64_t E = m.n_elems();
     std::vector<uint8_t> taken(E, 0);
+    // largest brick edge that still leaves >= 1024 bricks (enough wavefronts
+    // to fill the GPU); a positive spec.brick_max overrides the choice
+    int bmax = 1;
+    for (int B = 8; B >= 1; B >>= 1) {
+      int64_t per = 1;
+      for (int d = 0; d < dim; ++d) per *= B;
+      if (E / per >= 1024) {
+        bmax = B;
+        break;
+      }
+    }
+    if (sp.brick_max > 0) bmax = sp.brick_max;
     for (int c = 0; c < kBrickClasses; ++c) {
       BrickClass& bc = m.cls[c];
       int B = brick_side(c);
@@ -517,7 +529,7 @@ struct Builder {
           continue;
         }
         int32_t s = size_at(l);
-        bool ok = l >= b && i + n <= E;
+        bool ok = B <= bmax && l >= b && i + n <= E;
         for (int d = 0; ok && d < dim; ++d)
           if (m.leaf_anchor[3 * i + d] % (B * s)) ok = false;
         for (int64_t j = i; ok && j < i + n; ++j)
@@ -726,13 +738,28 @@ struct Builder {
     m.dim = dim;
     m.max_level = L;
     refine(m.leaf_level, m.leaf_anchor);
+    return finish();
+  }
+
+  // From an explicit leaf list already stored in m (levels, anchors).
+  int run_leaves() {
+    if (dim != 2 && dim != 3) {
+      msg = "dim must be 2 or 3";
+      return CHNS_EINVAL;
+    }
+    m.dim = dim;
+    m.max_level = L;
+    return finish();
+  }
+
+  int finish() {
     balance(m.leaf_level, m.leaf_anchor);
     int lmin = 99, lmax = -1;
     for (auto l : m.leaf_level) {
       lmin = std::min<int>(lmin, l);
       lmax = std::max<int>(lmax, l);
     }
-    m.uniform = lmin == lmax;
+    m.uniform = lmin == lmax && lmax == L;
     m.node_order = m.uniform ? 0 : 1;
     std::vector<int32_t> elem_corner, all_entry, all_coords;
     int rc = nodes(elem_corner, all_entry, all_coords);
@@ -754,6 +781,191 @@ struct Builder {
 };
 
 }  // namespace
+
+int build_host_mesh_from_leaves(int dim, int max_level, const std::vector<int8_t>& level,
+                                const std::vector<int32_t>& anchor, HostMesh& m, std::string& msg) {
+  try {
+    chns_mesh_spec sp{};
+    sp.dim = dim;
+    sp.min_level = 0;
+    sp.max_level = max_level;
+    sp.rule = CHNS_RULE_UNIFORM;
+    Builder b(sp, m, msg);
+    m.leaf_level = level;
+    m.leaf_anchor = anchor;
+    return b.run_leaves();
+  } catch (const std::bad_alloc&) {
+    msg = "host allocation failed while building a coarse mesh";
+    return CHNS_ENOMEM;
+  } catch (const std::logic_error& e) {
+    msg = std::string("internal consistency check failed: ") + e.what();
+    return CHNS_EINVAL;
+  }
+}
+
+void truncate_leaves(const HostMesh& f, int k, std::vector<int8_t>& lev, std::vector<int32_t>& anc) {
+  const int sh = f.max_level - k;
+  lev.clear();
+  anc.clear();
+  for (int64_t e = 0; e < f.n_elems(); ++e) {
+    int l = f.leaf_level[e];
+    int8_t nl = (int8_t)std::min(l, k);
+    int32_t a[3];
+    for (int d = 0; d < 3; ++d) {
+      int32_t v = f.leaf_anchor[3 * e + d] >> sh;
+      // anchor of the level-nl ancestor in units of 2^-k
+      const int32_t s = 1 << (k - nl);
+      a[d] = (v / s) * s;
+    }
+    const size_t n = lev.size();
+    if (n > 0 && lev[n - 1] == nl && anc[3 * n - 3] == a[0] && anc[3 * n - 2] == a[1] && anc[3 * n - 1] == a[2])
+      continue;  // descendants of one ancestor are contiguous in Morton order
+    lev.push_back(nl);
+    anc.insert(anc.end(), a, a + 3);
+  }
+}
+
+namespace {
+// node coordinate -> entry (independent id >= 0, hanging -(h+1))
+struct NodeLookup {
+  std::vector<uint64_t> key;
+  std::vector<int32_t> val;
+  uint64_t s1;
+  int dim;
+  explicit NodeLookup(const HostMesh& m) : s1((uint64_t)(1 << m.max_level) + 1), dim(m.dim) {
+    std::vector<std::pair<uint64_t, int32_t>> kv;
+    kv.reserve(m.n_indep + m.n_hanging);
+    for (int64_t i = 0; i < m.n_indep; ++i) kv.push_back({enc(&m.indep_coords[3 * i]), (int32_t)i});
+    for (int64_t h = 0; h < m.n_hanging; ++h) kv.push_back({enc(&m.hang_coords[3 * h]), -(int32_t)(h + 1)});
+    std::sort(kv.begin(), kv.end());
+    for (auto& p : kv) {
+      key.push_back(p.first);
+      val.push_back(p.second);
+    }
+  }
+  uint64_t enc(const int32_t* c) const {
+    uint64_t k = 0;
+    for (int d = dim - 1; d >= 0; --d) k = k * s1 + (uint64_t)c[d];
+    return k;
+  }
+  bool find(const int32_t* c, int32_t* out) const {
+    uint64_t k = enc(c);
+    auto it = std::lower_bound(key.begin(), key.end(), k);
+    if (it == key.end() || *it != k) return false;
+    *out = val[it - key.begin()];
+    return true;
+  }
+};
+
+void to_csr(const std::vector<std::vector<std::pair<int32_t, double>>>& rows, std::vector<int32_t>& ptr,
+            std::vector<int32_t>& col, std::vector<double>& val) {
+  ptr.assign(1, 0);
+  col.clear();
+  val.clear();
+  for (auto& r : rows) {
+    for (auto& e : r) {
+      col.push_back(e.first);
+      val.push_back(e.second);
+    }
+    ptr.push_back((int32_t)col.size());
+  }
+}
+}  // namespace
+
+int build_transfer(const HostMesh& fine, const HostMesh& coarse, Transfer& t, std::string& msg) {
+  const int dim = fine.dim;
+  if (coarse.max_level != fine.max_level - 1 || coarse.dim != dim) {
+    msg = "transfer needs meshes one level apart";
+    return CHNS_EINVAL;
+  }
+  const int Lc = coarse.max_level;
+  const int32_t side_f = 1 << fine.max_level;
+  const int nc = 1 << dim;
+  KeySet leaves((size_t)coarse.n_elems() * 2);
+  for (int64_t e = 0; e < coarse.n_elems(); ++e)
+    leaves.insert(leaf_key(dim, coarse.leaf_level[e], &coarse.leaf_anchor[3 * e]));
+  NodeLookup cl(coarse), fl(fine);
+  auto expand = [&](const HostMesh& m, int32_t entry, double w, std::vector<std::pair<int32_t, double>>& row) {
+    if (entry >= 0) {
+      row.push_back({entry, w});
+      return;
+    }
+    const int64_t h = -entry - 1;
+    const int np = m.hang_npar[h];
+    for (int q = 0; q < np; ++q) row.push_back({m.hang_parents[4 * h + q], w / np});
+  };
+  auto merge = [](std::vector<std::pair<int32_t, double>>& row) {
+    std::sort(row.begin(), row.end());
+    std::vector<std::pair<int32_t, double>> out;
+    for (auto& e : row) {
+      if (!out.empty() && out.back().first == e.first) out.back().second += e.second;
+      else out.push_back(e);
+    }
+    row.clear();
+    for (auto& e : out)
+      if (e.second != 0.0) row.push_back(e);
+  };
+  // prolongation rows: fine independent node <- coarse Q1 field at its position
+  std::vector<std::vector<std::pair<int32_t, double>>> P(fine.n_indep);
+  for (int64_t i = 0; i < fine.n_indep; ++i) {
+    const int32_t* x = &fine.indep_coords[3 * i];
+    int found = -1;
+    int32_t af[3] = {0, 0, 0}, ac[3] = {0, 0, 0};
+    int32_t sf = 0;
+    for (int mlev = Lc; mlev >= 0 && found < 0; --mlev) {
+      sf = 1 << (fine.max_level - mlev);  // coarse octant edge in fine units
+      for (int d = 0; d < dim; ++d) {
+        const int32_t q2 = 2 * x[d] + (x[d] < side_f ? 1 : -1);  // doubled, nudged inside
+        af[d] = (q2 / (2 * sf)) * sf;
+        ac[d] = af[d] / 2;
+      }
+      if (leaves.contains(leaf_key(dim, mlev, ac))) found = mlev;
+    }
+    if (found < 0) {
+      msg = "fine node outside the coarse mesh";
+      return CHNS_EINVAL;
+    }
+    for (int a = 0; a < nc; ++a) {
+      double w = 1.0;
+      int32_t cc[3] = {0, 0, 0};
+      for (int d = 0; d < dim; ++d) {
+        const int bit = (a >> d) & 1;
+        const double xi = (double)(x[d] - af[d]) / sf;
+        w *= bit ? xi : 1.0 - xi;
+        cc[d] = ac[d] + bit * (sf / 2);
+      }
+      if (w == 0.0) continue;
+      int32_t ent;
+      if (!cl.find(cc, &ent)) {
+        msg = "coarse leaf corner missing";
+        return CHNS_EINVAL;
+      }
+      expand(coarse, ent, w, P[i]);
+    }
+    merge(P[i]);
+  }
+  to_csr(P, t.P_ptr, t.P_col, t.P_val);
+  // restriction = transpose (coarse rows, fine columns in increasing order)
+  std::vector<std::vector<std::pair<int32_t, double>>> R(coarse.n_indep);
+  for (int64_t i = 0; i < fine.n_indep; ++i)
+    for (auto& e : P[i]) R[e.first].push_back({(int32_t)i, e.second});
+  to_csr(R, t.R_ptr, t.R_col, t.R_val);
+  // injection of nodal fields: coarse node value = fine field at that point
+  std::vector<std::vector<std::pair<int32_t, double>>> I(coarse.n_indep);
+  for (int64_t j = 0; j < coarse.n_indep; ++j) {
+    int32_t xf[3] = {0, 0, 0};
+    for (int d = 0; d < dim; ++d) xf[d] = 2 * coarse.indep_coords[3 * j + d];
+    int32_t ent;
+    if (!fl.find(xf, &ent)) {
+      msg = "coarse node is not a fine node";
+      return CHNS_EINVAL;
+    }
+    expand(fine, ent, 1.0, I[j]);
+    merge(I[j]);
+  }
+  to_csr(I, t.I_ptr, t.I_col, t.I_val);
+  return CHNS_OK;
+}
 
 int build_host_mesh(const chns_mesh_spec& spec, HostMesh& m, std::string& msg) {
   try {

@@ -65,5 +65,25 @@ struct HostMesh {
 
 // Build everything from a spec; returns CHNS_OK or an error with msg set.
 int build_host_mesh(const chns_mesh_spec& spec, HostMesh& m, std::string& msg);
+// Build from an explicit leaf list (levels and anchors in units of 2^-max_level).
+int build_host_mesh_from_leaves(int dim, int max_level, const std::vector<int8_t>& level,
+                                const std::vector<int32_t>& anchor, HostMesh& m, std::string& msg);
+// Leaves of `fine` with every leaf deeper than k replaced by its level-k
+// ancestor, in units of 2^-k (truncation keeps 2:1 balance).
+void truncate_leaves(const HostMesh& fine, int k, std::vector<int8_t>& level, std::vector<int32_t>& anchor);
+
+// Grid transfer between two meshes one level apart (coarse = fine truncated):
+// P (fine rows) evaluates the coarse Q1 field, hanging constraints of both
+// meshes included; R = P^T (coarse rows); I injects a fine nodal field into
+// the coarse nodes (value of the fine field at the coarse node).
+struct Transfer {
+  std::vector<int32_t> P_ptr, P_col;
+  std::vector<double> P_val;
+  std::vector<int32_t> R_ptr, R_col;
+  std::vector<double> R_val;
+  std::vector<int32_t> I_ptr, I_col;
+  std::vector<double> I_val;
+};
+int build_transfer(const HostMesh& fine, const HostMesh& coarse, Transfer& t, std::string& msg);
 
 }  // namespace chns

@@ -138,19 +138,21 @@ def _rhs(pair, seed=1):
     return ci.rhs_field(pair.x_unit, amps, waves)
 
 
+@pytest.mark.parametrize("pc", ["jacobi", "gmg"])
 @pytest.mark.parametrize("mode", ["fp64", "mixed"])
-def test_solve_pressure_reaches_1e8(case, mode):
+def test_solve_pressure_reaches_1e8(case, mode, pc):
     pair, phi, A = case
     ctx = _ctx(pair)
     ctx.set_phase_field(_dev(phi))
     f = _rhs(pair)
     b = ctx.apply(ctx.MASS, _dev(f))
-    x, st = ctx.solve_pressure(b, rtol=1e-8, mode=mode)
+    x, st = ctx.solve_pressure(b, rtol=1e-8, mode=mode, pc=pc)
     xo = pair.to_orc(x.cpu().numpy())
     bo = pair.to_orc(b.cpu().numpy())
     bo = bo - bo.mean()
     rel = np.linalg.norm(bo - A @ xo) / np.linalg.norm(bo)
-    print(f"{mode}: it={st.iterations} outer={st.outer_iterations} lib_rel={st.rel_residual:.3e} oracle_rel={rel:.3e}")
+    print(f"{mode}/{pc}: it={st.iterations} outer={st.outer_iterations} lib_rel={st.rel_residual:.3e} "
+          f"oracle_rel={rel:.3e}")
     assert st.rel_residual <= 1e-8
     assert rel <= 1.05e-8
     assert abs(xo.sum()) <= 1e-10 * np.abs(xo).sum()
@@ -158,3 +160,44 @@ def test_solve_pressure_reaches_1e8(case, mode):
         # same system solved by the oracle's own PCG: solutions agree to the solve tolerance
         xr, it, _ = krylov.pcg(A, bo, rtol=1e-11, M_inv_diag=1.0 / A.diagonal(), singular=True)
         assert np.linalg.norm(xo - xr) / np.linalg.norm(xr) <= 1e-5
+
+
+def test_gmg_cuts_iterations_and_is_reused_across_phase_fields():
+    pair = Pair("uniform", 3, 5, 5)
+    A_phi = pair.phi("drops", cn=0.02)
+    ctx = _ctx(pair)
+    f = _rhs(pair)
+    b = ctx.apply(ctx.MASS, _dev(f))
+    its = {}
+    for pc in ("jacobi", "gmg"):
+        ctx.set_phase_field(_dev(A_phi))
+        _, st = ctx.solve_pressure(b, rtol=1e-8, pc=pc)
+        its[pc] = st.iterations
+    assert its["gmg"] * 4 < its["jacobi"], its
+    # a new phase field re-runs the level set-up on the same hierarchy
+    phi2 = pair.phi("drops", seed=5, cn=0.02)
+    ctx.set_phase_field(_dev(phi2))
+    x, st = ctx.solve_pressure(b, rtol=1e-8, pc="gmg")
+    A2 = fem.pp_matrix(pair.orc, pair.to_orc(phi2), RHO_P, RHO_M)
+    bo = pair.to_orc(b.cpu().numpy())
+    bo = bo - bo.mean()
+    rel = np.linalg.norm(bo - A2 @ pair.to_orc(x.cpu().numpy())) / np.linalg.norm(bo)
+    assert rel <= 1.05e-8
+
+
+@pytest.mark.parametrize("pc,mode", [("jacobi", "fp64"), ("gmg", "fp64"), ("gmg", "mixed")])
+def test_graph_replays_match_eager_launches(pc, mode):
+    # every Krylov iteration replays one captured HIP graph; the same solve
+    # launched eagerly must give the bitwise identical iterate, on repeated
+    # replays with eager work in between
+    pair = Pair("band", 3, 2, 5, band=0.03)
+    phi = pair.phi("bubble", cn=0.02)
+    ctx = _ctx(pair)
+    ctx.set_phase_field(_dev(phi))
+    b = ctx.apply(ctx.MASS, _dev(_rhs(pair)))
+    x_eager, st_e = ctx.solve_pressure(b, pc=pc, mode=mode, graphs=False)
+    for rep in range(3):
+        ctx.apply(ctx.PRESSURE, _dev(ci.normal_vector(rep, pair.lib.n_nodes)))  # eager work between replays
+        x_g, st_g = ctx.solve_pressure(b, pc=pc, mode=mode, graphs=True)
+        assert st_g.iterations == st_e.iterations
+        assert np.array_equal(x_g.cpu().numpy().view(np.int64), x_eager.cpu().numpy().view(np.int64))

@@ -119,8 +119,15 @@ def test_multi_sphere_and_callback_rules():
     _compare(m2, om.from_predicate(2, 1, L, pred2))
 
 
+def test_brick_size_heuristic_keeps_enough_bricks():
+    # automatic choice: the largest brick edge leaving >= 1024 bricks
+    for level, expect in ((7, [4096, 0, 0, 0]), (6, [0, 4096, 0, 0]), (5, [0, 0, 4096, 0]), (3, [0, 0, 0, 512])):
+        m = _lib_mesh(dim=3, min_level=level, max_level=level, rule="uniform")
+        assert m.summary()["n_bricks"] == expect, level
+
+
 def test_bricks_cover_uniform_mesh_with_largest_bricks():
-    m = _lib_mesh(dim=3, min_level=5, max_level=5, rule="uniform")
+    m = _lib_mesh(dim=3, min_level=5, max_level=5, rule="uniform", brick_max=8)
     s = m.summary()
     assert s["n_bricks"] == [64, 0, 0, 0]
     assert s["n_colors"] == 8
