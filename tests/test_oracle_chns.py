@@ -9,7 +9,8 @@ O(1) mu); advection moves a drop along the velocity; with u^ = J = 0 the
 VMS operator reduces to (1/dt) M_rho + (1/2Re) K_eta assembled through the
 independent routines of oracle/fem.py; tau_m closed form; full steps
 conserve mass, do not increase the total energy, and the projection
-reduces the divergence.
+reduces the divergence; a static drop carries the Young-Laplace pressure
+jump.
 """
 import numpy as np
 import pytest
@@ -156,3 +157,26 @@ def test_projection_reduces_divergence():
         return np.sqrt((el.detJ[:, None] * d ** 2).sum())
 
     assert div_norm(u) < 0.5 * div_norm(v)
+
+
+def test_static_drop_pressure_jump_follows_laplace_law():
+    # Young-Laplace: for the equilibrium profile the capillary term
+    # (Cn/We) d_j(d_i phi d_j phi) integrates across a circular interface of
+    # radius R to a pressure jump (Cn/We)(1/R) int phi'^2 dr = 2 sqrt(2)/(3 We R).
+    # The scheme's momentum equation sees the average of p^k and p^{k+1}
+    # (the velocity update carries dt/2 grad(p^{k+1} - p^k)), so the average
+    # of consecutive pressures is compared.  A flipped or mis-scaled capillary
+    # term, or a wrong factor in the pressure / update chain, fails this.
+    m, el, prm, x = _setup(level=6, cn=0.04, Re=1.0, We=1.0, Fr=1e12, rho_minus=1.0, eta_minus=1.0, dt=1e-3)
+    R = 0.25
+    st = chns.initial_state(el, prm, ci.phi_drop2d(x, radius=R, cn=prm.Cn))
+    c = np.argmin(np.linalg.norm(x - 0.5, axis=1))
+    far = np.argmin(np.linalg.norm(x - 0.05, axis=1))
+    laplace = 2.0 * np.sqrt(2.0) / (3.0 * prm.We * R)
+    p_prev = st.p.copy()
+    for _ in range(2):
+        st, _info = chns.step(el, prm, st)
+        avg = 0.5 * (st.p + p_prev)
+        assert avg[c] - avg[far] == pytest.approx(laplace, rel=0.05)
+        p_prev = st.p.copy()
+    assert np.abs(st.u).max() < 0.01
