@@ -191,6 +191,89 @@ typedef struct chns_solve_stats {
 int chns_solve_pressure(chns_ctx* ctx, const double* b, double* x, const chns_solve_opts* opts,
                         chns_solve_stats* stats, void* stream);
 
+/* ------------------------------------------------- CHNS forms and stepping */
+
+/* Coefficient fields of the CHNS operators (device FP64, copied into the
+ * context; the caller keeps ownership).  Vectors are component-blocked
+ * (dim * n_nodes).  Async.
+ *   CHNS_OP_MOMENTUM:    fields = {phi~, mu~, u^}: time-averaged phase field
+ *                        and chemical potential, extrapolated velocity
+ *                        u^ = (3 u^k - u^{k-1})/2 (Sec. 3, Def. 3; the
+ *                        mixture current J is built from grad mu~)
+ *   CHNS_OP_CH_JACOBIAN: fields = {phi^{k+1} (Newton iterate), phi^k, u~}
+ *                        (Def. 6)
+ * EINVAL for any other op.                                                 */
+int chns_set_coefficients(chns_ctx* ctx, int op, const double* const* fields, void* stream);
+
+/* Right-hand sides, residuals and energy densities assembled matrix-free with
+ * the same gather / quadrature / conflict-free scatter as the operators.    */
+enum {
+  CHNS_FORM_CH_RESIDUAL = 0, /* fields {x = [phi^{k+1}; mu^{k+1}] (2n), phi^k, mu^k, u~ (dim n)}
+                                -> (R_phi, R_mu), 2n (Def. 6)                   */
+  CHNS_FORM_VP_RHS = 1,      /* fields {phi~, mu~, u^, u^k, p^k} -> dim n, wall rows 0
+                                (Def. 3 right-hand side incl. gravity, Korteweg
+                                and the known part of the VMS fine scales)     */
+  CHNS_FORM_PP_RHS = 2,      /* fields {.. as VP_RHS .., v} -> n (Def. 4, including
+                                the fine-scale term of the predicted velocity)  */
+  CHNS_FORM_VU_RHS = 3,      /* fields {.. as PP_RHS .., p^{k+1}} -> dim n, wall rows 0
+                                (Def. 5)                                        */
+  CHNS_FORM_ENERGY = 4       /* fields {phi, u} -> n: each leaf's free energy
+                                (kinetic + mixing + gravitational, Sec. 2) split
+                                equally over its corners; the sum is the total */
+};
+int chns_assemble(chns_ctx* ctx, int form, const double* const* fields, double* out, void* stream);
+
+/* mu^0 as the L2 projection (q, mu) = (q, psi'(phi)) + Cn^2 (grad q, grad phi)
+ * (the paper does not state the initial chemical potential).  phi, mu:
+ * device FP64, n_nodes.  Synchronises `stream`.                             */
+int chns_initial_mu(chns_ctx* ctx, const double* phi, double* mu, void* stream);
+
+/* State of the time stepper: caller-owned device FP64 arrays, updated in
+ * place from step k to k + 1.  u and u_prev: dim * n_nodes (component
+ * blocked; zero on the walls); p, phi, mu: n_nodes.                        */
+typedef struct chns_state {
+  double* u;
+  double* u_prev;
+  double* p;
+  double* phi;
+  double* mu;
+} chns_state;
+
+typedef struct chns_step_opts {
+  int blocks;          /* passes of CH -> VP -> PP -> VU per step; default 2     */
+  double newton_rtol;  /* Newton stop |R| <= max(newton_rtol |R0|, newton_atol); 1e-8 */
+  double newton_atol;  /* default 1e-12                                          */
+  int max_newton;      /* default 20                                             */
+  double lin_rtol;     /* relative residual of every linear solve; default 1e-8 */
+  int max_it;          /* iteration cap of each linear solve; default 5000      */
+  int restart;         /* GMRES restart length, 1..128; default 64              */
+  int pp_pc;           /* CHNS_PC_JACOBI (default) or CHNS_PC_GMG                */
+  int pp_mode;         /* CHNS_MODE_FP64 (default) or CHNS_MODE_MIXED_IR         */
+  int no_graphs;       /* 1: no HIP graph replay of Krylov iterations           */
+} chns_step_opts;
+
+typedef struct chns_step_stats {
+  int newton_iterations[4]; /* per block                                        */
+  int ch_iterations;        /* GMRES iterations of all Newton corrections      */
+  int vp_iterations;        /* GMRES iterations of the velocity prediction    */
+  int pp_iterations;        /* CG iterations of the pressure Poisson solves   */
+  int vu_iterations;        /* CG iterations of the velocity update          */
+  double ch_residual;       /* final |R| of the last Newton iteration        */
+  double mass;              /* integral of phi^{k+1}                          */
+  double energy;            /* total energy of the new state                  */
+  double ms;                /* wall time of the call                          */
+} chns_step_stats;
+
+/* One projection time step (paper Sec. 3 and its flowchart): `blocks` passes
+ * of Newton on the Cahn-Hilliard system (GMRES with 2x2 node-block Jacobi),
+ * velocity prediction (GMRES with Jacobi), pressure Poisson (CG) and velocity
+ * update (CG on the rho-weighted mass matrix), then
+ * (u_prev, u, p, phi, mu) <- (u^k, u^{k+1}, p^{k+1}, phi^{k+1}, mu^{k+1}).
+ * Synchronises `stream`.  ENOCONV if a solve or Newton stalls; the state is
+ * then left at step k.                                                     */
+int chns_advance_step(chns_ctx* ctx, chns_state* state, const chns_step_opts* opts, chns_step_stats* stats,
+                      void* stream);
+
 /* ------------------------------------------------------------ profiling */
 
 /* Per-kernel timers (paper Sec. 6 reports per-solver time breakdowns; these

@@ -204,6 +204,67 @@ class Context:
         return x, SolveStats(st.iterations, st.outer_iterations, st.rel_residual, st.ms_setup, st.ms_solve,
                              st.fallback, rc)
 
+    # ------------------------------------------------ CHNS forms and stepping
+    def _ptrs(self, fields, lens):
+        import torch
+        arr = (C.c_void_p * len(fields))()
+        for k, (f, nl) in enumerate(zip(fields, lens)):
+            arr[k] = _dev_ptr(f, torch.float64, nl * self.n).value
+        return arr
+
+    def set_coefficients(self, op, fields, stream=None):
+        """MOMENTUM: (phi~, mu~, u^); CH_JACOBIAN: (phi^{k+1}, phi^k, u~)."""
+        arr = self._ptrs(fields, (1, 1, self.dim))
+        L.check(L.lib().chns_set_coefficients(self._h, op, arr, _stream_ptr(stream)))
+
+    FORM_LENS = {L.FORM_CH_RESIDUAL: ("2", 1, 1, "d"), L.FORM_VP_RHS: (1, 1, "d", "d", 1),
+                 L.FORM_PP_RHS: (1, 1, "d", "d", 1, "d"), L.FORM_VU_RHS: (1, 1, "d", "d", 1, "d", 1),
+                 L.FORM_ENERGY: (1, "d")}
+    FORM_OUT = {L.FORM_CH_RESIDUAL: "2", L.FORM_VP_RHS: "d", L.FORM_PP_RHS: 1, L.FORM_VU_RHS: "d",
+                L.FORM_ENERGY: 1}
+
+    def _len(self, code):
+        return {"2": 2, "d": self.dim}.get(code, code)
+
+    def assemble(self, form, fields, out=None, stream=None):
+        import torch
+        lens = [self._len(c) for c in self.FORM_LENS[form]]
+        if len(fields) != len(lens):
+            raise ValueError(f"form {form} takes {len(lens)} fields")
+        arr = self._ptrs(fields, lens)
+        no = self._len(self.FORM_OUT[form]) * self.n
+        if out is None:
+            out = torch.empty(no, dtype=torch.float64, device=fields[0].device)
+        L.check(L.lib().chns_assemble(self._h, form, arr, _dev_ptr(out, torch.float64, no), _stream_ptr(stream)))
+        return out
+
+    def initial_mu(self, phi, mu=None, stream=None):
+        import torch
+        if mu is None:
+            mu = torch.empty_like(phi)
+        L.check(L.lib().chns_initial_mu(self._h, _dev_ptr(phi, torch.float64, self.n),
+                                        _dev_ptr(mu, torch.float64, self.n), _stream_ptr(stream)))
+        return mu
+
+    def advance_step(self, state: dict, blocks=2, newton_rtol=1e-8, newton_atol=1e-12, max_newton=20,
+                     lin_rtol=1e-8, max_it=5000, restart=64, pp_pc="jacobi", pp_mode="fp64", graphs=True,
+                     stream=None):
+        """state: dict of device FP64 tensors u, u_prev (dim*n), p, phi, mu (n), updated in place."""
+        import torch
+        d = self.dim * self.n
+        st = L.State(_dev_ptr(state["u"], torch.float64, d), _dev_ptr(state["u_prev"], torch.float64, d),
+                     _dev_ptr(state["p"], torch.float64, self.n), _dev_ptr(state["phi"], torch.float64, self.n),
+                     _dev_ptr(state["mu"], torch.float64, self.n))
+        o = L.StepOpts(blocks, newton_rtol, newton_atol, max_newton, lin_rtol, max_it, restart,
+                       {"jacobi": L.PC_JACOBI, "gmg": L.PC_GMG}[pp_pc],
+                       {"fp64": L.MODE_FP64, "mixed": L.MODE_MIXED_IR}[pp_mode], 0 if graphs else 1)
+        ss = L.StepStats()
+        L.check(L.lib().chns_advance_step(self._h, C.byref(st), C.byref(o), C.byref(ss), _stream_ptr(stream)))
+        return {"newton": list(ss.newton_iterations)[:blocks], "ch_iterations": ss.ch_iterations,
+                "vp_iterations": ss.vp_iterations, "pp_iterations": ss.pp_iterations,
+                "vu_iterations": ss.vu_iterations, "ch_residual": ss.ch_residual, "mass": ss.mass,
+                "energy": ss.energy, "ms": ss.ms}
+
     def profile(self, enable=True):
         L.check(L.lib().chns_profile_enable(self._h, int(enable)))
 

@@ -13,6 +13,7 @@ OP_PRESSURE, OP_MOMENTUM, OP_CH_JACOBIAN, OP_MASS_RHO, OP_MASS = 0, 1, 2, 3, 4
 FP64, FP32 = 0, 1
 PC_JACOBI, PC_GMG, PC_LEARNED, PC_NONE = 0, 1, 2, 3
 MODE_FP64, MODE_MIXED_IR = 0, 1
+FORM_CH_RESIDUAL, FORM_VP_RHS, FORM_PP_RHS, FORM_VU_RHS, FORM_ENERGY = 0, 1, 2, 3, 4
 
 REFINE_CB = C.CFUNCTYPE(C.c_int, C.POINTER(C.c_int64), C.c_int, C.c_void_p)
 
@@ -56,6 +57,27 @@ class SolveStats(C.Structure):
     ]
 
 
+class State(C.Structure):
+    _fields_ = [("u", C.c_void_p), ("u_prev", C.c_void_p), ("p", C.c_void_p), ("phi", C.c_void_p),
+                ("mu", C.c_void_p)]
+
+
+class StepOpts(C.Structure):
+    _fields_ = [
+        ("blocks", C.c_int), ("newton_rtol", C.c_double), ("newton_atol", C.c_double), ("max_newton", C.c_int),
+        ("lin_rtol", C.c_double), ("max_it", C.c_int), ("restart", C.c_int), ("pp_pc", C.c_int),
+        ("pp_mode", C.c_int), ("no_graphs", C.c_int),
+    ]
+
+
+class StepStats(C.Structure):
+    _fields_ = [
+        ("newton_iterations", C.c_int * 4), ("ch_iterations", C.c_int), ("vp_iterations", C.c_int),
+        ("pp_iterations", C.c_int), ("vu_iterations", C.c_int), ("ch_residual", C.c_double),
+        ("mass", C.c_double), ("energy", C.c_double), ("ms", C.c_double),
+    ]
+
+
 _lib = None
 
 # name -> (restype, argtypes)
@@ -78,6 +100,11 @@ SIGNATURES = {
     "chns_profile_reset": (C.c_int, [C.c_void_p]),
     "chns_solve_pressure": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(SolveOpts),
                                       C.POINTER(SolveStats), C.c_void_p]),
+    "chns_set_coefficients": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_void_p), C.c_void_p]),
+    "chns_assemble": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p]),
+    "chns_initial_mu": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "chns_advance_step": (C.c_int, [C.c_void_p, C.POINTER(State), C.POINTER(StepOpts), C.POINTER(StepStats),
+                                    C.c_void_p]),
 }
 
 

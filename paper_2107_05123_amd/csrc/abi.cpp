@@ -57,6 +57,7 @@ void Ctx::prof_end(const char* tag, hipStream_t s, hipEvent_t start) {
 }
 
 Ctx::~Ctx() {
+  destroy_stepper(*this);
   if (mg && mg->setup_exec) (void)hipGraphExecDestroy(mg->setup_exec);
   if (diag_exec) (void)hipGraphExecDestroy(diag_exec);
   delete mg;
@@ -347,6 +348,77 @@ int chns_solve_pressure(chns_ctx* ctx, const double* b, double* x, const chns_so
   }
   chns_solve_stats st{};
   int rc = solve_pressure_impl(ctx->c, b, x, o, st, (hipStream_t)stream);
+  if (stats) *stats = st;
+  return rc;
+  CHNS_GUARD_END
+}
+
+int chns_set_coefficients(chns_ctx* ctx, int op, const double* const* fields, void* stream) {
+  CHNS_GUARD_BEGIN
+  if (!ctx) {
+    set_error("null argument");
+    return CHNS_EINVAL;
+  }
+  return set_coefficients_impl(ctx->c, op, fields, (hipStream_t)stream);
+  CHNS_GUARD_END
+}
+
+int chns_assemble(chns_ctx* ctx, int form, const double* const* fields, double* out, void* stream) {
+  CHNS_GUARD_BEGIN
+  if (!ctx) {
+    set_error("null argument");
+    return CHNS_EINVAL;
+  }
+  return assemble_impl(ctx->c, form, fields, out, (hipStream_t)stream);
+  CHNS_GUARD_END
+}
+
+int chns_initial_mu(chns_ctx* ctx, const double* phi, double* mu, void* stream) {
+  CHNS_GUARD_BEGIN
+  if (!ctx || !phi || !mu) {
+    set_error("null argument");
+    return CHNS_EINVAL;
+  }
+  Ctx& c = ctx->c;
+  CHNS_HIP(hipEventRecord(c.ev_in, (hipStream_t)stream));
+  CHNS_HIP(hipStreamWaitEvent(c.work, c.ev_in, 0));
+  int rc = initial_mu_impl(c, phi, mu, c.work);
+  if (rc) return rc;
+  CHNS_HIP(hipStreamSynchronize(c.work));
+  return CHNS_OK;
+  CHNS_GUARD_END
+}
+
+int chns_advance_step(chns_ctx* ctx, chns_state* state, const chns_step_opts* opts, chns_step_stats* stats,
+                      void* stream) {
+  CHNS_GUARD_BEGIN
+  if (!ctx || !state || !state->u || !state->u_prev || !state->p || !state->phi || !state->mu) {
+    set_error("null argument");
+    return CHNS_EINVAL;
+  }
+  chns_step_opts o{};
+  o.blocks = 2;
+  o.newton_rtol = 1e-8;
+  o.newton_atol = 1e-12;
+  o.max_newton = 20;
+  o.lin_rtol = 1e-8;
+  o.max_it = 5000;
+  o.restart = 64;
+  o.pp_pc = CHNS_PC_JACOBI;
+  o.pp_mode = CHNS_MODE_FP64;
+  o.no_graphs = 0;
+  if (opts) {
+    o = *opts;
+    if (o.blocks <= 0) o.blocks = 2;
+    if (!(o.newton_rtol > 0.0)) o.newton_rtol = 1e-8;
+    if (!(o.newton_atol > 0.0)) o.newton_atol = 1e-12;
+    if (o.max_newton <= 0) o.max_newton = 20;
+    if (!(o.lin_rtol > 0.0)) o.lin_rtol = 1e-8;
+    if (o.max_it <= 0) o.max_it = 5000;
+    if (o.restart <= 0) o.restart = 64;
+  }
+  chns_step_stats st{};
+  int rc = advance_step_impl(ctx->c, *state, o, st, (hipStream_t)stream);
   if (stats) *stats = st;
   return rc;
   CHNS_GUARD_END

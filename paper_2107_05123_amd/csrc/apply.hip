@@ -16,6 +16,7 @@
 //     the result is bitwise reproducible.
 #include "brick_geom.h"
 #include "chns_internal.h"
+#include "elem_chns.h"
 
 namespace chns {
 namespace {
@@ -135,24 +136,34 @@ __device__ __forceinline__ void elem_mass_apply(const T* x, const T* r, T* y) {
 }
 
 // ------------------------------------------------------------ op traits
-enum OpKind { K_PP = 0, K_MASS = 1, K_MASS_RHO = 2 };
+// NI gathered input fields (the vector x; wall nodes read as zero when
+// MASK), NCF coefficient fields, NO output fields; WALL: 0 no special rows,
+// 1 identity rows on the walls (y = x), 2 zero rows on the walls.
+enum OpKind {
+  K_PP = 0, K_MASS = 1, K_MASS_RHO = 2, K_CH_RES = 3, K_CH_JAC = 4, K_VP = 5, K_VP_RHS = 6, K_PP_RHS = 7,
+  K_VU_RHS = 8, K_ENERGY = 9
+};
 template <int OP, int DIM>
 struct Traits;
-template <int DIM>
-struct Traits<K_PP, DIM> {
-  static constexpr int NF = 1, NCF = 1;
-  static constexpr bool MASK = false;
-};
-template <int DIM>
-struct Traits<K_MASS, DIM> {
-  static constexpr int NF = 1, NCF = 0;
-  static constexpr bool MASK = false;
-};
-template <int DIM>
-struct Traits<K_MASS_RHO, DIM> {
-  static constexpr int NF = DIM, NCF = 1;
-  static constexpr bool MASK = true;
-};
+#define CHNS_TRAITS(OPK, ni, ncf, no, mask, wall)                  \
+  template <int DIM>                                               \
+  struct Traits<OPK, DIM> {                                        \
+    static constexpr int NI = ni, NCF = ncf, NO = no, WALL = wall; \
+    static constexpr bool MASK = mask;                             \
+  };
+CHNS_TRAITS(K_PP, 1, 1, 1, false, 0)
+CHNS_TRAITS(K_MASS, 1, 0, 1, false, 0)
+CHNS_TRAITS(K_MASS_RHO, DIM, 1, DIM, true, 1)
+CHNS_TRAITS(K_CH_RES, 2, 2 + DIM, 2, false, 0)
+CHNS_TRAITS(K_CH_JAC, 2, 2 + DIM, 2, false, 0)
+CHNS_TRAITS(K_VP, DIM, 2 + DIM, DIM, true, 1)
+CHNS_TRAITS(K_VP_RHS, 0, 2 * DIM + 3, DIM, false, 2)
+CHNS_TRAITS(K_PP_RHS, 0, 3 * DIM + 3, 1, false, 0)
+CHNS_TRAITS(K_VU_RHS, 0, 3 * DIM + 4, DIM, false, 2)
+CHNS_TRAITS(K_ENERGY, 0, 2 + DIM, 1, false, 0)
+#undef CHNS_TRAITS
+
+constexpr int kMaxCoef = kMaxCoefFields;
 
 template <typename T>
 struct BrickArgs {
@@ -165,12 +176,13 @@ struct BrickArgs {
   int64_t n;        // field stride of x and y
   int64_t n_slots;  // field stride of slots
   const T* x;
-  const T* coef;    // phase field phi~ (stride n) or null
+  const T* cf[kMaxCoef];  // coefficient fields (stride n each)
   T* y;
   T* slots;
   const int32_t* hang;
   const uint8_t* wall;
   double alpha, beta;  // rho(phi) = alpha phi + beta
+  Phys phys;           // physical parameters of the CHNS forms
   double* partials;    // fused x.y partial per block, or null
   const int* done;
   // structured (uniform, lexicographically numbered) meshes: node indices are
@@ -179,6 +191,277 @@ struct BrickArgs {
   int64_t sy, sz;         // index strides of y and z
   int32_t side;           // nodes per edge - 1
 };
+
+// -------------------------------------------------- CHNS element routines
+// (corner arrays as in elem_chns.h; w = det J, gs = 2/h)
+template <int DIM>
+__device__ __forceinline__ void el_ch_res(const double (*x)[1 << DIM], const double (*c)[1 << DIM], const Phys& P,
+                                          double gs, double w, double (*y)[1 << DIM]) {
+  constexpr int NC = 1 << DIM;
+  double pt[NC], mt[NC], dp[NC];
+#pragma unroll
+  for (int a = 0; a < NC; ++a) {
+    pt[a] = 0.5 * (x[0][a] + c[0][a]);
+    mt[a] = 0.5 * (x[1][a] + c[1][a]);
+    dp[a] = x[0][a] - c[0][a];
+    y[0][a] = 0.0;
+    y[1][a] = 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    const double ptq = QP<DIM>::val(pt, q), dpq = QP<DIM>::val(dp, q), mtq = QP<DIM>::val(mt, q);
+    double gpt[DIM], gmt[DIM], fl[DIM], fm[DIM];
+    QP<DIM>::grad(pt, q, gs, gpt);
+    QP<DIM>::grad(mt, q, gs, gmt);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const double ut = QP<DIM>::val(c[2 + d], q);
+      fl[d] = w * (-ut * ptq + gmt[d] / (P.Pe * P.Cn));
+      fm[d] = w * P.Cn * P.Cn * gpt[d];
+    }
+    const double fphi = w * dpq / P.dt, fmu = w * (dpsi(ptq) - mtq);
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+      double s0 = refN<DIM>(q, a) * fphi, s1 = refN<DIM>(q, a) * fmu;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const double gN = gs * refD<DIM>(q, a, d);
+        s0 += gN * fl[d];
+        s1 += gN * fm[d];
+      }
+      y[0][a] += s0;
+      y[1][a] += s1;
+    }
+  }
+}
+
+template <int DIM>
+__device__ __forceinline__ void el_ch_jac(const double (*x)[1 << DIM], const double (*c)[1 << DIM], const Phys& P,
+                                          double gs, double w, double (*y)[1 << DIM]) {
+  constexpr int NC = 1 << DIM;
+  double pt[NC];
+#pragma unroll
+  for (int a = 0; a < NC; ++a) {
+    pt[a] = 0.5 * (c[0][a] + c[1][a]);
+    y[0][a] = 0.0;
+    y[1][a] = 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    const double ptq = QP<DIM>::val(pt, q), dph = QP<DIM>::val(x[0], q), dmu = QP<DIM>::val(x[1], q);
+    double gdph[DIM], gdmu[DIM], fl[DIM], fm[DIM];
+    QP<DIM>::grad(x[0], q, gs, gdph);
+    QP<DIM>::grad(x[1], q, gs, gdmu);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const double ut = QP<DIM>::val(c[2 + d], q);
+      fl[d] = w * (-0.5 * ut * dph + gdmu[d] / (2.0 * P.Pe * P.Cn));
+      fm[d] = w * 0.5 * P.Cn * P.Cn * gdph[d];
+    }
+    const double fphi = w * dph / P.dt, fmu = w * (0.5 * d2psi(ptq) * dph - 0.5 * dmu);
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+      double s0 = refN<DIM>(q, a) * fphi, s1 = refN<DIM>(q, a) * fmu;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const double gN = gs * refD<DIM>(q, a, d);
+        s0 += gN * fl[d];
+        s1 += gN * fm[d];
+      }
+      y[0][a] += s0;
+      y[1][a] += s1;
+    }
+  }
+}
+
+// velocity prediction operator, all DIM components (identical scalar operator)
+template <int DIM>
+__device__ __forceinline__ void el_vp(const double (*x)[1 << DIM], const double (*c)[1 << DIM], const Phys& P,
+                                      double gs, double w, double (*y)[1 << DIM]) {
+  constexpr int NC = 1 << DIM;
+  const double* uh[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) uh[d] = c[2 + d];
+#pragma unroll
+  for (int f = 0; f < DIM; ++f)
+#pragma unroll
+    for (int a = 0; a < NC; ++a) y[f][a] = 0.0;
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    MomQ<DIM> M;
+    M.init(P, c[0], c[1], uh, q, gs);
+    double sN[NC];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+      double gN[DIM];
+      gradN<DIM>(q, a, gs, gN);
+      sN[a] = M.s(P, gN);
+    }
+#pragma unroll
+    for (int f = 0; f < DIM; ++f) {
+      const double vq = QP<DIM>::val(x[f], q);
+      double gv[DIM];
+      QP<DIM>::grad(x[f], q, gs, gv);
+      const double rl = M.rlin(P, vq, gv);
+      const double fN = w * (M.rho * vq / P.dt + 0.5 * M.rho * M.dot(M.uh, gv) + M.dot(M.J, gv) / (2.0 * P.Pe));
+      const double fst = w * M.tau * rl;
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        double gN[DIM];
+        gradN<DIM>(q, a, gs, gN);
+        y[f][a] += refN<DIM>(q, a) * fN + w * M.eta * M.dot(gN, gv) / (2.0 * P.Re) + sN[a] * fst;
+      }
+    }
+  }
+}
+
+// right-hand sides: coefficient layout phi~, mu~, u^ (DIM), u^k (DIM), p^k,
+// then v (DIM) and p^{k+1}
+template <int DIM>
+__device__ __forceinline__ void el_vp_rhs(const double (*c)[1 << DIM], const Phys& P, double gs, double w,
+                                          double (*y)[1 << DIM]) {
+  constexpr int NC = 1 << DIM;
+  const double* uh[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) uh[d] = c[2 + d];
+  const double* pk = c[2 + 2 * DIM];
+#pragma unroll
+  for (int f = 0; f < DIM; ++f)
+#pragma unroll
+    for (int a = 0; a < NC; ++a) y[f][a] = 0.0;
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    MomQ<DIM> M;
+    M.init(P, c[0], c[1], uh, q, gs);
+    double gp[DIM];
+    QP<DIM>::grad(pk, q, gs, gp);
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+      const double* uk = c[2 + DIM + i];
+      const double ui = QP<DIM>::val(uk, q);
+      double gui[DIM];
+      QP<DIM>::grad(uk, q, gs, gui);
+      const double kort = kort_i<DIM>(c[0], q, i, gs, M.gphi);
+      const double rk = M.rknown(P, i, ui, gui, gp, kort);
+      const double g = i == P.gaxis ? -1.0 : 0.0;
+      const double fN = w * (M.rho * ui / P.dt - 0.5 * M.rho * M.dot(M.uh, gui) - M.dot(M.J, gui) / (2.0 * P.Pe) -
+                             gp[i] + M.rho * g / P.Fr);
+      double fG[DIM];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) fG[d] = w * (-M.eta * gui[d] / (2.0 * P.Re) + P.Cn / P.We * M.gphi[i] * M.gphi[d]);
+      const double fst = -w * M.tau * rk;
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        double gN[DIM];
+        gradN<DIM>(q, a, gs, gN);
+        y[i][a] += refN<DIM>(q, a) * fN + M.dot(gN, fG) + M.s(P, gN) * fst;
+      }
+    }
+  }
+}
+
+template <int DIM>
+__device__ __forceinline__ void el_pp_rhs(const double (*c)[1 << DIM], const Phys& P, double gs, double w,
+                                          double (*y)[1 << DIM]) {
+  constexpr int NC = 1 << DIM;
+  const double* uh[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) uh[d] = c[2 + d];
+  const double* pk = c[2 + 2 * DIM];
+#pragma unroll
+  for (int a = 0; a < NC; ++a) y[0][a] = 0.0;
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    MomQ<DIM> M;
+    M.init(P, c[0], c[1], uh, q, gs);
+    double gp[DIM], fG[DIM];
+    QP<DIM>::grad(pk, q, gs, gp);
+    double div = 0.0;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+      const double* v = c[3 + 2 * DIM + i];
+      const double* uk = c[2 + DIM + i];
+      double gv[DIM], gui[DIM];
+      QP<DIM>::grad(v, q, gs, gv);
+      QP<DIM>::grad(uk, q, gs, gui);
+      div += gv[i];
+      const double rl = M.rlin(P, QP<DIM>::val(v, q), gv);
+      const double rk = M.rknown(P, i, QP<DIM>::val(uk, q), gui, gp, kort_i<DIM>(c[0], q, i, gs, M.gphi));
+      fG[i] = w * (-(2.0 / P.dt) * M.tau * (rl + rk) / M.rho + gp[i] / M.rho);
+    }
+    const double fN = -w * (2.0 / P.dt) * div;
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+      double gN[DIM];
+      gradN<DIM>(q, a, gs, gN);
+      y[0][a] += refN<DIM>(q, a) * fN + M.dot(gN, fG);
+    }
+  }
+}
+
+template <int DIM>
+__device__ __forceinline__ void el_vu_rhs(const double (*c)[1 << DIM], const Phys& P, double gs, double w,
+                                          double (*y)[1 << DIM]) {
+  constexpr int NC = 1 << DIM;
+  const double* uh[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) uh[d] = c[2 + d];
+  const double* pk = c[2 + 2 * DIM];
+  const double* pn = c[3 + 3 * DIM];
+#pragma unroll
+  for (int f = 0; f < DIM; ++f)
+#pragma unroll
+    for (int a = 0; a < NC; ++a) y[f][a] = 0.0;
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    MomQ<DIM> M;
+    M.init(P, c[0], c[1], uh, q, gs);
+    double gp[DIM], gpn[DIM];
+    QP<DIM>::grad(pk, q, gs, gp);
+    QP<DIM>::grad(pn, q, gs, gpn);
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+      const double* v = c[3 + 2 * DIM + i];
+      const double* uk = c[2 + DIM + i];
+      double gv[DIM], gui[DIM];
+      QP<DIM>::grad(v, q, gs, gv);
+      QP<DIM>::grad(uk, q, gs, gui);
+      const double vq = QP<DIM>::val(v, q);
+      const double rl = M.rlin(P, vq, gv);
+      const double rk = M.rknown(P, i, QP<DIM>::val(uk, q), gui, gp, kort_i<DIM>(c[0], q, i, gs, M.gphi));
+      const double f = w * (M.rho * vq - M.tau * (rl + rk) - 0.5 * P.dt * (gpn[i] - gp[i]));
+#pragma unroll
+      for (int a = 0; a < NC; ++a) y[i][a] += refN<DIM>(q, a) * f;
+    }
+  }
+}
+
+// energy density of the leaf, split equally over its corners:
+// 1/2 rho |u|^2 + (psi + Cn^2/2 |grad phi|^2)/(Cn We) + rho y / Fr
+// (coefficients: phi, the vertical coordinate, u)
+template <int DIM>
+__device__ __forceinline__ void el_energy(const double (*c)[1 << DIM], const Phys& P, double gs, double w,
+                                          double (*y)[1 << DIM]) {
+  constexpr int NC = 1 << DIM;
+  double e = 0.0;
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    const double ph = QP<DIM>::val(c[0], q);
+    const double rho = P.alpha * pull_back(ph) + P.beta;
+    double g[DIM];
+    QP<DIM>::grad(c[0], q, gs, g);
+    double uu = 0.0, gg = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const double u = QP<DIM>::val(c[2 + d], q);
+      uu += u * u;
+      gg += g[d] * g[d];
+    }
+    e += w * (0.5 * rho * uu + (psi(ph) + 0.5 * P.Cn * P.Cn * gg) / (P.Cn * P.We) + rho * QP<DIM>::val(c[1], q) / P.Fr);
+  }
+#pragma unroll
+  for (int a = 0; a < NC; ++a) y[0][a] = e / NC;
+}
 
 template <typename T, bool MASK>
 __device__ __forceinline__ T fetch(const T* v, const uint8_t* wall, int32_t i) {
@@ -210,7 +493,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 template <int DIM, int B, typename T, int OP, bool WHOLE, bool STRUCT>
 __global__ __launch_bounds__(64) void k_brick(BrickArgs<T> a) {
   using TR = Traits<OP, DIM>;
-  constexpr int NF = TR::NF, NCF = TR::NCF, NV = NF + NCF;
+  constexpr int NI = TR::NI, NCF = TR::NCF, NO = TR::NO, NV = NI + NCF;
+  constexpr int NIa = NI > 0 ? NI : 1, NCa = NCF > 0 ? NCF : 1;
   constexpr int LPB = DIM == 3 ? B * B : B;  // lanes (leaf columns) per brick
   constexpr int BPB = 64 / LPB;              // bricks per wavefront
   constexpr int NL = DIM == 3 ? (B + 1) * (B + 1) : (B + 1);  // nodes per layer
@@ -220,7 +504,7 @@ __global__ __launch_bounds__(64) void k_brick(BrickArgs<T> a) {
   __shared__ T lay[RING][BPB][NV][NL];
   // per-corner-type leaf contributions, indexed by the node they land on
   // (zero where no leaf of the brick lands): a node sums NH entries
-  __shared__ T accn[BPB][NF][NH][NL];
+  __shared__ T accn[BPB][NO][NH][NL];
   if (a.done && *a.done) return;
   const int lane = threadIdx.x, bl = lane / LPB, ll = lane % LPB;
   const int64_t brick = (int64_t)blockIdx.x * BPB + bl;
@@ -254,16 +538,16 @@ __global__ __launch_bounds__(64) void k_brick(BrickArgs<T> a) {
   };
   auto value = [&](int f, int64_t e, int z, int p) -> T {
     if constexpr (STRUCT) {
-      if (f < NF) {
+      if (f < NI) {
         if constexpr (TR::MASK) {
           if (on_wall(z, p)) return T(0);
         }
         return a.x[f * a.n + e];
       }
-      return a.coef[(f - NF) * a.n + e];
+      return a.cf[f - NI][e];
     } else {
-      if (f < NF) return gather<T, TR::MASK>(a.x + f * a.n, a.wall, a.hang, (int32_t)e);
-      return gather<T, false>(a.coef + (f - NF) * a.n, nullptr, a.hang, (int32_t)e);
+      if (f < NI) return gather<T, TR::MASK>(a.x + f * a.n, a.wall, a.hang, (int32_t)e);
+      return gather<T, false>(a.cf[f - NI], nullptr, a.hang, (int32_t)e);
     }
   };
   // per-level folded constants (powers of two are exact); FP32 fields carry
@@ -277,11 +561,13 @@ __global__ __launch_bounds__(64) void k_brick(BrickArgs<T> a) {
     Bc = T(ldexp(beta0, e));
   } else if constexpr (OP == K_MASS) {
     Bc = T(ldexp(1.0, -(lev + 1) * DIM - 2 * DIM));
-  } else {
+  } else if constexpr (OP == K_MASS_RHO) {
     const int e = -(lev + 1) * DIM - 2 * DIM;
     A = T(ldexp(a.alpha, e - DIM));
     Bc = T(ldexp(beta0, e));
   }
+  // CHNS forms: physical gradient scale 2/h and det J = (h/2)^d
+  const double gs = ldexp(1.0, lev + 1), wdet = ldexp(1.0, -(lev + 1) * DIM);
 
   // -------- layered pipeline state (entries three layers ahead, values two)
   int64_t ent[KL];
@@ -334,9 +620,9 @@ __global__ __launch_bounds__(64) void k_brick(BrickArgs<T> a) {
       const int p = ll + k * LPB;
       if (p >= NL) continue;
       const int jx = p % (B + 1), jy = DIM == 3 ? p / (B + 1) : 0;
-      T v[NF];
+      T v[NO];
 #pragma unroll
-      for (int f = 0; f < NF; ++f) {
+      for (int f = 0; f < NO; ++f) {
         T t = accn[bl][f][0][p];
 #pragma unroll
         for (int cl = 1; cl < NH; ++cl) t += accn[bl][f][cl][p];
@@ -348,21 +634,23 @@ __global__ __launch_bounds__(64) void k_brick(BrickArgs<T> a) {
         if constexpr (STRUCT) e = entry(z, p);
         else e = eo[k];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) {
+        for (int f = 0; f < NO; ++f) {
           a.y[f * a.n + e] = v[f];
-          if (a.partials) dot += (double)lay[buf][bl][f][p] * (double)v[f];
+          if constexpr (NI == NO) {
+            if (a.partials) dot += (double)lay[buf][bl][f][p] * (double)v[f];
+          }
         }
       } else {
         const int64_t sl = a.slot_base + brick * a.nbnd + brick_rank(DIM, B, jx, jy, z);
 #pragma unroll
-        for (int f = 0; f < NF; ++f) a.slots[f * a.n_slots + sl] = v[f];
+        for (int f = 0; f < NO; ++f) a.slots[f * a.n_slots + sl] = v[f];
       }
     }
   };
 
-  T carry[NF][NH];
+  T carry[NO][NH];
 #pragma unroll
-  for (int f = 0; f < NF; ++f)
+  for (int f = 0; f < NO; ++f)
 #pragma unroll
     for (int c = 0; c < NH; ++c) carry[f][c] = T(0);
 
@@ -372,7 +660,7 @@ __global__ __launch_bounds__(64) void k_brick(BrickArgs<T> a) {
       const int p = ll + k * LPB;
       if (p < NL)
 #pragma unroll
-        for (int f = 0; f < NF; ++f)
+        for (int f = 0; f < NO; ++f)
 #pragma unroll
           for (int cl = 0; cl < NH; ++cl) accn[bl][f][cl][p] = T(0);
     }
@@ -416,7 +704,7 @@ __global__ __launch_bounds__(64) void k_brick(BrickArgs<T> a) {
   __syncthreads();
   // corner values of the upper node layer of one leaf layer are the lower
   // corners of the next: keep them in registers and read only the new layer
-  T xc[NF][NC], cc[NCF > 0 ? NCF : 1][NC];
+  T xc[NIa][NC], cc[NCa][NC];
   auto read_half = [&](int z, int half) {
 #pragma unroll
     for (int c = 0; c < NH; ++c) {
@@ -424,34 +712,48 @@ __global__ __launch_bounds__(64) void k_brick(BrickArgs<T> a) {
       const int p = (ix + bx) + (DIM == 3 ? (iy + by) * (B + 1) : 0);
       const int buf = z % RING;
 #pragma unroll
-      for (int f = 0; f < NF; ++f) xc[f][c + half * NH] = lay[buf][bl][f][p];
+      for (int f = 0; f < NI; ++f) xc[f][c + half * NH] = lay[buf][bl][f][p];
 #pragma unroll
-      for (int f = 0; f < NCF; ++f) cc[f][c + half * NH] = lay[buf][bl][NF + f][p];
+      for (int f = 0; f < NCF; ++f) cc[f][c + half * NH] = lay[buf][bl][NI + f][p];
     }
   };
   if (active) read_half(0, 1);
   for (int ez = 0; ez < B; ++ez) {
     load_emit_entries(ez);
     if (active) {
-      T ye[NF][NC];
+      T ye[NO][NC];
 #pragma unroll
       for (int c = 0; c < NH; ++c) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) xc[f][c] = xc[f][c + NH];
+        for (int f = 0; f < NI; ++f) xc[f][c] = xc[f][c + NH];
 #pragma unroll
         for (int f = 0; f < NCF; ++f) cc[f][c] = cc[f][c + NH];
       }
       read_half(ez + 1, 1);
       if constexpr (OP == K_PP) {
         elem_pp<DIM, T>(xc[0], cc[0], A, Bc, ye[0]);
-      } else {
+      } else if constexpr (OP == K_MASS || OP == K_MASS_RHO) {
         T r[NC];
         elem_mass_coef<DIM, T, OP == K_MASS_RHO>(cc[0], A, Bc, r);
 #pragma unroll
-        for (int f = 0; f < NF; ++f) elem_mass_apply<DIM, T>(xc[f], r, ye[f]);
+        for (int f = 0; f < NI; ++f) elem_mass_apply<DIM, T>(xc[f], r, ye[f]);
+      } else if constexpr (OP == K_CH_RES) {
+        el_ch_res<DIM>(xc, cc, a.phys, gs, wdet, ye);
+      } else if constexpr (OP == K_CH_JAC) {
+        el_ch_jac<DIM>(xc, cc, a.phys, gs, wdet, ye);
+      } else if constexpr (OP == K_VP) {
+        el_vp<DIM>(xc, cc, a.phys, gs, wdet, ye);
+      } else if constexpr (OP == K_VP_RHS) {
+        el_vp_rhs<DIM>(cc, a.phys, gs, wdet, ye);
+      } else if constexpr (OP == K_PP_RHS) {
+        el_pp_rhs<DIM>(cc, a.phys, gs, wdet, ye);
+      } else if constexpr (OP == K_VU_RHS) {
+        el_vu_rhs<DIM>(cc, a.phys, gs, wdet, ye);
+      } else {
+        el_energy<DIM>(cc, a.phys, gs, wdet, ye);
       }
 #pragma unroll
-      for (int f = 0; f < NF; ++f)
+      for (int f = 0; f < NO; ++f)
 #pragma unroll
         for (int c = 0; c < NH; ++c) {
           const int p = (ix + (c & 1)) + (DIM == 3 ? (iy + ((c >> 1) & 1)) * (B + 1) : 0);
@@ -471,7 +773,7 @@ __global__ __launch_bounds__(64) void k_brick(BrickArgs<T> a) {
   load_emit_entries(B);
   if (active) {
 #pragma unroll
-    for (int f = 0; f < NF; ++f)
+    for (int f = 0; f < NO; ++f)
 #pragma unroll
       for (int c = 0; c < NH; ++c) {
         const int p = (ix + (c & 1)) + (DIM == 3 ? (iy + ((c >> 1) & 1)) * (B + 1) : 0);
@@ -498,7 +800,7 @@ __device__ double block_sum256(double v, double* sh) {
   return r;
 }
 
-template <typename T, int NF, bool MASK>
+template <typename T, int NO, int WALL>
 __global__ __launch_bounds__(256) void k_combine(const int32_t* __restrict__ node, const int32_t* __restrict__ ptr,
                                                  const uint32_t* __restrict__ ent, int64_t nrows,
                                                  const T* __restrict__ slots, int64_t n_slots, T* __restrict__ y,
@@ -512,7 +814,7 @@ __global__ __launch_bounds__(256) void k_combine(const int32_t* __restrict__ nod
     const int32_t i = node[row];
     const int32_t k0 = ptr[row], k1 = ptr[row + 1];
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
+    for (int f = 0; f < NO; ++f) {
       T v = T(0);
       for (int32_t k = k0; k < k1; ++k) {
         const uint32_t e = ent[k];
@@ -520,8 +822,11 @@ __global__ __launch_bounds__(256) void k_combine(const int32_t* __restrict__ nod
         const T s = slots[f * n_slots + (e & 0x3fffffffu)];
         v += code == 0 ? s : (code == 1 ? s * T(0.5) : s * T(0.25));
       }
-      if constexpr (MASK) {
+      // wall rows: identity (WALL 1) or zero (WALL 2)
+      if constexpr (WALL == 1) {
         if (wall[i]) v = x[f * n + i];
+      } else if constexpr (WALL == 2) {
+        if (wall[i]) v = T(0);
       }
       y[f * n + i] = v;
       if (partials) dot += (double)x[f * n + i] * (double)v;
@@ -560,22 +865,33 @@ __global__ __launch_bounds__(1024) void k_sum_partials(const double* partials, i
 // combine, which handles them); nothing else is needed here.
 
 // Diagonal probing helpers.
+// x = indicator of colour c in field `field` (every field when field < 0)
 template <typename T>
-__global__ void k_indicator(T* x, const uint8_t* color, int c, int64_t n, int nf) {
+__global__ void k_indicator(T* x, const uint8_t* color, int c, int64_t n, int nf, int field) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   T v = color[i] == c ? T(1) : T(0);
-  for (int f = 0; f < nf; ++f) x[f * n + i] = v;
+  for (int f = 0; f < nf; ++f) x[f * n + i] = (field < 0 || f == field) ? v : T(0);
 }
 template <typename T>
-__global__ void k_take_diag(T* d, const T* y, const uint8_t* color, int c, int64_t n, int nf, int invert) {
+__global__ void k_take_diag(T* d, const T* y, const uint8_t* color, int c, int64_t n, int nf, int invert,
+                            int field) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (color[i] != c) return;
   for (int f = 0; f < nf; ++f) {
+    if (field >= 0 && f != field) continue;
     T v = y[f * n + i];
     d[f * n + i] = invert ? (v != T(0) ? T(1) / v : T(1)) : v;
   }
+}
+// column `field` of the nf x nf node blocks: blk[(g * nf + field) * n + i] = y_g,i
+__global__ void k_take_block(double* blk, const double* y, const uint8_t* color, int c, int64_t n, int nf,
+                             int field) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (color[i] != c) return;
+  for (int g = 0; g < nf; ++g) blk[(g * nf + field) * n + i] = y[g * n + i];
 }
 
 template <int DIM, int B, typename T, int OP>
@@ -584,7 +900,7 @@ constexpr bool whole_fits() {
   constexpr int LPB = DIM == 3 ? B * B : B;
   constexpr int NL = DIM == 3 ? (B + 1) * (B + 1) : (B + 1);
   // deep bricks keep the three-layer ring (better occupancy, loads pipelined)
-  return B <= 4 && (64 / LPB) * NL * (B + 1) * (TR::NF + TR::NCF) * (int)sizeof(T) <= 12 * 1024;
+  return B <= 4 && (64 / LPB) * NL * (B + 1) * (TR::NI + TR::NCF) * (int)sizeof(T) <= 12 * 1024;
 }
 
 template <int DIM, typename T, int OP, bool STRUCT>
@@ -631,31 +947,67 @@ int launch_bricks(const DevMesh& dm, BrickArgs<T> a, hipStream_t s, int& part_of
 
 int64_t combine_blocks(const DevMesh& dm) { return (dm.n_comb + 255) / 256; }
 
+Phys phys_of(const chns_params& p) {
+  Phys f{};
+  f.dt = p.dt;
+  f.Pe = p.Pe;
+  f.Cn = p.Cn;
+  f.We = p.We;
+  f.Re = p.Re;
+  f.Fr = p.Fr;
+  f.C_I = p.C_I;
+  f.alpha = (p.rho_plus - p.rho_minus) / (2.0 * p.rho_plus);
+  f.beta = (p.rho_plus + p.rho_minus) / (2.0 * p.rho_plus);
+  f.gam = (p.eta_plus - p.eta_minus) / (2.0 * p.eta_plus);
+  f.xi = (p.eta_plus + p.eta_minus) / (2.0 * p.eta_plus);
+  f.cJ = (p.rho_minus - p.rho_plus) / (2.0 * p.rho_plus * p.Cn);
+  f.gaxis = p.gravity_axis;
+  return f;
+}
+
+const char* op_tag(int op, bool fp64) {
+  static const char* tags[10][2] = {{"pp_brick_fp64", "pp_brick_fp32"},
+                                    {"mass_brick_fp64", "mass_brick_fp32"},
+                                    {"massrho_brick_fp64", "massrho_brick_fp32"},
+                                    {"chres_brick_fp64", "chres_brick_fp32"},
+                                    {"chjac_brick_fp64", "chjac_brick_fp32"},
+                                    {"vp_brick_fp64", "vp_brick_fp32"},
+                                    {"vprhs_brick_fp64", "vprhs_brick_fp32"},
+                                    {"pprhs_brick_fp64", "pprhs_brick_fp32"},
+                                    {"vurhs_brick_fp64", "vurhs_brick_fp32"},
+                                    {"energy_brick_fp64", "energy_brick_fp32"}};
+  return tags[op][fp64 ? 0 : 1];
+}
+
+// cf: the op's NCF coefficient fields (each n long, device)
 template <int DIM, typename T, int OP>
-int apply_t(Ctx& c, const LevelView& L, const T* x, T* y, const T* phi, hipStream_t s, const ApplyOut& o) {
+int apply_t(Ctx& c, const LevelView& L, const T* x, T* y, const T* const* cf, hipStream_t s, const ApplyOut& o) {
   using TR = Traits<OP, DIM>;
+  static_assert(TR::NCF <= kMaxCoef, "too many coefficient fields");
   const DevMesh& dm = *L.dm;
+  if (o.fuse_dot && TR::NI != TR::NO) {
+    set_error("fused dot needs as many inputs as outputs");
+    return CHNS_EINVAL;
+  }
   BrickArgs<T> a{};
   a.n = dm.n;
   a.n_slots = dm.n_slots;
   a.x = x;
-  a.coef = phi;
+  for (int k = 0; k < TR::NCF; ++k) a.cf[k] = cf[k];
   a.y = y;
   a.slots = (T*)L.slots;
   a.hang = dm.hang_par;
   a.wall = dm.wall;
-  a.alpha = (c.prm.rho_plus - c.prm.rho_minus) / (2.0 * c.prm.rho_plus);
-  a.beta = (c.prm.rho_plus + c.prm.rho_minus) / (2.0 * c.prm.rho_plus);
+  a.phys = phys_of(c.prm);
+  a.alpha = a.phys.alpha;
+  a.beta = a.phys.beta;
   a.partials = o.fuse_dot ? c.partials : nullptr;
   a.done = o.done;
   a.sy = dm.side + 1;
   a.sz = (int64_t)(dm.side + 1) * (dm.side + 1);
   a.side = dm.side;
   int part_off = 0;
-  static const char* tags[3][2] = {{"pp_brick_fp64", "pp_brick_fp32"},
-                                   {"mass_brick_fp64", "mass_brick_fp32"},
-                                   {"massrho_brick_fp64", "massrho_brick_fp32"}};
-  const char* tag = tags[OP][sizeof(T) == 8 ? 0 : 1];
+  const char* tag = op_tag(OP, sizeof(T) == 8);
   hipEvent_t ev;
   c.prof_begin(tag, s, &ev);
   int rc = launch_bricks<DIM, T, OP>(dm, a, s, part_off);
@@ -670,7 +1022,7 @@ int apply_t(Ctx& c, const LevelView& L, const T* x, T* y, const T* phi, hipStrea
   if (cb > 0 || o.fuse_dot) {
     const unsigned g = (unsigned)(cb > 0 ? cb : 1);
     c.prof_begin("combine", s, &ev);
-    k_combine<T, TR::NF, TR::MASK><<<dim3(g), dim3(256), 0, s>>>(
+    k_combine<T, TR::NO, TR::WALL><<<dim3(g), dim3(256), 0, s>>>(
         dm.comb_node, dm.comb_ptr, dm.comb_ent, dm.n_comb, (const T*)L.slots, dm.n_slots, y, x, dm.n, dm.wall,
         o.fuse_dot ? c.partials + part_off : nullptr, o.done);
     CHNS_HIP(hipGetLastError());
@@ -683,18 +1035,41 @@ int apply_t(Ctx& c, const LevelView& L, const T* x, T* y, const T* phi, hipStrea
   return CHNS_OK;
 }
 
+template <int OP, typename T>
+int apply_d(Ctx& c, const LevelView& L, const T* x, T* y, const T* const* cf, hipStream_t s, const ApplyOut& o) {
+  return L.dm->dim == 3 ? apply_t<3, T, OP>(c, L, x, y, cf, s, o) : apply_t<2, T, OP>(c, L, x, y, cf, s, o);
+}
+
 template <typename T>
 int apply_dispatch(Ctx& c, const LevelView& L, int op, const T* x, T* y, const T* phi, hipStream_t s,
                    const ApplyOut& o) {
-  const int dim = L.dm->dim;
+  const T* one[1] = {phi};
   switch (op) {
     case CHNS_OP_PRESSURE:
-      return dim == 3 ? apply_t<3, T, K_PP>(c, L, x, y, phi, s, o) : apply_t<2, T, K_PP>(c, L, x, y, phi, s, o);
+      return apply_d<K_PP, T>(c, L, x, y, one, s, o);
     case CHNS_OP_MASS:
-      return dim == 3 ? apply_t<3, T, K_MASS>(c, L, x, y, phi, s, o) : apply_t<2, T, K_MASS>(c, L, x, y, phi, s, o);
+      return apply_d<K_MASS, T>(c, L, x, y, one, s, o);
     case CHNS_OP_MASS_RHO:
-      return dim == 3 ? apply_t<3, T, K_MASS_RHO>(c, L, x, y, phi, s, o)
-                      : apply_t<2, T, K_MASS_RHO>(c, L, x, y, phi, s, o);
+      return apply_d<K_MASS_RHO, T>(c, L, x, y, one, s, o);
+  }
+  if constexpr (sizeof(T) == 8) {
+    const int64_t n = L.dm->n;
+    const double* cf[kMaxCoef] = {};
+    if (op == CHNS_OP_MOMENTUM || op == CHNS_OP_CH_JACOBIAN) {
+      const bool mom = op == CHNS_OP_MOMENTUM;
+      const double* base = mom ? c.coef_mom : c.coef_chj;
+      if (!base || !(mom ? c.coef_mom_set : c.coef_chj_set)) {
+        set_error("chns_set_coefficients must be called for this operator first");
+        return CHNS_ESTATE;
+      }
+      for (int k = 0; k < 2 + L.dm->dim; ++k) cf[k] = base + k * n;
+      return mom ? apply_d<K_VP, double>(c, L, x, y, cf, s, o) : apply_d<K_CH_JAC, double>(c, L, x, y, cf, s, o);
+    }
+  } else {
+    if (op == CHNS_OP_MOMENTUM || op == CHNS_OP_CH_JACOBIAN) {
+      set_error("the momentum and Cahn-Hilliard operators are FP64 only");
+      return CHNS_EINVAL;
+    }
   }
   set_error("operator not available");
   return CHNS_EINVAL;
@@ -720,9 +1095,13 @@ LevelView fine_view(Ctx& c) { return LevelView{&c.dm, c.phi64, c.phi32, c.slots}
 
 int launch_apply_lv(Ctx& c, const LevelView& L, int op, int prec, const void* x, void* y, hipStream_t s,
                     const ApplyOut& o) {
-  if (op != CHNS_OP_MASS && !c.phi_set) {
+  if ((op == CHNS_OP_PRESSURE || op == CHNS_OP_MASS_RHO) && !c.phi_set) {
     set_error("set_phase_field must be called before this operator");
     return CHNS_ESTATE;
+  }
+  if ((op == CHNS_OP_MOMENTUM || op == CHNS_OP_CH_JACOBIAN) && L.dm != &c.dm) {
+    set_error("the momentum and Cahn-Hilliard operators act on the fine mesh only");
+    return CHNS_EINVAL;
   }
   if (prec == CHNS_FP64) return apply_dispatch<double>(c, L, op, (const double*)x, (double*)y, L.phi64, s, o);
   if (prec == CHNS_FP32) return apply_dispatch<float>(c, L, op, (const float*)x, (float*)y, L.phi32, s, o);
@@ -734,6 +1113,34 @@ int launch_apply(Ctx& c, int op, int prec, const void* x, void* y, hipStream_t s
   return launch_apply_lv(c, fine_view(c), op, prec, x, y, s, o);
 }
 
+static_assert((int)FORM_CH_RES == (int)K_CH_RES && (int)FORM_CH_JAC == (int)K_CH_JAC && (int)FORM_VP == (int)K_VP &&
+                  (int)FORM_VP_RHS == (int)K_VP_RHS && (int)FORM_PP_RHS == (int)K_PP_RHS &&
+                  (int)FORM_VU_RHS == (int)K_VU_RHS && (int)FORM_ENERGY == (int)K_ENERGY,
+              "form numbering");
+
+int launch_form(Ctx& c, int form, const double* x, const double* const* cf, double* y, hipStream_t s,
+                const ApplyOut& o) {
+  const LevelView L = fine_view(c);
+  switch (form) {
+    case FORM_CH_RES:
+      return apply_d<K_CH_RES, double>(c, L, x, y, cf, s, o);
+    case FORM_CH_JAC:
+      return apply_d<K_CH_JAC, double>(c, L, x, y, cf, s, o);
+    case FORM_VP:
+      return apply_d<K_VP, double>(c, L, x, y, cf, s, o);
+    case FORM_VP_RHS:
+      return apply_d<K_VP_RHS, double>(c, L, x, y, cf, s, o);
+    case FORM_PP_RHS:
+      return apply_d<K_PP_RHS, double>(c, L, x, y, cf, s, o);
+    case FORM_VU_RHS:
+      return apply_d<K_VU_RHS, double>(c, L, x, y, cf, s, o);
+    case FORM_ENERGY:
+      return apply_d<K_ENERGY, double>(c, L, x, y, cf, s, o);
+  }
+  set_error("unknown form");
+  return CHNS_EINVAL;
+}
+
 // Exact diagonal of P^T K P by probing: colour classes never share a leaf
 // (directly or through constraint parents), so y = A 1_c has y_i = A_ii on
 // colour c.
@@ -743,20 +1150,44 @@ int launch_diagonal_lv(Ctx& c, const LevelView& L, int op, int prec, void* d, bo
   const int nf = op_fields(op, L.dm->dim);
   const unsigned g = (unsigned)((n + 255) / 256);
   ApplyOut o{};
+  // fields of the Cahn-Hilliard Jacobian are coupled: probe them one at a time
+  const bool coupled = op == CHNS_OP_CH_JACOBIAN;
   for (int col = 0; col < L.dm->n_colors; ++col) {
-    if (prec == CHNS_FP64)
-      k_indicator<double><<<g, 256, 0, s>>>((double*)xi, L.dm->color, col, n, nf);
-    else
-      k_indicator<float><<<g, 256, 0, s>>>((float*)xi, L.dm->color, col, n, nf);
-    CHNS_HIP(hipGetLastError());
-    int rc = launch_apply_lv(c, L, op, prec, xi, yi, s, o);
-    if (rc) return rc;
-    if (prec == CHNS_FP64)
-      k_take_diag<double><<<g, 256, 0, s>>>((double*)d, (const double*)yi, L.dm->color, col, n, nf, invert);
-    else
-      k_take_diag<float><<<g, 256, 0, s>>>((float*)d, (const float*)yi, L.dm->color, col, n, nf, invert);
-    CHNS_HIP(hipGetLastError());
+    for (int f = coupled ? 0 : -1; f < (coupled ? nf : 0); ++f) {
+      if (prec == CHNS_FP64)
+        k_indicator<double><<<g, 256, 0, s>>>((double*)xi, L.dm->color, col, n, nf, f);
+      else
+        k_indicator<float><<<g, 256, 0, s>>>((float*)xi, L.dm->color, col, n, nf, f);
+      CHNS_HIP(hipGetLastError());
+      int rc = launch_apply_lv(c, L, op, prec, xi, yi, s, o);
+      if (rc) return rc;
+      if (prec == CHNS_FP64)
+        k_take_diag<double><<<g, 256, 0, s>>>((double*)d, (const double*)yi, L.dm->color, col, n, nf, invert, f);
+      else
+        k_take_diag<float><<<g, 256, 0, s>>>((float*)d, (const float*)yi, L.dm->color, col, n, nf, invert, f);
+      CHNS_HIP(hipGetLastError());
+    }
   }
+  return CHNS_OK;
+}
+
+// nf x nf node blocks of an FP64 operator (the couplings between the fields
+// of one node), by probing every field of every colour class
+int launch_block_diagonal(Ctx& c, int op, double* blk, double* xi, double* yi, hipStream_t s) {
+  const LevelView L = fine_view(c);
+  const int64_t n = L.dm->n;
+  const int nf = op_fields(op, L.dm->dim);
+  const unsigned g = (unsigned)((n + 255) / 256);
+  ApplyOut o{};
+  for (int col = 0; col < L.dm->n_colors; ++col)
+    for (int f = 0; f < nf; ++f) {
+      k_indicator<double><<<g, 256, 0, s>>>(xi, L.dm->color, col, n, nf, f);
+      CHNS_HIP(hipGetLastError());
+      int rc = launch_apply_lv(c, L, op, CHNS_FP64, xi, yi, s, o);
+      if (rc) return rc;
+      k_take_block<<<g, 256, 0, s>>>(blk, yi, L.dm->color, col, n, nf, f);
+      CHNS_HIP(hipGetLastError());
+    }
   return CHNS_OK;
 }
 

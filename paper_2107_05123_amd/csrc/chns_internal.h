@@ -133,12 +133,23 @@ struct Ctx {
 
   Multigrid* mg = nullptr;
 
+  // coefficient fields of the momentum and Cahn-Hilliard Jacobian operators
+  // (context-owned copies, (2 + dim) * n each): [phi~, mu~, u^] and
+  // [phi^{k+1}, phi^k, u~]
+  double* coef_mom = nullptr;
+  double* coef_chj = nullptr;
+  bool coef_mom_set = false, coef_chj_set = false;
+
+  struct Stepper* step = nullptr;  // time-step work arrays (chns_step.hip)
+
   // solves run on a context-owned stream (default priority) so that their
   // iterations can be captured into HIP graphs, cached per configuration
   hipStream_t work = nullptr;
   hipEvent_t ev_in = nullptr;
   struct GraphEntry {
-    int prec, pc, flexible;
+    int prec, pc, flexible, op;
+    const void* x;
+    const void* dinv;
     hipGraphExec_t exec;
   };
   std::vector<GraphEntry> graphs;
@@ -168,6 +179,7 @@ struct Ctx {
 };
 
 constexpr int kMaxPartials = 1 << 16;
+constexpr int kMaxCoefFields = 16;  // coefficient fields one element form may read
 
 // A mesh level as seen by the apply kernels: the fine level of a context or
 // one level of its multigrid hierarchy.
@@ -216,6 +228,21 @@ int run_captured(Ctx& c, hipGraphExec_t* cache, hipStream_t s, F&& enqueue) {
   return CHNS_OK;
 }
 
+// Element forms beyond the public operators (numbering shared with the
+// apply kernels).  Fields (each n long, vectors component-blocked):
+//   CH_RES  x = [phi^{k+1}, mu^{k+1}], cf = [phi^k, mu^k, u~_0..]    -> 2 fields
+//   CH_JAC  x = [dphi, dmu],           cf = [phi^{k+1}, phi^k, u~]   -> 2 fields
+//   VP      x = v (dim),               cf = [phi~, mu~, u^]          -> dim fields
+//   VP_RHS  cf = [phi~, mu~, u^, u^k, p^k]                          -> dim fields
+//   PP_RHS  cf = [phi~, mu~, u^, u^k, p^k, v]                       -> 1 field
+//   VU_RHS  cf = [phi~, mu~, u^, u^k, p^k, v, p^{k+1}]              -> dim fields
+//   ENERGY  cf = [phi, vertical coordinate, u]                       -> 1 field
+enum Form { FORM_CH_RES = 3, FORM_CH_JAC = 4, FORM_VP = 5, FORM_VP_RHS = 6, FORM_PP_RHS = 7, FORM_VU_RHS = 8,
+            FORM_ENERGY = 9 };
+int launch_form(Ctx& c, int form, const double* x, const double* const* cf, double* y, hipStream_t s,
+                const ApplyOut& o);
+int launch_block_diagonal(Ctx& c, int op, double* blk, double* xi, double* yi, hipStream_t s);
+
 // ---- geometric multigrid (gmg.hip)
 int mg_build(Ctx& c);
 int mg_setup(Ctx& c, hipStream_t s);
@@ -226,6 +253,18 @@ int mg_vcycle32(Ctx& c, const float* r, float* z, hipStream_t s);
 int launch_set_phase(Ctx& c, const double* phi, const double* prev, hipStream_t s);
 int solve_pressure_impl(Ctx& c, const double* b, double* x, const chns_solve_opts& o, chns_solve_stats& st,
                         hipStream_t s);
+// Jacobi-preconditioned CG to |b - A x| <= rtol |b| for an SPD operator (no
+// projection), on the calling stream; x in/out (n_fields * n).
+int solve_spd_impl(Ctx& c, int op, const double* b, double* x, const double* dinv, double rtol, int max_it,
+                   bool graphs, hipStream_t s, int* iters, double* rel);
+
+// ---- CHNS time step (chns_step.hip)
+int set_coefficients_impl(Ctx& c, int op, const double* const* fields, hipStream_t s);
+int assemble_impl(Ctx& c, int form, const double* const* fields, double* out, hipStream_t s);
+int initial_mu_impl(Ctx& c, const double* phi, double* mu, hipStream_t s);
+int advance_step_impl(Ctx& c, const chns_state& st, const chns_step_opts& o, chns_step_stats& stats,
+                      hipStream_t s);
+void destroy_stepper(Ctx& c);
 
 }  // namespace chns
 

@@ -384,9 +384,10 @@ int apply_pc(Ctx& c, int pc, const T* r, T* z, hipStream_t s) {
 // and the dot products.  flexible selects the Polak-Ribiere beta, which keeps
 // CG convergent for a preconditioner that varies between iterations.
 template <typename T>
-int pcg(Ctx& c, const T* b, T* x, int pc, const T* dinv, bool flexible, double tol2, int max_it, int depth,
+int pcg(Ctx& c, int op, const T* b, T* x, int pc, const T* dinv, bool flexible, double tol2, int max_it, int depth,
         bool graphs, hipStream_t s, int* iters, double* rr_out) {
-  const int64_t n = c.dm.n;
+  // all fields of the operator form one vector (block-diagonal operators)
+  const int64_t n = c.dm.n * op_fields(op, c.dm.dim);
   const int prec = sizeof(T) == 8 ? CHNS_FP64 : CHNS_FP32;
   for (int k = 0; k < 4; ++k)
     if (ensure_work<T>(c, k)) return CHNS_ENOMEM;
@@ -401,7 +402,7 @@ int pcg(Ctx& c, const T* b, T* x, int pc, const T* dinv, bool flexible, double t
   if (rc) return rc;
   k_init_scalars<<<1, 1, 0, s>>>(c.sc, tol2, max_it);
   ApplyOut plain{};
-  if ((rc = launch_apply(c, CHNS_OP_PRESSURE, prec, x, q, s, plain))) return rc;
+  if ((rc = launch_apply(c, op, prec, x, q, s, plain))) return rc;
   if (fused_pc) {
     k_cg_init<T><<<g, kThreads, 0, s>>>(b, q, r, z, p, pc == PCK_JACOBI ? dinv : nullptr, n, c.sc, c.partials,
                                         c.counter);
@@ -418,7 +419,7 @@ int pcg(Ctx& c, const T* b, T* x, int pc, const T* dinv, bool flexible, double t
   fused.done = &c.sc->done;
   auto iteration = [&](hipStream_t st) -> int {
     int e;
-    if ((e = launch_apply(c, CHNS_OP_PRESSURE, prec, p, q, st, fused))) return e;
+    if ((e = launch_apply(c, op, prec, p, q, st, fused))) return e;
     if (fused_pc) {
       k_cg_update<T><<<g, kThreads, 0, st>>>(x, r, z, p, q, pc == PCK_JACOBI ? dinv : nullptr, n, c.sc,
                                              c.partials, c.counter);
@@ -433,12 +434,15 @@ int pcg(Ctx& c, const T* b, T* x, int pc, const T* dinv, bool flexible, double t
     CHNS_HIP(hipGetLastError());
     return CHNS_OK;
   };
-  // one HIP graph per (precision, preconditioner, variant); buffers are
-  // context-owned, so the graph stays valid across solves
+  // one HIP graph per (operator, precision, preconditioner, variant, solution
+  // and diagonal buffers); work buffers are context-owned, so the graph stays
+  // valid across solves
   hipGraphExec_t exec = nullptr;
   if (graphs && !c.prof) {
     for (auto& ge : c.graphs)
-      if (ge.prec == prec && ge.pc == pc && ge.flexible == (int)flexible) exec = ge.exec;
+      if (ge.prec == prec && ge.pc == pc && ge.flexible == (int)flexible && ge.op == op && ge.x == (const void*)x &&
+          ge.dinv == (const void*)dinv)
+        exec = ge.exec;
     if (!exec) {
       hipGraph_t graph = nullptr;
       CHNS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
@@ -449,7 +453,7 @@ int pcg(Ctx& c, const T* b, T* x, int pc, const T* dinv, bool flexible, double t
       hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
       (void)hipGraphDestroy(graph);
       if (ie != hipSuccess) return hip_fail(ie, "hipGraphInstantiate");
-      c.graphs.push_back({prec, pc, (int)flexible, exec});
+      c.graphs.push_back({prec, pc, (int)flexible, op, (const void*)x, (const void*)dinv, exec});
     }
   }
   DevScalars snap{};
@@ -569,7 +573,7 @@ int solve_pressure_impl(Ctx& c, const double* b_in, double* x_out, const chns_so
   if (!mixed) {
     int it = 0;
     double rr = 0;
-    rc = pcg<double>(c, b, x, pck, c.diag64, false, tol2, o.max_it, depth, graphs, s, &it, &rr);
+    rc = pcg<double>(c, CHNS_OP_PRESSURE, b, x, pck, c.diag64, false, tol2, o.max_it, depth, graphs, s, &it, &rr);
     if (rc) return rc;
     st.iterations = it;
     st.outer_iterations = 1;
@@ -603,8 +607,8 @@ int solve_pressure_impl(Ctx& c, const double* b_in, double* x_out, const chns_so
       int it = 0;
       double rri = 0;
       const double itol = o.inner_rtol;
-      rc = pcg<float>(c, r32, d32, pck, c.diag32, false, itol * itol, o.max_it - total, depth, graphs, s, &it,
-                      &rri);
+      rc = pcg<float>(c, CHNS_OP_PRESSURE, r32, d32, pck, c.diag32, false, itol * itol, o.max_it - total, depth,
+                      graphs, s, &it, &rri);
       if (rc) return rc;
       total += it;
       k_ir_correct<<<g, kThreads, 0, s>>>(x, d32, rn, n);
@@ -629,6 +633,34 @@ int solve_pressure_impl(Ctx& c, const double* b_in, double* x_out, const chns_so
   st.ms_solve = t_solve.ms();
   if (!(st.rel_residual <= o.rtol)) {
     set_error("pressure solve did not reach rtol");
+    return CHNS_ENOCONV;
+  }
+  return CHNS_OK;
+}
+
+int solve_spd_impl(Ctx& c, int op, const double* b, double* x, const double* dinv, double rtol, int max_it,
+                   bool graphs, hipStream_t s, int* iters, double* rel) {
+  const int64_t n = c.dm.n * op_fields(op, c.dm.dim);
+  const unsigned g = grid_for(n);
+  int rc;
+  k_dot<double><<<g, kThreads, 0, s>>>(b, b, n, c.partials, c.counter, &c.sc->bb);
+  if ((rc = fin(c, s, g, 1, FIN_STORE, &c.sc->bb, 0))) return rc;
+  if ((rc = read_scalars(c, s))) return rc;
+  const double bb = c.sc_host->bb;
+  *iters = 0;
+  *rel = 0.0;
+  if (bb == 0.0) {
+    k_fill<double><<<g, kThreads, 0, s>>>(x, 0.0, n);
+    CHNS_HIP(hipGetLastError());
+    return CHNS_OK;
+  }
+  double rr = 0.0;
+  rc = pcg<double>(c, op, b, x, dinv ? PCK_JACOBI : PCK_NONE, dinv, false, rtol * rtol * bb, max_it, 16, graphs, s,
+                   iters, &rr);
+  if (rc) return rc;
+  *rel = std::sqrt(rr / bb);
+  if (!(*rel <= rtol)) {
+    set_error("CG solve did not reach rtol");
     return CHNS_ENOCONV;
   }
   return CHNS_OK;

@@ -1,0 +1,242 @@
+"""GPU parity of the Cahn-Hilliard / VMS momentum forms and of the projection
+time step against the FP64 oracle (oracle/chns.py).
+
+Bars: every matrix-free form (CH residual, Newton Jacobian apply, velocity
+prediction apply, the three right-hand sides, energy) agrees with the
+oracle's assembled result to 1e-12 relative (2-norm of the difference over the
+2-norm of the oracle result, and every entry within 1e-12 of max|ref|); the
+initial chemical potential (a CG solve to 1e-13) to 1e-10; whole time steps
+to 1e-6 relative in the 2-norm of every field after ten steps of the 2D 64x64
+configuration (the tolerance proposed for it), with the same Newton
+iteration counts.  The oracle solves every linear system exactly; in the
+parity runs the GPU's Krylov solves stop at a relative residual of 1e-11, so
+that the comparison measures the discretisation arithmetic: at the default
+1e-8 the pressure of the singular, ill-conditioned Poisson system can differ
+by cond(A) * 1e-8, of order 1e-5 on this mesh.
+"""
+import numpy as np
+import pytest
+
+from oracle import chns
+
+from ._pairs import Pair
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+# (kind, dim, lmin, lmax, phase-field kind, Cn)
+CASES = [
+    ("uniform", 2, 6, 6, "drop2d", 0.02),
+    ("band", 2, 3, 7, "bubble", 0.02),
+    ("uniform", 3, 3, 3, "bubble", 0.05),
+    ("band", 3, 2, 5, "bubble", 0.03),
+]
+
+
+def _params(cn):
+    return dict(Re=100.0, We=1.0, Cn=cn, Fr=1.0, rho_plus=1.0, rho_minus=0.1, eta_plus=1.0, eta_minus=0.1,
+                dt=1e-3)
+
+
+def _dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _close(y, ref, tol=1e-12):
+    r2 = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    rinf = np.abs(y - ref).max() / np.abs(ref).max()
+    assert r2 <= tol and rinf <= tol, (r2, rinf)
+
+
+class Case:
+    def __init__(self, spec):
+        kind, dim, lmin, lmax, phik, cn = spec
+        from paper_2107_05123_amd import Context
+        self.pair = Pair(kind, dim, lmin, lmax, band=0.03 if dim == 3 else 0.02)
+        self.dim = dim
+        self.n = self.pair.lib.n_nodes
+        self.prm_kw = _params(cn)
+        self.prm = chns.Params(**self.prm_kw)
+        self.ctx = Context(self.pair.lib, **self.prm_kw)
+        self.el = chns.Elems(self.pair.orc)
+        rng = np.random.default_rng(7)
+        n = self.n
+        # library-order inputs
+        self.phi0 = self.pair.phi(phik, cn=cn)
+        self.phi1 = self.phi0 + 0.05 * rng.standard_normal(n)
+        self.mu0 = 0.1 * rng.standard_normal(n)
+        self.mu1 = self.mu0 + 0.05 * rng.standard_normal(n)
+        self.u = 0.3 * rng.standard_normal((dim, n))
+        self.uprev = 0.3 * rng.standard_normal((dim, n))
+        self.v = 0.3 * rng.standard_normal((dim, n))
+        self.p = rng.standard_normal(n)
+        self.pnew = rng.standard_normal(n)
+        print(f"case {spec}: n={n} hanging={self.pair.lib.info.n_hanging}", flush=True)
+
+    def o(self, v):  # library order -> oracle order (vectors or stacks of them)
+        v = np.asarray(v)
+        return np.stack([self.pair.to_orc(c) for c in v]) if v.ndim == 2 else self.pair.to_orc(v)
+
+    def lib(self, v):
+        v = np.asarray(v)
+        return np.stack([self.pair.to_lib(c) for c in v]) if v.ndim == 2 else self.pair.to_lib(v)
+
+    def qpstate(self, phit, mut, uhat):
+        return chns.QPState(self.el, self.prm, self.o(phit), self.o(mut), self.o(uhat), self.o(self.u),
+                            self.o(self.p))
+
+
+@pytest.fixture(scope="module", params=CASES, ids=lambda c: f"{c[0]}{c[1]}d_l{c[2]}-{c[3]}")
+def case(request):
+    return Case(request.param)
+
+
+def test_ch_residual_matches_oracle(case):
+    from paper_2107_05123_amd import _lib as L
+    c = case
+    ut = 0.5 * (c.u + c.v)
+    X = np.concatenate([c.phi1, c.mu1])
+    r = c.ctx.assemble(L.FORM_CH_RESIDUAL, [_dev(X), _dev(c.phi0), _dev(c.mu0), _dev(ut.reshape(-1))])
+    r = r.cpu().numpy().reshape(2, -1)
+    Rp, Rm = chns.ch_residual(c.el, c.prm, c.o(c.phi1), c.o(c.mu1), c.o(c.phi0), c.o(c.mu0), c.o(ut))
+    _close(r[0], c.lib(Rp))
+    _close(r[1], c.lib(Rm))
+
+
+def test_ch_jacobian_apply_and_diagonal_match_oracle(case):
+    c = case
+    ut = 0.5 * (c.u + c.v)
+    c.ctx.set_coefficients(c.ctx.CH_JACOBIAN, [_dev(c.phi1), _dev(c.phi0), _dev(ut.reshape(-1))])
+    d = np.random.default_rng(3).standard_normal((2, c.n))
+    y = c.ctx.apply(c.ctx.CH_JACOBIAN, _dev(d.reshape(-1))).cpu().numpy().reshape(2, -1)
+    J = chns.ch_jacobian(c.el, c.prm, c.o(c.phi1), c.o(c.phi0), c.o(ut))
+    ref = (J @ np.concatenate([c.o(d[0]), c.o(d[1])])).reshape(2, -1)
+    _close(y[0], c.lib(ref[0]))
+    _close(y[1], c.lib(ref[1]))
+    dg = c.ctx.diagonal(c.ctx.CH_JACOBIAN).cpu().numpy().reshape(2, -1)
+    dref = J.diagonal().reshape(2, -1)
+    _close(dg[0], c.lib(dref[0]))
+    _close(dg[1], c.lib(dref[1]))
+
+
+def test_momentum_apply_and_diagonal_match_oracle(case):
+    c = case
+    phit, mut = 0.5 * (c.phi1 + c.phi0), 0.5 * (c.mu1 + c.mu0)
+    uhat = 1.5 * c.u - 0.5 * c.uprev
+    c.ctx.set_coefficients(c.ctx.MOMENTUM, [_dev(phit), _dev(mut), _dev(uhat.reshape(-1))])
+    y = c.ctx.apply(c.ctx.MOMENTUM, _dev(c.v.reshape(-1))).cpu().numpy().reshape(c.dim, -1)
+    A = chns.vp_matrix(c.el, c.prm, c.qpstate(phit, mut, uhat))
+    for i in range(c.dim):
+        _close(y[i], c.lib(A @ c.o(c.v[i])))
+    dg = c.ctx.diagonal(c.ctx.MOMENTUM).cpu().numpy().reshape(c.dim, -1)
+    for i in range(c.dim):
+        _close(dg[i], c.lib(A.diagonal()))
+
+
+def test_right_hand_sides_match_oracle(case):
+    from paper_2107_05123_amd import _lib as L
+    c = case
+    phit, mut = 0.5 * (c.phi1 + c.phi0), 0.5 * (c.mu1 + c.mu0)
+    uhat = 1.5 * c.u - 0.5 * c.uprev
+    S = c.qpstate(phit, mut, uhat)
+    base = [_dev(phit), _dev(mut), _dev(uhat.reshape(-1)), _dev(c.u.reshape(-1)), _dev(c.p)]
+    vp = c.ctx.assemble(L.FORM_VP_RHS, base).cpu().numpy().reshape(c.dim, -1)
+    ref = chns.vp_rhs(c.el, c.prm, S, c.o(c.u), c.o(c.p), c.o(phit))
+    for i in range(c.dim):
+        _close(vp[i], c.lib(ref[i]))
+    pp = c.ctx.assemble(L.FORM_PP_RHS, base + [_dev(c.v.reshape(-1))]).cpu().numpy()
+    _close(pp, c.lib(chns.pp_rhs(c.el, c.prm, S, c.o(c.v), c.o(c.p))))
+    vu = c.ctx.assemble(L.FORM_VU_RHS, base + [_dev(c.v.reshape(-1)), _dev(c.pnew)]).cpu().numpy()
+    vu = vu.reshape(c.dim, -1)
+    ref = chns.vu_rhs(c.el, c.prm, S, c.o(c.v), c.o(c.pnew), c.o(c.p))
+    for i in range(c.dim):
+        _close(vu[i], c.lib(ref[i]))
+
+
+def test_energy_and_initial_mu_match_oracle(case):
+    from paper_2107_05123_amd import _lib as L
+    c = case
+    e = c.ctx.assemble(L.FORM_ENERGY, [_dev(c.phi1), _dev(c.u.reshape(-1))]).sum().item()
+    st = chns.State(u=c.o(c.u), u_prev=c.o(c.u), p=c.o(c.p), phi=c.o(c.phi1), mu=c.o(c.mu1))
+    ref = chns.energy(c.el, c.prm, st)
+    assert abs(e - ref) <= 1e-12 * abs(ref), (e, ref)
+    mu = c.ctx.initial_mu(_dev(c.phi0)).cpu().numpy()
+    mref = c.lib(chns.initial_mu(c.el, c.prm, c.o(c.phi0)))
+    _close(mu, mref, tol=1e-10)
+
+
+def _run_steps(case, nsteps, **kw):
+    c = case
+    kw.setdefault("lin_rtol", 1e-11)
+    phi0 = c.phi0
+    mu0 = c.ctx.initial_mu(_dev(phi0))
+    z = np.zeros((c.dim, c.n))
+    state = {"u": _dev(z.reshape(-1)), "u_prev": _dev(z.reshape(-1)), "p": _dev(np.zeros(c.n)), "phi": _dev(phi0),
+             "mu": mu0}
+    stats = [c.ctx.advance_step(state, **kw) for _ in range(nsteps)]
+    return state, stats
+
+
+def _oracle_steps(case, nsteps):
+    c = case
+    st = chns.initial_state(c.el, c.prm, c.o(c.phi0))
+    infos = []
+    for _ in range(nsteps):
+        st, info = chns.step(c.el, c.prm, st)
+        infos.append(info)
+    return st, infos
+
+
+def _compare_states(case, state, st, tol):
+    c = case
+    got = {k: v.cpu().numpy() for k, v in state.items()}
+    for name, ref in (("phi", st.phi), ("mu", st.mu), ("p", st.p)):
+        g = c.o(got[name])
+        err = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+        assert err <= tol, (name, err)
+    u = c.o(got["u"].reshape(c.dim, -1))
+    err = np.linalg.norm(u - st.u) / np.linalg.norm(st.u)
+    assert err <= tol, ("u", err)
+
+
+@pytest.mark.parametrize("nsteps", [10])
+def test_ten_steps_of_the_2d_drop_match_oracle(nsteps):
+    c = Case(CASES[0])
+    state, stats = _run_steps(c, nsteps)
+    st, infos = _oracle_steps(c, nsteps)
+    for s, i in zip(stats, infos):
+        print("gpu", s, "oracle newton", i["newton"], flush=True)
+        assert s["newton"] == i["newton"]
+    _compare_states(c, state, st, 1e-6)
+    assert abs(stats[-1]["mass"] - chns.mass(c.el, st.phi)) <= 1e-10 * abs(chns.mass(c.el, st.phi))
+    e = chns.energy(c.el, c.prm, st)
+    assert abs(stats[-1]["energy"] - e) <= 1e-8 * abs(e)
+
+
+@pytest.mark.parametrize("idx", [1, 2, 3])
+def test_steps_on_adaptive_and_3d_meshes_match_oracle(idx):
+    c = Case(CASES[idx])
+    nsteps = 2
+    state, stats = _run_steps(c, nsteps)
+    st, infos = _oracle_steps(c, nsteps)
+    for s, i in zip(stats, infos):
+        print("gpu", s, "oracle newton", i["newton"], flush=True)
+    _compare_states(c, state, st, 1e-6)
+
+
+def test_step_is_deterministic_and_graph_replay_matches_eager():
+    c = Case(CASES[1])
+    a, _ = _run_steps(c, 2)
+    b, _ = _run_steps(c, 2)
+    e, _ = _run_steps(c, 2, graphs=False)
+    for k in a:
+        assert torch.equal(a[k], b[k]), k
+        assert torch.equal(a[k], e[k]), k
+
+
+def test_step_with_gmg_pressure_solves_matches_oracle():
+    c = Case(CASES[0])
+    state, stats = _run_steps(c, 3, pp_pc="gmg")
+    st, _ = _oracle_steps(c, 3)
+    _compare_states(c, state, st, 1e-6)
+    assert all(s["pp_iterations"] < 200 for s in stats)
