@@ -181,6 +181,61 @@ def profile_run(torch, with_solve=True):
     print(json.dumps({"profile_run": "done", "iterations": it, "copy_bytes": 2 * big.numel() * 8}))
 
 
+def time_op(torch, ctx, op, x, n_warm=5, n_rep=30):
+    """Median HIP-event time of one apply of `op`."""
+    y = torch.empty_like(x)
+    for _ in range(n_warm):
+        ctx.apply(op, x, y)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_rep)]
+    for a, b in ev:
+        a.record()
+        ctx.apply(op, x, y)
+        b.record()
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+
+def chns_measure(torch, mesh, ctx, phi_d):
+    """CHNS applies on the 128^3 mesh (VMS momentum, 3 DoF per node; CH Newton
+    Jacobian, 2 DoF per node) and the per-step time of the 2D 64x64 drop
+    (Re 100, We 1, Cn 0.02, density and viscosity ratios 10, dt 1e-3, two
+    blocks per step)."""
+    from paper_2107_05123_amd import Context, Mesh
+    n = mesh.n_nodes
+    g = torch.Generator(device="cuda").manual_seed(5)
+    mu = 0.1 * torch.randn(n, dtype=torch.float64, device="cuda", generator=g)
+    u = 0.3 * torch.randn(3 * n, dtype=torch.float64, device="cuda", generator=g)
+    ctx.set_coefficients(ctx.MOMENTUM, [phi_d, mu, u])
+    ctx.set_coefficients(ctx.CH_JACOBIAN, [phi_d, phi_d, u])
+    ms_vp = time_op(torch, ctx, ctx.MOMENTUM, torch.randn(3 * n, dtype=torch.float64, device="cuda", generator=g))
+    ms_ch = time_op(torch, ctx, ctx.CH_JACOBIAN, torch.randn(2 * n, dtype=torch.float64, device="cuda",
+                                                             generator=g))
+    out = {"momentum_apply": {"ms": ms_vp, "gdof_s": 3 * n / (ms_vp * 1e-3) / 1e9},
+           "ch_jacobian_apply": {"ms": ms_ch, "gdof_s": 2 * n / (ms_ch * 1e-3) / 1e9}}
+    # 2D drop, 64 x 64
+    m2 = Mesh(dim=2, min_level=6, max_level=6, rule="uniform")
+    x2 = ci.unit_coords(m2.node_coords(), 6)
+    c2 = Context(m2, Re=100.0, We=1.0, Cn=0.02, Fr=1.0, rho_plus=1.0, rho_minus=0.1, eta_plus=1.0,
+                 eta_minus=0.1, dt=1e-3)
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+    phi2 = dev(ci.phi_drop2d(x2, cn=0.02))
+    n2 = m2.n_nodes
+    st = {"u": dev(np.zeros(2 * n2)), "u_prev": dev(np.zeros(2 * n2)), "p": dev(np.zeros(n2)), "phi": phi2,
+          "mu": c2.initial_mu(phi2)}
+    c2.advance_step(st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [c2.advance_step(st) for _ in range(10)]
+    torch.cuda.synchronize()
+    out["step_2d_64"] = {"ms_per_step": 1e3 * (time.perf_counter() - t0) / 10,
+                         "newton": stats[-1]["newton"], "ch_gmres_it": stats[-1]["ch_iterations"],
+                         "vp_gmres_it": stats[-1]["vp_iterations"], "pp_cg_it": stats[-1]["pp_iterations"],
+                         "vu_cg_it": stats[-1]["vu_iterations"], "mass": stats[-1]["mass"],
+                         "energy": stats[-1]["energy"]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -281,6 +336,7 @@ def main():
         "iterations": st.iterations,
         "rel_residual": st.rel_residual,
         "host_mesh_build_s": t_mesh,
+        "chns": chns_measure(torch, mesh, ctx, phi_d),
     }
     if not args.no_cpu_baseline:
         lex = np.arange(n)  # uniform meshes are numbered lexicographically, x fastest
