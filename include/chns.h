@@ -274,6 +274,57 @@ typedef struct chns_step_stats {
 int chns_advance_step(chns_ctx* ctx, chns_state* state, const chns_step_opts* opts, chns_step_stats* stats,
                       void* stream);
 
+/* ------------------------------------------------ learned preconditioner */
+
+/* A 3D U-Net on the node grid of a uniform 3D mesh (4 levels, channels
+ * 16/32/48/64, two 3x3x3 conv + ReLU per level and side, 2x2x2 average
+ * pooling, nearest upsampling with skip concatenation, 1x1x1 output conv),
+ * bfloat16 weights and activations with FP32 accumulation (MFMA), FP32
+ * master weights and Adam.  Inputs per voxel: log(1/rho(phi*)) normalised by
+ * log(rho+/rho-), and r / rms(r).  As the preconditioner CHNS_PC_LEARNED of
+ * chns_solve_pressure (flexible CG): z = rms(r) K Net(...) with 1^T z = 0.
+ * The paper preconditions with algebraic multigrid; this network is an
+ * addition of this library.  Weights belong to the context.               */
+
+/* Deterministic He initialisation from `seed`; out_scale is K.  Async.     */
+int chns_pc_init(chns_ctx* ctx, uint64_t seed, float out_scale, void* stream);
+/* Weight blob: "CHNSUNET", u32 version (1), u32 layers (14), f32 K, then per
+ * layer u32 ci, u32 co, f32 W[27][ci][co] (tap = 9(dz+1) + 3(dy+1) + dx+1),
+ * then u32 16, f32 w_out[16]; little endian.  EINVAL on any mismatch.      */
+int chns_pc_load(chns_ctx* ctx, const void* blob, size_t n, void* stream);
+/* *n = blob size; writes the blob when blob != NULL and cap >= *n.         */
+int chns_pc_save(chns_ctx* ctx, void* blob, size_t cap, size_t* n);
+/* Number of FP32 parameters (the blob's weights in order).                 */
+int chns_pc_param_count(chns_ctx* ctx, size_t* n);
+/* Gradient of the last chns_pc_train_step's mean loss, in parameter order,
+ * host buffer of exactly chns_pc_param_count floats.                       */
+int chns_pc_gradients(chns_ctx* ctx, float* host, size_t n);
+
+/* Network output on a crop of the node grid: crop^3 voxels (crop a multiple
+ * of 8) starting at node `origin` (x, y, z; host) with axes mirrored inside
+ * the crop by the bits of `flip`; voxels beyond the grid are zero input.
+ * phi, r: device FP64 node vectors; out: device FP32, crop^3 (x fastest).
+ * Async.                                                                   */
+int chns_pc_forward(chns_ctx* ctx, const double* phi, const double* r, const int32_t* origin, int flip, int crop,
+                    float* out, void* stream);
+
+/* One training step: for each sample the crop of (phi, r, e) is packed as
+ * above, the target is e / (rms(r) K) (e = exact solution minus iterate),
+ * the loss is the mean squared error over voxels inside the grid, averaged
+ * over the samples; gradients by backpropagation (MFMA input and weight
+ * gradients), then one Adam step (b1 0.9, b2 0.999, eps 1e-8) when lr > 0.
+ * Synchronises `stream`.                                                   */
+typedef struct chns_pc_batch {
+  int n;                      /* samples                                      */
+  const double* const* phi;   /* host array of n device pointers (n_nodes)   */
+  const double* const* r;     /* residuals                                   */
+  const double* const* e;     /* errors                                      */
+  const int32_t* origin;      /* host, 3 per sample (x, y, z) in nodes       */
+  const int32_t* flip;        /* host, per sample; may be NULL               */
+  int crop;                   /* crop edge, multiple of 8                    */
+} chns_pc_batch;
+int chns_pc_train_step(chns_ctx* ctx, const chns_pc_batch* batch, float lr, float* loss, void* stream);
+
 /* ------------------------------------------------------------ profiling */
 
 /* Per-kernel timers (paper Sec. 6 reports per-solver time breakdowns; these

@@ -265,6 +265,56 @@ class Context:
                 "vu_iterations": ss.vu_iterations, "ch_residual": ss.ch_residual, "mass": ss.mass,
                 "energy": ss.energy, "ms": ss.ms}
 
+    # ------------------------------------------------ learned preconditioner
+    def pc_init(self, seed=0, out_scale=1.0, stream=None):
+        L.check(L.lib().chns_pc_init(self._h, int(seed), float(out_scale), _stream_ptr(stream)))
+
+    def pc_load(self, blob: bytes, stream=None):
+        buf = C.create_string_buffer(bytes(blob), len(blob))
+        L.check(L.lib().chns_pc_load(self._h, buf, len(blob), _stream_ptr(stream)))
+
+    def pc_save(self) -> bytes:
+        n = C.c_size_t()
+        L.check(L.lib().chns_pc_save(self._h, None, 0, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        L.check(L.lib().chns_pc_save(self._h, buf, n.value, C.byref(n)))
+        return buf.raw[:n.value]
+
+    def pc_param_count(self) -> int:
+        n = C.c_size_t()
+        L.check(L.lib().chns_pc_param_count(self._h, C.byref(n)))
+        return n.value
+
+    def pc_gradients(self) -> np.ndarray:
+        n = self.pc_param_count()
+        g = np.empty(n, dtype=np.float32)
+        L.check(L.lib().chns_pc_gradients(self._h, g.ctypes.data_as(C.c_void_p), n))
+        return g
+
+    def pc_forward(self, phi, r, origin=(0, 0, 0), flip=0, crop=16, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(crop ** 3, dtype=torch.float32, device=phi.device)
+        org = (C.c_int32 * 3)(*[int(v) for v in origin])
+        L.check(L.lib().chns_pc_forward(self._h, _dev_ptr(phi, torch.float64, self.n),
+                                        _dev_ptr(r, torch.float64, self.n), org, int(flip), int(crop),
+                                        _dev_ptr(out, torch.float32, crop ** 3), _stream_ptr(stream)))
+        return out
+
+    def pc_train_step(self, phis, rs, es, origins, crop, flips=None, lr=1e-3, stream=None) -> float:
+        import torch
+        k = len(rs)
+        P = (C.c_void_p * k)(*[_dev_ptr(t, torch.float64, self.n).value for t in phis])
+        R = (C.c_void_p * k)(*[_dev_ptr(t, torch.float64, self.n).value for t in rs])
+        E = (C.c_void_p * k)(*[_dev_ptr(t, torch.float64, self.n).value for t in es])
+        O = (C.c_int32 * (3 * k))(*[int(v) for o in origins for v in o])
+        F = (C.c_int32 * k)(*([int(f) for f in flips] if flips is not None else [0] * k))
+        b = L.PcBatch(k, C.cast(P, C.POINTER(C.c_void_p)), C.cast(R, C.POINTER(C.c_void_p)),
+                      C.cast(E, C.POINTER(C.c_void_p)), O, F, int(crop))
+        loss = C.c_float()
+        L.check(L.lib().chns_pc_train_step(self._h, C.byref(b), float(lr), C.byref(loss), _stream_ptr(stream)))
+        return loss.value
+
     def profile(self, enable=True):
         L.check(L.lib().chns_profile_enable(self._h, int(enable)))
 

@@ -78,6 +78,12 @@ class StepStats(C.Structure):
     ]
 
 
+class PcBatch(C.Structure):
+    _fields_ = [("n", C.c_int), ("phi", C.POINTER(C.c_void_p)), ("r", C.POINTER(C.c_void_p)),
+                ("e", C.POINTER(C.c_void_p)), ("origin", C.POINTER(C.c_int32)), ("flip", C.POINTER(C.c_int32)),
+                ("crop", C.c_int)]
+
+
 _lib = None
 
 # name -> (restype, argtypes)
@@ -105,6 +111,14 @@ SIGNATURES = {
     "chns_initial_mu": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "chns_advance_step": (C.c_int, [C.c_void_p, C.POINTER(State), C.POINTER(StepOpts), C.POINTER(StepStats),
                                     C.c_void_p]),
+    "chns_pc_init": (C.c_int, [C.c_void_p, C.c_uint64, C.c_float, C.c_void_p]),
+    "chns_pc_load": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "chns_pc_save": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)]),
+    "chns_pc_param_count": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    "chns_pc_gradients": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "chns_pc_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32), C.c_int, C.c_int,
+                                  C.c_void_p, C.c_void_p]),
+    "chns_pc_train_step": (C.c_int, [C.c_void_p, C.POINTER(PcBatch), C.c_float, C.POINTER(C.c_float), C.c_void_p]),
 }
 
 

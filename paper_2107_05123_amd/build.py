@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libchns.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["mesh_host.cpp", "abi.cpp", "apply.hip", "krylov.hip", "gmg.hip", "chns_step.hip"]
+SOURCES = ["mesh_host.cpp", "abi.cpp", "apply.hip", "krylov.hip", "gmg.hip", "chns_step.hip", "unet.hip"]
 
 COMMON = [
     "-std=c++17", "-O3", "-fPIC", "--offload-arch=gfx950",

@@ -58,6 +58,7 @@ void Ctx::prof_end(const char* tag, hipStream_t s, hipEvent_t start) {
 
 Ctx::~Ctx() {
   destroy_stepper(*this);
+  unet_destroy(*this);
   if (mg && mg->setup_exec) (void)hipGraphExecDestroy(mg->setup_exec);
   if (diag_exec) (void)hipGraphExecDestroy(diag_exec);
   delete mg;
@@ -421,6 +422,80 @@ int chns_advance_step(chns_ctx* ctx, chns_state* state, const chns_step_opts* op
   int rc = advance_step_impl(ctx->c, *state, o, st, (hipStream_t)stream);
   if (stats) *stats = st;
   return rc;
+  CHNS_GUARD_END
+}
+
+int chns_pc_init(chns_ctx* ctx, uint64_t seed, float out_scale, void* stream) {
+  CHNS_GUARD_BEGIN
+  if (!ctx || !(out_scale > 0.0f)) {
+    set_error("null context or non-positive output scale");
+    return CHNS_EINVAL;
+  }
+  return unet_init(ctx->c, seed, out_scale, (hipStream_t)stream);
+  CHNS_GUARD_END
+}
+
+int chns_pc_load(chns_ctx* ctx, const void* blob, size_t n, void* stream) {
+  CHNS_GUARD_BEGIN
+  if (!ctx || !blob) {
+    set_error("null argument");
+    return CHNS_EINVAL;
+  }
+  return unet_load(ctx->c, blob, n, (hipStream_t)stream);
+  CHNS_GUARD_END
+}
+
+int chns_pc_save(chns_ctx* ctx, void* blob, size_t cap, size_t* n) {
+  CHNS_GUARD_BEGIN
+  if (!ctx || !n) {
+    set_error("null argument");
+    return CHNS_EINVAL;
+  }
+  return unet_save(ctx->c, blob, cap, n);
+  CHNS_GUARD_END
+}
+
+int chns_pc_param_count(chns_ctx* ctx, size_t* n) {
+  CHNS_GUARD_BEGIN
+  if (!ctx || !n) {
+    set_error("null argument");
+    return CHNS_EINVAL;
+  }
+  int rc = unet_create(ctx->c);
+  if (rc) return rc;
+  *n = unet_param_count(ctx->c);
+  return CHNS_OK;
+  CHNS_GUARD_END
+}
+
+int chns_pc_gradients(chns_ctx* ctx, float* host, size_t n) {
+  CHNS_GUARD_BEGIN
+  if (!ctx || !host) {
+    set_error("null argument");
+    return CHNS_EINVAL;
+  }
+  return unet_gradients(ctx->c, host, n);
+  CHNS_GUARD_END
+}
+
+int chns_pc_forward(chns_ctx* ctx, const double* phi, const double* r, const int32_t* origin, int flip, int crop,
+                    float* out, void* stream) {
+  CHNS_GUARD_BEGIN
+  if (!ctx || !phi || !r || !origin || !out) {
+    set_error("null argument");
+    return CHNS_EINVAL;
+  }
+  return unet_forward_crop(ctx->c, phi, r, origin, flip, crop, out, (hipStream_t)stream);
+  CHNS_GUARD_END
+}
+
+int chns_pc_train_step(chns_ctx* ctx, const chns_pc_batch* batch, float lr, float* loss, void* stream) {
+  CHNS_GUARD_BEGIN
+  if (!ctx || !batch) {
+    set_error("null argument");
+    return CHNS_EINVAL;
+  }
+  return unet_train_step(ctx->c, *batch, lr, loss, (hipStream_t)stream);
   CHNS_GUARD_END
 }
 

@@ -141,6 +141,7 @@ struct Ctx {
   bool coef_mom_set = false, coef_chj_set = false;
 
   struct Stepper* step = nullptr;  // time-step work arrays (chns_step.hip)
+  struct UNet* unet = nullptr;     // learned preconditioner (unet.hip)
 
   // solves run on a context-owned stream (default priority) so that their
   // iterations can be captured into HIP graphs, cached per configuration
@@ -257,6 +258,22 @@ int solve_pressure_impl(Ctx& c, const double* b, double* x, const chns_solve_opt
 // projection), on the calling stream; x in/out (n_fields * n).
 int solve_spd_impl(Ctx& c, int op, const double* b, double* x, const double* dinv, double rtol, int max_it,
                    bool graphs, hipStream_t s, int* iters, double* rel);
+
+// ---- learned preconditioner (unet.hip)
+int unet_create(Ctx& c);
+void unet_destroy(Ctx& c);
+int unet_init(Ctx& c, uint64_t seed, float K, hipStream_t s);
+int unet_load(Ctx& c, const void* blob, size_t n, hipStream_t s);
+int unet_save(Ctx& c, void* blob, size_t cap, size_t* n);
+int unet_gradients(Ctx& c, float* host, size_t n);
+size_t unet_param_count(const Ctx& c);
+int unet_forward_crop(Ctx& c, const double* phi, const double* r, const int32_t* origin, int flip, int crop,
+                      float* out, hipStream_t s);
+int unet_train_step(Ctx& c, const chns_pc_batch& b, float lr, float* loss, hipStream_t s);
+int unet_prepare(Ctx& c);
+bool unet_ready(const Ctx& c);
+template <typename T>
+int unet_apply(Ctx& c, const T* r, T* z, hipStream_t s);
 
 // ---- CHNS time step (chns_step.hip)
 int set_coefficients_impl(Ctx& c, int op, const double* const* fields, hipStream_t s);

@@ -12,6 +12,7 @@
 // the paper solves the pressure Poisson system with PETSc Krylov methods
 // (appendix on solver options); CG is the natural choice for the symmetric
 // positive semi-definite operator.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 
@@ -366,7 +367,10 @@ struct Poller {
   }
 };
 
-enum PcKind { PCK_NONE = 0, PCK_JACOBI = 1, PCK_GMG = 2 };
+enum PcKind { PCK_NONE = 0, PCK_JACOBI = 1, PCK_GMG = 2, PCK_LEARNED = 3 };
+// iterations of flexible CG with the learned preconditioner before it is
+// abandoned for Jacobi (stagnation guard)
+constexpr int kLearnedCap = 400;
 
 template <typename T>
 int apply_pc(Ctx& c, int pc, const T* r, T* z, hipStream_t s) {
@@ -374,6 +378,7 @@ int apply_pc(Ctx& c, int pc, const T* r, T* z, hipStream_t s) {
     if constexpr (sizeof(T) == 8) return mg_vcycle64(c, (const double*)r, (double*)z, s);
     else return mg_vcycle32(c, (const float*)r, (float*)z, s);
   }
+  if (pc == PCK_LEARNED) return unet_apply<T>(c, r, z, s);
   set_error("unknown preconditioner");
   return CHNS_EINVAL;
 }
@@ -507,13 +512,23 @@ int solve_pressure_impl(Ctx& c, const double* b_in, double* x_out, const chns_so
     set_error("set_phase_field must be called before solve_pressure");
     return CHNS_ESTATE;
   }
-  if (o.pc != CHNS_PC_JACOBI && o.pc != CHNS_PC_NONE && o.pc != CHNS_PC_GMG) {
-    set_error("requested preconditioner is not available in this build");
+  if (o.pc != CHNS_PC_JACOBI && o.pc != CHNS_PC_NONE && o.pc != CHNS_PC_GMG && o.pc != CHNS_PC_LEARNED) {
+    set_error("unknown preconditioner");
     return CHNS_EINVAL;
   }
-  const int pck = o.pc == CHNS_PC_JACOBI ? PCK_JACOBI : (o.pc == CHNS_PC_GMG ? PCK_GMG : PCK_NONE);
+  const bool learned = o.pc == CHNS_PC_LEARNED;
+  if (learned) {
+    if (!unet_ready(c)) {
+      set_error("no learned preconditioner weights in this context (chns_pc_load or chns_pc_init)");
+      return CHNS_ESTATE;
+    }
+    int e = unet_prepare(c);
+    if (e) return e;
+  }
+  int pck = o.pc == CHNS_PC_JACOBI ? PCK_JACOBI
+                                   : (o.pc == CHNS_PC_GMG ? PCK_GMG : (learned ? PCK_LEARNED : PCK_NONE));
   // poll depth: cheap iterations can run far ahead, expensive ones not
-  const int depth = pck == PCK_GMG ? 2 : o.check_every;
+  const int depth = (pck == PCK_GMG || learned) ? 2 : o.check_every;
   Timer t_setup;
   // projected right-hand side kept in w64[4]
   for (int k = 0; k < 6; ++k)
@@ -532,7 +547,8 @@ int solve_pressure_impl(Ctx& c, const double* b_in, double* x_out, const chns_so
     if ((rc = mg_build(c))) return rc;
     if (!c.mg->setup_valid && (rc = mg_setup(c, s))) return rc;
   }
-  if (o.pc == CHNS_PC_JACOBI) {
+  if (o.pc == CHNS_PC_JACOBI || learned) {
+    // (the learned preconditioner falls back to Jacobi when it stagnates)
     if (!c.diag_valid) {
       if (!c.diag64) c.diag64 = (double*)c.dalloc(sizeof(double) * n);
       if (!c.diag32) c.diag32 = (float*)c.dalloc(sizeof(float) * n);
@@ -573,10 +589,20 @@ int solve_pressure_impl(Ctx& c, const double* b_in, double* x_out, const chns_so
   if (!mixed) {
     int it = 0;
     double rr = 0;
-    rc = pcg<double>(c, CHNS_OP_PRESSURE, b, x, pck, c.diag64, false, tol2, o.max_it, depth, graphs, s, &it, &rr);
+    const int cap = learned ? std::min(o.max_it, kLearnedCap) : o.max_it;
+    rc = pcg<double>(c, CHNS_OP_PRESSURE, b, x, pck, c.diag64, learned, tol2, cap, depth, graphs, s, &it, &rr);
     if (rc) return rc;
     st.iterations = it;
     st.outer_iterations = 1;
+    if (learned && !(rr <= tol2) && o.max_it > it) {
+      // stagnation guard: continue from the current iterate with Jacobi-PCG
+      st.fallback = 1;
+      int it2 = 0;
+      rc = pcg<double>(c, CHNS_OP_PRESSURE, b, x, PCK_JACOBI, c.diag64, false, tol2, o.max_it - it, o.check_every,
+                       graphs, s, &it2, &rr);
+      if (rc) return rc;
+      st.iterations += it2;
+    }
   } else {
     // FP64 iterative refinement: r = b - A x (FP64), inner FP32 CG on A d = r/|r|
     for (int k = 0; k < 5; ++k)
@@ -607,10 +633,17 @@ int solve_pressure_impl(Ctx& c, const double* b_in, double* x_out, const chns_so
       int it = 0;
       double rri = 0;
       const double itol = o.inner_rtol;
-      rc = pcg<float>(c, CHNS_OP_PRESSURE, r32, d32, pck, c.diag32, false, itol * itol, o.max_it - total, depth,
-                      graphs, s, &it, &rri);
+      const bool fcg = pck == PCK_LEARNED;
+      const int cap = fcg ? std::min(o.max_it - total, kLearnedCap) : o.max_it - total;
+      rc = pcg<float>(c, CHNS_OP_PRESSURE, r32, d32, pck, c.diag32, fcg, itol * itol, cap, depth, graphs, s, &it,
+                      &rri);
       if (rc) return rc;
       total += it;
+      if (fcg && !(rri <= itol * itol)) {
+        // stagnation guard: the remaining refinement steps use Jacobi
+        st.fallback = 1;
+        pck = PCK_JACOBI;
+      }
       k_ir_correct<<<g, kThreads, 0, s>>>(x, d32, rn, n);
       CHNS_HIP(hipGetLastError());
       st.outer_iterations = outer + 1;

@@ -1,0 +1,1101 @@
+// Learned preconditioner for the pressure Poisson solve: a 3D U-Net on the
+// node grid of a uniform mesh, evaluated and trained with hand-written
+// kernels for gfx950.
+//
+// Network (4 levels, channels 16/32/48/64, two 3x3x3 conv + ReLU per level
+// and side, average pooling down, nearest-neighbour upsampling and channel
+// concatenation [upsampled, skip] up, a 1x1x1 convolution to one channel).
+// Input channels: 0 = log(1/rho(phi*)) / log(rho+/rho-), 1 = r / rms(r)
+// (channels 2..7 are zero padding so that every stored row is 16 bytes).
+// As a preconditioner: z = rms(r) K Net(coef, r / rms(r)), projected to
+// 1^T z = 0; K is a fixed output scale stored with the weights.
+//
+// Storage: activations channels-last (voxel-major) bfloat16; weights FP32
+// masters with two bfloat16 copies, [tap][co][ci] for the forward pass and
+// [flipped tap][ci][co] for the input gradient.  The 3x3x3 convolutions are
+// implicit GEMMs on v_mfma_f32_16x16x32_bf16 (M = voxels, N = output
+// channels, K = 27 taps x input channels, FP32 accumulation); the input
+// gradient is the same kernel with the flipped, transposed weights; the
+// weight gradient (M = input channels, N = output channels, K = voxels)
+// stages voxel tiles in LDS and reduces split partial sums in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "chns_internal.h"
+
+namespace chns {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kLayers = 14;
+constexpr int kInCh = 8;
+constexpr int kCh[4] = {16, 32, 48, 64};
+constexpr int kWgradSplits = 48;
+
+struct ULayer {
+  int ci = 0, co = 0;
+  size_t off = 0;  // offset of W[27][ci][co] in the FP32 parameter vector
+  uint16_t* wf = nullptr;
+  uint16_t* wb = nullptr;
+};
+
+// activations (and their gradients) for one cubic grid edge E
+struct UActs {
+  int E = 0;
+  bool grads = false;
+  uint16_t *X = nullptr, *A0 = nullptr, *cat0 = nullptr, *P0 = nullptr, *A2 = nullptr, *cat1 = nullptr,
+           *P1 = nullptr, *A4 = nullptr, *cat2 = nullptr, *P2 = nullptr, *A6 = nullptr, *A7 = nullptr,
+           *A8 = nullptr, *A9 = nullptr, *A10 = nullptr, *A11 = nullptr, *A12 = nullptr, *A13 = nullptr;
+  uint16_t *dA13 = nullptr, *dA12 = nullptr, *dcat0 = nullptr, *dA11 = nullptr, *dA10 = nullptr,
+           *dcat1 = nullptr, *dA9 = nullptr, *dA8 = nullptr, *dcat2 = nullptr, *dA7 = nullptr, *dA6 = nullptr,
+           *dP2 = nullptr, *dA4 = nullptr, *dP1 = nullptr, *dA2 = nullptr, *dP0 = nullptr, *dA0 = nullptr;
+  float *out = nullptr, *target = nullptr, *mask = nullptr, *dout = nullptr;
+};
+
+struct UNet {
+  ULayer L[kLayers];
+  size_t nparam = 0;   // 3x3x3 weights of all layers, then w_out[16]
+  size_t wout_off = 0;
+  float* W = nullptr;  // FP32 masters
+  float* m = nullptr;
+  float* v = nullptr;
+  float* grad = nullptr;
+  uint16_t* wbf = nullptr;
+  float K = 1.0f;
+  int step = 0;
+  bool ready = false;
+  std::vector<UActs> acts;
+  float* partial = nullptr;
+  size_t partial_cap = 0;
+  double* red = nullptr;      // reduction partials (device)
+  double* scal = nullptr;     // device scalars: [0] rms, [1] sum, [2] loss, [3] count
+  double* scal_host = nullptr;
+  float* gout_part = nullptr;  // w_out gradient partials
+};
+
+namespace {
+
+constexpr int kT = 256;
+constexpr int kRedBlocks = 1024;
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ bf16x8 as_bf(u32x4 t) { return __builtin_bit_cast(bf16x8, t); }
+
+#define ULOOP(i, n) for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+
+inline unsigned nblk(int64_t n) {
+  int64_t g = (n + kT - 1) / kT;
+  if (g > 65535) g = 65535;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+// ---------------------------------------------------------- convolution
+// out[v][n] = sum_tap sum_k in[v + off(tap)][k] wt[tap][n][k], zero outside
+// the E^3 grid; n < 16 NB, k < ci.  One wave computes 32 voxels x 16 NB
+// channels: two 16-voxel row blocks, NB 16-channel column blocks, K in
+// chunks of 32 (one MFMA per block pair and chunk).
+template <int NB>
+__global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ in, int cs_in, int ci,
+                                               const uint16_t* __restrict__ wt, uint16_t* __restrict__ out,
+                                               int cs_out, int E, int relu) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, g = lane >> 4;
+  const int V = E * E * E;
+  const int co = NB * 16;
+  const int vb = (blockIdx.x * 4 + wave) * 32;
+  if (vb >= V) return;
+  int vz[2], vy[2], vx[2];
+  bool ok[2];
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb) {
+    const int v = vb + mb * 16 + r16;
+    ok[mb] = v < V;
+    vx[mb] = v % E;
+    vy[mb] = (v / E) % E;
+    vz[mb] = v / (E * E);
+  }
+  f32x4 acc[2][NB];
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int nchunk = (ci + 31) >> 5;
+  for (int tap = 0; tap < 27; ++tap) {
+    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+    int64_t src[2];
+    bool val[2];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+      const int z = vz[mb] + dz, y = vy[mb] + dy, x = vx[mb] + dx;
+      val[mb] = ok[mb] && z >= 0 && z < E && y >= 0 && y < E && x >= 0 && x < E;
+      src[mb] = val[mb] ? ((int64_t)(z * E + y) * E + x) * cs_in : 0;
+    }
+    const uint16_t* wtap = wt + (int64_t)tap * co * ci;
+    for (int c = 0; c < nchunk; ++c) {
+      const int k0 = c * 32 + g * 8;
+      const bool kin = k0 < ci;
+      bf16x8 a[2], b[NB];
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb) {
+        u32x4 t = {0u, 0u, 0u, 0u};
+        if (val[mb] && kin) t = *(const u32x4*)(in + src[mb] + k0);
+        a[mb] = as_bf(t);
+      }
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        u32x4 t = {0u, 0u, 0u, 0u};
+        if (kin) t = *(const u32x4*)(wtap + (int64_t)(nb * 16 + r16) * ci + k0);
+        b[nb] = as_bf(t);
+      }
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], b[nb], acc[mb][nb], 0, 0, 0);
+    }
+  }
+  // lane holds rows 4 g + r (voxels) of column r16 (channel) of each block
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int v = vb + mb * 16 + 4 * g + r;
+      if (v >= V) continue;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        float x = acc[mb][nb][r];
+        if (relu) x = fmaxf(x, 0.0f);
+        out[(int64_t)v * cs_out + nb * 16 + r16] = f2bf(x);
+      }
+    }
+}
+
+// Weight gradient, one tap per block row: partial[s][tap][i][j] =
+// sum over this split's voxels v of in[v + off(tap)][i] dy[v][j]
+// (i < 16 MB input channels, zero beyond ci; j < 16 NB output channels).
+template <int MB, int NB>
+__global__ __launch_bounds__(64) void k_wgrad(const uint16_t* __restrict__ in, int cs_in, int ci,
+                                              const uint16_t* __restrict__ dy, int cs_dy, int E, int S,
+                                              float* __restrict__ partial) {
+  constexpr int CI = MB * 16, CO = NB * 16;
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[32][CI + 8];
+  __shared__ __attribute__((aligned(16))) uint16_t Ys[32][CO + 8];
+  const int lane = threadIdx.x, r16 = lane & 15, g = lane >> 4;
+  const int tap = blockIdx.y, s = blockIdx.x;
+  const int dz = tap / 9 - 1, dy_ = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+  const int V = E * E * E;
+  f32x4 acc[MB][NB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int nq = (V + 31) / 32;
+  for (int q = s; q < nq; q += S) {
+    const int v0 = q * 32;
+    for (int i = lane; i < 32 * NB * 2; i += 64) {
+      const int j = i / (NB * 2), c8 = (i % (NB * 2)) * 8;
+      const int v = v0 + j;
+      u32x4 t = {0u, 0u, 0u, 0u};
+      if (v < V) t = *(const u32x4*)(dy + (int64_t)v * cs_dy + c8);
+      *(u32x4*)&Ys[j][c8] = t;
+    }
+    for (int i = lane; i < 32 * MB * 2; i += 64) {
+      const int j = i / (MB * 2), c8 = (i % (MB * 2)) * 8;
+      const int v = v0 + j;
+      u32x4 t = {0u, 0u, 0u, 0u};
+      if (v < V && c8 < ci) {
+        const int x = v % E + dx, y = (v / E) % E + dy_, z = v / (E * E) + dz;
+        if (x >= 0 && x < E && y >= 0 && y < E && z >= 0 && z < E)
+          t = *(const u32x4*)(in + ((int64_t)(z * E + y) * E + x) * cs_in + c8);
+      }
+      *(u32x4*)&Xs[j][c8] = t;
+    }
+    __syncthreads();
+    bf16x8 a[MB], b[NB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      u32x4 t;
+#pragma unroll
+      for (int h = 0; h < 4; ++h)
+        t[h] = (uint32_t)Xs[8 * g + 2 * h][mb * 16 + r16] | ((uint32_t)Xs[8 * g + 2 * h + 1][mb * 16 + r16] << 16);
+      a[mb] = as_bf(t);
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      u32x4 t;
+#pragma unroll
+      for (int h = 0; h < 4; ++h)
+        t[h] = (uint32_t)Ys[8 * g + 2 * h][nb * 16 + r16] | ((uint32_t)Ys[8 * g + 2 * h + 1][nb * 16 + r16] << 16);
+      b[nb] = as_bf(t);
+    }
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], b[nb], acc[mb][nb], 0, 0, 0);
+    __syncthreads();
+  }
+  float* p = partial + ((int64_t)s * 27 + tap) * CI * CO;
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) p[(mb * 16 + 4 * g + r) * CO + nb * 16 + r16] = acc[mb][nb][r];
+}
+
+// grad[t][i][j] (+)= sum_s partial[s][t][i][j], fixed order over s
+__global__ void k_wgrad_reduce(const float* partial, int S, int ci, int co, int CI, int CO, float* grad,
+                               float scale, int accumulate) {
+  ULOOP(idx, (int64_t)27 * ci * co) {
+    const int j = (int)(idx % co), i = (int)((idx / co) % ci), t = (int)(idx / ((int64_t)ci * co));
+    float sum = 0.0f;
+    for (int s = 0; s < S; ++s) sum += partial[(((int64_t)s * 27 + t) * CI + i) * CO + j];
+    grad[idx] = (accumulate ? grad[idx] : 0.0f) + scale * sum;
+  }
+}
+
+// ------------------------------------------------------- other layers
+// P[z][y][x][c] = mean of the 2x2x2 children (coarse edge Ec)
+__global__ void k_pool(const uint16_t* in, int cs_in, uint16_t* out, int C, int Ec) {
+  const int64_t n = (int64_t)Ec * Ec * Ec * C;
+  const int Ef = 2 * Ec;
+  ULOOP(idx, n) {
+    const int c = (int)(idx % C);
+    const int64_t p = idx / C;
+    const int x = (int)(p % Ec), y = (int)((p / Ec) % Ec), z = (int)(p / ((int64_t)Ec * Ec));
+    float s = 0.0f;
+    for (int k = 0; k < 8; ++k) {
+      const int fz = 2 * z + (k >> 2), fy = 2 * y + ((k >> 1) & 1), fx = 2 * x + (k & 1);
+      s += bf2f(in[((int64_t)(fz * Ef + fy) * Ef + fx) * cs_in + c]);
+    }
+    out[p * C + c] = f2bf(s * 0.125f);
+  }
+}
+// dskip[v][c] += dP[parent(v)][c] / 8 (fine edge Ef)
+__global__ void k_pool_bwd_add(const uint16_t* dP, int C, uint16_t* dskip, int cs, int Ef) {
+  const int64_t n = (int64_t)Ef * Ef * Ef * C;
+  const int Ec = Ef / 2;
+  ULOOP(idx, n) {
+    const int c = (int)(idx % C);
+    const int64_t v = idx / C;
+    const int x = (int)(v % Ef), y = (int)((v / Ef) % Ef), z = (int)(v / ((int64_t)Ef * Ef));
+    const int64_t p = ((int64_t)(z / 2) * Ec + y / 2) * Ec + x / 2;
+    uint16_t* d = dskip + v * cs + c;
+    *d = f2bf(bf2f(*d) + bf2f(dP[p * C + c]) * 0.125f);
+  }
+}
+// out[v][c] (stride cs_out) = in[parent(v)][c] (fine edge Ef)
+__global__ void k_up(const uint16_t* in, int C, uint16_t* out, int cs_out, int Ef) {
+  const int64_t n = (int64_t)Ef * Ef * Ef * C;
+  const int Ec = Ef / 2;
+  ULOOP(idx, n) {
+    const int c = (int)(idx % C);
+    const int64_t v = idx / C;
+    const int x = (int)(v % Ef), y = (int)((v / Ef) % Ef), z = (int)(v / ((int64_t)Ef * Ef));
+    out[v * cs_out + c] = in[(((int64_t)(z / 2) * Ec + y / 2) * Ec + x / 2) * C + c];
+  }
+}
+// out[p][c] = sum of d[child][c] (stride cs), coarse edge Ec
+__global__ void k_up_bwd(const uint16_t* d, int cs, uint16_t* out, int C, int Ec) {
+  const int64_t n = (int64_t)Ec * Ec * Ec * C;
+  const int Ef = 2 * Ec;
+  ULOOP(idx, n) {
+    const int c = (int)(idx % C);
+    const int64_t p = idx / C;
+    const int x = (int)(p % Ec), y = (int)((p / Ec) % Ec), z = (int)(p / ((int64_t)Ec * Ec));
+    float s = 0.0f;
+    for (int k = 0; k < 8; ++k) {
+      const int fz = 2 * z + (k >> 2), fy = 2 * y + ((k >> 1) & 1), fx = 2 * x + (k & 1);
+      s += bf2f(d[((int64_t)(fz * Ef + fy) * Ef + fx) * cs + c]);
+    }
+    out[p * C + c] = f2bf(s);
+  }
+}
+// dy = dy * (a > 0)
+__global__ void k_relu_bwd(uint16_t* dy, int cs_dy, const uint16_t* a, int cs_a, int C, int64_t V) {
+  ULOOP(idx, V * C) {
+    const int c = (int)(idx % C);
+    const int64_t v = idx / C;
+    if (!(bf2f(a[v * cs_a + c]) > 0.0f)) dy[v * cs_dy + c] = 0;
+  }
+}
+// out[v] = sum_c w[c] a[v][c]
+__global__ void k_out(const uint16_t* a, const float* w, float* out, int64_t V) {
+  ULOOP(v, V) {
+    float s = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) s += w[c] * bf2f(a[v * 16 + c]);
+    out[v] = s;
+  }
+}
+// loss partials and dout = 2 (out - t) mask / count
+__global__ __launch_bounds__(kT) void k_mse(const float* out, const float* t, const float* mask, int64_t V,
+                                           double* part) {
+  __shared__ double sh[2][4];
+  double l = 0.0, c = 0.0;
+  ULOOP(v, V) {
+    const double d = ((double)out[v] - (double)t[v]) * mask[v];
+    l += d * d;
+    c += mask[v];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    l += __shfl_xor(l, o, 64);
+    c += __shfl_xor(c, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = l;
+    sh[1][threadIdx.x >> 6] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = (sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3]);
+    part[kRedBlocks + blockIdx.x] = (sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]);
+  }
+}
+__global__ void k_sum2(const double* part, int np, double* out) {
+  if (threadIdx.x != 0) return;
+  double a = 0.0, b = 0.0;
+  for (int i = 0; i < np; ++i) {
+    a += part[i];
+    b += part[kRedBlocks + i];
+  }
+  out[0] = a;
+  out[1] = b;
+}
+__global__ void k_dout(const float* out, const float* t, const float* mask, const double* lc, float* dout,
+                       int64_t V) {
+  const float inv = (float)(2.0 / lc[1]);
+  ULOOP(v, V) dout[v] = (out[v] - t[v]) * mask[v] * inv;
+}
+// dA13[v][c] = w[c] dout[v]; partial w_out gradient per block
+__global__ __launch_bounds__(kT) void k_out_bwd(const uint16_t* a, const float* w, const float* dout, int64_t V,
+                                               uint16_t* da, float* gpart) {
+  __shared__ float sh[16][kT / 64];
+  float g[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) g[c] = 0.0f;
+  ULOOP(v, V) {
+    const float d = dout[v];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      da[v * 16 + c] = f2bf(w[c] * d);
+      g[c] += bf2f(a[v * 16 + c]) * d;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    float t = g[c];
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[c][threadIdx.x >> 6] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    const int c = threadIdx.x;
+    gpart[blockIdx.x * 16 + c] = (sh[c][0] + sh[c][1]) + (sh[c][2] + sh[c][3]);
+  }
+}
+__global__ void k_gout_reduce(const float* gpart, int nb, float* grad, float scale, int accumulate) {
+  const int c = threadIdx.x;
+  if (c >= 16) return;
+  float s = 0.0f;
+  for (int b = 0; b < nb; ++b) s += gpart[b * 16 + c];
+  grad[c] = (accumulate ? grad[c] : 0.0f) + scale * s;
+}
+
+// bf16 copies of the FP32 masters in the two layouts
+__global__ void k_prep_weights(const float* W, int ci, int co, uint16_t* wf, uint16_t* wb) {
+  ULOOP(idx, (int64_t)27 * ci * co) {
+    const int o = (int)(idx % co), i = (int)((idx / co) % ci), t = (int)(idx / ((int64_t)ci * co));
+    const uint16_t h = f2bf(W[idx]);
+    wf[((int64_t)t * co + o) * ci + i] = h;
+    wb[((int64_t)(26 - t) * ci + i) * co + o] = h;
+  }
+}
+__global__ void k_adam(float* W, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2,
+                       float c1, float c2, float eps) {
+  ULOOP(i, n) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    W[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+}
+
+// ------------------------------------------------------------- packing
+// sum of squares of r (partials), for rms(r)
+template <typename T>
+__global__ __launch_bounds__(kT) void k_sumsq(const T* r, int64_t n, double* part) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  ULOOP(i, n) s += (double)r[i] * (double)r[i];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+// rms = sqrt(sum / n) into scal[0]
+__global__ void k_rms(const double* part, int np, int64_t n, double* scal) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < np; ++i) s += part[i];
+  scal[0] = s > 0.0 ? sqrt(s / (double)n) : 1.0;
+}
+
+struct PackGeo {
+  int side;            // nodes per axis - 1
+  int E;               // grid edge in voxels
+  int ox, oy, oz;      // crop origin (nodes)
+  int flip;            // bit d mirrors axis d inside the crop
+};
+__device__ __forceinline__ int64_t voxel_node(const PackGeo& g, int64_t v) {
+  int x = (int)(v % g.E), y = (int)((v / g.E) % g.E), z = (int)(v / ((int64_t)g.E * g.E));
+  if (g.flip & 1) x = g.E - 1 - x;
+  if (g.flip & 2) y = g.E - 1 - y;
+  if (g.flip & 4) z = g.E - 1 - z;
+  x += g.ox;
+  y += g.oy;
+  z += g.oz;
+  if (x > g.side || y > g.side || z > g.side) return -1;
+  const int64_t s1 = g.side + 1;
+  return x + s1 * (y + s1 * (int64_t)z);
+}
+// network input (and training target / mask)
+template <typename T>
+__global__ void k_pack(PackGeo geo, const double* phi, const T* r, const double* e, const double* scal,
+                       double alpha, double beta, double inv_lratio, float K, uint16_t* X, float* target,
+                       float* mask) {
+  const int64_t V = (int64_t)geo.E * geo.E * geo.E;
+  const double rinv = 1.0 / scal[0];
+  ULOOP(v, V) {
+    const int64_t i = voxel_node(geo, v);
+    float c0 = 0.0f, c1 = 0.0f, tg = 0.0f, mk = 0.0f;
+    if (i >= 0) {
+      const double p = fmin(fmax(phi[i], -1.0), 1.0);
+      const double rho = alpha * p + beta;
+      c0 = (float)(-log(rho) * inv_lratio);
+      c1 = (float)((double)r[i] * rinv);
+      if (e) tg = (float)(e[i] * rinv / (double)K);
+      mk = 1.0f;
+    }
+    u32x4 lo = {(uint32_t)f2bf(c0) | ((uint32_t)f2bf(c1) << 16), 0u, 0u, 0u};
+    *(u32x4*)(X + v * kInCh) = lo;
+    if (target) {
+      target[v] = tg;
+      mask[v] = mk;
+    }
+  }
+}
+// z[node] = rms K sum_c w[c] a13[v][c] for every voxel that is a node
+template <typename T>
+__global__ void k_unpack(PackGeo geo, const uint16_t* a, const float* w, const double* scal, float K, T* z) {
+  const int64_t V = (int64_t)geo.E * geo.E * geo.E;
+  const double sc = scal[0] * (double)K;
+  ULOOP(v, V) {
+    const int64_t i = voxel_node(geo, v);
+    if (i < 0) continue;
+    float s = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) s += w[c] * bf2f(a[v * 16 + c]);
+    z[i] = (T)(sc * (double)s);
+  }
+}
+template <typename T>
+__global__ __launch_bounds__(kT) void k_sum_part(const T* z, int64_t n, double* part) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  ULOOP(i, n) s += (double)z[i];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+__global__ void k_mean(const double* part, int np, int64_t n, double* scal) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < np; ++i) s += part[i];
+  scal[1] = s / (double)n;
+}
+template <typename T>
+__global__ void k_sub(T* z, int64_t n, const double* scal) {
+  const double m = scal[1];
+  ULOOP(i, n) z[i] = (T)((double)z[i] - m);
+}
+
+// ------------------------------------------------------------ host side
+int conv(const uint16_t* in, int cs_in, int ci, const uint16_t* wt, uint16_t* out, int cs_out, int co, int E,
+         bool relu, hipStream_t s) {
+  const int64_t V = (int64_t)E * E * E;
+  const unsigned g = (unsigned)((V + 127) / 128);
+  const int r = relu ? 1 : 0;
+  switch (co / 16) {
+    case 1: k_conv3<1><<<g, 256, 0, s>>>(in, cs_in, ci, wt, out, cs_out, E, r); break;
+    case 2: k_conv3<2><<<g, 256, 0, s>>>(in, cs_in, ci, wt, out, cs_out, E, r); break;
+    case 3: k_conv3<3><<<g, 256, 0, s>>>(in, cs_in, ci, wt, out, cs_out, E, r); break;
+    case 4: k_conv3<4><<<g, 256, 0, s>>>(in, cs_in, ci, wt, out, cs_out, E, r); break;
+    case 5: k_conv3<5><<<g, 256, 0, s>>>(in, cs_in, ci, wt, out, cs_out, E, r); break;
+    case 7: k_conv3<7><<<g, 256, 0, s>>>(in, cs_in, ci, wt, out, cs_out, E, r); break;
+    default:
+      set_error("unsupported channel count");
+      return CHNS_EINVAL;
+  }
+  CHNS_HIP(hipGetLastError());
+  return CHNS_OK;
+}
+
+int wgrad(UNet& u, int layer, const uint16_t* in, int cs_in, const uint16_t* dy, int cs_dy, int E, float scale,
+          int accumulate, hipStream_t s) {
+  const ULayer& l = u.L[layer];
+  const int MB = (l.ci + 15) / 16, NB = l.co / 16;
+  const dim3 g(kWgradSplits, 27);
+#define WG(a, b) \
+  k_wgrad<a, b><<<g, 64, 0, s>>>(in, cs_in, l.ci, dy, cs_dy, E, kWgradSplits, u.partial)
+  const int key = MB * 10 + NB;
+  switch (key) {
+    case 11: WG(1, 1); break;
+    case 12: WG(1, 2); break;
+    case 22: WG(2, 2); break;
+    case 23: WG(2, 3); break;
+    case 33: WG(3, 3); break;
+    case 34: WG(3, 4); break;
+    case 44: WG(4, 4); break;
+    case 73: WG(7, 3); break;
+    case 52: WG(5, 2); break;
+    case 31: WG(3, 1); break;
+    default:
+      set_error("unsupported weight-gradient shape");
+      return CHNS_EINVAL;
+  }
+#undef WG
+  CHNS_HIP(hipGetLastError());
+  k_wgrad_reduce<<<nblk((int64_t)27 * l.ci * l.co), kT, 0, s>>>(u.partial, kWgradSplits, l.ci, l.co, MB * 16, NB * 16,
+                                                                 u.grad + l.off, scale, accumulate);
+  CHNS_HIP(hipGetLastError());
+  return CHNS_OK;
+}
+
+int ensure_acts(Ctx& c, int E, bool grads, UActs** out) {
+  UNet& u = *c.unet;
+  for (auto& a : u.acts)
+    if (a.E == E && (a.grads || !grads)) {
+      *out = &a;
+      return CHNS_OK;
+    }
+  UActs a;
+  a.E = E;
+  a.grads = grads;
+  const int64_t V0 = (int64_t)E * E * E, V1 = V0 / 8, V2 = V1 / 8, V3 = V2 / 8;
+  auto B = [&](int64_t n) { return (uint16_t*)c.dalloc(sizeof(uint16_t) * (size_t)std::max<int64_t>(n, 8)); };
+  auto F = [&](int64_t n) { return (float*)c.dalloc(sizeof(float) * (size_t)std::max<int64_t>(n, 1)); };
+  a.X = B(V0 * kInCh);
+  a.A0 = B(V0 * 16);
+  a.cat0 = B(V0 * 48);
+  a.P0 = B(V1 * 16);
+  a.A2 = B(V1 * 32);
+  a.cat1 = B(V1 * 80);
+  a.P1 = B(V2 * 32);
+  a.A4 = B(V2 * 48);
+  a.cat2 = B(V2 * 112);
+  a.P2 = B(V3 * 48);
+  a.A6 = B(V3 * 64);
+  a.A7 = B(V3 * 64);
+  a.A8 = B(V2 * 48);
+  a.A9 = B(V2 * 48);
+  a.A10 = B(V1 * 32);
+  a.A11 = B(V1 * 32);
+  a.A12 = B(V0 * 16);
+  a.A13 = B(V0 * 16);
+  a.out = F(V0);
+  if (!a.X || !a.A0 || !a.cat0 || !a.P0 || !a.A2 || !a.cat1 || !a.P1 || !a.A4 || !a.cat2 || !a.P2 || !a.A6 ||
+      !a.A7 || !a.A8 || !a.A9 || !a.A10 || !a.A11 || !a.A12 || !a.A13 || !a.out)
+    return CHNS_ENOMEM;
+  if (grads) {
+    a.dA13 = B(V0 * 16);
+    a.dA12 = B(V0 * 16);
+    a.dcat0 = B(V0 * 48);
+    a.dA11 = B(V1 * 32);
+    a.dA10 = B(V1 * 32);
+    a.dcat1 = B(V1 * 80);
+    a.dA9 = B(V2 * 48);
+    a.dA8 = B(V2 * 48);
+    a.dcat2 = B(V2 * 112);
+    a.dA7 = B(V3 * 64);
+    a.dA6 = B(V3 * 64);
+    a.dP2 = B(V3 * 48);
+    a.dA4 = B(V2 * 48);
+    a.dP1 = B(V2 * 32);
+    a.dA2 = B(V1 * 32);
+    a.dP0 = B(V1 * 16);
+    a.dA0 = B(V0 * 16);
+    a.target = F(V0);
+    a.mask = F(V0);
+    a.dout = F(V0);
+    if (!a.dA13 || !a.dA12 || !a.dcat0 || !a.dA11 || !a.dA10 || !a.dcat1 || !a.dA9 || !a.dA8 || !a.dcat2 ||
+        !a.dA7 || !a.dA6 || !a.dP2 || !a.dA4 || !a.dP1 || !a.dA2 || !a.dP0 || !a.dA0 || !a.target || !a.mask ||
+        !a.dout)
+      return CHNS_ENOMEM;
+  }
+  u.acts.push_back(a);
+  *out = &u.acts.back();
+  return CHNS_OK;
+}
+
+// forward pass on the packed input a.X
+int forward(UNet& u, UActs& a, hipStream_t s) {
+  const int E0 = a.E, E1 = E0 / 2, E2 = E1 / 2, E3 = E2 / 2;
+  const ULayer* L = u.L;
+  int rc;
+#define CV(in, csi, k, out, cso, E) \
+  if ((rc = conv(in, csi, L[k].ci, L[k].wf, out, cso, L[k].co, E, true, s))) return rc;
+  CV(a.X, kInCh, 0, a.A0, 16, E0);
+  CV(a.A0, 16, 1, a.cat0 + 32, 48, E0);
+  k_pool<<<nblk((int64_t)E1 * E1 * E1 * 16), kT, 0, s>>>(a.cat0 + 32, 48, a.P0, 16, E1);
+  CV(a.P0, 16, 2, a.A2, 32, E1);
+  CV(a.A2, 32, 3, a.cat1 + 48, 80, E1);
+  k_pool<<<nblk((int64_t)E2 * E2 * E2 * 32), kT, 0, s>>>(a.cat1 + 48, 80, a.P1, 32, E2);
+  CV(a.P1, 32, 4, a.A4, 48, E2);
+  CV(a.A4, 48, 5, a.cat2 + 64, 112, E2);
+  k_pool<<<nblk((int64_t)E3 * E3 * E3 * 48), kT, 0, s>>>(a.cat2 + 64, 112, a.P2, 48, E3);
+  CV(a.P2, 48, 6, a.A6, 64, E3);
+  CV(a.A6, 64, 7, a.A7, 64, E3);
+  k_up<<<nblk((int64_t)E2 * E2 * E2 * 64), kT, 0, s>>>(a.A7, 64, a.cat2, 112, E2);
+  CV(a.cat2, 112, 8, a.A8, 48, E2);
+  CV(a.A8, 48, 9, a.A9, 48, E2);
+  k_up<<<nblk((int64_t)E1 * E1 * E1 * 48), kT, 0, s>>>(a.A9, 48, a.cat1, 80, E1);
+  CV(a.cat1, 80, 10, a.A10, 32, E1);
+  CV(a.A10, 32, 11, a.A11, 32, E1);
+  k_up<<<nblk((int64_t)E0 * E0 * E0 * 32), kT, 0, s>>>(a.A11, 32, a.cat0, 48, E0);
+  CV(a.cat0, 48, 12, a.A12, 16, E0);
+  CV(a.A12, 16, 13, a.A13, 16, E0);
+#undef CV
+  CHNS_HIP(hipGetLastError());
+  return CHNS_OK;
+}
+
+// backward pass from a.dout; weight gradients scaled by `scale` and added
+// into u.grad when `accumulate`
+int backward(UNet& u, UActs& a, float scale, int accumulate, hipStream_t s) {
+  const int E0 = a.E, E1 = E0 / 2, E2 = E1 / 2, E3 = E2 / 2;
+  const int64_t V0 = (int64_t)E0 * E0 * E0, V1 = V0 / 8, V2 = V1 / 8, V3 = V2 / 8;
+  const ULayer* L = u.L;
+  int rc;
+  const unsigned gb = (unsigned)std::min<int64_t>(kRedBlocks, (V0 + kT - 1) / kT);
+  k_out_bwd<<<gb, kT, 0, s>>>(a.A13, u.W + u.wout_off, a.dout, V0, a.dA13, u.gout_part);
+  k_gout_reduce<<<1, 64, 0, s>>>(u.gout_part, (int)gb, u.grad + u.wout_off, scale, accumulate);
+  CHNS_HIP(hipGetLastError());
+  // one layer: relu mask, weight gradient, input gradient
+  auto layer = [&](int k, uint16_t* dy, int cs_dy, const uint16_t* act, int cs_act, const uint16_t* in, int cs_in,
+                   uint16_t* dx, int cs_dx, int E, int64_t V) -> int {
+    k_relu_bwd<<<nblk(V * L[k].co), kT, 0, s>>>(dy, cs_dy, act, cs_act, L[k].co, V);
+    CHNS_HIP(hipGetLastError());
+    int e = wgrad(u, k, in, cs_in, dy, cs_dy, E, scale, accumulate, s);
+    if (e) return e;
+    if (dx) return conv(dy, cs_dy, L[k].co, L[k].wb, dx, cs_dx, L[k].ci, E, false, s);
+    return CHNS_OK;
+  };
+  if ((rc = layer(13, a.dA13, 16, a.A13, 16, a.A12, 16, a.dA12, 16, E0, V0))) return rc;
+  if ((rc = layer(12, a.dA12, 16, a.A12, 16, a.cat0, 48, a.dcat0, 48, E0, V0))) return rc;
+  k_up_bwd<<<nblk(V1 * 32), kT, 0, s>>>(a.dcat0, 48, a.dA11, 32, E1);
+  if ((rc = layer(11, a.dA11, 32, a.A11, 32, a.A10, 32, a.dA10, 32, E1, V1))) return rc;
+  if ((rc = layer(10, a.dA10, 32, a.A10, 32, a.cat1, 80, a.dcat1, 80, E1, V1))) return rc;
+  k_up_bwd<<<nblk(V2 * 48), kT, 0, s>>>(a.dcat1, 80, a.dA9, 48, E2);
+  if ((rc = layer(9, a.dA9, 48, a.A9, 48, a.A8, 48, a.dA8, 48, E2, V2))) return rc;
+  if ((rc = layer(8, a.dA8, 48, a.A8, 48, a.cat2, 112, a.dcat2, 112, E2, V2))) return rc;
+  k_up_bwd<<<nblk(V3 * 64), kT, 0, s>>>(a.dcat2, 112, a.dA7, 64, E3);
+  if ((rc = layer(7, a.dA7, 64, a.A7, 64, a.A6, 64, a.dA6, 64, E3, V3))) return rc;
+  if ((rc = layer(6, a.dA6, 64, a.A6, 64, a.P2, 48, a.dP2, 48, E3, V3))) return rc;
+  k_pool_bwd_add<<<nblk(V2 * 48), kT, 0, s>>>(a.dP2, 48, a.dcat2 + 64, 112, E2);
+  if ((rc = layer(5, a.dcat2 + 64, 112, a.cat2 + 64, 112, a.A4, 48, a.dA4, 48, E2, V2))) return rc;
+  if ((rc = layer(4, a.dA4, 48, a.A4, 48, a.P1, 32, a.dP1, 32, E2, V2))) return rc;
+  k_pool_bwd_add<<<nblk(V1 * 32), kT, 0, s>>>(a.dP1, 32, a.dcat1 + 48, 80, E1);
+  if ((rc = layer(3, a.dcat1 + 48, 80, a.cat1 + 48, 80, a.A2, 32, a.dA2, 32, E1, V1))) return rc;
+  if ((rc = layer(2, a.dA2, 32, a.A2, 32, a.P0, 16, a.dP0, 16, E1, V1))) return rc;
+  k_pool_bwd_add<<<nblk(V0 * 16), kT, 0, s>>>(a.dP0, 16, a.dcat0 + 32, 48, E0);
+  if ((rc = layer(1, a.dcat0 + 32, 48, a.cat0 + 32, 48, a.A0, 16, a.dA0, 16, E0, V0))) return rc;
+  if ((rc = layer(0, a.dA0, 16, a.A0, 16, a.X, kInCh, nullptr, 0, E0, V0))) return rc;
+  CHNS_HIP(hipGetLastError());
+  return CHNS_OK;
+}
+
+int prep_weights(UNet& u, hipStream_t s) {
+  for (int k = 0; k < kLayers; ++k) {
+    const ULayer& l = u.L[k];
+    k_prep_weights<<<nblk((int64_t)27 * l.ci * l.co), kT, 0, s>>>(u.W + l.off, l.ci, l.co, l.wf, l.wb);
+  }
+  CHNS_HIP(hipGetLastError());
+  return CHNS_OK;
+}
+
+double lratio(const Ctx& c) {
+  const double r = c.prm.rho_plus / c.prm.rho_minus;
+  return r > 1.0 ? std::log(r) : 1.0;
+}
+
+// rho(phi) = alpha phi* + beta, normalised by rho+
+void rho_ab(const Ctx& c, double* a, double* b) {
+  *a = (c.prm.rho_plus - c.prm.rho_minus) / (2.0 * c.prm.rho_plus);
+  *b = (c.prm.rho_plus + c.prm.rho_minus) / (2.0 * c.prm.rho_plus);
+}
+
+int check_grid(const Ctx& c) {
+  if (c.dm.dim != 3 || !c.dm.structured) {
+    set_error("the learned preconditioner needs a uniform 3D mesh");
+    return CHNS_EINVAL;
+  }
+  return CHNS_OK;
+}
+
+// splitmix64 -> two uniforms -> Box-Muller normal
+uint64_t splitmix(uint64_t& s) {
+  uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+double normal(uint64_t& s) {
+  const double u1 = ((splitmix(s) >> 11) + 1.0) * (1.0 / 9007199254740993.0);
+  const double u2 = (splitmix(s) >> 11) * (1.0 / 9007199254740992.0);
+  return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- API
+int unet_create(Ctx& c) {
+  if (c.unet) return CHNS_OK;
+  c.unet = new UNet();
+  UNet& u = *c.unet;
+  const int c0 = kCh[0], c1 = kCh[1], c2 = kCh[2], c3 = kCh[3];
+  const int shapes[kLayers][2] = {{kInCh, c0}, {c0, c0}, {c0, c1}, {c1, c1}, {c1, c2}, {c2, c2}, {c2, c3},
+                                  {c3, c3}, {c3 + c2, c2}, {c2, c2}, {c2 + c1, c1}, {c1, c1}, {c1 + c0, c0},
+                                  {c0, c0}};
+  size_t off = 0, nbf = 0;
+  for (int k = 0; k < kLayers; ++k) {
+    u.L[k].ci = shapes[k][0];
+    u.L[k].co = shapes[k][1];
+    u.L[k].off = off;
+    off += (size_t)27 * shapes[k][0] * shapes[k][1];
+  }
+  u.wout_off = off;
+  u.nparam = off + 16;
+  nbf = 2 * off;
+  u.W = (float*)c.dalloc(sizeof(float) * u.nparam);
+  u.m = (float*)c.dalloc(sizeof(float) * u.nparam);
+  u.v = (float*)c.dalloc(sizeof(float) * u.nparam);
+  u.grad = (float*)c.dalloc(sizeof(float) * u.nparam);
+  u.wbf = (uint16_t*)c.dalloc(sizeof(uint16_t) * nbf);
+  size_t pmax = 0;
+  for (int k = 0; k < kLayers; ++k)
+    pmax = std::max(pmax, (size_t)kWgradSplits * 27 * ((u.L[k].ci + 15) / 16 * 16) * u.L[k].co);
+  u.partial = (float*)c.dalloc(sizeof(float) * pmax);
+  u.partial_cap = pmax;
+  u.red = (double*)c.dalloc(sizeof(double) * 2 * kRedBlocks);
+  u.scal = (double*)c.dalloc(sizeof(double) * 8);
+  u.gout_part = (float*)c.dalloc(sizeof(float) * 16 * kRedBlocks);
+  if (!u.W || !u.m || !u.v || !u.grad || !u.wbf || !u.partial || !u.red || !u.scal || !u.gout_part)
+    return CHNS_ENOMEM;
+  CHNS_HIP(hipHostMalloc((void**)&u.scal_host, sizeof(double) * 8, hipHostMallocDefault));
+  size_t b = 0;
+  for (int k = 0; k < kLayers; ++k) {
+    const size_t n = (size_t)27 * u.L[k].ci * u.L[k].co;
+    u.L[k].wf = u.wbf + b;
+    u.L[k].wb = u.wbf + b + n;
+    b += 2 * n;
+  }
+  return CHNS_OK;
+}
+
+void unet_destroy(Ctx& c) {
+  if (!c.unet) return;
+  if (c.unet->scal_host) (void)hipHostFree(c.unet->scal_host);
+  delete c.unet;
+  c.unet = nullptr;
+}
+
+static int set_params(Ctx& c, const std::vector<float>& w, float K, hipStream_t s) {
+  UNet& u = *c.unet;
+  CHNS_HIP(hipMemcpyAsync(u.W, w.data(), sizeof(float) * u.nparam, hipMemcpyHostToDevice, s));
+  CHNS_HIP(hipMemsetAsync(u.m, 0, sizeof(float) * u.nparam, s));
+  CHNS_HIP(hipMemsetAsync(u.v, 0, sizeof(float) * u.nparam, s));
+  CHNS_HIP(hipMemsetAsync(u.grad, 0, sizeof(float) * u.nparam, s));
+  int rc = prep_weights(u, s);
+  if (rc) return rc;
+  CHNS_HIP(hipStreamSynchronize(s));
+  u.K = K;
+  u.step = 0;
+  u.ready = true;
+  return CHNS_OK;
+}
+
+int unet_init(Ctx& c, uint64_t seed, float K, hipStream_t s) {
+  int rc = unet_create(c);
+  if (rc) return rc;
+  UNet& u = *c.unet;
+  std::vector<float> w(u.nparam);
+  uint64_t st = seed;
+  for (int k = 0; k < kLayers; ++k) {
+    // He initialisation over the fan-in of the real input channels
+    const int fan = 27 * (k == 0 ? 2 : u.L[k].ci);
+    const double sd = std::sqrt(2.0 / fan);
+    for (int t = 0; t < 27; ++t)
+      for (int i = 0; i < u.L[k].ci; ++i)
+        for (int o = 0; o < u.L[k].co; ++o) {
+          const double x = normal(st) * sd;
+          w[u.L[k].off + ((size_t)t * u.L[k].ci + i) * u.L[k].co + o] = (k == 0 && i >= 2) ? 0.0f : (float)x;
+        }
+  }
+  for (int c2 = 0; c2 < 16; ++c2) w[u.wout_off + c2] = (float)(normal(st) * std::sqrt(1.0 / 16));
+  return set_params(c, w, K, s);
+}
+
+// blob: "CHNSUNET", u32 version 1, u32 layers, f32 K, per layer u32 ci, u32 co,
+// f32 W[27][ci][co]; u32 16, f32 w_out[16]
+int unet_load(Ctx& c, const void* blob, size_t n, hipStream_t s) {
+  int rc = unet_create(c);
+  if (rc) return rc;
+  UNet& u = *c.unet;
+  const uint8_t* p = (const uint8_t*)blob;
+  size_t pos = 0;
+  auto take = [&](void* dst, size_t k) -> bool {
+    if (pos + k > n) return false;
+    std::memcpy(dst, p + pos, k);
+    pos += k;
+    return true;
+  };
+  char magic[8];
+  uint32_t ver = 0, nl = 0;
+  float K = 1.0f;
+  if (!blob || !take(magic, 8) || std::memcmp(magic, "CHNSUNET", 8) != 0 || !take(&ver, 4) || ver != 1 ||
+      !take(&nl, 4) || nl != kLayers || !take(&K, 4)) {
+    set_error("not a U-Net weight blob of this library");
+    return CHNS_EINVAL;
+  }
+  std::vector<float> w(u.nparam);
+  for (int k = 0; k < kLayers; ++k) {
+    uint32_t ci = 0, co = 0;
+    if (!take(&ci, 4) || !take(&co, 4) || (int)ci != u.L[k].ci || (int)co != u.L[k].co ||
+        !take(w.data() + u.L[k].off, sizeof(float) * 27 * ci * co)) {
+      set_error("U-Net blob does not match the network shape");
+      return CHNS_EINVAL;
+    }
+  }
+  uint32_t no = 0;
+  if (!take(&no, 4) || no != 16 || !take(w.data() + u.wout_off, sizeof(float) * 16) || pos != n) {
+    set_error("U-Net blob is truncated or has trailing bytes");
+    return CHNS_EINVAL;
+  }
+  return set_params(c, w, K, s);
+}
+
+size_t unet_blob_size(const Ctx& c) {
+  if (!c.unet) return 0;
+  const UNet& u = *c.unet;
+  return 8 + 4 + 4 + 4 + kLayers * 8 + (u.nparam - 16) * 4 + 4 + 64;
+}
+
+int unet_save(Ctx& c, void* blob, size_t cap, size_t* n) {
+  if (!c.unet || !c.unet->ready) {
+    set_error("no U-Net weights in this context");
+    return CHNS_ESTATE;
+  }
+  UNet& u = *c.unet;
+  const size_t need = unet_blob_size(c);
+  *n = need;
+  if (!blob) return CHNS_OK;
+  if (cap < need) {
+    set_error("blob buffer too small");
+    return CHNS_EINVAL;
+  }
+  std::vector<float> w(u.nparam);
+  CHNS_HIP(hipMemcpy(w.data(), u.W, sizeof(float) * u.nparam, hipMemcpyDeviceToHost));
+  uint8_t* p = (uint8_t*)blob;
+  size_t pos = 0;
+  auto put = [&](const void* src, size_t k) {
+    std::memcpy(p + pos, src, k);
+    pos += k;
+  };
+  const uint32_t ver = 1, nl = kLayers, no = 16;
+  put("CHNSUNET", 8);
+  put(&ver, 4);
+  put(&nl, 4);
+  put(&u.K, 4);
+  for (int k = 0; k < kLayers; ++k) {
+    const uint32_t ci = u.L[k].ci, co = u.L[k].co;
+    put(&ci, 4);
+    put(&co, 4);
+    put(w.data() + u.L[k].off, sizeof(float) * 27 * ci * co);
+  }
+  put(&no, 4);
+  put(w.data() + u.wout_off, sizeof(float) * 16);
+  return CHNS_OK;
+}
+
+int unet_gradients(Ctx& c, float* host, size_t n) {
+  if (!c.unet || !c.unet->ready) {
+    set_error("no U-Net weights in this context");
+    return CHNS_ESTATE;
+  }
+  if (n != c.unet->nparam) {
+    set_error("gradient buffer must hold exactly the parameter count");
+    return CHNS_EINVAL;
+  }
+  CHNS_HIP(hipMemcpy(host, c.unet->grad, sizeof(float) * n, hipMemcpyDeviceToHost));
+  return CHNS_OK;
+}
+
+size_t unet_param_count(const Ctx& c) { return c.unet ? c.unet->nparam : 0; }
+
+static int pack_sample(Ctx& c, UActs& a, const double* phi, const double* r, const double* e, const int32_t* origin,
+                       int flip, hipStream_t s) {
+  UNet& u = *c.unet;
+  const int64_t n = c.dm.n;
+  const unsigned g = (unsigned)std::min<int64_t>(kRedBlocks, (n + kT - 1) / kT);
+  k_sumsq<double><<<g, kT, 0, s>>>(r, n, u.red);
+  k_rms<<<1, 64, 0, s>>>(u.red, (int)g, n, u.scal);
+  PackGeo geo{c.dm.side, a.E, origin ? origin[0] : 0, origin ? origin[1] : 0, origin ? origin[2] : 0, flip};
+  double al, be;
+  rho_ab(c, &al, &be);
+  const int64_t V = (int64_t)a.E * a.E * a.E;
+  k_pack<double><<<nblk(V), kT, 0, s>>>(geo, phi, r, e, u.scal, al, be, 1.0 / lratio(c), u.K, a.X, a.target,
+                                        a.mask);
+  CHNS_HIP(hipGetLastError());
+  return CHNS_OK;
+}
+
+int unet_forward_crop(Ctx& c, const double* phi, const double* r, const int32_t* origin, int flip, int crop,
+                      float* out, hipStream_t s) {
+  int rc;
+  if ((rc = check_grid(c))) return rc;
+  if (!c.unet || !c.unet->ready) {
+    set_error("no U-Net weights in this context");
+    return CHNS_ESTATE;
+  }
+  if (crop < 8 || crop % 8) {
+    set_error("crop edge must be a positive multiple of 8");
+    return CHNS_EINVAL;
+  }
+  for (int k = 0; k < 3; ++k)
+    if (origin && (origin[k] < 0 || origin[k] > c.dm.side)) {
+      set_error("crop origin outside the node grid");
+      return CHNS_EINVAL;
+    }
+  UActs* a = nullptr;
+  if ((rc = ensure_acts(c, crop, false, &a))) return rc;
+  if ((rc = pack_sample(c, *a, phi, r, nullptr, origin, flip, s))) return rc;
+  if ((rc = forward(*c.unet, *a, s))) return rc;
+  const int64_t V = (int64_t)crop * crop * crop;
+  k_out<<<nblk(V), kT, 0, s>>>(a->A13, c.unet->W + c.unet->wout_off, out, V);
+  CHNS_HIP(hipGetLastError());
+  return CHNS_OK;
+}
+
+int unet_train_step(Ctx& c, const chns_pc_batch& b, float lr, float* loss, hipStream_t s) {
+  int rc;
+  if ((rc = check_grid(c))) return rc;
+  if (!c.unet || !c.unet->ready) {
+    set_error("no U-Net weights in this context");
+    return CHNS_ESTATE;
+  }
+  if (b.n < 1 || !b.phi || !b.r || !b.e || !b.origin || b.crop < 8 || b.crop % 8) {
+    set_error("bad training batch");
+    return CHNS_EINVAL;
+  }
+  for (int k = 0; k < 3 * b.n; ++k)
+    if (b.origin[k] < 0 || b.origin[k] > c.dm.side) {
+      set_error("crop origin outside the node grid");
+      return CHNS_EINVAL;
+    }
+  UNet& u = *c.unet;
+  UActs* a = nullptr;
+  if ((rc = ensure_acts(c, b.crop, true, &a))) return rc;
+  const int64_t V = (int64_t)b.crop * b.crop * b.crop;
+  const unsigned gl = (unsigned)std::min<int64_t>(kRedBlocks, (V + kT - 1) / kT);
+  double total = 0.0;
+  const float scale = 1.0f / (float)b.n;
+  for (int k = 0; k < b.n; ++k) {
+    if (!b.phi[k] || !b.r[k] || !b.e[k]) {
+      set_error("null field in training batch");
+      return CHNS_EINVAL;
+    }
+    if ((rc = pack_sample(c, *a, b.phi[k], b.r[k], b.e[k], b.origin + 3 * k, b.flip ? b.flip[k] : 0, s))) return rc;
+    if ((rc = forward(u, *a, s))) return rc;
+    k_out<<<nblk(V), kT, 0, s>>>(a->A13, u.W + u.wout_off, a->out, V);
+    k_mse<<<gl, kT, 0, s>>>(a->out, a->target, a->mask, V, u.red);
+    k_sum2<<<1, 64, 0, s>>>(u.red, (int)gl, u.scal + 2);
+    k_dout<<<nblk(V), kT, 0, s>>>(a->out, a->target, a->mask, u.scal + 2, a->dout, V);
+    CHNS_HIP(hipGetLastError());
+    if ((rc = backward(u, *a, scale, k > 0 ? 1 : 0, s))) return rc;
+    CHNS_HIP(hipMemcpyAsync(u.scal_host, u.scal, sizeof(double) * 4, hipMemcpyDeviceToHost, s));
+    CHNS_HIP(hipStreamSynchronize(s));
+    total += u.scal_host[3] > 0.0 ? u.scal_host[2] / u.scal_host[3] : 0.0;
+  }
+  if (loss) *loss = (float)(total / b.n);
+  if (lr > 0.0f) {
+    u.step += 1;
+    const double b1 = 0.9, b2 = 0.999;
+    const float c1 = (float)(1.0 - std::pow(b1, u.step)), c2 = (float)(1.0 - std::pow(b2, u.step));
+    k_adam<<<nblk((int64_t)u.nparam), kT, 0, s>>>(u.W, u.m, u.v, u.grad, (int64_t)u.nparam, lr, (float)b1,
+                                                  (float)b2, c1, c2, 1e-8f);
+    CHNS_HIP(hipGetLastError());
+    if ((rc = prep_weights(u, s))) return rc;
+  }
+  CHNS_HIP(hipStreamSynchronize(s));
+  return CHNS_OK;
+}
+
+bool unet_ready(const Ctx& c) { return c.unet && c.unet->ready; }
+
+// activations of the full node grid, allocated before any graph capture
+int unet_prepare(Ctx& c) {
+  int rc;
+  if ((rc = check_grid(c))) return rc;
+  UActs* a = nullptr;
+  return ensure_acts(c, ((c.dm.side + 1 + 7) / 8) * 8, false, &a);
+}
+
+// Preconditioner: z = rms(r) K Net(coef, r / rms(r)), then 1^T z = 0.
+// Kernels only (graph-capturable); the phase field is the context's phi~.
+template <typename T>
+int unet_apply(Ctx& c, const T* r, T* z, hipStream_t s) {
+  int rc;
+  if ((rc = check_grid(c))) return rc;
+  UNet& u = *c.unet;
+  const int E = ((c.dm.side + 1 + 7) / 8) * 8;
+  UActs* a = nullptr;
+  if ((rc = ensure_acts(c, E, false, &a))) return rc;
+  const int64_t n = c.dm.n;
+  const unsigned g = (unsigned)std::min<int64_t>(kRedBlocks, (n + kT - 1) / kT);
+  k_sumsq<T><<<g, kT, 0, s>>>(r, n, u.red);
+  k_rms<<<1, 64, 0, s>>>(u.red, (int)g, n, u.scal);
+  PackGeo geo{c.dm.side, E, 0, 0, 0, 0};
+  double al, be;
+  rho_ab(c, &al, &be);
+  const int64_t V = (int64_t)E * E * E;
+  k_pack<T><<<nblk(V), kT, 0, s>>>(geo, c.phi64, r, nullptr, u.scal, al, be, 1.0 / lratio(c), u.K, a->X, nullptr,
+                                   nullptr);
+  CHNS_HIP(hipGetLastError());
+  if ((rc = forward(u, *a, s))) return rc;
+  k_unpack<T><<<nblk(V), kT, 0, s>>>(geo, a->A13, u.W + u.wout_off, u.scal, u.K, z);
+  k_sum_part<T><<<g, kT, 0, s>>>(z, n, u.red);
+  k_mean<<<1, 64, 0, s>>>(u.red, (int)g, n, u.scal);
+  k_sub<T><<<nblk(n), kT, 0, s>>>(z, n, u.scal);
+  CHNS_HIP(hipGetLastError());
+  return CHNS_OK;
+}
+template int unet_apply<double>(Ctx&, const double*, double*, hipStream_t);
+template int unet_apply<float>(Ctx&, const float*, float*, hipStream_t);
+
+}  // namespace chns

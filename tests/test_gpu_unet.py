@@ -1,0 +1,182 @@
+"""GPU parity of the learned preconditioner's U-Net against the FP64 oracle
+(oracle/unet.py), and its use inside the pressure solve.
+
+The oracle runs with bfloat16 storage emulation at the same points as the
+GPU (input, 3x3x3 weights, stored activations and activation gradients), so
+the remaining differences come from FP32 versus FP64 accumulation flipping
+the rounding of individual stored values by one bfloat16 ulp (2^-8
+relative).  Along the longest path (28 stores) such flips accumulate like a
+random walk: the bars are 2e-2 relative (2-norm) for the forward output and
+5e-2 for each layer's weight gradient (ReLU masks can flip at values that
+are zero to within the rounding).  The Adam update is FP32 arithmetic on the
+GPU's own gradient: within one FP32 rounding of the new weight plus 1e-5 of
+the step.
+"""
+import struct
+
+import numpy as np
+import pytest
+
+from oracle import fem, unet
+
+from ._pairs import Pair
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+RHO_P, RHO_M = 1.0, 1e-3
+
+
+def _dev(a, dt=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+
+
+def _params(seed):
+    r = np.random.default_rng(seed)
+    W = []
+    for k, (ci, co) in enumerate(unet.layer_shapes()):
+        w = r.standard_normal((27, ci, co)) * np.sqrt(2.0 / (27 * (2 if k == 0 else ci)))
+        if k == 0:
+            w[:, 2:, :] = 0.0
+        W.append(w.astype(np.float32).astype(np.float64))
+    wo = (r.standard_normal(16) * 0.25).astype(np.float32).astype(np.float64)
+    return {"W": W, "w_out": wo}
+
+
+def _blob(params, K):
+    out = [b"CHNSUNET", struct.pack("<IIf", 1, 14, K)]
+    for w, (ci, co) in zip(params["W"], unet.layer_shapes()):
+        out.append(struct.pack("<II", ci, co))
+        out.append(np.ascontiguousarray(w, dtype="<f4").tobytes())
+    out.append(struct.pack("<I", 16))
+    out.append(np.ascontiguousarray(params["w_out"], dtype="<f4").tobytes())
+    return b"".join(out)
+
+
+def _pack(side, phi, r, e, origin, flip, E, K):
+    """Network input and target of a crop, written out from the definitions."""
+    a, b = fem.rho_coeffs(RHO_P, RHO_M)
+    rms = np.sqrt(np.mean(r * r))
+    z, y, x = np.meshgrid(np.arange(E), np.arange(E), np.arange(E), indexing="ij")
+    lx = np.where(flip & 1, E - 1 - x, x) + origin[0]
+    ly = np.where(flip & 2, E - 1 - y, y) + origin[1]
+    lz = np.where(flip & 4, E - 1 - z, z) + origin[2]
+    valid = (lx <= side) & (ly <= side) & (lz <= side)
+    node = np.where(valid, lx + (side + 1) * (ly + (side + 1) * lz), 0)
+    X = np.zeros((E, E, E, unet.IN_CH))
+    rho = a * np.clip(phi[node], -1, 1) + b
+    X[..., 0] = np.where(valid, -np.log(rho) / np.log(RHO_P / RHO_M), 0.0)
+    X[..., 1] = np.where(valid, r[node] / rms, 0.0)
+    T = np.where(valid, e[node] / (rms * K), 0.0).astype(np.float32).astype(np.float64)
+    return X, T, valid.astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def setup():
+    from paper_2107_05123_amd import Context
+    pair = Pair("uniform", 3, 4, 4)
+    ctx = Context(pair.lib, Cn=0.05, rho_plus=RHO_P, rho_minus=RHO_M)
+    rng = np.random.default_rng(11)
+    n = pair.lib.n_nodes
+    phi = pair.phi("bubble", cn=0.05)
+    r = rng.standard_normal(n)
+    e = rng.standard_normal(n) * 3.0
+    params = _params(3)
+    K = 2.5
+    ctx.pc_load(_blob(params, K))
+    print(f"unet setup: n={n}", flush=True)
+    return ctx, pair, phi, r, e, params, K
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("crop,origin,flip", [(16, (0, 0, 0), 0), (24, (0, 0, 0), 0), (16, (2, 1, 3), 5)])
+def test_forward_matches_oracle(setup, crop, origin, flip):
+    ctx, pair, phi, r, e, params, K = setup
+    out = ctx.pc_forward(_dev(phi), _dev(r), origin=origin, flip=flip, crop=crop).cpu().numpy()
+    out = out.reshape(crop, crop, crop)
+    X, _, _ = _pack(16, phi, r, e, origin, flip, crop, K)
+    ref, _ = unet.forward(params, X, store="bf16")
+    assert _rel(out, ref) <= 2e-2, _rel(out, ref)
+    ref64, _ = unet.forward(params, X)
+    assert _rel(out, ref64) <= 1e-1
+
+
+def test_gradients_and_adam_match_oracle(setup):
+    from paper_2107_05123_amd import Context
+    ctx, pair, phi, r, e, params, K = setup
+    origin, flip, crop = (1, 0, 2), 3, 16
+    loss = ctx.pc_train_step([_dev(phi)], [_dev(r)], [_dev(e)], [origin], crop, flips=[flip], lr=0.0)
+    g = ctx.pc_gradients()
+    X, T, mask = _pack(16, phi, r, e, origin, flip, crop, K)
+    out, cache = unet.forward(params, X, store="bf16")
+    L, dout = unet.mse(out, T, mask)
+    assert abs(loss - L) <= 2e-2 * L, (loss, L)
+    ref = unet.backward(cache, dout, store="bf16")
+    off = 0
+    for k, (ci, co) in enumerate(unet.layer_shapes()):
+        gk = g[off:off + 27 * ci * co].reshape(27, ci, co).astype(np.float64)
+        off += 27 * ci * co
+        rk = ref["W"][k]
+        if k == 0:
+            gk, rk = gk[:, :2], rk[:, :2]
+        assert _rel(gk, rk) <= 5e-2, (k, _rel(gk, rk))
+    assert _rel(g[off:].astype(np.float64), ref["w_out"]) <= 2e-2
+    # one Adam step on the GPU's own gradient (fresh moments)
+    c2 = Context(pair.lib, Cn=0.05, rho_plus=RHO_P, rho_minus=RHO_M)
+    c2.pc_load(_blob(params, K))
+    c2.pc_train_step([_dev(phi)], [_dev(r)], [_dev(e)], [origin], crop, flips=[flip], lr=1e-3)
+    g2 = c2.pc_gradients().astype(np.float64)
+    w1 = np.frombuffer(c2.pc_save(), dtype=np.uint8)
+    flat0 = np.concatenate([w.reshape(-1) for w in params["W"]] + [params["w_out"]])
+    # parse the saved blob back into a flat vector
+    pos, flat1 = 20, []
+    for ci, co in unet.layer_shapes():
+        pos += 8
+        flat1.append(np.frombuffer(w1[pos:pos + 4 * 27 * ci * co].tobytes(), dtype="<f4"))
+        pos += 4 * 27 * ci * co
+    pos += 4
+    flat1.append(np.frombuffer(w1[pos:pos + 64].tobytes(), dtype="<f4"))
+    flat1 = np.concatenate(flat1).astype(np.float64)
+    exp, _, _ = unet.adam(flat0, g2, np.zeros_like(g2), np.zeros_like(g2), 1, 1e-3)
+    # FP32 weights: one rounding of w (2^-24 |w|) plus FP32 error in the step
+    step = np.abs(exp - flat0)
+    assert np.all(np.abs(flat1 - exp) <= 2.0 ** -23 * np.abs(exp) + 1e-5 * step + 1e-12)
+
+
+def test_training_lowers_the_loss(setup):
+    from paper_2107_05123_amd import Context
+    ctx, pair, phi, r, e, params, K = setup
+    c2 = Context(pair.lib, Cn=0.05, rho_plus=RHO_P, rho_minus=RHO_M)
+    c2.pc_init(seed=1, out_scale=K)
+    # a smooth target: e = A^+ r for a smooth r on this mesh
+    A = fem.pp_matrix(pair.orc, pair.to_orc(phi), RHO_P, RHO_M).toarray()
+    x = pair.x_unit
+    rs = np.cos(np.pi * x[:, 0]) * np.cos(2 * np.pi * x[:, 1]) + 0.3 * np.cos(3 * np.pi * x[:, 2])
+    es = pair.to_lib(np.linalg.lstsq(A, pair.to_orc(rs - rs.mean()), rcond=None)[0])
+    args = ([_dev(phi)], [_dev(rs)], [_dev(es)], [(0, 0, 0)], 24)
+    losses = [c2.pc_train_step(*args, lr=2e-3) for _ in range(40)]
+    print("losses", losses[0], losses[-1], flush=True)
+    assert losses[-1] < 0.5 * losses[0]
+
+
+def test_learned_preconditioner_solve_reaches_tolerance():
+    from paper_2107_05123_amd import Context
+    pair = Pair("uniform", 3, 5, 5)
+    ctx = Context(pair.lib, Cn=0.02, rho_plus=RHO_P, rho_minus=RHO_M)
+    phi = pair.phi("drops", cn=0.02)
+    ctx.set_phase_field(_dev(phi))
+    ctx.pc_init(seed=7, out_scale=1.0)
+    A = fem.pp_matrix(pair.orc, pair.to_orc(phi), RHO_P, RHO_M)
+    rng = np.random.default_rng(2)
+    b = rng.standard_normal(pair.lib.n_nodes)
+    b -= b.mean()
+    for mode in ("fp64", "mixed"):
+        x, st = ctx.solve_pressure(_dev(b), pc="learned", mode=mode)
+        xo = pair.to_orc(x.cpu().numpy())
+        bo = pair.to_orc(b)
+        res = np.linalg.norm(bo - A @ xo) / np.linalg.norm(bo)
+        print(mode, st, res, flush=True)
+        assert res <= 1.05e-8 and st.rel_residual <= 1e-8
