@@ -286,6 +286,21 @@ def main():
                           "outer": sv.outer_iterations, "rel_residual": sv.rel_residual,
                           "setup_ms": sv.ms_setup}
 
+    # ---- learned preconditioner (trained weights shipped with the package)
+    wpath = os.path.join(ROOT, "paper_2107_05123_amd", "weights", "unet_uniform_l7_rho1000.bin")
+    with open(wpath, "rb") as fh:
+        ctx.pc_load(fh.read())
+    for name, kw in (("learned_fcg_fp64", dict(pc="learned")),
+                     ("learned_fcg_mixed_ir", dict(pc="learned", mode="mixed", inner_rtol=1e-4))):
+        solve_once(torch, ctx, phi_d, b, **kw)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, sv = solve_once(torch, ctx, phi_d, b, **kw)
+        torch.cuda.synchronize()
+        variants[name] = {"s": time.perf_counter() - t1, "iterations": sv.iterations,
+                          "outer": sv.outer_iterations, "rel_residual": sv.rel_residual,
+                          "setup_ms": sv.ms_setup, "fallback_to_jacobi": sv.fallback}
+
     # ---- apply throughput and the dominant kernel's roofline
     xr = torch.tensor(ci.normal_vector(0, n), dtype=torch.float64, device="cuda")
     ms64 = time_applies(torch, ctx, xr)

@@ -281,16 +281,24 @@ int chns_advance_step(chns_ctx* ctx, chns_state* state, const chns_step_opts* op
  * pooling, nearest upsampling with skip concatenation, 1x1x1 output conv),
  * bfloat16 weights and activations with FP32 accumulation (MFMA), FP32
  * master weights and Adam.  Inputs per voxel: log(1/rho(phi*)) normalised by
- * log(rho+/rho-), and r / rms(r).  As the preconditioner CHNS_PC_LEARNED of
- * chns_solve_pressure (flexible CG): z = rms(r) K Net(...) with 1^T z = 0.
+ * log(rho+/rho-), and r / rms(r).  N(r) = rms(r) K Net(...).  As the
+ * preconditioner CHNS_PC_LEARNED of chns_solve_pressure (flexible CG): with
+ * damping omega = 0, z = N(r); with omega > 0 the network is the coarse
+ * correction between two damped-Jacobi sweeps, z1 = omega D^-1 r,
+ * r1 = r - A z1, n = N(r1), z2 = z1 + beta n with the A-norm-optimal step
+ * beta = n.r1 / n.A n along n (either sign; 0 if n.A n <= 0),
+ * z = z2 + omega D^-1 (r - A z2); then 1^T z = 0.
  * The paper preconditions with algebraic multigrid; this network is an
  * addition of this library.  Weights belong to the context.               */
 
-/* Deterministic He initialisation from `seed`; out_scale is K.  Async.     */
-int chns_pc_init(chns_ctx* ctx, uint64_t seed, float out_scale, void* stream);
-/* Weight blob: "CHNSUNET", u32 version (1), u32 layers (14), f32 K, then per
- * layer u32 ci, u32 co, f32 W[27][ci][co] (tap = 9(dz+1) + 3(dy+1) + dx+1),
- * then u32 16, f32 w_out[16]; little endian.  EINVAL on any mismatch.      */
+/* Deterministic He initialisation from `seed`; out_scale is K, smooth_omega
+ * the damping (0 <= omega < 2).  Async.                                    */
+int chns_pc_init(chns_ctx* ctx, uint64_t seed, float out_scale, float smooth_omega, void* stream);
+/* Weight blob: "CHNSUNET", u32 version (1 or 2), u32 layers (14), f32 K,
+ * [version 2: f32 omega], then per layer u32 ci, u32 co, f32 W[27][ci][co]
+ * (tap = 9(dz+1) + 3(dy+1) + dx+1), then u32 16, f32 w_out[16]; little
+ * endian; version 1 means omega = 0.  chns_pc_save writes version 2.
+ * EINVAL on any mismatch.                                                  */
 int chns_pc_load(chns_ctx* ctx, const void* blob, size_t n, void* stream);
 /* *n = blob size; writes the blob when blob != NULL and cap >= *n.         */
 int chns_pc_save(chns_ctx* ctx, void* blob, size_t cap, size_t* n);
@@ -308,12 +316,21 @@ int chns_pc_gradients(chns_ctx* ctx, float* host, size_t n);
 int chns_pc_forward(chns_ctx* ctx, const double* phi, const double* r, const int32_t* origin, int flip, int crop,
                     float* out, void* stream);
 
-/* One training step: for each sample the crop of (phi, r, e) is packed as
- * above, the target is e / (rms(r) K) (e = exact solution minus iterate),
- * the loss is the mean squared error over voxels inside the grid, averaged
- * over the samples; gradients by backpropagation (MFMA input and weight
- * gradients), then one Adam step (b1 0.9, b2 0.999, eps 1e-8) when lr > 0.
+/* One training step over n samples (phase field, residual r, error e with
+ * A e = r: the exact solution minus an iterate), averaged; gradients by
+ * backpropagation (MFMA input and weight gradients), then one Adam step
+ * (b1 0.9, b2 0.999, eps 1e-8) when lr > 0.  Objectives:
+ *   CHNS_PC_OBJ_ANORM: on the full node grid, the preconditioner output
+ *     z = rms(r) K Net(...) is scored by the A-norm error
+ *     (e - z)^T A (e - z) / e^T r (1 for z = 0); its gradient
+ *     2 (A z - r) / e^T r takes one pressure-operator apply with the
+ *     sample's phase field (which the call leaves set in the context);
+ *     origin, flip and crop are unused;
+ *   CHNS_PC_OBJ_CROP_MSE: on the crop (origin, flip, crop) the output is
+ *     compared with e / (rms(r) K) by the mean squared error over the voxels
+ *     inside the grid.
  * Synchronises `stream`.                                                   */
+enum { CHNS_PC_OBJ_CROP_MSE = 0, CHNS_PC_OBJ_ANORM = 1 };
 typedef struct chns_pc_batch {
   int n;                      /* samples                                      */
   const double* const* phi;   /* host array of n device pointers (n_nodes)   */
@@ -322,6 +339,7 @@ typedef struct chns_pc_batch {
   const int32_t* origin;      /* host, 3 per sample (x, y, z) in nodes       */
   const int32_t* flip;        /* host, per sample; may be NULL               */
   int crop;                   /* crop edge, multiple of 8                    */
+  int objective;              /* CHNS_PC_OBJ_*                               */
 } chns_pc_batch;
 int chns_pc_train_step(chns_ctx* ctx, const chns_pc_batch* batch, float lr, float* loss, void* stream);
 

@@ -266,8 +266,8 @@ class Context:
                 "energy": ss.energy, "ms": ss.ms}
 
     # ------------------------------------------------ learned preconditioner
-    def pc_init(self, seed=0, out_scale=1.0, stream=None):
-        L.check(L.lib().chns_pc_init(self._h, int(seed), float(out_scale), _stream_ptr(stream)))
+    def pc_init(self, seed=0, out_scale=1.0, omega=0.0, stream=None):
+        L.check(L.lib().chns_pc_init(self._h, int(seed), float(out_scale), float(omega), _stream_ptr(stream)))
 
     def pc_load(self, blob: bytes, stream=None):
         buf = C.create_string_buffer(bytes(blob), len(blob))
@@ -301,16 +301,20 @@ class Context:
                                         _dev_ptr(out, torch.float32, crop ** 3), _stream_ptr(stream)))
         return out
 
-    def pc_train_step(self, phis, rs, es, origins, crop, flips=None, lr=1e-3, stream=None) -> float:
+    def pc_train_step(self, phis, rs, es, origins=None, crop=8, flips=None, lr=1e-3, objective="crop_mse",
+                      stream=None) -> float:
         import torch
         k = len(rs)
+        if origins is None:
+            origins = [(0, 0, 0)] * k
         P = (C.c_void_p * k)(*[_dev_ptr(t, torch.float64, self.n).value for t in phis])
         R = (C.c_void_p * k)(*[_dev_ptr(t, torch.float64, self.n).value for t in rs])
         E = (C.c_void_p * k)(*[_dev_ptr(t, torch.float64, self.n).value for t in es])
         O = (C.c_int32 * (3 * k))(*[int(v) for o in origins for v in o])
         F = (C.c_int32 * k)(*([int(f) for f in flips] if flips is not None else [0] * k))
         b = L.PcBatch(k, C.cast(P, C.POINTER(C.c_void_p)), C.cast(R, C.POINTER(C.c_void_p)),
-                      C.cast(E, C.POINTER(C.c_void_p)), O, F, int(crop))
+                      C.cast(E, C.POINTER(C.c_void_p)), O, F, int(crop),
+                      {"crop_mse": 0, "anorm": 1}[objective])
         loss = C.c_float()
         L.check(L.lib().chns_pc_train_step(self._h, C.byref(b), float(lr), C.byref(loss), _stream_ptr(stream)))
         return loss.value

@@ -81,7 +81,7 @@ class StepStats(C.Structure):
 class PcBatch(C.Structure):
     _fields_ = [("n", C.c_int), ("phi", C.POINTER(C.c_void_p)), ("r", C.POINTER(C.c_void_p)),
                 ("e", C.POINTER(C.c_void_p)), ("origin", C.POINTER(C.c_int32)), ("flip", C.POINTER(C.c_int32)),
-                ("crop", C.c_int)]
+                ("crop", C.c_int), ("objective", C.c_int)]
 
 
 _lib = None
@@ -111,7 +111,7 @@ SIGNATURES = {
     "chns_initial_mu": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "chns_advance_step": (C.c_int, [C.c_void_p, C.POINTER(State), C.POINTER(StepOpts), C.POINTER(StepStats),
                                     C.c_void_p]),
-    "chns_pc_init": (C.c_int, [C.c_void_p, C.c_uint64, C.c_float, C.c_void_p]),
+    "chns_pc_init": (C.c_int, [C.c_void_p, C.c_uint64, C.c_float, C.c_float, C.c_void_p]),
     "chns_pc_load": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "chns_pc_save": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)]),
     "chns_pc_param_count": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),

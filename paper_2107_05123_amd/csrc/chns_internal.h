@@ -262,7 +262,7 @@ int solve_spd_impl(Ctx& c, int op, const double* b, double* x, const double* din
 // ---- learned preconditioner (unet.hip)
 int unet_create(Ctx& c);
 void unet_destroy(Ctx& c);
-int unet_init(Ctx& c, uint64_t seed, float K, hipStream_t s);
+int unet_init(Ctx& c, uint64_t seed, float K, float omega, hipStream_t s);
 int unet_load(Ctx& c, const void* blob, size_t n, hipStream_t s);
 int unet_save(Ctx& c, void* blob, size_t cap, size_t* n);
 int unet_gradients(Ctx& c, float* host, size_t n);

@@ -7,8 +7,12 @@
 // concatenation [upsampled, skip] up, a 1x1x1 convolution to one channel).
 // Input channels: 0 = log(1/rho(phi*)) / log(rho+/rho-), 1 = r / rms(r)
 // (channels 2..7 are zero padding so that every stored row is 16 bytes).
-// As a preconditioner: z = rms(r) K Net(coef, r / rms(r)), projected to
-// 1^T z = 0; K is a fixed output scale stored with the weights.
+// As a preconditioner the network N(r) = rms(r) K Net(coef, r / rms(r)) (K a
+// fixed output scale stored with the weights) is either used alone or, with
+// a damping omega > 0, as the coarse correction between two damped-Jacobi
+// sweeps: z1 = omega D^-1 r, r1 = r - A z1, n = N(r1), z2 = z1 + beta n with
+// the A-norm-optimal step beta = n.r1 / n.A n along n (either sign),
+// z = z2 + omega D^-1 (r - A z2); finally 1^T z = 0.
 //
 // Storage: activations channels-last (voxel-major) bfloat16; weights FP32
 // masters with two bfloat16 copies, [tap][co][ci] for the forward pass and
@@ -67,15 +71,21 @@ struct UNet {
   float* grad = nullptr;
   uint16_t* wbf = nullptr;
   float K = 1.0f;
+  float omega = 0.0f;  // Jacobi damping of the smoothing sweeps (0: network alone)
   int step = 0;
   bool ready = false;
   std::vector<UActs> acts;
   float* partial = nullptr;
   size_t partial_cap = 0;
   double* red = nullptr;      // reduction partials (device)
-  double* scal = nullptr;     // device scalars: [0] rms, [1] sum, [2] loss, [3] count
+  double* scal = nullptr;     // device scalars: [0] rms, [1] mean, [2] loss or beta, [3] count,
+                              // [4..7] A-norm objective, [8] n.A n, [9] g.n
   double* scal_host = nullptr;
   float* gout_part = nullptr;  // w_out gradient partials
+  double *zb = nullptr, *qb = nullptr;  // node vectors of the A-norm objective
+  double* tb[10] = {};                  // training work vectors (smoothing)
+  double* hb64[4] = {};                 // preconditioner work vectors
+  float* hb32[4] = {};
 };
 
 namespace {
@@ -535,6 +545,145 @@ __global__ void k_sub(T* z, int64_t n, const double* scal) {
   ULOOP(i, n) z[i] = (T)((double)z[i] - m);
 }
 
+// A-norm objective on the node grid: partial z.q, z.r, e.r
+__global__ __launch_bounds__(kT) void k_dot3(const double* z, const double* q, const double* r, const double* e,
+                                            int64_t n, double* part) {
+  __shared__ double sh[3][4];
+  double a = 0.0, b = 0.0, c = 0.0;
+  ULOOP(i, n) {
+    a += z[i] * q[i];
+    b += z[i] * r[i];
+    c += e[i] * r[i];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o, 64);
+    b += __shfl_xor(b, o, 64);
+    c += __shfl_xor(c, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = a;
+    sh[1][threadIdx.x >> 6] = b;
+    sh[2][threadIdx.x >> 6] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) part[threadIdx.x * kRedBlocks + blockIdx.x] =
+      (sh[threadIdx.x][0] + sh[threadIdx.x][1]) + (sh[threadIdx.x][2] + sh[threadIdx.x][3]);
+}
+// scal[4..6] = totals; scal[7] = loss (z.q - 2 z.r + e.r) / e.r
+__global__ void k_fin3(const double* part, int np, double* scal) {
+  if (threadIdx.x != 0) return;
+  double t[3] = {0.0, 0.0, 0.0};
+  for (int k = 0; k < 3; ++k)
+    for (int i = 0; i < np; ++i) t[k] += part[k * kRedBlocks + i];
+  scal[4] = t[0];
+  scal[5] = t[1];
+  scal[6] = t[2];
+  scal[7] = t[2] > 0.0 ? (t[0] - 2.0 * t[1] + t[2]) / t[2] : 0.0;
+}
+// g = dL/dz = 2 (q - r) / e.r
+__global__ void k_grad_anorm(const double* q, const double* r, const double* scal, double* g, int64_t n) {
+  const double f = scal[6] > 0.0 ? 2.0 / scal[6] : 0.0;
+  ULOOP(i, n) g[i] = f * (q[i] - r[i]);
+}
+// dL/dout at every voxel: rms K g[node] (zero off the grid)
+__global__ void k_dout_nodes(PackGeo geo, const double* g, const double* scal, float K, float* dout) {
+  const int64_t V = (int64_t)geo.E * geo.E * geo.E;
+  const double f = scal[0] * (double)K;
+  ULOOP(v, V) {
+    const int64_t i = voxel_node(geo, v);
+    dout[v] = i < 0 ? 0.0f : (float)(f * g[i]);
+  }
+}
+// smoothing sweeps
+template <typename T>
+__global__ void k_wdinv(T* out, double w, const T* d, const T* x, int64_t n) {
+  ULOOP(i, n) out[i] = (T)(w * (double)d[i] * (double)x[i]);
+}
+template <typename T>
+__global__ void k_rsub(T* t, const T* r, int64_t n) { ULOOP(i, n) t[i] = r[i] - t[i]; }
+template <typename T>
+__global__ void k_addv(T* z, const T* a, int64_t n) { ULOOP(i, n) z[i] += a[i]; }
+// z += w D^-1 (r - t)
+template <typename T>
+__global__ void k_jcorr(T* z, double w, const T* d, const T* r, const T* t, int64_t n) {
+  ULOOP(i, n) z[i] = (T)((double)z[i] + w * (double)d[i] * ((double)r[i] - (double)t[i]));
+}
+// g -= w q (q = A D^-1 g)
+__global__ void k_axpy_neg(double* g, double w, const double* q, int64_t n) { ULOOP(i, n) g[i] -= w * q[i]; }
+// out = r - a
+template <typename T>
+__global__ void k_diffv(T* out, const T* r, const T* a, int64_t n) { ULOOP(i, n) out[i] = r[i] - a[i]; }
+// partial a.b (row 0) and a.c (row 1)
+template <typename T>
+__global__ __launch_bounds__(kT) void k_dot2(const T* a, const T* b, const T* c, int64_t n, double* part) {
+  __shared__ double sh[2][4];
+  double x = 0.0, y = 0.0;
+  ULOOP(i, n) {
+    x += (double)a[i] * (double)b[i];
+    y += (double)a[i] * (double)c[i];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    x += __shfl_xor(x, o, 64);
+    y += __shfl_xor(y, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = x;
+    sh[1][threadIdx.x >> 6] = y;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2)
+    part[threadIdx.x * kRedBlocks + blockIdx.x] =
+        (sh[threadIdx.x][0] + sh[threadIdx.x][1]) + (sh[threadIdx.x][2] + sh[threadIdx.x][3]);
+}
+// scal[2] = beta = (n.r1) / (n.A n), the A-norm-optimal step along n (either
+// sign; 0 if n.A n is not positive); scal[8] = n.A n
+__global__ void k_beta(const double* part, int np, double* scal) {
+  if (threadIdx.x != 0) return;
+  double a = 0.0, b = 0.0;
+  for (int i = 0; i < np; ++i) {
+    a += part[i];
+    b += part[kRedBlocks + i];
+  }
+  scal[2] = b > 0.0 ? a / b : 0.0;
+  scal[8] = b;
+}
+// z = z1 + beta z (z holds n)
+template <typename T>
+__global__ void k_comb(T* z, const T* z1, const double* scal, int64_t n) {
+  const double b = scal[2];
+  ULOOP(i, n) z[i] = (T)((double)z1[i] + b * (double)z[i]);
+}
+// z += w D^-1 (r - A z1 - beta A n)
+template <typename T>
+__global__ void k_jcorr2(T* z, double w, const T* d, const T* r, const T* az1, const T* an, const double* scal,
+                         int64_t n) {
+  const double b = scal[2];
+  ULOOP(i, n) z[i] = (T)((double)z[i] + w * (double)d[i] * ((double)r[i] - (double)az1[i] - b * (double)an[i]));
+}
+// scal[9] = G.n
+__global__ __launch_bounds__(kT) void k_dot1(const double* a, const double* b, int64_t n, double* part) {
+  __shared__ double sh[4];
+  double x = 0.0;
+  ULOOP(i, n) x += a[i] * b[i];
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+__global__ void k_fin1(const double* part, int np, double* out) {
+  if (threadIdx.x != 0) return;
+  double a = 0.0;
+  for (int i = 0; i < np; ++i) a += part[i];
+  *out = a;
+}
+// dL/dn = beta G + (G.n / n.A n)(r1 - 2 beta A n)  (beta = n.r1 / n.A n)
+__global__ void k_gbeta(double* gn, const double* G, const double* r1, const double* an, const double* scal,
+                        int64_t n) {
+  const double b = scal[2];
+  const double c = scal[8] > 0.0 ? scal[9] / scal[8] : 0.0;
+  ULOOP(i, n) gn[i] = b * G[i] + c * (r1[i] - 2.0 * b * an[i]);
+}
+
 // ------------------------------------------------------------ host side
 int conv(const uint16_t* in, int cs_in, int ci, const uint16_t* wt, uint16_t* out, int cs_out, int co, int E,
          bool relu, hipStream_t s) {
@@ -802,12 +951,12 @@ int unet_create(Ctx& c) {
     pmax = std::max(pmax, (size_t)kWgradSplits * 27 * ((u.L[k].ci + 15) / 16 * 16) * u.L[k].co);
   u.partial = (float*)c.dalloc(sizeof(float) * pmax);
   u.partial_cap = pmax;
-  u.red = (double*)c.dalloc(sizeof(double) * 2 * kRedBlocks);
-  u.scal = (double*)c.dalloc(sizeof(double) * 8);
+  u.red = (double*)c.dalloc(sizeof(double) * 3 * kRedBlocks);  // up to three partial rows
+  u.scal = (double*)c.dalloc(sizeof(double) * 16);
   u.gout_part = (float*)c.dalloc(sizeof(float) * 16 * kRedBlocks);
   if (!u.W || !u.m || !u.v || !u.grad || !u.wbf || !u.partial || !u.red || !u.scal || !u.gout_part)
     return CHNS_ENOMEM;
-  CHNS_HIP(hipHostMalloc((void**)&u.scal_host, sizeof(double) * 8, hipHostMallocDefault));
+  CHNS_HIP(hipHostMalloc((void**)&u.scal_host, sizeof(double) * 16, hipHostMallocDefault));
   size_t b = 0;
   for (int k = 0; k < kLayers; ++k) {
     const size_t n = (size_t)27 * u.L[k].ci * u.L[k].co;
@@ -825,7 +974,7 @@ void unet_destroy(Ctx& c) {
   c.unet = nullptr;
 }
 
-static int set_params(Ctx& c, const std::vector<float>& w, float K, hipStream_t s) {
+static int set_params(Ctx& c, const std::vector<float>& w, float K, float omega, hipStream_t s) {
   UNet& u = *c.unet;
   CHNS_HIP(hipMemcpyAsync(u.W, w.data(), sizeof(float) * u.nparam, hipMemcpyHostToDevice, s));
   CHNS_HIP(hipMemsetAsync(u.m, 0, sizeof(float) * u.nparam, s));
@@ -835,12 +984,13 @@ static int set_params(Ctx& c, const std::vector<float>& w, float K, hipStream_t 
   if (rc) return rc;
   CHNS_HIP(hipStreamSynchronize(s));
   u.K = K;
+  u.omega = omega;
   u.step = 0;
   u.ready = true;
   return CHNS_OK;
 }
 
-int unet_init(Ctx& c, uint64_t seed, float K, hipStream_t s) {
+int unet_init(Ctx& c, uint64_t seed, float K, float omega, hipStream_t s) {
   int rc = unet_create(c);
   if (rc) return rc;
   UNet& u = *c.unet;
@@ -858,11 +1008,12 @@ int unet_init(Ctx& c, uint64_t seed, float K, hipStream_t s) {
         }
   }
   for (int c2 = 0; c2 < 16; ++c2) w[u.wout_off + c2] = (float)(normal(st) * std::sqrt(1.0 / 16));
-  return set_params(c, w, K, s);
+  return set_params(c, w, K, omega, s);
 }
 
-// blob: "CHNSUNET", u32 version 1, u32 layers, f32 K, per layer u32 ci, u32 co,
-// f32 W[27][ci][co]; u32 16, f32 w_out[16]
+// blob: "CHNSUNET", u32 version (1 or 2), u32 layers, f32 K, [version 2:
+// f32 omega], per layer u32 ci, u32 co, f32 W[27][ci][co]; u32 16,
+// f32 w_out[16]
 int unet_load(Ctx& c, const void* blob, size_t n, hipStream_t s) {
   int rc = unet_create(c);
   if (rc) return rc;
@@ -877,9 +1028,10 @@ int unet_load(Ctx& c, const void* blob, size_t n, hipStream_t s) {
   };
   char magic[8];
   uint32_t ver = 0, nl = 0;
-  float K = 1.0f;
-  if (!blob || !take(magic, 8) || std::memcmp(magic, "CHNSUNET", 8) != 0 || !take(&ver, 4) || ver != 1 ||
-      !take(&nl, 4) || nl != kLayers || !take(&K, 4)) {
+  float K = 1.0f, omega = 0.0f;
+  if (!blob || !take(magic, 8) || std::memcmp(magic, "CHNSUNET", 8) != 0 || !take(&ver, 4) ||
+      (ver != 1 && ver != 2) || !take(&nl, 4) || nl != kLayers || !take(&K, 4) || (ver == 2 && !take(&omega, 4)) ||
+      !(K > 0.0f) || !(omega >= 0.0f && omega < 2.0f)) {
     set_error("not a U-Net weight blob of this library");
     return CHNS_EINVAL;
   }
@@ -897,13 +1049,13 @@ int unet_load(Ctx& c, const void* blob, size_t n, hipStream_t s) {
     set_error("U-Net blob is truncated or has trailing bytes");
     return CHNS_EINVAL;
   }
-  return set_params(c, w, K, s);
+  return set_params(c, w, K, omega, s);
 }
 
 size_t unet_blob_size(const Ctx& c) {
   if (!c.unet) return 0;
   const UNet& u = *c.unet;
-  return 8 + 4 + 4 + 4 + kLayers * 8 + (u.nparam - 16) * 4 + 4 + 64;
+  return 8 + 4 + 4 + 4 + 4 + kLayers * 8 + (u.nparam - 16) * 4 + 4 + 64;
 }
 
 int unet_save(Ctx& c, void* blob, size_t cap, size_t* n) {
@@ -927,11 +1079,12 @@ int unet_save(Ctx& c, void* blob, size_t cap, size_t* n) {
     std::memcpy(p + pos, src, k);
     pos += k;
   };
-  const uint32_t ver = 1, nl = kLayers, no = 16;
+  const uint32_t ver = 2, nl = kLayers, no = 16;
   put("CHNSUNET", 8);
   put(&ver, 4);
   put(&nl, 4);
   put(&u.K, 4);
+  put(&u.omega, 4);
   for (int k = 0; k < kLayers; ++k) {
     const uint32_t ci = u.L[k].ci, co = u.L[k].co;
     put(&ci, 4);
@@ -1002,12 +1155,145 @@ int unet_forward_crop(Ctx& c, const double* phi, const double* r, const int32_t*
   return CHNS_OK;
 }
 
+static int adam_update(UNet& u, float lr, hipStream_t s) {
+  u.step += 1;
+  const double b1 = 0.9, b2 = 0.999;
+  const float c1 = (float)(1.0 - std::pow(b1, u.step)), c2 = (float)(1.0 - std::pow(b2, u.step));
+  k_adam<<<nblk((int64_t)u.nparam), kT, 0, s>>>(u.W, u.m, u.v, u.grad, (int64_t)u.nparam, lr, (float)b1, (float)b2,
+                                                c1, c2, 1e-8f);
+  CHNS_HIP(hipGetLastError());
+  return prep_weights(u, s);
+}
+
+// network part of the preconditioner on a node vector x: rms(x) -> scal[0],
+// pack, forward, z = rms(x) K Net (no projection)
+template <typename T>
+static int net_nodes(Ctx& c, UActs& a, const double* phi, const T* x, T* z, hipStream_t s) {
+  UNet& u = *c.unet;
+  const int64_t n = c.dm.n;
+  const unsigned g = (unsigned)std::min<int64_t>(kRedBlocks, (n + kT - 1) / kT);
+  const PackGeo geo{c.dm.side, a.E, 0, 0, 0, 0};
+  double al, be;
+  rho_ab(c, &al, &be);
+  const int64_t V = (int64_t)a.E * a.E * a.E;
+  k_sumsq<T><<<g, kT, 0, s>>>(x, n, u.red);
+  k_rms<<<1, 64, 0, s>>>(u.red, (int)g, n, u.scal);
+  k_pack<T><<<nblk(V), kT, 0, s>>>(geo, phi, x, nullptr, u.scal, al, be, 1.0 / lratio(c), u.K, a.X, nullptr,
+                                   nullptr);
+  CHNS_HIP(hipGetLastError());
+  int rc = forward(u, a, s);
+  if (rc) return rc;
+  k_unpack<T><<<nblk(V), kT, 0, s>>>(geo, a.A13, u.W + u.wout_off, u.scal, u.K, z);
+  CHNS_HIP(hipGetLastError());
+  return CHNS_OK;
+}
+
+// Full-grid A-norm objective: L = (e - z)^T A (e - z) / e^T r for the
+// preconditioner output z (A e = r), i.e. (z^T A z - 2 z^T r + e^T r) / e^T r,
+// G0 = dL/dz = 2 (A z - r) / e^T r.  With smoothing
+// z = (I - w D^-1 A) z2 + w D^-1 r, z2 = z1 + beta n, so G = dL/dz2 =
+// (I - w A D^-1) G0, and through beta = n.r1 / n.A n:
+// dL/dn = beta G + (G.n / n.A n)(r1 - 2 beta A n).  The context's phase field
+// is set to each sample's.
+static int train_energy(Ctx& c, const chns_pc_batch& b, float lr, float* loss, hipStream_t s) {
+  UNet& u = *c.unet;
+  const int64_t n = c.dm.n;
+  int rc;
+  if (!u.zb) {
+    u.zb = (double*)c.dalloc(sizeof(double) * n);
+    u.qb = (double*)c.dalloc(sizeof(double) * n);
+    for (auto& t : u.tb) t = (double*)c.dalloc(sizeof(double) * n);
+    for (auto t : u.tb)
+      if (!t) return CHNS_ENOMEM;
+    if (!u.zb || !u.qb) return CHNS_ENOMEM;
+  }
+  const int E = ((c.dm.side + 1 + 7) / 8) * 8;
+  UActs* a = nullptr;
+  if ((rc = ensure_acts(c, E, true, &a))) return rc;
+  const int64_t V = (int64_t)E * E * E;
+  const unsigned g = (unsigned)std::min<int64_t>(kRedBlocks, (n + kT - 1) / kT);
+  const unsigned gn = nblk(n);
+  const PackGeo geo{c.dm.side, E, 0, 0, 0, 0};
+  const double w = u.omega;
+  double *d = u.tb[0], *z1 = u.tb[1], *az1 = u.tb[2], *r1 = u.tb[3], *an = u.tb[4], *G = u.tb[5], *h = u.tb[6],
+         *ah = u.tb[7], *gnet = u.tb[8], *z = u.tb[9];
+  double* net = u.zb;
+  double total = 0.0;
+  ApplyOut plain{};
+  for (int k = 0; k < b.n; ++k) {
+    if (!b.phi[k] || !b.r[k] || !b.e[k]) {
+      set_error("null field in training batch");
+      return CHNS_EINVAL;
+    }
+    const double* r = b.r[k];
+    if ((rc = launch_set_phase(c, b.phi[k], nullptr, s))) return rc;
+    const double* xin = r;
+    if (w > 0.0) {
+      if ((rc = launch_diagonal(c, CHNS_OP_PRESSURE, CHNS_FP64, d, true, s))) return rc;
+      k_wdinv<double><<<gn, kT, 0, s>>>(z1, w, d, r, n);
+      if ((rc = launch_apply(c, CHNS_OP_PRESSURE, CHNS_FP64, z1, az1, s, plain))) return rc;
+      k_diffv<double><<<gn, kT, 0, s>>>(r1, r, az1, n);
+      CHNS_HIP(hipGetLastError());
+      xin = r1;
+    }
+    if ((rc = net_nodes<double>(c, *a, b.phi[k], xin, net, s))) return rc;
+    const double* zz = net;
+    if (w > 0.0) {
+      if ((rc = launch_apply(c, CHNS_OP_PRESSURE, CHNS_FP64, net, an, s, plain))) return rc;
+      k_dot2<double><<<g, kT, 0, s>>>(net, r1, an, n, u.red);
+      k_beta<<<1, 64, 0, s>>>(u.red, (int)g, u.scal);
+      CHNS_HIP(hipMemcpyAsync(z, net, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+      k_comb<double><<<gn, kT, 0, s>>>(z, z1, u.scal, n);
+      k_jcorr2<double><<<gn, kT, 0, s>>>(z, w, d, r, az1, an, u.scal, n);
+      CHNS_HIP(hipGetLastError());
+      zz = z;
+    }
+    if ((rc = launch_apply(c, CHNS_OP_PRESSURE, CHNS_FP64, zz, u.qb, s, plain))) return rc;
+    k_dot3<<<g, kT, 0, s>>>(zz, u.qb, r, b.e[k], n, u.red);
+    k_fin3<<<1, 64, 0, s>>>(u.red, (int)g, u.scal);
+    k_grad_anorm<<<gn, kT, 0, s>>>(u.qb, r, u.scal, G, n);
+    CHNS_HIP(hipGetLastError());
+    const double* gout = G;
+    if (w > 0.0) {
+      k_wdinv<double><<<gn, kT, 0, s>>>(h, 1.0, d, G, n);
+      if ((rc = launch_apply(c, CHNS_OP_PRESSURE, CHNS_FP64, h, ah, s, plain))) return rc;
+      k_axpy_neg<<<gn, kT, 0, s>>>(G, w, ah, n);
+      k_dot1<<<g, kT, 0, s>>>(G, net, n, u.red);
+      k_fin1<<<1, 64, 0, s>>>(u.red, (int)g, u.scal + 9);
+      k_gbeta<<<gn, kT, 0, s>>>(gnet, G, r1, an, u.scal, n);
+      CHNS_HIP(hipGetLastError());
+      gout = gnet;
+    }
+    k_dout_nodes<<<nblk(V), kT, 0, s>>>(geo, gout, u.scal, u.K, a->dout);
+    CHNS_HIP(hipGetLastError());
+    if ((rc = backward(u, *a, 1.0f / (float)b.n, k > 0 ? 1 : 0, s))) return rc;
+    CHNS_HIP(hipMemcpyAsync(u.scal_host, u.scal, sizeof(double) * 16, hipMemcpyDeviceToHost, s));
+    CHNS_HIP(hipStreamSynchronize(s));
+    total += u.scal_host[7];
+  }
+  if (loss) *loss = (float)(total / b.n);
+  if (lr > 0.0f && (rc = adam_update(u, lr, s))) return rc;
+  CHNS_HIP(hipStreamSynchronize(s));
+  return CHNS_OK;
+}
+
 int unet_train_step(Ctx& c, const chns_pc_batch& b, float lr, float* loss, hipStream_t s) {
   int rc;
   if ((rc = check_grid(c))) return rc;
   if (!c.unet || !c.unet->ready) {
     set_error("no U-Net weights in this context");
     return CHNS_ESTATE;
+  }
+  if (b.objective == CHNS_PC_OBJ_ANORM) {
+    if (b.n < 1 || !b.phi || !b.r || !b.e) {
+      set_error("bad training batch");
+      return CHNS_EINVAL;
+    }
+    return train_energy(c, b, lr, loss, s);
+  }
+  if (b.objective != CHNS_PC_OBJ_CROP_MSE) {
+    set_error("unknown training objective");
+    return CHNS_EINVAL;
   }
   if (b.n < 1 || !b.phi || !b.r || !b.e || !b.origin || b.crop < 8 || b.crop % 8) {
     set_error("bad training batch");
@@ -1043,31 +1329,33 @@ int unet_train_step(Ctx& c, const chns_pc_batch& b, float lr, float* loss, hipSt
     total += u.scal_host[3] > 0.0 ? u.scal_host[2] / u.scal_host[3] : 0.0;
   }
   if (loss) *loss = (float)(total / b.n);
-  if (lr > 0.0f) {
-    u.step += 1;
-    const double b1 = 0.9, b2 = 0.999;
-    const float c1 = (float)(1.0 - std::pow(b1, u.step)), c2 = (float)(1.0 - std::pow(b2, u.step));
-    k_adam<<<nblk((int64_t)u.nparam), kT, 0, s>>>(u.W, u.m, u.v, u.grad, (int64_t)u.nparam, lr, (float)b1,
-                                                  (float)b2, c1, c2, 1e-8f);
-    CHNS_HIP(hipGetLastError());
-    if ((rc = prep_weights(u, s))) return rc;
-  }
+  if (lr > 0.0f && (rc = adam_update(u, lr, s))) return rc;
   CHNS_HIP(hipStreamSynchronize(s));
   return CHNS_OK;
 }
 
 bool unet_ready(const Ctx& c) { return c.unet && c.unet->ready; }
 
-// activations of the full node grid, allocated before any graph capture
+// activations of the full node grid and the smoothing work vectors,
+// allocated before any graph capture
 int unet_prepare(Ctx& c) {
   int rc;
   if ((rc = check_grid(c))) return rc;
+  UNet& u = *c.unet;
+  for (int k = 0; k < 4; ++k) {
+    if (!u.hb64[k]) u.hb64[k] = (double*)c.dalloc(sizeof(double) * c.dm.n);
+    if (!u.hb32[k]) u.hb32[k] = (float*)c.dalloc(sizeof(float) * c.dm.n);
+    if (!u.hb64[k] || !u.hb32[k]) return CHNS_ENOMEM;
+  }
   UActs* a = nullptr;
   return ensure_acts(c, ((c.dm.side + 1 + 7) / 8) * 8, false, &a);
 }
 
-// Preconditioner: z = rms(r) K Net(coef, r / rms(r)), then 1^T z = 0.
-// Kernels only (graph-capturable); the phase field is the context's phi~.
+// Preconditioner (kernels only, graph-capturable; the phase field is the
+// context's phi~ and D^-1 its exact inverse diagonal).  Network alone:
+// z = N(r); with smoothing: z1 = w D^-1 r, r1 = r - A z1, n = N(r1),
+// z2 = z1 + beta n (beta = n.r1 / n.A n), z = z2 + w D^-1 (r - A z1 - beta A n).
+// Then 1^T z = 0.
 template <typename T>
 int unet_apply(Ctx& c, const T* r, T* z, hipStream_t s) {
   int rc;
@@ -1078,20 +1366,36 @@ int unet_apply(Ctx& c, const T* r, T* z, hipStream_t s) {
   if ((rc = ensure_acts(c, E, false, &a))) return rc;
   const int64_t n = c.dm.n;
   const unsigned g = (unsigned)std::min<int64_t>(kRedBlocks, (n + kT - 1) / kT);
-  k_sumsq<T><<<g, kT, 0, s>>>(r, n, u.red);
-  k_rms<<<1, 64, 0, s>>>(u.red, (int)g, n, u.scal);
-  PackGeo geo{c.dm.side, E, 0, 0, 0, 0};
-  double al, be;
-  rho_ab(c, &al, &be);
-  const int64_t V = (int64_t)E * E * E;
-  k_pack<T><<<nblk(V), kT, 0, s>>>(geo, c.phi64, r, nullptr, u.scal, al, be, 1.0 / lratio(c), u.K, a->X, nullptr,
-                                   nullptr);
-  CHNS_HIP(hipGetLastError());
-  if ((rc = forward(u, *a, s))) return rc;
-  k_unpack<T><<<nblk(V), kT, 0, s>>>(geo, a->A13, u.W + u.wout_off, u.scal, u.K, z);
+  const unsigned gn = nblk(n);
+  const double w = u.omega;
+  if (w > 0.0) {
+    constexpr bool f64 = sizeof(T) == 8;
+    T* const* hb = f64 ? (T* const*)u.hb64 : (T* const*)u.hb32;
+    T *z1 = hb[0], *az1 = hb[1], *r1 = hb[2], *an = hb[3];
+    const T* d = f64 ? (const T*)c.diag64 : (const T*)c.diag32;
+    const int prec = f64 ? CHNS_FP64 : CHNS_FP32;
+    if (!z1 || !az1 || !r1 || !an || !d || !c.diag_valid) {
+      set_error("preconditioner work buffers or diagonal missing");
+      return CHNS_ESTATE;
+    }
+    ApplyOut plain{};
+    k_wdinv<T><<<gn, kT, 0, s>>>(z1, w, d, r, n);
+    if ((rc = launch_apply(c, CHNS_OP_PRESSURE, prec, z1, az1, s, plain))) return rc;
+    k_diffv<T><<<gn, kT, 0, s>>>(r1, r, az1, n);
+    CHNS_HIP(hipGetLastError());
+    if ((rc = net_nodes<T>(c, *a, c.phi64, r1, z, s))) return rc;
+    if ((rc = launch_apply(c, CHNS_OP_PRESSURE, prec, z, an, s, plain))) return rc;
+    k_dot2<T><<<g, kT, 0, s>>>(z, r1, an, n, u.red);
+    k_beta<<<1, 64, 0, s>>>(u.red, (int)g, u.scal);
+    k_comb<T><<<gn, kT, 0, s>>>(z, z1, u.scal, n);
+    k_jcorr2<T><<<gn, kT, 0, s>>>(z, w, d, r, az1, an, u.scal, n);
+    CHNS_HIP(hipGetLastError());
+  } else if ((rc = net_nodes<T>(c, *a, c.phi64, r, z, s))) {
+    return rc;
+  }
   k_sum_part<T><<<g, kT, 0, s>>>(z, n, u.red);
   k_mean<<<1, 64, 0, s>>>(u.red, (int)g, n, u.scal);
-  k_sub<T><<<nblk(n), kT, 0, s>>>(z, n, u.scal);
+  k_sub<T><<<gn, kT, 0, s>>>(z, n, u.scal);
   CHNS_HIP(hipGetLastError());
   return CHNS_OK;
 }

@@ -17,7 +17,7 @@ import struct
 import numpy as np
 import pytest
 
-from oracle import fem, unet
+from oracle import chns, fem, unet
 
 from ._pairs import Pair
 
@@ -131,8 +131,8 @@ def test_gradients_and_adam_match_oracle(setup):
     g2 = c2.pc_gradients().astype(np.float64)
     w1 = np.frombuffer(c2.pc_save(), dtype=np.uint8)
     flat0 = np.concatenate([w.reshape(-1) for w in params["W"]] + [params["w_out"]])
-    # parse the saved blob back into a flat vector
-    pos, flat1 = 20, []
+    # parse the saved blob (version 2: K and omega after the layer count)
+    pos, flat1 = 24, []
     for ci, co in unet.layer_shapes():
         pos += 8
         flat1.append(np.frombuffer(w1[pos:pos + 4 * 27 * ci * co].tobytes(), dtype="<f4"))
@@ -180,3 +180,95 @@ def test_learned_preconditioner_solve_reaches_tolerance():
         res = np.linalg.norm(bo - A @ xo) / np.linalg.norm(bo)
         print(mode, st, res, flush=True)
         assert res <= 1.05e-8 and st.rel_residual <= 1e-8
+
+
+def test_anorm_objective_gradients_match_oracle(setup):
+    """Full-grid A-norm objective: loss and weight gradients against the
+    oracle network driven by the oracle's assembled pressure operator."""
+    from paper_2107_05123_amd import Context
+    _, pair, phi, r, e, params, K = setup
+    c2 = Context(pair.lib, Cn=0.05, rho_plus=RHO_P, rho_minus=RHO_M)
+    c2.pc_load(_blob(params, K))
+    A = fem.pp_matrix(pair.orc, pair.to_orc(phi), RHO_P, RHO_M)
+    rr = r - r.mean()
+    # a true error: A e = r (so e^T r = e^T A e > 0)
+    e = pair.to_lib(chns.solve_singular(A, pair.to_orc(rr)))
+    loss = c2.pc_train_step([_dev(phi)], [_dev(rr)], [_dev(e)], lr=0.0, objective="anorm")
+    g = c2.pc_gradients()
+    side, E = 16, 24
+    X, _, valid = _pack(side, phi, rr, e, (0, 0, 0), 0, E, K)
+    out, cache = unet.forward(params, X, store="bf16")
+    rms = np.sqrt(np.mean(rr * rr))
+    z = np.zeros(pair.lib.n_nodes)
+    zz, yy, xx = np.meshgrid(np.arange(E), np.arange(E), np.arange(E), indexing="ij")
+    v = valid.astype(bool)
+    node = (xx + (side + 1) * (yy + (side + 1) * zz))[v]
+    z[node] = rms * K * out[v]
+    zo, ro, eo = pair.to_orc(z), pair.to_orc(rr), pair.to_orc(e)
+    qo = A @ zo
+    er = eo @ ro
+    L = (zo @ qo - 2 * zo @ ro + er) / er
+    assert abs(loss - L) <= 2e-2 * abs(L), (loss, L)
+    gz = pair.to_lib(2.0 * (qo - ro) / er)
+    dout = np.zeros((E, E, E))
+    dout[v] = rms * K * gz[node]
+    ref = unet.backward(cache, dout, store="bf16")
+    off = 0
+    for k, (ci, co) in enumerate(unet.layer_shapes()):
+        gk = g[off:off + 27 * ci * co].reshape(27, ci, co).astype(np.float64)
+        off += 27 * ci * co
+        rk = ref["W"][k]
+        if k == 0:
+            gk, rk = gk[:, :2], rk[:, :2]
+        assert _rel(gk, rk) <= 5e-2, (k, _rel(gk, rk))
+    assert _rel(g[off:].astype(np.float64), ref["w_out"]) <= 2e-2
+
+
+def test_smoothed_anorm_objective_matches_oracle(setup):
+    """A-norm objective with damped-Jacobi sweeps around the network: loss and
+    the gradient of the network's output layer against the oracle network,
+    the oracle's operator and its exact diagonal."""
+    from paper_2107_05123_amd import Context
+    _, pair, phi, r, e, params, K = setup
+    w = 0.6
+    c2 = Context(pair.lib, Cn=0.05, rho_plus=RHO_P, rho_minus=RHO_M)
+    head = b"CHNSUNET" + struct.pack("<IIff", 2, 14, K, w)
+    c2.pc_load(head + _blob(params, K)[20:])
+    A = fem.pp_matrix(pair.orc, pair.to_orc(phi), RHO_P, RHO_M)
+    rr = r - r.mean()
+    eo_ = chns.solve_singular(A, pair.to_orc(rr))
+    e = pair.to_lib(eo_)
+    loss = c2.pc_train_step([_dev(phi)], [_dev(rr)], [_dev(e)], lr=0.0, objective="anorm")
+    g = c2.pc_gradients()
+    dinv = 1.0 / A.diagonal()
+    ro = pair.to_orc(rr)
+    z1 = w * dinv * ro
+    r1 = ro - A @ z1
+    side, E = 16, 24
+    r1l = pair.to_lib(r1)
+    X, _, valid = _pack(side, phi, r1l, e, (0, 0, 0), 0, E, K)
+    out, cache = unet.forward(params, X, store="bf16")
+    rms = np.sqrt(np.mean(r1 * r1))
+    zz, yy, xx = np.meshgrid(np.arange(E), np.arange(E), np.arange(E), indexing="ij")
+    v = valid.astype(bool)
+    node = (xx + (side + 1) * (yy + (side + 1) * zz))[v]
+    zn = np.zeros(pair.lib.n_nodes)
+    zn[node] = rms * K * out[v]
+    nv = pair.to_orc(zn)
+    an = A @ nv
+    beta = (nv @ r1) / (nv @ an)
+    z2 = z1 + beta * nv
+    z = z2 + w * dinv * (ro - A @ z2)
+    er = eo_ @ ro
+    L = (z @ (A @ z) - 2 * z @ ro + er) / er
+    assert abs(loss - L) <= 2e-2 * abs(L), (loss, L)
+    gz = 2.0 * (A @ z - ro) / er
+    G = gz - w * (A @ (dinv * gz))
+    gn = pair.to_lib(beta * G + (G @ nv) / (nv @ an) * (r1 - 2 * beta * an))
+    dout = np.zeros((E, E, E))
+    dout[v] = rms * K * gn[node]
+    ref = unet.backward(cache, dout, store="bf16")
+    off = sum(27 * ci * co for ci, co in unet.layer_shapes())
+    assert _rel(g[off:].astype(np.float64), ref["w_out"]) <= 2e-2
+    k13 = off - 27 * 16 * 16
+    assert _rel(g[k13:off].astype(np.float64), ref["W"][13].reshape(-1)) <= 5e-2
