@@ -236,6 +236,42 @@ def chns_measure(torch, mesh, ctx, phi_d):
     return out
 
 
+def profile_chns(torch):
+    """Fixed sequence for rocprofv3: CHNS applies on 128^3, three steps of the
+    2D 64x64 drop, three U-Net forward passes on a 128^3 crop."""
+    mesh, ctx, phi_d, b, *_ = setup(torch)
+    n = mesh.n_nodes
+    g = torch.Generator(device="cuda").manual_seed(5)
+    mu = 0.1 * torch.randn(n, dtype=torch.float64, device="cuda", generator=g)
+    u = 0.3 * torch.randn(3 * n, dtype=torch.float64, device="cuda", generator=g)
+    ctx.set_coefficients(ctx.MOMENTUM, [phi_d, mu, u])
+    ctx.set_coefficients(ctx.CH_JACOBIAN, [phi_d, phi_d, u])
+    for _ in range(5):
+        ctx.apply(ctx.MOMENTUM, u)
+        ctx.apply(ctx.CH_JACOBIAN, u[:2 * n])
+    wpath = os.path.join(ROOT, "paper_2107_05123_amd", "weights", "unet_uniform_l7_rho1000.bin")
+    with open(wpath, "rb") as fh:
+        ctx.pc_load(fh.read())
+    r = torch.randn(n, dtype=torch.float64, device="cuda", generator=g)
+    for _ in range(3):
+        ctx.pc_forward(phi_d, r, crop=128)
+    torch.cuda.synchronize()
+    from paper_2107_05123_amd import Context, Mesh
+    m2 = Mesh(dim=2, min_level=6, max_level=6, rule="uniform")
+    x2 = ci.unit_coords(m2.node_coords(), 6)
+    c2 = Context(m2, Re=100.0, We=1.0, Cn=0.02, Fr=1.0, rho_plus=1.0, rho_minus=0.1, eta_plus=1.0,
+                 eta_minus=0.1, dt=1e-3)
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+    phi2 = dev(ci.phi_drop2d(x2, cn=0.02))
+    n2 = m2.n_nodes
+    st = {"u": dev(np.zeros(2 * n2)), "u_prev": dev(np.zeros(2 * n2)), "p": dev(np.zeros(n2)), "phi": phi2,
+          "mu": c2.initial_mu(phi2)}
+    for _ in range(3):
+        c2.advance_step(st)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_run": "chns done"}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -243,7 +279,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-run", nargs="?", const="full", default=None,
-                    help="fixed sequence for rocprofv3; 'applies' skips the solve (for counter passes)")
+                    help="fixed sequence for rocprofv3; 'applies' skips the solve (for counter passes), "
+                         "'chns' runs the CHNS applies, steps and network passes")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -251,6 +288,9 @@ def main():
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
+    if args.profile_run == "chns":
+        profile_chns(torch)
+        return
     if args.profile_run:
         profile_run(torch, with_solve=args.profile_run != "applies")
         return
