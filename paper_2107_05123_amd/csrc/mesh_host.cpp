@@ -240,11 +240,16 @@ struct Builder {
     int ndir = 1;
     for (int d = 0; d < dim; ++d) ndir *= 3;
     for (int l = L; l >= 2; --l) {
+      // the neighbour checks depend only on the parent block: once per parent
+      KeySet parents(bylev[l].size() / 4 + 1);
       for (size_t idx = 0; idx < bylev[l].size(); ++idx) {
         std::array<int32_t, 3> a = bylev[l][idx];
         if (!S.contains(leaf_key(dim, l, a.data()))) continue;
         int32_t P[3];
         align(a.data(), l - 1, P);
+        const uint64_t pk = leaf_key(dim, l - 1, P);
+        if (parents.contains(pk)) continue;
+        parents.insert(pk);
         int32_t sP = size_at(l - 1);
         for (int t = 0; t < ndir; ++t) {
           int dir[3] = {0, 0, 0};
@@ -259,15 +264,22 @@ struct Builder {
             if (N[d] < 0 || N[d] >= side) inside = false;
           }
           if (zero || !inside) continue;
-          // level of the leaf covering N (aligned at l-1), -1 if covered finer
+          // exactly one leaf contains the point N: probe level l-1 first,
+          // then finer levels (the neighbour block is already refined: no
+          // action), then coarser ones (the leaf to split)
           int cover = -1;
           int32_t am[3];
-          for (int mlev = l - 1; mlev >= 0; --mlev) {
+          bool finer = false;
+          for (int mlev = l - 1; mlev <= L && cover < 0 && !finer; ++mlev) {
             align(N, mlev, am);
             if (S.contains(leaf_key(dim, mlev, am))) {
-              cover = mlev;
-              break;
+              if (mlev == l - 1) cover = mlev;
+              else finer = true;
             }
+          }
+          for (int mlev = l - 2; mlev >= 0 && cover < 0 && !finer; --mlev) {
+            align(N, mlev, am);
+            if (S.contains(leaf_key(dim, mlev, am))) cover = mlev;
           }
           if (cover < 0 || cover >= l - 1) continue;
           for (int mlev = cover; mlev < l - 1; ++mlev) {
