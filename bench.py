@@ -272,6 +272,85 @@ def profile_chns(torch):
     print(json.dumps({"profile_run": "chns done"}))
 
 
+def adaptive_workload(torch, lmax):
+    """Adaptive octree, levels 5..lmax refined within 3 Cn of the rising-bubble
+    interface (R 0.15, centre (0.5, 0.3, 0.5), Cn 0.01), density ratio 1000:
+    apply throughput and pressure solves to 1e-8, FP64 plain vs FP32 applies
+    inside FP64 iterative refinement."""
+    from paper_2107_05123_amd import Context, Mesh
+    t0 = time.time()
+    mesh = Mesh(dim=3, min_level=5, max_level=lmax, rule="sphere_band", centres=[(0.5, 0.3, 0.5)], radii=[0.15],
+                band=3 * CN)
+    t_mesh = time.time() - t0
+    print(f"# mesh built in {t_mesh:.1f} s: {mesh.summary()['n_elems']} leaves", file=sys.stderr, flush=True)
+    x_unit = ci.unit_coords(mesh.node_coords(), lmax)
+    ctx = Context(mesh, Cn=CN, rho_plus=RHO_P, rho_minus=RHO_M)
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+    phi_d = dev(ci.phi_bubble(x_unit, cn=CN))
+    ctx.set_phase_field(phi_d)
+    amps, waves = ci.rhs_modes(1)
+    b = ctx.apply(ctx.MASS, dev(ci.rhs_field(x_unit, amps, waves)))
+    n = mesh.n_nodes
+    xr = torch.tensor(ci.normal_vector(0, n), dtype=torch.float64, device="cuda")
+    ms64 = time_applies(torch, ctx, xr)
+    ms32 = time_applies(torch, ctx, xr.float())
+    out = {"workload": f"3D adaptive octree levels 5-{lmax}, band 3 Cn around the rising bubble (Cn 0.01), "
+                       "density ratio 1000, pressure Poisson",
+           "n_elems": mesh.n_elems, "n_dof": n, "n_hanging": mesh.summary()["n_hanging"],
+           "host_mesh_build_s": t_mesh,
+           "apply_gdof_s": {"fp64": n / (ms64 * 1e-3) / 1e9, "fp32": n / (ms32 * 1e-3) / 1e9,
+                            "fp64_ms": ms64, "fp32_ms": ms32},
+           "hbm_frac_algorithmic_fp64": PP_BYTES_PER_DOF[8] * n / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "solves": {}}
+    for name, kw in (("gmg_pcg_fp64", dict(pc="gmg")), ("gmg_pcg_mixed_ir", dict(pc="gmg", mode="mixed")),
+                     ("jacobi_pcg_fp64", dict(pc="jacobi", max_it=40000)),
+                     ("jacobi_pcg_mixed_ir", dict(pc="jacobi", mode="mixed", max_it=40000))):
+        solve_once(torch, ctx, phi_d, b, **kw)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, sv = solve_once(torch, ctx, phi_d, b, **kw)
+        torch.cuda.synchronize()
+        out["solves"][name] = {"s": time.perf_counter() - t1, "iterations": sv.iterations,
+                               "outer": sv.outer_iterations, "rel_residual": sv.rel_residual,
+                               "setup_ms": sv.ms_setup}
+        print(f"# {name}: {out['solves'][name]}", file=sys.stderr, flush=True)
+    return out
+
+
+def bubble_steps(torch, lmax, nsteps):
+    """Projection time steps of the 3D rising bubble (density ratio 1000,
+    viscosity ratio 100, Re 35, We 10, Cn 0.005, dt 5e-4) on the adaptive
+    octree of levels 5..lmax refined within 3 Cn of the interface."""
+    from paper_2107_05123_amd import Context, Mesh
+    cn = 0.005
+    t0 = time.time()
+    mesh = Mesh(dim=3, min_level=5, max_level=lmax, rule="sphere_band", centres=[(0.5, 0.3, 0.5)], radii=[0.15],
+                band=3 * cn)
+    t_mesh = time.time() - t0
+    x_unit = ci.unit_coords(mesh.node_coords(), lmax)
+    ctx = Context(mesh, Re=35.0, We=10.0, Cn=cn, Fr=1.0, rho_plus=1.0, rho_minus=1e-3, eta_plus=1.0,
+                  eta_minus=1e-2, dt=5e-4)
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+    n = mesh.n_nodes
+    phi = dev(ci.phi_bubble(x_unit, cn=cn))
+    st = {"u": dev(np.zeros(3 * n)), "u_prev": dev(np.zeros(3 * n)), "p": dev(np.zeros(n)), "phi": phi,
+          "mu": ctx.initial_mu(phi)}
+    out = {"workload": f"3D rising bubble, adaptive levels 5-{lmax} (band 3 Cn, Cn 0.005), density ratio 1000, "
+                       "viscosity ratio 100, Re 35, We 10, dt 5e-4",
+           "n_elems": mesh.n_elems, "n_nodes": n, "host_mesh_build_s": t_mesh, "steps": []}
+    for mode in ("fp64", "mixed"):
+        for k in range(nsteps):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            s = ctx.advance_step(st, pp_pc="gmg", pp_mode=mode)
+            torch.cuda.synchronize()
+            s["wall_s"] = time.perf_counter() - t1
+            s["pressure_mode"] = mode
+            out["steps"].append(s)
+            print(f"# step {k} ({mode}): {s}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -281,6 +360,10 @@ def main():
     ap.add_argument("--profile-run", nargs="?", const="full", default=None,
                     help="fixed sequence for rocprofv3; 'applies' skips the solve (for counter passes), "
                          "'chns' runs the CHNS applies, steps and network passes")
+    ap.add_argument("--workload", default="uniform_l7", choices=("uniform_l7", "adaptive", "bubble_steps"),
+                    help="uniform_l7: the benchmark line; adaptive: levels 5..--max-level band mesh solves; "
+                         "bubble_steps: projection steps of the 3D rising bubble")
+    ap.add_argument("--max-level", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -288,6 +371,12 @@ def main():
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
+    if args.workload == "adaptive":
+        print(json.dumps(adaptive_workload(torch, args.max_level)))
+        return
+    if args.workload == "bubble_steps":
+        print(json.dumps(bubble_steps(torch, args.max_level, args.steps)))
+        return
     if args.profile_run == "chns":
         profile_chns(torch)
         return

@@ -179,7 +179,7 @@ struct Ctx {
   ~Ctx();
 };
 
-constexpr int kMaxPartials = 1 << 16;
+constexpr int kMaxPartials = 1 << 20;  // per-block reduction partials (bricks + combine blocks of the largest meshes)
 constexpr int kMaxCoefFields = 16;  // coefficient fields one element form may read
 
 // A mesh level as seen by the apply kernels: the fine level of a context or
