@@ -419,8 +419,10 @@ def main():
     wpath = os.path.join(ROOT, "paper_2107_05123_amd", "weights", "unet_uniform_l7_rho1000.bin")
     with open(wpath, "rb") as fh:
         ctx.pc_load(fh.read())
-    for name, kw in (("learned_fcg_fp64", dict(pc="learned")),
-                     ("learned_fcg_mixed_ir", dict(pc="learned", mode="mixed", inner_rtol=1e-4))):
+    for name, kw in (("learned_fcg_every8_fp64", dict(pc="learned", learned_every=8)),
+                     ("learned_fcg_every8_mixed_ir", dict(pc="learned", learned_every=8, mode="mixed",
+                                                          inner_rtol=1e-4)),
+                     ("learned_fcg_every_iteration_fp64", dict(pc="learned"))):
         solve_once(torch, ctx, phi_d, b, **kw)
         torch.cuda.synchronize()
         t1 = time.perf_counter()

@@ -172,6 +172,10 @@ typedef struct chns_solve_opts {
   int max_outer;      /* MIXED_IR refinement steps; default 30                       */
   int no_graphs;      /* 1: launch every kernel eagerly instead of replaying one HIP
                          graph per Krylov iteration (same arithmetic, same result)  */
+  int learned_every;  /* CHNS_PC_LEARNED: 0 = network preconditioner in every
+                         flexible-CG iteration (abandoned for Jacobi after 400
+                         iterations without convergence); k > 0 = network on r_0
+                         and after every k-th iteration, Jacobi after the others */
 } chns_solve_opts;
 
 typedef struct chns_solve_stats {

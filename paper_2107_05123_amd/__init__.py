@@ -188,14 +188,15 @@ class Context:
         return d
 
     def solve_pressure(self, b, x=None, rtol=1e-8, max_it=20000, pc="jacobi", mode="fp64", inner_rtol=1e-4,
-                       check_every=16, max_outer=30, graphs=True, stream=None, raise_on_noconv=True):
+                       check_every=16, max_outer=30, graphs=True, learned_every=0, stream=None,
+                       raise_on_noconv=True):
         import torch
         if x is None:
             x = torch.zeros_like(b)
         o = L.SolveOpts(rtol, max_it, {"jacobi": L.PC_JACOBI, "gmg": L.PC_GMG, "learned": L.PC_LEARNED,
                                        "none": L.PC_NONE}[pc],
                         {"fp64": L.MODE_FP64, "mixed": L.MODE_MIXED_IR}[mode], inner_rtol, check_every, max_outer,
-                        0 if graphs else 1)
+                        0 if graphs else 1, int(learned_every))
         st = L.SolveStats()
         rc = L.lib().chns_solve_pressure(self._h, _dev_ptr(b, torch.float64, self.n),
                                          _dev_ptr(x, torch.float64, self.n), C.byref(o), C.byref(st),

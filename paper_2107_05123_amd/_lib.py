@@ -47,6 +47,7 @@ class SolveOpts(C.Structure):
     _fields_ = [
         ("rtol", C.c_double), ("max_it", C.c_int), ("pc", C.c_int), ("mode", C.c_int),
         ("inner_rtol", C.c_double), ("check_every", C.c_int), ("max_outer", C.c_int), ("no_graphs", C.c_int),
+        ("learned_every", C.c_int),
     ]
 
 

@@ -367,13 +367,26 @@ struct Poller {
   }
 };
 
-enum PcKind { PCK_NONE = 0, PCK_JACOBI = 1, PCK_GMG = 2, PCK_LEARNED = 3 };
+// PCK_JACOBI_FLEX: Jacobi applied between update and dot products (the
+// flexible-CG form), for iterations that alternate with another preconditioner
+enum PcKind { PCK_NONE = 0, PCK_JACOBI = 1, PCK_GMG = 2, PCK_LEARNED = 3, PCK_JACOBI_FLEX = 4 };
 // iterations of flexible CG with the learned preconditioner before it is
 // abandoned for Jacobi (stagnation guard)
 constexpr int kLearnedCap = 400;
 
 template <typename T>
-int apply_pc(Ctx& c, int pc, const T* r, T* z, hipStream_t s) {
+__global__ void k_jacobi_pc(const T* d, const T* r, T* z, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+    z[i] = d[i] * r[i];
+}
+
+template <typename T>
+int apply_pc(Ctx& c, int pc, const T* r, T* z, hipStream_t s, const T* dinv = nullptr, int64_t n = 0) {
+  if (pc == PCK_JACOBI_FLEX) {
+    k_jacobi_pc<T><<<grid_for(n), kThreads, 0, s>>>(dinv, r, z, n);
+    CHNS_HIP(hipGetLastError());
+    return CHNS_OK;
+  }
   if (pc == PCK_GMG) {
     if constexpr (sizeof(T) == 8) return mg_vcycle64(c, (const double*)r, (double*)z, s);
     else return mg_vcycle32(c, (const float*)r, (float*)z, s);
@@ -387,10 +400,12 @@ int apply_pc(Ctx& c, int pc, const T* r, T* z, hipStream_t s) {
 // the operator in precision T, dot products in FP64.  Jacobi (or none) is
 // fused into the vector update; other preconditioners run between the update
 // and the dot products.  flexible selects the Polak-Ribiere beta, which keeps
-// CG convergent for a preconditioner that varies between iterations.
+// CG convergent for a preconditioner that varies between iterations.  With
+// every > 0 (flexible only) the preconditioner `pc` is applied to r_0 and
+// after every `every`-th iteration, Jacobi after the others.
 template <typename T>
 int pcg(Ctx& c, int op, const T* b, T* x, int pc, const T* dinv, bool flexible, double tol2, int max_it, int depth,
-        bool graphs, hipStream_t s, int* iters, double* rr_out) {
+        bool graphs, hipStream_t s, int* iters, double* rr_out, int every = 0) {
   // all fields of the operator form one vector (block-diagonal operators)
   const int64_t n = c.dm.n * op_fields(op, c.dm.dim);
   const int prec = sizeof(T) == 8 ? CHNS_FP64 : CHNS_FP32;
@@ -413,7 +428,7 @@ int pcg(Ctx& c, int op, const T* b, T* x, int pc, const T* dinv, bool flexible, 
                                         c.counter);
   } else {
     k_cg_init_nopc<T><<<g, kThreads, 0, s>>>(b, q, r, n, c.partials);
-    if ((rc = apply_pc<T>(c, pc, r, z, s))) return rc;
+    if ((rc = apply_pc<T>(c, pc, r, z, s, dinv, n))) return rc;
     k_dot_rz<T><<<g, kThreads, 0, s>>>(r, z, nullptr, n, c.sc, c.partials, 0);
     k_copy<T><<<g, kThreads, 0, s>>>(p, z, n);
   }
@@ -422,7 +437,7 @@ int pcg(Ctx& c, int op, const T* b, T* x, int pc, const T* dinv, bool flexible, 
   ApplyOut fused{};
   fused.fuse_dot = true;
   fused.done = &c.sc->done;
-  auto iteration = [&](hipStream_t st) -> int {
+  auto iteration = [&](hipStream_t st, int pck) -> int {
     int e;
     if ((e = launch_apply(c, op, prec, p, q, st, fused))) return e;
     if (fused_pc) {
@@ -431,7 +446,7 @@ int pcg(Ctx& c, int op, const T* b, T* x, int pc, const T* dinv, bool flexible, 
       if ((e = fin(c, st, g, 2, FIN_CG_UPDATE, nullptr, 1))) return e;
     } else {
       k_cg_update_nopc<T><<<g, kThreads, 0, st>>>(x, r, r_old, p, q, n, c.sc, c.partials);
-      if ((e = apply_pc<T>(c, pc, r, z, st))) return e;
+      if ((e = apply_pc<T>(c, pck, r, z, st, dinv, n))) return e;
       k_dot_rz<T><<<g, kThreads, 0, st>>>(r, z, r_old, n, c.sc, c.partials, 1);
       if ((e = fin(c, st, g, flexible ? 3 : 2, flexible ? FIN_FCG_UPDATE : FIN_CG_UPDATE, nullptr, 1))) return e;
     }
@@ -442,31 +457,40 @@ int pcg(Ctx& c, int op, const T* b, T* x, int pc, const T* dinv, bool flexible, 
   // one HIP graph per (operator, precision, preconditioner, variant, solution
   // and diagonal buffers); work buffers are context-owned, so the graph stays
   // valid across solves
-  hipGraphExec_t exec = nullptr;
-  if (graphs && !c.prof) {
+  auto get_graph = [&](int pck, hipGraphExec_t* out) -> int {
+    *out = nullptr;
+    if (!graphs || c.prof) return CHNS_OK;
     for (auto& ge : c.graphs)
-      if (ge.prec == prec && ge.pc == pc && ge.flexible == (int)flexible && ge.op == op && ge.x == (const void*)x &&
-          ge.dinv == (const void*)dinv)
-        exec = ge.exec;
-    if (!exec) {
-      hipGraph_t graph = nullptr;
-      CHNS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
-      int e = iteration(s);
-      hipError_t ce = hipStreamEndCapture(s, &graph);
-      if (e) return e;
-      if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
-      hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
-      if (ie != hipSuccess) return hip_fail(ie, "hipGraphInstantiate");
-      c.graphs.push_back({prec, pc, (int)flexible, op, (const void*)x, (const void*)dinv, exec});
-    }
-  }
+      if (ge.prec == prec && ge.pc == pck && ge.flexible == (int)flexible && ge.op == op &&
+          ge.x == (const void*)x && ge.dinv == (const void*)dinv)
+        *out = ge.exec;
+    if (*out) return CHNS_OK;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t ex = nullptr;
+    CHNS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    int e = iteration(s, pck);
+    hipError_t ce = hipStreamEndCapture(s, &graph);
+    if (e) return e;
+    if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+    hipError_t ie = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return hip_fail(ie, "hipGraphInstantiate");
+    c.graphs.push_back({prec, pck, (int)flexible, op, (const void*)x, (const void*)dinv, ex});
+    *out = ex;
+    return CHNS_OK;
+  };
+  const bool sched = flexible && every > 0 && !fused_pc;
+  hipGraphExec_t exec = nullptr, exec_j = nullptr;
+  if ((rc = get_graph(pc, &exec))) return rc;
+  if (sched && (rc = get_graph(PCK_JACOBI_FLEX, &exec_j))) return rc;
   DevScalars snap{};
   int it = 0;
   while (true) {
-    if (exec) {
-      CHNS_HIP(hipGraphLaunch(exec, s));
-    } else if ((rc = iteration(s))) {
+    const bool jac = sched && (it + 1) % every != 0;
+    hipGraphExec_t ex = jac ? exec_j : exec;
+    if (ex) {
+      CHNS_HIP(hipGraphLaunch(ex, s));
+    } else if ((rc = iteration(s, jac ? PCK_JACOBI_FLEX : pc))) {
       return rc;
     }
     if ((rc = poll.post(it))) return rc;
@@ -589,8 +613,12 @@ int solve_pressure_impl(Ctx& c, const double* b_in, double* x_out, const chns_so
   if (!mixed) {
     int it = 0;
     double rr = 0;
-    const int cap = learned ? std::min(o.max_it, kLearnedCap) : o.max_it;
-    rc = pcg<double>(c, CHNS_OP_PRESSURE, b, x, pck, c.diag64, learned, tol2, cap, depth, graphs, s, &it, &rr);
+    // learned every iteration: stagnation guard; on a schedule the Jacobi
+    // iterations in between keep CG convergent
+    const int every = learned ? o.learned_every : 0;
+    const int cap = learned && every == 0 ? std::min(o.max_it, kLearnedCap) : o.max_it;
+    rc = pcg<double>(c, CHNS_OP_PRESSURE, b, x, pck, c.diag64, learned, tol2, cap, every > 0 ? o.check_every : depth,
+                     graphs, s, &it, &rr, every);
     if (rc) return rc;
     st.iterations = it;
     st.outer_iterations = 1;
@@ -634,9 +662,10 @@ int solve_pressure_impl(Ctx& c, const double* b_in, double* x_out, const chns_so
       double rri = 0;
       const double itol = o.inner_rtol;
       const bool fcg = pck == PCK_LEARNED;
-      const int cap = fcg ? std::min(o.max_it - total, kLearnedCap) : o.max_it - total;
-      rc = pcg<float>(c, CHNS_OP_PRESSURE, r32, d32, pck, c.diag32, fcg, itol * itol, cap, depth, graphs, s, &it,
-                      &rri);
+      const int every = fcg ? o.learned_every : 0;
+      const int cap = fcg && every == 0 ? std::min(o.max_it - total, kLearnedCap) : o.max_it - total;
+      rc = pcg<float>(c, CHNS_OP_PRESSURE, r32, d32, pck, c.diag32, fcg, itol * itol, cap,
+                      every > 0 ? o.check_every : depth, graphs, s, &it, &rri, every);
       if (rc) return rc;
       total += it;
       if (fcg && !(rri <= itol * itol)) {

@@ -102,6 +102,19 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 
 __device__ __forceinline__ bf16x8 as_bf(u32x4 t) { return __builtin_bit_cast(bf16x8, t); }
 
+// fixed-order sum of part[0 .. np) (stride `step`) by one block of 256
+// threads; every thread returns the total
+__device__ double block_total(const double* part, int np, double* sh, int step = 1) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < np; i += 256) v += part[(int64_t)i * step];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double t = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  __syncthreads();
+  return t;
+}
+
 #define ULOOP(i, n) for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
 
 inline unsigned nblk(int64_t n) {
@@ -112,83 +125,181 @@ inline unsigned nblk(int64_t n) {
 
 // ---------------------------------------------------------- convolution
 // out[v][n] = sum_tap sum_k in[v + off(tap)][k] wt[tap][n][k], zero outside
-// the E^3 grid; n < 16 NB, k < ci.  One wave computes 32 voxels x 16 NB
-// channels: two 16-voxel row blocks, NB 16-channel column blocks, K in
-// chunks of 32 (one MFMA per block pair and chunk).
+// the E^3 grid; n < 16 NB, k < ci (implicit GEMM: M = voxels, N = output
+// channels, K = 27 taps x input channels in chunks of 32, one MFMA per
+// 16-voxel row block, column block and chunk).
+// The input is staged in LDS: a workgroup (four waves)
+// owns an output tile of 4 (z) x 4 (y) x 16 (x) voxels; per chunk of 32 input
+// channels the (4+2) x (4+2) x (16+2) halo is loaded once (16-byte rows,
+// zero outside the grid and beyond ci) and the 27 taps read it from LDS.
+// Wave w computes the z-slice w of the tile: four 16-voxel rows (one per y)
+// times NB 16-channel column blocks.
+constexpr int kTX = 16, kTY = 4, kTZ = 4;
+constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2;
+constexpr int kHRow = 40;  // bf16 per halo voxel: 32 channels + 8 padding (bank spread)
 template <int NB>
-__global__ __launch_bounds__(256) void k_conv3(const uint16_t* __restrict__ in, int cs_in, int ci,
-                                               const uint16_t* __restrict__ wt, uint16_t* __restrict__ out,
-                                               int cs_out, int E, int relu) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+__global__ __launch_bounds__(256) void k_conv3_tile(const uint16_t* __restrict__ in, int cs_in, int ci,
+                                                    const uint16_t* __restrict__ wt, uint16_t* __restrict__ out,
+                                                    int cs_out, int E, int relu) {
+  __shared__ __attribute__((aligned(16))) uint16_t H[kHZ * kHY * kHX * kHRow];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r16 = lane & 15, g = lane >> 4;
-  const int V = E * E * E;
   const int co = NB * 16;
-  const int vb = (blockIdx.x * 4 + wave) * 32;
-  if (vb >= V) return;
-  int vz[2], vy[2], vx[2];
-  bool ok[2];
+  const int ox = blockIdx.x * kTX, oy = blockIdx.y * kTY, oz = blockIdx.z * kTZ;
+  f32x4 acc[4][NB];
 #pragma unroll
-  for (int mb = 0; mb < 2; ++mb) {
-    const int v = vb + mb * 16 + r16;
-    ok[mb] = v < V;
-    vx[mb] = v % E;
-    vy[mb] = (v / E) % E;
-    vz[mb] = v / (E * E);
-  }
-  f32x4 acc[2][NB];
-#pragma unroll
-  for (int mb = 0; mb < 2; ++mb)
+  for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int nchunk = (ci + 31) >> 5;
-  for (int tap = 0; tap < 27; ++tap) {
-    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-    int64_t src[2];
-    bool val[2];
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb) {
-      const int z = vz[mb] + dz, y = vy[mb] + dy, x = vx[mb] + dx;
-      val[mb] = ok[mb] && z >= 0 && z < E && y >= 0 && y < E && x >= 0 && x < E;
-      src[mb] = val[mb] ? ((int64_t)(z * E + y) * E + x) * cs_in : 0;
+  for (int c = 0; c < nchunk; ++c) {
+    // stage the halo of this channel chunk: 4 rows of 16 bytes per voxel
+    for (int i = tid; i < kHZ * kHY * kHX * 4; i += 256) {
+      const int hv = i >> 2, part = i & 3;
+      const int hx = hv % kHX, hy = (hv / kHX) % kHY, hz = hv / (kHX * kHY);
+      const int x = ox + hx - 1, y = oy + hy - 1, z = oz + hz - 1;
+      const int k = c * 32 + part * 8;
+      u32x4 t = {0u, 0u, 0u, 0u};
+      if (k < ci && x >= 0 && x < E && y >= 0 && y < E && z >= 0 && z < E)
+        t = *(const u32x4*)(in + ((int64_t)(z * E + y) * E + x) * cs_in + k);
+      *(u32x4*)&H[hv * kHRow + part * 8] = t;
     }
-    const uint16_t* wtap = wt + (int64_t)tap * co * ci;
-    for (int c = 0; c < nchunk; ++c) {
-      const int k0 = c * 32 + g * 8;
-      const bool kin = k0 < ci;
-      bf16x8 a[2], b[NB];
+    __syncthreads();
+    const int k0 = c * 32 + g * 8;
+    const bool kin = k0 < ci;
+    // weight fragments of a group of taps are loaded together (one latency
+    // per group instead of one per tap)
+    constexpr int TG = NB <= 2 ? 9 : 3;
+    for (int t0 = 0; t0 < 27; t0 += TG) {
+      u32x4 w[TG][NB];
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb) {
-        u32x4 t = {0u, 0u, 0u, 0u};
-        if (val[mb] && kin) t = *(const u32x4*)(in + src[mb] + k0);
-        a[mb] = as_bf(t);
+      for (int t = 0; t < TG; ++t)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          w[t][nb] = u32x4{0u, 0u, 0u, 0u};
+          if (kin) w[t][nb] = *(const u32x4*)(wt + ((int64_t)(t0 + t) * co + nb * 16 + r16) * ci + k0);
+        }
+#pragma unroll
+      for (int t = 0; t < TG; ++t) {
+        const int tap = t0 + t;
+        const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+        const int hz = wave + 1 + dz, hx = r16 + 1 + dx;
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+          const int hy = mb + 1 + dy;
+          const u32x4 ta = *(const u32x4*)&H[((hz * kHY + hy) * kHX + hx) * kHRow + g * 8];
+          const bf16x8 av = as_bf(ta);
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, as_bf(w[t][nb]), acc[mb][nb], 0, 0, 0);
+        }
       }
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        u32x4 t = {0u, 0u, 0u, 0u};
-        if (kin) t = *(const u32x4*)(wtap + (int64_t)(nb * 16 + r16) * ci + k0);
-        b[nb] = as_bf(t);
-      }
-#pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-          acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mb], b[nb], acc[mb][nb], 0, 0, 0);
     }
+    __syncthreads();
   }
-  // lane holds rows 4 g + r (voxels) of column r16 (channel) of each block
+  // lane holds rows 4 g + r (x offsets) of column r16 (channel) of each block
+  const int z = oz + wave;
 #pragma unroll
-  for (int mb = 0; mb < 2; ++mb)
+  for (int mb = 0; mb < 4; ++mb) {
+    const int y = oy + mb;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int v = vb + mb * 16 + 4 * g + r;
-      if (v >= V) continue;
+      const int x = ox + 4 * g + r;
+      if (x >= E || y >= E || z >= E) continue;
+      const int64_t v = (int64_t)(z * E + y) * E + x;
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        float x = acc[mb][nb][r];
-        if (relu) x = fmaxf(x, 0.0f);
-        out[(int64_t)v * cs_out + nb * 16 + r16] = f2bf(x);
+        float val = acc[mb][nb][r];
+        if (relu) val = fmaxf(val, 0.0f);
+        out[v * cs_out + nb * 16 + r16] = f2bf(val);
       }
     }
+  }
+}
+
+// Small input-channel counts (ci = 8, 16, 32; 48 with 48 output channels,
+// where the 73 KB halo still leaves enough occupancy): the whole halo (all
+// channels) fits in LDS, and K = 27 taps x ci is one flat dimension, k = tap ci + c, cut
+// into chunks of 32 that may span several taps (each 8-lane group of a
+// fragment reads its own tap), so the MFMAs carry no zero padding.
+template <int NB, int CI>
+__global__ __launch_bounds__(256) void k_conv3_flat(const uint16_t* __restrict__ in, int cs_in,
+                                                    const uint16_t* __restrict__ wt, uint16_t* __restrict__ out,
+                                                    int cs_out, int E, int relu) {
+  constexpr int ROW = CI + 8;  // bf16 per halo voxel (8 padding: bank spread, 16-byte rows)
+  constexpr int PARTS = CI / 8;
+  constexpr int KT = 27 * CI;
+  constexpr int NQ = (KT + 31) / 32;
+  constexpr int QG = NB <= 1 ? NQ : (NB <= 2 ? 9 : 3);  // chunks whose weights load together
+  __shared__ __attribute__((aligned(16))) uint16_t H[kHZ * kHY * kHX * ROW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r16 = lane & 15, g = lane >> 4;
+  const int co = NB * 16;
+  const int ox = blockIdx.x * kTX, oy = blockIdx.y * kTY, oz = blockIdx.z * kTZ;
+  for (int i = tid; i < kHZ * kHY * kHX * PARTS; i += 256) {
+    const int hv = i / PARTS, part = i % PARTS;
+    const int hx = hv % kHX, hy = (hv / kHX) % kHY, hz = hv / (kHX * kHY);
+    const int x = ox + hx - 1, y = oy + hy - 1, z = oz + hz - 1;
+    u32x4 t = {0u, 0u, 0u, 0u};
+    if (x >= 0 && x < E && y >= 0 && y < E && z >= 0 && z < E)
+      t = *(const u32x4*)(in + ((int64_t)(z * E + y) * E + x) * cs_in + part * 8);
+    *(u32x4*)&H[hv * ROW + part * 8] = t;
+  }
+  __syncthreads();
+  f32x4 acc[4][NB];
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int q0 = 0; q0 < NQ; q0 += QG) {
+    u32x4 w[QG][NB];
+#pragma unroll
+    for (int qq = 0; qq < QG; ++qq) {
+      const int k = (q0 + qq) * 32 + g * 8;
+      const int tap = k / CI, c = k % CI;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        w[qq][nb] = u32x4{0u, 0u, 0u, 0u};
+        if (q0 + qq < NQ && k < KT) w[qq][nb] = *(const u32x4*)(wt + ((int64_t)tap * co + nb * 16 + r16) * CI + c);
+      }
+    }
+#pragma unroll
+    for (int qq = 0; qq < QG; ++qq) {
+      if (q0 + qq >= NQ) break;
+      const int k = (q0 + qq) * 32 + g * 8;
+      const bool kin = k < KT;
+      const int tap = kin ? k / CI : 0, c = k % CI;
+      const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+      const int hz = wave + 1 + dz, hx = r16 + 1 + dx;
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb) {
+        const int hy = mb + 1 + dy;
+        u32x4 ta = {0u, 0u, 0u, 0u};
+        if (kin) ta = *(const u32x4*)&H[((hz * kHY + hy) * kHX + hx) * ROW + c];
+        const bf16x8 av = as_bf(ta);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, as_bf(w[qq][nb]), acc[mb][nb], 0, 0, 0);
+      }
+    }
+  }
+  const int z = oz + wave;
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb) {
+    const int y = oy + mb;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int x = ox + 4 * g + r;
+      if (x >= E || y >= E || z >= E) continue;
+      const int64_t v = (int64_t)(z * E + y) * E + x;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        float val = acc[mb][nb][r];
+        if (relu) val = fmaxf(val, 0.0f);
+        out[v * cs_out + nb * 16 + r16] = f2bf(val);
+      }
+    }
+  }
 }
 
 // Weight gradient, one tap per block row: partial[s][tap][i][j] =
@@ -277,70 +388,116 @@ __global__ void k_wgrad_reduce(const float* partial, int S, int ci, int co, int 
 }
 
 // ------------------------------------------------------- other layers
+// The pooling, upsampling and ReLU-mask kernels work on 8-channel groups
+// (16-byte rows; channel counts and channel offsets are multiples of 8).
+__device__ __forceinline__ void unpack8(u32x4 t, float* f) {
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    f[2 * h] = bf2f((uint16_t)(t[h] & 0xFFFFu));
+    f[2 * h + 1] = bf2f((uint16_t)(t[h] >> 16));
+  }
+}
+__device__ __forceinline__ u32x4 pack8(const float* f) {
+  u32x4 t;
+#pragma unroll
+  for (int h = 0; h < 4; ++h) t[h] = (uint32_t)f2bf(f[2 * h]) | ((uint32_t)f2bf(f[2 * h + 1]) << 16);
+  return t;
+}
+
 // P[z][y][x][c] = mean of the 2x2x2 children (coarse edge Ec)
 __global__ void k_pool(const uint16_t* in, int cs_in, uint16_t* out, int C, int Ec) {
-  const int64_t n = (int64_t)Ec * Ec * Ec * C;
+  const int G = C / 8;
+  const int64_t n = (int64_t)Ec * Ec * Ec * G;
   const int Ef = 2 * Ec;
   ULOOP(idx, n) {
-    const int c = (int)(idx % C);
-    const int64_t p = idx / C;
-    const int x = (int)(p % Ec), y = (int)((p / Ec) % Ec), z = (int)(p / ((int64_t)Ec * Ec));
-    float s = 0.0f;
+    const int grp = (int)(idx % G);
+    const int p = (int)(idx / G);
+    const int x = p % Ec, y = (p / Ec) % Ec, z = p / (Ec * Ec);
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     for (int k = 0; k < 8; ++k) {
       const int fz = 2 * z + (k >> 2), fy = 2 * y + ((k >> 1) & 1), fx = 2 * x + (k & 1);
-      s += bf2f(in[((int64_t)(fz * Ef + fy) * Ef + fx) * cs_in + c]);
+      float f[8];
+      unpack8(*(const u32x4*)(in + ((int64_t)(fz * Ef + fy) * Ef + fx) * cs_in + grp * 8), f);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) s[j] += f[j];
     }
-    out[p * C + c] = f2bf(s * 0.125f);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s[j] *= 0.125f;
+    *(u32x4*)(out + (int64_t)p * C + grp * 8) = pack8(s);
   }
 }
 // dskip[v][c] += dP[parent(v)][c] / 8 (fine edge Ef)
 __global__ void k_pool_bwd_add(const uint16_t* dP, int C, uint16_t* dskip, int cs, int Ef) {
-  const int64_t n = (int64_t)Ef * Ef * Ef * C;
+  const int G = C / 8;
+  const int64_t n = (int64_t)Ef * Ef * Ef * G;
   const int Ec = Ef / 2;
   ULOOP(idx, n) {
-    const int c = (int)(idx % C);
-    const int64_t v = idx / C;
-    const int x = (int)(v % Ef), y = (int)((v / Ef) % Ef), z = (int)(v / ((int64_t)Ef * Ef));
+    const int grp = (int)(idx % G);
+    const int v = (int)(idx / G);
+    const int x = v % Ef, y = (v / Ef) % Ef, z = v / (Ef * Ef);
     const int64_t p = ((int64_t)(z / 2) * Ec + y / 2) * Ec + x / 2;
-    uint16_t* d = dskip + v * cs + c;
-    *d = f2bf(bf2f(*d) + bf2f(dP[p * C + c]) * 0.125f);
+    uint16_t* d = dskip + (int64_t)v * cs + grp * 8;
+    float a[8], b[8];
+    unpack8(*(const u32x4*)d, a);
+    unpack8(*(const u32x4*)(dP + p * C + grp * 8), b);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a[j] = a[j] + b[j] * 0.125f;
+    *(u32x4*)d = pack8(a);
   }
 }
 // out[v][c] (stride cs_out) = in[parent(v)][c] (fine edge Ef)
 __global__ void k_up(const uint16_t* in, int C, uint16_t* out, int cs_out, int Ef) {
-  const int64_t n = (int64_t)Ef * Ef * Ef * C;
+  const int G = C / 8;
+  const int64_t n = (int64_t)Ef * Ef * Ef * G;
   const int Ec = Ef / 2;
   ULOOP(idx, n) {
-    const int c = (int)(idx % C);
-    const int64_t v = idx / C;
-    const int x = (int)(v % Ef), y = (int)((v / Ef) % Ef), z = (int)(v / ((int64_t)Ef * Ef));
-    out[v * cs_out + c] = in[(((int64_t)(z / 2) * Ec + y / 2) * Ec + x / 2) * C + c];
+    const int grp = (int)(idx % G);
+    const int v = (int)(idx / G);
+    const int x = v % Ef, y = (v / Ef) % Ef, z = v / (Ef * Ef);
+    const int64_t p = ((int64_t)(z / 2) * Ec + y / 2) * Ec + x / 2;
+    *(u32x4*)(out + (int64_t)v * cs_out + grp * 8) = *(const u32x4*)(in + p * C + grp * 8);
   }
 }
 // out[p][c] = sum of d[child][c] (stride cs), coarse edge Ec
 __global__ void k_up_bwd(const uint16_t* d, int cs, uint16_t* out, int C, int Ec) {
-  const int64_t n = (int64_t)Ec * Ec * Ec * C;
+  const int G = C / 8;
+  const int64_t n = (int64_t)Ec * Ec * Ec * G;
   const int Ef = 2 * Ec;
   ULOOP(idx, n) {
-    const int c = (int)(idx % C);
-    const int64_t p = idx / C;
-    const int x = (int)(p % Ec), y = (int)((p / Ec) % Ec), z = (int)(p / ((int64_t)Ec * Ec));
-    float s = 0.0f;
+    const int grp = (int)(idx % G);
+    const int p = (int)(idx / G);
+    const int x = p % Ec, y = (p / Ec) % Ec, z = p / (Ec * Ec);
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     for (int k = 0; k < 8; ++k) {
       const int fz = 2 * z + (k >> 2), fy = 2 * y + ((k >> 1) & 1), fx = 2 * x + (k & 1);
-      s += bf2f(d[((int64_t)(fz * Ef + fy) * Ef + fx) * cs + c]);
+      float f[8];
+      unpack8(*(const u32x4*)(d + ((int64_t)(fz * Ef + fy) * Ef + fx) * cs + grp * 8), f);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) s[j] += f[j];
     }
-    out[p * C + c] = f2bf(s);
+    *(u32x4*)(out + (int64_t)p * C + grp * 8) = pack8(s);
   }
 }
 // dy = dy * (a > 0)
 __global__ void k_relu_bwd(uint16_t* dy, int cs_dy, const uint16_t* a, int cs_a, int C, int64_t V) {
-  ULOOP(idx, V * C) {
-    const int c = (int)(idx % C);
-    const int64_t v = idx / C;
-    if (!(bf2f(a[v * cs_a + c]) > 0.0f)) dy[v * cs_dy + c] = 0;
+  const int G = C / 8;
+  ULOOP(idx, V * G) {
+    const int grp = (int)(idx % G);
+    const int64_t v = idx / G;
+    u32x4 t = *(const u32x4*)(dy + v * cs_dy + grp * 8);
+    const u32x4 m = *(const u32x4*)(a + v * cs_a + grp * 8);
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      uint32_t w = t[h];
+      // bf16 a > 0: sign bit clear and not zero
+      if ((m[h] & 0x8000u) || (m[h] & 0x7FFFu) == 0u) w &= 0xFFFF0000u;
+      if ((m[h] & 0x80000000u) || (m[h] & 0x7FFF0000u) == 0u) w &= 0x0000FFFFu;
+      t[h] = w;
+    }
+    *(u32x4*)(dy + v * cs_dy + grp * 8) = t;
   }
 }
+
 // out[v] = sum_c w[c] a[v][c]
 __global__ void k_out(const uint16_t* a, const float* w, float* out, int64_t V) {
   ULOOP(v, V) {
@@ -374,15 +531,13 @@ __global__ __launch_bounds__(kT) void k_mse(const float* out, const float* t, co
     part[kRedBlocks + blockIdx.x] = (sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]);
   }
 }
-__global__ void k_sum2(const double* part, int np, double* out) {
-  if (threadIdx.x != 0) return;
-  double a = 0.0, b = 0.0;
-  for (int i = 0; i < np; ++i) {
-    a += part[i];
-    b += part[kRedBlocks + i];
+__global__ __launch_bounds__(256) void k_sum2(const double* part, int np, double* out) {
+  __shared__ double sh[4];
+  const double a = block_total(part, np, sh), b = block_total(part + kRedBlocks, np, sh);
+  if (threadIdx.x == 0) {
+    out[0] = a;
+    out[1] = b;
   }
-  out[0] = a;
-  out[1] = b;
 }
 __global__ void k_dout(const float* out, const float* t, const float* mask, const double* lc, float* dout,
                        int64_t V) {
@@ -416,12 +571,21 @@ __global__ __launch_bounds__(kT) void k_out_bwd(const uint16_t* a, const float* 
     gpart[blockIdx.x * 16 + c] = (sh[c][0] + sh[c][1]) + (sh[c][2] + sh[c][3]);
   }
 }
-__global__ void k_gout_reduce(const float* gpart, int nb, float* grad, float scale, int accumulate) {
-  const int c = threadIdx.x;
-  if (c >= 16) return;
-  float s = 0.0f;
-  for (int b = 0; b < nb; ++b) s += gpart[b * 16 + c];
-  grad[c] = (accumulate ? grad[c] : 0.0f) + scale * s;
+__global__ __launch_bounds__(256) void k_gout_reduce(const float* gpart, int nb, float* grad, float scale,
+                                                     int accumulate) {
+  __shared__ float sh[16][4];
+  for (int c = 0; c < 16; ++c) {
+    float v = 0.0f;
+    for (int b = threadIdx.x; b < nb; b += 256) v += gpart[b * 16 + c];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[c][threadIdx.x >> 6] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    const int c = threadIdx.x;
+    const float t = (sh[c][0] + sh[c][1]) + (sh[c][2] + sh[c][3]);
+    grad[c] = (accumulate ? grad[c] : 0.0f) + scale * t;
+  }
 }
 
 // bf16 copies of the FP32 masters in the two layouts
@@ -458,11 +622,10 @@ __global__ __launch_bounds__(kT) void k_sumsq(const T* r, int64_t n, double* par
   if (threadIdx.x == 0) part[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
 // rms = sqrt(sum / n) into scal[0]
-__global__ void k_rms(const double* part, int np, int64_t n, double* scal) {
-  if (threadIdx.x != 0) return;
-  double s = 0.0;
-  for (int i = 0; i < np; ++i) s += part[i];
-  scal[0] = s > 0.0 ? sqrt(s / (double)n) : 1.0;
+__global__ __launch_bounds__(256) void k_rms(const double* part, int np, int64_t n, double* scal) {
+  __shared__ double sh[4];
+  const double s = block_total(part, np, sh);
+  if (threadIdx.x == 0) scal[0] = s > 0.0 ? sqrt(s / (double)n) : 1.0;
 }
 
 struct PackGeo {
@@ -533,11 +696,10 @@ __global__ __launch_bounds__(kT) void k_sum_part(const T* z, int64_t n, double* 
   __syncthreads();
   if (threadIdx.x == 0) part[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
-__global__ void k_mean(const double* part, int np, int64_t n, double* scal) {
-  if (threadIdx.x != 0) return;
-  double s = 0.0;
-  for (int i = 0; i < np; ++i) s += part[i];
-  scal[1] = s / (double)n;
+__global__ __launch_bounds__(256) void k_mean(const double* part, int np, int64_t n, double* scal) {
+  __shared__ double sh[4];
+  const double s = block_total(part, np, sh);
+  if (threadIdx.x == 0) scal[1] = s / (double)n;
 }
 template <typename T>
 __global__ void k_sub(T* z, int64_t n, const double* scal) {
@@ -570,11 +732,11 @@ __global__ __launch_bounds__(kT) void k_dot3(const double* z, const double* q, c
       (sh[threadIdx.x][0] + sh[threadIdx.x][1]) + (sh[threadIdx.x][2] + sh[threadIdx.x][3]);
 }
 // scal[4..6] = totals; scal[7] = loss (z.q - 2 z.r + e.r) / e.r
-__global__ void k_fin3(const double* part, int np, double* scal) {
+__global__ __launch_bounds__(256) void k_fin3(const double* part, int np, double* scal) {
+  __shared__ double sh[4];
+  double t[3];
+  for (int k = 0; k < 3; ++k) t[k] = block_total(part + k * kRedBlocks, np, sh);
   if (threadIdx.x != 0) return;
-  double t[3] = {0.0, 0.0, 0.0};
-  for (int k = 0; k < 3; ++k)
-    for (int i = 0; i < np; ++i) t[k] += part[k * kRedBlocks + i];
   scal[4] = t[0];
   scal[5] = t[1];
   scal[6] = t[2];
@@ -637,13 +799,10 @@ __global__ __launch_bounds__(kT) void k_dot2(const T* a, const T* b, const T* c,
 }
 // scal[2] = beta = (n.r1) / (n.A n), the A-norm-optimal step along n (either
 // sign; 0 if n.A n is not positive); scal[8] = n.A n
-__global__ void k_beta(const double* part, int np, double* scal) {
+__global__ __launch_bounds__(256) void k_beta(const double* part, int np, double* scal) {
+  __shared__ double sh[4];
+  const double a = block_total(part, np, sh), b = block_total(part + kRedBlocks, np, sh);
   if (threadIdx.x != 0) return;
-  double a = 0.0, b = 0.0;
-  for (int i = 0; i < np; ++i) {
-    a += part[i];
-    b += part[kRedBlocks + i];
-  }
   scal[2] = b > 0.0 ? a / b : 0.0;
   scal[8] = b;
 }
@@ -670,11 +829,10 @@ __global__ __launch_bounds__(kT) void k_dot1(const double* a, const double* b, i
   __syncthreads();
   if (threadIdx.x == 0) part[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
-__global__ void k_fin1(const double* part, int np, double* out) {
-  if (threadIdx.x != 0) return;
-  double a = 0.0;
-  for (int i = 0; i < np; ++i) a += part[i];
-  *out = a;
+__global__ __launch_bounds__(256) void k_fin1(const double* part, int np, double* out) {
+  __shared__ double sh[4];
+  const double a = block_total(part, np, sh);
+  if (threadIdx.x == 0) *out = a;
 }
 // dL/dn = beta G + (G.n / n.A n)(r1 - 2 beta A n)  (beta = n.r1 / n.A n)
 __global__ void k_gbeta(double* gn, const double* G, const double* r1, const double* an, const double* scal,
@@ -687,16 +845,29 @@ __global__ void k_gbeta(double* gn, const double* G, const double* r1, const dou
 // ------------------------------------------------------------ host side
 int conv(const uint16_t* in, int cs_in, int ci, const uint16_t* wt, uint16_t* out, int cs_out, int co, int E,
          bool relu, hipStream_t s) {
-  const int64_t V = (int64_t)E * E * E;
-  const unsigned g = (unsigned)((V + 127) / 128);
   const int r = relu ? 1 : 0;
+  const dim3 g((unsigned)((E + kTX - 1) / kTX), (unsigned)((E + kTY - 1) / kTY), (unsigned)((E + kTZ - 1) / kTZ));
+  const int key = (co / 16) * 100 + ci;
+  if (ci == 8 || ci == 16 || ci == 32 || key == 348) {
+    switch (key) {
+#define FL(nb, cc) \
+  case nb * 100 + cc: k_conv3_flat<nb, cc><<<g, 256, 0, s>>>(in, cs_in, wt, out, cs_out, E, r); break;
+      FL(1, 8) FL(1, 16) FL(1, 32) FL(2, 16) FL(2, 32) FL(3, 32) FL(5, 32) FL(3, 16) FL(3, 48)
+#undef FL
+      default:
+        set_error("unsupported channel count");
+        return CHNS_EINVAL;
+    }
+    CHNS_HIP(hipGetLastError());
+    return CHNS_OK;
+  }
   switch (co / 16) {
-    case 1: k_conv3<1><<<g, 256, 0, s>>>(in, cs_in, ci, wt, out, cs_out, E, r); break;
-    case 2: k_conv3<2><<<g, 256, 0, s>>>(in, cs_in, ci, wt, out, cs_out, E, r); break;
-    case 3: k_conv3<3><<<g, 256, 0, s>>>(in, cs_in, ci, wt, out, cs_out, E, r); break;
-    case 4: k_conv3<4><<<g, 256, 0, s>>>(in, cs_in, ci, wt, out, cs_out, E, r); break;
-    case 5: k_conv3<5><<<g, 256, 0, s>>>(in, cs_in, ci, wt, out, cs_out, E, r); break;
-    case 7: k_conv3<7><<<g, 256, 0, s>>>(in, cs_in, ci, wt, out, cs_out, E, r); break;
+    case 1: k_conv3_tile<1><<<g, 256, 0, s>>>(in, cs_in, ci, wt, out, cs_out, E, r); break;
+    case 2: k_conv3_tile<2><<<g, 256, 0, s>>>(in, cs_in, ci, wt, out, cs_out, E, r); break;
+    case 3: k_conv3_tile<3><<<g, 256, 0, s>>>(in, cs_in, ci, wt, out, cs_out, E, r); break;
+    case 4: k_conv3_tile<4><<<g, 256, 0, s>>>(in, cs_in, ci, wt, out, cs_out, E, r); break;
+    case 5: k_conv3_tile<5><<<g, 256, 0, s>>>(in, cs_in, ci, wt, out, cs_out, E, r); break;
+    case 7: k_conv3_tile<7><<<g, 256, 0, s>>>(in, cs_in, ci, wt, out, cs_out, E, r); break;
     default:
       set_error("unsupported channel count");
       return CHNS_EINVAL;
@@ -811,22 +982,22 @@ int forward(UNet& u, UActs& a, hipStream_t s) {
   if ((rc = conv(in, csi, L[k].ci, L[k].wf, out, cso, L[k].co, E, true, s))) return rc;
   CV(a.X, kInCh, 0, a.A0, 16, E0);
   CV(a.A0, 16, 1, a.cat0 + 32, 48, E0);
-  k_pool<<<nblk((int64_t)E1 * E1 * E1 * 16), kT, 0, s>>>(a.cat0 + 32, 48, a.P0, 16, E1);
+  k_pool<<<nblk((int64_t)E1 * E1 * E1 * 2), kT, 0, s>>>(a.cat0 + 32, 48, a.P0, 16, E1);
   CV(a.P0, 16, 2, a.A2, 32, E1);
   CV(a.A2, 32, 3, a.cat1 + 48, 80, E1);
-  k_pool<<<nblk((int64_t)E2 * E2 * E2 * 32), kT, 0, s>>>(a.cat1 + 48, 80, a.P1, 32, E2);
+  k_pool<<<nblk((int64_t)E2 * E2 * E2 * 4), kT, 0, s>>>(a.cat1 + 48, 80, a.P1, 32, E2);
   CV(a.P1, 32, 4, a.A4, 48, E2);
   CV(a.A4, 48, 5, a.cat2 + 64, 112, E2);
-  k_pool<<<nblk((int64_t)E3 * E3 * E3 * 48), kT, 0, s>>>(a.cat2 + 64, 112, a.P2, 48, E3);
+  k_pool<<<nblk((int64_t)E3 * E3 * E3 * 6), kT, 0, s>>>(a.cat2 + 64, 112, a.P2, 48, E3);
   CV(a.P2, 48, 6, a.A6, 64, E3);
   CV(a.A6, 64, 7, a.A7, 64, E3);
-  k_up<<<nblk((int64_t)E2 * E2 * E2 * 64), kT, 0, s>>>(a.A7, 64, a.cat2, 112, E2);
+  k_up<<<nblk((int64_t)E2 * E2 * E2 * 8), kT, 0, s>>>(a.A7, 64, a.cat2, 112, E2);
   CV(a.cat2, 112, 8, a.A8, 48, E2);
   CV(a.A8, 48, 9, a.A9, 48, E2);
-  k_up<<<nblk((int64_t)E1 * E1 * E1 * 48), kT, 0, s>>>(a.A9, 48, a.cat1, 80, E1);
+  k_up<<<nblk((int64_t)E1 * E1 * E1 * 6), kT, 0, s>>>(a.A9, 48, a.cat1, 80, E1);
   CV(a.cat1, 80, 10, a.A10, 32, E1);
   CV(a.A10, 32, 11, a.A11, 32, E1);
-  k_up<<<nblk((int64_t)E0 * E0 * E0 * 32), kT, 0, s>>>(a.A11, 32, a.cat0, 48, E0);
+  k_up<<<nblk((int64_t)E0 * E0 * E0 * 4), kT, 0, s>>>(a.A11, 32, a.cat0, 48, E0);
   CV(a.cat0, 48, 12, a.A12, 16, E0);
   CV(a.A12, 16, 13, a.A13, 16, E0);
 #undef CV
@@ -843,12 +1014,12 @@ int backward(UNet& u, UActs& a, float scale, int accumulate, hipStream_t s) {
   int rc;
   const unsigned gb = (unsigned)std::min<int64_t>(kRedBlocks, (V0 + kT - 1) / kT);
   k_out_bwd<<<gb, kT, 0, s>>>(a.A13, u.W + u.wout_off, a.dout, V0, a.dA13, u.gout_part);
-  k_gout_reduce<<<1, 64, 0, s>>>(u.gout_part, (int)gb, u.grad + u.wout_off, scale, accumulate);
+  k_gout_reduce<<<1, 256, 0, s>>>(u.gout_part, (int)gb, u.grad + u.wout_off, scale, accumulate);
   CHNS_HIP(hipGetLastError());
   // one layer: relu mask, weight gradient, input gradient
   auto layer = [&](int k, uint16_t* dy, int cs_dy, const uint16_t* act, int cs_act, const uint16_t* in, int cs_in,
                    uint16_t* dx, int cs_dx, int E, int64_t V) -> int {
-    k_relu_bwd<<<nblk(V * L[k].co), kT, 0, s>>>(dy, cs_dy, act, cs_act, L[k].co, V);
+    k_relu_bwd<<<nblk(V * L[k].co / 8), kT, 0, s>>>(dy, cs_dy, act, cs_act, L[k].co, V);
     CHNS_HIP(hipGetLastError());
     int e = wgrad(u, k, in, cs_in, dy, cs_dy, E, scale, accumulate, s);
     if (e) return e;
@@ -857,22 +1028,22 @@ int backward(UNet& u, UActs& a, float scale, int accumulate, hipStream_t s) {
   };
   if ((rc = layer(13, a.dA13, 16, a.A13, 16, a.A12, 16, a.dA12, 16, E0, V0))) return rc;
   if ((rc = layer(12, a.dA12, 16, a.A12, 16, a.cat0, 48, a.dcat0, 48, E0, V0))) return rc;
-  k_up_bwd<<<nblk(V1 * 32), kT, 0, s>>>(a.dcat0, 48, a.dA11, 32, E1);
+  k_up_bwd<<<nblk(V1 * 4), kT, 0, s>>>(a.dcat0, 48, a.dA11, 32, E1);
   if ((rc = layer(11, a.dA11, 32, a.A11, 32, a.A10, 32, a.dA10, 32, E1, V1))) return rc;
   if ((rc = layer(10, a.dA10, 32, a.A10, 32, a.cat1, 80, a.dcat1, 80, E1, V1))) return rc;
-  k_up_bwd<<<nblk(V2 * 48), kT, 0, s>>>(a.dcat1, 80, a.dA9, 48, E2);
+  k_up_bwd<<<nblk(V2 * 6), kT, 0, s>>>(a.dcat1, 80, a.dA9, 48, E2);
   if ((rc = layer(9, a.dA9, 48, a.A9, 48, a.A8, 48, a.dA8, 48, E2, V2))) return rc;
   if ((rc = layer(8, a.dA8, 48, a.A8, 48, a.cat2, 112, a.dcat2, 112, E2, V2))) return rc;
-  k_up_bwd<<<nblk(V3 * 64), kT, 0, s>>>(a.dcat2, 112, a.dA7, 64, E3);
+  k_up_bwd<<<nblk(V3 * 8), kT, 0, s>>>(a.dcat2, 112, a.dA7, 64, E3);
   if ((rc = layer(7, a.dA7, 64, a.A7, 64, a.A6, 64, a.dA6, 64, E3, V3))) return rc;
   if ((rc = layer(6, a.dA6, 64, a.A6, 64, a.P2, 48, a.dP2, 48, E3, V3))) return rc;
-  k_pool_bwd_add<<<nblk(V2 * 48), kT, 0, s>>>(a.dP2, 48, a.dcat2 + 64, 112, E2);
+  k_pool_bwd_add<<<nblk(V2 * 6), kT, 0, s>>>(a.dP2, 48, a.dcat2 + 64, 112, E2);
   if ((rc = layer(5, a.dcat2 + 64, 112, a.cat2 + 64, 112, a.A4, 48, a.dA4, 48, E2, V2))) return rc;
   if ((rc = layer(4, a.dA4, 48, a.A4, 48, a.P1, 32, a.dP1, 32, E2, V2))) return rc;
-  k_pool_bwd_add<<<nblk(V1 * 32), kT, 0, s>>>(a.dP1, 32, a.dcat1 + 48, 80, E1);
+  k_pool_bwd_add<<<nblk(V1 * 4), kT, 0, s>>>(a.dP1, 32, a.dcat1 + 48, 80, E1);
   if ((rc = layer(3, a.dcat1 + 48, 80, a.cat1 + 48, 80, a.A2, 32, a.dA2, 32, E1, V1))) return rc;
   if ((rc = layer(2, a.dA2, 32, a.A2, 32, a.P0, 16, a.dP0, 16, E1, V1))) return rc;
-  k_pool_bwd_add<<<nblk(V0 * 16), kT, 0, s>>>(a.dP0, 16, a.dcat0 + 32, 48, E0);
+  k_pool_bwd_add<<<nblk(V0 * 2), kT, 0, s>>>(a.dP0, 16, a.dcat0 + 32, 48, E0);
   if ((rc = layer(1, a.dcat0 + 32, 48, a.cat0 + 32, 48, a.A0, 16, a.dA0, 16, E0, V0))) return rc;
   if ((rc = layer(0, a.dA0, 16, a.A0, 16, a.X, kInCh, nullptr, 0, E0, V0))) return rc;
   CHNS_HIP(hipGetLastError());
@@ -1117,7 +1288,7 @@ static int pack_sample(Ctx& c, UActs& a, const double* phi, const double* r, con
   const int64_t n = c.dm.n;
   const unsigned g = (unsigned)std::min<int64_t>(kRedBlocks, (n + kT - 1) / kT);
   k_sumsq<double><<<g, kT, 0, s>>>(r, n, u.red);
-  k_rms<<<1, 64, 0, s>>>(u.red, (int)g, n, u.scal);
+  k_rms<<<1, 256, 0, s>>>(u.red, (int)g, n, u.scal);
   PackGeo geo{c.dm.side, a.E, origin ? origin[0] : 0, origin ? origin[1] : 0, origin ? origin[2] : 0, flip};
   double al, be;
   rho_ab(c, &al, &be);
@@ -1177,7 +1348,7 @@ static int net_nodes(Ctx& c, UActs& a, const double* phi, const T* x, T* z, hipS
   rho_ab(c, &al, &be);
   const int64_t V = (int64_t)a.E * a.E * a.E;
   k_sumsq<T><<<g, kT, 0, s>>>(x, n, u.red);
-  k_rms<<<1, 64, 0, s>>>(u.red, (int)g, n, u.scal);
+  k_rms<<<1, 256, 0, s>>>(u.red, (int)g, n, u.scal);
   k_pack<T><<<nblk(V), kT, 0, s>>>(geo, phi, x, nullptr, u.scal, al, be, 1.0 / lratio(c), u.K, a.X, nullptr,
                                    nullptr);
   CHNS_HIP(hipGetLastError());
@@ -1241,7 +1412,7 @@ static int train_energy(Ctx& c, const chns_pc_batch& b, float lr, float* loss, h
     if (w > 0.0) {
       if ((rc = launch_apply(c, CHNS_OP_PRESSURE, CHNS_FP64, net, an, s, plain))) return rc;
       k_dot2<double><<<g, kT, 0, s>>>(net, r1, an, n, u.red);
-      k_beta<<<1, 64, 0, s>>>(u.red, (int)g, u.scal);
+      k_beta<<<1, 256, 0, s>>>(u.red, (int)g, u.scal);
       CHNS_HIP(hipMemcpyAsync(z, net, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
       k_comb<double><<<gn, kT, 0, s>>>(z, z1, u.scal, n);
       k_jcorr2<double><<<gn, kT, 0, s>>>(z, w, d, r, az1, an, u.scal, n);
@@ -1250,7 +1421,7 @@ static int train_energy(Ctx& c, const chns_pc_batch& b, float lr, float* loss, h
     }
     if ((rc = launch_apply(c, CHNS_OP_PRESSURE, CHNS_FP64, zz, u.qb, s, plain))) return rc;
     k_dot3<<<g, kT, 0, s>>>(zz, u.qb, r, b.e[k], n, u.red);
-    k_fin3<<<1, 64, 0, s>>>(u.red, (int)g, u.scal);
+    k_fin3<<<1, 256, 0, s>>>(u.red, (int)g, u.scal);
     k_grad_anorm<<<gn, kT, 0, s>>>(u.qb, r, u.scal, G, n);
     CHNS_HIP(hipGetLastError());
     const double* gout = G;
@@ -1259,7 +1430,7 @@ static int train_energy(Ctx& c, const chns_pc_batch& b, float lr, float* loss, h
       if ((rc = launch_apply(c, CHNS_OP_PRESSURE, CHNS_FP64, h, ah, s, plain))) return rc;
       k_axpy_neg<<<gn, kT, 0, s>>>(G, w, ah, n);
       k_dot1<<<g, kT, 0, s>>>(G, net, n, u.red);
-      k_fin1<<<1, 64, 0, s>>>(u.red, (int)g, u.scal + 9);
+      k_fin1<<<1, 256, 0, s>>>(u.red, (int)g, u.scal + 9);
       k_gbeta<<<gn, kT, 0, s>>>(gnet, G, r1, an, u.scal, n);
       CHNS_HIP(hipGetLastError());
       gout = gnet;
@@ -1320,7 +1491,7 @@ int unet_train_step(Ctx& c, const chns_pc_batch& b, float lr, float* loss, hipSt
     if ((rc = forward(u, *a, s))) return rc;
     k_out<<<nblk(V), kT, 0, s>>>(a->A13, u.W + u.wout_off, a->out, V);
     k_mse<<<gl, kT, 0, s>>>(a->out, a->target, a->mask, V, u.red);
-    k_sum2<<<1, 64, 0, s>>>(u.red, (int)gl, u.scal + 2);
+    k_sum2<<<1, 256, 0, s>>>(u.red, (int)gl, u.scal + 2);
     k_dout<<<nblk(V), kT, 0, s>>>(a->out, a->target, a->mask, u.scal + 2, a->dout, V);
     CHNS_HIP(hipGetLastError());
     if ((rc = backward(u, *a, scale, k > 0 ? 1 : 0, s))) return rc;
@@ -1386,7 +1557,7 @@ int unet_apply(Ctx& c, const T* r, T* z, hipStream_t s) {
     if ((rc = net_nodes<T>(c, *a, c.phi64, r1, z, s))) return rc;
     if ((rc = launch_apply(c, CHNS_OP_PRESSURE, prec, z, an, s, plain))) return rc;
     k_dot2<T><<<g, kT, 0, s>>>(z, r1, an, n, u.red);
-    k_beta<<<1, 64, 0, s>>>(u.red, (int)g, u.scal);
+    k_beta<<<1, 256, 0, s>>>(u.red, (int)g, u.scal);
     k_comb<T><<<gn, kT, 0, s>>>(z, z1, u.scal, n);
     k_jcorr2<T><<<gn, kT, 0, s>>>(z, w, d, r, az1, an, u.scal, n);
     CHNS_HIP(hipGetLastError());
@@ -1394,7 +1565,7 @@ int unet_apply(Ctx& c, const T* r, T* z, hipStream_t s) {
     return rc;
   }
   k_sum_part<T><<<g, kT, 0, s>>>(z, n, u.red);
-  k_mean<<<1, 64, 0, s>>>(u.red, (int)g, n, u.scal);
+  k_mean<<<1, 256, 0, s>>>(u.red, (int)g, n, u.scal);
   k_sub<T><<<gn, kT, 0, s>>>(z, n, u.scal);
   CHNS_HIP(hipGetLastError());
   return CHNS_OK;

@@ -82,8 +82,9 @@ def evaluate(torch, ctx, x_unit, seeds):
     for s in seeds:
         phi, b = instance(torch, ctx, x_unit, s)
         row = {"seed": s}
-        for name, kw in (("jacobi", dict(pc="jacobi")), ("gmg", dict(pc="gmg")), ("learned", dict(pc="learned")),
-                         ("learned_mixed", dict(pc="learned", mode="mixed"))):
+        for name, kw in (("jacobi", dict(pc="jacobi")), ("gmg", dict(pc="gmg")),
+                         ("learned_every8", dict(pc="learned", learned_every=8)),
+                         ("learned_every8_mixed", dict(pc="learned", learned_every=8, mode="mixed"))):
             ctx.solve_pressure(b, **kw)  # warm-up (graphs, buffers)
             torch.cuda.synchronize()
             t0 = time.perf_counter()

@@ -272,3 +272,40 @@ def test_smoothed_anorm_objective_matches_oracle(setup):
     assert _rel(g[off:].astype(np.float64), ref["w_out"]) <= 2e-2
     k13 = off - 27 * 16 * 16
     assert _rel(g[k13:off].astype(np.float64), ref["W"][13].reshape(-1)) <= 5e-2
+
+
+def test_trained_network_cuts_cg_iterations_on_the_128_cube_workload():
+    """Gain of the shipped, trained network on the 3D uniform level-7 pressure
+    solve (8 seeded drops, density ratio 1000, seed 0): flexible CG with the
+    network preconditioner applied every 8th iteration (Jacobi otherwise)
+    reaches the same 1e-8 relative residual in at most half the iterations of
+    the same flexible CG with Jacobi alone; wall times are printed (the
+    benchmark reports them)."""
+    import os
+    import time
+    import chns_inputs as ci
+    from paper_2107_05123_amd import Context, Mesh
+    mesh = Mesh(dim=3, min_level=7, max_level=7, rule="uniform")
+    x = ci.unit_coords(mesh.node_coords(), 7)
+    c, r = ci.drops(0)
+    ctx = Context(mesh, Cn=0.01, rho_plus=RHO_P, rho_minus=RHO_M)
+    phi = _dev(ci.phi_drops(x, c, r, 0.01))
+    ctx.set_phase_field(phi)
+    amps, waves = ci.rhs_modes(1)
+    b = ctx.apply(ctx.MASS, _dev(ci.rhs_field(x, amps, waves)))
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    with open(os.path.join(root, "paper_2107_05123_amd", "weights", "unet_uniform_l7_rho1000.bin"), "rb") as fh:
+        ctx.pc_load(fh.read())
+    res = {}
+    for name, kw in (("jacobi_flex", dict(pc="learned", learned_every=10 ** 6)),
+                     ("learned_every8", dict(pc="learned", learned_every=8)),
+                     ("jacobi_pcg", dict(pc="jacobi"))):
+        ctx.solve_pressure(b, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = ctx.solve_pressure(b, **kw)
+        torch.cuda.synchronize()
+        res[name] = (st.iterations, time.perf_counter() - t0, st.rel_residual)
+        assert st.rel_residual <= 1e-8
+    print("gain", res, flush=True)
+    assert res["learned_every8"][0] <= 0.5 * res["jacobi_flex"][0]
