@@ -452,7 +452,7 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": ach_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": frac_hbm, "traffic": traffic}
-    roof.update({"kernel": "k_brick<3,8,double,PP>", "kernel_ms": k64,
+    roof.update({"kernel": "k_brick_o4<3,8,double,PP>", "kernel_ms": k64,
                  "algorithmic_bytes_per_launch": bytes64, "algorithmic_flops_per_launch": flops,
                  "hbm_frac_algorithmic": frac_hbm, "alu_frac": frac_alu})
 

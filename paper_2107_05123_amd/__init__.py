@@ -70,6 +70,7 @@ class Mesh:
         h = C.c_void_p()
         L.check(lib.chns_octree_build(C.byref(spec), C.byref(h)))
         self._h = h
+        self._destroy = L.lib().chns_mesh_destroy
         self.dim = dim
         self.info = self._info()
 
@@ -118,10 +119,13 @@ class Mesh:
                 "n_colors": i.n_colors, "level_counts": {l: c for l, c in enumerate(i.level_counts) if c}}
 
     def __del__(self):
+        # only attributes of the object itself: module globals may already be
+        # gone when this runs at interpreter shutdown
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            L.lib().chns_mesh_destroy(h)
-            self._h = C.c_void_p()
+        destroy = getattr(self, "_destroy", None)
+        if h is not None and h.value and destroy is not None:
+            destroy(h)
+            h.value = None
 
 
 def octree_build(**kw) -> Mesh:
@@ -154,6 +158,7 @@ class Context:
         h = C.c_void_p()
         L.check(L.lib().chns_context_create(mesh._h, C.byref(p), C.byref(h)))
         self._h = h
+        self._destroy = L.lib().chns_context_destroy
         self.n = mesh.n_nodes
         self.dim = mesh.dim
 
@@ -333,7 +338,10 @@ class Context:
         return ms.value, n.value
 
     def __del__(self):
+        # only attributes of the object itself: module globals may already be
+        # gone when this runs at interpreter shutdown
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            L.lib().chns_context_destroy(h)
-            self._h = C.c_void_p()
+        destroy = getattr(self, "_destroy", None)
+        if h is not None and h.value and destroy is not None:
+            destroy(h)
+            h.value = None

@@ -72,6 +72,7 @@ Ctx::~Ctx() {
   for (auto e : prof_pool) (void)hipEventDestroy(e);
   for (void* p : allocs) (void)hipFree(p);
   if (sc_host) (void)hipHostFree(sc_host);
+  if (flag_host) (void)hipHostFree(flag_host);
 }
 
 template <typename T>
@@ -92,7 +93,8 @@ static int upload_mesh(Ctx& c) {
   d.n_slots = m.n_slots;
   d.n_colors = m.n_colors;
   d.side = 1 << m.max_level;
-  d.structured = m.uniform && m.node_order == 0 && m.n_hanging == 0;
+  // structured kernels address nodes with 32-bit offsets
+  d.structured = m.uniform && m.node_order == 0 && m.n_hanging == 0 && m.n_indep < ((int64_t)1 << 31);
   int rc;
   for (int k = 0; k < kBrickClasses; ++k) {
     const BrickClass& h = m.cls[k];
@@ -269,6 +271,9 @@ int chns_context_create(chns_mesh* mesh, const chns_params* params, chns_ctx** o
   if (!rc && hipMemset(c.sc, 0, sizeof(DevScalars)) != hipSuccess) rc = hip_fail(hipErrorUnknown, "memset");
   if (!rc && hipHostMalloc((void**)&c.sc_host, sizeof(DevScalars), hipHostMallocDefault) != hipSuccess)
     rc = hip_fail(hipErrorOutOfMemory, "hipHostMalloc");
+  if (!rc && hipHostMalloc((void**)&c.flag_host, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess)
+    rc = hip_fail(hipErrorOutOfMemory, "hipHostMalloc");
+  if (!rc) c.flag_host[0] = c.flag_host[1] = 0;
   if (!rc && hipStreamCreateWithFlags(&c.work, hipStreamNonBlocking) != hipSuccess)
     rc = hip_fail(hipErrorUnknown, "hipStreamCreateWithFlags");
   if (!rc && hipEventCreateWithFlags(&c.ev_in, hipEventDisableTiming) != hipSuccess)

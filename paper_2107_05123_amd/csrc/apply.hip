@@ -489,9 +489,11 @@ __device__ __forceinline__ double wave_sum(double v) {
 // along the last axis.  WHOLE: every node of the brick is gathered into LDS
 // up front (all loads in flight together); otherwise a three-layer LDS ring
 // is refilled from registers two layers ahead.  STRUCT: uniform mesh with
-// lexicographic node numbers, indices computed from the brick anchor.
+// lexicographic node numbers, 32-bit offsets computed from the brick anchor.
+// The layer march is unrolled for the small scalar forms (pressure, mass):
+// ring slots, carries and node offsets become constants.
 template <int DIM, int B, typename T, int OP, bool WHOLE, bool STRUCT>
-__global__ __launch_bounds__(64) void k_brick(BrickArgs<T> a) {
+__device__ __forceinline__ void brick_body(const BrickArgs<T>& a) {
   using TR = Traits<OP, DIM>;
   constexpr int NI = TR::NI, NCF = TR::NCF, NO = TR::NO, NV = NI + NCF;
   constexpr int NIa = NI > 0 ? NI : 1, NCa = NCF > 0 ? NCF : 1;
@@ -512,7 +514,7 @@ __global__ __launch_bounds__(64) void k_brick(BrickArgs<T> a) {
   const int ix = ll % B, iy = DIM == 3 ? ll / B : 0;
   const int32_t* tab = a.table + (active ? brick : 0) * (int64_t)(NL * (B + 1));
   const int lev = active ? a.level[brick] : 0;
-  int64_t base = 0;
+  int32_t base = 0;
   int32_t ax = 0, ay = 0, az = 0;
   if constexpr (STRUCT) {
     if (active) {
@@ -520,13 +522,13 @@ __global__ __launch_bounds__(64) void k_brick(BrickArgs<T> a) {
       ay = a.anchor[3 * brick + 1];
       az = a.anchor[3 * brick + 2];
     }
-    base = DIM == 3 ? ax + ay * a.sy + az * a.sz : ax + ay * a.sy;
+    base = DIM == 3 ? ax + ay * (int32_t)a.sy + az * (int32_t)a.sz : ax + ay * (int32_t)a.sy;
   }
   // index of layer-z node p (STRUCT) or its table entry
   auto entry = [&](int z, int p) -> int64_t {
     if constexpr (STRUCT) {
       const int jx = p % (B + 1), jy = DIM == 3 ? p / (B + 1) : 0;
-      return DIM == 3 ? base + jx + jy * a.sy + z * a.sz : base + jx + z * a.sy;
+      return DIM == 3 ? base + jx + jy * (int32_t)a.sy + z * (int32_t)a.sz : base + jx + z * (int32_t)a.sy;
     } else {
       return tab[z * NL + p];
     }
@@ -542,9 +544,9 @@ __global__ __launch_bounds__(64) void k_brick(BrickArgs<T> a) {
         if constexpr (TR::MASK) {
           if (on_wall(z, p)) return T(0);
         }
-        return a.x[f * a.n + e];
+        return (a.x + f * a.n)[(int32_t)e];
       }
-      return a.cf[f - NI][e];
+      return a.cf[f - NI][(int32_t)e];
     } else {
       if (f < NI) return gather<T, TR::MASK>(a.x + f * a.n, a.wall, a.hang, (int32_t)e);
       return gather<T, false>(a.cf[f - NI], nullptr, a.hang, (int32_t)e);
@@ -572,11 +574,15 @@ __global__ __launch_bounds__(64) void k_brick(BrickArgs<T> a) {
   // -------- layered pipeline state (entries three layers ahead, values two)
   int64_t ent[KL];
   T val[KL][NV];
+  // table meshes read the node entries one layer ahead of the values;
+  // structured meshes compute them where they are used
   auto load_entries = [&](int z) {
+    if constexpr (!STRUCT) {
 #pragma unroll
-    for (int k = 0; k < KL; ++k) {
-      const int p = ll + k * LPB;
-      ent[k] = (active && z <= B && p < NL) ? entry(z, p) : 0;
+      for (int k = 0; k < KL; ++k) {
+        const int p = ll + k * LPB;
+        ent[k] = (active && z <= B && p < NL) ? entry(z, p) : 0;
+      }
     }
   };
   auto gather_vals = [&](int z) {
@@ -584,8 +590,9 @@ __global__ __launch_bounds__(64) void k_brick(BrickArgs<T> a) {
     for (int k = 0; k < KL; ++k) {
       const int p = ll + k * LPB;
       if (active && z <= B && p < NL) {
+        const int64_t e = STRUCT ? entry(z, p) : ent[k];
 #pragma unroll
-        for (int f = 0; f < NV; ++f) val[k][f] = value(f, ent[k], z, p);
+        for (int f = 0; f < NV; ++f) val[k][f] = value(f, e, z, p);
       }
     }
   };
@@ -718,6 +725,8 @@ __global__ __launch_bounds__(64) void k_brick(BrickArgs<T> a) {
     }
   };
   if (active) read_half(0, 1);
+  constexpr int kUnroll = (OP == K_PP || OP == K_MASS) ? B : 1;
+#pragma unroll kUnroll
   for (int ez = 0; ez < B; ++ez) {
     load_emit_entries(ez);
     if (active) {
@@ -762,9 +771,12 @@ __global__ __launch_bounds__(64) void k_brick(BrickArgs<T> a) {
         }
     }
     __syncthreads();
+    // values of layer ez + 2 (loads in flight since the previous layer) go to
+    // LDS before this layer's outputs are stored: waiting for those loads
+    // then does not also wait for the stores
+    if constexpr (!WHOLE) store_vals(ez + 2);
     emit_layer(ez);
     if constexpr (!WHOLE) {
-      store_vals(ez + 2);
       gather_vals(ez + 3);
       load_entries(ez + 4);
     }
@@ -786,6 +798,18 @@ __global__ __launch_bounds__(64) void k_brick(BrickArgs<T> a) {
     dot = wave_sum(dot);
     if (lane == 0) a.partials[blockIdx.x] = dot;
   }
+}
+
+template <int DIM, int B, typename T, int OP, bool WHOLE, bool STRUCT>
+__global__ __launch_bounds__(64) void k_brick(BrickArgs<T> a) {
+  brick_body<DIM, B, T, OP, WHOLE, STRUCT>(a);
+}
+// the pressure and mass forms (at most 128 VGPRs in FP64): capped at four
+// waves per SIMD, which keeps the FP32 instances from trading their latency
+// hiding for occupancy
+template <int DIM, int B, typename T, int OP, bool WHOLE, bool STRUCT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_brick_o4(BrickArgs<T> a) {
+  brick_body<DIM, B, T, OP, WHOLE, STRUCT>(a);
 }
 
 // Block-wide deterministic sum of one double (256 threads).
@@ -903,14 +927,20 @@ constexpr bool whole_fits() {
   return B <= 4 && (64 / LPB) * NL * (B + 1) * (TR::NI + TR::NCF) * (int)sizeof(T) <= 12 * 1024;
 }
 
+template <int DIM, int B, typename T, int OP, bool STRUCT>
+void launch_one(int64_t grid, hipStream_t s, const BrickArgs<T>& a) {
+  const dim3 g((unsigned)grid), blk(64);
+  constexpr bool W = whole_fits<DIM, B, T, OP>();
+  if constexpr (OP == K_PP || OP == K_MASS) k_brick_o4<DIM, B, T, OP, W, STRUCT><<<g, blk, 0, s>>>(a);
+  else k_brick<DIM, B, T, OP, W, STRUCT><<<g, blk, 0, s>>>(a);
+}
 template <int DIM, typename T, int OP, bool STRUCT>
 void launch_b(int B, int64_t grid, hipStream_t s, const BrickArgs<T>& a) {
-  const dim3 g((unsigned)grid), blk(64);
   switch (B) {
-    case 8: k_brick<DIM, 8, T, OP, whole_fits<DIM, 8, T, OP>(), STRUCT><<<g, blk, 0, s>>>(a); break;
-    case 4: k_brick<DIM, 4, T, OP, whole_fits<DIM, 4, T, OP>(), STRUCT><<<g, blk, 0, s>>>(a); break;
-    case 2: k_brick<DIM, 2, T, OP, whole_fits<DIM, 2, T, OP>(), STRUCT><<<g, blk, 0, s>>>(a); break;
-    default: k_brick<DIM, 1, T, OP, whole_fits<DIM, 1, T, OP>(), STRUCT><<<g, blk, 0, s>>>(a); break;
+    case 8: launch_one<DIM, 8, T, OP, STRUCT>(grid, s, a); break;
+    case 4: launch_one<DIM, 4, T, OP, STRUCT>(grid, s, a); break;
+    case 2: launch_one<DIM, 2, T, OP, STRUCT>(grid, s, a); break;
+    default: launch_one<DIM, 1, T, OP, STRUCT>(grid, s, a); break;
   }
 }
 

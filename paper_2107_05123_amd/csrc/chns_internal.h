@@ -123,6 +123,9 @@ struct Ctx {
   unsigned* counter = nullptr;  // ticket counters
   DevScalars* sc = nullptr;     // device scalars
   DevScalars* sc_host = nullptr;  // pinned mirror
+  // pinned host words {done, it} that the CG finaliser stores to directly
+  // (system scope), so convergence polling needs no copy on the stream
+  int* flag_host = nullptr;
 
   // work vectors (lazily allocated)
   double* w64[8] = {};

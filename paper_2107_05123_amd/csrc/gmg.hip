@@ -161,7 +161,8 @@ int upload_dm(Ctx& c, const HostMesh& m, DevMesh& d) {
   d.n_slots = m.n_slots;
   d.n_colors = m.n_colors;
   d.side = 1 << m.max_level;
-  d.structured = m.uniform && m.node_order == 0 && m.n_hanging == 0;
+  // structured kernels address nodes with 32-bit offsets
+  d.structured = m.uniform && m.node_order == 0 && m.n_hanging == 0 && m.n_indep < ((int64_t)1 << 31);
   int rc;
   for (int k = 0; k < kBrickClasses; ++k) {
     const BrickClass& h = m.cls[k];

@@ -56,7 +56,8 @@ enum FinMode { FIN_STORE = 0, FIN_CG_INIT = 1, FIN_CG_UPDATE = 2, FIN_FCG_UPDATE
 // partials are read with many loads in flight.
 constexpr int kFinThreads = 1024;
 __global__ __launch_bounds__(kFinThreads) void k_finalize(const double* partials, int nparts, int nv, int mode,
-                                                          DevScalars* sc, double* out, int respect_done) {
+                                                          DevScalars* sc, double* out, int respect_done,
+                                                          int* flag_host) {
   __shared__ double sh[kFinThreads / 64];
   if (respect_done && sc->done) return;
   double tot[3] = {0.0, 0.0, 0.0};
@@ -99,6 +100,12 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const double* partials
     sc->beta = (mode == FIN_FCG_UPDATE ? tot[0] - tot[2] : tot[0]) / sc->rz_old;
     sc->it = sc->it + 1;
     sc->done = (tot[1] <= sc->tol2 || sc->it >= sc->max_it || !(tot[1] == tot[1])) ? 1 : 0;
+  }
+  if (flag_host && mode != FIN_STORE) {
+    // vector stores with system scope into pinned host memory; visible to
+    // the host once an event recorded after this kernel has completed
+    __hip_atomic_store(&flag_host[1], sc->it, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&flag_host[0], sc->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
@@ -294,7 +301,7 @@ __global__ void k_promote(const float* a, double* b, int64_t n) {
 }
 
 int fin(Ctx& c, hipStream_t s, unsigned nparts, int nv, int mode, double* out, int respect_done) {
-  k_finalize<<<1, kFinThreads, 0, s>>>(c.partials, (int)nparts, nv, mode, c.sc, out, respect_done);
+  k_finalize<<<1, kFinThreads, 0, s>>>(c.partials, (int)nparts, nv, mode, c.sc, out, respect_done, c.flag_host);
   CHNS_HIP(hipGetLastError());
   return CHNS_OK;
 }
@@ -331,38 +338,34 @@ int read_scalars(Ctx& c, hipStream_t s) {
 }
 
 // Host-side convergence polling that keeps the device busy: after each
-// iteration the device scalars are copied (async) into a pinned ring slot and
-// an event is recorded; the host only waits for the iteration `depth - 1`
-// behind the one it has just enqueued.  Iterations enqueued after
-// convergence are no-ops for the CG kernels (they test the flag).
+// iteration an event is recorded; the host only waits for the iteration
+// `depth - 1` behind the one it has just enqueued and then reads the done
+// flag that the finaliser stores into pinned host memory (the value of that
+// iteration or of a later one; done never returns to 0 within a solve).
+// Iterations enqueued after convergence are no-ops for the CG kernels (they
+// test the flag).
 struct Poller {
   Ctx& c;
   hipStream_t s;
   int depth;
   std::vector<hipEvent_t> ev;
-  DevScalars* ring = nullptr;
   Poller(Ctx& cc, hipStream_t ss, int d) : c(cc), s(ss), depth(d), ev(d, nullptr) {}
   ~Poller() {
     for (auto e : ev)
       if (e) (void)hipEventDestroy(e);
-    if (ring) (void)hipHostFree(ring);
   }
   int init() {
-    CHNS_HIP(hipHostMalloc((void**)&ring, sizeof(DevScalars) * depth, hipHostMallocDefault));
     for (auto& e : ev) CHNS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     return CHNS_OK;
   }
   int post(int it) {
-    const int k = it % depth;
-    CHNS_HIP(hipMemcpyAsync(&ring[k], c.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
-    CHNS_HIP(hipEventRecord(ev[k], s));
+    CHNS_HIP(hipEventRecord(ev[it % depth], s));
     return CHNS_OK;
   }
-  // wait for iteration `it` (already posted); returns its scalars
-  int wait(int it, DevScalars* out) {
-    const int k = it % depth;
-    CHNS_HIP(hipEventSynchronize(ev[k]));
-    *out = ring[k];
+  // wait for iteration `it` (already posted); true once the solve is done
+  int wait(int it, bool* done) {
+    CHNS_HIP(hipEventSynchronize(ev[it % depth]));
+    *done = __atomic_load_n(&c.flag_host[0], __ATOMIC_ACQUIRE) != 0;
     return CHNS_OK;
   }
 };
@@ -483,7 +486,7 @@ int pcg(Ctx& c, int op, const T* b, T* x, int pc, const T* dinv, bool flexible, 
   hipGraphExec_t exec = nullptr, exec_j = nullptr;
   if ((rc = get_graph(pc, &exec))) return rc;
   if (sched && (rc = get_graph(PCK_JACOBI_FLEX, &exec_j))) return rc;
-  DevScalars snap{};
+  bool done = false;
   int it = 0;
   while (true) {
     const bool jac = sched && (it + 1) % every != 0;
@@ -497,8 +500,8 @@ int pcg(Ctx& c, int op, const T* b, T* x, int pc, const T* dinv, bool flexible, 
     ++it;
     if (it >= max_it) break;
     if (it >= depth) {
-      if ((rc = poll.wait(it - depth, &snap))) return rc;
-      if (snap.done) break;
+      if ((rc = poll.wait(it - depth, &done))) return rc;
+      if (done) break;
     }
   }
   CHNS_HIP(hipStreamSynchronize(s));
