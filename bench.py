@@ -159,7 +159,7 @@ def load_traffic(tag, launches_ms):
     return d.get("bytes_per_launch")
 
 
-def profile_run(torch, with_solve=True):
+def profile_run(torch, with_solve=True, pc="jacobi"):
     """Fixed sequence for rocprofv3: copy of known size, FP64/FP32 applies, one solve."""
     mesh, ctx, phi_d, b, *_ = setup(torch)
     big = torch.empty(1 << 25, dtype=torch.float64, device="cuda")  # 256 MiB
@@ -175,7 +175,7 @@ def profile_run(torch, with_solve=True):
     torch.cuda.synchronize()
     it = 0
     if with_solve:
-        _, st = solve_once(torch, ctx, phi_d, b)
+        _, st = solve_once(torch, ctx, phi_d, b, pc=pc)
         it = st.iterations
     torch.cuda.synchronize()
     print(json.dumps({"profile_run": "done", "iterations": it, "copy_bytes": 2 * big.numel() * 8}))
@@ -359,7 +359,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-run", nargs="?", const="full", default=None,
                     help="fixed sequence for rocprofv3; 'applies' skips the solve (for counter passes), "
-                         "'chns' runs the CHNS applies, steps and network passes")
+                         "'gmg' solves with multigrid CG, 'chns' runs the CHNS applies, steps and network passes")
     ap.add_argument("--workload", default="uniform_l7", choices=("uniform_l7", "adaptive", "bubble_steps"),
                     help="uniform_l7: the benchmark line; adaptive: levels 5..--max-level band mesh solves; "
                          "bubble_steps: projection steps of the 3D rising bubble")
@@ -381,7 +381,8 @@ def main():
         profile_chns(torch)
         return
     if args.profile_run:
-        profile_run(torch, with_solve=args.profile_run != "applies")
+        profile_run(torch, with_solve=args.profile_run != "applies",
+                    pc="gmg" if args.profile_run == "gmg" else "jacobi")
         return
     mesh, ctx, phi_d, b, x_unit, phi, f, t_mesh = setup(torch)
     n = mesh.n_nodes

@@ -83,6 +83,10 @@ struct MgLevel {
   float* R_val32 = nullptr;
   int32_t *I_ptr = nullptr, *I_col = nullptr;
   double* I_val = nullptr;
+  // structured levels above the coarsest: the assembled operator as a
+  // (3^d)-point stencil, SoA [offset][node], offsets x fastest over -1..1
+  double* S64 = nullptr;
+  float* S32 = nullptr;
   // coarsest level: dense inverse of the rank-one regularised operator
   double* inv64 = nullptr;
   float* inv32 = nullptr;

@@ -10,6 +10,17 @@
 // operator regularised by (1/n) 1 1^T, which returns the mean-free solution
 // for a right-hand side in the range.  The cycle is symmetric, so it is a
 // fixed SPD preconditioner for CG.
+//
+// Uniform coarse levels (all of them below a uniform fine mesh, the levels
+// at or below the minimum level of an adaptive one) hold their operator
+// assembled as a 3^d-point stencil, computed once per phase field from the
+// same element integrals (2-point Gauss, 1/rho of the clamped phase field at
+// the Gauss points).  On them a smoothing sweep is one kernel (stencil
+// product and Jacobi update together; the two pre-smoothing sweeps from a
+// zero guess are one kernel), where the matrix-free path needs a brick
+// launch, a combine launch and an update launch: on levels of a few
+// thousand nodes every launch costs the same few microseconds, whatever its
+// size.
 #include <cmath>
 #include <cstring>
 
@@ -49,6 +60,10 @@ template <typename T>
 __global__ void k_jacobi(T* z, const T* r, const T* t, const T* dinv, T w, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
     z[i] += w * dinv[i] * (r[i] - t[i]);
+}
+template <typename T>
+__global__ void k_copy_t(const T* a, T* b, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) b[i] = a[i];
 }
 // t = r - t
 template <typename T>
@@ -138,6 +153,183 @@ __global__ void k_to32(const double* a, float* b, int64_t n) {
 __global__ void k_phase32(const double* a, float* b, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
     b[i] = (float)(1.0 + a[i]);
+}
+
+// ---- assembled stencils on uniform (structured) levels
+// Node (i, j, k) of a level with s cells per edge, lexicographic index
+// i + (s+1) (j + (s+1) k).  Row of node i: for each of the (up to) 2^d leaves
+// around it, the row of that leaf's matrix for the corner i occupies,
+//   K_ab = (h/2)^(d-2) sum_q c_q gradN_a(xi_q) . gradN_b(xi_q),
+// c_q = 1 / (alpha clamp(phi_q, -1, 1) + beta), phi_q = sum_b N_b(xi_q) phi_b,
+// reference trilinear (bilinear) N on [-1, 1]^d, Gauss points +-1/sqrt 3.
+template <int DIM>
+__global__ void k_stencil_pp(const double* __restrict__ phi, double alpha, double beta, int s, double* S64,
+                             float* S32, double* dinv64, float* dinv32) {
+  constexpr int NC = 1 << DIM, NS = DIM == 3 ? 27 : 9;
+  const int64_t s1 = s + 1;
+  const int64_t n = DIM == 3 ? s1 * s1 * s1 : s1 * s1;
+  const double g = 0.57735026918962576451;
+  const double hf = ldexp(1.0, -1) / s;  // h / 2
+  const double scale = DIM == 3 ? hf : 1.0;
+  for (int64_t node = (int64_t)blockIdx.x * kT + threadIdx.x; node < n; node += (int64_t)gridDim.x * kT) {
+    const int I = (int)(node % s1), J = (int)((node / s1) % s1), K = DIM == 3 ? (int)(node / (s1 * s1)) : 0;
+    double acc[NS];
+#pragma unroll
+    for (int o = 0; o < NS; ++o) acc[o] = 0.0;
+#pragma unroll
+    for (int e = 0; e < NC; ++e) {
+      // leaf anchor = node - (1 if the node is the leaf's upper corner in that axis)
+      const int ux = e & 1, uy = (e >> 1) & 1, uz = DIM == 3 ? (e >> 2) & 1 : 0;
+      const int ax = I - ux, ay = J - uy, az = K - uz;
+      if (ax < 0 || ax >= s || ay < 0 || ay >= s || (DIM == 3 && (az < 0 || az >= s))) continue;
+      double ph[NC];
+#pragma unroll
+      for (int b = 0; b < NC; ++b) {
+        const int bx = b & 1, by = (b >> 1) & 1, bz = DIM == 3 ? (b >> 2) & 1 : 0;
+        ph[b] = phi[((int64_t)(az + bz) * s1 + (ay + by)) * s1 + (ax + bx)];
+      }
+      // corner a of the node within the leaf: sign +1 on the upper side
+      const double sa[3] = {ux ? 1.0 : -1.0, uy ? 1.0 : -1.0, uz ? 1.0 : -1.0};
+      double row[NC];
+#pragma unroll
+      for (int b = 0; b < NC; ++b) row[b] = 0.0;
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        const double xq[3] = {(q & 1) ? g : -g, ((q >> 1) & 1) ? g : -g, DIM == 3 ? (((q >> 2) & 1) ? g : -g) : 0.0};
+        double pq = 0.0;
+        double gb[NC][DIM];
+#pragma unroll
+        for (int b = 0; b < NC; ++b) {
+          const double sb[3] = {(b & 1) ? 1.0 : -1.0, ((b >> 1) & 1) ? 1.0 : -1.0,
+                                DIM == 3 ? (((b >> 2) & 1) ? 1.0 : -1.0) : 0.0};
+          double f[3];
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) f[d] = 1.0 + sb[d] * xq[d];
+          const double nb = DIM == 3 ? f[0] * f[1] * f[2] / 8.0 : f[0] * f[1] / 4.0;
+          pq += nb * ph[b];
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) {
+            double t = sb[d] / (DIM == 3 ? 8.0 : 4.0);
+#pragma unroll
+            for (int d2 = 0; d2 < DIM; ++d2)
+              if (d2 != d) t *= f[d2];
+            gb[b][d] = t;
+          }
+        }
+        const double cq = 1.0 / (alpha * fmin(fmax(pq, -1.0), 1.0) + beta);
+        // gradient of N_a at q
+        double ga[DIM];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+          double t = sa[d] / (DIM == 3 ? 8.0 : 4.0);
+#pragma unroll
+          for (int d2 = 0; d2 < DIM; ++d2)
+            if (d2 != d) t *= 1.0 + sa[d2] * xq[d2];
+          ga[d] = t;
+        }
+#pragma unroll
+        for (int b = 0; b < NC; ++b) {
+          double dp = 0.0;
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) dp += ga[d] * gb[b][d];
+          row[b] += cq * dp;
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < NC; ++b) {
+        // neighbour offset in -1..1 per axis
+        const int ox = ax + (b & 1) - I, oy = ay + ((b >> 1) & 1) - J, oz = DIM == 3 ? az + ((b >> 2) & 1) - K : 0;
+        const int o = (ox + 1) + 3 * (oy + 1) + (DIM == 3 ? 9 * (oz + 1) : 0);
+        acc[o] += scale * row[b];
+      }
+    }
+#pragma unroll
+    for (int o = 0; o < NS; ++o) {
+      S64[o * n + node] = acc[o];
+      S32[o * n + node] = (float)acc[o];
+    }
+    constexpr int C = NS / 2;
+    dinv64[node] = 1.0 / acc[C];
+    dinv32[node] = (float)(1.0 / acc[C]);
+  }
+}
+
+// sum_o S_o(i) v(i + off_o) on a uniform level (zero stencil entries reach
+// no node outside the level; their indices are skipped)
+template <typename T, int DIM>
+__device__ __forceinline__ T stencil_row(const T* __restrict__ S, const T* __restrict__ v, int64_t node, int64_t n,
+                                         int I, int J, int K, int s) {
+  const int64_t s1 = s + 1;
+  T acc = T(0);
+#pragma unroll
+  for (int oz = (DIM == 3 ? -1 : 0); oz <= (DIM == 3 ? 1 : 0); ++oz) {
+    if (DIM == 3 && (K + oz < 0 || K + oz > s)) continue;
+#pragma unroll
+    for (int oy = -1; oy <= 1; ++oy) {
+      if (J + oy < 0 || J + oy > s) continue;
+#pragma unroll
+      for (int ox = -1; ox <= 1; ++ox) {
+        if (I + ox < 0 || I + ox > s) continue;
+        const int o = (ox + 1) + 3 * (oy + 1) + (DIM == 3 ? 9 * (oz + 1) : 0);
+        acc += S[o * n + node] * v[node + ox + oy * s1 + (DIM == 3 ? oz * s1 * s1 : 0)];
+      }
+    }
+  }
+  return acc;
+}
+template <int DIM>
+__device__ __forceinline__ void node_ijk(int64_t node, int s, int& I, int& J, int& K) {
+  const int64_t s1 = s + 1;
+  I = (int)(node % s1);
+  J = (int)((node / s1) % s1);
+  K = DIM == 3 ? (int)(node / (s1 * s1)) : 0;
+}
+// two damped-Jacobi sweeps from z = 0: z1 = w D^-1 r, z2 = z1 + w D^-1 (r - A z1)
+template <typename T, int DIM>
+__global__ void k_st_pre2(const T* __restrict__ S, const T* __restrict__ dinv, const T* __restrict__ r,
+                          T* __restrict__ z, T w, int s, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+    int I, J, K;
+    node_ijk<DIM>(i, s, I, J, K);
+    const int64_t s1 = s + 1;
+    T az = T(0);
+#pragma unroll
+    for (int oz = (DIM == 3 ? -1 : 0); oz <= (DIM == 3 ? 1 : 0); ++oz) {
+      if (DIM == 3 && (K + oz < 0 || K + oz > s)) continue;
+#pragma unroll
+      for (int oy = -1; oy <= 1; ++oy) {
+        if (J + oy < 0 || J + oy > s) continue;
+#pragma unroll
+        for (int ox = -1; ox <= 1; ++ox) {
+          if (I + ox < 0 || I + ox > s) continue;
+          const int o = (ox + 1) + 3 * (oy + 1) + (DIM == 3 ? 9 * (oz + 1) : 0);
+          const int64_t j = i + ox + oy * s1 + (DIM == 3 ? oz * s1 * s1 : 0);
+          az += S[o * n + i] * (w * dinv[j] * r[j]);
+        }
+      }
+    }
+    const T z1 = w * dinv[i] * r[i];
+    z[i] = z1 + w * dinv[i] * (r[i] - az);
+  }
+}
+// zo = zi + w D^-1 (r - A zi)
+template <typename T, int DIM>
+__global__ void k_st_sweep(const T* __restrict__ S, const T* __restrict__ dinv, const T* __restrict__ r,
+                           const T* __restrict__ zi, T* __restrict__ zo, T w, int s, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+    int I, J, K;
+    node_ijk<DIM>(i, s, I, J, K);
+    zo[i] = zi[i] + w * dinv[i] * (r[i] - stencil_row<T, DIM>(S, zi, i, n, I, J, K, s));
+  }
+}
+// t = A z
+template <typename T, int DIM>
+__global__ void k_st_apply(const T* __restrict__ S, const T* __restrict__ z, T* __restrict__ t, int s, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+    int I, J, K;
+    node_ijk<DIM>(i, s, I, J, K);
+    t[i] = stencil_row<T, DIM>(S, z, i, n, I, J, K, s);
+  }
 }
 
 template <typename T>
@@ -239,6 +431,7 @@ struct Prec<double> {
   static const double* Pv(MgLevel& L) { return L.P_val64; }
   static const double* Rv(MgLevel& L) { return L.R_val64; }
   static const double* inv(MgLevel& L) { return L.inv64; }
+  static const double* S(MgLevel& L) { return L.S64; }
   static double* fine_dinv(Multigrid& m) { return m.fine_dinv64; }
   static double* fine_t(Multigrid& m) { return m.fine_t64; }
 };
@@ -250,9 +443,68 @@ struct Prec<float> {
   static const float* Pv(MgLevel& L) { return L.P_val32; }
   static const float* Rv(MgLevel& L) { return L.R_val32; }
   static const float* inv(MgLevel& L) { return L.inv32; }
+  static const float* S(MgLevel& L) { return L.S32; }
   static float* fine_dinv(Multigrid& m) { return m.fine_dinv32; }
   static float* fine_t(Multigrid& m) { return m.fine_t32; }
 };
+
+template <typename T>
+int vcycle(Ctx& c, int k, const T* r, T* z, hipStream_t s);
+
+// V-cycle from a uniform coarse level k > 0 with an assembled stencil: the
+// same damped-Jacobi sweeps and transfers as the matrix-free levels, six
+// launches per level (two-sweep pre-smoothing, A z, restriction,
+// prolongation, two post-smoothing sweeps)
+template <typename T>
+int vcycle_stencil(Ctx& c, int k, const T* r, T* z, hipStream_t s) {
+  using PR = Prec<T>;
+  Multigrid& mg = *c.mg;
+  MgLevel& L = mg.lv[k];
+  MgLevel& C = mg.lv[k + 1];
+  const int64_t n = L.dm.n;
+  const int side = L.dm.side, dim = L.dm.dim;
+  const T* S = PR::S(L);
+  const T* dinv = PR::dinv(L);
+  T* t = PR::v(L, 2);
+  T* z2 = PR::v(L, 3);
+  const T w = (T)mg.omega;
+  const unsigned g = blocks(n);
+  auto pre2 = [&]() {
+    if (dim == 3) k_st_pre2<T, 3><<<g, kT, 0, s>>>(S, dinv, r, z, w, side, n);
+    else k_st_pre2<T, 2><<<g, kT, 0, s>>>(S, dinv, r, z, w, side, n);
+  };
+  auto sweep = [&](const T* zi, T* zo) {
+    if (dim == 3) k_st_sweep<T, 3><<<g, kT, 0, s>>>(S, dinv, r, zi, zo, w, side, n);
+    else k_st_sweep<T, 2><<<g, kT, 0, s>>>(S, dinv, r, zi, zo, w, side, n);
+  };
+  // pre-smoothing: nu sweeps from a zero guess, result in z
+  if (mg.nu >= 2) {
+    pre2();
+    for (int it = 2; it < mg.nu; ++it) {
+      sweep(z, z2);
+      k_copy_t<T><<<g, kT, 0, s>>>(z2, z, n);
+    }
+  } else {
+    k_jacobi0<T><<<g, kT, 0, s>>>(z, r, dinv, w, n);
+  }
+  if (dim == 3) k_st_apply<T, 3><<<g, kT, 0, s>>>(S, z, t, side, n);
+  else k_st_apply<T, 2><<<g, kT, 0, s>>>(S, z, t, side, n);
+  T* rc_ = PR::v(C, 0);
+  T* zc = PR::v(C, 1);
+  k_restrict_s<T><<<blocks(C.dm.n), kT, 0, s>>>(r, t, rc_, C.dm.side, dim);
+  CHNS_HIP(hipGetLastError());
+  int rc;
+  if ((rc = vcycle<T>(c, k + 1, rc_, zc, s))) return rc;
+  k_prolong_s<T><<<g, kT, 0, s>>>(zc, z, C.dm.side, dim);
+  // post-smoothing: nu sweeps, ping-pong between z and z2, ending in z
+  for (int it = 0; it < mg.nu; ++it) {
+    if (it % 2 == 0) sweep(z, z2);
+    else sweep(z2, z);
+  }
+  if (mg.nu % 2) k_copy_t<T><<<g, kT, 0, s>>>(z2, z, n);
+  CHNS_HIP(hipGetLastError());
+  return CHNS_OK;
+}
 
 // z = V(r) on level k (k = 0 is the context's mesh)
 template <typename T>
@@ -274,6 +526,7 @@ int vcycle(Ctx& c, int k, const T* r, T* z, hipStream_t s) {
   const unsigned g = blocks(n);
   ApplyOut plain{};
   int rc;
+  if (k > 0 && mg.lv[k].S64) return vcycle_stencil<T>(c, k, r, z, s);
   k_jacobi0<T><<<g, kT, 0, s>>>(z, r, dinv, w, n);
   for (int it = 1; it < mg.nu; ++it) {
     if ((rc = launch_apply_lv(c, V, CHNS_OP_PRESSURE, PR::P, z, t, s, plain))) return rc;
@@ -373,6 +626,17 @@ int mg_build(Ctx& c) {
       }
     }
   }
+  for (size_t k = 1; k + 1 < mg->lv.size(); ++k) {
+    MgLevel& L = mg->lv[k];
+    if (!(L.dm.structured && mg->lv[k + 1].dm.structured)) continue;
+    const int64_t ns = (L.dm.dim == 3 ? 27 : 9) * L.dm.n;
+    L.S64 = (double*)c.dalloc(sizeof(double) * ns);
+    L.S32 = (float*)c.dalloc(sizeof(float) * ns);
+    if (!L.S64 || !L.S32) {
+      rc = CHNS_ENOMEM;
+      goto fail;
+    }
+  }
   {
     MgLevel& B = mg->lv.back();
     const int64_t n = B.dm.n;
@@ -430,7 +694,15 @@ int mg_setup(Ctx& c, hipStream_t s) {
       k_phase32<<<blocks(nk), kT, 0, st>>>(L.phi64, L.phi32, nk);
       CHNS_HIP(hipGetLastError());
       phi_f = L.phi64;
-      if (k + 1 < mg.lv.size()) {
+      if (L.S64) {
+        const double al = (c.prm.rho_plus - c.prm.rho_minus) / (2.0 * c.prm.rho_plus);
+        const double be = (c.prm.rho_plus + c.prm.rho_minus) / (2.0 * c.prm.rho_plus);
+        if (L.dm.dim == 3)
+          k_stencil_pp<3><<<blocks(nk), kT, 0, st>>>(L.phi64, al, be, L.dm.side, L.S64, L.S32, L.dinv64, L.dinv32);
+        else
+          k_stencil_pp<2><<<blocks(nk), kT, 0, st>>>(L.phi64, al, be, L.dm.side, L.S64, L.S32, L.dinv64, L.dinv32);
+        CHNS_HIP(hipGetLastError());
+      } else if (k + 1 < mg.lv.size()) {
         if ((e = launch_diagonal_lv(c, view(L), CHNS_OP_PRESSURE, CHNS_FP64, L.dinv64, true, L.v64[0], L.v64[3],
                                     st)))
           return e;
