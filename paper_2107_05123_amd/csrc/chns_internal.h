@@ -99,6 +99,8 @@ struct Multigrid {
   float* fine_dinv32 = nullptr;
   double* fine_t64 = nullptr;
   float* fine_t32 = nullptr;
+  // stencil of a uniform fine level (source of the first Galerkin product)
+  double* fine_S64 = nullptr;
   bool setup_valid = false;
   hipGraphExec_t setup_exec = nullptr;  // captured device part of the set-up
   int nu = 2;            // damped-Jacobi sweeps before and after the correction

@@ -246,11 +246,107 @@ __global__ void k_stencil_pp(const double* __restrict__ phi, double alpha, doubl
 #pragma unroll
     for (int o = 0; o < NS; ++o) {
       S64[o * n + node] = acc[o];
-      S32[o * n + node] = (float)acc[o];
+      if (S32) S32[o * n + node] = (float)acc[o];
     }
     constexpr int C = NS / 2;
-    dinv64[node] = 1.0 / acc[C];
-    dinv32[node] = (float)(1.0 / acc[C]);
+    if (dinv64) dinv64[node] = 1.0 / acc[C];
+    if (dinv32) dinv32[node] = (float)(1.0 / acc[C]);
+  }
+}
+
+// Galerkin coarse stencil R A P on a uniform level with sc cells per edge
+// from the stencil of the uniform level above (sf = 2 sc): P is the Q1
+// embedding (weight 1 at coincident nodes, 1/2 per axis at midpoints), R =
+// P^T.  A_c(I, J) = sum_i sum_j P(i, I) A(i, j) P(j, J) over the fine nodes
+// i around 2I and their stencil neighbours j, accumulated in a fixed order.
+// Outputs as k_stencil_pp (S32, dinv nullable); the coarse stencil is again
+// 3^d points because every such j has its parents J within one coarse cell
+// of I.
+template <int DIM>
+__global__ void k_rap_s(const double* __restrict__ Sf, int sc, double* Sc, float* S32, double* dinv64,
+                        float* dinv32) {
+  constexpr int NS = DIM == 3 ? 27 : 9;
+  const int sf = 2 * sc;
+  const int64_t c1 = sc + 1, f1 = sf + 1;
+  const int64_t nc = DIM == 3 ? c1 * c1 * c1 : c1 * c1;
+  const int64_t nf = DIM == 3 ? f1 * f1 * f1 : f1 * f1;
+  for (int64_t node = (int64_t)blockIdx.x * kT + threadIdx.x; node < nc; node += (int64_t)gridDim.x * kT) {
+    const int I = (int)(node % c1), J = (int)((node / c1) % c1), K = DIM == 3 ? (int)(node / (c1 * c1)) : 0;
+    double acc[NS];
+#pragma unroll
+    for (int o = 0; o < NS; ++o) acc[o] = 0.0;
+    // fine node i = 2I + a, neighbour j = i + o; with t = a + o the parents
+    // of j lie at I + floor(t/2) .. I + floor((t+1)/2) (one when t is even):
+    // all offsets are compile-time constants once the loops are unrolled
+#pragma unroll
+    for (int az = (DIM == 3 ? -1 : 0); az <= (DIM == 3 ? 1 : 0); ++az) {
+      const int iz = 2 * K + az;
+      if (DIM == 3 && (iz < 0 || iz > sf)) continue;
+#pragma unroll
+      for (int ay = -1; ay <= 1; ++ay) {
+        const int iy = 2 * J + ay;
+        if (iy < 0 || iy > sf) continue;
+#pragma unroll
+        for (int ax = -1; ax <= 1; ++ax) {
+          const int ix = 2 * I + ax;
+          if (ix < 0 || ix > sf) continue;
+          const double wi = (ax ? 0.5 : 1.0) * (ay ? 0.5 : 1.0) * (az ? 0.5 : 1.0);
+          const int64_t fi = DIM == 3 ? ((int64_t)iz * f1 + iy) * f1 + ix : (int64_t)iy * f1 + ix;
+#pragma unroll
+          for (int oz = (DIM == 3 ? -1 : 0); oz <= (DIM == 3 ? 1 : 0); ++oz) {
+            if (DIM == 3 && (iz + oz < 0 || iz + oz > sf)) continue;
+#pragma unroll
+            for (int oy = -1; oy <= 1; ++oy) {
+              if (iy + oy < 0 || iy + oy > sf) continue;
+#pragma unroll
+              for (int ox = -1; ox <= 1; ++ox) {
+                if (ix + ox < 0 || ix + ox > sf) continue;
+                const int o = (ox + 1) + 3 * (oy + 1) + (DIM == 3 ? 9 * (oz + 1) : 0);
+                const double v = wi * Sf[o * nf + fi];
+                const int tx = ax + ox, ty = ay + oy, tz = az + oz;
+                // floor(t / 2) for t in -2..2
+                const int xa = (tx + 2) / 2 - 1, xb = (tx + 3) / 2 - 1;
+                const int ya = (ty + 2) / 2 - 1, yb = (ty + 3) / 2 - 1;
+                const int za = DIM == 3 ? (tz + 2) / 2 - 1 : 0, zb = DIM == 3 ? (tz + 3) / 2 - 1 : 0;
+                const double w = (tx & 1 ? 0.5 : 1.0) * (ty & 1 ? 0.5 : 1.0) * (DIM == 3 && (tz & 1) ? 0.5 : 1.0);
+#pragma unroll
+                for (int pz = za; pz <= zb; ++pz)
+#pragma unroll
+                  for (int py = ya; py <= yb; ++py)
+#pragma unroll
+                    for (int px = xa; px <= xb; ++px)
+                      acc[(px + 1) + 3 * (py + 1) + (DIM == 3 ? 9 * (pz + 1) : 0)] += v * w;
+              }
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int o = 0; o < NS; ++o) {
+      Sc[o * nc + node] = acc[o];
+      if (S32) S32[o * nc + node] = (float)acc[o];
+    }
+    constexpr int C = NS / 2;
+    if (dinv64) dinv64[node] = 1.0 / acc[C];
+    if (dinv32) dinv32[node] = (float)(1.0 / acc[C]);
+  }
+}
+// dense n x n matrix (row-major) of a uniform level's stencil
+template <int DIM>
+__global__ void k_stencil_dense(const double* __restrict__ S, int s, double* M) {
+  constexpr int NS = DIM == 3 ? 27 : 9;
+  const int64_t s1 = s + 1;
+  const int64_t n = DIM == 3 ? s1 * s1 * s1 : s1 * s1;
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+    const int I = (int)(i % s1), J = (int)((i / s1) % s1), K = DIM == 3 ? (int)(i / (s1 * s1)) : 0;
+    for (int64_t j = 0; j < n; ++j) M[i * n + j] = 0.0;
+    for (int o = 0; o < NS; ++o) {
+      const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = DIM == 3 ? o / 9 - 1 : 0;
+      if (I + ox < 0 || I + ox > s || J + oy < 0 || J + oy > s) continue;
+      if (DIM == 3 && (K + oz < 0 || K + oz > s)) continue;
+      M[i * n + (i + ox + oy * s1 + (DIM == 3 ? oz * s1 * s1 : 0))] = S[o * n + i];
+    }
   }
 }
 
@@ -626,15 +722,32 @@ int mg_build(Ctx& c) {
       }
     }
   }
-  for (size_t k = 1; k + 1 < mg->lv.size(); ++k) {
-    MgLevel& L = mg->lv[k];
-    if (!(L.dm.structured && mg->lv[k + 1].dm.structured)) continue;
-    const int64_t ns = (L.dm.dim == 3 ? 27 : 9) * L.dm.n;
-    L.S64 = (double*)c.dalloc(sizeof(double) * ns);
-    L.S32 = (float*)c.dalloc(sizeof(float) * ns);
-    if (!L.S64 || !L.S32) {
-      rc = CHNS_ENOMEM;
-      goto fail;
+  // stencils: every uniform level above the coarsest whose next coarser
+  // level is uniform (stencil V-cycle); the uniform fine level and the
+  // uniform coarsest level when the level next to them has one (Galerkin
+  // products)
+  {
+    const size_t K = mg->lv.size() - 1;
+    for (size_t k = 1; k <= K; ++k) {
+      MgLevel& L = mg->lv[k];
+      if (!L.dm.structured) continue;
+      const bool finer_st = k == 1 ? c.dm.structured : mg->lv[k - 1].dm.structured;
+      const bool vcyc = k < K && mg->lv[k + 1].dm.structured;
+      if (!vcyc && !(k == K && finer_st)) continue;
+      const int64_t ns = (L.dm.dim == 3 ? 27 : 9) * L.dm.n;
+      L.S64 = (double*)c.dalloc(sizeof(double) * ns);
+      if (vcyc) L.S32 = (float*)c.dalloc(sizeof(float) * ns);
+      if (!L.S64 || (vcyc && !L.S32)) {
+        rc = CHNS_ENOMEM;
+        goto fail;
+      }
+    }
+    if (c.dm.structured && mg->lv[1].dm.structured) {
+      mg->fine_S64 = (double*)c.dalloc(sizeof(double) * (c.dm.dim == 3 ? 27 : 9) * c.dm.n);
+      if (!mg->fine_S64) {
+        rc = CHNS_ENOMEM;
+        goto fail;
+      }
     }
   }
   {
@@ -682,6 +795,17 @@ int mg_setup(Ctx& c, hipStream_t s) {
     if ((e = launch_diagonal_lv(c, fine_view(c), CHNS_OP_PRESSURE, CHNS_FP32, mg.fine_dinv32, true, c.w32[6],
                                 c.w32[7], st)))
       return e;
+    const double al = (c.prm.rho_plus - c.prm.rho_minus) / (2.0 * c.prm.rho_plus);
+    const double be = (c.prm.rho_plus + c.prm.rho_minus) / (2.0 * c.prm.rho_plus);
+    if (mg.fine_S64) {
+      if (c.dm.dim == 3)
+        k_stencil_pp<3><<<blocks(c.dm.n), kT, 0, st>>>(c.phi64, al, be, c.dm.side, mg.fine_S64, nullptr, nullptr,
+                                                        nullptr);
+      else
+        k_stencil_pp<2><<<blocks(c.dm.n), kT, 0, st>>>(c.phi64, al, be, c.dm.side, mg.fine_S64, nullptr, nullptr,
+                                                        nullptr);
+      CHNS_HIP(hipGetLastError());
+    }
     const double* phi_f = c.phi64;
     for (size_t k = 1; k < mg.lv.size(); ++k) {
       MgLevel& L = mg.lv[k];
@@ -695,12 +819,20 @@ int mg_setup(Ctx& c, hipStream_t s) {
       CHNS_HIP(hipGetLastError());
       phi_f = L.phi64;
       if (L.S64) {
-        const double al = (c.prm.rho_plus - c.prm.rho_minus) / (2.0 * c.prm.rho_plus);
-        const double be = (c.prm.rho_plus + c.prm.rho_minus) / (2.0 * c.prm.rho_plus);
-        if (L.dm.dim == 3)
-          k_stencil_pp<3><<<blocks(nk), kT, 0, st>>>(L.phi64, al, be, L.dm.side, L.S64, L.S32, L.dinv64, L.dinv32);
-        else
-          k_stencil_pp<2><<<blocks(nk), kT, 0, st>>>(L.phi64, al, be, L.dm.side, L.S64, L.S32, L.dinv64, L.dinv32);
+        // Galerkin product of the uniform level above when it has a stencil,
+        // else the rediscretised operator
+        const double* Sf = k == 1 ? mg.fine_S64 : mg.lv[k - 1].S64;
+        const bool last = k + 1 == mg.lv.size();
+        double* d64 = last ? nullptr : L.dinv64;
+        float* d32 = last ? nullptr : L.dinv32;
+        if (Sf) {
+          if (L.dm.dim == 3) k_rap_s<3><<<blocks(nk), kT, 0, st>>>(Sf, L.dm.side, L.S64, L.S32, d64, d32);
+          else k_rap_s<2><<<blocks(nk), kT, 0, st>>>(Sf, L.dm.side, L.S64, L.S32, d64, d32);
+        } else if (L.dm.dim == 3) {
+          k_stencil_pp<3><<<blocks(nk), kT, 0, st>>>(L.phi64, al, be, L.dm.side, L.S64, L.S32, d64, d32);
+        } else {
+          k_stencil_pp<2><<<blocks(nk), kT, 0, st>>>(L.phi64, al, be, L.dm.side, L.S64, L.S32, d64, d32);
+        }
         CHNS_HIP(hipGetLastError());
       } else if (k + 1 < mg.lv.size()) {
         if ((e = launch_diagonal_lv(c, view(L), CHNS_OP_PRESSURE, CHNS_FP64, L.dinv64, true, L.v64[0], L.v64[3],
@@ -710,6 +842,12 @@ int mg_setup(Ctx& c, hipStream_t s) {
                                     st)))
           return e;
       }
+    }
+    if (B.S64) {
+      if (B.dm.dim == 3) k_stencil_dense<3><<<blocks(n), kT, 0, st>>>(B.S64, B.dm.side, B.dense);
+      else k_stencil_dense<2><<<blocks(n), kT, 0, st>>>(B.S64, B.dm.side, B.dense);
+      CHNS_HIP(hipGetLastError());
+      return CHNS_OK;
     }
     ApplyOut plain{};
     for (int j = 0; j < n; ++j) {
