@@ -87,6 +87,7 @@ struct MgLevel {
   // (3^d)-point stencil, SoA [offset][node], offsets x fastest over -1..1
   double* S64 = nullptr;
   float* S32 = nullptr;
+  double* E64 = nullptr;  // element matrices of those levels (NC^2 per leaf)
   // coarsest level: dense inverse of the rank-one regularised operator
   double* inv64 = nullptr;
   float* inv32 = nullptr;
@@ -99,8 +100,12 @@ struct Multigrid {
   float* fine_dinv32 = nullptr;
   double* fine_t64 = nullptr;
   float* fine_t32 = nullptr;
-  // stencil of a uniform fine level (source of the first Galerkin product)
-  double* fine_S64 = nullptr;
+  // reference tables of the element-matrix Galerkin products (device):
+  // G (q, a, b), P (c, b, A), H (c, q, A, B); H only when the fine level is
+  // uniform and feeds the first coarse level directly
+  double* tab_G = nullptr;
+  double* tab_P = nullptr;
+  double* tab_H = nullptr;
   bool setup_valid = false;
   hipGraphExec_t setup_exec = nullptr;  // captured device part of the set-up
   int nu = 2;            // damped-Jacobi sweeps before and after the correction

@@ -155,92 +155,149 @@ __global__ void k_phase32(const double* a, float* b, int64_t n) {
     b[i] = (float)(1.0 + a[i]);
 }
 
-// ---- assembled stencils on uniform (structured) levels
-// Node (i, j, k) of a level with s cells per edge, lexicographic index
-// i + (s+1) (j + (s+1) k).  Row of node i: for each of the (up to) 2^d leaves
-// around it, the row of that leaf's matrix for the corner i occupies,
-//   K_ab = (h/2)^(d-2) sum_q c_q gradN_a(xi_q) . gradN_b(xi_q),
-// c_q = 1 / (alpha clamp(phi_q, -1, 1) + beta), phi_q = sum_b N_b(xi_q) phi_b,
-// reference trilinear (bilinear) N on [-1, 1]^d, Gauss points +-1/sqrt 3.
+// ---- assembled operators on uniform (structured) levels
+// Elements of a uniform level with s cells per edge are numbered by anchor,
+// x fastest; nodes i + (s+1) (j + (s+1) k).  Corner, Gauss point and child
+// indices use bit d for axis d.  Element matrices (NC x NC, row-major):
+//   K_ab = (h/2)^(d-2) sum_q c_q G_q(a, b),  G_q(a, b) = gradN_a . gradN_b at
+//   the reference Gauss point q (+-1/sqrt 3 per axis), c_q = 1 / (alpha
+//   clamp(phi_q, -1, 1) + beta), phi_q interpolated from the corners;
+// a Galerkin coarse element (R A P with P the Q1 embedding, R = P^T) is
+//   K_C = sum_children P_c^T K_c P_c, P_c(b, A) the weight of coarse corner A
+//   at corner b of child c,
+// which for children taken straight from the fine phase field is
+//   K_C = (h_f/2)^(d-2) sum_{c,q} c_{c,q} H_{c,q},  H_{c,q} = P_c^T G_q P_c.
+// Tables G (q, a, b), P (c, b, A) and H (c, q, A, B) are built on the host.
+
+__device__ __forceinline__ double coef_at(const double* ph, int q, int dim, double alpha, double beta) {
+  // phase field at reference Gauss point q from the corner values
+  const double g = 0.57735026918962576451;
+  const int nc = 1 << dim;
+  double v = 0.0;
+  for (int b = 0; b < nc; ++b) {
+    double w = 1.0;
+    for (int d = 0; d < dim; ++d) {
+      const double sb = ((b >> d) & 1) ? 1.0 : -1.0, xq = ((q >> d) & 1) ? g : -g;
+      w *= 0.5 * (1.0 + sb * xq);
+    }
+    v += w * ph[b];
+  }
+  return 1.0 / (alpha * fmin(fmax(v, -1.0), 1.0) + beta);
+}
+
+// element matrices of a uniform level from its own phase field
+// (one wave per element, lane (a, b) one entry)
 template <int DIM>
-__global__ void k_stencil_pp(const double* __restrict__ phi, double alpha, double beta, int s, double* S64,
-                             float* S32, double* dinv64, float* dinv32) {
-  constexpr int NC = 1 << DIM, NS = DIM == 3 ? 27 : 9;
+__global__ __launch_bounds__(64) void k_el_rediscr(const double* __restrict__ phi, int s, const double* __restrict__ Gt,
+                                                   double alpha, double beta, double scale, double* E) {
+  constexpr int NC = 1 << DIM, NE = NC * NC;
+  __shared__ double cq[NC];
+  const int64_t e = blockIdx.x;
+  const int64_t s1 = s + 1;
+  const int X = (int)(e % s), Y = (int)((e / s) % s), Z = DIM == 3 ? (int)(e / ((int64_t)s * s)) : 0;
+  const int t = threadIdx.x;
+  if (t < NC) {
+    double ph[NC];
+    for (int b = 0; b < NC; ++b)
+      ph[b] = phi[((int64_t)(Z + ((b >> 2) & 1)) * s1 + (Y + ((b >> 1) & 1))) * s1 + (X + (b & 1))];
+    cq[t] = coef_at(ph, t, DIM, alpha, beta);
+  }
+  __syncthreads();
+  if (t < NE) {
+    double acc = 0.0;
+    for (int q = 0; q < NC; ++q) acc += cq[q] * Gt[q * NE + t];
+    E[e * NE + t] = scale * acc;
+  }
+}
+
+// Galerkin element matrices of a uniform level (sc cells per edge) straight
+// from the phase field of the uniform level above (sf = 2 sc)
+template <int DIM>
+__global__ __launch_bounds__(64) void k_gal_phi(const double* __restrict__ phi, int sf, const double* __restrict__ Ht,
+                                                double alpha, double beta, double scale, double* E) {
+  constexpr int NC = 1 << DIM, NE = NC * NC;
+  __shared__ double cq[NE];
+  const int64_t e = blockIdx.x;
+  const int sc = sf / 2;
+  const int64_t f1 = sf + 1;
+  const int X = (int)(e % sc), Y = (int)((e / sc) % sc), Z = DIM == 3 ? (int)(e / ((int64_t)sc * sc)) : 0;
+  const int t = threadIdx.x;
+  if (t < NE) {
+    // lane t: child c = t / NC, Gauss point q = t % NC of that child
+    const int c = t / NC, q = t % NC;
+    const int cx = 2 * X + (c & 1), cy = 2 * Y + ((c >> 1) & 1), cz = DIM == 3 ? 2 * Z + ((c >> 2) & 1) : 0;
+    double ph[NC];
+    for (int b = 0; b < NC; ++b)
+      ph[b] = phi[((int64_t)(cz + ((b >> 2) & 1)) * f1 + (cy + ((b >> 1) & 1))) * f1 + (cx + (b & 1))];
+    cq[t] = coef_at(ph, q, DIM, alpha, beta);
+  }
+  __syncthreads();
+  if (t < NE) {
+    double acc = 0.0;
+    for (int k = 0; k < NE; ++k) acc += cq[k] * Ht[k * NE + t];
+    E[e * NE + t] = scale * acc;
+  }
+}
+
+// Galerkin element matrices of a uniform level from the element matrices of
+// the uniform level above: K_C = sum_c P_c^T K_c P_c (fixed child order)
+template <int DIM>
+__global__ __launch_bounds__(64) void k_gal_elem(const double* __restrict__ Ef, int sf, const double* __restrict__ Pt,
+                                                 double* E) {
+  constexpr int NC = 1 << DIM, NE = NC * NC;
+  __shared__ double K[NE], T[NE];
+  const int64_t e = blockIdx.x;
+  const int sc = sf / 2;
+  const int X = (int)(e % sc), Y = (int)((e / sc) % sc), Z = DIM == 3 ? (int)(e / ((int64_t)sc * sc)) : 0;
+  const int t = threadIdx.x;
+  const int r = t / NC, col = t % NC;
+  double acc = 0.0;
+  for (int c = 0; c < NC; ++c) {
+    const int64_t ce = (2 * X + (c & 1)) + (int64_t)sf * ((2 * Y + ((c >> 1) & 1)) +
+                                                          (DIM == 3 ? (int64_t)sf * (2 * Z + ((c >> 2) & 1)) : 0));
+    if (t < NE) K[t] = Ef[ce * NE + t];
+    __syncthreads();
+    // T = K_c P_c (row b = r, coarse column col)
+    if (t < NE) {
+      double v = 0.0;
+      for (int b2 = 0; b2 < NC; ++b2) v += K[r * NC + b2] * Pt[(c * NC + b2) * NC + col];
+      T[t] = v;
+    }
+    __syncthreads();
+    // K_C(A = r, B = col) += sum_b P_c(b, A) T(b, B)
+    if (t < NE)
+      for (int b = 0; b < NC; ++b) acc += Pt[(c * NC + b) * NC + r] * T[b * NC + col];
+    __syncthreads();
+  }
+  if (t < NE) E[e * NE + t] = acc;
+}
+
+// 3^d-point stencil (and inverse diagonal) of a uniform level from its
+// element matrices: node row = sum over the leaves around the node of the
+// leaf matrix row of the corner the node occupies (fixed leaf order)
+template <int DIM>
+__global__ void k_el_stencil(const double* __restrict__ E, int s, double* S64, float* S32, double* dinv64,
+                             float* dinv32) {
+  constexpr int NC = 1 << DIM, NE = NC * NC, NS = DIM == 3 ? 27 : 9;
   const int64_t s1 = s + 1;
   const int64_t n = DIM == 3 ? s1 * s1 * s1 : s1 * s1;
-  const double g = 0.57735026918962576451;
-  const double hf = ldexp(1.0, -1) / s;  // h / 2
-  const double scale = DIM == 3 ? hf : 1.0;
   for (int64_t node = (int64_t)blockIdx.x * kT + threadIdx.x; node < n; node += (int64_t)gridDim.x * kT) {
     const int I = (int)(node % s1), J = (int)((node / s1) % s1), K = DIM == 3 ? (int)(node / (s1 * s1)) : 0;
     double acc[NS];
 #pragma unroll
     for (int o = 0; o < NS; ++o) acc[o] = 0.0;
 #pragma unroll
-    for (int e = 0; e < NC; ++e) {
-      // leaf anchor = node - (1 if the node is the leaf's upper corner in that axis)
-      const int ux = e & 1, uy = (e >> 1) & 1, uz = DIM == 3 ? (e >> 2) & 1 : 0;
+    for (int u = 0; u < NC; ++u) {
+      // the node is the upper corner of the leaf along axis d where bit d of u is set
+      const int ux = u & 1, uy = (u >> 1) & 1, uz = DIM == 3 ? (u >> 2) & 1 : 0;
       const int ax = I - ux, ay = J - uy, az = K - uz;
       if (ax < 0 || ax >= s || ay < 0 || ay >= s || (DIM == 3 && (az < 0 || az >= s))) continue;
-      double ph[NC];
+      const int64_t e = ax + (int64_t)s * (ay + (DIM == 3 ? (int64_t)s * az : 0));
+      const double* row = E + e * NE + u * NC;
 #pragma unroll
       for (int b = 0; b < NC; ++b) {
-        const int bx = b & 1, by = (b >> 1) & 1, bz = DIM == 3 ? (b >> 2) & 1 : 0;
-        ph[b] = phi[((int64_t)(az + bz) * s1 + (ay + by)) * s1 + (ax + bx)];
-      }
-      // corner a of the node within the leaf: sign +1 on the upper side
-      const double sa[3] = {ux ? 1.0 : -1.0, uy ? 1.0 : -1.0, uz ? 1.0 : -1.0};
-      double row[NC];
-#pragma unroll
-      for (int b = 0; b < NC; ++b) row[b] = 0.0;
-#pragma unroll
-      for (int q = 0; q < NC; ++q) {
-        const double xq[3] = {(q & 1) ? g : -g, ((q >> 1) & 1) ? g : -g, DIM == 3 ? (((q >> 2) & 1) ? g : -g) : 0.0};
-        double pq = 0.0;
-        double gb[NC][DIM];
-#pragma unroll
-        for (int b = 0; b < NC; ++b) {
-          const double sb[3] = {(b & 1) ? 1.0 : -1.0, ((b >> 1) & 1) ? 1.0 : -1.0,
-                                DIM == 3 ? (((b >> 2) & 1) ? 1.0 : -1.0) : 0.0};
-          double f[3];
-#pragma unroll
-          for (int d = 0; d < DIM; ++d) f[d] = 1.0 + sb[d] * xq[d];
-          const double nb = DIM == 3 ? f[0] * f[1] * f[2] / 8.0 : f[0] * f[1] / 4.0;
-          pq += nb * ph[b];
-#pragma unroll
-          for (int d = 0; d < DIM; ++d) {
-            double t = sb[d] / (DIM == 3 ? 8.0 : 4.0);
-#pragma unroll
-            for (int d2 = 0; d2 < DIM; ++d2)
-              if (d2 != d) t *= f[d2];
-            gb[b][d] = t;
-          }
-        }
-        const double cq = 1.0 / (alpha * fmin(fmax(pq, -1.0), 1.0) + beta);
-        // gradient of N_a at q
-        double ga[DIM];
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-          double t = sa[d] / (DIM == 3 ? 8.0 : 4.0);
-#pragma unroll
-          for (int d2 = 0; d2 < DIM; ++d2)
-            if (d2 != d) t *= 1.0 + sa[d2] * xq[d2];
-          ga[d] = t;
-        }
-#pragma unroll
-        for (int b = 0; b < NC; ++b) {
-          double dp = 0.0;
-#pragma unroll
-          for (int d = 0; d < DIM; ++d) dp += ga[d] * gb[b][d];
-          row[b] += cq * dp;
-        }
-      }
-#pragma unroll
-      for (int b = 0; b < NC; ++b) {
-        // neighbour offset in -1..1 per axis
-        const int ox = ax + (b & 1) - I, oy = ay + ((b >> 1) & 1) - J, oz = DIM == 3 ? az + ((b >> 2) & 1) - K : 0;
-        const int o = (ox + 1) + 3 * (oy + 1) + (DIM == 3 ? 9 * (oz + 1) : 0);
-        acc[o] += scale * row[b];
+        const int ox = (b & 1) - ux, oy = ((b >> 1) & 1) - uy, oz = DIM == 3 ? ((b >> 2) & 1) - uz : 0;
+        acc[(ox + 1) + 3 * (oy + 1) + (DIM == 3 ? 9 * (oz + 1) : 0)] += row[b];
       }
     }
 #pragma unroll
@@ -254,84 +311,30 @@ __global__ void k_stencil_pp(const double* __restrict__ phi, double alpha, doubl
   }
 }
 
-// Galerkin coarse stencil R A P on a uniform level with sc cells per edge
-// from the stencil of the uniform level above (sf = 2 sc): P is the Q1
-// embedding (weight 1 at coincident nodes, 1/2 per axis at midpoints), R =
-// P^T.  A_c(I, J) = sum_i sum_j P(i, I) A(i, j) P(j, J) over the fine nodes
-// i around 2I and their stencil neighbours j, accumulated in a fixed order.
-// Outputs as k_stencil_pp (S32, dinv nullable); the coarse stencil is again
-// 3^d points because every such j has its parents J within one coarse cell
-// of I.
+// inverse diagonal of a uniform fine level straight from its phase field
 template <int DIM>
-__global__ void k_rap_s(const double* __restrict__ Sf, int sc, double* Sc, float* S32, double* dinv64,
-                        float* dinv32) {
-  constexpr int NS = DIM == 3 ? 27 : 9;
-  const int sf = 2 * sc;
-  const int64_t c1 = sc + 1, f1 = sf + 1;
-  const int64_t nc = DIM == 3 ? c1 * c1 * c1 : c1 * c1;
-  const int64_t nf = DIM == 3 ? f1 * f1 * f1 : f1 * f1;
-  for (int64_t node = (int64_t)blockIdx.x * kT + threadIdx.x; node < nc; node += (int64_t)gridDim.x * kT) {
-    const int I = (int)(node % c1), J = (int)((node / c1) % c1), K = DIM == 3 ? (int)(node / (c1 * c1)) : 0;
-    double acc[NS];
-#pragma unroll
-    for (int o = 0; o < NS; ++o) acc[o] = 0.0;
-    // fine node i = 2I + a, neighbour j = i + o; with t = a + o the parents
-    // of j lie at I + floor(t/2) .. I + floor((t+1)/2) (one when t is even):
-    // all offsets are compile-time constants once the loops are unrolled
-#pragma unroll
-    for (int az = (DIM == 3 ? -1 : 0); az <= (DIM == 3 ? 1 : 0); ++az) {
-      const int iz = 2 * K + az;
-      if (DIM == 3 && (iz < 0 || iz > sf)) continue;
-#pragma unroll
-      for (int ay = -1; ay <= 1; ++ay) {
-        const int iy = 2 * J + ay;
-        if (iy < 0 || iy > sf) continue;
-#pragma unroll
-        for (int ax = -1; ax <= 1; ++ax) {
-          const int ix = 2 * I + ax;
-          if (ix < 0 || ix > sf) continue;
-          const double wi = (ax ? 0.5 : 1.0) * (ay ? 0.5 : 1.0) * (az ? 0.5 : 1.0);
-          const int64_t fi = DIM == 3 ? ((int64_t)iz * f1 + iy) * f1 + ix : (int64_t)iy * f1 + ix;
-#pragma unroll
-          for (int oz = (DIM == 3 ? -1 : 0); oz <= (DIM == 3 ? 1 : 0); ++oz) {
-            if (DIM == 3 && (iz + oz < 0 || iz + oz > sf)) continue;
-#pragma unroll
-            for (int oy = -1; oy <= 1; ++oy) {
-              if (iy + oy < 0 || iy + oy > sf) continue;
-#pragma unroll
-              for (int ox = -1; ox <= 1; ++ox) {
-                if (ix + ox < 0 || ix + ox > sf) continue;
-                const int o = (ox + 1) + 3 * (oy + 1) + (DIM == 3 ? 9 * (oz + 1) : 0);
-                const double v = wi * Sf[o * nf + fi];
-                const int tx = ax + ox, ty = ay + oy, tz = az + oz;
-                // floor(t / 2) for t in -2..2
-                const int xa = (tx + 2) / 2 - 1, xb = (tx + 3) / 2 - 1;
-                const int ya = (ty + 2) / 2 - 1, yb = (ty + 3) / 2 - 1;
-                const int za = DIM == 3 ? (tz + 2) / 2 - 1 : 0, zb = DIM == 3 ? (tz + 3) / 2 - 1 : 0;
-                const double w = (tx & 1 ? 0.5 : 1.0) * (ty & 1 ? 0.5 : 1.0) * (DIM == 3 && (tz & 1) ? 0.5 : 1.0);
-#pragma unroll
-                for (int pz = za; pz <= zb; ++pz)
-#pragma unroll
-                  for (int py = ya; py <= yb; ++py)
-#pragma unroll
-                    for (int px = xa; px <= xb; ++px)
-                      acc[(px + 1) + 3 * (py + 1) + (DIM == 3 ? 9 * (pz + 1) : 0)] += v * w;
-              }
-            }
-          }
-        }
-      }
+__global__ void k_diag_phi(const double* __restrict__ phi, int s, const double* __restrict__ Gt, double alpha,
+                           double beta, double scale, double* dinv64, float* dinv32) {
+  constexpr int NC = 1 << DIM, NE = NC * NC;
+  const int64_t s1 = s + 1;
+  const int64_t n = DIM == 3 ? s1 * s1 * s1 : s1 * s1;
+  for (int64_t node = (int64_t)blockIdx.x * kT + threadIdx.x; node < n; node += (int64_t)gridDim.x * kT) {
+    const int I = (int)(node % s1), J = (int)((node / s1) % s1), K = DIM == 3 ? (int)(node / (s1 * s1)) : 0;
+    double acc = 0.0;
+    for (int u = 0; u < NC; ++u) {
+      const int ux = u & 1, uy = (u >> 1) & 1, uz = DIM == 3 ? (u >> 2) & 1 : 0;
+      const int ax = I - ux, ay = J - uy, az = K - uz;
+      if (ax < 0 || ax >= s || ay < 0 || ay >= s || (DIM == 3 && (az < 0 || az >= s))) continue;
+      double ph[NC];
+      for (int b = 0; b < NC; ++b)
+        ph[b] = phi[((int64_t)(az + ((b >> 2) & 1)) * s1 + (ay + ((b >> 1) & 1))) * s1 + (ax + (b & 1))];
+      for (int q = 0; q < NC; ++q) acc += coef_at(ph, q, DIM, alpha, beta) * Gt[q * NE + u * NC + u];
     }
-#pragma unroll
-    for (int o = 0; o < NS; ++o) {
-      Sc[o * nc + node] = acc[o];
-      if (S32) S32[o * nc + node] = (float)acc[o];
-    }
-    constexpr int C = NS / 2;
-    if (dinv64) dinv64[node] = 1.0 / acc[C];
-    if (dinv32) dinv32[node] = (float)(1.0 / acc[C]);
+    dinv64[node] = 1.0 / (scale * acc);
+    dinv32[node] = (float)(1.0 / (scale * acc));
   }
 }
+
 // dense n x n matrix (row-major) of a uniform level's stencil
 template <int DIM>
 __global__ void k_stencil_dense(const double* __restrict__ S, int s, double* M) {
@@ -655,6 +658,54 @@ int vcycle(Ctx& c, int k, const T* r, T* z, hipStream_t s) {
 
 }  // namespace
 
+// Host: reference tables of the element-matrix Galerkin products (see the
+// kernels above); bit d of a corner / Gauss point / child index is axis d.
+void reference_tables(int dim, std::vector<double>& tg, std::vector<double>& tp, std::vector<double>& th) {
+  const int nc = 1 << dim, ne = nc * nc;
+  const double g = 0.57735026918962576451;
+  const double norm = dim == 3 ? 0.125 : 0.25;
+  tg.assign((size_t)nc * ne, 0.0);
+  for (int q = 0; q < nc; ++q) {
+    double grad[8][3];
+    for (int a = 0; a < nc; ++a)
+      for (int d = 0; d < dim; ++d) {
+        double v = norm * (((a >> d) & 1) ? 1.0 : -1.0);
+        for (int d2 = 0; d2 < dim; ++d2)
+          if (d2 != d) v *= 1.0 + (((a >> d2) & 1) ? 1.0 : -1.0) * (((q >> d2) & 1) ? g : -g);
+        grad[a][d] = v;
+      }
+    for (int a = 0; a < nc; ++a)
+      for (int b = 0; b < nc; ++b) {
+        double v = 0.0;
+        for (int d = 0; d < dim; ++d) v += grad[a][d] * grad[b][d];
+        tg[(size_t)q * ne + a * nc + b] = v;
+      }
+  }
+  // P_c(b, A): fine position c_d + b_d in {0, 1, 2} against coarse corner A_d
+  tp.assign((size_t)nc * ne, 0.0);
+  for (int c = 0; c < nc; ++c)
+    for (int b = 0; b < nc; ++b)
+      for (int A = 0; A < nc; ++A) {
+        double w = 1.0;
+        for (int d = 0; d < dim; ++d) {
+          const int f = ((c >> d) & 1) + ((b >> d) & 1), ad = (A >> d) & 1;
+          w *= f == 1 ? 0.5 : ((f == 0) == (ad == 0) ? 1.0 : 0.0);
+        }
+        tp[((size_t)c * nc + b) * nc + A] = w;
+      }
+  th.assign((size_t)ne * ne, 0.0);
+  for (int c = 0; c < nc; ++c)
+    for (int q = 0; q < nc; ++q)
+      for (int A = 0; A < nc; ++A)
+        for (int B = 0; B < nc; ++B) {
+          double v = 0.0;
+          for (int a = 0; a < nc; ++a)
+            for (int b = 0; b < nc; ++b)
+              v += tp[((size_t)c * nc + a) * nc + A] * tg[(size_t)q * ne + a * nc + b] * tp[((size_t)c * nc + b) * nc + B];
+          th[(size_t)(c * nc + q) * ne + A * nc + B] = v;
+        }
+}
+
 int mg_build(Ctx& c) {
   if (c.mg) return CHNS_OK;
   const HostMesh& f = *c.host;
@@ -722,10 +773,10 @@ int mg_build(Ctx& c) {
       }
     }
   }
-  // stencils: every uniform level above the coarsest whose next coarser
-  // level is uniform (stencil V-cycle); the uniform fine level and the
-  // uniform coarsest level when the level next to them has one (Galerkin
-  // products)
+  // stencils and element matrices: every uniform level above the coarsest
+  // whose next coarser level is uniform (stencil V-cycle), and the uniform
+  // coarsest level when the level above it is uniform (dense matrix from
+  // the Galerkin product)
   {
     const size_t K = mg->lv.size() - 1;
     for (size_t k = 1; k <= K; ++k) {
@@ -735,20 +786,19 @@ int mg_build(Ctx& c) {
       const bool vcyc = k < K && mg->lv[k + 1].dm.structured;
       if (!vcyc && !(k == K && finer_st)) continue;
       const int64_t ns = (L.dm.dim == 3 ? 27 : 9) * L.dm.n;
+      const int64_t ne = (int64_t)1 << (L.dm.dim * L.host.max_level);
       L.S64 = (double*)c.dalloc(sizeof(double) * ns);
+      L.E64 = (double*)c.dalloc(sizeof(double) * ne * (L.dm.dim == 3 ? 64 : 16));
       if (vcyc) L.S32 = (float*)c.dalloc(sizeof(float) * ns);
-      if (!L.S64 || (vcyc && !L.S32)) {
+      if (!L.S64 || !L.E64 || (vcyc && !L.S32)) {
         rc = CHNS_ENOMEM;
         goto fail;
       }
     }
-    if (c.dm.structured && mg->lv[1].dm.structured) {
-      mg->fine_S64 = (double*)c.dalloc(sizeof(double) * (c.dm.dim == 3 ? 27 : 9) * c.dm.n);
-      if (!mg->fine_S64) {
-        rc = CHNS_ENOMEM;
-        goto fail;
-      }
-    }
+    std::vector<double> tg, tp, th;
+    reference_tables(c.dm.dim, tg, tp, th);
+    if ((rc = upload(c, &mg->tab_G, tg)) || (rc = upload(c, &mg->tab_P, tp))) goto fail;
+    if (c.dm.structured && mg->lv[1].E64 && (rc = upload(c, &mg->tab_H, th))) goto fail;
   }
   {
     MgLevel& B = mg->lv.back();
@@ -789,22 +839,32 @@ int mg_setup(Ctx& c, hipStream_t s) {
   const int n = (int)B.dm.n;
   auto device_part = [&](hipStream_t st) -> int {
     int e;
-    if ((e = launch_diagonal_lv(c, fine_view(c), CHNS_OP_PRESSURE, CHNS_FP64, mg.fine_dinv64, true, c.w64[6],
-                                c.w64[7], st)))
-      return e;
-    if ((e = launch_diagonal_lv(c, fine_view(c), CHNS_OP_PRESSURE, CHNS_FP32, mg.fine_dinv32, true, c.w32[6],
-                                c.w32[7], st)))
-      return e;
     const double al = (c.prm.rho_plus - c.prm.rho_minus) / (2.0 * c.prm.rho_plus);
     const double be = (c.prm.rho_plus + c.prm.rho_minus) / (2.0 * c.prm.rho_plus);
-    if (mg.fine_S64) {
-      if (c.dm.dim == 3)
-        k_stencil_pp<3><<<blocks(c.dm.n), kT, 0, st>>>(c.phi64, al, be, c.dm.side, mg.fine_S64, nullptr, nullptr,
-                                                        nullptr);
-      else
-        k_stencil_pp<2><<<blocks(c.dm.n), kT, 0, st>>>(c.phi64, al, be, c.dm.side, mg.fine_S64, nullptr, nullptr,
-                                                        nullptr);
+    const int dim = c.dm.dim;
+    // (h/2)^(d-2) of a uniform level with s cells per edge
+    auto lscale = [&](int s) { return dim == 3 ? 0.5 / s : 1.0; };
+    if (mg.tab_H) {
+      // uniform fine level: inverse diagonal straight from the phase field,
+      // first coarse level's element matrices as Galerkin products
+      const unsigned gl = (unsigned)((int64_t)1 << (dim * (c.dm.max_level - 1)));
+      if (dim == 3) {
+        k_diag_phi<3><<<blocks(c.dm.n), kT, 0, st>>>(c.phi64, c.dm.side, mg.tab_G, al, be, lscale(c.dm.side),
+                                                      mg.fine_dinv64, mg.fine_dinv32);
+        k_gal_phi<3><<<gl, 64, 0, st>>>(c.phi64, c.dm.side, mg.tab_H, al, be, lscale(c.dm.side), mg.lv[1].E64);
+      } else {
+        k_diag_phi<2><<<blocks(c.dm.n), kT, 0, st>>>(c.phi64, c.dm.side, mg.tab_G, al, be, lscale(c.dm.side),
+                                                      mg.fine_dinv64, mg.fine_dinv32);
+        k_gal_phi<2><<<gl, 64, 0, st>>>(c.phi64, c.dm.side, mg.tab_H, al, be, lscale(c.dm.side), mg.lv[1].E64);
+      }
       CHNS_HIP(hipGetLastError());
+    } else {
+      if ((e = launch_diagonal_lv(c, fine_view(c), CHNS_OP_PRESSURE, CHNS_FP64, mg.fine_dinv64, true, c.w64[6],
+                                  c.w64[7], st)))
+        return e;
+      if ((e = launch_diagonal_lv(c, fine_view(c), CHNS_OP_PRESSURE, CHNS_FP32, mg.fine_dinv32, true, c.w32[6],
+                                  c.w32[7], st)))
+        return e;
     }
     const double* phi_f = c.phi64;
     for (size_t k = 1; k < mg.lv.size(); ++k) {
@@ -818,20 +878,24 @@ int mg_setup(Ctx& c, hipStream_t s) {
       k_phase32<<<blocks(nk), kT, 0, st>>>(L.phi64, L.phi32, nk);
       CHNS_HIP(hipGetLastError());
       phi_f = L.phi64;
-      if (L.S64) {
-        // Galerkin product of the uniform level above when it has a stencil,
-        // else the rediscretised operator
-        const double* Sf = k == 1 ? mg.fine_S64 : mg.lv[k - 1].S64;
+      if (L.E64) {
+        // element matrices: Galerkin products from the level above when it
+        // has them (done there), else rediscretised from the injected field
+        const bool from_above = k == 1 ? mg.tab_H != nullptr : mg.lv[k - 1].E64 != nullptr;
+        const unsigned ne = (unsigned)((int64_t)1 << (dim * L.host.max_level));
+        if (!from_above) {
+          if (dim == 3) k_el_rediscr<3><<<ne, 64, 0, st>>>(L.phi64, L.dm.side, mg.tab_G, al, be, lscale(L.dm.side), L.E64);
+          else k_el_rediscr<2><<<ne, 64, 0, st>>>(L.phi64, L.dm.side, mg.tab_G, al, be, lscale(L.dm.side), L.E64);
+        }
         const bool last = k + 1 == mg.lv.size();
         double* d64 = last ? nullptr : L.dinv64;
         float* d32 = last ? nullptr : L.dinv32;
-        if (Sf) {
-          if (L.dm.dim == 3) k_rap_s<3><<<blocks(nk), kT, 0, st>>>(Sf, L.dm.side, L.S64, L.S32, d64, d32);
-          else k_rap_s<2><<<blocks(nk), kT, 0, st>>>(Sf, L.dm.side, L.S64, L.S32, d64, d32);
-        } else if (L.dm.dim == 3) {
-          k_stencil_pp<3><<<blocks(nk), kT, 0, st>>>(L.phi64, al, be, L.dm.side, L.S64, L.S32, d64, d32);
-        } else {
-          k_stencil_pp<2><<<blocks(nk), kT, 0, st>>>(L.phi64, al, be, L.dm.side, L.S64, L.S32, d64, d32);
+        if (dim == 3) k_el_stencil<3><<<blocks(nk), kT, 0, st>>>(L.E64, L.dm.side, L.S64, L.S32, d64, d32);
+        else k_el_stencil<2><<<blocks(nk), kT, 0, st>>>(L.E64, L.dm.side, L.S64, L.S32, d64, d32);
+        if (!last && mg.lv[k + 1].E64) {
+          const unsigned nc = ne >> dim;
+          if (dim == 3) k_gal_elem<3><<<nc, 64, 0, st>>>(L.E64, L.dm.side, mg.tab_P, mg.lv[k + 1].E64);
+          else k_gal_elem<2><<<nc, 64, 0, st>>>(L.E64, L.dm.side, mg.tab_P, mg.lv[k + 1].E64);
         }
         CHNS_HIP(hipGetLastError());
       } else if (k + 1 < mg.lv.size()) {
