@@ -162,6 +162,52 @@ def load_traffic(tag, launches_ms):
     return d.get("bytes_per_launch")
 
 
+def summarize_stats(db, out_md, title, command, note, limit=30):
+    """Markdown table of the top_kernels view of a rocprofv3 database."""
+    import sqlite3
+    con = sqlite3.connect(db)
+    rows = list(con.execute("select name, total_calls, total_duration, average, percentage from top_kernels "
+                            f"limit {int(limit)}"))
+    lines = [f"# {title}", "", "Command (run from /tmp with TMPDIR=/tmp, repository at $R):", "",
+             f"    {command}", "", "The table is the `top_kernels` view of the rocpd database that command writes "
+             "(durations in us).", note, "", "| calls | avg (us) | total (ms) | share | kernel |",
+             "|---:|---:|---:|---:|---|"]
+    for name, calls, tot, avg, pct in rows:
+        lines.append(f"| {calls} | {avg:.2f} | {tot / 1e3:.3f} | {pct:.2f}% | `{name[:150]}` |")
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
+def summarize_pmc(fetch_csv, write_csv, out_json, commands):
+    """HBM bytes per launch of the FP64 pressure brick kernel (and the
+    combine) from FETCH_SIZE / WRITE_SIZE passes, calibrated on the 256 MiB
+    device copy of the same run (copy reads and writes 262144 KiB)."""
+    import csv
+
+    def per_kernel(path, key):
+        with open(path) as fh:
+            return [float(r["Counter_Value"]) for r in csv.DictReader(fh) if key in r["Kernel_Name"]]
+    avg = lambda v: sum(v) / len(v)
+    ff = 262144.0 / max(per_kernel(fetch_csv, "copyBuffer"))
+    fw = 262144.0 / max(per_kernel(write_csv, "copyBuffer"))
+    fb = per_kernel(fetch_csv, "k_brick_o4<3, 8, double, 0")
+    wb = per_kernel(write_csv, "k_brick_o4<3, 8, double, 0")
+    fc = per_kernel(fetch_csv, "k_combine<double, 1, 0>")
+    wc = per_kernel(write_csv, "k_combine<double, 1, 0>")
+    fetch, write = avg(fb) * ff * 1024, avg(wb) * fw * 1024
+    d = {"kernel": "k_brick_o4<3,8,double,PP> (pressure-Poisson apply, FP64, 128^3)", "src_hash": src_hash(),
+         "fetch_size_kib_per_dispatch": avg(fb), "write_size_kib_per_dispatch": avg(wb), "dispatches": len(fb),
+         "fetch_factor": ff, "write_factor": fw,
+         "calibration": "256 MiB device copy: FETCH_SIZE x fetch_factor and WRITE_SIZE x write_factor give "
+                        "262144 KiB each",
+         "bytes_per_launch": fetch + write, "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
+         "combine_fetch_bytes_per_launch": avg(fc) * ff * 1024,
+         "combine_write_bytes_per_launch": avg(wc) * fw * 1024, "commands": commands}
+    with open(out_json, "w") as fh:
+        json.dump(d, fh, indent=1)
+    return d
+
+
 def profile_run(torch, with_solve=True, pc="jacobi"):
     """Fixed sequence for rocprofv3: copy of known size, FP64/FP32 applies, one solve."""
     mesh, ctx, phi_d, b, *_ = setup(torch)
@@ -367,7 +413,19 @@ def main():
                     help="uniform_l7: the benchmark line; adaptive: levels 5..--max-level band mesh solves; "
                          "bubble_steps: projection steps of the 3D rising bubble")
     ap.add_argument("--max-level", type=int, default=10)
+    ap.add_argument("--summarize-stats", nargs=5, metavar=("DB", "OUT_MD", "TITLE", "COMMAND", "NOTE"),
+                    help="write the kernel-statistics table of a rocprofv3 database (no GPU needed)")
+    ap.add_argument("--summarize-pmc", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON", "CMD1", "CMD2"),
+                    help="write the HBM-traffic summary of the pressure brick kernel (no GPU needed)")
     args = ap.parse_args()
+    if args.summarize_stats:
+        db, out, title, cmd, note = args.summarize_stats
+        summarize_stats(db, out, title, cmd, note)
+        return
+    if args.summarize_pmc:
+        fc, wc, out, c1, c2 = args.summarize_pmc
+        print(json.dumps(summarize_pmc(fc, wc, out, [c1, c2]), indent=1))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md)", file=sys.stderr)
