@@ -185,6 +185,10 @@ struct BrickArgs {
   Phys phys;           // physical parameters of the CHNS forms
   double* partials;    // fused x.y partial per block, or null
   const int* done;
+  // damped-Jacobi sweep (pressure operator): y = x + sm_w sm_d (sm_r - A x)
+  const T* sm_r;
+  const T* sm_d;
+  T sm_w;
   // structured (uniform, lexicographically numbered) meshes: node indices are
   // computed from the brick anchor instead of read from the table
   const int32_t* anchor;  // 3 per brick, integer node coordinates
@@ -640,6 +644,9 @@ __device__ __forceinline__ void brick_body(const BrickArgs<T>& a) {
         int64_t e;
         if constexpr (STRUCT) e = entry(z, p);
         else e = eo[k];
+        if constexpr (OP == K_PP) {
+          if (a.sm_r) v[0] = lay[buf][bl][0][p] + a.sm_w * a.sm_d[e] * (a.sm_r[e] - v[0]);
+        }
 #pragma unroll
         for (int f = 0; f < NO; ++f) {
           a.y[f * a.n + e] = v[f];
@@ -829,7 +836,8 @@ __global__ __launch_bounds__(256) void k_combine(const int32_t* __restrict__ nod
                                                  const uint32_t* __restrict__ ent, int64_t nrows,
                                                  const T* __restrict__ slots, int64_t n_slots, T* __restrict__ y,
                                                  const T* __restrict__ x, int64_t n, const uint8_t* __restrict__ wall,
-                                                 double* partials, const int* done) {
+                                                 double* partials, const int* done, const T* __restrict__ sm_r,
+                                                 const T* __restrict__ sm_d, T sm_w) {
   __shared__ double sh[4];
   if (done && *done) return;
   const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -852,6 +860,7 @@ __global__ __launch_bounds__(256) void k_combine(const int32_t* __restrict__ nod
       } else if constexpr (WALL == 2) {
         if (wall[i]) v = T(0);
       }
+      if (sm_r) v = x[i] + sm_w * sm_d[i] * (sm_r[i] - v);
       y[f * n + i] = v;
       if (partials) dot += (double)x[f * n + i] * (double)v;
     }
@@ -1019,6 +1028,10 @@ int apply_t(Ctx& c, const LevelView& L, const T* x, T* y, const T* const* cf, hi
     set_error("fused dot needs as many inputs as outputs");
     return CHNS_EINVAL;
   }
+  if (o.sm_r && (OP != K_PP || o.fuse_dot || x == y)) {
+    set_error("a fused smoothing sweep needs the pressure operator, no fused dot and y distinct from x");
+    return CHNS_EINVAL;
+  }
   BrickArgs<T> a{};
   a.n = dm.n;
   a.n_slots = dm.n_slots;
@@ -1033,6 +1046,9 @@ int apply_t(Ctx& c, const LevelView& L, const T* x, T* y, const T* const* cf, hi
   a.beta = a.phys.beta;
   a.partials = o.fuse_dot ? c.partials : nullptr;
   a.done = o.done;
+  a.sm_r = (const T*)o.sm_r;
+  a.sm_d = (const T*)o.sm_dinv;
+  a.sm_w = (T)o.sm_w;
   a.sy = dm.side + 1;
   a.sz = (int64_t)(dm.side + 1) * (dm.side + 1);
   a.side = dm.side;
@@ -1054,7 +1070,8 @@ int apply_t(Ctx& c, const LevelView& L, const T* x, T* y, const T* const* cf, hi
     c.prof_begin("combine", s, &ev);
     k_combine<T, TR::NO, TR::WALL><<<dim3(g), dim3(256), 0, s>>>(
         dm.comb_node, dm.comb_ptr, dm.comb_ent, dm.n_comb, (const T*)L.slots, dm.n_slots, y, x, dm.n, dm.wall,
-        o.fuse_dot ? c.partials + part_off : nullptr, o.done);
+        o.fuse_dot ? c.partials + part_off : nullptr, o.done, (const T*)o.sm_r, (const T*)o.sm_dinv,
+        (T)o.sm_w);
     CHNS_HIP(hipGetLastError());
     c.prof_end("combine", s, ev);
   }

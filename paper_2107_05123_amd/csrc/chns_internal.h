@@ -210,6 +210,12 @@ struct ApplyOut {
   // optional fused reduction: sum_i x_i * y_i over written nodes into sc->pq
   bool fuse_dot = false;
   const int* done = nullptr;  // skip all work when *done != 0
+  // pressure operator only: a damped-Jacobi sweep instead of the product,
+  // y = x + w dinv (r - A x) (y must not alias x); vectors of the apply's
+  // precision
+  const void* sm_r = nullptr;
+  const void* sm_dinv = nullptr;
+  double sm_w = 0.0;
 };
 int launch_apply(Ctx& c, int op, int prec, const void* x, void* y, hipStream_t s, const ApplyOut& o);
 int launch_apply_lv(Ctx& c, const LevelView& L, int op, int prec, const void* x, void* y, hipStream_t s,

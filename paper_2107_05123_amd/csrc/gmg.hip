@@ -23,6 +23,7 @@
 // size.
 #include <cmath>
 #include <cstring>
+#include <utility>
 
 #include "chns_internal.h"
 
@@ -54,12 +55,6 @@ template <typename T>
 __global__ void k_jacobi0(T* z, const T* r, const T* dinv, T w, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
     z[i] = w * dinv[i] * r[i];
-}
-// z += w dinv (r - t)
-template <typename T>
-__global__ void k_jacobi(T* z, const T* r, const T* t, const T* dinv, T w, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
-    z[i] += w * dinv[i] * (r[i] - t[i]);
 }
 template <typename T>
 __global__ void k_copy_t(const T* a, T* b, int64_t n) {
@@ -211,31 +206,41 @@ __global__ __launch_bounds__(64) void k_el_rediscr(const double* __restrict__ ph
 }
 
 // Galerkin element matrices of a uniform level (sc cells per edge) straight
-// from the phase field of the uniform level above (sf = 2 sc)
+// from the phase field of the uniform level above (sf = 2 sc).  One wave
+// handles kGalPerWave coarse elements; lane t keeps column t of H (the 64
+// table entries it needs) in registers across them.
+constexpr int kGalPerWave = 64;
 template <int DIM>
 __global__ __launch_bounds__(64) void k_gal_phi(const double* __restrict__ phi, int sf, const double* __restrict__ Ht,
-                                                double alpha, double beta, double scale, double* E) {
+                                                double alpha, double beta, double scale, double* E, int64_t ne) {
   constexpr int NC = 1 << DIM, NE = NC * NC;
   __shared__ double cq[NE];
-  const int64_t e = blockIdx.x;
   const int sc = sf / 2;
   const int64_t f1 = sf + 1;
-  const int X = (int)(e % sc), Y = (int)((e / sc) % sc), Z = DIM == 3 ? (int)(e / ((int64_t)sc * sc)) : 0;
   const int t = threadIdx.x;
-  if (t < NE) {
-    // lane t: child c = t / NC, Gauss point q = t % NC of that child
-    const int c = t / NC, q = t % NC;
-    const int cx = 2 * X + (c & 1), cy = 2 * Y + ((c >> 1) & 1), cz = DIM == 3 ? 2 * Z + ((c >> 2) & 1) : 0;
-    double ph[NC];
-    for (int b = 0; b < NC; ++b)
-      ph[b] = phi[((int64_t)(cz + ((b >> 2) & 1)) * f1 + (cy + ((b >> 1) & 1))) * f1 + (cx + (b & 1))];
-    cq[t] = coef_at(ph, q, DIM, alpha, beta);
-  }
-  __syncthreads();
-  if (t < NE) {
-    double acc = 0.0;
-    for (int k = 0; k < NE; ++k) acc += cq[k] * Ht[k * NE + t];
-    E[e * NE + t] = scale * acc;
+  double h[NE];
+#pragma unroll
+  for (int k = 0; k < NE; ++k) h[k] = t < NE ? Ht[k * NE + t] : 0.0;
+  const int64_t e0 = (int64_t)blockIdx.x * kGalPerWave;
+  for (int64_t e = e0; e < e0 + kGalPerWave && e < ne; ++e) {
+    const int X = (int)(e % sc), Y = (int)((e / sc) % sc), Z = DIM == 3 ? (int)(e / ((int64_t)sc * sc)) : 0;
+    if (t < NE) {
+      // lane t: child c = t / NC, Gauss point q = t % NC of that child
+      const int c = t / NC, q = t % NC;
+      const int cx = 2 * X + (c & 1), cy = 2 * Y + ((c >> 1) & 1), cz = DIM == 3 ? 2 * Z + ((c >> 2) & 1) : 0;
+      double ph[NC];
+      for (int b = 0; b < NC; ++b)
+        ph[b] = phi[((int64_t)(cz + ((b >> 2) & 1)) * f1 + (cy + ((b >> 1) & 1))) * f1 + (cx + (b & 1))];
+      cq[t] = coef_at(ph, q, DIM, alpha, beta);
+    }
+    __syncthreads();
+    if (t < NE) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < NE; ++k) acc += cq[k] * h[k];
+      E[e * NE + t] = scale * acc;
+    }
+    __syncthreads();
   }
 }
 
@@ -626,10 +631,21 @@ int vcycle(Ctx& c, int k, const T* r, T* z, hipStream_t s) {
   ApplyOut plain{};
   int rc;
   if (k > 0 && mg.lv[k].S64) return vcycle_stencil<T>(c, k, r, z, s);
-  k_jacobi0<T><<<g, kT, 0, s>>>(z, r, dinv, w, n);
-  for (int it = 1; it < mg.nu; ++it) {
-    if ((rc = launch_apply_lv(c, V, CHNS_OP_PRESSURE, PR::P, z, t, s, plain))) return rc;
-    k_jacobi<T><<<g, kT, 0, s>>>(z, r, t, dinv, w, n);
+  // sweeps fused into the apply (brick and combine write x + w D^-1 (r - A x)
+  // into the other buffer), alternating between z and t so that the last
+  // pre-smoothing sweep lands in z
+  ApplyOut sm{};
+  sm.sm_r = r;
+  sm.sm_dinv = dinv;
+  sm.sm_w = mg.omega;
+  {
+    T* cur = (mg.nu % 2 == 1) ? z : t;  // after nu - 1 sweeps the result is in z
+    T* oth = cur == z ? t : z;
+    k_jacobi0<T><<<g, kT, 0, s>>>(cur, r, dinv, w, n);
+    for (int it = 1; it < mg.nu; ++it) {
+      if ((rc = launch_apply_lv(c, V, CHNS_OP_PRESSURE, PR::P, cur, oth, s, sm))) return rc;
+      std::swap(cur, oth);
+    }
   }
   if ((rc = launch_apply_lv(c, V, CHNS_OP_PRESSURE, PR::P, z, t, s, plain))) return rc;
   MgLevel& C = mg.lv[k + 1];
@@ -648,9 +664,14 @@ int vcycle(Ctx& c, int k, const T* r, T* z, hipStream_t s) {
     k_prolong_s<T><<<g, kT, 0, s>>>(zc, z, C.dm.side, C.dm.dim);
   else
     k_spmv<T, T><<<g, kT, 0, s>>>(C.P_ptr, C.P_col, PR::Pv(C), zc, z, n, 1);
-  for (int it = 0; it < mg.nu; ++it) {
-    if ((rc = launch_apply_lv(c, V, CHNS_OP_PRESSURE, PR::P, z, t, s, plain))) return rc;
-    k_jacobi<T><<<g, kT, 0, s>>>(z, r, t, dinv, w, n);
+  {
+    T* cur = z;
+    T* oth = t;
+    for (int it = 0; it < mg.nu; ++it) {
+      if ((rc = launch_apply_lv(c, V, CHNS_OP_PRESSURE, PR::P, cur, oth, s, sm))) return rc;
+      std::swap(cur, oth);
+    }
+    if (cur != z) k_copy_t<T><<<g, kT, 0, s>>>(cur, z, n);
   }
   CHNS_HIP(hipGetLastError());
   return CHNS_OK;
@@ -847,15 +868,18 @@ int mg_setup(Ctx& c, hipStream_t s) {
     if (mg.tab_H) {
       // uniform fine level: inverse diagonal straight from the phase field,
       // first coarse level's element matrices as Galerkin products
-      const unsigned gl = (unsigned)((int64_t)1 << (dim * (c.dm.max_level - 1)));
+      const int64_t ncoarse = (int64_t)1 << (dim * (c.dm.max_level - 1));
+      const unsigned gl = (unsigned)((ncoarse + kGalPerWave - 1) / kGalPerWave);
       if (dim == 3) {
         k_diag_phi<3><<<blocks(c.dm.n), kT, 0, st>>>(c.phi64, c.dm.side, mg.tab_G, al, be, lscale(c.dm.side),
                                                       mg.fine_dinv64, mg.fine_dinv32);
-        k_gal_phi<3><<<gl, 64, 0, st>>>(c.phi64, c.dm.side, mg.tab_H, al, be, lscale(c.dm.side), mg.lv[1].E64);
+        k_gal_phi<3><<<gl, 64, 0, st>>>(c.phi64, c.dm.side, mg.tab_H, al, be, lscale(c.dm.side), mg.lv[1].E64,
+                                         ncoarse);
       } else {
         k_diag_phi<2><<<blocks(c.dm.n), kT, 0, st>>>(c.phi64, c.dm.side, mg.tab_G, al, be, lscale(c.dm.side),
                                                       mg.fine_dinv64, mg.fine_dinv32);
-        k_gal_phi<2><<<gl, 64, 0, st>>>(c.phi64, c.dm.side, mg.tab_H, al, be, lscale(c.dm.side), mg.lv[1].E64);
+        k_gal_phi<2><<<gl, 64, 0, st>>>(c.phi64, c.dm.side, mg.tab_H, al, be, lscale(c.dm.side), mg.lv[1].E64,
+                                         ncoarse);
       }
       CHNS_HIP(hipGetLastError());
     } else {
