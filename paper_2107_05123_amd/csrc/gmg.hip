@@ -360,8 +360,8 @@ __global__ void k_stencil_dense(const double* __restrict__ S, int s, double* M) 
 
 // sum_o S_o(i) v(i + off_o) on a uniform level (zero stencil entries reach
 // no node outside the level; their indices are skipped)
-template <typename T, int DIM>
-__device__ __forceinline__ T stencil_row(const T* __restrict__ S, const T* __restrict__ v, int64_t node, int64_t n,
+template <typename T, int DIM, typename ST>
+__device__ __forceinline__ T stencil_row(const ST* __restrict__ S, const T* __restrict__ v, int64_t node, int64_t n,
                                          int I, int J, int K, int s) {
   const int64_t s1 = s + 1;
   T acc = T(0);
@@ -375,7 +375,7 @@ __device__ __forceinline__ T stencil_row(const T* __restrict__ S, const T* __res
       for (int ox = -1; ox <= 1; ++ox) {
         if (I + ox < 0 || I + ox > s) continue;
         const int o = (ox + 1) + 3 * (oy + 1) + (DIM == 3 ? 9 * (oz + 1) : 0);
-        acc += S[o * n + node] * v[node + ox + oy * s1 + (DIM == 3 ? oz * s1 * s1 : 0)];
+        acc += (T)S[o * n + node] * v[node + ox + oy * s1 + (DIM == 3 ? oz * s1 * s1 : 0)];
       }
     }
   }
@@ -389,8 +389,8 @@ __device__ __forceinline__ void node_ijk(int64_t node, int s, int& I, int& J, in
   K = DIM == 3 ? (int)(node / (s1 * s1)) : 0;
 }
 // two damped-Jacobi sweeps from z = 0: z1 = w D^-1 r, z2 = z1 + w D^-1 (r - A z1)
-template <typename T, int DIM>
-__global__ void k_st_pre2(const T* __restrict__ S, const T* __restrict__ dinv, const T* __restrict__ r,
+template <typename T, int DIM, typename ST>
+__global__ void k_st_pre2(const ST* __restrict__ S, const T* __restrict__ dinv, const T* __restrict__ r,
                           T* __restrict__ z, T w, int s, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
     int I, J, K;
@@ -408,7 +408,7 @@ __global__ void k_st_pre2(const T* __restrict__ S, const T* __restrict__ dinv, c
           if (I + ox < 0 || I + ox > s) continue;
           const int o = (ox + 1) + 3 * (oy + 1) + (DIM == 3 ? 9 * (oz + 1) : 0);
           const int64_t j = i + ox + oy * s1 + (DIM == 3 ? oz * s1 * s1 : 0);
-          az += S[o * n + i] * (w * dinv[j] * r[j]);
+          az += (T)S[o * n + i] * (w * dinv[j] * r[j]);
         }
       }
     }
@@ -417,22 +417,22 @@ __global__ void k_st_pre2(const T* __restrict__ S, const T* __restrict__ dinv, c
   }
 }
 // zo = zi + w D^-1 (r - A zi)
-template <typename T, int DIM>
-__global__ void k_st_sweep(const T* __restrict__ S, const T* __restrict__ dinv, const T* __restrict__ r,
+template <typename T, int DIM, typename ST>
+__global__ void k_st_sweep(const ST* __restrict__ S, const T* __restrict__ dinv, const T* __restrict__ r,
                            const T* __restrict__ zi, T* __restrict__ zo, T w, int s, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
     int I, J, K;
     node_ijk<DIM>(i, s, I, J, K);
-    zo[i] = zi[i] + w * dinv[i] * (r[i] - stencil_row<T, DIM>(S, zi, i, n, I, J, K, s));
+    zo[i] = zi[i] + w * dinv[i] * (r[i] - stencil_row<T, DIM, ST>(S, zi, i, n, I, J, K, s));
   }
 }
 // t = A z
-template <typename T, int DIM>
-__global__ void k_st_apply(const T* __restrict__ S, const T* __restrict__ z, T* __restrict__ t, int s, int64_t n) {
+template <typename T, int DIM, typename ST>
+__global__ void k_st_apply(const ST* __restrict__ S, const T* __restrict__ z, T* __restrict__ t, int s, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
     int I, J, K;
     node_ijk<DIM>(i, s, I, J, K);
-    t[i] = stencil_row<T, DIM>(S, z, i, n, I, J, K, s);
+    t[i] = stencil_row<T, DIM, ST>(S, z, i, n, I, J, K, s);
   }
 }
 
@@ -535,7 +535,6 @@ struct Prec<double> {
   static const double* Pv(MgLevel& L) { return L.P_val64; }
   static const double* Rv(MgLevel& L) { return L.R_val64; }
   static const double* inv(MgLevel& L) { return L.inv64; }
-  static const double* S(MgLevel& L) { return L.S64; }
   static double* fine_dinv(Multigrid& m) { return m.fine_dinv64; }
   static double* fine_t(Multigrid& m) { return m.fine_t64; }
 };
@@ -547,7 +546,6 @@ struct Prec<float> {
   static const float* Pv(MgLevel& L) { return L.P_val32; }
   static const float* Rv(MgLevel& L) { return L.R_val32; }
   static const float* inv(MgLevel& L) { return L.inv32; }
-  static const float* S(MgLevel& L) { return L.S32; }
   static float* fine_dinv(Multigrid& m) { return m.fine_dinv32; }
   static float* fine_t(Multigrid& m) { return m.fine_t32; }
 };
@@ -567,19 +565,23 @@ int vcycle_stencil(Ctx& c, int k, const T* r, T* z, hipStream_t s) {
   MgLevel& C = mg.lv[k + 1];
   const int64_t n = L.dm.n;
   const int side = L.dm.side, dim = L.dm.dim;
-  const T* S = PR::S(L);
+  // the coarse operator's values are read in FP32 in both precisions (half
+  // the stencil stream; the arithmetic stays in T, and the FP32-rounded
+  // operator is a fixed symmetric matrix, so the cycle is still a fixed SPD
+  // preconditioner)
+  const float* S = L.S32;
   const T* dinv = PR::dinv(L);
   T* t = PR::v(L, 2);
   T* z2 = PR::v(L, 3);
   const T w = (T)mg.omega;
   const unsigned g = blocks(n);
   auto pre2 = [&]() {
-    if (dim == 3) k_st_pre2<T, 3><<<g, kT, 0, s>>>(S, dinv, r, z, w, side, n);
-    else k_st_pre2<T, 2><<<g, kT, 0, s>>>(S, dinv, r, z, w, side, n);
+    if (dim == 3) k_st_pre2<T, 3, float><<<g, kT, 0, s>>>(S, dinv, r, z, w, side, n);
+    else k_st_pre2<T, 2, float><<<g, kT, 0, s>>>(S, dinv, r, z, w, side, n);
   };
   auto sweep = [&](const T* zi, T* zo) {
-    if (dim == 3) k_st_sweep<T, 3><<<g, kT, 0, s>>>(S, dinv, r, zi, zo, w, side, n);
-    else k_st_sweep<T, 2><<<g, kT, 0, s>>>(S, dinv, r, zi, zo, w, side, n);
+    if (dim == 3) k_st_sweep<T, 3, float><<<g, kT, 0, s>>>(S, dinv, r, zi, zo, w, side, n);
+    else k_st_sweep<T, 2, float><<<g, kT, 0, s>>>(S, dinv, r, zi, zo, w, side, n);
   };
   // pre-smoothing: nu sweeps from a zero guess, result in z
   if (mg.nu >= 2) {
@@ -591,8 +593,8 @@ int vcycle_stencil(Ctx& c, int k, const T* r, T* z, hipStream_t s) {
   } else {
     k_jacobi0<T><<<g, kT, 0, s>>>(z, r, dinv, w, n);
   }
-  if (dim == 3) k_st_apply<T, 3><<<g, kT, 0, s>>>(S, z, t, side, n);
-  else k_st_apply<T, 2><<<g, kT, 0, s>>>(S, z, t, side, n);
+  if (dim == 3) k_st_apply<T, 3, float><<<g, kT, 0, s>>>(S, z, t, side, n);
+  else k_st_apply<T, 2, float><<<g, kT, 0, s>>>(S, z, t, side, n);
   T* rc_ = PR::v(C, 0);
   T* zc = PR::v(C, 1);
   k_restrict_s<T><<<blocks(C.dm.n), kT, 0, s>>>(r, t, rc_, C.dm.side, dim);
