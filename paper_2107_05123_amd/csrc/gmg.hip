@@ -753,7 +753,7 @@ int mg_build(Ctx& c) {
   }
   if (mg->lv.size() < 2) {
     delete mg;
-    set_error("mesh too coarse for multigrid (needs max_level >= 3)");
+    set_error("mesh too coarse for multigrid (needs max_level >= 2)");
     return CHNS_EINVAL;
   }
   int rc;
