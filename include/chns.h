@@ -254,7 +254,14 @@ typedef struct chns_step_opts {
   int pp_pc;           /* CHNS_PC_JACOBI (default) or CHNS_PC_GMG                */
   int pp_mode;         /* CHNS_MODE_FP64 (default) or CHNS_MODE_MIXED_IR         */
   int no_graphs;       /* 1: no HIP graph replay of Krylov iterations           */
+  int ch_pc;           /* preconditioner of the CH Newton GMRES: CHNS_CH_PC_BLOCK_JACOBI
+                        * (default: 2x2 node blocks of the Jacobian) or
+                        * CHNS_CH_PC_SCHUR_GMG (block lower-triangular with a
+                        * multigrid Schur-complement approximation; needs a
+                        * mesh of max_level >= 2)                              */
 } chns_step_opts;
+
+enum { CHNS_CH_PC_BLOCK_JACOBI = 0, CHNS_CH_PC_SCHUR_GMG = 1 };
 
 typedef struct chns_step_stats {
   int newton_iterations[4]; /* per block                                        */
@@ -269,7 +276,12 @@ typedef struct chns_step_stats {
 } chns_step_stats;
 
 /* One projection time step (paper Sec. 3 and its flowchart): `blocks` passes
- * of Newton on the Cahn-Hilliard system (GMRES with 2x2 node-block Jacobi),
+ * of Newton on the Cahn-Hilliard system (GMRES with 2x2 node-block Jacobi, or
+ * with opts->ch_pc = CHNS_CH_PC_SCHUR_GMG the block lower-triangular
+ * preconditioner whose Schur complement ~ (1/dt)(M + sqrt(b) K) M_L^-1
+ * (M + sqrt(b) K), b = dt Cn / (2 Pe), is applied with two multigrid V-cycles;
+ * the multigrid hierarchy is shared with the pressure solve and set up again
+ * for it),
  * velocity prediction (GMRES with Jacobi), pressure Poisson (CG) and velocity
  * update (CG on the rho-weighted mass matrix), then
  * (u_prev, u, p, phi, mu) <- (u^k, u^{k+1}, p^{k+1}, phi^{k+1}, mu^{k+1}).

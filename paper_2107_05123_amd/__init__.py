@@ -254,7 +254,7 @@ class Context:
 
     def advance_step(self, state: dict, blocks=2, newton_rtol=1e-8, newton_atol=1e-12, max_newton=20,
                      lin_rtol=1e-8, max_it=5000, restart=64, pp_pc="jacobi", pp_mode="fp64", graphs=True,
-                     stream=None):
+                     ch_pc="block", stream=None):
         """state: dict of device FP64 tensors u, u_prev (dim*n), p, phi, mu (n), updated in place."""
         import torch
         d = self.dim * self.n
@@ -263,7 +263,8 @@ class Context:
                      _dev_ptr(state["mu"], torch.float64, self.n))
         o = L.StepOpts(blocks, newton_rtol, newton_atol, max_newton, lin_rtol, max_it, restart,
                        {"jacobi": L.PC_JACOBI, "gmg": L.PC_GMG}[pp_pc],
-                       {"fp64": L.MODE_FP64, "mixed": L.MODE_MIXED_IR}[pp_mode], 0 if graphs else 1)
+                       {"fp64": L.MODE_FP64, "mixed": L.MODE_MIXED_IR}[pp_mode], 0 if graphs else 1,
+                       {"block": L.CH_PC_BLOCK_JACOBI, "schur": L.CH_PC_SCHUR_GMG}[ch_pc])
         ss = L.StepStats()
         L.check(L.lib().chns_advance_step(self._h, C.byref(st), C.byref(o), C.byref(ss), _stream_ptr(stream)))
         return {"newton": list(ss.newton_iterations)[:blocks], "ch_iterations": ss.ch_iterations,

@@ -60,6 +60,9 @@ Ctx::~Ctx() {
   destroy_stepper(*this);
   unet_destroy(*this);
   if (mg && mg->setup_exec) (void)hipGraphExecDestroy(mg->setup_exec);
+  if (mg)
+    for (auto& e : mg->shifted_setups)
+      if (e.second) (void)hipGraphExecDestroy(e.second);
   if (diag_exec) (void)hipGraphExecDestroy(diag_exec);
   delete mg;
   for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
@@ -422,6 +425,10 @@ int chns_advance_step(chns_ctx* ctx, chns_state* state, const chns_step_opts* op
     if (!(o.lin_rtol > 0.0)) o.lin_rtol = 1e-8;
     if (o.max_it <= 0) o.max_it = 5000;
     if (o.restart <= 0) o.restart = 64;
+  }
+  if (o.ch_pc != CHNS_CH_PC_BLOCK_JACOBI && o.ch_pc != CHNS_CH_PC_SCHUR_GMG) {
+    set_error("unknown Cahn-Hilliard preconditioner");
+    return CHNS_EINVAL;
   }
   chns_step_stats st{};
   int rc = advance_step_impl(ctx->c, *state, o, st, (hipStream_t)stream);

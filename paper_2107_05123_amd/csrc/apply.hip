@@ -141,7 +141,7 @@ __device__ __forceinline__ void elem_mass_apply(const T* x, const T* r, T* y) {
 // 1 identity rows on the walls (y = x), 2 zero rows on the walls.
 enum OpKind {
   K_PP = 0, K_MASS = 1, K_MASS_RHO = 2, K_CH_RES = 3, K_CH_JAC = 4, K_VP = 5, K_VP_RHS = 6, K_PP_RHS = 7,
-  K_VU_RHS = 8, K_ENERGY = 9
+  K_VU_RHS = 8, K_ENERGY = 9, K_PPS = 10
 };
 template <int OP, int DIM>
 struct Traits;
@@ -161,6 +161,7 @@ CHNS_TRAITS(K_VP_RHS, 0, 2 * DIM + 3, DIM, false, 2)
 CHNS_TRAITS(K_PP_RHS, 0, 3 * DIM + 3, 1, false, 0)
 CHNS_TRAITS(K_VU_RHS, 0, 3 * DIM + 4, DIM, false, 2)
 CHNS_TRAITS(K_ENERGY, 0, 2 + DIM, 1, false, 0)
+CHNS_TRAITS(K_PPS, 1, 1, 1, false, 0)  // pressure operator + shift * mass
 #undef CHNS_TRAITS
 
 constexpr int kMaxCoef = kMaxCoefFields;
@@ -189,6 +190,7 @@ struct BrickArgs {
   const T* sm_r;
   const T* sm_d;
   T sm_w;
+  double shift;  // K_PPS: mass shift
   // structured (uniform, lexicographically numbered) meshes: node indices are
   // computed from the brick anchor instead of read from the table
   const int32_t* anchor;  // 3 per brick, integer node coordinates
@@ -559,8 +561,9 @@ __device__ __forceinline__ void brick_body(const BrickArgs<T>& a) {
   // per-level folded constants (powers of two are exact); FP32 fields carry
   // 1 + phi, so rho = (beta - alpha) + alpha (1 + phi)
   const double beta0 = sizeof(T) == 8 ? a.beta : a.beta - a.alpha;
-  T A = 0, Bc = 0;
-  if constexpr (OP == K_PP) {
+  T A = 0, Bc = 0, Ms = 0;
+  if constexpr (OP == K_PPS) Ms = T(a.shift * ldexp(1.0, -(lev + 1) * DIM - 2 * DIM));
+  if constexpr (OP == K_PP || OP == K_PPS) {
     // c~ = detJ (2/h)^2 / 4^d / rho = 1 / (rho / K); K = 2^{-(lev+1)(d-2) - 2d}
     const int e = (lev + 1) * (DIM - 2) + 2 * DIM;
     A = T(ldexp(a.alpha, e - DIM));
@@ -644,7 +647,7 @@ __device__ __forceinline__ void brick_body(const BrickArgs<T>& a) {
         int64_t e;
         if constexpr (STRUCT) e = entry(z, p);
         else e = eo[k];
-        if constexpr (OP == K_PP) {
+        if constexpr (OP == K_PP || OP == K_PPS) {
           if (a.sm_r) v[0] = lay[buf][bl][0][p] + a.sm_w * a.sm_d[e] * (a.sm_r[e] - v[0]);
         }
 #pragma unroll
@@ -732,7 +735,7 @@ __device__ __forceinline__ void brick_body(const BrickArgs<T>& a) {
     }
   };
   if (active) read_half(0, 1);
-  constexpr int kUnroll = (OP == K_PP || OP == K_MASS) ? B : 1;
+  constexpr int kUnroll = (OP == K_PP || OP == K_PPS || OP == K_MASS) ? B : 1;
 #pragma unroll kUnroll
   for (int ez = 0; ez < B; ++ez) {
     load_emit_entries(ez);
@@ -746,8 +749,16 @@ __device__ __forceinline__ void brick_body(const BrickArgs<T>& a) {
         for (int f = 0; f < NCF; ++f) cc[f][c] = cc[f][c + NH];
       }
       read_half(ez + 1, 1);
-      if constexpr (OP == K_PP) {
+      if constexpr (OP == K_PP || OP == K_PPS) {
         elem_pp<DIM, T>(xc[0], cc[0], A, Bc, ye[0]);
+        if constexpr (OP == K_PPS) {
+          T r[NC], ym[NC];
+#pragma unroll
+          for (int i = 0; i < NC; ++i) r[i] = Ms;
+          elem_mass_apply<DIM, T>(xc[0], r, ym);
+#pragma unroll
+          for (int i = 0; i < NC; ++i) ye[0][i] += ym[i];
+        }
       } else if constexpr (OP == K_MASS || OP == K_MASS_RHO) {
         T r[NC];
         elem_mass_coef<DIM, T, OP == K_MASS_RHO>(cc[0], A, Bc, r);
@@ -940,7 +951,7 @@ template <int DIM, int B, typename T, int OP, bool STRUCT>
 void launch_one(int64_t grid, hipStream_t s, const BrickArgs<T>& a) {
   const dim3 g((unsigned)grid), blk(64);
   constexpr bool W = whole_fits<DIM, B, T, OP>();
-  if constexpr (OP == K_PP || OP == K_MASS) k_brick_o4<DIM, B, T, OP, W, STRUCT><<<g, blk, 0, s>>>(a);
+  if constexpr (OP == K_PP || OP == K_PPS || OP == K_MASS) k_brick_o4<DIM, B, T, OP, W, STRUCT><<<g, blk, 0, s>>>(a);
   else k_brick<DIM, B, T, OP, W, STRUCT><<<g, blk, 0, s>>>(a);
 }
 template <int DIM, typename T, int OP, bool STRUCT>
@@ -1005,7 +1016,7 @@ Phys phys_of(const chns_params& p) {
 }
 
 const char* op_tag(int op, bool fp64) {
-  static const char* tags[10][2] = {{"pp_brick_fp64", "pp_brick_fp32"},
+  static const char* tags[11][2] = {{"pp_brick_fp64", "pp_brick_fp32"},
                                     {"mass_brick_fp64", "mass_brick_fp32"},
                                     {"massrho_brick_fp64", "massrho_brick_fp32"},
                                     {"chres_brick_fp64", "chres_brick_fp32"},
@@ -1014,7 +1025,8 @@ const char* op_tag(int op, bool fp64) {
                                     {"vprhs_brick_fp64", "vprhs_brick_fp32"},
                                     {"pprhs_brick_fp64", "pprhs_brick_fp32"},
                                     {"vurhs_brick_fp64", "vurhs_brick_fp32"},
-                                    {"energy_brick_fp64", "energy_brick_fp32"}};
+                                    {"energy_brick_fp64", "energy_brick_fp32"},
+                                    {"pps_brick_fp64", "pps_brick_fp32"}};
   return tags[op][fp64 ? 0 : 1];
 }
 
@@ -1028,7 +1040,7 @@ int apply_t(Ctx& c, const LevelView& L, const T* x, T* y, const T* const* cf, hi
     set_error("fused dot needs as many inputs as outputs");
     return CHNS_EINVAL;
   }
-  if (o.sm_r && (OP != K_PP || o.fuse_dot || x == y)) {
+  if (o.sm_r && ((OP != K_PP && OP != K_PPS) || o.fuse_dot || x == y)) {
     set_error("a fused smoothing sweep needs the pressure operator, no fused dot and y distinct from x");
     return CHNS_EINVAL;
   }
@@ -1049,6 +1061,7 @@ int apply_t(Ctx& c, const LevelView& L, const T* x, T* y, const T* const* cf, hi
   a.sm_r = (const T*)o.sm_r;
   a.sm_d = (const T*)o.sm_dinv;
   a.sm_w = (T)o.sm_w;
+  a.shift = c.pp_shift;
   a.sy = dm.side + 1;
   a.sz = (int64_t)(dm.side + 1) * (dm.side + 1);
   a.side = dm.side;
@@ -1093,6 +1106,7 @@ int apply_dispatch(Ctx& c, const LevelView& L, int op, const T* x, T* y, const T
   const T* one[1] = {phi};
   switch (op) {
     case CHNS_OP_PRESSURE:
+      if (c.pp_shift != 0.0) return apply_d<K_PPS, T>(c, L, x, y, one, s, o);
       return apply_d<K_PP, T>(c, L, x, y, one, s, o);
     case CHNS_OP_MASS:
       return apply_d<K_MASS, T>(c, L, x, y, one, s, o);

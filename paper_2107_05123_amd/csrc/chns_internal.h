@@ -106,8 +106,11 @@ struct Multigrid {
   double* tab_G = nullptr;
   double* tab_P = nullptr;
   double* tab_H = nullptr;
+  double* tab_M = nullptr;  // reference mass sum_q N_a N_b (for a mass shift)
   bool setup_valid = false;
   hipGraphExec_t setup_exec = nullptr;  // captured device part of the set-up
+  // captured set-ups of shifted operators (mass shift, graph)
+  std::vector<std::pair<double, hipGraphExec_t>> shifted_setups;
   int nu = 2;            // damped-Jacobi sweeps before and after the correction
   double omega = 0.6;    // damping
 };
@@ -146,6 +149,10 @@ struct Ctx {
   bool diag_valid = false;
 
   Multigrid* mg = nullptr;
+  // mass shift g of the pressure operator (K_{1/rho} + g M): 0 for the
+  // public operator; set only while the Cahn-Hilliard preconditioner uses
+  // the multigrid hierarchy
+  double pp_shift = 0.0;
 
   // coefficient fields of the momentum and Cahn-Hilliard Jacobian operators
   // (context-owned copies, (2 + dim) * n each): [phi~, mu~, u^] and

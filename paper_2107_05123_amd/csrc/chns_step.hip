@@ -37,7 +37,9 @@ struct GmDev {
   double H[(kGmMax + 1) * kGmMax];
 };
 
-enum GmPc { GPC_NONE = 0, GPC_JACOBI = 1, GPC_BLOCK2 = 2 };
+// GPC_SCHUR: block lower-triangular preconditioner of the Cahn-Hilliard
+// Jacobian with a multigrid Schur-complement approximation (pcd = lumped mass)
+enum GmPc { GPC_NONE = 0, GPC_JACOBI = 1, GPC_BLOCK2 = 2, GPC_SCHUR = 3 };
 
 struct Stepper {
   int64_t n = 0, nv = 0;  // nodes, longest vector (max(2, dim) * n)
@@ -62,6 +64,10 @@ struct Stepper {
   double *uhat = nullptr, *ut = nullptr, *unew = nullptr, *v = nullptr, *pnew = nullptr;
   double *phit = nullptr, *mut = nullptr, *ycoord = nullptr, *tmp = nullptr, *zero = nullptr;
   double *blk = nullptr, *binv = nullptr, *dvp = nullptr, *dvu = nullptr, *dm = nullptr;
+  // Cahn-Hilliard Schur-complement preconditioner: lumped mass, work vectors
+  double *mL = nullptr, *pin = nullptr, *pout = nullptr, *pt1 = nullptr, *pt2 = nullptr, *pz = nullptr,
+         *pj = nullptr;
+  double sc_scale = 0.0;  // dt / b of the Schur approximation
 };
 
 namespace {
@@ -110,6 +116,7 @@ __global__ void k_axpby(double* out, double a, const double* x, double b, const 
 }
 __global__ void k_scal(double* out, double a, const double* x, int64_t n) { GRID_LOOP(i, n) out[i] = a * x[i]; }
 __global__ void k_fill0(double* x, int64_t n) { GRID_LOOP(i, n) x[i] = 0.0; }
+__global__ void k_fill1(double* x, int64_t n) { GRID_LOOP(i, n) x[i] = 1.0; }
 __global__ void k_add(double* x, const double* d, int64_t n) { GRID_LOOP(i, n) x[i] += d[i]; }
 
 // inverse of the 2 x 2 node blocks [a b; c d] (row-major field blocks)
@@ -310,6 +317,35 @@ __global__ void k_gm_update(double* x, const double* V, int64_t nv, int64_t n, c
   }
 }
 
+// pin = V_j (Schur preconditioner input)
+__global__ void k_gm_copyj(const double* V, int64_t nv, double* out, const GmDev* gd) {
+  if (gd->done) return;
+  const double* v = V + (int64_t)gd->j * nv;
+  GRID_LOOP(i, nv) out[i] = v[i];
+}
+// out = sum_k y_k V_k
+__global__ void k_gm_combine(double* out, const double* V, int64_t nv, const GmDev* gd) {
+  const int j = gd->j;
+  GRID_LOOP(i, nv) {
+    double a = 0.0;
+    for (int k = 0; k < j; ++k) a += gd->y[k] * V[(int64_t)k * nv + i];
+    out[i] = a;
+  }
+}
+__global__ void k_mul(double* out, const double* a, const double* b, int64_t n) { GRID_LOOP(i, n) out[i] = a[i] * b[i]; }
+// dphi = s t (into the output and into the phi block of pz, whose mu block stays 0)
+__global__ void k_sc_phi(double* out, double* pz, const double* t, double s, int64_t n) {
+  GRID_LOOP(i, n) {
+    const double v = s * t[i];
+    out[i] = v;
+    pz[i] = v;
+  }
+}
+// dmu = -2 mL^-1 (v_mu - C dphi)
+__global__ void k_sc_mu(double* out_mu, const double* v_mu, const double* cdphi, const double* mL, int64_t n) {
+  GRID_LOOP(i, n) out_mu[i] = -2.0 * (v_mu[i] - cdphi[i]) / mL[i];
+}
+
 struct Clock {
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
   double ms() const {
@@ -388,6 +424,34 @@ int dot_sync(Ctx& c, const double* a, const double* b, int64_t n, hipStream_t s,
   return CHNS_OK;
 }
 
+// Block lower-triangular preconditioner of the Cahn-Hilliard Jacobian
+// J = [[A, B], [C, D]] (A = M/dt - advection/2, B = K/(2 Pe Cn),
+// C = (M_psi'' + Cn^2 K)/2, D = -M/2):
+//   dphi = S~^-1 v_phi,  dmu = D^-1 (v_mu - C dphi),  D^-1 ~ -2 M_L^-1,
+// with the Schur complement S = A - B D^-1 C approximated, dropping the
+// advection and psi'' parts, by (1/dt)(M + sqrt(b) K) M_L^-1 (M + sqrt(b) K),
+// b = dt Cn / (2 Pe):  S~^-1 = (dt/b) A_g^-1 M_L A_g^-1, A_g = K + M/sqrt(b),
+// each A_g^-1 one multigrid V-cycle of the pressure hierarchy set up with
+// rho = 1 and the mass shift 1/sqrt(b).  C dphi is the mu block of J [dphi, 0].
+// A fixed linear map (fixed cycles), so plain right-preconditioned GMRES
+// applies.  in / out: 2n, in = [v_phi, v_mu].
+int ch_schur_apply(Ctx& c, const double* in, double* out, hipStream_t s) {
+  Stepper& S = *c.step;
+  const int64_t n = c.dm.n;
+  const unsigned g = blocks_for(n);
+  int rc;
+  if ((rc = mg_vcycle64(c, in, S.pt1, s))) return rc;
+  k_mul<<<g, kT, 0, s>>>(S.pt2, S.mL, S.pt1, n);
+  if ((rc = mg_vcycle64(c, S.pt2, S.pt1, s))) return rc;
+  k_sc_phi<<<g, kT, 0, s>>>(out, S.pz, S.pt1, S.sc_scale, n);
+  CHNS_HIP(hipGetLastError());
+  ApplyOut plain{};
+  if ((rc = launch_apply(c, CHNS_OP_CH_JACOBIAN, CHNS_FP64, S.pz, S.pj, s, plain))) return rc;
+  k_sc_mu<<<g, kT, 0, s>>>(out + n, in + n, S.pj + n, S.mL, n);
+  CHNS_HIP(hipGetLastError());
+  return CHNS_OK;
+}
+
 // Restarted right-preconditioned GMRES(m) on A x = b, A = the public
 // operator `op` with its current coefficient fields; x in/out.
 int gmres(Ctx& c, int op, const double* b, double* x, int pc, const double* pcd, double rtol, int max_it, int m,
@@ -413,9 +477,16 @@ int gmres(Ctx& c, int op, const double* b, double* x, int pc, const double* pcd,
   ApplyOut gated{};
   gated.done = &S.gd->done;
   auto step = [&](hipStream_t st) -> int {
-    k_gm_pc<<<pc == GPC_BLOCK2 ? gn : g, kT, 0, st>>>(S.V, nv, n, S.z, S.gd, pc, pcd);
-    CHNS_HIP(hipGetLastError());
-    int e = launch_apply(c, op, CHNS_FP64, S.z, S.w, st, gated);
+    int e;
+    if (pc == GPC_SCHUR) {
+      k_gm_copyj<<<g, kT, 0, st>>>(S.V, nv, S.pin, S.gd);
+      CHNS_HIP(hipGetLastError());
+      if ((e = ch_schur_apply(c, S.pin, S.z, st))) return e;
+    } else {
+      k_gm_pc<<<pc == GPC_BLOCK2 ? gn : g, kT, 0, st>>>(S.V, nv, n, S.z, S.gd, pc, pcd);
+      CHNS_HIP(hipGetLastError());
+    }
+    e = launch_apply(c, op, CHNS_FP64, S.z, S.w, st, gated);
     if (e) return e;
     for (int pass = 1; pass <= 2; ++pass) {
       k_gm_multidot<<<g, kT, 0, st>>>(S.V, nv, S.w, S.gd, S.part);
@@ -474,7 +545,14 @@ int gmres(Ctx& c, int op, const double* b, double* x, int pc, const double* pcd,
     CHNS_HIP(hipStreamSynchronize(s));
     total += S.gd_host->j;
     k_gm_solve<<<1, 64, 0, s>>>(S.gd);
-    k_gm_update<<<pc == GPC_BLOCK2 ? gn : g, kT, 0, s>>>(x, S.V, nv, n, S.gd, pc, pcd);
+    if (pc == GPC_SCHUR) {
+      k_gm_combine<<<g, kT, 0, s>>>(S.pin, S.V, nv, S.gd);
+      CHNS_HIP(hipGetLastError());
+      if ((rc = ch_schur_apply(c, S.pin, S.pout, s))) return rc;
+      k_add<<<g, kT, 0, s>>>(x, S.pout, nv);
+    } else {
+      k_gm_update<<<pc == GPC_BLOCK2 ? gn : g, kT, 0, s>>>(x, S.V, nv, n, S.gd, pc, pcd);
+    }
     CHNS_HIP(hipGetLastError());
   }
   *iters = total;
@@ -498,8 +576,60 @@ int ensure_coef(Ctx& c, double** buf) {
 // Newton iteration for the Cahn-Hilliard block: X = [phi, mu] holds the
 // guess on entry and the iterate on exit (Def. 6; x <- x - J^-1 R until
 // |R| <= max(rtol |R_0|, atol)).
+// Multigrid hierarchy for the Schur preconditioner: rho = 1 (phase field 1)
+// and the mass shift 1/sqrt(b); lumped mass and work vectors on first use.
+// The pressure solve of the step sets its own phase field afterwards, which
+// invalidates this set-up.
+int schur_setup(Ctx& c, hipStream_t s) {
+  Stepper& S = *c.step;
+  const int64_t n = c.dm.n;
+  int rc;
+  if (!S.mL) {
+    auto A = [&](int64_t cnt) { return (double*)c.dalloc(sizeof(double) * (size_t)cnt); };
+    S.mL = A(n);
+    S.pin = A(2 * n);
+    S.pout = A(2 * n);
+    S.pt1 = A(n);
+    S.pt2 = A(n);
+    S.pz = A(2 * n);
+    S.pj = A(2 * n);
+    if (!S.mL || !S.pin || !S.pout || !S.pt1 || !S.pt2 || !S.pz || !S.pj) return CHNS_ENOMEM;
+    // the mu block of pz stays zero; lumped mass M 1
+    k_fill0<<<blocks_for(2 * n), kT, 0, s>>>(S.pz, 2 * n);
+    k_fill1<<<blocks_for(n), kT, 0, s>>>(S.pt2, n);
+    CHNS_HIP(hipGetLastError());
+    ApplyOut plain{};
+    if ((rc = launch_apply(c, CHNS_OP_MASS, CHNS_FP64, S.pt2, S.mL, s, plain))) return rc;
+  }
+  const double Pe = c.prm.Pe > 0.0 ? c.prm.Pe : 1.0 / (3.0 * c.prm.Cn * c.prm.Cn);
+  const double b = c.prm.dt * c.prm.Cn / (2.0 * Pe);
+  S.sc_scale = c.prm.dt / b;
+  if ((rc = mg_build(c))) return rc;
+  k_fill1<<<blocks_for(n), kT, 0, s>>>(S.pt1, n);
+  CHNS_HIP(hipGetLastError());
+  if ((rc = launch_set_phase(c, S.pt1, nullptr, s))) return rc;
+  c.pp_shift = 1.0 / std::sqrt(b);
+  rc = mg_setup(c, s);
+  return rc;
+}
+
+int newton_ch_impl(Ctx& c, const double* phi0, const double* mu0, const double* ut, const chns_step_opts& o,
+                   bool graphs, hipStream_t s, int* newton_it, int* lin_it, double* rfinal);
+
+// the mass shift is the pressure operator's only while the Newton solve runs
 int newton_ch(Ctx& c, const double* phi0, const double* mu0, const double* ut, const chns_step_opts& o, bool graphs,
               hipStream_t s, int* newton_it, int* lin_it, double* rfinal) {
+  const int rc = newton_ch_impl(c, phi0, mu0, ut, o, graphs, s, newton_it, lin_it, rfinal);
+  if (c.pp_shift != 0.0) {
+    c.pp_shift = 0.0;
+    c.diag_valid = false;
+    if (c.mg) c.mg->setup_valid = false;
+  }
+  return rc;
+}
+
+int newton_ch_impl(Ctx& c, const double* phi0, const double* mu0, const double* ut, const chns_step_opts& o,
+                   bool graphs, hipStream_t s, int* newton_it, int* lin_it, double* rfinal) {
   Stepper& S = *c.step;
   const int64_t n = c.dm.n;
   const int dim = c.dm.dim;
@@ -517,6 +647,8 @@ int newton_ch(Ctx& c, const double* phi0, const double* mu0, const double* ut, c
   double rn = r0;
   int it = 0;
   if ((rc = ensure_coef(c, &c.coef_chj))) return rc;
+  const bool schur = o.ch_pc == CHNS_CH_PC_SCHUR_GMG;
+  if (schur && (rc = schur_setup(c, s))) return rc;
   while (rn > std::max(o.newton_rtol * r0, o.newton_atol) && it < o.max_newton) {
     // Jacobian coefficients [phi^{k+1}, phi^k, u~] and its 2x2 node blocks
     if ((rc = copy(c.coef_chj, S.X, n, s))) return rc;
@@ -527,15 +659,17 @@ int newton_ch(Ctx& c, const double* phi0, const double* mu0, const double* ut, c
       if (!c.w64[k]) c.w64[k] = (double*)c.dalloc(sizeof(double) * n * 3);
       if (!c.w64[k]) return CHNS_ENOMEM;
     }
-    if ((rc = launch_block_diagonal(c, CHNS_OP_CH_JACOBIAN, S.blk, c.w64[6], c.w64[7], s))) return rc;
-    k_inv2<<<blocks_for(n), kT, 0, s>>>(S.blk, S.binv, n);
+    if (!schur) {
+      if ((rc = launch_block_diagonal(c, CHNS_OP_CH_JACOBIAN, S.blk, c.w64[6], c.w64[7], s))) return rc;
+      k_inv2<<<blocks_for(n), kT, 0, s>>>(S.blk, S.binv, n);
+    }
     k_scal<<<g2, kT, 0, s>>>(S.rhs, -1.0, S.R, 2 * n);
     k_fill0<<<g2, kT, 0, s>>>(S.dX, 2 * n);
     CHNS_HIP(hipGetLastError());
     int li = 0;
     double rel = 0.0;
-    rc = gmres(c, CHNS_OP_CH_JACOBIAN, S.rhs, S.dX, GPC_BLOCK2, S.binv, o.lin_rtol, o.max_it, o.restart, graphs, s,
-               &li, &rel);
+    rc = gmres(c, CHNS_OP_CH_JACOBIAN, S.rhs, S.dX, schur ? GPC_SCHUR : GPC_BLOCK2, schur ? S.mL : S.binv,
+               o.lin_rtol, o.max_it, o.restart, graphs, s, &li, &rel);
     *lin_it += li;
     if (rc) return rc;
     k_add<<<g2, kT, 0, s>>>(S.X, S.dX, 2 * n);

@@ -184,7 +184,8 @@ __device__ __forceinline__ double coef_at(const double* ph, int q, int dim, doub
 // (one wave per element, lane (a, b) one entry)
 template <int DIM>
 __global__ __launch_bounds__(64) void k_el_rediscr(const double* __restrict__ phi, int s, const double* __restrict__ Gt,
-                                                   double alpha, double beta, double scale, double* E) {
+                                                   double alpha, double beta, double scale, double* E,
+                                                   const double* __restrict__ Mt, double mshift) {
   constexpr int NC = 1 << DIM, NE = NC * NC;
   __shared__ double cq[NC];
   const int64_t e = blockIdx.x;
@@ -201,7 +202,7 @@ __global__ __launch_bounds__(64) void k_el_rediscr(const double* __restrict__ ph
   if (t < NE) {
     double acc = 0.0;
     for (int q = 0; q < NC; ++q) acc += cq[q] * Gt[q * NE + t];
-    E[e * NE + t] = scale * acc;
+    E[e * NE + t] = scale * acc + mshift * Mt[t];
   }
 }
 
@@ -212,7 +213,8 @@ __global__ __launch_bounds__(64) void k_el_rediscr(const double* __restrict__ ph
 constexpr int kGalPerWave = 64;
 template <int DIM>
 __global__ __launch_bounds__(64) void k_gal_phi(const double* __restrict__ phi, int sf, const double* __restrict__ Ht,
-                                                double alpha, double beta, double scale, double* E, int64_t ne) {
+                                                double alpha, double beta, double scale, double* E, int64_t ne,
+                                                const double* __restrict__ Mt, double mshift) {
   constexpr int NC = 1 << DIM, NE = NC * NC;
   __shared__ double cq[NE];
   const int sc = sf / 2;
@@ -221,6 +223,9 @@ __global__ __launch_bounds__(64) void k_gal_phi(const double* __restrict__ phi, 
   double h[NE];
 #pragma unroll
   for (int k = 0; k < NE; ++k) h[k] = t < NE ? Ht[k * NE + t] : 0.0;
+  // the mass part of a shifted operator is reproduced exactly by the
+  // Galerkin product (Q1 spaces are nested, 2-point Gauss is exact for it)
+  const double m = t < NE ? mshift * Mt[t] : 0.0;
   const int64_t e0 = (int64_t)blockIdx.x * kGalPerWave;
   for (int64_t e = e0; e < e0 + kGalPerWave && e < ne; ++e) {
     const int X = (int)(e % sc), Y = (int)((e / sc) % sc), Z = DIM == 3 ? (int)(e / ((int64_t)sc * sc)) : 0;
@@ -238,7 +243,7 @@ __global__ __launch_bounds__(64) void k_gal_phi(const double* __restrict__ phi, 
       double acc = 0.0;
 #pragma unroll
       for (int k = 0; k < NE; ++k) acc += cq[k] * h[k];
-      E[e * NE + t] = scale * acc;
+      E[e * NE + t] = scale * acc + m;
     }
     __syncthreads();
   }
@@ -319,13 +324,14 @@ __global__ void k_el_stencil(const double* __restrict__ E, int s, double* S64, f
 // inverse diagonal of a uniform fine level straight from its phase field
 template <int DIM>
 __global__ void k_diag_phi(const double* __restrict__ phi, int s, const double* __restrict__ Gt, double alpha,
-                           double beta, double scale, double* dinv64, float* dinv32) {
+                           double beta, double scale, double* dinv64, float* dinv32, const double* __restrict__ Mt,
+                           double mshift) {
   constexpr int NC = 1 << DIM, NE = NC * NC;
   const int64_t s1 = s + 1;
   const int64_t n = DIM == 3 ? s1 * s1 * s1 : s1 * s1;
   for (int64_t node = (int64_t)blockIdx.x * kT + threadIdx.x; node < n; node += (int64_t)gridDim.x * kT) {
     const int I = (int)(node % s1), J = (int)((node / s1) % s1), K = DIM == 3 ? (int)(node / (s1 * s1)) : 0;
-    double acc = 0.0;
+    double acc = 0.0, macc = 0.0;
     for (int u = 0; u < NC; ++u) {
       const int ux = u & 1, uy = (u >> 1) & 1, uz = DIM == 3 ? (u >> 2) & 1 : 0;
       const int ax = I - ux, ay = J - uy, az = K - uz;
@@ -334,9 +340,11 @@ __global__ void k_diag_phi(const double* __restrict__ phi, int s, const double* 
       for (int b = 0; b < NC; ++b)
         ph[b] = phi[((int64_t)(az + ((b >> 2) & 1)) * s1 + (ay + ((b >> 1) & 1))) * s1 + (ax + (b & 1))];
       for (int q = 0; q < NC; ++q) acc += coef_at(ph, q, DIM, alpha, beta) * Gt[q * NE + u * NC + u];
+      macc += Mt[u * NC + u];
     }
-    dinv64[node] = 1.0 / (scale * acc);
-    dinv32[node] = (float)(1.0 / (scale * acc));
+    const double d = scale * acc + mshift * macc;
+    dinv64[node] = 1.0 / d;
+    dinv32[node] = (float)(1.0 / d);
   }
 }
 
@@ -486,14 +494,17 @@ int upload_dm(Ctx& c, const HostMesh& m, DevMesh& d) {
 
 LevelView view(MgLevel& L) { return LevelView{&L.dm, L.phi64, L.phi32, L.slots}; }
 
-// Host: regularised dense inverse (Cholesky of A + (1/n) 1 1^T).
-int dense_inverse(std::vector<double>& A, int n) {
+// Host: dense inverse by Cholesky of A, of A + (scale/n) 1 1^T when
+// regularise (singular pressure operator: the inverse then returns the
+// mean-free solution for a right-hand side in the range).
+int dense_inverse(std::vector<double>& A, int n, bool regularise) {
   double scale = 0.0;
   for (int i = 0; i < n; ++i) scale = std::max(scale, A[(size_t)i * n + i]);
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) A[(size_t)i * n + j] = 0.5 * (A[(size_t)i * n + j] + A[(size_t)j * n + i]);
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) A[(size_t)i * n + j] += scale / n;
+  if (regularise)
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) A[(size_t)i * n + j] += scale / n;
   std::vector<double> Lc((size_t)n * n, 0.0);
   for (int j = 0; j < n; ++j) {
     double d = A[(size_t)j * n + j];
@@ -683,7 +694,8 @@ int vcycle(Ctx& c, int k, const T* r, T* z, hipStream_t s) {
 
 // Host: reference tables of the element-matrix Galerkin products (see the
 // kernels above); bit d of a corner / Gauss point / child index is axis d.
-void reference_tables(int dim, std::vector<double>& tg, std::vector<double>& tp, std::vector<double>& th) {
+void reference_tables(int dim, std::vector<double>& tg, std::vector<double>& tp, std::vector<double>& th,
+                      std::vector<double>& tm) {
   const int nc = 1 << dim, ne = nc * nc;
   const double g = 0.57735026918962576451;
   const double norm = dim == 3 ? 0.125 : 0.25;
@@ -715,6 +727,19 @@ void reference_tables(int dim, std::vector<double>& tg, std::vector<double>& tp,
           w *= f == 1 ? 0.5 : ((f == 0) == (ad == 0) ? 1.0 : 0.0);
         }
         tp[((size_t)c * nc + b) * nc + A] = w;
+      }
+  // reference mass: sum_q N_a N_b at the Gauss points (N = prod (1 +- xi) / 2)
+  tm.assign((size_t)ne, 0.0);
+  for (int q = 0; q < nc; ++q)
+    for (int a = 0; a < nc; ++a)
+      for (int b = 0; b < nc; ++b) {
+        double na = 1.0, nb = 1.0;
+        for (int d = 0; d < dim; ++d) {
+          const double xq = ((q >> d) & 1) ? g : -g;
+          na *= 0.5 * (1.0 + (((a >> d) & 1) ? 1.0 : -1.0) * xq);
+          nb *= 0.5 * (1.0 + (((b >> d) & 1) ? 1.0 : -1.0) * xq);
+        }
+        tm[(size_t)a * nc + b] += na * nb;
       }
   th.assign((size_t)ne * ne, 0.0);
   for (int c = 0; c < nc; ++c)
@@ -818,9 +843,10 @@ int mg_build(Ctx& c) {
         goto fail;
       }
     }
-    std::vector<double> tg, tp, th;
-    reference_tables(c.dm.dim, tg, tp, th);
-    if ((rc = upload(c, &mg->tab_G, tg)) || (rc = upload(c, &mg->tab_P, tp))) goto fail;
+    std::vector<double> tg, tp, th, tm;
+    reference_tables(c.dm.dim, tg, tp, th, tm);
+    if ((rc = upload(c, &mg->tab_G, tg)) || (rc = upload(c, &mg->tab_P, tp)) || (rc = upload(c, &mg->tab_M, tm)))
+      goto fail;
     if (c.dm.structured && mg->lv[1].E64 && (rc = upload(c, &mg->tab_H, th))) goto fail;
   }
   {
@@ -867,6 +893,8 @@ int mg_setup(Ctx& c, hipStream_t s) {
     const int dim = c.dm.dim;
     // (h/2)^(d-2) of a uniform level with s cells per edge
     auto lscale = [&](int s) { return dim == 3 ? 0.5 / s : 1.0; };
+    // mass shift of a uniform level: g (h/2)^d
+    auto mshift = [&](int s) { return c.pp_shift * std::pow(0.5 / s, dim); };
     if (mg.tab_H) {
       // uniform fine level: inverse diagonal straight from the phase field,
       // first coarse level's element matrices as Galerkin products
@@ -874,14 +902,14 @@ int mg_setup(Ctx& c, hipStream_t s) {
       const unsigned gl = (unsigned)((ncoarse + kGalPerWave - 1) / kGalPerWave);
       if (dim == 3) {
         k_diag_phi<3><<<blocks(c.dm.n), kT, 0, st>>>(c.phi64, c.dm.side, mg.tab_G, al, be, lscale(c.dm.side),
-                                                      mg.fine_dinv64, mg.fine_dinv32);
+                                                      mg.fine_dinv64, mg.fine_dinv32, mg.tab_M, mshift(c.dm.side));
         k_gal_phi<3><<<gl, 64, 0, st>>>(c.phi64, c.dm.side, mg.tab_H, al, be, lscale(c.dm.side), mg.lv[1].E64,
-                                         ncoarse);
+                                         ncoarse, mg.tab_M, mshift(c.dm.side / 2));
       } else {
         k_diag_phi<2><<<blocks(c.dm.n), kT, 0, st>>>(c.phi64, c.dm.side, mg.tab_G, al, be, lscale(c.dm.side),
-                                                      mg.fine_dinv64, mg.fine_dinv32);
+                                                      mg.fine_dinv64, mg.fine_dinv32, mg.tab_M, mshift(c.dm.side));
         k_gal_phi<2><<<gl, 64, 0, st>>>(c.phi64, c.dm.side, mg.tab_H, al, be, lscale(c.dm.side), mg.lv[1].E64,
-                                         ncoarse);
+                                         ncoarse, mg.tab_M, mshift(c.dm.side / 2));
       }
       CHNS_HIP(hipGetLastError());
     } else {
@@ -910,8 +938,12 @@ int mg_setup(Ctx& c, hipStream_t s) {
         const bool from_above = k == 1 ? mg.tab_H != nullptr : mg.lv[k - 1].E64 != nullptr;
         const unsigned ne = (unsigned)((int64_t)1 << (dim * L.host.max_level));
         if (!from_above) {
-          if (dim == 3) k_el_rediscr<3><<<ne, 64, 0, st>>>(L.phi64, L.dm.side, mg.tab_G, al, be, lscale(L.dm.side), L.E64);
-          else k_el_rediscr<2><<<ne, 64, 0, st>>>(L.phi64, L.dm.side, mg.tab_G, al, be, lscale(L.dm.side), L.E64);
+          if (dim == 3)
+            k_el_rediscr<3><<<ne, 64, 0, st>>>(L.phi64, L.dm.side, mg.tab_G, al, be, lscale(L.dm.side), L.E64,
+                                               mg.tab_M, mshift(L.dm.side));
+          else
+            k_el_rediscr<2><<<ne, 64, 0, st>>>(L.phi64, L.dm.side, mg.tab_G, al, be, lscale(L.dm.side), L.E64,
+                                               mg.tab_M, mshift(L.dm.side));
         }
         const bool last = k + 1 == mg.lv.size();
         double* d64 = last ? nullptr : L.dinv64;
@@ -948,11 +980,23 @@ int mg_setup(Ctx& c, hipStream_t s) {
     CHNS_HIP(hipGetLastError());
     return CHNS_OK;
   };
-  if ((rc = run_captured(c, &mg.setup_exec, s, device_part))) return rc;
+  // the captured kernels carry the shift: one graph per shift value
+  hipGraphExec_t* exec = &mg.setup_exec;
+  if (c.pp_shift != 0.0) {
+    exec = nullptr;
+    for (auto& e : mg.shifted_setups)
+      if (e.first == c.pp_shift) exec = &e.second;
+    if (!exec) {
+      mg.shifted_setups.push_back({c.pp_shift, nullptr});
+      exec = &mg.shifted_setups.back().second;
+    }
+  }
+  if ((rc = run_captured(c, exec, s, device_part))) return rc;
   std::vector<double> A((size_t)n * n);
   CHNS_HIP(hipMemcpyAsync(A.data(), B.dense, sizeof(double) * A.size(), hipMemcpyDeviceToHost, s));
   CHNS_HIP(hipStreamSynchronize(s));
-  if ((rc = dense_inverse(A, n))) {
+  // a shifted operator is definite: no rank-one regularisation
+  if ((rc = dense_inverse(A, n, c.pp_shift == 0.0))) {
     set_error("coarsest multigrid operator is not positive semi-definite");
     return rc;
   }
