@@ -376,14 +376,18 @@ def bubble_steps(torch, lmax, nsteps, ch_pc="block"):
     mesh = Mesh(dim=3, min_level=5, max_level=lmax, rule="sphere_band", centres=[(0.5, 0.3, 0.5)], radii=[0.15],
                 band=3 * cn)
     t_mesh = time.time() - t0
+    print(f"# mesh built in {t_mesh:.1f} s: {mesh.n_elems} leaves, {mesh.n_nodes} nodes", file=sys.stderr, flush=True)
     x_unit = ci.unit_coords(mesh.node_coords(), lmax)
     ctx = Context(mesh, Re=35.0, We=10.0, Cn=cn, Fr=1.0, rho_plus=1.0, rho_minus=1e-3, eta_plus=1.0,
                   eta_minus=1e-2, dt=5e-4)
+    print(f"# context ready ({time.time() - t0:.1f} s)", file=sys.stderr, flush=True)
     dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
     n = mesh.n_nodes
     phi = dev(ci.phi_bubble(x_unit, cn=cn))
     st = {"u": dev(np.zeros(3 * n)), "u_prev": dev(np.zeros(3 * n)), "p": dev(np.zeros(n)), "phi": phi,
           "mu": ctx.initial_mu(phi)}
+    torch.cuda.synchronize()
+    print(f"# initial state ready ({time.time() - t0:.1f} s)", file=sys.stderr, flush=True)
     out = {"workload": f"3D rising bubble, adaptive levels 5-{lmax} (band 3 Cn, Cn 0.005), density ratio 1000, "
                        "viscosity ratio 100, Re 35, We 10, dt 5e-4",
            "ch_preconditioner": ch_pc,

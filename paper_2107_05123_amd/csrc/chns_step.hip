@@ -67,7 +67,9 @@ struct Stepper {
   // Cahn-Hilliard Schur-complement preconditioner: lumped mass, work vectors
   double *mL = nullptr, *pin = nullptr, *pout = nullptr, *pt1 = nullptr, *pt2 = nullptr, *pz = nullptr,
          *pj = nullptr;
+  double *dMinv = nullptr, *cx = nullptr, *cr = nullptr, *cd = nullptr;  // Chebyshev solve with M
   double sc_scale = 0.0;  // dt / b of the Schur approximation
+  double m_lmax = 0.0;    // Gershgorin bound of eig(D_M^-1 M)
 };
 
 namespace {
@@ -332,7 +334,6 @@ __global__ void k_gm_combine(double* out, const double* V, int64_t nv, const GmD
     out[i] = a;
   }
 }
-__global__ void k_mul(double* out, const double* a, const double* b, int64_t n) { GRID_LOOP(i, n) out[i] = a[i] * b[i]; }
 // dphi = s t (into the output and into the phi block of pz, whose mu block stays 0)
 __global__ void k_sc_phi(double* out, double* pz, const double* t, double s, int64_t n) {
   GRID_LOOP(i, n) {
@@ -341,9 +342,35 @@ __global__ void k_sc_phi(double* out, double* pz, const double* t, double s, int
     pz[i] = v;
   }
 }
-// dmu = -2 mL^-1 (v_mu - C dphi)
-__global__ void k_sc_mu(double* out_mu, const double* v_mu, const double* cdphi, const double* mL, int64_t n) {
-  GRID_LOOP(i, n) out_mu[i] = -2.0 * (v_mu[i] - cdphi[i]) / mL[i];
+// Chebyshev iteration for M x = r (Jacobi-scaled, zero start), fixed degree:
+// start: r = v_mu - C dphi, x = 0, d = D^-1 r / theta
+__global__ void k_ch_start(double* r, double* x, double* d, const double* v_mu, const double* cdphi,
+                           const double* dinv, double theta, int64_t n) {
+  GRID_LOOP(i, n) {
+    const double ri = v_mu[i] - cdphi[i];
+    r[i] = ri;
+    x[i] = 0.0;
+    d[i] = dinv[i] * ri / theta;
+  }
+}
+// x += d; r -= M d (md); d = c1 d + c2 D^-1 r
+__global__ void k_ch_step(double* x, double* r, double* d, const double* md, const double* dinv, double c1, double c2,
+                          int64_t n) {
+  GRID_LOOP(i, n) {
+    const double di = d[i];
+    x[i] += di;
+    const double ri = r[i] - md[i];
+    r[i] = ri;
+    d[i] = c1 * di + c2 * dinv[i] * ri;
+  }
+}
+// out = s (x + d)  (the last step's x update folded in)
+__global__ void k_ch_finish(double* out, const double* x, const double* d, double s, int64_t n) {
+  GRID_LOOP(i, n) out[i] = s * (x[i] + d[i]);
+}
+// lambda_i = (M 1)_i / M_ii (Gershgorin row bound of D^-1 M, all entries >= 0)
+__global__ void k_ratio(double* out, const double* ml, const double* dinv, int64_t n) {
+  GRID_LOOP(i, n) out[i] = ml[i] * dinv[i];
 }
 
 struct Clock {
@@ -435,19 +462,32 @@ int dot_sync(Ctx& c, const double* a, const double* b, int64_t n, hipStream_t s,
 // rho = 1 and the mass shift 1/sqrt(b).  C dphi is the mu block of J [dphi, 0].
 // A fixed linear map (fixed cycles), so plain right-preconditioned GMRES
 // applies.  in / out: 2n, in = [v_phi, v_mu].
+constexpr int kMassCheb = 8;  // Chebyshev degree of the mass solve
 int ch_schur_apply(Ctx& c, const double* in, double* out, hipStream_t s) {
   Stepper& S = *c.step;
   const int64_t n = c.dm.n;
   const unsigned g = blocks_for(n);
   int rc;
+  ApplyOut plain{};
   if ((rc = mg_vcycle64(c, in, S.pt1, s))) return rc;
-  k_mul<<<g, kT, 0, s>>>(S.pt2, S.mL, S.pt1, n);
+  if ((rc = launch_apply(c, CHNS_OP_MASS, CHNS_FP64, S.pt1, S.pt2, s, plain))) return rc;
   if ((rc = mg_vcycle64(c, S.pt2, S.pt1, s))) return rc;
   k_sc_phi<<<g, kT, 0, s>>>(out, S.pz, S.pt1, S.sc_scale, n);
   CHNS_HIP(hipGetLastError());
-  ApplyOut plain{};
   if ((rc = launch_apply(c, CHNS_OP_CH_JACOBIAN, CHNS_FP64, S.pz, S.pj, s, plain))) return rc;
-  k_sc_mu<<<g, kT, 0, s>>>(out + n, in + n, S.pj + n, S.mL, n);
+  // dmu = -2 M^-1 (v_mu - C dphi): Chebyshev on [lmax / 27, lmax] (the
+  // Jacobi-scaled Q1 mass spectrum spans a factor 3^d on uniform meshes)
+  const double lmax = S.m_lmax, lmin = lmax / (c.dm.dim == 3 ? 27.0 : 9.0);
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+  k_ch_start<<<g, kT, 0, s>>>(S.cr, S.cx, S.cd, in + n, S.pj + n, S.dMinv, theta, n);
+  double rho = 1.0 / sigma;
+  for (int k = 1; k < kMassCheb; ++k) {
+    if ((rc = launch_apply(c, CHNS_OP_MASS, CHNS_FP64, S.cd, S.pt2, s, plain))) return rc;
+    const double rho1 = 1.0 / (2.0 * sigma - rho);
+    k_ch_step<<<g, kT, 0, s>>>(S.cx, S.cr, S.cd, S.pt2, S.dMinv, rho1 * rho, 2.0 * rho1 / delta, n);
+    rho = rho1;
+  }
+  k_ch_finish<<<g, kT, 0, s>>>(out + n, S.cx, S.cd, -2.0, n);
   CHNS_HIP(hipGetLastError());
   return CHNS_OK;
 }
@@ -587,6 +627,11 @@ int schur_setup(Ctx& c, hipStream_t s) {
   if (!S.mL) {
     auto A = [&](int64_t cnt) { return (double*)c.dalloc(sizeof(double) * (size_t)cnt); };
     S.mL = A(n);
+    S.dMinv = A(n);
+    S.cx = A(n);
+    S.cr = A(n);
+    S.cd = A(n);
+    if (!S.dMinv || !S.cx || !S.cr || !S.cd) return CHNS_ENOMEM;
     S.pin = A(2 * n);
     S.pout = A(2 * n);
     S.pt1 = A(n);
@@ -600,6 +645,14 @@ int schur_setup(Ctx& c, hipStream_t s) {
     CHNS_HIP(hipGetLastError());
     ApplyOut plain{};
     if ((rc = launch_apply(c, CHNS_OP_MASS, CHNS_FP64, S.pt2, S.mL, s, plain))) return rc;
+    // inverse mass diagonal and the Gershgorin bound max_i (M 1)_i / M_ii
+    if ((rc = launch_diagonal(c, CHNS_OP_MASS, CHNS_FP64, S.dMinv, true, s))) return rc;
+    k_ratio<<<blocks_for(n), kT, 0, s>>>(S.pt1, S.mL, S.dMinv, n);
+    CHNS_HIP(hipGetLastError());
+    std::vector<double> ratio((size_t)n);
+    CHNS_HIP(hipMemcpyAsync(ratio.data(), S.pt1, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    CHNS_HIP(hipStreamSynchronize(s));
+    S.m_lmax = *std::max_element(ratio.begin(), ratio.end());
   }
   const double Pe = c.prm.Pe > 0.0 ? c.prm.Pe : 1.0 / (3.0 * c.prm.Cn * c.prm.Cn);
   const double b = c.prm.dt * c.prm.Cn / (2.0 * Pe);
