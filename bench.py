@@ -418,7 +418,7 @@ def main():
                     help="uniform_l7: the benchmark line; adaptive: levels 5..--max-level band mesh solves; "
                          "bubble_steps: projection steps of the 3D rising bubble")
     ap.add_argument("--max-level", type=int, default=10)
-    ap.add_argument("--ch-pc", default="block", choices=("block", "schur"),
+    ap.add_argument("--ch-pc", default="schur", choices=("block", "schur"),
                     help="bubble_steps: preconditioner of the Cahn-Hilliard GMRES (2x2 node-block Jacobi, or the "
                          "block-triangular multigrid Schur-complement preconditioner)")
     ap.add_argument("--summarize-stats", nargs=5, metavar=("DB", "OUT_MD", "TITLE", "COMMAND", "NOTE"),
