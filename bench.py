@@ -366,7 +366,7 @@ def adaptive_workload(torch, lmax):
     return out
 
 
-def bubble_steps(torch, lmax, nsteps, ch_pc="block", restart=16):
+def bubble_steps(torch, lmax, nsteps, ch_pc="block", restart=16, vp_pc="jacobi", modes=("fp64", "mixed")):
     """Projection time steps of the 3D rising bubble (density ratio 1000,
     viscosity ratio 100, Re 35, We 10, Cn 0.005, dt 5e-4) on the adaptive
     octree of levels 5..lmax refined within 3 Cn of the interface."""
@@ -390,13 +390,13 @@ def bubble_steps(torch, lmax, nsteps, ch_pc="block", restart=16):
     print(f"# initial state ready ({time.time() - t0:.1f} s)", file=sys.stderr, flush=True)
     out = {"workload": f"3D rising bubble, adaptive levels 5-{lmax} (band 3 Cn, Cn 0.005), density ratio 1000, "
                        "viscosity ratio 100, Re 35, We 10, dt 5e-4",
-           "ch_preconditioner": ch_pc, "gmres_restart": restart,
+           "ch_preconditioner": ch_pc, "vp_preconditioner": vp_pc, "gmres_restart": restart,
            "n_elems": mesh.n_elems, "n_nodes": n, "host_mesh_build_s": t_mesh, "steps": []}
-    for mode in ("fp64", "mixed"):
+    for mode in modes:
         for k in range(nsteps):
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            s = ctx.advance_step(st, pp_pc="gmg", pp_mode=mode, ch_pc=ch_pc, restart=restart)
+            s = ctx.advance_step(st, pp_pc="gmg", pp_mode=mode, ch_pc=ch_pc, restart=restart, vp_pc=vp_pc)
             torch.cuda.synchronize()
             s["wall_s"] = time.perf_counter() - t1
             s["pressure_mode"] = mode
@@ -424,6 +424,11 @@ def main():
     ap.add_argument("--ch-pc", default="schur", choices=("block", "schur"),
                     help="bubble_steps: preconditioner of the Cahn-Hilliard GMRES (2x2 node-block Jacobi, or the "
                          "block-triangular multigrid Schur-complement preconditioner)")
+    ap.add_argument("--vp-pc", default="gmg", choices=("jacobi", "gmg"),
+                    help="bubble_steps: preconditioner of the velocity-prediction GMRES (Jacobi, or multigrid "
+                         "V-cycles of the scalar mass + viscous operator per component)")
+    ap.add_argument("--pp-modes", default="fp64,mixed",
+                    help="bubble_steps: pressure solve modes to step with, in order (comma-separated)")
     ap.add_argument("--summarize-stats", nargs=5, metavar=("DB", "OUT_MD", "TITLE", "COMMAND", "NOTE"),
                     help="write the kernel-statistics table of a rocprofv3 database (no GPU needed)")
     ap.add_argument("--summarize-pmc", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON", "CMD1", "CMD2"),
@@ -447,7 +452,8 @@ def main():
         print(json.dumps(adaptive_workload(torch, args.max_level)))
         return
     if args.workload == "bubble_steps":
-        print(json.dumps(bubble_steps(torch, args.max_level, args.steps, args.ch_pc, args.restart)))
+        print(json.dumps(bubble_steps(torch, args.max_level, args.steps, args.ch_pc, args.restart, args.vp_pc,
+                                      tuple(args.pp_modes.split(",")))))
         return
     if args.profile_run == "chns":
         profile_chns(torch)

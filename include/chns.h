@@ -142,7 +142,12 @@ enum {
                               2 fields (phi block then mu block)                */
   CHNS_OP_MASS_RHO = 3,    /* (w, rho(phi*~) u): velocity update (Def. 5), dim
                               fields, wall rows identity                        */
-  CHNS_OP_MASS = 4         /* (q, u): plain Q1 mass, 1 field                    */
+  CHNS_OP_MASS = 4,        /* (q, u): plain Q1 mass, 1 field                    */
+  CHNS_OP_MOMENTUM_SCALAR = 5 /* (w, rho(phi*~)/dt u) + (grad w, eta(phi*~)/(2 Re)
+                              grad u): the mass and viscous part of Def. 3 for one
+                              velocity component, natural BCs (no wall rows); the
+                              operator of the momentum multigrid preconditioner;
+                              1 field, uses the phase field                     */
 };
 enum { CHNS_FP64 = 0, CHNS_FP32 = 1 };
 
@@ -259,9 +264,15 @@ typedef struct chns_step_opts {
                         * CHNS_CH_PC_SCHUR_GMG (block lower-triangular with a
                         * multigrid Schur-complement approximation; needs a
                         * mesh of max_level >= 2)                              */
+  int vp_pc;           /* preconditioner of the velocity-prediction GMRES:
+                        * CHNS_VP_PC_JACOBI (default) or CHNS_VP_PC_GMG (one
+                        * V-cycle of CHNS_OP_MOMENTUM_SCALAR per velocity
+                        * component on the interior rows, identity on the wall
+                        * rows; needs a mesh of max_level >= 2)                 */
 } chns_step_opts;
 
 enum { CHNS_CH_PC_BLOCK_JACOBI = 0, CHNS_CH_PC_SCHUR_GMG = 1 };
+enum { CHNS_VP_PC_JACOBI = 0, CHNS_VP_PC_GMG = 1 };
 
 typedef struct chns_step_stats {
   int newton_iterations[4]; /* per block                                        */
@@ -282,7 +293,10 @@ typedef struct chns_step_stats {
  * (M + sqrt(b) K), b = dt Cn / (2 Pe), is applied with two multigrid V-cycles;
  * the multigrid hierarchy is shared with the pressure solve and set up again
  * for it),
- * velocity prediction (GMRES with Jacobi), pressure Poisson (CG) and velocity
+ * velocity prediction (GMRES with Jacobi, or with opts->vp_pc =
+ * CHNS_VP_PC_GMG multigrid V-cycles of the scalar mass + viscous operator of
+ * each component, hierarchy set up for it and again for the pressure solve),
+ * pressure Poisson (CG) and velocity
  * update (CG on the rho-weighted mass matrix), then
  * (u_prev, u, p, phi, mu) <- (u^k, u^{k+1}, p^{k+1}, phi^{k+1}, mu^{k+1}).
  * Synchronises `stream`.  ENOCONV if a solve or Newton stalls; the state is

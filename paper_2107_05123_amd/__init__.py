@@ -147,8 +147,8 @@ class Context:
     """Device state for one mesh and parameter set (uploads the mesh to the
     current device)."""
 
-    PRESSURE, MOMENTUM, CH_JACOBIAN, MASS_RHO, MASS = (L.OP_PRESSURE, L.OP_MOMENTUM, L.OP_CH_JACOBIAN,
-                                                       L.OP_MASS_RHO, L.OP_MASS)
+    PRESSURE, MOMENTUM, CH_JACOBIAN, MASS_RHO, MASS, MOMENTUM_SCALAR = (
+        L.OP_PRESSURE, L.OP_MOMENTUM, L.OP_CH_JACOBIAN, L.OP_MASS_RHO, L.OP_MASS, L.OP_MOMENTUM_SCALAR)
 
     def __init__(self, mesh: Mesh, Re=100.0, We=1.0, Cn=0.01, Pe=0.0, Fr=1.0, rho_plus=1.0, rho_minus=1.0,
                  eta_plus=1.0, eta_minus=1.0, dt=1e-3, C_I=6.0, gravity_axis=1):
@@ -164,7 +164,7 @@ class Context:
 
     def fields(self, op: int) -> int:
         return {L.OP_PRESSURE: 1, L.OP_MASS: 1, L.OP_MASS_RHO: self.dim, L.OP_MOMENTUM: self.dim,
-                L.OP_CH_JACOBIAN: 2}[op]
+                L.OP_CH_JACOBIAN: 2, L.OP_MOMENTUM_SCALAR: 1}[op]
 
     def set_phase_field(self, phi, phi_prev=None, stream=None):
         import torch
@@ -254,7 +254,7 @@ class Context:
 
     def advance_step(self, state: dict, blocks=2, newton_rtol=1e-8, newton_atol=1e-12, max_newton=20,
                      lin_rtol=1e-8, max_it=5000, restart=64, pp_pc="jacobi", pp_mode="fp64", graphs=True,
-                     ch_pc="block", stream=None):
+                     ch_pc="block", vp_pc="jacobi", stream=None):
         """state: dict of device FP64 tensors u, u_prev (dim*n), p, phi, mu (n), updated in place."""
         import torch
         d = self.dim * self.n
@@ -264,7 +264,8 @@ class Context:
         o = L.StepOpts(blocks, newton_rtol, newton_atol, max_newton, lin_rtol, max_it, restart,
                        {"jacobi": L.PC_JACOBI, "gmg": L.PC_GMG}[pp_pc],
                        {"fp64": L.MODE_FP64, "mixed": L.MODE_MIXED_IR}[pp_mode], 0 if graphs else 1,
-                       {"block": L.CH_PC_BLOCK_JACOBI, "schur": L.CH_PC_SCHUR_GMG}[ch_pc])
+                       {"block": L.CH_PC_BLOCK_JACOBI, "schur": L.CH_PC_SCHUR_GMG}[ch_pc],
+                       {"jacobi": L.VP_PC_JACOBI, "gmg": L.VP_PC_GMG}[vp_pc])
         ss = L.StepStats()
         L.check(L.lib().chns_advance_step(self._h, C.byref(st), C.byref(o), C.byref(ss), _stream_ptr(stream)))
         return {"newton": list(ss.newton_iterations)[:blocks], "ch_iterations": ss.ch_iterations,

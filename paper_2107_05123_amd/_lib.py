@@ -9,8 +9,9 @@ LIB_PATH = os.path.join(HERE, "libchns.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, ESTATE = 0, -1, -2, -3, -4, -5
 CH_PC_BLOCK_JACOBI, CH_PC_SCHUR_GMG = 0, 1
+VP_PC_JACOBI, VP_PC_GMG = 0, 1
 RULE_UNIFORM, RULE_SPHERE_BAND, RULE_MULTI_SPHERE_BAND, RULE_CALLBACK = 0, 1, 2, 3
-OP_PRESSURE, OP_MOMENTUM, OP_CH_JACOBIAN, OP_MASS_RHO, OP_MASS = 0, 1, 2, 3, 4
+OP_PRESSURE, OP_MOMENTUM, OP_CH_JACOBIAN, OP_MASS_RHO, OP_MASS, OP_MOMENTUM_SCALAR = 0, 1, 2, 3, 4, 5
 FP64, FP32 = 0, 1
 PC_JACOBI, PC_GMG, PC_LEARNED, PC_NONE = 0, 1, 2, 3
 MODE_FP64, MODE_MIXED_IR = 0, 1
@@ -68,7 +69,7 @@ class StepOpts(C.Structure):
     _fields_ = [
         ("blocks", C.c_int), ("newton_rtol", C.c_double), ("newton_atol", C.c_double), ("max_newton", C.c_int),
         ("lin_rtol", C.c_double), ("max_it", C.c_int), ("restart", C.c_int), ("pp_pc", C.c_int),
-        ("pp_mode", C.c_int), ("no_graphs", C.c_int), ("ch_pc", C.c_int),
+        ("pp_mode", C.c_int), ("no_graphs", C.c_int), ("ch_pc", C.c_int), ("vp_pc", C.c_int),
     ]
 
 

@@ -60,6 +60,7 @@ Ctx::~Ctx() {
   destroy_stepper(*this);
   unet_destroy(*this);
   if (mg && mg->setup_exec) (void)hipGraphExecDestroy(mg->setup_exec);
+  if (mg && mg->mom_setup_exec) (void)hipGraphExecDestroy(mg->mom_setup_exec);
   if (mg)
     for (auto& e : mg->shifted_setups)
       if (e.second) (void)hipGraphExecDestroy(e.second);
@@ -428,6 +429,10 @@ int chns_advance_step(chns_ctx* ctx, chns_state* state, const chns_step_opts* op
   }
   if (o.ch_pc != CHNS_CH_PC_BLOCK_JACOBI && o.ch_pc != CHNS_CH_PC_SCHUR_GMG) {
     set_error("unknown Cahn-Hilliard preconditioner");
+    return CHNS_EINVAL;
+  }
+  if (o.vp_pc != CHNS_VP_PC_JACOBI && o.vp_pc != CHNS_VP_PC_GMG) {
+    set_error("unknown velocity-prediction preconditioner");
     return CHNS_EINVAL;
   }
   chns_step_stats st{};

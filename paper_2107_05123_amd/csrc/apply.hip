@@ -71,7 +71,7 @@ __host__ __device__ constexpr int insert0(int r, int d) { return (r & ((1 << d) 
 
 // Pressure Poisson: y_a = sum_q detJ (2/h)^2 c_q gradN_a . grad x,
 // c_q = 1/rho(clamp(phi_q)) (Def. 2, VMS pressure Poisson; pull back remark).
-template <int DIM, typename T>
+template <int DIM, typename T, bool RCP = true>
 __device__ __forceinline__ void elem_pp(const T* x, const T* ph, T A, T Bc, T* y) {
   constexpr int NC = 1 << DIM, H = NC / 2;
   T q[NC];
@@ -80,7 +80,11 @@ __device__ __forceinline__ void elem_pp(const T* x, const T* ph, T A, T Bc, T* y
   all_stages<DIM>(q);
   T c[NC];
 #pragma unroll
-  for (int i = 0; i < NC; ++i) c[i] = rcp_t(__builtin_fma(A, clamp_t(q[i], T(NC)), Bc));
+  for (int i = 0; i < NC; ++i) {
+    // coefficient 1 / (A phi + B) (pressure) or A phi + B (viscosity)
+    const T lin = __builtin_fma(A, clamp_t(q[i], T(NC)), Bc);
+    c[i] = RCP ? rcp_t(lin) : lin;
+  }
 #pragma unroll
   for (int i = 0; i < NC; ++i) y[i] = T(0);
 #pragma unroll
@@ -141,7 +145,7 @@ __device__ __forceinline__ void elem_mass_apply(const T* x, const T* r, T* y) {
 // 1 identity rows on the walls (y = x), 2 zero rows on the walls.
 enum OpKind {
   K_PP = 0, K_MASS = 1, K_MASS_RHO = 2, K_CH_RES = 3, K_CH_JAC = 4, K_VP = 5, K_VP_RHS = 6, K_PP_RHS = 7,
-  K_VU_RHS = 8, K_ENERGY = 9, K_PPS = 10
+  K_VU_RHS = 8, K_ENERGY = 9, K_PPS = 10, K_VPS = 11
 };
 template <int OP, int DIM>
 struct Traits;
@@ -162,6 +166,7 @@ CHNS_TRAITS(K_PP_RHS, 0, 3 * DIM + 3, 1, false, 0)
 CHNS_TRAITS(K_VU_RHS, 0, 3 * DIM + 4, DIM, false, 2)
 CHNS_TRAITS(K_ENERGY, 0, 2 + DIM, 1, false, 0)
 CHNS_TRAITS(K_PPS, 1, 1, 1, false, 0)  // pressure operator + shift * mass
+CHNS_TRAITS(K_VPS, 1, 1, 1, false, 0)  // scalar momentum: K_{eta/(2 Re)} + M_{rho/dt}
 #undef CHNS_TRAITS
 
 constexpr int kMaxCoef = kMaxCoefFields;
@@ -561,8 +566,19 @@ __device__ __forceinline__ void brick_body(const BrickArgs<T>& a) {
   // per-level folded constants (powers of two are exact); FP32 fields carry
   // 1 + phi, so rho = (beta - alpha) + alpha (1 + phi)
   const double beta0 = sizeof(T) == 8 ? a.beta : a.beta - a.alpha;
-  T A = 0, Bc = 0, Ms = 0;
+  T A = 0, Bc = 0, Ms = 0, Am = 0, Bm = 0;
   if constexpr (OP == K_PPS) Ms = T(a.shift * ldexp(1.0, -(lev + 1) * DIM - 2 * DIM));
+  if constexpr (OP == K_VPS) {
+    // viscosity eta/(2 Re) = (gam phi + xi)/(2 Re) on the stiffness (folded
+    // like the pressure coefficient, without the reciprocal) and rho/dt on
+    // the mass
+    const int es = (lev + 1) * (DIM - 2) + 2 * DIM, em = -(lev + 1) * DIM - 2 * DIM;
+    const double g2 = a.phys.gam / (2.0 * a.phys.Re), x2 = a.phys.xi / (2.0 * a.phys.Re);
+    A = T(ldexp(g2, -es - DIM));
+    Bc = T(ldexp(sizeof(T) == 8 ? x2 : x2 - g2, -es));
+    Am = T(ldexp(a.alpha / a.phys.dt, em - DIM));
+    Bm = T(ldexp(beta0 / a.phys.dt, em));
+  }
   if constexpr (OP == K_PP || OP == K_PPS) {
     // c~ = detJ (2/h)^2 / 4^d / rho = 1 / (rho / K); K = 2^{-(lev+1)(d-2) - 2d}
     const int e = (lev + 1) * (DIM - 2) + 2 * DIM;
@@ -647,7 +663,7 @@ __device__ __forceinline__ void brick_body(const BrickArgs<T>& a) {
         int64_t e;
         if constexpr (STRUCT) e = entry(z, p);
         else e = eo[k];
-        if constexpr (OP == K_PP || OP == K_PPS) {
+        if constexpr (OP == K_PP || OP == K_PPS || OP == K_VPS) {
           if (a.sm_r) v[0] = lay[buf][bl][0][p] + a.sm_w * a.sm_d[e] * (a.sm_r[e] - v[0]);
         }
 #pragma unroll
@@ -735,7 +751,7 @@ __device__ __forceinline__ void brick_body(const BrickArgs<T>& a) {
     }
   };
   if (active) read_half(0, 1);
-  constexpr int kUnroll = (OP == K_PP || OP == K_PPS || OP == K_MASS) ? B : 1;
+  constexpr int kUnroll = (OP == K_PP || OP == K_PPS || OP == K_VPS || OP == K_MASS) ? B : 1;
 #pragma unroll kUnroll
   for (int ez = 0; ez < B; ++ez) {
     load_emit_entries(ez);
@@ -759,6 +775,13 @@ __device__ __forceinline__ void brick_body(const BrickArgs<T>& a) {
 #pragma unroll
           for (int i = 0; i < NC; ++i) ye[0][i] += ym[i];
         }
+      } else if constexpr (OP == K_VPS) {
+        elem_pp<DIM, T, false>(xc[0], cc[0], A, Bc, ye[0]);
+        T r[NC], ym[NC];
+        elem_mass_coef<DIM, T, true>(cc[0], Am, Bm, r);
+        elem_mass_apply<DIM, T>(xc[0], r, ym);
+#pragma unroll
+        for (int i = 0; i < NC; ++i) ye[0][i] += ym[i];
       } else if constexpr (OP == K_MASS || OP == K_MASS_RHO) {
         T r[NC];
         elem_mass_coef<DIM, T, OP == K_MASS_RHO>(cc[0], A, Bc, r);
@@ -951,7 +974,8 @@ template <int DIM, int B, typename T, int OP, bool STRUCT>
 void launch_one(int64_t grid, hipStream_t s, const BrickArgs<T>& a) {
   const dim3 g((unsigned)grid), blk(64);
   constexpr bool W = whole_fits<DIM, B, T, OP>();
-  if constexpr (OP == K_PP || OP == K_PPS || OP == K_MASS) k_brick_o4<DIM, B, T, OP, W, STRUCT><<<g, blk, 0, s>>>(a);
+  if constexpr (OP == K_PP || OP == K_PPS || OP == K_VPS || OP == K_MASS)
+    k_brick_o4<DIM, B, T, OP, W, STRUCT><<<g, blk, 0, s>>>(a);
   else k_brick<DIM, B, T, OP, W, STRUCT><<<g, blk, 0, s>>>(a);
 }
 template <int DIM, typename T, int OP, bool STRUCT>
@@ -1016,7 +1040,7 @@ Phys phys_of(const chns_params& p) {
 }
 
 const char* op_tag(int op, bool fp64) {
-  static const char* tags[11][2] = {{"pp_brick_fp64", "pp_brick_fp32"},
+  static const char* tags[12][2] = {{"pp_brick_fp64", "pp_brick_fp32"},
                                     {"mass_brick_fp64", "mass_brick_fp32"},
                                     {"massrho_brick_fp64", "massrho_brick_fp32"},
                                     {"chres_brick_fp64", "chres_brick_fp32"},
@@ -1026,7 +1050,8 @@ const char* op_tag(int op, bool fp64) {
                                     {"pprhs_brick_fp64", "pprhs_brick_fp32"},
                                     {"vurhs_brick_fp64", "vurhs_brick_fp32"},
                                     {"energy_brick_fp64", "energy_brick_fp32"},
-                                    {"pps_brick_fp64", "pps_brick_fp32"}};
+                                    {"pps_brick_fp64", "pps_brick_fp32"},
+                                    {"vps_brick_fp64", "vps_brick_fp32"}};
   return tags[op][fp64 ? 0 : 1];
 }
 
@@ -1040,7 +1065,7 @@ int apply_t(Ctx& c, const LevelView& L, const T* x, T* y, const T* const* cf, hi
     set_error("fused dot needs as many inputs as outputs");
     return CHNS_EINVAL;
   }
-  if (o.sm_r && ((OP != K_PP && OP != K_PPS) || o.fuse_dot || x == y)) {
+  if (o.sm_r && ((OP != K_PP && OP != K_PPS && OP != K_VPS) || o.fuse_dot || x == y)) {
     set_error("a fused smoothing sweep needs the pressure operator, no fused dot and y distinct from x");
     return CHNS_EINVAL;
   }
@@ -1106,12 +1131,15 @@ int apply_dispatch(Ctx& c, const LevelView& L, int op, const T* x, T* y, const T
   const T* one[1] = {phi};
   switch (op) {
     case CHNS_OP_PRESSURE:
+      if (c.pp_kind == 1) return apply_d<K_VPS, T>(c, L, x, y, one, s, o);
       if (c.pp_shift != 0.0) return apply_d<K_PPS, T>(c, L, x, y, one, s, o);
       return apply_d<K_PP, T>(c, L, x, y, one, s, o);
     case CHNS_OP_MASS:
       return apply_d<K_MASS, T>(c, L, x, y, one, s, o);
     case CHNS_OP_MASS_RHO:
       return apply_d<K_MASS_RHO, T>(c, L, x, y, one, s, o);
+    case CHNS_OP_MOMENTUM_SCALAR:
+      return apply_d<K_VPS, T>(c, L, x, y, one, s, o);
   }
   if constexpr (sizeof(T) == 8) {
     const int64_t n = L.dm->n;
@@ -1142,6 +1170,7 @@ int op_fields(int op, int dim) {
   switch (op) {
     case CHNS_OP_PRESSURE:
     case CHNS_OP_MASS:
+    case CHNS_OP_MOMENTUM_SCALAR:
       return 1;
     case CHNS_OP_MASS_RHO:
     case CHNS_OP_MOMENTUM:
@@ -1156,7 +1185,7 @@ LevelView fine_view(Ctx& c) { return LevelView{&c.dm, c.phi64, c.phi32, c.slots}
 
 int launch_apply_lv(Ctx& c, const LevelView& L, int op, int prec, const void* x, void* y, hipStream_t s,
                     const ApplyOut& o) {
-  if ((op == CHNS_OP_PRESSURE || op == CHNS_OP_MASS_RHO) && !c.phi_set) {
+  if ((op == CHNS_OP_PRESSURE || op == CHNS_OP_MASS_RHO || op == CHNS_OP_MOMENTUM_SCALAR) && !c.phi_set) {
     set_error("set_phase_field must be called before this operator");
     return CHNS_ESTATE;
   }

@@ -107,8 +107,13 @@ struct Multigrid {
   double* tab_P = nullptr;
   double* tab_H = nullptr;
   double* tab_M = nullptr;  // reference mass sum_q N_a N_b (for a mass shift)
+  // per-Gauss-point reference mass Mq (q, a, b) and its Galerkin products
+  // Hm (c, q, A, B) = P_c^T Mq_q P_c (variable-density mass)
+  double* tab_Mq = nullptr;
+  double* tab_Hm = nullptr;
   bool setup_valid = false;
   hipGraphExec_t setup_exec = nullptr;  // captured device part of the set-up
+  hipGraphExec_t mom_setup_exec = nullptr;  // the same for the scalar momentum operator
   // captured set-ups of shifted operators (mass shift, graph)
   std::vector<std::pair<double, hipGraphExec_t>> shifted_setups;
   int nu = 2;            // damped-Jacobi sweeps before and after the correction
@@ -153,6 +158,10 @@ struct Ctx {
   // public operator; set only while the Cahn-Hilliard preconditioner uses
   // the multigrid hierarchy
   double pp_shift = 0.0;
+  // 1: the "pressure" operator stands for the scalar momentum operator
+  // K_{eta(phi)/(2 Re)} + M_{rho(phi)/dt} (one velocity component) while the
+  // velocity-prediction preconditioner uses the multigrid hierarchy; 0 otherwise
+  int pp_kind = 0;
 
   // coefficient fields of the momentum and Cahn-Hilliard Jacobian operators
   // (context-owned copies, (2 + dim) * n each): [phi~, mu~, u^] and

@@ -39,7 +39,9 @@ struct GmDev {
 
 // GPC_SCHUR: block lower-triangular preconditioner of the Cahn-Hilliard
 // Jacobian with a multigrid Schur-complement approximation (pcd = lumped mass)
-enum GmPc { GPC_NONE = 0, GPC_JACOBI = 1, GPC_BLOCK2 = 2, GPC_SCHUR = 3 };
+// GPC_VPMG: one multigrid V-cycle of the scalar momentum operator per
+// velocity component (interior rows), identity on the wall rows.
+enum GmPc { GPC_NONE = 0, GPC_JACOBI = 1, GPC_BLOCK2 = 2, GPC_SCHUR = 3, GPC_VPMG = 4 };
 
 struct Stepper {
   int64_t n = 0, nv = 0;  // nodes, longest vector (max(2, dim) * n)
@@ -68,6 +70,7 @@ struct Stepper {
   double *mL = nullptr, *pin = nullptr, *pout = nullptr, *pt1 = nullptr, *pt2 = nullptr, *pz = nullptr,
          *pj = nullptr;
   double *dMinv = nullptr, *cx = nullptr, *cr = nullptr, *cd = nullptr;  // Chebyshev solve with M
+  double* vmask = nullptr;  // momentum multigrid preconditioner: masked input component
   double sc_scale = 0.0;  // dt / b of the Schur approximation
   double m_lmax = 0.0;    // Gershgorin bound of eig(D_M^-1 M)
 };
@@ -492,6 +495,58 @@ int ch_schur_apply(Ctx& c, const double* in, double* out, hipStream_t s) {
   return CHNS_OK;
 }
 
+// input/output vectors of the multigrid-based GMRES preconditioners (up to
+// three fields)
+int ensure_pc_io(Ctx& c) {
+  Stepper& S = *c.step;
+  const size_t bytes = sizeof(double) * 3 * (size_t)c.dm.n;
+  if (!S.pin) S.pin = (double*)c.dalloc(bytes);
+  if (!S.pout) S.pout = (double*)c.dalloc(bytes);
+  return S.pin && S.pout ? CHNS_OK : CHNS_ENOMEM;
+}
+
+__global__ void k_mask_walls(const double* __restrict__ in, const uint8_t* __restrict__ wall, double* out, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
+    out[i] = wall[i] ? 0.0 : in[i];
+}
+__global__ void k_wall_rows(double* z, const double* __restrict__ in, const uint8_t* __restrict__ wall, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
+    if (wall[i]) z[i] = in[i];
+}
+
+// Momentum preconditioner: per velocity component, one V-cycle of the
+// scalar operator rho/dt M + eta/(2 Re) K (natural boundary rows, set up by
+// vp_mg_setup) on the input with its wall entries dropped; the wall rows of
+// the momentum operator are the identity, so they pass the input through.
+int vp_mg_apply(Ctx& c, const double* in, double* out, hipStream_t s) {
+  Stepper& S = *c.step;
+  const int64_t n = c.dm.n;
+  const unsigned g = blocks_for(n);
+  for (int d = 0; d < c.dm.dim; ++d) {
+    k_mask_walls<<<g, kT, 0, s>>>(in + d * n, c.dm.wall, S.vmask, n);
+    CHNS_HIP(hipGetLastError());
+    int rc = mg_vcycle64(c, S.vmask, out + d * n, s);
+    if (rc) return rc;
+    k_wall_rows<<<g, kT, 0, s>>>(out + d * n, in + d * n, c.dm.wall, n);
+    CHNS_HIP(hipGetLastError());
+  }
+  return CHNS_OK;
+}
+
+// Multigrid hierarchy of the scalar momentum operator at the context's
+// phase field; the caller restores the pressure operator afterwards.
+int vp_mg_setup(Ctx& c, hipStream_t s) {
+  Stepper& S = *c.step;
+  int rc;
+  if ((rc = ensure_pc_io(c))) return rc;
+  if (!S.vmask && !(S.vmask = (double*)c.dalloc(sizeof(double) * (size_t)c.dm.n))) return CHNS_ENOMEM;
+  if ((rc = mg_build(c))) return rc;
+  c.pp_kind = 1;
+  c.pp_shift = 0.0;
+  c.mg->setup_valid = false;
+  return mg_setup(c, s);
+}
+
 // Restarted right-preconditioned GMRES(m) on A x = b, A = the public
 // operator `op` with its current coefficient fields; x in/out.
 int gmres(Ctx& c, int op, const double* b, double* x, int pc, const double* pcd, double rtol, int max_it, int m,
@@ -518,10 +573,10 @@ int gmres(Ctx& c, int op, const double* b, double* x, int pc, const double* pcd,
   gated.done = &S.gd->done;
   auto step = [&](hipStream_t st) -> int {
     int e;
-    if (pc == GPC_SCHUR) {
+    if (pc == GPC_SCHUR || pc == GPC_VPMG) {
       k_gm_copyj<<<g, kT, 0, st>>>(S.V, nv, S.pin, S.gd);
       CHNS_HIP(hipGetLastError());
-      if ((e = ch_schur_apply(c, S.pin, S.z, st))) return e;
+      if ((e = pc == GPC_SCHUR ? ch_schur_apply(c, S.pin, S.z, st) : vp_mg_apply(c, S.pin, S.z, st))) return e;
     } else {
       k_gm_pc<<<pc == GPC_BLOCK2 ? gn : g, kT, 0, st>>>(S.V, nv, n, S.z, S.gd, pc, pcd);
       CHNS_HIP(hipGetLastError());
@@ -585,10 +640,10 @@ int gmres(Ctx& c, int op, const double* b, double* x, int pc, const double* pcd,
     CHNS_HIP(hipStreamSynchronize(s));
     total += S.gd_host->j;
     k_gm_solve<<<1, 64, 0, s>>>(S.gd);
-    if (pc == GPC_SCHUR) {
+    if (pc == GPC_SCHUR || pc == GPC_VPMG) {
       k_gm_combine<<<g, kT, 0, s>>>(S.pin, S.V, nv, S.gd);
       CHNS_HIP(hipGetLastError());
-      if ((rc = ch_schur_apply(c, S.pin, S.pout, s))) return rc;
+      if ((rc = pc == GPC_SCHUR ? ch_schur_apply(c, S.pin, S.pout, s) : vp_mg_apply(c, S.pin, S.pout, s))) return rc;
       k_add<<<g, kT, 0, s>>>(x, S.pout, nv);
     } else {
       k_gm_update<<<pc == GPC_BLOCK2 ? gn : g, kT, 0, s>>>(x, S.V, nv, n, S.gd, pc, pcd);
@@ -632,13 +687,12 @@ int schur_setup(Ctx& c, hipStream_t s) {
     S.cr = A(n);
     S.cd = A(n);
     if (!S.dMinv || !S.cx || !S.cr || !S.cd) return CHNS_ENOMEM;
-    S.pin = A(2 * n);
-    S.pout = A(2 * n);
+    if ((rc = ensure_pc_io(c))) return rc;
     S.pt1 = A(n);
     S.pt2 = A(n);
     S.pz = A(2 * n);
     S.pj = A(2 * n);
-    if (!S.mL || !S.pin || !S.pout || !S.pt1 || !S.pt2 || !S.pz || !S.pj) return CHNS_ENOMEM;
+    if (!S.mL || !S.pt1 || !S.pt2 || !S.pz || !S.pj) return CHNS_ENOMEM;
     // the mu block of pz stays zero; lumped mass M 1
     k_fill0<<<blocks_for(2 * n), kT, 0, s>>>(S.pz, 2 * n);
     k_fill1<<<blocks_for(n), kT, 0, s>>>(S.pt2, n);
@@ -910,16 +964,30 @@ int advance_step_impl(Ctx& c, const chns_state& st, const chns_step_opts& o, chn
     if ((rc = copy(c.coef_mom + n, S.mut, n, s))) return rc;
     if ((rc = copy(c.coef_mom + 2 * n, S.uhat, dim * n, s))) return rc;
     c.coef_mom_set = true;
-    if ((rc = launch_diagonal(c, CHNS_OP_MOMENTUM, CHNS_FP64, S.dvp, true, s))) return rc;
-    if ((rc = copy(S.v, st.u, dim * n, s))) return rc;
+    // phase field phi~ of the pressure solve (and of the momentum multigrid)
+    if ((rc = launch_set_phase(c, S.X, st.phi, s))) return rc;
+    const bool vpmg = o.vp_pc == CHNS_VP_PC_GMG;
+    if (vpmg) {
+      rc = vp_mg_setup(c, s);
+    } else {
+      rc = launch_diagonal(c, CHNS_OP_MOMENTUM, CHNS_FP64, S.dvp, true, s);
+    }
+    if (!rc) rc = copy(S.v, st.u, dim * n, s);
     int li = 0;
     double rel = 0.0;
-    rc = gmres(c, CHNS_OP_MOMENTUM, S.rhs, S.v, GPC_JACOBI, S.dvp, o.lin_rtol, o.max_it, o.restart, graphs, s, &li,
-               &rel);
+    if (!rc)
+      rc = gmres(c, CHNS_OP_MOMENTUM, S.rhs, S.v, vpmg ? GPC_VPMG : GPC_JACOBI, vpmg ? nullptr : S.dvp, o.lin_rtol,
+                 o.max_it, o.restart, graphs, s, &li, &rel);
+    if (vpmg) {
+      // the hierarchy and the operator behind CHNS_OP_PRESSURE return to
+      // the pressure Poisson problem
+      c.pp_kind = 0;
+      c.diag_valid = false;
+      if (c.mg) c.mg->setup_valid = false;
+    }
     stats.vp_iterations += li;
     if (rc) return rc;
     // ---- pressure Poisson with 1/rho(phi~)
-    if ((rc = launch_set_phase(c, S.X, st.phi, s))) return rc;
     for (int d = 0; d < dim; ++d) cf[k++] = S.v + d * n;
     if ((rc = launch_form(c, FORM_PP_RHS, nullptr, cf, S.rhs, s, plain))) return rc;
     chns_solve_opts po{};

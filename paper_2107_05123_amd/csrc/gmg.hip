@@ -164,7 +164,18 @@ __global__ void k_phase32(const double* a, float* b, int64_t n) {
 //   K_C = (h_f/2)^(d-2) sum_{c,q} c_{c,q} H_{c,q},  H_{c,q} = P_c^T G_q P_c.
 // Tables G (q, a, b), P (c, b, A) and H (c, q, A, B) are built on the host.
 
-__device__ __forceinline__ double coef_at(const double* ph, int q, int dim, double alpha, double beta) {
+// Gauss-point coefficients of a level operator at the clamped phase value v:
+// stiffness 1 / (a v + b) (pressure Poisson, 1/rho) or a v + b (one velocity
+// component of the momentum operator, eta/(2 Re)); mass ma v + mb (a
+// constant shift, or rho/dt)
+struct QCoef {
+  double a, b, ma, mb;
+  int lin;
+  __device__ __forceinline__ double k(double v) const { return lin ? a * v + b : 1.0 / (a * v + b); }
+  __device__ __forceinline__ double m(double v) const { return ma * v + mb; }
+};
+
+__device__ __forceinline__ double phase_at(const double* ph, int q, int dim) {
   // phase field at reference Gauss point q from the corner values
   const double g = 0.57735026918962576451;
   const int nc = 1 << dim;
@@ -177,17 +188,17 @@ __device__ __forceinline__ double coef_at(const double* ph, int q, int dim, doub
     }
     v += w * ph[b];
   }
-  return 1.0 / (alpha * fmin(fmax(v, -1.0), 1.0) + beta);
+  return fmin(fmax(v, -1.0), 1.0);
 }
 
 // element matrices of a uniform level from its own phase field
 // (one wave per element, lane (a, b) one entry)
 template <int DIM>
 __global__ __launch_bounds__(64) void k_el_rediscr(const double* __restrict__ phi, int s, const double* __restrict__ Gt,
-                                                   double alpha, double beta, double scale, double* E,
-                                                   const double* __restrict__ Mt, double mshift) {
+                                                   QCoef cf, double scale, double* E, const double* __restrict__ Mq,
+                                                   double mscale) {
   constexpr int NC = 1 << DIM, NE = NC * NC;
-  __shared__ double cq[NC];
+  __shared__ double cq[NC], cm[NC];
   const int64_t e = blockIdx.x;
   const int64_t s1 = s + 1;
   const int X = (int)(e % s), Y = (int)((e / s) % s), Z = DIM == 3 ? (int)(e / ((int64_t)s * s)) : 0;
@@ -196,27 +207,36 @@ __global__ __launch_bounds__(64) void k_el_rediscr(const double* __restrict__ ph
     double ph[NC];
     for (int b = 0; b < NC; ++b)
       ph[b] = phi[((int64_t)(Z + ((b >> 2) & 1)) * s1 + (Y + ((b >> 1) & 1))) * s1 + (X + (b & 1))];
-    cq[t] = coef_at(ph, t, DIM, alpha, beta);
+    const double v = phase_at(ph, t, DIM);
+    cq[t] = cf.k(v);
+    cm[t] = cf.m(v);
   }
   __syncthreads();
   if (t < NE) {
-    double acc = 0.0;
-    for (int q = 0; q < NC; ++q) acc += cq[q] * Gt[q * NE + t];
-    E[e * NE + t] = scale * acc + mshift * Mt[t];
+    double acc = 0.0, macc = 0.0;
+    for (int q = 0; q < NC; ++q) {
+      acc += cq[q] * Gt[q * NE + t];
+      macc += cm[q] * Mq[q * NE + t];
+    }
+    E[e * NE + t] = scale * acc + mscale * macc;
   }
 }
 
 // Galerkin element matrices of a uniform level (sc cells per edge) straight
 // from the phase field of the uniform level above (sf = 2 sc).  One wave
 // handles kGalPerWave coarse elements; lane t keeps column t of H (the 64
-// table entries it needs) in registers across them.
+// table entries it needs) in registers across them.  A constant mass
+// (VARM false) is the coarse mass times mconst; a variable one (rho/dt) is
+// the Galerkin product of the fine Gauss-point masses, sum cm_{c,q} Hm_{c,q}
+// scaled by the fine det J (Hm staged in LDS).
 constexpr int kGalPerWave = 64;
-template <int DIM>
+template <int DIM, bool VARM>
 __global__ __launch_bounds__(64) void k_gal_phi(const double* __restrict__ phi, int sf, const double* __restrict__ Ht,
-                                                double alpha, double beta, double scale, double* E, int64_t ne,
-                                                const double* __restrict__ Mt, double mshift) {
+                                                QCoef cf, double scale, double* E, int64_t ne,
+                                                const double* __restrict__ Mt, double mconst,
+                                                const double* __restrict__ Hm, double mscale) {
   constexpr int NC = 1 << DIM, NE = NC * NC;
-  __shared__ double cq[NE];
+  __shared__ double cq[NE], cm[VARM ? NE : 1], hm[VARM ? NE * NE : 1];
   const int sc = sf / 2;
   const int64_t f1 = sf + 1;
   const int t = threadIdx.x;
@@ -225,7 +245,10 @@ __global__ __launch_bounds__(64) void k_gal_phi(const double* __restrict__ phi, 
   for (int k = 0; k < NE; ++k) h[k] = t < NE ? Ht[k * NE + t] : 0.0;
   // the mass part of a shifted operator is reproduced exactly by the
   // Galerkin product (Q1 spaces are nested, 2-point Gauss is exact for it)
-  const double m = t < NE ? mshift * Mt[t] : 0.0;
+  const double m = t < NE ? mconst * Mt[t] : 0.0;
+  if constexpr (VARM) {
+    for (int k = t; k < NE * NE; k += 64) hm[k] = Hm[k];
+  }
   const int64_t e0 = (int64_t)blockIdx.x * kGalPerWave;
   for (int64_t e = e0; e < e0 + kGalPerWave && e < ne; ++e) {
     const int X = (int)(e % sc), Y = (int)((e / sc) % sc), Z = DIM == 3 ? (int)(e / ((int64_t)sc * sc)) : 0;
@@ -236,14 +259,22 @@ __global__ __launch_bounds__(64) void k_gal_phi(const double* __restrict__ phi, 
       double ph[NC];
       for (int b = 0; b < NC; ++b)
         ph[b] = phi[((int64_t)(cz + ((b >> 2) & 1)) * f1 + (cy + ((b >> 1) & 1))) * f1 + (cx + (b & 1))];
-      cq[t] = coef_at(ph, q, DIM, alpha, beta);
+      const double v = phase_at(ph, q, DIM);
+      cq[t] = cf.k(v);
+      if constexpr (VARM) cm[t] = cf.m(v);
     }
     __syncthreads();
     if (t < NE) {
       double acc = 0.0;
 #pragma unroll
       for (int k = 0; k < NE; ++k) acc += cq[k] * h[k];
-      E[e * NE + t] = scale * acc + m;
+      if constexpr (VARM) {
+        double macc = 0.0;
+        for (int k = 0; k < NE; ++k) macc += cm[k] * hm[k * NE + t];
+        E[e * NE + t] = scale * acc + mscale * macc;
+      } else {
+        E[e * NE + t] = scale * acc + m;
+      }
     }
     __syncthreads();
   }
@@ -323,9 +354,9 @@ __global__ void k_el_stencil(const double* __restrict__ E, int s, double* S64, f
 
 // inverse diagonal of a uniform fine level straight from its phase field
 template <int DIM>
-__global__ void k_diag_phi(const double* __restrict__ phi, int s, const double* __restrict__ Gt, double alpha,
-                           double beta, double scale, double* dinv64, float* dinv32, const double* __restrict__ Mt,
-                           double mshift) {
+__global__ void k_diag_phi(const double* __restrict__ phi, int s, const double* __restrict__ Gt, QCoef cf,
+                           double scale, double* dinv64, float* dinv32, const double* __restrict__ Mq,
+                           double mscale) {
   constexpr int NC = 1 << DIM, NE = NC * NC;
   const int64_t s1 = s + 1;
   const int64_t n = DIM == 3 ? s1 * s1 * s1 : s1 * s1;
@@ -339,10 +370,13 @@ __global__ void k_diag_phi(const double* __restrict__ phi, int s, const double* 
       double ph[NC];
       for (int b = 0; b < NC; ++b)
         ph[b] = phi[((int64_t)(az + ((b >> 2) & 1)) * s1 + (ay + ((b >> 1) & 1))) * s1 + (ax + (b & 1))];
-      for (int q = 0; q < NC; ++q) acc += coef_at(ph, q, DIM, alpha, beta) * Gt[q * NE + u * NC + u];
-      macc += Mt[u * NC + u];
+      for (int q = 0; q < NC; ++q) {
+        const double v = phase_at(ph, q, DIM);
+        acc += cf.k(v) * Gt[q * NE + u * NC + u];
+        macc += cf.m(v) * Mq[q * NE + u * NC + u];
+      }
     }
-    const double d = scale * acc + mshift * macc;
+    const double d = scale * acc + mscale * macc;
     dinv64[node] = 1.0 / d;
     dinv32[node] = (float)(1.0 / d);
   }
@@ -695,7 +729,7 @@ int vcycle(Ctx& c, int k, const T* r, T* z, hipStream_t s) {
 // Host: reference tables of the element-matrix Galerkin products (see the
 // kernels above); bit d of a corner / Gauss point / child index is axis d.
 void reference_tables(int dim, std::vector<double>& tg, std::vector<double>& tp, std::vector<double>& th,
-                      std::vector<double>& tm) {
+                      std::vector<double>& tm, std::vector<double>& tmq, std::vector<double>& thm) {
   const int nc = 1 << dim, ne = nc * nc;
   const double g = 0.57735026918962576451;
   const double norm = dim == 3 ? 0.125 : 0.25;
@@ -728,8 +762,10 @@ void reference_tables(int dim, std::vector<double>& tg, std::vector<double>& tp,
         }
         tp[((size_t)c * nc + b) * nc + A] = w;
       }
-  // reference mass: sum_q N_a N_b at the Gauss points (N = prod (1 +- xi) / 2)
+  // reference mass: N_a N_b at each Gauss point (N = prod (1 +- xi) / 2)
+  // and its sum over them
   tm.assign((size_t)ne, 0.0);
+  tmq.assign((size_t)nc * ne, 0.0);
   for (int q = 0; q < nc; ++q)
     for (int a = 0; a < nc; ++a)
       for (int b = 0; b < nc; ++b) {
@@ -740,18 +776,25 @@ void reference_tables(int dim, std::vector<double>& tg, std::vector<double>& tp,
           nb *= 0.5 * (1.0 + (((b >> d) & 1) ? 1.0 : -1.0) * xq);
         }
         tm[(size_t)a * nc + b] += na * nb;
+        tmq[(size_t)q * ne + a * nc + b] = na * nb;
       }
-  th.assign((size_t)ne * ne, 0.0);
-  for (int c = 0; c < nc; ++c)
-    for (int q = 0; q < nc; ++q)
-      for (int A = 0; A < nc; ++A)
-        for (int B = 0; B < nc; ++B) {
-          double v = 0.0;
-          for (int a = 0; a < nc; ++a)
-            for (int b = 0; b < nc; ++b)
-              v += tp[((size_t)c * nc + a) * nc + A] * tg[(size_t)q * ne + a * nc + b] * tp[((size_t)c * nc + b) * nc + B];
-          th[(size_t)(c * nc + q) * ne + A * nc + B] = v;
-        }
+  // Galerkin products P_c^T T_q P_c of the per-point stiffness and mass
+  auto galerkin = [&](const std::vector<double>& t, std::vector<double>& out) {
+    out.assign((size_t)ne * ne, 0.0);
+    for (int c = 0; c < nc; ++c)
+      for (int q = 0; q < nc; ++q)
+        for (int A = 0; A < nc; ++A)
+          for (int B = 0; B < nc; ++B) {
+            double v = 0.0;
+            for (int a = 0; a < nc; ++a)
+              for (int b = 0; b < nc; ++b)
+                v += tp[((size_t)c * nc + a) * nc + A] * t[(size_t)q * ne + a * nc + b] *
+                     tp[((size_t)c * nc + b) * nc + B];
+            out[(size_t)(c * nc + q) * ne + A * nc + B] = v;
+          }
+  };
+  galerkin(tg, th);
+  galerkin(tmq, thm);
 }
 
 int mg_build(Ctx& c) {
@@ -843,11 +886,14 @@ int mg_build(Ctx& c) {
         goto fail;
       }
     }
-    std::vector<double> tg, tp, th, tm;
-    reference_tables(c.dm.dim, tg, tp, th, tm);
-    if ((rc = upload(c, &mg->tab_G, tg)) || (rc = upload(c, &mg->tab_P, tp)) || (rc = upload(c, &mg->tab_M, tm)))
+    std::vector<double> tg, tp, th, tm, tmq, thm;
+    reference_tables(c.dm.dim, tg, tp, th, tm, tmq, thm);
+    if ((rc = upload(c, &mg->tab_G, tg)) || (rc = upload(c, &mg->tab_P, tp)) || (rc = upload(c, &mg->tab_M, tm)) ||
+        (rc = upload(c, &mg->tab_Mq, tmq)))
       goto fail;
-    if (c.dm.structured && mg->lv[1].E64 && (rc = upload(c, &mg->tab_H, th))) goto fail;
+    if (c.dm.structured && mg->lv[1].E64 &&
+        ((rc = upload(c, &mg->tab_H, th)) || (rc = upload(c, &mg->tab_Hm, thm))))
+      goto fail;
   }
   {
     MgLevel& B = mg->lv.back();
@@ -891,25 +937,42 @@ int mg_setup(Ctx& c, hipStream_t s) {
     const double al = (c.prm.rho_plus - c.prm.rho_minus) / (2.0 * c.prm.rho_plus);
     const double be = (c.prm.rho_plus + c.prm.rho_minus) / (2.0 * c.prm.rho_plus);
     const int dim = c.dm.dim;
-    // (h/2)^(d-2) of a uniform level with s cells per edge
+    QCoef cf{al, be, 0.0, c.pp_shift, 0};
+    if (c.pp_kind == 1) {
+      // eta/(2 Re) on the stiffness, rho/dt on the mass
+      const double ga = (c.prm.eta_plus - c.prm.eta_minus) / (2.0 * c.prm.eta_plus);
+      const double xi = (c.prm.eta_plus + c.prm.eta_minus) / (2.0 * c.prm.eta_plus);
+      cf = QCoef{ga / (2.0 * c.prm.Re), xi / (2.0 * c.prm.Re), al / c.prm.dt, be / c.prm.dt, 1};
+    }
+    const bool varm = cf.ma != 0.0;
+    // (h/2)^(d-2) and det J = (h/2)^d of a uniform level with s cells per edge
     auto lscale = [&](int s) { return dim == 3 ? 0.5 / s : 1.0; };
-    // mass shift of a uniform level: g (h/2)^d
-    auto mshift = [&](int s) { return c.pp_shift * std::pow(0.5 / s, dim); };
+    auto mscale = [&](int s) { return std::pow(0.5 / s, dim); };
     if (mg.tab_H) {
       // uniform fine level: inverse diagonal straight from the phase field,
       // first coarse level's element matrices as Galerkin products
       const int64_t ncoarse = (int64_t)1 << (dim * (c.dm.max_level - 1));
       const unsigned gl = (unsigned)((ncoarse + kGalPerWave - 1) / kGalPerWave);
+      const int sf = c.dm.side;
+      const double mc = cf.mb * mscale(sf / 2);
       if (dim == 3) {
-        k_diag_phi<3><<<blocks(c.dm.n), kT, 0, st>>>(c.phi64, c.dm.side, mg.tab_G, al, be, lscale(c.dm.side),
-                                                      mg.fine_dinv64, mg.fine_dinv32, mg.tab_M, mshift(c.dm.side));
-        k_gal_phi<3><<<gl, 64, 0, st>>>(c.phi64, c.dm.side, mg.tab_H, al, be, lscale(c.dm.side), mg.lv[1].E64,
-                                         ncoarse, mg.tab_M, mshift(c.dm.side / 2));
+        k_diag_phi<3><<<blocks(c.dm.n), kT, 0, st>>>(c.phi64, sf, mg.tab_G, cf, lscale(sf), mg.fine_dinv64,
+                                                      mg.fine_dinv32, mg.tab_Mq, mscale(sf));
+        if (varm)
+          k_gal_phi<3, true><<<gl, 64, 0, st>>>(c.phi64, sf, mg.tab_H, cf, lscale(sf), mg.lv[1].E64, ncoarse,
+                                                mg.tab_M, mc, mg.tab_Hm, mscale(sf));
+        else
+          k_gal_phi<3, false><<<gl, 64, 0, st>>>(c.phi64, sf, mg.tab_H, cf, lscale(sf), mg.lv[1].E64, ncoarse,
+                                                 mg.tab_M, mc, mg.tab_Hm, mscale(sf));
       } else {
-        k_diag_phi<2><<<blocks(c.dm.n), kT, 0, st>>>(c.phi64, c.dm.side, mg.tab_G, al, be, lscale(c.dm.side),
-                                                      mg.fine_dinv64, mg.fine_dinv32, mg.tab_M, mshift(c.dm.side));
-        k_gal_phi<2><<<gl, 64, 0, st>>>(c.phi64, c.dm.side, mg.tab_H, al, be, lscale(c.dm.side), mg.lv[1].E64,
-                                         ncoarse, mg.tab_M, mshift(c.dm.side / 2));
+        k_diag_phi<2><<<blocks(c.dm.n), kT, 0, st>>>(c.phi64, sf, mg.tab_G, cf, lscale(sf), mg.fine_dinv64,
+                                                      mg.fine_dinv32, mg.tab_Mq, mscale(sf));
+        if (varm)
+          k_gal_phi<2, true><<<gl, 64, 0, st>>>(c.phi64, sf, mg.tab_H, cf, lscale(sf), mg.lv[1].E64, ncoarse,
+                                                mg.tab_M, mc, mg.tab_Hm, mscale(sf));
+        else
+          k_gal_phi<2, false><<<gl, 64, 0, st>>>(c.phi64, sf, mg.tab_H, cf, lscale(sf), mg.lv[1].E64, ncoarse,
+                                                 mg.tab_M, mc, mg.tab_Hm, mscale(sf));
       }
       CHNS_HIP(hipGetLastError());
     } else {
@@ -939,11 +1002,11 @@ int mg_setup(Ctx& c, hipStream_t s) {
         const unsigned ne = (unsigned)((int64_t)1 << (dim * L.host.max_level));
         if (!from_above) {
           if (dim == 3)
-            k_el_rediscr<3><<<ne, 64, 0, st>>>(L.phi64, L.dm.side, mg.tab_G, al, be, lscale(L.dm.side), L.E64,
-                                               mg.tab_M, mshift(L.dm.side));
+            k_el_rediscr<3><<<ne, 64, 0, st>>>(L.phi64, L.dm.side, mg.tab_G, cf, lscale(L.dm.side), L.E64,
+                                               mg.tab_Mq, mscale(L.dm.side));
           else
-            k_el_rediscr<2><<<ne, 64, 0, st>>>(L.phi64, L.dm.side, mg.tab_G, al, be, lscale(L.dm.side), L.E64,
-                                               mg.tab_M, mshift(L.dm.side));
+            k_el_rediscr<2><<<ne, 64, 0, st>>>(L.phi64, L.dm.side, mg.tab_G, cf, lscale(L.dm.side), L.E64,
+                                               mg.tab_Mq, mscale(L.dm.side));
         }
         const bool last = k + 1 == mg.lv.size();
         double* d64 = last ? nullptr : L.dinv64;
@@ -980,9 +1043,12 @@ int mg_setup(Ctx& c, hipStream_t s) {
     CHNS_HIP(hipGetLastError());
     return CHNS_OK;
   };
-  // the captured kernels carry the shift: one graph per shift value
+  // the captured kernels carry the coefficients: one graph per shift value
+  // and one for the scalar momentum operator
   hipGraphExec_t* exec = &mg.setup_exec;
-  if (c.pp_shift != 0.0) {
+  if (c.pp_kind == 1) {
+    exec = &mg.mom_setup_exec;
+  } else if (c.pp_shift != 0.0) {
     exec = nullptr;
     for (auto& e : mg.shifted_setups)
       if (e.first == c.pp_shift) exec = &e.second;
@@ -995,8 +1061,9 @@ int mg_setup(Ctx& c, hipStream_t s) {
   std::vector<double> A((size_t)n * n);
   CHNS_HIP(hipMemcpyAsync(A.data(), B.dense, sizeof(double) * A.size(), hipMemcpyDeviceToHost, s));
   CHNS_HIP(hipStreamSynchronize(s));
-  // a shifted operator is definite: no rank-one regularisation
-  if ((rc = dense_inverse(A, n, c.pp_shift == 0.0))) {
+  // a shifted operator or one with a mass term is definite: no rank-one
+  // regularisation
+  if ((rc = dense_inverse(A, n, c.pp_shift == 0.0 && c.pp_kind == 0))) {
     set_error("coarsest multigrid operator is not positive semi-definite");
     return rc;
   }
