@@ -116,6 +116,7 @@ struct Multigrid {
   hipGraphExec_t mom_setup_exec = nullptr;  // the same for the scalar momentum operator
   // captured set-ups of shifted operators (mass shift, graph)
   std::vector<std::pair<double, hipGraphExec_t>> shifted_setups;
+  bool transfer32_exact = false;  // every transfer weight is exact in FP32
   int nu = 2;            // damped-Jacobi sweeps before and after the correction
   double omega = 0.6;    // damping
 };

@@ -50,6 +50,24 @@ __global__ void k_spmv(const int32_t* __restrict__ ptr, const int32_t* __restric
   }
 }
 
+// the same with L lanes per row (lane-strided partial sums, then a fixed
+// butterfly): coalesced reads of the column and value arrays
+template <typename T, typename V, int L>
+__global__ __launch_bounds__(kT) void k_spmv_g(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                               const V* __restrict__ val, const T* __restrict__ x,
+                                               T* __restrict__ y, int64_t rows, int accumulate) {
+  const int lane = threadIdx.x & (L - 1);
+  const int64_t stride = (int64_t)gridDim.x * (kT / L);
+  for (int64_t i = ((int64_t)blockIdx.x * kT + threadIdx.x) / L; i < rows; i += stride) {
+    const int32_t b = ptr[i], e = ptr[i + 1];
+    T acc = T(0);
+    for (int32_t k = b + lane; k < e; k += L) acc += (T)val[k] * x[col[k]];
+#pragma unroll
+    for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, L);
+    if (lane == 0) y[i] = accumulate ? y[i] + acc : acc;
+  }
+}
+
 // z = w dinv r
 template <typename T>
 __global__ void k_jacobi0(T* z, const T* r, const T* dinv, T w, int64_t n) {
@@ -598,6 +616,18 @@ struct Prec<float> {
 template <typename T>
 int vcycle(Ctx& c, int k, const T* r, T* z, hipStream_t s);
 
+// transfer y (+)= A x with L lanes per row; FP64 vectors read the FP32 copy
+// of the weights when all of them are exact in FP32 (dyadic Q1 weights)
+template <typename T, int L>
+void transfer(const Multigrid& mg, const int32_t* ptr, const int32_t* col, const T* val, const float* val32,
+              const T* x, T* y, int64_t rows, int accumulate, hipStream_t s) {
+  const unsigned g = blocks(rows * L);
+  if (sizeof(T) == 8 && mg.transfer32_exact)
+    k_spmv_g<T, float, L><<<g, kT, 0, s>>>(ptr, col, val32, x, y, rows, accumulate);
+  else
+    k_spmv_g<T, T, L><<<g, kT, 0, s>>>(ptr, col, val, x, y, rows, accumulate);
+}
+
 // V-cycle from a uniform coarse level k > 0 with an assembled stencil: the
 // same damped-Jacobi sweeps and transfers as the matrix-free levels, six
 // launches per level (two-sweep pre-smoothing, A z, restriction,
@@ -703,14 +733,14 @@ int vcycle(Ctx& c, int k, const T* r, T* z, hipStream_t s) {
     k_restrict_s<T><<<blocks(C.dm.n), kT, 0, s>>>(r, t, rc_, C.dm.side, C.dm.dim);
   } else {
     k_resid<T><<<g, kT, 0, s>>>(r, t, n);
-    k_spmv<T, T><<<blocks(C.dm.n), kT, 0, s>>>(C.R_ptr, C.R_col, PR::Rv(C), t, rc_, C.dm.n, 0);
+    transfer<T, 8>(mg, C.R_ptr, C.R_col, PR::Rv(C), C.R_val32, t, rc_, C.dm.n, 0, s);
   }
   CHNS_HIP(hipGetLastError());
   if ((rc = vcycle<T>(c, k + 1, rc_, zc, s))) return rc;
   if (structured)
     k_prolong_s<T><<<g, kT, 0, s>>>(zc, z, C.dm.side, C.dm.dim);
   else
-    k_spmv<T, T><<<g, kT, 0, s>>>(C.P_ptr, C.P_col, PR::Pv(C), zc, z, n, 1);
+    transfer<T, 4>(mg, C.P_ptr, C.P_col, PR::Pv(C), C.P_val32, zc, z, n, 1, s);
   {
     T* cur = z;
     T* oth = t;
@@ -835,6 +865,10 @@ int mg_build(Ctx& c) {
       return rc;
     }
     if ((rc = upload_dm(c, L.host, L.dm))) goto fail;
+    if (k == 1) mg->transfer32_exact = true;
+    for (const std::vector<double>* vals : {&t.P_val, &t.R_val})
+      for (double v : *vals)
+        if ((double)(float)v != v) mg->transfer32_exact = false;
     L.P_rows = fine.n_indep;
     if ((rc = upload(c, &L.P_ptr, t.P_ptr)) || (rc = upload(c, &L.P_col, t.P_col)) ||
         (rc = upload(c, &L.P_val64, t.P_val)) || (rc = upload_as_float(c, &L.P_val32, t.P_val)) ||
