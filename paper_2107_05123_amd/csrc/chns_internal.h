@@ -117,8 +117,8 @@ struct Multigrid {
   // captured set-ups of shifted operators (mass shift, graph)
   std::vector<std::pair<double, hipGraphExec_t>> shifted_setups;
   bool transfer32_exact = false;  // every transfer weight is exact in FP32
-  int nu = 2;            // damped-Jacobi sweeps before and after the correction
-  double omega = 0.6;    // damping
+  int nu = 2;            // damped-Jacobi sweeps before and after the correction (per set-up)
+  double omega = 0.6;    // damping (per set-up)
 };
 
 struct Ctx {

@@ -457,10 +457,10 @@ int dot_sync(Ctx& c, const double* a, const double* b, int64_t n, hipStream_t s,
 // Block lower-triangular preconditioner of the Cahn-Hilliard Jacobian
 // J = [[A, B], [C, D]] (A = M/dt - advection/2, B = K/(2 Pe Cn),
 // C = (M_psi'' + Cn^2 K)/2, D = -M/2):
-//   dphi = S~^-1 v_phi,  dmu = D^-1 (v_mu - C dphi),  D^-1 ~ -2 M_L^-1,
+//   dphi = S~^-1 v_phi,  dmu = D^-1 (v_mu - C dphi),  D^-1 = -2 M^-1,
 // with the Schur complement S = A - B D^-1 C approximated, dropping the
-// advection and psi'' parts, by (1/dt)(M + sqrt(b) K) M_L^-1 (M + sqrt(b) K),
-// b = dt Cn / (2 Pe):  S~^-1 = (dt/b) A_g^-1 M_L A_g^-1, A_g = K + M/sqrt(b),
+// advection and psi'' parts, by (1/dt)(M + sqrt(b) K) M^-1 (M + sqrt(b) K),
+// b = dt Cn / (2 Pe):  S~^-1 = (dt/b) A_g^-1 M A_g^-1, A_g = K + M/sqrt(b),
 // each A_g^-1 one multigrid V-cycle of the pressure hierarchy set up with
 // rho = 1 and the mass shift 1/sqrt(b).  C dphi is the mu block of J [dphi, 0].
 // A fixed linear map (fixed cycles), so plain right-preconditioned GMRES

@@ -959,6 +959,13 @@ fail:
 int mg_setup(Ctx& c, hipStream_t s) {
   Multigrid& mg = *c.mg;
   int rc;
+  // smoothing per operator: the pressure Poisson cycle (CG) runs one
+  // damped-Jacobi sweep each way with omega 0.9 (fewer fine-level applies
+  // per iteration outweigh the extra iteration); the shifted and momentum
+  // cycles inside GMRES keep two sweeps with omega 0.6
+  const bool pressure = c.pp_kind == 0 && c.pp_shift == 0.0;
+  mg.nu = pressure ? 1 : 2;
+  mg.omega = pressure ? 0.9 : 0.6;
   for (int k = 6; k < 8; ++k) {
     if (!c.w64[k]) c.w64[k] = (double*)c.dalloc(sizeof(double) * c.dm.n * 3);
     if (!c.w32[k]) c.w32[k] = (float*)c.dalloc(sizeof(float) * c.dm.n * 3);

@@ -278,7 +278,7 @@ def test_steps_with_schur_multigrid_ch_preconditioner_match_oracle(idx):
     _compare_states(c, state, st, 1e-6)
 
 
-@pytest.mark.parametrize("idx", [0, 1, 3])
+@pytest.mark.parametrize("idx", [0, 1, 2, 3])
 def test_steps_with_multigrid_momentum_preconditioner_match_oracle(idx):
     """Multigrid V-cycles of the scalar mass + viscous operator as the
     velocity-prediction preconditioner: same states as the oracle to 1e-6 and
