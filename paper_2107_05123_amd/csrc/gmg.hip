@@ -50,12 +50,13 @@ __global__ void k_spmv(const int32_t* __restrict__ ptr, const int32_t* __restric
   }
 }
 
-// the same with L lanes per row (lane-strided partial sums, then a fixed
-// butterfly): coalesced reads of the column and value arrays
+// y = yin + A x (yin null: y = A x; yin may be y) with L lanes per row
+// (lane-strided partial sums, then a fixed butterfly): coalesced reads of
+// the column and value arrays
 template <typename T, typename V, int L>
 __global__ __launch_bounds__(kT) void k_spmv_g(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
-                                               const V* __restrict__ val, const T* __restrict__ x,
-                                               T* __restrict__ y, int64_t rows, int accumulate) {
+                                               const V* __restrict__ val, const T* __restrict__ x, T* y,
+                                               int64_t rows, const T* yin) {
   const int lane = threadIdx.x & (L - 1);
   const int64_t stride = (int64_t)gridDim.x * (kT / L);
   for (int64_t i = ((int64_t)blockIdx.x * kT + threadIdx.x) / L; i < rows; i += stride) {
@@ -64,7 +65,7 @@ __global__ __launch_bounds__(kT) void k_spmv_g(const int32_t* __restrict__ ptr, 
     for (int32_t k = b + lane; k < e; k += L) acc += (T)val[k] * x[col[k]];
 #pragma unroll
     for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, L);
-    if (lane == 0) y[i] = accumulate ? y[i] + acc : acc;
+    if (lane == 0) y[i] = yin ? yin[i] + acc : acc;
   }
 }
 
@@ -128,7 +129,7 @@ __global__ void k_restrict_s(const T* __restrict__ r, const T* __restrict__ t, T
   }
 }
 template <typename T>
-__global__ void k_prolong_s(const T* __restrict__ zc, T* __restrict__ z, int nc, int dim) {
+__global__ void k_prolong_s(const T* __restrict__ zc, const T* zin, T* zout, int nc, int dim) {
   const int nf = 2 * nc;
   const int64_t s1 = nc + 1, f1 = nf + 1;
   const int64_t fcount = dim == 3 ? f1 * f1 * f1 : f1 * f1;
@@ -142,7 +143,7 @@ __global__ void k_prolong_s(const T* __restrict__ zc, T* __restrict__ z, int nc,
                       (at(i0, j0, k1) + at(i1, j0, k1)) + (at(i0, j1, k1) + at(i1, j1, k1)));
     else
       v = T(0.25) * ((at(i0, j0, 0) + at(i1, j0, 0)) + (at(i0, j1, 0) + at(i1, j1, 0)));
-    z[f] += v;
+    zout[f] = zin[f] + v;  // zin may be zout
   }
 }
 __global__ void k_inject_s(const double* __restrict__ fine, double* __restrict__ out, int nc, int dim) {
@@ -476,6 +477,34 @@ __global__ void k_st_pre2(const ST* __restrict__ S, const T* __restrict__ dinv, 
     z[i] = z1 + w * dinv[i] * (r[i] - az);
   }
 }
+// one damped-Jacobi sweep from z = 0 and its image: z = w D^-1 r, t = A z
+template <typename T, int DIM, typename ST>
+__global__ void k_st_pre1(const ST* __restrict__ S, const T* __restrict__ dinv, const T* __restrict__ r,
+                          T* __restrict__ z, T* __restrict__ t, T w, int s, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+    int I, J, K;
+    node_ijk<DIM>(i, s, I, J, K);
+    const int64_t s1 = s + 1;
+    T az = T(0);
+#pragma unroll
+    for (int oz = (DIM == 3 ? -1 : 0); oz <= (DIM == 3 ? 1 : 0); ++oz) {
+      if (DIM == 3 && (K + oz < 0 || K + oz > s)) continue;
+#pragma unroll
+      for (int oy = -1; oy <= 1; ++oy) {
+        if (J + oy < 0 || J + oy > s) continue;
+#pragma unroll
+        for (int ox = -1; ox <= 1; ++ox) {
+          if (I + ox < 0 || I + ox > s) continue;
+          const int o = (ox + 1) + 3 * (oy + 1) + (DIM == 3 ? 9 * (oz + 1) : 0);
+          const int64_t j = i + ox + oy * s1 + (DIM == 3 ? oz * s1 * s1 : 0);
+          az += (T)S[o * n + i] * (w * dinv[j] * r[j]);
+        }
+      }
+    }
+    z[i] = w * dinv[i] * r[i];
+    t[i] = az;
+  }
+}
 // zo = zi + w D^-1 (r - A zi)
 template <typename T, int DIM, typename ST>
 __global__ void k_st_sweep(const ST* __restrict__ S, const T* __restrict__ dinv, const T* __restrict__ r,
@@ -620,12 +649,12 @@ int vcycle(Ctx& c, int k, const T* r, T* z, hipStream_t s);
 // of the weights when all of them are exact in FP32 (dyadic Q1 weights)
 template <typename T, int L>
 void transfer(const Multigrid& mg, const int32_t* ptr, const int32_t* col, const T* val, const float* val32,
-              const T* x, T* y, int64_t rows, int accumulate, hipStream_t s) {
+              const T* x, T* y, int64_t rows, const T* yin, hipStream_t s) {
   const unsigned g = blocks(rows * L);
   if (sizeof(T) == 8 && mg.transfer32_exact)
-    k_spmv_g<T, float, L><<<g, kT, 0, s>>>(ptr, col, val32, x, y, rows, accumulate);
+    k_spmv_g<T, float, L><<<g, kT, 0, s>>>(ptr, col, val32, x, y, rows, yin);
   else
-    k_spmv_g<T, T, L><<<g, kT, 0, s>>>(ptr, col, val, x, y, rows, accumulate);
+    k_spmv_g<T, T, L><<<g, kT, 0, s>>>(ptr, col, val, x, y, rows, yin);
 }
 
 // V-cycle from a uniform coarse level k > 0 with an assembled stencil: the
@@ -658,31 +687,35 @@ int vcycle_stencil(Ctx& c, int k, const T* r, T* z, hipStream_t s) {
     if (dim == 3) k_st_sweep<T, 3, float><<<g, kT, 0, s>>>(S, dinv, r, zi, zo, w, side, n);
     else k_st_sweep<T, 2, float><<<g, kT, 0, s>>>(S, dinv, r, zi, zo, w, side, n);
   };
-  // pre-smoothing: nu sweeps from a zero guess, result in z
-  if (mg.nu >= 2) {
+  // pre-smoothing: nu sweeps from a zero guess, result in z; t = A z
+  if (mg.nu == 1) {
+    if (dim == 3) k_st_pre1<T, 3, float><<<g, kT, 0, s>>>(S, dinv, r, z, t, w, side, n);
+    else k_st_pre1<T, 2, float><<<g, kT, 0, s>>>(S, dinv, r, z, t, w, side, n);
+  } else {
     pre2();
     for (int it = 2; it < mg.nu; ++it) {
       sweep(z, z2);
       k_copy_t<T><<<g, kT, 0, s>>>(z2, z, n);
     }
-  } else {
-    k_jacobi0<T><<<g, kT, 0, s>>>(z, r, dinv, w, n);
+    if (dim == 3) k_st_apply<T, 3, float><<<g, kT, 0, s>>>(S, z, t, side, n);
+    else k_st_apply<T, 2, float><<<g, kT, 0, s>>>(S, z, t, side, n);
   }
-  if (dim == 3) k_st_apply<T, 3, float><<<g, kT, 0, s>>>(S, z, t, side, n);
-  else k_st_apply<T, 2, float><<<g, kT, 0, s>>>(S, z, t, side, n);
   T* rc_ = PR::v(C, 0);
   T* zc = PR::v(C, 1);
   k_restrict_s<T><<<blocks(C.dm.n), kT, 0, s>>>(r, t, rc_, C.dm.side, dim);
   CHNS_HIP(hipGetLastError());
   int rc;
   if ((rc = vcycle<T>(c, k + 1, rc_, zc, s))) return rc;
-  k_prolong_s<T><<<g, kT, 0, s>>>(zc, z, C.dm.side, dim);
-  // post-smoothing: nu sweeps, ping-pong between z and z2, ending in z
+  // post-smoothing: nu sweeps alternating between z and z2; for odd nu the
+  // prolongation writes the corrected iterate to z2, so they end in z
+  const bool odd = mg.nu % 2 == 1;
+  T* cur = odd ? z2 : z;
+  T* oth = odd ? z : z2;
+  k_prolong_s<T><<<g, kT, 0, s>>>(zc, z, cur, C.dm.side, dim);
   for (int it = 0; it < mg.nu; ++it) {
-    if (it % 2 == 0) sweep(z, z2);
-    else sweep(z2, z);
+    sweep(cur, oth);
+    std::swap(cur, oth);
   }
-  if (mg.nu % 2) k_copy_t<T><<<g, kT, 0, s>>>(z2, z, n);
   CHNS_HIP(hipGetLastError());
   return CHNS_OK;
 }
@@ -733,22 +766,24 @@ int vcycle(Ctx& c, int k, const T* r, T* z, hipStream_t s) {
     k_restrict_s<T><<<blocks(C.dm.n), kT, 0, s>>>(r, t, rc_, C.dm.side, C.dm.dim);
   } else {
     k_resid<T><<<g, kT, 0, s>>>(r, t, n);
-    transfer<T, 8>(mg, C.R_ptr, C.R_col, PR::Rv(C), C.R_val32, t, rc_, C.dm.n, 0, s);
+    transfer<T, 8>(mg, C.R_ptr, C.R_col, PR::Rv(C), C.R_val32, t, rc_, C.dm.n, nullptr, s);
   }
   CHNS_HIP(hipGetLastError());
   if ((rc = vcycle<T>(c, k + 1, rc_, zc, s))) return rc;
-  if (structured)
-    k_prolong_s<T><<<g, kT, 0, s>>>(zc, z, C.dm.side, C.dm.dim);
-  else
-    transfer<T, 4>(mg, C.P_ptr, C.P_col, PR::Pv(C), C.P_val32, zc, z, n, 1, s);
+  // post-smoothing alternating between z and t; for odd nu the prolongation
+  // writes the corrected iterate to t, so the sweeps end in z
   {
-    T* cur = z;
-    T* oth = t;
+    const bool odd = mg.nu % 2 == 1;
+    T* cur = odd ? t : z;
+    T* oth = odd ? z : t;
+    if (structured)
+      k_prolong_s<T><<<g, kT, 0, s>>>(zc, z, cur, C.dm.side, C.dm.dim);
+    else
+      transfer<T, 4>(mg, C.P_ptr, C.P_col, PR::Pv(C), C.P_val32, zc, cur, n, z, s);
     for (int it = 0; it < mg.nu; ++it) {
       if ((rc = launch_apply_lv(c, V, CHNS_OP_PRESSURE, PR::P, cur, oth, s, sm))) return rc;
       std::swap(cur, oth);
     }
-    if (cur != z) k_copy_t<T><<<g, kT, 0, s>>>(cur, z, n);
   }
   CHNS_HIP(hipGetLastError());
   return CHNS_OK;
