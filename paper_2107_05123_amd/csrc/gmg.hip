@@ -99,29 +99,34 @@ __global__ void k_dense(const T* M, const T* r, T* z, int n) {
 //   restriction: coarse(I) = sum_{a in -1..1}^d w(a) (r - t)(2I + a)
 //   prolongation: z(i) += coarse field at i
 //   injection: coarse(I) = fine(2I)
-template <typename T>
-__global__ void k_restrict_s(const T* __restrict__ r, const T* __restrict__ t, T* __restrict__ out, int nc,
-                             int dim) {
+// Neighbours outside the level get weight 0 at a clamped (valid) index, so
+// that every load is unconditional and a thread issues all of them at once
+// (on the small levels nothing else hides their latency); the added zeros
+// leave the sums unchanged.
+template <typename T, int DIM>
+__global__ void k_restrict_s(const T* __restrict__ r, const T* __restrict__ t, T* __restrict__ out, int nc) {
   const int nf = 2 * nc;
   const int64_t s1 = nc + 1, f1 = nf + 1;
-  const int64_t ncount = dim == 3 ? s1 * s1 * s1 : s1 * s1;
+  const int64_t ncount = DIM == 3 ? s1 * s1 * s1 : s1 * s1;
   for (int64_t c = (int64_t)blockIdx.x * kT + threadIdx.x; c < ncount; c += (int64_t)gridDim.x * kT) {
-    const int I = (int)(c % s1), J = (int)((c / s1) % s1), K = dim == 3 ? (int)(c / (s1 * s1)) : 0;
+    const int I = (int)(c % s1), J = (int)((c / s1) % s1), K = DIM == 3 ? (int)(c / (s1 * s1)) : 0;
     T acc = T(0);
-    for (int cz = (dim == 3 ? -1 : 0); cz <= (dim == 3 ? 1 : 0); ++cz) {
+#pragma unroll
+    for (int cz = (DIM == 3 ? -1 : 0); cz <= (DIM == 3 ? 1 : 0); ++cz) {
       const int k = 2 * K + cz;
-      if (k < 0 || k > nf) continue;
-      const T wz = cz ? T(0.5) : T(1);
+      const T wz = (k < 0 || k > nf) ? T(0) : (cz ? T(0.5) : T(1));
+      const int kk = min(max(k, 0), nf);
+#pragma unroll
       for (int cy = -1; cy <= 1; ++cy) {
         const int j = 2 * J + cy;
-        if (j < 0 || j > nf) continue;
-        const T wy = cy ? wz * T(0.5) : wz;
-        const int64_t row = ((int64_t)k * f1 + j) * f1;
+        const T wy = (j < 0 || j > nf) ? T(0) : (cy ? wz * T(0.5) : wz);
+        const int64_t row = ((int64_t)kk * f1 + min(max(j, 0), nf)) * f1;
+#pragma unroll
         for (int cx = -1; cx <= 1; ++cx) {
           const int i = 2 * I + cx;
-          if (i < 0 || i > nf) continue;
-          const T w = cx ? wy * T(0.5) : wy;
-          acc += w * (t ? r[row + i] - t[row + i] : r[row + i]);
+          const T w = (i < 0 || i > nf) ? T(0) : (cx ? wy * T(0.5) : wy);
+          const int64_t ii = row + min(max(i, 0), nf);
+          acc += w * (t ? r[ii] - t[ii] : r[ii]);
         }
       }
     }
@@ -421,6 +426,15 @@ __global__ void k_stencil_dense(const double* __restrict__ S, int s, double* M) 
 
 // sum_o S_o(i) v(i + off_o) on a uniform level (zero stencil entries reach
 // no node outside the level; their indices are skipped)
+//
+// Index of the neighbour at offset (ox, oy, oz), clamped into the level: the
+// stencil value of an offset outside the level is 0, so every load can be
+// unconditional (all issued at once) and the sum is the same.
+template <int DIM>
+__device__ __forceinline__ int64_t nbr(int64_t node, int ox, int oy, int oz, int64_t s1, int64_t n) {
+  const int64_t j = node + ox + oy * s1 + (DIM == 3 ? oz * s1 * s1 : 0);
+  return j < 0 ? 0 : (j >= n ? n - 1 : j);
+}
 template <typename T, int DIM, typename ST>
 __device__ __forceinline__ T stencil_row(const ST* __restrict__ S, const T* __restrict__ v, int64_t node, int64_t n,
                                          int I, int J, int K, int s) {
@@ -428,15 +442,12 @@ __device__ __forceinline__ T stencil_row(const ST* __restrict__ S, const T* __re
   T acc = T(0);
 #pragma unroll
   for (int oz = (DIM == 3 ? -1 : 0); oz <= (DIM == 3 ? 1 : 0); ++oz) {
-    if (DIM == 3 && (K + oz < 0 || K + oz > s)) continue;
 #pragma unroll
     for (int oy = -1; oy <= 1; ++oy) {
-      if (J + oy < 0 || J + oy > s) continue;
 #pragma unroll
       for (int ox = -1; ox <= 1; ++ox) {
-        if (I + ox < 0 || I + ox > s) continue;
         const int o = (ox + 1) + 3 * (oy + 1) + (DIM == 3 ? 9 * (oz + 1) : 0);
-        acc += (T)S[o * n + node] * v[node + ox + oy * s1 + (DIM == 3 ? oz * s1 * s1 : 0)];
+        acc += (T)S[o * n + node] * v[nbr<DIM>(node, ox, oy, oz, s1, n)];
       }
     }
   }
@@ -454,21 +465,16 @@ template <typename T, int DIM, typename ST>
 __global__ void k_st_pre2(const ST* __restrict__ S, const T* __restrict__ dinv, const T* __restrict__ r,
                           T* __restrict__ z, T w, int s, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
-    int I, J, K;
-    node_ijk<DIM>(i, s, I, J, K);
     const int64_t s1 = s + 1;
     T az = T(0);
 #pragma unroll
     for (int oz = (DIM == 3 ? -1 : 0); oz <= (DIM == 3 ? 1 : 0); ++oz) {
-      if (DIM == 3 && (K + oz < 0 || K + oz > s)) continue;
 #pragma unroll
       for (int oy = -1; oy <= 1; ++oy) {
-        if (J + oy < 0 || J + oy > s) continue;
 #pragma unroll
         for (int ox = -1; ox <= 1; ++ox) {
-          if (I + ox < 0 || I + ox > s) continue;
           const int o = (ox + 1) + 3 * (oy + 1) + (DIM == 3 ? 9 * (oz + 1) : 0);
-          const int64_t j = i + ox + oy * s1 + (DIM == 3 ? oz * s1 * s1 : 0);
+          const int64_t j = nbr<DIM>(i, ox, oy, oz, s1, n);
           az += (T)S[o * n + i] * (w * dinv[j] * r[j]);
         }
       }
@@ -482,21 +488,16 @@ template <typename T, int DIM, typename ST>
 __global__ void k_st_pre1(const ST* __restrict__ S, const T* __restrict__ dinv, const T* __restrict__ r,
                           T* __restrict__ z, T* __restrict__ t, T w, int s, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
-    int I, J, K;
-    node_ijk<DIM>(i, s, I, J, K);
     const int64_t s1 = s + 1;
     T az = T(0);
 #pragma unroll
     for (int oz = (DIM == 3 ? -1 : 0); oz <= (DIM == 3 ? 1 : 0); ++oz) {
-      if (DIM == 3 && (K + oz < 0 || K + oz > s)) continue;
 #pragma unroll
       for (int oy = -1; oy <= 1; ++oy) {
-        if (J + oy < 0 || J + oy > s) continue;
 #pragma unroll
         for (int ox = -1; ox <= 1; ++ox) {
-          if (I + ox < 0 || I + ox > s) continue;
           const int o = (ox + 1) + 3 * (oy + 1) + (DIM == 3 ? 9 * (oz + 1) : 0);
-          const int64_t j = i + ox + oy * s1 + (DIM == 3 ? oz * s1 * s1 : 0);
+          const int64_t j = nbr<DIM>(i, ox, oy, oz, s1, n);
           az += (T)S[o * n + i] * (w * dinv[j] * r[j]);
         }
       }
@@ -702,7 +703,8 @@ int vcycle_stencil(Ctx& c, int k, const T* r, T* z, hipStream_t s) {
   }
   T* rc_ = PR::v(C, 0);
   T* zc = PR::v(C, 1);
-  k_restrict_s<T><<<blocks(C.dm.n), kT, 0, s>>>(r, t, rc_, C.dm.side, dim);
+  if (dim == 3) k_restrict_s<T, 3><<<blocks(C.dm.n), kT, 0, s>>>(r, t, rc_, C.dm.side);
+  else k_restrict_s<T, 2><<<blocks(C.dm.n), kT, 0, s>>>(r, t, rc_, C.dm.side);
   CHNS_HIP(hipGetLastError());
   int rc;
   if ((rc = vcycle<T>(c, k + 1, rc_, zc, s))) return rc;
@@ -763,7 +765,8 @@ int vcycle(Ctx& c, int k, const T* r, T* z, hipStream_t s) {
   T* zc = PR::v(C, 1);
   const bool structured = V.dm->structured && C.dm.structured;
   if (structured) {
-    k_restrict_s<T><<<blocks(C.dm.n), kT, 0, s>>>(r, t, rc_, C.dm.side, C.dm.dim);
+    if (C.dm.dim == 3) k_restrict_s<T, 3><<<blocks(C.dm.n), kT, 0, s>>>(r, t, rc_, C.dm.side);
+    else k_restrict_s<T, 2><<<blocks(C.dm.n), kT, 0, s>>>(r, t, rc_, C.dm.side);
   } else {
     k_resid<T><<<g, kT, 0, s>>>(r, t, n);
     transfer<T, 8>(mg, C.R_ptr, C.R_col, PR::Rv(C), C.R_val32, t, rc_, C.dm.n, nullptr, s);
