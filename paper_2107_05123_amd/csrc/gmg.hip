@@ -195,7 +195,15 @@ __global__ void k_phase32(const double* a, float* b, int64_t n) {
 struct QCoef {
   double a, b, ma, mb;
   int lin;
-  __device__ __forceinline__ double k(double v) const { return lin ? a * v + b : 1.0 / (a * v + b); }
+  __device__ __forceinline__ double k(double v) const { return lin ? a * v + b : rcp(a * v + b); }
+  // hardware reciprocal estimate refined by two Newton steps
+  __device__ __forceinline__ static double rcp(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    e = __builtin_fma(-x, y, 1.0);
+    return __builtin_fma(y, e, y);
+  }
   __device__ __forceinline__ double m(double v) const { return ma * v + mb; }
 };
 
@@ -273,16 +281,27 @@ __global__ __launch_bounds__(64) void k_gal_phi(const double* __restrict__ phi, 
   if constexpr (VARM) {
     for (int k = t; k < NE * NE; k += 64) hm[k] = Hm[k];
   }
-  const int64_t e0 = (int64_t)blockIdx.x * kGalPerWave;
-  for (int64_t e = e0; e < e0 + kGalPerWave && e < ne; ++e) {
+  // lane t: child c = t / NC, Gauss point q = t % NC of that child; the
+  // child's corner phase values of the next element are loaded while the
+  // current one is reduced
+  const int c = t / NC, q = t % NC;
+  auto load = [&](int64_t e, double* ph) {
     const int X = (int)(e % sc), Y = (int)((e / sc) % sc), Z = DIM == 3 ? (int)(e / ((int64_t)sc * sc)) : 0;
+    const int cx = 2 * X + (c & 1), cy = 2 * Y + ((c >> 1) & 1), cz = DIM == 3 ? 2 * Z + ((c >> 2) & 1) : 0;
+#pragma unroll
+    for (int b = 0; b < NC; ++b)
+      ph[b] = phi[((int64_t)(cz + ((b >> 2) & 1)) * f1 + (cy + ((b >> 1) & 1))) * f1 + (cx + (b & 1))];
+  };
+  const int64_t e0 = (int64_t)blockIdx.x * kGalPerWave;
+  const int64_t e1 = e0 + kGalPerWave < ne ? e0 + kGalPerWave : ne;
+  double nx[NC];
+  if (t < NE && e0 < e1) load(e0, nx);
+  for (int64_t e = e0; e < e1; ++e) {
+    double ph[NC];
+#pragma unroll
+    for (int b = 0; b < NC; ++b) ph[b] = nx[b];
+    if (t < NE && e + 1 < e1) load(e + 1, nx);
     if (t < NE) {
-      // lane t: child c = t / NC, Gauss point q = t % NC of that child
-      const int c = t / NC, q = t % NC;
-      const int cx = 2 * X + (c & 1), cy = 2 * Y + ((c >> 1) & 1), cz = DIM == 3 ? 2 * Z + ((c >> 2) & 1) : 0;
-      double ph[NC];
-      for (int b = 0; b < NC; ++b)
-        ph[b] = phi[((int64_t)(cz + ((b >> 2) & 1)) * f1 + (cy + ((b >> 1) & 1))) * f1 + (cx + (b & 1))];
       const double v = phase_at(ph, q, DIM);
       cq[t] = cf.k(v);
       if constexpr (VARM) cm[t] = cf.m(v);
@@ -384,21 +403,40 @@ __global__ void k_diag_phi(const double* __restrict__ phi, int s, const double* 
   constexpr int NC = 1 << DIM, NE = NC * NC;
   const int64_t s1 = s + 1;
   const int64_t n = DIM == 3 ? s1 * s1 * s1 : s1 * s1;
+  constexpr int NB = DIM == 3 ? 27 : 9;
   for (int64_t node = (int64_t)blockIdx.x * kT + threadIdx.x; node < n; node += (int64_t)gridDim.x * kT) {
     const int I = (int)(node % s1), J = (int)((node / s1) % s1), K = DIM == 3 ? (int)(node / (s1 * s1)) : 0;
+    // the 3^d phase values around the node, loaded once (clamped indices:
+    // the values of elements outside the level are computed but not added)
+    double p[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      const int i = min(max(I + c % 3 - 1, 0), s), j = min(max(J + (c / 3) % 3 - 1, 0), s);
+      const int k = DIM == 3 ? min(max(K + c / 9 - 1, 0), s) : 0;
+      p[c] = phi[((int64_t)k * s1 + j) * s1 + i];
+    }
     double acc = 0.0, macc = 0.0;
+#pragma unroll
     for (int u = 0; u < NC; ++u) {
       const int ux = u & 1, uy = (u >> 1) & 1, uz = DIM == 3 ? (u >> 2) & 1 : 0;
       const int ax = I - ux, ay = J - uy, az = K - uz;
-      if (ax < 0 || ax >= s || ay < 0 || ay >= s || (DIM == 3 && (az < 0 || az >= s))) continue;
+      const bool inside = ax >= 0 && ax < s && ay >= 0 && ay < s && (DIM == 2 || (az >= 0 && az < s));
       double ph[NC];
-      for (int b = 0; b < NC; ++b)
-        ph[b] = phi[((int64_t)(az + ((b >> 2) & 1)) * s1 + (ay + ((b >> 1) & 1))) * s1 + (ax + (b & 1))];
+#pragma unroll
+      for (int b = 0; b < NC; ++b) {
+        // corner b of the element sits at offset (b - u) from the node
+        const int ox = (b & 1) - ux, oy = ((b >> 1) & 1) - uy, oz = DIM == 3 ? ((b >> 2) & 1) - uz : 0;
+        ph[b] = p[(ox + 1) + 3 * (oy + 1) + (DIM == 3 ? 9 * (oz + 1) : 0)];
+      }
+      double ea = 0.0, em = 0.0;
+#pragma unroll
       for (int q = 0; q < NC; ++q) {
         const double v = phase_at(ph, q, DIM);
-        acc += cf.k(v) * Gt[q * NE + u * NC + u];
-        macc += cf.m(v) * Mq[q * NE + u * NC + u];
+        ea += cf.k(v) * Gt[q * NE + u * NC + u];
+        em += cf.m(v) * Mq[q * NE + u * NC + u];
       }
+      acc += inside ? ea : 0.0;
+      macc += inside ? em : 0.0;
     }
     const double d = scale * acc + mscale * macc;
     dinv64[node] = 1.0 / d;
