@@ -104,11 +104,10 @@ __global__ void k_dense(const T* M, const T* r, T* z, int n) {
 // (on the small levels nothing else hides their latency); the added zeros
 // leave the sums unchanged.
 template <typename T, int DIM>
-__global__ void k_restrict_s(const T* __restrict__ r, const T* __restrict__ t, T* __restrict__ out, int nc) {
+__device__ __forceinline__ T restrict_at(const T* __restrict__ r, const T* __restrict__ t, int64_t c, int nc) {
   const int nf = 2 * nc;
   const int64_t s1 = nc + 1, f1 = nf + 1;
-  const int64_t ncount = DIM == 3 ? s1 * s1 * s1 : s1 * s1;
-  for (int64_t c = (int64_t)blockIdx.x * kT + threadIdx.x; c < ncount; c += (int64_t)gridDim.x * kT) {
+  {
     const int I = (int)(c % s1), J = (int)((c / s1) % s1), K = DIM == 3 ? (int)(c / (s1 * s1)) : 0;
     T acc = T(0);
 #pragma unroll
@@ -130,26 +129,34 @@ __global__ void k_restrict_s(const T* __restrict__ r, const T* __restrict__ t, T
         }
       }
     }
-    out[c] = acc;
+    return acc;
   }
+}
+template <typename T, int DIM>
+__global__ void k_restrict_s(const T* __restrict__ r, const T* __restrict__ t, T* __restrict__ out, int nc) {
+  const int64_t s1 = nc + 1;
+  const int64_t ncount = DIM == 3 ? s1 * s1 * s1 : s1 * s1;
+  for (int64_t c = (int64_t)blockIdx.x * kT + threadIdx.x; c < ncount; c += (int64_t)gridDim.x * kT)
+    out[c] = restrict_at<T, DIM>(r, t, c, nc);
+}
+// coarse-field value at fine node f (bilinear / trilinear interpolation)
+template <typename T>
+__device__ __forceinline__ T prolong_at(const T* __restrict__ zc, int64_t f, int nc, int dim) {
+  const int64_t s1 = nc + 1, f1 = 2 * nc + 1;
+  const int i = (int)(f % f1), j = (int)((f / f1) % f1), k = dim == 3 ? (int)(f / (f1 * f1)) : 0;
+  const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1, k0 = k >> 1, k1 = (k + 1) >> 1;
+  auto at = [&](int a, int b, int c) { return zc[((int64_t)c * s1 + b) * s1 + a]; };
+  if (dim == 3)
+    return T(0.125) * ((at(i0, j0, k0) + at(i1, j0, k0)) + (at(i0, j1, k0) + at(i1, j1, k0)) +
+                       (at(i0, j0, k1) + at(i1, j0, k1)) + (at(i0, j1, k1) + at(i1, j1, k1)));
+  return T(0.25) * ((at(i0, j0, 0) + at(i1, j0, 0)) + (at(i0, j1, 0) + at(i1, j1, 0)));
 }
 template <typename T>
 __global__ void k_prolong_s(const T* __restrict__ zc, const T* zin, T* zout, int nc, int dim) {
-  const int nf = 2 * nc;
-  const int64_t s1 = nc + 1, f1 = nf + 1;
+  const int64_t f1 = 2 * nc + 1;
   const int64_t fcount = dim == 3 ? f1 * f1 * f1 : f1 * f1;
-  for (int64_t f = (int64_t)blockIdx.x * kT + threadIdx.x; f < fcount; f += (int64_t)gridDim.x * kT) {
-    const int i = (int)(f % f1), j = (int)((f / f1) % f1), k = dim == 3 ? (int)(f / (f1 * f1)) : 0;
-    const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1, k0 = k >> 1, k1 = (k + 1) >> 1;
-    auto at = [&](int a, int b, int c) { return zc[((int64_t)c * s1 + b) * s1 + a]; };
-    T v;
-    if (dim == 3)
-      v = T(0.125) * ((at(i0, j0, k0) + at(i1, j0, k0)) + (at(i0, j1, k0) + at(i1, j1, k0)) +
-                      (at(i0, j0, k1) + at(i1, j0, k1)) + (at(i0, j1, k1) + at(i1, j1, k1)));
-    else
-      v = T(0.25) * ((at(i0, j0, 0) + at(i1, j0, 0)) + (at(i0, j1, 0) + at(i1, j1, 0)));
-    zout[f] = zin[f] + v;  // zin may be zout
-  }
+  for (int64_t f = (int64_t)blockIdx.x * kT + threadIdx.x; f < fcount; f += (int64_t)gridDim.x * kT)
+    zout[f] = zin[f] + prolong_at<T>(zc, f, nc, dim);  // zin may be zout
 }
 __global__ void k_inject_s(const double* __restrict__ fine, double* __restrict__ out, int nc, int dim) {
   const int64_t s1 = nc + 1, f1 = 2 * nc + 1;
