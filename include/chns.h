@@ -154,7 +154,9 @@ enum { CHNS_FP64 = 0, CHNS_FP32 = 1 };
 /* y = Op x, matrix-free: per leaf, gather (with hanging-node interpolation),
  * 2-point Gauss quadrature, and a conflict-free deterministic scatter-add
  * (transpose interpolation).  x and y: device, n_fields * n_nodes of the
- * precision's type; x and y must not alias.  Async.                         */
+ * precision's type; x and y must not alias.  CHNS_FP32 is available for
+ * PRESSURE, MASS, MASS_RHO and MOMENTUM_SCALAR; MOMENTUM and CH_JACOBIAN are
+ * FP64 only (CHNS_EINVAL).  Async.                                          */
 int chns_apply_operator(chns_ctx* ctx, int op, int prec, const void* x, void* y, void* stream);
 
 /* Exact diagonal of the constrained operator diag(P^T (sum_e K_e) P),
