@@ -105,6 +105,40 @@ int chns_mesh_leaves(const chns_mesh* mesh, int32_t* level, int64_t* anchor);
  * (independent-node indices, -1 padded), host buffers.                     */
 int chns_mesh_hanging(const chns_mesh* mesh, int64_t* coords, int32_t* parents);
 
+/* ------------------------------------------------------------- remeshing */
+
+/* Remeshing by the phase field (paper: adaptive refinement of the interface
+ * region |phi| <= 0.95, Sec. 4.2 top-down refinement by a predicate, and the
+ * scaling section's refine/coarsen as the interface moves): a new octree of
+ * the same dimension and max_level whose octants are refined to max_level
+ * wherever the nodal values of `phi` inside the octant's half-open box (the
+ * old mesh's independent nodes, and its hanging nodes at the mean of their
+ * parents) span a range that meets [-threshold, threshold], and to
+ * min_level elsewhere; 2:1 balanced like chns_octree_build.  phi: host,
+ * old n_nodes doubles in vector order.  brick_max as in chns_mesh_spec.
+ * Host-only.  EINVAL on a bad argument; *out is owned by the caller.       */
+int chns_mesh_remesh(const chns_mesh* old, const double* phi, int min_level, double threshold, int brick_max,
+                     chns_mesh** out);
+
+/* Intergrid transfer of nodal fields from mesh `from` to mesh `to` (same
+ * dimension and max_level; paper Sec. 4, traversal-based intergrid
+ * transfers): every node of `to` takes the value of the Q1 field of `from`
+ * (hanging constraints included) at its position.  This copies at
+ * coincident nodes, interpolates the shape functions into refined leaves and
+ * takes the coinciding fine values for coarsened ones; with nested Q1
+ * spaces it equals any sequence of one-level transfers.  Not conservative.
+ * create: host-only, builds the CSR (rows: nodes of `to`, columns: nodes of
+ * `from`); info / matrix copy it to host buffers (ptr rows + 1, col and val
+ * nnz); apply: y (rows * n_fields, device) = the transfer of x (cols *
+ * n_fields, device), field-blocked, on `stream`; x and y must not alias; the
+ * first apply uploads the CSR to the current device.  Async.               */
+typedef struct chns_transfer chns_transfer;
+int chns_transfer_create(const chns_mesh* from, const chns_mesh* to, chns_transfer** out);
+int chns_transfer_info(const chns_transfer* t, int64_t* rows, int64_t* cols, int64_t* nnz);
+int chns_transfer_matrix(const chns_transfer* t, int32_t* ptr, int32_t* col, double* val);
+int chns_transfer_apply(chns_transfer* t, int n_fields, const double* x, double* y, void* stream);
+int chns_transfer_destroy(chns_transfer* t);
+
 /* --------------------------------------------------------------- context */
 
 /* Non-dimensional parameters (paper Sec. 2 and its non-dimensionalisation

@@ -79,6 +79,27 @@ class Mesh:
         L.check(L.lib().chns_mesh_info_get(self._h, C.byref(info)))
         return info
 
+    @classmethod
+    def _wrap(cls, h, dim):
+        m = cls.__new__(cls)
+        m._keep = []
+        m._h = h
+        m._destroy = L.lib().chns_mesh_destroy
+        m.dim = dim
+        m.info = m._info()
+        return m
+
+    def remesh(self, phi, min_level, threshold=0.95, brick_max=0) -> "Mesh":
+        """New mesh refined to max_level where the nodal phase field (host
+        array in this mesh's vector order) meets |phi| <= threshold."""
+        p = np.ascontiguousarray(np.asarray(phi, dtype=np.float64).reshape(-1))
+        if p.shape[0] != self.n_nodes:
+            raise ValueError("phi must have one value per node")
+        h = C.c_void_p()
+        L.check(L.lib().chns_mesh_remesh(self._h, p.ctypes.data_as(C.c_void_p), int(min_level), float(threshold),
+                                         int(brick_max), C.byref(h)))
+        return Mesh._wrap(h, self.dim)
+
     @property
     def n_nodes(self) -> int:
         return int(self.info.n_nodes)
@@ -130,6 +151,45 @@ class Mesh:
 
 def octree_build(**kw) -> Mesh:
     return Mesh(**kw)
+
+
+class Transfer:
+    """Intergrid transfer of nodal fields from one mesh to another (same
+    dimension and max_level): each node of `dst` takes the Q1 field of `src`
+    at its position."""
+
+    def __init__(self, src: Mesh, dst: Mesh):
+        h = C.c_void_p()
+        L.check(L.lib().chns_transfer_create(src._h, dst._h, C.byref(h)))
+        self._h = h
+        self._destroy = L.lib().chns_transfer_destroy
+        r, c, z = C.c_int64(), C.c_int64(), C.c_int64()
+        L.check(L.lib().chns_transfer_info(h, C.byref(r), C.byref(c), C.byref(z)))
+        self.rows, self.cols, self.nnz = r.value, c.value, z.value
+
+    def matrix(self):
+        """(ptr, col, val) of the CSR on the host."""
+        ptr = np.empty(self.rows + 1, dtype=np.int32)
+        col = np.empty(max(self.nnz, 1), dtype=np.int32)
+        val = np.empty(max(self.nnz, 1), dtype=np.float64)
+        L.check(L.lib().chns_transfer_matrix(self._h, ptr.ctypes.data_as(C.c_void_p),
+                                             col.ctypes.data_as(C.c_void_p), val.ctypes.data_as(C.c_void_p)))
+        return ptr, col[:self.nnz], val[:self.nnz]
+
+    def apply(self, x, n_fields=1, y=None, stream=None):
+        import torch
+        if y is None:
+            y = torch.empty(n_fields * self.rows, dtype=torch.float64, device=x.device)
+        L.check(L.lib().chns_transfer_apply(self._h, int(n_fields), _dev_ptr(x, torch.float64, n_fields * self.cols),
+                                            _dev_ptr(y, torch.float64, n_fields * self.rows), _stream_ptr(stream)))
+        return y
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        destroy = getattr(self, "_destroy", None)
+        if h is not None and h.value and destroy is not None:
+            destroy(h)
+            h.value = None
 
 
 @dataclass

@@ -99,6 +99,13 @@ SIGNATURES = {
     "chns_mesh_node_coords": (C.c_int, [C.c_void_p, C.c_void_p]),
     "chns_mesh_leaves": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "chns_mesh_hanging": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "chns_mesh_remesh": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_int, C.POINTER(C.c_void_p)]),
+    "chns_transfer_create": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "chns_transfer_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                     C.POINTER(C.c_int64)]),
+    "chns_transfer_matrix": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "chns_transfer_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "chns_transfer_destroy": (C.c_int, [C.c_void_p]),
     "chns_context_create": (C.c_int, [C.c_void_p, C.POINTER(Params), C.POINTER(C.c_void_p)]),
     "chns_context_destroy": (C.c_int, [C.c_void_p]),
     "chns_set_phase_field": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

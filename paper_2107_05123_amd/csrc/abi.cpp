@@ -1,6 +1,7 @@
 // C ABI entry points of libchns (declared in include/chns.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -232,6 +233,110 @@ int chns_mesh_hanging(const chns_mesh* mesh, int64_t* coords, int32_t* parents) 
     for (int d = 0; d < m.dim; ++d) coords[h * m.dim + d] = m.hang_coords[3 * h + d];
     for (int q = 0; q < 4; ++q) parents[4 * h + q] = m.hang_parents[4 * h + q];
   }
+  return CHNS_OK;
+}
+
+int chns_mesh_remesh(const chns_mesh* old, const double* phi, int min_level, double threshold, int brick_max,
+                     chns_mesh** out) {
+  CHNS_GUARD_BEGIN
+  if (!old || !phi || !out) {
+    set_error("null argument");
+    return CHNS_EINVAL;
+  }
+  *out = nullptr;
+  auto* m = new chns_mesh();
+  std::string msg;
+  int rc = build_host_mesh_remesh(old->m, phi, min_level, threshold, brick_max, m->m, msg);
+  if (rc) {
+    set_error(msg);
+    delete m;
+    return rc;
+  }
+  *out = m;
+  return CHNS_OK;
+  CHNS_GUARD_END
+}
+
+chns_transfer::~chns_transfer() {
+  if (d_ptr) (void)hipFree(d_ptr);
+  if (d_col) (void)hipFree(d_col);
+  if (d_val) (void)hipFree(d_val);
+}
+
+int chns_transfer_create(const chns_mesh* from, const chns_mesh* to, chns_transfer** out) {
+  CHNS_GUARD_BEGIN
+  if (!from || !to || !out) {
+    set_error("null argument");
+    return CHNS_EINVAL;
+  }
+  *out = nullptr;
+  auto* t = new chns_transfer();
+  std::string msg;
+  int rc = build_interp(from->m, to->m, t->ptr, t->col, t->val, msg);
+  if (rc) {
+    set_error(msg);
+    delete t;
+    return rc;
+  }
+  t->rows = to->m.n_indep;
+  t->cols = from->m.n_indep;
+  *out = t;
+  return CHNS_OK;
+  CHNS_GUARD_END
+}
+
+int chns_transfer_info(const chns_transfer* t, int64_t* rows, int64_t* cols, int64_t* nnz) {
+  if (!t || !rows || !cols || !nnz) {
+    set_error("null argument");
+    return CHNS_EINVAL;
+  }
+  *rows = t->rows;
+  *cols = t->cols;
+  *nnz = (int64_t)t->val.size();
+  return CHNS_OK;
+}
+
+int chns_transfer_matrix(const chns_transfer* t, int32_t* ptr, int32_t* col, double* val) {
+  if (!t || !ptr || (!t->val.empty() && (!col || !val))) {
+    set_error("null argument");
+    return CHNS_EINVAL;
+  }
+  std::copy(t->ptr.begin(), t->ptr.end(), ptr);
+  std::copy(t->col.begin(), t->col.end(), col);
+  std::copy(t->val.begin(), t->val.end(), val);
+  return CHNS_OK;
+}
+
+int chns_transfer_apply(chns_transfer* t, int n_fields, const double* x, double* y, void* stream) {
+  CHNS_GUARD_BEGIN
+  if (!t || !x || !y || n_fields < 1 || (const void*)x == (const void*)y) {
+    set_error("null argument, n_fields < 1 or aliased x and y");
+    return CHNS_EINVAL;
+  }
+  int dev = 0;
+  CHNS_HIP(hipGetDevice(&dev));
+  if (t->device != dev) {
+    if (t->device >= 0) {
+      set_error("transfer was uploaded to another device");
+      return CHNS_EINVAL;
+    }
+    const size_t nnz = t->val.size();
+    CHNS_HIP(hipMalloc(&t->d_ptr, sizeof(int32_t) * t->ptr.size()));
+    CHNS_HIP(hipMalloc(&t->d_col, sizeof(int32_t) * std::max<size_t>(nnz, 1)));
+    CHNS_HIP(hipMalloc(&t->d_val, sizeof(double) * std::max<size_t>(nnz, 1)));
+    CHNS_HIP(hipMemcpy(t->d_ptr, t->ptr.data(), sizeof(int32_t) * t->ptr.size(), hipMemcpyHostToDevice));
+    if (nnz) {
+      CHNS_HIP(hipMemcpy(t->d_col, t->col.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
+      CHNS_HIP(hipMemcpy(t->d_val, t->val.data(), sizeof(double) * nnz, hipMemcpyHostToDevice));
+    }
+    t->device = dev;
+  }
+  return interp_apply(t->d_ptr, t->d_col, t->d_val, t->rows, t->cols, n_fields, x, y, (hipStream_t)stream);
+  CHNS_GUARD_END
+}
+
+int chns_transfer_destroy(chns_transfer* t) {
+  delete t;
   return CHNS_OK;
 }
 

@@ -285,6 +285,9 @@ int launch_block_diagonal(Ctx& c, int op, double* blk, double* xi, double* yi, h
 int mg_build(Ctx& c);
 int mg_setup(Ctx& c, hipStream_t s);
 int mg_vcycle64(Ctx& c, const double* r, double* z, hipStream_t s);
+// y = P x per field (CSR P: rows x cols; x, y field-blocked, nf fields)
+int interp_apply(const int32_t* ptr, const int32_t* col, const double* val, int64_t rows, int64_t cols, int nf,
+                 const double* x, double* y, hipStream_t s);
 int mg_vcycle32(Ctx& c, const float* r, float* z, hipStream_t s);
 
 // ---- krylov (krylov.hip)
@@ -324,6 +327,16 @@ void destroy_stepper(Ctx& c);
 
 struct chns_mesh {
   chns::HostMesh m;
+};
+struct chns_transfer {
+  int64_t rows = 0, cols = 0;
+  std::vector<int32_t> ptr, col;
+  std::vector<double> val;
+  // device copy, uploaded by the first apply
+  int device = -1;
+  int32_t *d_ptr = nullptr, *d_col = nullptr;
+  double* d_val = nullptr;
+  ~chns_transfer();
 };
 struct chns_ctx {
   chns::Ctx c;

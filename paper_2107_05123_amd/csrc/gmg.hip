@@ -1199,6 +1199,15 @@ int mg_setup(Ctx& c, hipStream_t s) {
 }
 
 int mg_vcycle64(Ctx& c, const double* r, double* z, hipStream_t s) { return vcycle<double>(c, 0, r, z, s); }
+
+int interp_apply(const int32_t* ptr, const int32_t* col, const double* val, int64_t rows, int64_t cols, int nf,
+                 const double* x, double* y, hipStream_t s) {
+  for (int f = 0; f < nf; ++f)
+    k_spmv_g<double, double, 4><<<blocks(rows * 4), kT, 0, s>>>(ptr, col, val, x + f * cols, y + f * rows, rows,
+                                                                nullptr);
+  CHNS_HIP(hipGetLastError());
+  return CHNS_OK;
+}
 int mg_vcycle32(Ctx& c, const float* r, float* z, hipStream_t s) { return vcycle<float>(c, 0, r, z, s); }
 
 }  // namespace chns

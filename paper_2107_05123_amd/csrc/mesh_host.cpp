@@ -869,6 +869,30 @@ struct NodeLookup {
   }
 };
 
+// a node entry (independent id, or -(h + 1) for hanging node h) with weight
+// w, hanging nodes expanded into their parents (equal shares)
+void expand_entry(const HostMesh& m, int32_t entry, double w, std::vector<std::pair<int32_t, double>>& row) {
+  if (entry >= 0) {
+    row.push_back({entry, w});
+    return;
+  }
+  const int64_t h = -entry - 1;
+  const int np = m.hang_npar[h];
+  for (int q = 0; q < np; ++q) row.push_back({m.hang_parents[4 * h + q], w / np});
+}
+// sort by column, sum duplicates, drop zeros
+void merge_row(std::vector<std::pair<int32_t, double>>& row) {
+  std::sort(row.begin(), row.end());
+  std::vector<std::pair<int32_t, double>> out;
+  for (auto& e : row) {
+    if (!out.empty() && out.back().first == e.first) out.back().second += e.second;
+    else out.push_back(e);
+  }
+  row.clear();
+  for (auto& e : out)
+    if (e.second != 0.0) row.push_back(e);
+}
+
 void to_csr(const std::vector<std::vector<std::pair<int32_t, double>>>& rows, std::vector<int32_t>& ptr,
             std::vector<int32_t>& col, std::vector<double>& val) {
   ptr.assign(1, 0);
@@ -897,26 +921,8 @@ int build_transfer(const HostMesh& fine, const HostMesh& coarse, Transfer& t, st
   for (int64_t e = 0; e < coarse.n_elems(); ++e)
     leaves.insert(leaf_key(dim, coarse.leaf_level[e], &coarse.leaf_anchor[3 * e]));
   NodeLookup cl(coarse), fl(fine);
-  auto expand = [&](const HostMesh& m, int32_t entry, double w, std::vector<std::pair<int32_t, double>>& row) {
-    if (entry >= 0) {
-      row.push_back({entry, w});
-      return;
-    }
-    const int64_t h = -entry - 1;
-    const int np = m.hang_npar[h];
-    for (int q = 0; q < np; ++q) row.push_back({m.hang_parents[4 * h + q], w / np});
-  };
-  auto merge = [](std::vector<std::pair<int32_t, double>>& row) {
-    std::sort(row.begin(), row.end());
-    std::vector<std::pair<int32_t, double>> out;
-    for (auto& e : row) {
-      if (!out.empty() && out.back().first == e.first) out.back().second += e.second;
-      else out.push_back(e);
-    }
-    row.clear();
-    for (auto& e : out)
-      if (e.second != 0.0) row.push_back(e);
-  };
+  auto expand = expand_entry;
+  auto merge = merge_row;
   // prolongation rows: fine independent node <- coarse Q1 field at its position
   std::vector<std::vector<std::pair<int32_t, double>>> P(fine.n_indep);
   for (int64_t i = 0; i < fine.n_indep; ++i) {
@@ -989,6 +995,159 @@ int build_host_mesh(const chns_mesh_spec& spec, HostMesh& m, std::string& msg) {
   } catch (const std::logic_error& e) {
     msg = std::string("internal consistency check failed: ") + e.what();
     return CHNS_EINVAL;
+  }
+}
+
+// ------------------------------------------------------------ remeshing
+namespace {
+
+// Range of a nodal field over the nodes inside half-open aligned octants:
+// the nodes sorted by Morton key (the box of an aligned octant is one key
+// range), with per-block minima and maxima for the range queries.
+struct BandQuery {
+  static constexpr int64_t kBlk = 1024;
+  int dim, L;
+  double thr;
+  std::vector<uint64_t> key;
+  std::vector<double> v, bmin, bmax;
+
+  BandQuery(const HostMesh& m, const double* phi, double t) : dim(m.dim), L(m.max_level), thr(t) {
+    std::vector<std::pair<uint64_t, double>> kv;
+    kv.reserve((size_t)(m.n_indep + m.n_hanging));
+    for (int64_t i = 0; i < m.n_indep; ++i) kv.push_back({morton(dim, &m.indep_coords[3 * i]), phi[i]});
+    for (int64_t h = 0; h < m.n_hanging; ++h) {
+      // a hanging node's value: the mean of its parents (its constraint)
+      const int np = m.hang_npar[h];
+      double s = 0.0;
+      for (int q = 0; q < np; ++q) s += phi[m.hang_parents[4 * h + q]];
+      kv.push_back({morton(dim, &m.hang_coords[3 * h]), s / np});
+    }
+    std::sort(kv.begin(), kv.end());
+    key.resize(kv.size());
+    v.resize(kv.size());
+    for (size_t i = 0; i < kv.size(); ++i) {
+      key[i] = kv[i].first;
+      v[i] = kv[i].second;
+    }
+    const int64_t nb = ((int64_t)v.size() + kBlk - 1) / kBlk;
+    bmin.assign((size_t)nb, INFINITY);
+    bmax.assign((size_t)nb, -INFINITY);
+    for (size_t i = 0; i < v.size(); ++i) {
+      bmin[i / kBlk] = std::min(bmin[i / kBlk], v[i]);
+      bmax[i / kBlk] = std::max(bmax[i / kBlk], v[i]);
+    }
+  }
+  // do the values of the keys in [lo, hi) span a range meeting [-thr, thr]?
+  bool meets(uint64_t lo, uint64_t hi) const {
+    int64_t a = std::lower_bound(key.begin(), key.end(), lo) - key.begin();
+    const int64_t b = std::lower_bound(key.begin(), key.end(), hi) - key.begin();
+    if (a >= b) return false;
+    double mn = INFINITY, mx = -INFINITY;
+    while (a < b) {
+      if (a % kBlk == 0 && a + kBlk <= b) {
+        mn = std::min(mn, bmin[a / kBlk]);
+        mx = std::max(mx, bmax[a / kBlk]);
+        a += kBlk;
+      } else {
+        mn = std::min(mn, v[a]);
+        mx = std::max(mx, v[a]);
+        ++a;
+      }
+    }
+    return mx >= -thr && mn <= thr;
+  }
+};
+
+int band_refine(const int64_t anchor[3], int level, void* user) {
+  const BandQuery& q = *static_cast<const BandQuery*>(user);
+  const int32_t a[3] = {(int32_t)anchor[0], (int32_t)anchor[1], (int32_t)anchor[2]};
+  const uint64_t lo = morton(q.dim, a);
+  return q.meets(lo, lo + (1ull << (q.dim * (q.L - level)))) ? 1 : 0;
+}
+
+}  // namespace
+
+int build_host_mesh_remesh(const HostMesh& old, const double* phi, int min_level, double thr, int brick_max,
+                           HostMesh& out, std::string& msg) {
+  if (!phi || min_level < 0 || min_level > old.max_level || !(thr >= 0.0)) {
+    msg = "remesh needs the phase field, 0 <= min_level <= max_level and threshold >= 0";
+    return CHNS_EINVAL;
+  }
+  try {
+    BandQuery q(old, phi, thr);
+    chns_mesh_spec sp{};
+    sp.dim = old.dim;
+    sp.min_level = min_level;
+    sp.max_level = old.max_level;
+    sp.rule = CHNS_RULE_CALLBACK;
+    sp.refine = band_refine;
+    sp.user = &q;
+    sp.brick_max = brick_max;
+    return build_host_mesh(sp, out, msg);
+  } catch (const std::bad_alloc&) {
+    msg = "host allocation failed while remeshing";
+    return CHNS_ENOMEM;
+  }
+}
+
+int build_interp(const HostMesh& src, const HostMesh& dst, std::vector<int32_t>& ptr, std::vector<int32_t>& col,
+                 std::vector<double>& val, std::string& msg) {
+  if (src.dim != dst.dim || src.max_level != dst.max_level) {
+    msg = "transfer needs meshes of the same dimension and max_level";
+    return CHNS_EINVAL;
+  }
+  try {
+    const int dim = src.dim, L = src.max_level;
+    const int32_t side = 1 << L;
+    const int nc = 1 << dim;
+    KeySet leaves((size_t)src.n_elems() * 2);
+    for (int64_t e = 0; e < src.n_elems(); ++e)
+      leaves.insert(leaf_key(dim, src.leaf_level[e], &src.leaf_anchor[3 * e]));
+    NodeLookup sl(src);
+    std::vector<std::vector<std::pair<int32_t, double>>> rows((size_t)dst.n_indep);
+    for (int64_t i = 0; i < dst.n_indep; ++i) {
+      const int32_t* x = &dst.indep_coords[3 * i];
+      // the source leaf whose box holds x (nudged inside at the far faces)
+      int32_t af[3] = {0, 0, 0};
+      int32_t sf = 0;
+      int found = -1;
+      for (int lev = L; lev >= 0 && found < 0; --lev) {
+        sf = 1 << (L - lev);
+        for (int d = 0; d < dim; ++d) {
+          const int32_t q2 = 2 * x[d] + (x[d] < side ? 1 : -1);
+          af[d] = (q2 / (2 * sf)) * sf;
+        }
+        if (leaves.contains(leaf_key(dim, lev, af))) found = lev;
+      }
+      if (found < 0) {
+        msg = "node outside the source mesh";
+        return CHNS_EINVAL;
+      }
+      // the source Q1 field at x: trilinear weights of the leaf's corners
+      for (int a = 0; a < nc; ++a) {
+        double w = 1.0;
+        int32_t cc[3] = {0, 0, 0};
+        for (int d = 0; d < dim; ++d) {
+          const int bit = (a >> d) & 1;
+          const double xi = (double)(x[d] - af[d]) / sf;
+          w *= bit ? xi : 1.0 - xi;
+          cc[d] = af[d] + bit * sf;
+        }
+        if (w == 0.0) continue;
+        int32_t ent;
+        if (!sl.find(cc, &ent)) {
+          msg = "source leaf corner missing";
+          return CHNS_EINVAL;
+        }
+        expand_entry(src, ent, w, rows[(size_t)i]);
+      }
+      merge_row(rows[(size_t)i]);
+    }
+    to_csr(rows, ptr, col, val);
+    return CHNS_OK;
+  } catch (const std::bad_alloc&) {
+    msg = "host allocation failed while building the transfer";
+    return CHNS_ENOMEM;
   }
 }
 

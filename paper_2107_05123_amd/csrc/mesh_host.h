@@ -86,4 +86,16 @@ struct Transfer {
 };
 int build_transfer(const HostMesh& fine, const HostMesh& coarse, Transfer& t, std::string& msg);
 
+// Remeshing by the phase field: a new octree of the same dimension and
+// max_level, refined to max_level wherever the nodal values of phi (old
+// mesh, vector order) inside an octant's half-open box span a range meeting
+// [-thr, thr], and to min_level elsewhere; 2:1 balanced.
+int build_host_mesh_remesh(const HostMesh& old, const double* phi, int min_level, double thr, int brick_max,
+                           HostMesh& out, std::string& msg);
+// Intergrid transfer of nodal fields: row i (destination node i) evaluates
+// the source Q1 field, hanging constraints included, at the node's
+// position.  CSR with dst.n_indep rows and src.n_indep columns.
+int build_interp(const HostMesh& src, const HostMesh& dst, std::vector<int32_t>& ptr, std::vector<int32_t>& col,
+                 std::vector<double>& val, std::string& msg);
+
 }  // namespace chns
