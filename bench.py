@@ -366,11 +366,14 @@ def adaptive_workload(torch, lmax):
     return out
 
 
-def bubble_steps(torch, lmax, nsteps, ch_pc="block", restart=16, vp_pc="jacobi", modes=("fp64", "mixed")):
+def bubble_steps(torch, lmax, nsteps, ch_pc="block", restart=16, vp_pc="jacobi", modes=("fp64", "mixed"),
+                 remesh_every=0):
     """Projection time steps of the 3D rising bubble (density ratio 1000,
     viscosity ratio 100, Re 35, We 10, Cn 0.005, dt 5e-4) on the adaptive
-    octree of levels 5..lmax refined within 3 Cn of the interface."""
-    from paper_2107_05123_amd import Context, Mesh
+    octree of levels 5..lmax refined within 3 Cn of the interface; with
+    remesh_every = K > 0 the mesh is rebuilt around |phi| <= 0.95 after every
+    K steps and the state carried over by the intergrid transfer."""
+    from paper_2107_05123_amd import Context, Mesh, Transfer
     cn = 0.005
     t0 = time.time()
     mesh = Mesh(dim=3, min_level=5, max_level=lmax, rule="sphere_band", centres=[(0.5, 0.3, 0.5)], radii=[0.15],
@@ -378,8 +381,8 @@ def bubble_steps(torch, lmax, nsteps, ch_pc="block", restart=16, vp_pc="jacobi",
     t_mesh = time.time() - t0
     print(f"# mesh built in {t_mesh:.1f} s: {mesh.n_elems} leaves, {mesh.n_nodes} nodes", file=sys.stderr, flush=True)
     x_unit = ci.unit_coords(mesh.node_coords(), lmax)
-    ctx = Context(mesh, Re=35.0, We=10.0, Cn=cn, Fr=1.0, rho_plus=1.0, rho_minus=1e-3, eta_plus=1.0,
-                  eta_minus=1e-2, dt=5e-4)
+    prm = dict(Re=35.0, We=10.0, Cn=cn, Fr=1.0, rho_plus=1.0, rho_minus=1e-3, eta_plus=1.0, eta_minus=1e-2, dt=5e-4)
+    ctx = Context(mesh, **prm)
     print(f"# context ready ({time.time() - t0:.1f} s)", file=sys.stderr, flush=True)
     dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
     n = mesh.n_nodes
@@ -391,7 +394,7 @@ def bubble_steps(torch, lmax, nsteps, ch_pc="block", restart=16, vp_pc="jacobi",
     out = {"workload": f"3D rising bubble, adaptive levels 5-{lmax} (band 3 Cn, Cn 0.005), density ratio 1000, "
                        "viscosity ratio 100, Re 35, We 10, dt 5e-4",
            "ch_preconditioner": ch_pc, "vp_preconditioner": vp_pc, "gmres_restart": restart,
-           "n_elems": mesh.n_elems, "n_nodes": n, "host_mesh_build_s": t_mesh, "steps": []}
+           "n_elems": mesh.n_elems, "n_nodes": n, "host_mesh_build_s": t_mesh, "steps": [], "remesh": []}
     for mode in modes:
         for k in range(nsteps):
             torch.cuda.synchronize()
@@ -400,8 +403,35 @@ def bubble_steps(torch, lmax, nsteps, ch_pc="block", restart=16, vp_pc="jacobi",
             torch.cuda.synchronize()
             s["wall_s"] = time.perf_counter() - t1
             s["pressure_mode"] = mode
+            s["n_elems"] = mesh.n_elems
             out["steps"].append(s)
             print(f"# step {k} ({mode}): {s}", file=sys.stderr, flush=True)
+            if remesh_every > 0 and (k + 1) % remesh_every == 0:
+                # remesh around |phi| <= 0.95 and carry the state over
+                r = {"after_step": k, "old_elems": mesh.n_elems}
+                t2 = time.perf_counter()
+                phi_h = st["phi"].cpu().numpy()
+                new = mesh.remesh(phi_h, 5, 0.95)
+                r["host_remesh_s"] = time.perf_counter() - t2
+                t2 = time.perf_counter()
+                tr = Transfer(mesh, new)
+                r["host_transfer_build_s"] = time.perf_counter() - t2
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                st = {"u": tr.apply(st["u"], n_fields=3), "u_prev": tr.apply(st["u_prev"], n_fields=3),
+                      "p": tr.apply(st["p"]), "phi": tr.apply(st["phi"]), "mu": tr.apply(st["mu"])}
+                torch.cuda.synchronize()
+                r["device_transfer_ms"] = (time.perf_counter() - t2) * 1e3
+                del ctx
+                t2 = time.perf_counter()
+                ctx = Context(new, **prm)
+                torch.cuda.synchronize()
+                r["context_s"] = time.perf_counter() - t2
+                mesh = new
+                r["new_elems"] = mesh.n_elems
+                r["new_nodes"] = mesh.n_nodes
+                out["remesh"].append(r)
+                print(f"# remesh: {r}", file=sys.stderr, flush=True)
     return out
 
 
@@ -427,6 +457,8 @@ def main():
     ap.add_argument("--vp-pc", default="gmg", choices=("jacobi", "gmg"),
                     help="bubble_steps: preconditioner of the velocity-prediction GMRES (Jacobi, or multigrid "
                          "V-cycles of the scalar mass + viscous operator per component)")
+    ap.add_argument("--remesh-every", type=int, default=0,
+                    help="bubble_steps: rebuild the mesh around |phi| <= 0.95 after every K steps (0: never)")
     ap.add_argument("--pp-modes", default="fp64,mixed",
                     help="bubble_steps: pressure solve modes to step with, in order (comma-separated)")
     ap.add_argument("--summarize-stats", nargs=5, metavar=("DB", "OUT_MD", "TITLE", "COMMAND", "NOTE"),
@@ -453,7 +485,7 @@ def main():
         return
     if args.workload == "bubble_steps":
         print(json.dumps(bubble_steps(torch, args.max_level, args.steps, args.ch_pc, args.restart, args.vp_pc,
-                                      tuple(args.pp_modes.split(",")))))
+                                      tuple(args.pp_modes.split(",")), args.remesh_every)))
         return
     if args.profile_run == "chns":
         profile_chns(torch)
