@@ -24,6 +24,7 @@
 #include <cmath>
 #include <cstring>
 #include <stdexcept>
+#include <thread>
 
 namespace chns {
 namespace {
@@ -880,32 +881,93 @@ void expand_entry(const HostMesh& m, int32_t entry, double w, std::vector<std::p
   const int np = m.hang_npar[h];
   for (int q = 0; q < np; ++q) row.push_back({m.hang_parents[4 * h + q], w / np});
 }
-// sort by column, sum duplicates, drop zeros
+// sort by (column, value), sum duplicates in that order, drop zeros
 void merge_row(std::vector<std::pair<int32_t, double>>& row) {
   std::sort(row.begin(), row.end());
-  std::vector<std::pair<int32_t, double>> out;
-  for (auto& e : row) {
-    if (!out.empty() && out.back().first == e.first) out.back().second += e.second;
-    else out.push_back(e);
+  size_t w = 0;
+  for (size_t r = 0; r < row.size(); ++r) {
+    if (w > 0 && row[w - 1].first == row[r].first) row[w - 1].second += row[r].second;
+    else row[w++] = row[r];
   }
-  row.clear();
-  for (auto& e : out)
-    if (e.second != 0.0) row.push_back(e);
+  row.resize(w);
+  w = 0;
+  for (size_t r = 0; r < row.size(); ++r)
+    if (row[r].second != 0.0) row[w++] = row[r];
+  row.resize(w);
 }
 
-void to_csr(const std::vector<std::vector<std::pair<int32_t, double>>>& rows, std::vector<int32_t>& ptr,
-            std::vector<int32_t>& col, std::vector<double>& val) {
+// CSR matrix built row by row on several host threads: row(i, entries)
+// appends the entries of row i (any order, duplicates allowed) and returns
+// false with msg set on an error; rows are merged and concatenated in order.
+template <typename RowFn>
+int build_rows(int64_t nrows, RowFn row, std::vector<int32_t>& ptr, std::vector<int32_t>& col,
+               std::vector<double>& val, std::string& msg) {
+  const int64_t nt = std::max<int64_t>(1, std::min<int64_t>(16, std::min<int64_t>(
+                                                                    (int64_t)std::thread::hardware_concurrency(),
+                                                                    nrows / 4096 + 1)));
+  struct Part {
+    std::vector<int32_t> len, col;
+    std::vector<double> val;
+    std::string err;
+  };
+  std::vector<Part> parts((size_t)nt);
+  auto work = [&](int64_t t) {
+    Part& p = parts[(size_t)t];
+    const int64_t a = nrows * t / nt, b = nrows * (t + 1) / nt;
+    std::vector<std::pair<int32_t, double>> e;
+    p.len.reserve((size_t)(b - a));
+    for (int64_t i = a; i < b; ++i) {
+      e.clear();
+      if (!row(i, e, p.err)) return;
+      merge_row(e);
+      p.len.push_back((int32_t)e.size());
+      for (auto& x : e) {
+        p.col.push_back(x.first);
+        p.val.push_back(x.second);
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  for (int64_t t = 1; t < nt; ++t) th.emplace_back(work, t);
+  work(0);
+  for (auto& x : th) x.join();
+  for (auto& p : parts)
+    if (!p.err.empty()) {
+      msg = p.err;
+      return CHNS_EINVAL;
+    }
   ptr.assign(1, 0);
+  ptr.reserve((size_t)nrows + 1);
   col.clear();
   val.clear();
-  for (auto& r : rows) {
-    for (auto& e : r) {
-      col.push_back(e.first);
-      val.push_back(e.second);
-    }
-    ptr.push_back((int32_t)col.size());
+  for (auto& p : parts) {
+    for (int32_t l : p.len) ptr.push_back(ptr.back() + l);
+    col.insert(col.end(), p.col.begin(), p.col.end());
+    val.insert(val.end(), p.val.begin(), p.val.end());
   }
+  return CHNS_OK;
 }
+
+// transpose of a CSR matrix (rows x cols): entries of each transposed row in
+// increasing original row order
+void csr_transpose(int64_t cols, const std::vector<int32_t>& ptr, const std::vector<int32_t>& col,
+                   const std::vector<double>& val, std::vector<int32_t>& tptr, std::vector<int32_t>& tcol,
+                   std::vector<double>& tval) {
+  const int64_t rows = (int64_t)ptr.size() - 1;
+  tptr.assign((size_t)cols + 1, 0);
+  for (int32_t c : col) ++tptr[(size_t)c + 1];
+  for (int64_t c = 0; c < cols; ++c) tptr[(size_t)c + 1] += tptr[(size_t)c];
+  std::vector<int32_t> cur(tptr.begin(), tptr.end() - 1);
+  tcol.resize(col.size());
+  tval.resize(val.size());
+  for (int64_t i = 0; i < rows; ++i)
+    for (int32_t k = ptr[(size_t)i]; k < ptr[(size_t)i + 1]; ++k) {
+      const int32_t pos = cur[(size_t)col[(size_t)k]]++;
+      tcol[(size_t)pos] = (int32_t)i;
+      tval[(size_t)pos] = val[(size_t)k];
+    }
+}
+
 }  // namespace
 
 int build_transfer(const HostMesh& fine, const HostMesh& coarse, Transfer& t, std::string& msg) {
@@ -921,68 +983,65 @@ int build_transfer(const HostMesh& fine, const HostMesh& coarse, Transfer& t, st
   for (int64_t e = 0; e < coarse.n_elems(); ++e)
     leaves.insert(leaf_key(dim, coarse.leaf_level[e], &coarse.leaf_anchor[3 * e]));
   NodeLookup cl(coarse), fl(fine);
-  auto expand = expand_entry;
-  auto merge = merge_row;
   // prolongation rows: fine independent node <- coarse Q1 field at its position
-  std::vector<std::vector<std::pair<int32_t, double>>> P(fine.n_indep);
-  for (int64_t i = 0; i < fine.n_indep; ++i) {
-    const int32_t* x = &fine.indep_coords[3 * i];
-    int found = -1;
-    int32_t af[3] = {0, 0, 0}, ac[3] = {0, 0, 0};
-    int32_t sf = 0;
-    for (int mlev = Lc; mlev >= 0 && found < 0; --mlev) {
-      sf = 1 << (fine.max_level - mlev);  // coarse octant edge in fine units
-      for (int d = 0; d < dim; ++d) {
-        const int32_t q2 = 2 * x[d] + (x[d] < side_f ? 1 : -1);  // doubled, nudged inside
-        af[d] = (q2 / (2 * sf)) * sf;
-        ac[d] = af[d] / 2;
-      }
-      if (leaves.contains(leaf_key(dim, mlev, ac))) found = mlev;
-    }
-    if (found < 0) {
-      msg = "fine node outside the coarse mesh";
-      return CHNS_EINVAL;
-    }
-    for (int a = 0; a < nc; ++a) {
-      double w = 1.0;
-      int32_t cc[3] = {0, 0, 0};
-      for (int d = 0; d < dim; ++d) {
-        const int bit = (a >> d) & 1;
-        const double xi = (double)(x[d] - af[d]) / sf;
-        w *= bit ? xi : 1.0 - xi;
-        cc[d] = ac[d] + bit * (sf / 2);
-      }
-      if (w == 0.0) continue;
-      int32_t ent;
-      if (!cl.find(cc, &ent)) {
-        msg = "coarse leaf corner missing";
-        return CHNS_EINVAL;
-      }
-      expand(coarse, ent, w, P[i]);
-    }
-    merge(P[i]);
-  }
-  to_csr(P, t.P_ptr, t.P_col, t.P_val);
+  int rc = build_rows(
+      fine.n_indep,
+      [&](int64_t i, std::vector<std::pair<int32_t, double>>& row, std::string& err) {
+        const int32_t* x = &fine.indep_coords[3 * i];
+        int found = -1;
+        int32_t af[3] = {0, 0, 0}, ac[3] = {0, 0, 0};
+        int32_t sf = 0;
+        for (int mlev = Lc; mlev >= 0 && found < 0; --mlev) {
+          sf = 1 << (fine.max_level - mlev);  // coarse octant edge in fine units
+          for (int d = 0; d < dim; ++d) {
+            const int32_t q2 = 2 * x[d] + (x[d] < side_f ? 1 : -1);  // doubled, nudged inside
+            af[d] = (q2 / (2 * sf)) * sf;
+            ac[d] = af[d] / 2;
+          }
+          if (leaves.contains(leaf_key(dim, mlev, ac))) found = mlev;
+        }
+        if (found < 0) {
+          err = "fine node outside the coarse mesh";
+          return false;
+        }
+        for (int a = 0; a < nc; ++a) {
+          double w = 1.0;
+          int32_t cc[3] = {0, 0, 0};
+          for (int d = 0; d < dim; ++d) {
+            const int bit = (a >> d) & 1;
+            const double xi = (double)(x[d] - af[d]) / sf;
+            w *= bit ? xi : 1.0 - xi;
+            cc[d] = ac[d] + bit * (sf / 2);
+          }
+          if (w == 0.0) continue;
+          int32_t ent;
+          if (!cl.find(cc, &ent)) {
+            err = "coarse leaf corner missing";
+            return false;
+          }
+          expand_entry(coarse, ent, w, row);
+        }
+        return true;
+      },
+      t.P_ptr, t.P_col, t.P_val, msg);
+  if (rc) return rc;
   // restriction = transpose (coarse rows, fine columns in increasing order)
-  std::vector<std::vector<std::pair<int32_t, double>>> R(coarse.n_indep);
-  for (int64_t i = 0; i < fine.n_indep; ++i)
-    for (auto& e : P[i]) R[e.first].push_back({(int32_t)i, e.second});
-  to_csr(R, t.R_ptr, t.R_col, t.R_val);
+  csr_transpose(coarse.n_indep, t.P_ptr, t.P_col, t.P_val, t.R_ptr, t.R_col, t.R_val);
   // injection of nodal fields: coarse node value = fine field at that point
-  std::vector<std::vector<std::pair<int32_t, double>>> I(coarse.n_indep);
-  for (int64_t j = 0; j < coarse.n_indep; ++j) {
-    int32_t xf[3] = {0, 0, 0};
-    for (int d = 0; d < dim; ++d) xf[d] = 2 * coarse.indep_coords[3 * j + d];
-    int32_t ent;
-    if (!fl.find(xf, &ent)) {
-      msg = "coarse node is not a fine node";
-      return CHNS_EINVAL;
-    }
-    expand(fine, ent, 1.0, I[j]);
-    merge(I[j]);
-  }
-  to_csr(I, t.I_ptr, t.I_col, t.I_val);
-  return CHNS_OK;
+  return build_rows(
+      coarse.n_indep,
+      [&](int64_t j, std::vector<std::pair<int32_t, double>>& row, std::string& err) {
+        int32_t xf[3] = {0, 0, 0};
+        for (int d = 0; d < dim; ++d) xf[d] = 2 * coarse.indep_coords[3 * j + d];
+        int32_t ent;
+        if (!fl.find(xf, &ent)) {
+          err = "coarse node is not a fine node";
+          return false;
+        }
+        expand_entry(fine, ent, 1.0, row);
+        return true;
+      },
+      t.I_ptr, t.I_col, t.I_val, msg);
 }
 
 int build_host_mesh(const chns_mesh_spec& spec, HostMesh& m, std::string& msg) {
@@ -1104,47 +1163,47 @@ int build_interp(const HostMesh& src, const HostMesh& dst, std::vector<int32_t>&
     for (int64_t e = 0; e < src.n_elems(); ++e)
       leaves.insert(leaf_key(dim, src.leaf_level[e], &src.leaf_anchor[3 * e]));
     NodeLookup sl(src);
-    std::vector<std::vector<std::pair<int32_t, double>>> rows((size_t)dst.n_indep);
-    for (int64_t i = 0; i < dst.n_indep; ++i) {
-      const int32_t* x = &dst.indep_coords[3 * i];
-      // the source leaf whose box holds x (nudged inside at the far faces)
-      int32_t af[3] = {0, 0, 0};
-      int32_t sf = 0;
-      int found = -1;
-      for (int lev = L; lev >= 0 && found < 0; --lev) {
-        sf = 1 << (L - lev);
-        for (int d = 0; d < dim; ++d) {
-          const int32_t q2 = 2 * x[d] + (x[d] < side ? 1 : -1);
-          af[d] = (q2 / (2 * sf)) * sf;
-        }
-        if (leaves.contains(leaf_key(dim, lev, af))) found = lev;
-      }
-      if (found < 0) {
-        msg = "node outside the source mesh";
-        return CHNS_EINVAL;
-      }
-      // the source Q1 field at x: trilinear weights of the leaf's corners
-      for (int a = 0; a < nc; ++a) {
-        double w = 1.0;
-        int32_t cc[3] = {0, 0, 0};
-        for (int d = 0; d < dim; ++d) {
-          const int bit = (a >> d) & 1;
-          const double xi = (double)(x[d] - af[d]) / sf;
-          w *= bit ? xi : 1.0 - xi;
-          cc[d] = af[d] + bit * sf;
-        }
-        if (w == 0.0) continue;
-        int32_t ent;
-        if (!sl.find(cc, &ent)) {
-          msg = "source leaf corner missing";
-          return CHNS_EINVAL;
-        }
-        expand_entry(src, ent, w, rows[(size_t)i]);
-      }
-      merge_row(rows[(size_t)i]);
-    }
-    to_csr(rows, ptr, col, val);
-    return CHNS_OK;
+    return build_rows(
+        dst.n_indep,
+        [&](int64_t i, std::vector<std::pair<int32_t, double>>& row, std::string& err) {
+          const int32_t* x = &dst.indep_coords[3 * i];
+          // the source leaf whose box holds x (nudged inside at the far faces)
+          int32_t af[3] = {0, 0, 0};
+          int32_t sf = 0;
+          int found = -1;
+          for (int lev = L; lev >= 0 && found < 0; --lev) {
+            sf = 1 << (L - lev);
+            for (int d = 0; d < dim; ++d) {
+              const int32_t q2 = 2 * x[d] + (x[d] < side ? 1 : -1);
+              af[d] = (q2 / (2 * sf)) * sf;
+            }
+            if (leaves.contains(leaf_key(dim, lev, af))) found = lev;
+          }
+          if (found < 0) {
+            err = "node outside the source mesh";
+            return false;
+          }
+          // the source Q1 field at x: trilinear weights of the leaf's corners
+          for (int a = 0; a < nc; ++a) {
+            double w = 1.0;
+            int32_t cc[3] = {0, 0, 0};
+            for (int d = 0; d < dim; ++d) {
+              const int bit = (a >> d) & 1;
+              const double xi = (double)(x[d] - af[d]) / sf;
+              w *= bit ? xi : 1.0 - xi;
+              cc[d] = af[d] + bit * sf;
+            }
+            if (w == 0.0) continue;
+            int32_t ent;
+            if (!sl.find(cc, &ent)) {
+              err = "source leaf corner missing";
+              return false;
+            }
+            expand_entry(src, ent, w, row);
+          }
+          return true;
+        },
+        ptr, col, val, msg);
   } catch (const std::bad_alloc&) {
     msg = "host allocation failed while building the transfer";
     return CHNS_ENOMEM;
