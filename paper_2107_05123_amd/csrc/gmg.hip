@@ -336,28 +336,36 @@ template <int DIM>
 __global__ __launch_bounds__(64) void k_gal_elem(const double* __restrict__ Ef, int sf, const double* __restrict__ Pt,
                                                  double* E) {
   constexpr int NC = 1 << DIM, NE = NC * NC;
-  __shared__ double K[NE], T[NE];
+  __shared__ double K[NE], T[NE], Ps[NC * NE];
   const int64_t e = blockIdx.x;
   const int sc = sf / 2;
   const int X = (int)(e % sc), Y = (int)((e / sc) % sc), Z = DIM == 3 ? (int)(e / ((int64_t)sc * sc)) : 0;
   const int t = threadIdx.x;
   const int r = t / NC, col = t % NC;
   double acc = 0.0;
+  // every child's entry t loaded at once (one memory latency, not NC)
+  double kv[NC];
+#pragma unroll
   for (int c = 0; c < NC; ++c) {
     const int64_t ce = (2 * X + (c & 1)) + (int64_t)sf * ((2 * Y + ((c >> 1) & 1)) +
                                                           (DIM == 3 ? (int64_t)sf * (2 * Z + ((c >> 2) & 1)) : 0));
-    if (t < NE) K[t] = Ef[ce * NE + t];
+    kv[c] = t < NE ? Ef[ce * NE + t] : 0.0;
+  }
+  for (int k = t; k < NC * NE; k += 64) Ps[k] = Pt[k];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    if (t < NE) K[t] = kv[c];
     __syncthreads();
     // T = K_c P_c (row b = r, coarse column col)
     if (t < NE) {
       double v = 0.0;
-      for (int b2 = 0; b2 < NC; ++b2) v += K[r * NC + b2] * Pt[(c * NC + b2) * NC + col];
+      for (int b2 = 0; b2 < NC; ++b2) v += K[r * NC + b2] * Ps[(c * NC + b2) * NC + col];
       T[t] = v;
     }
     __syncthreads();
     // K_C(A = r, B = col) += sum_b P_c(b, A) T(b, B)
     if (t < NE)
-      for (int b = 0; b < NC; ++b) acc += Pt[(c * NC + b) * NC + r] * T[b * NC + col];
+      for (int b = 0; b < NC; ++b) acc += Ps[(c * NC + b) * NC + r] * T[b * NC + col];
     __syncthreads();
   }
   if (t < NE) E[e * NE + t] = acc;
