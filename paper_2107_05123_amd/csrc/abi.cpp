@@ -321,14 +321,24 @@ int chns_transfer_apply(chns_transfer* t, int n_fields, const double* x, double*
       return CHNS_EINVAL;
     }
     const size_t nnz = t->val.size();
-    CHNS_HIP(hipMalloc(&t->d_ptr, sizeof(int32_t) * t->ptr.size()));
-    CHNS_HIP(hipMalloc(&t->d_col, sizeof(int32_t) * std::max<size_t>(nnz, 1)));
-    CHNS_HIP(hipMalloc(&t->d_val, sizeof(double) * std::max<size_t>(nnz, 1)));
-    CHNS_HIP(hipMemcpy(t->d_ptr, t->ptr.data(), sizeof(int32_t) * t->ptr.size(), hipMemcpyHostToDevice));
-    if (nnz) {
-      CHNS_HIP(hipMemcpy(t->d_col, t->col.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
-      CHNS_HIP(hipMemcpy(t->d_val, t->val.data(), sizeof(double) * nnz, hipMemcpyHostToDevice));
+    int32_t *dp = nullptr, *dc = nullptr;
+    double* dv = nullptr;
+    hipError_t e = hipMalloc(&dp, sizeof(int32_t) * t->ptr.size());
+    if (e == hipSuccess) e = hipMalloc(&dc, sizeof(int32_t) * std::max<size_t>(nnz, 1));
+    if (e == hipSuccess) e = hipMalloc(&dv, sizeof(double) * std::max<size_t>(nnz, 1));
+    if (e == hipSuccess) e = hipMemcpy(dp, t->ptr.data(), sizeof(int32_t) * t->ptr.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && nnz) e = hipMemcpy(dc, t->col.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice);
+    if (e == hipSuccess && nnz) e = hipMemcpy(dv, t->val.data(), sizeof(double) * nnz, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      // nothing kept: a later call can try again
+      if (dp) (void)hipFree(dp);
+      if (dc) (void)hipFree(dc);
+      if (dv) (void)hipFree(dv);
+      return hip_fail(e, "transfer upload");
     }
+    t->d_ptr = dp;
+    t->d_col = dc;
+    t->d_val = dv;
     t->device = dev;
   }
   return interp_apply(t->d_ptr, t->d_col, t->d_val, t->rows, t->cols, n_fields, x, y, (hipStream_t)stream);
