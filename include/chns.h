@@ -131,7 +131,11 @@ int chns_mesh_remesh(const chns_mesh* old, const double* phi, int min_level, dou
  * `from`); info / matrix copy it to host buffers (ptr rows + 1, col and val
  * nnz); apply: y (rows * n_fields, device) = the transfer of x (cols *
  * n_fields, device), field-blocked, on `stream`; x and y must not alias; the
- * first apply uploads the CSR to the current device.  Async.               */
+ * first apply uploads the CSR to the current device (synchronously), later
+ * applies on another device are EINVAL.  Async.  EINVAL for meshes of
+ * different dimension or max_level, null pointers or n_fields < 1.  *out
+ * is owned by the caller and freed, with its device copy, by
+ * chns_transfer_destroy.                                                   */
 typedef struct chns_transfer chns_transfer;
 int chns_transfer_create(const chns_mesh* from, const chns_mesh* to, chns_transfer** out);
 int chns_transfer_info(const chns_transfer* t, int64_t* rows, int64_t* cols, int64_t* nnz);
