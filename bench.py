@@ -475,8 +475,8 @@ def main():
         print(json.dumps(summarize_pmc(fc, wc, out, [c1, c2]), indent=1))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (it would shard by "
+              "contiguous Morton ranges of bricks, with halo exchange of shared nodes)", file=sys.stderr)
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
