@@ -111,6 +111,7 @@ struct Multigrid {
   // Hm (c, q, A, B) = P_c^T Mq_q P_c (variable-density mass)
   double* tab_Mq = nullptr;
   double* tab_Hm = nullptr;
+  double* diag_part = nullptr;  // 3^d fine-diagonal partials per first-coarse-level element
   bool setup_valid = false;
   hipGraphExec_t setup_exec = nullptr;  // captured device part of the set-up
   hipGraphExec_t mom_setup_exec = nullptr;  // the same for the scalar momentum operator

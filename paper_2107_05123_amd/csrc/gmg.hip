@@ -269,13 +269,22 @@ __global__ __launch_bounds__(64) void k_el_rediscr(const double* __restrict__ ph
 // the Galerkin product of the fine Gauss-point masses, sum cm_{c,q} Hm_{c,q}
 // scaled by the fine det J (Hm staged in LDS).
 constexpr int kGalPerWave = 64;
+//
+// The same pass also yields the fine level's diagonal: lane (c, u) forms
+// child c's diagonal entry at its corner u from the child's Gauss-point
+// coefficients (the G_q(u, u) and Mq_q(u, u) tables), the 3^d fine nodes of
+// the coarse element sum their contributions in a fixed order into DP
+// (3^d partials per coarse element), and k_diag_gather adds the partials of
+// the coarse elements around each fine node.
 template <int DIM, bool VARM>
 __global__ __launch_bounds__(64) void k_gal_phi(const double* __restrict__ phi, int sf, const double* __restrict__ Ht,
                                                 QCoef cf, double scale, double* E, int64_t ne,
                                                 const double* __restrict__ Mt, double mconst,
-                                                const double* __restrict__ Hm, double mscale) {
-  constexpr int NC = 1 << DIM, NE = NC * NC;
-  __shared__ double cq[NE], cm[VARM ? NE : 1], hm[VARM ? NE * NE : 1];
+                                                const double* __restrict__ Hm, double mscale,
+                                                const double* __restrict__ Gt, const double* __restrict__ Mq,
+                                                double fmscale, double* DP) {
+  constexpr int NC = 1 << DIM, NE = NC * NC, NB = DIM == 3 ? 27 : 9;
+  __shared__ double cq[NE], cm[NE], hm[VARM ? NE * NE : 1], dd[NE];
   const int sc = sf / 2;
   const int64_t f1 = sf + 1;
   const int t = threadIdx.x;
@@ -292,6 +301,14 @@ __global__ __launch_bounds__(64) void k_gal_phi(const double* __restrict__ phi, 
   // child's corner phase values of the next element are loaded while the
   // current one is reduced
   const int c = t / NC, q = t % NC;
+  // diagonal tables of corner u = t % NC (lane t = (child, corner) in the
+  // diagonal pass)
+  double gd[NC], md[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    gd[k] = t < NE ? Gt[k * NE + q * NC + q] : 0.0;
+    md[k] = t < NE ? Mq[k * NE + q * NC + q] : 0.0;
+  }
   auto load = [&](int64_t e, double* ph) {
     const int X = (int)(e % sc), Y = (int)((e / sc) % sc), Z = DIM == 3 ? (int)(e / ((int64_t)sc * sc)) : 0;
     const int cx = 2 * X + (c & 1), cy = 2 * Y + ((c >> 1) & 1), cz = DIM == 3 ? 2 * Z + ((c >> 2) & 1) : 0;
@@ -311,9 +328,35 @@ __global__ __launch_bounds__(64) void k_gal_phi(const double* __restrict__ phi, 
     if (t < NE) {
       const double v = phase_at(ph, q, DIM);
       cq[t] = cf.k(v);
-      if constexpr (VARM) cm[t] = cf.m(v);
+      cm[t] = cf.m(v);
     }
     __syncthreads();
+    if (t < NE) {
+      // child c = t / NC, corner u = t % NC: that child's diagonal entry there
+      double a = 0.0, b = 0.0;
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        a += cq[c * NC + k] * gd[k];
+        b += cm[c * NC + k] * md[k];
+      }
+      dd[t] = scale * a + fmscale * b;
+    }
+    __syncthreads();
+    if (t < NB) {
+      // local fine node (i, j, k) in {0, 1, 2}^d: children and corners with
+      // c_d + u_d = i_d (child c spans fine cells c_d .. c_d + 1), in a
+      // fixed order
+      const int li[3] = {t % 3, (t / 3) % 3, DIM == 3 ? t / 9 : 0};
+      double s = 0.0;
+      for (int cz = 0; cz < (DIM == 3 ? 2 : 1); ++cz)
+        for (int cy = 0; cy < 2; ++cy)
+          for (int cx = 0; cx < 2; ++cx) {
+            const int ux = li[0] - cx, uy = li[1] - cy, uz = li[2] - cz;
+            if (ux < 0 || ux > 1 || uy < 0 || uy > 1 || uz < 0 || uz > 1) continue;
+            s += dd[(cx + 2 * cy + 4 * cz) * NC + (ux + 2 * uy + 4 * uz)];
+          }
+      DP[e * NB + t] = s;
+    }
     if (t < NE) {
       double acc = 0.0;
 #pragma unroll
@@ -327,6 +370,54 @@ __global__ __launch_bounds__(64) void k_gal_phi(const double* __restrict__ phi, 
       }
     }
     __syncthreads();
+  }
+}
+
+// inverse diagonal of the fine level from the per-coarse-element partials
+// of k_gal_phi: the partials of the (up to 2^d) coarse elements around each
+// fine node, in a fixed order
+template <int DIM>
+__global__ void k_diag_gather(const double* __restrict__ DP, int sc, double* dinv64, float* dinv32) {
+  constexpr int NB = DIM == 3 ? 27 : 9;
+  const int sf = 2 * sc;
+  const int64_t f1 = sf + 1;
+  const int64_t n = DIM == 3 ? f1 * f1 * f1 : f1 * f1;
+  for (int64_t node = (int64_t)blockIdx.x * kT + threadIdx.x; node < n; node += (int64_t)gridDim.x * kT) {
+    const int P[3] = {(int)(node % f1), (int)((node / f1) % f1), DIM == 3 ? (int)(node / (f1 * f1)) : 0};
+    // per axis: (coarse index, local index) options
+    int ce[3][2], lo[3][2], no[3];
+    for (int d = 0; d < 3; ++d) {
+      no[d] = 0;
+      if (d >= DIM) {
+        ce[d][0] = 0;
+        lo[d][0] = 0;
+        no[d] = 1;
+        continue;
+      }
+      if (P[d] % 2) {
+        ce[d][0] = (P[d] - 1) / 2;
+        lo[d][0] = 1;
+        no[d] = 1;
+      } else {
+        if (P[d] / 2 - 1 >= 0) {
+          ce[d][no[d]] = P[d] / 2 - 1;
+          lo[d][no[d]++] = 2;
+        }
+        if (P[d] / 2 < sc) {
+          ce[d][no[d]] = P[d] / 2;
+          lo[d][no[d]++] = 0;
+        }
+      }
+    }
+    double acc = 0.0;
+    for (int kz = 0; kz < no[2]; ++kz)
+      for (int ky = 0; ky < no[1]; ++ky)
+        for (int kx = 0; kx < no[0]; ++kx) {
+          const int64_t e = ce[0][kx] + (int64_t)sc * (ce[1][ky] + (DIM == 3 ? (int64_t)sc * ce[2][kz] : 0));
+          acc += DP[e * NB + lo[0][kx] + 3 * lo[1][ky] + 9 * lo[2][kz]];
+        }
+    dinv64[node] = 1.0 / acc;
+    dinv32[node] = (float)(1.0 / acc);
   }
 }
 
@@ -407,55 +498,6 @@ __global__ void k_el_stencil(const double* __restrict__ E, int s, double* S64, f
     constexpr int C = NS / 2;
     if (dinv64) dinv64[node] = 1.0 / acc[C];
     if (dinv32) dinv32[node] = (float)(1.0 / acc[C]);
-  }
-}
-
-// inverse diagonal of a uniform fine level straight from its phase field
-template <int DIM>
-__global__ void k_diag_phi(const double* __restrict__ phi, int s, const double* __restrict__ Gt, QCoef cf,
-                           double scale, double* dinv64, float* dinv32, const double* __restrict__ Mq,
-                           double mscale) {
-  constexpr int NC = 1 << DIM, NE = NC * NC;
-  const int64_t s1 = s + 1;
-  const int64_t n = DIM == 3 ? s1 * s1 * s1 : s1 * s1;
-  constexpr int NB = DIM == 3 ? 27 : 9;
-  for (int64_t node = (int64_t)blockIdx.x * kT + threadIdx.x; node < n; node += (int64_t)gridDim.x * kT) {
-    const int I = (int)(node % s1), J = (int)((node / s1) % s1), K = DIM == 3 ? (int)(node / (s1 * s1)) : 0;
-    // the 3^d phase values around the node, loaded once (clamped indices:
-    // the values of elements outside the level are computed but not added)
-    double p[NB];
-#pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      const int i = min(max(I + c % 3 - 1, 0), s), j = min(max(J + (c / 3) % 3 - 1, 0), s);
-      const int k = DIM == 3 ? min(max(K + c / 9 - 1, 0), s) : 0;
-      p[c] = phi[((int64_t)k * s1 + j) * s1 + i];
-    }
-    double acc = 0.0, macc = 0.0;
-#pragma unroll
-    for (int u = 0; u < NC; ++u) {
-      const int ux = u & 1, uy = (u >> 1) & 1, uz = DIM == 3 ? (u >> 2) & 1 : 0;
-      const int ax = I - ux, ay = J - uy, az = K - uz;
-      const bool inside = ax >= 0 && ax < s && ay >= 0 && ay < s && (DIM == 2 || (az >= 0 && az < s));
-      double ph[NC];
-#pragma unroll
-      for (int b = 0; b < NC; ++b) {
-        // corner b of the element sits at offset (b - u) from the node
-        const int ox = (b & 1) - ux, oy = ((b >> 1) & 1) - uy, oz = DIM == 3 ? ((b >> 2) & 1) - uz : 0;
-        ph[b] = p[(ox + 1) + 3 * (oy + 1) + (DIM == 3 ? 9 * (oz + 1) : 0)];
-      }
-      double ea = 0.0, em = 0.0;
-#pragma unroll
-      for (int q = 0; q < NC; ++q) {
-        const double v = phase_at(ph, q, DIM);
-        ea += cf.k(v) * Gt[q * NE + u * NC + u];
-        em += cf.m(v) * Mq[q * NE + u * NC + u];
-      }
-      acc += inside ? ea : 0.0;
-      macc += inside ? em : 0.0;
-    }
-    const double d = scale * acc + mscale * macc;
-    dinv64[node] = 1.0 / d;
-    dinv32[node] = (float)(1.0 / d);
   }
 }
 
@@ -1016,9 +1058,15 @@ int mg_build(Ctx& c) {
     if ((rc = upload(c, &mg->tab_G, tg)) || (rc = upload(c, &mg->tab_P, tp)) || (rc = upload(c, &mg->tab_M, tm)) ||
         (rc = upload(c, &mg->tab_Mq, tmq)))
       goto fail;
-    if (c.dm.structured && mg->lv[1].E64 &&
-        ((rc = upload(c, &mg->tab_H, th)) || (rc = upload(c, &mg->tab_Hm, thm))))
-      goto fail;
+    if (c.dm.structured && mg->lv[1].E64) {
+      if ((rc = upload(c, &mg->tab_H, th)) || (rc = upload(c, &mg->tab_Hm, thm))) goto fail;
+      const int64_t ncoarse = (int64_t)1 << (c.dm.dim * (c.dm.max_level - 1));
+      mg->diag_part = (double*)c.dalloc(sizeof(double) * (size_t)ncoarse * (c.dm.dim == 3 ? 27 : 9));
+      if (!mg->diag_part) {
+        rc = CHNS_ENOMEM;
+        goto fail;
+      }
+    }
   }
   {
     MgLevel& B = mg->lv.back();
@@ -1087,24 +1135,27 @@ int mg_setup(Ctx& c, hipStream_t s) {
       const unsigned gl = (unsigned)((ncoarse + kGalPerWave - 1) / kGalPerWave);
       const int sf = c.dm.side;
       const double mc = cf.mb * mscale(sf / 2);
+      const double fm = mscale(sf);
       if (dim == 3) {
-        k_diag_phi<3><<<blocks(c.dm.n), kT, 0, st>>>(c.phi64, sf, mg.tab_G, cf, lscale(sf), mg.fine_dinv64,
-                                                      mg.fine_dinv32, mg.tab_Mq, mscale(sf));
         if (varm)
           k_gal_phi<3, true><<<gl, 64, 0, st>>>(c.phi64, sf, mg.tab_H, cf, lscale(sf), mg.lv[1].E64, ncoarse,
-                                                mg.tab_M, mc, mg.tab_Hm, mscale(sf));
+                                                mg.tab_M, mc, mg.tab_Hm, mscale(sf), mg.tab_G, mg.tab_Mq, fm,
+                                                mg.diag_part);
         else
           k_gal_phi<3, false><<<gl, 64, 0, st>>>(c.phi64, sf, mg.tab_H, cf, lscale(sf), mg.lv[1].E64, ncoarse,
-                                                 mg.tab_M, mc, mg.tab_Hm, mscale(sf));
+                                                 mg.tab_M, mc, mg.tab_Hm, mscale(sf), mg.tab_G, mg.tab_Mq, fm,
+                                                 mg.diag_part);
+        k_diag_gather<3><<<blocks(c.dm.n), kT, 0, st>>>(mg.diag_part, sf / 2, mg.fine_dinv64, mg.fine_dinv32);
       } else {
-        k_diag_phi<2><<<blocks(c.dm.n), kT, 0, st>>>(c.phi64, sf, mg.tab_G, cf, lscale(sf), mg.fine_dinv64,
-                                                      mg.fine_dinv32, mg.tab_Mq, mscale(sf));
         if (varm)
           k_gal_phi<2, true><<<gl, 64, 0, st>>>(c.phi64, sf, mg.tab_H, cf, lscale(sf), mg.lv[1].E64, ncoarse,
-                                                mg.tab_M, mc, mg.tab_Hm, mscale(sf));
+                                                mg.tab_M, mc, mg.tab_Hm, mscale(sf), mg.tab_G, mg.tab_Mq, fm,
+                                                mg.diag_part);
         else
           k_gal_phi<2, false><<<gl, 64, 0, st>>>(c.phi64, sf, mg.tab_H, cf, lscale(sf), mg.lv[1].E64, ncoarse,
-                                                 mg.tab_M, mc, mg.tab_Hm, mscale(sf));
+                                                 mg.tab_M, mc, mg.tab_Hm, mscale(sf), mg.tab_G, mg.tab_Mq, fm,
+                                                 mg.diag_part);
+        k_diag_gather<2><<<blocks(c.dm.n), kT, 0, st>>>(mg.diag_part, sf / 2, mg.fine_dinv64, mg.fine_dinv32);
       }
       CHNS_HIP(hipGetLastError());
     } else {
