@@ -492,7 +492,7 @@ __global__ void k_el_stencil(const double* __restrict__ E, int s, double* S64, f
     }
 #pragma unroll
     for (int o = 0; o < NS; ++o) {
-      S64[o * n + node] = acc[o];
+      if (S64) S64[o * n + node] = acc[o];
       if (S32) S32[o * n + node] = (float)acc[o];
     }
     constexpr int C = NS / 2;
@@ -1171,17 +1171,20 @@ int mg_setup(Ctx& c, hipStream_t s) {
       MgLevel& L = mg.lv[k];
       const int64_t nk = L.dm.n;
       const DevMesh& F = k == 1 ? c.dm : mg.lv[k - 1].dm;
-      if (F.structured && L.dm.structured)
-        k_inject_s<<<blocks(nk), kT, 0, st>>>(phi_f, L.phi64, L.dm.side, L.dm.dim);
-      else
-        k_spmv<double, double><<<blocks(nk), kT, 0, st>>>(L.I_ptr, L.I_col, L.I_val, phi_f, L.phi64, nk, 0);
-      k_phase32<<<blocks(nk), kT, 0, st>>>(L.phi64, L.phi32, nk);
-      CHNS_HIP(hipGetLastError());
-      phi_f = L.phi64;
+      // element matrices: Galerkin products from the level above when it has
+      // them (done there), else rediscretised from the injected field; a
+      // Galerkin level (and every level below it) needs no phase field
+      const bool from_above = L.E64 && (k == 1 ? mg.tab_H != nullptr : mg.lv[k - 1].E64 != nullptr);
+      if (!from_above) {
+        if (F.structured && L.dm.structured)
+          k_inject_s<<<blocks(nk), kT, 0, st>>>(phi_f, L.phi64, L.dm.side, L.dm.dim);
+        else
+          k_spmv<double, double><<<blocks(nk), kT, 0, st>>>(L.I_ptr, L.I_col, L.I_val, phi_f, L.phi64, nk, 0);
+        k_phase32<<<blocks(nk), kT, 0, st>>>(L.phi64, L.phi32, nk);
+        CHNS_HIP(hipGetLastError());
+        phi_f = L.phi64;
+      }
       if (L.E64) {
-        // element matrices: Galerkin products from the level above when it
-        // has them (done there), else rediscretised from the injected field
-        const bool from_above = k == 1 ? mg.tab_H != nullptr : mg.lv[k - 1].E64 != nullptr;
         const unsigned ne = (unsigned)((int64_t)1 << (dim * L.host.max_level));
         if (!from_above) {
           if (dim == 3)
@@ -1194,8 +1197,11 @@ int mg_setup(Ctx& c, hipStream_t s) {
         const bool last = k + 1 == mg.lv.size();
         double* d64 = last ? nullptr : L.dinv64;
         float* d32 = last ? nullptr : L.dinv32;
-        if (dim == 3) k_el_stencil<3><<<blocks(nk), kT, 0, st>>>(L.E64, L.dm.side, L.S64, L.S32, d64, d32);
-        else k_el_stencil<2><<<blocks(nk), kT, 0, st>>>(L.E64, L.dm.side, L.S64, L.S32, d64, d32);
+        // the cycle reads the stencils in FP32; the FP64 copy only feeds the
+        // coarsest level's dense matrix
+        double* s64 = last ? L.S64 : nullptr;
+        if (dim == 3) k_el_stencil<3><<<blocks(nk), kT, 0, st>>>(L.E64, L.dm.side, s64, L.S32, d64, d32);
+        else k_el_stencil<2><<<blocks(nk), kT, 0, st>>>(L.E64, L.dm.side, s64, L.S32, d64, d32);
         if (!last && mg.lv[k + 1].E64) {
           const unsigned nc = ne >> dim;
           if (dim == 3) k_gal_elem<3><<<nc, 64, 0, st>>>(L.E64, L.dm.side, mg.tab_P, mg.lv[k + 1].E64);
