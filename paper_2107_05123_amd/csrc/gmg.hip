@@ -358,9 +358,12 @@ __global__ __launch_bounds__(64) void k_gal_phi(const double* __restrict__ phi, 
       DP[e * NB + t] = s;
     }
     if (t < NE) {
-      double acc = 0.0;
+      // four independent partial sums: a 64-long dependent chain would
+      // dominate the per-element latency
+      double a4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int k = 0; k < NE; ++k) acc += cq[k] * h[k];
+      for (int k = 0; k < NE; ++k) a4[k & 3] += cq[k] * h[k];
+      const double acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
       if constexpr (VARM) {
         double macc = 0.0;
         for (int k = 0; k < NE; ++k) macc += cm[k] * hm[k * NE + t];
