@@ -465,7 +465,7 @@ int dot_sync(Ctx& c, const double* a, const double* b, int64_t n, hipStream_t s,
 // rho = 1 and the mass shift 1/sqrt(b).  C dphi is the mu block of J [dphi, 0].
 // A fixed linear map (fixed cycles), so plain right-preconditioned GMRES
 // applies.  in / out: 2n, in = [v_phi, v_mu].
-constexpr int kMassCheb = 8;  // Chebyshev degree of the mass solve
+constexpr int kMassCheb = 12;  // Chebyshev degree of the mass solve
 int ch_schur_apply(Ctx& c, const double* in, double* out, hipStream_t s) {
   Stepper& S = *c.step;
   const int64_t n = c.dm.n;
