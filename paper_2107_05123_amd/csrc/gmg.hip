@@ -430,39 +430,38 @@ template <int DIM>
 __global__ __launch_bounds__(64) void k_gal_elem(const double* __restrict__ Ef, int sf, const double* __restrict__ Pt,
                                                  double* E) {
   constexpr int NC = 1 << DIM, NE = NC * NC;
-  __shared__ double K[NE], T[NE], Ps[NC * NE];
+  // all children at once: K_c and T_c = K_c P_c for every child in LDS, two
+  // barriers per coarse element (the same sums in the same order as child
+  // by child)
+  __shared__ double K[NC * NE], T[NC * NE], Ps[NC * NE];
   const int64_t e = blockIdx.x;
   const int sc = sf / 2;
   const int X = (int)(e % sc), Y = (int)((e / sc) % sc), Z = DIM == 3 ? (int)(e / ((int64_t)sc * sc)) : 0;
   const int t = threadIdx.x;
   const int r = t / NC, col = t % NC;
-  double acc = 0.0;
-  // every child's entry t loaded at once (one memory latency, not NC)
-  double kv[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const int64_t ce = (2 * X + (c & 1)) + (int64_t)sf * ((2 * Y + ((c >> 1) & 1)) +
                                                           (DIM == 3 ? (int64_t)sf * (2 * Z + ((c >> 2) & 1)) : 0));
-    kv[c] = t < NE ? Ef[ce * NE + t] : 0.0;
+    if (t < NE) K[c * NE + t] = Ef[ce * NE + t];
   }
   for (int k = t; k < NC * NE; k += 64) Ps[k] = Pt[k];
-#pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    if (t < NE) K[t] = kv[c];
-    __syncthreads();
-    // T = K_c P_c (row b = r, coarse column col)
-    if (t < NE) {
+  __syncthreads();
+  // T_c(b = r, B = col) = sum_b2 K_c(r, b2) P_c(b2, col)
+  if (t < NE)
+    for (int c = 0; c < NC; ++c) {
       double v = 0.0;
-      for (int b2 = 0; b2 < NC; ++b2) v += K[r * NC + b2] * Ps[(c * NC + b2) * NC + col];
-      T[t] = v;
+      for (int b2 = 0; b2 < NC; ++b2) v += K[c * NE + r * NC + b2] * Ps[(c * NC + b2) * NC + col];
+      T[c * NE + t] = v;
     }
-    __syncthreads();
-    // K_C(A = r, B = col) += sum_b P_c(b, A) T(b, B)
-    if (t < NE)
-      for (int b = 0; b < NC; ++b) acc += Ps[(c * NC + b) * NC + r] * T[b * NC + col];
-    __syncthreads();
+  __syncthreads();
+  // K_C(A = r, B = col) = sum_c sum_b P_c(b, A) T_c(b, B)
+  if (t < NE) {
+    double acc = 0.0;
+    for (int c = 0; c < NC; ++c)
+      for (int b = 0; b < NC; ++b) acc += Ps[(c * NC + b) * NC + r] * T[c * NE + b * NC + col];
+    E[e * NE + t] = acc;
   }
-  if (t < NE) E[e * NE + t] = acc;
 }
 
 // 3^d-point stencil (and inverse diagonal) of a uniform level from its
