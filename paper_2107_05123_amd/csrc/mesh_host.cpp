@@ -912,23 +912,39 @@ int build_rows(int64_t nrows, RowFn row, std::vector<int32_t>& ptr, std::vector<
   };
   std::vector<Part> parts((size_t)nt);
   auto work = [&](int64_t t) {
+    // no exception may leave a worker thread
     Part& p = parts[(size_t)t];
-    const int64_t a = nrows * t / nt, b = nrows * (t + 1) / nt;
-    std::vector<std::pair<int32_t, double>> e;
-    p.len.reserve((size_t)(b - a));
-    for (int64_t i = a; i < b; ++i) {
-      e.clear();
-      if (!row(i, e, p.err)) return;
-      merge_row(e);
-      p.len.push_back((int32_t)e.size());
-      for (auto& x : e) {
-        p.col.push_back(x.first);
-        p.val.push_back(x.second);
+    try {
+      const int64_t a = nrows * t / nt, b = nrows * (t + 1) / nt;
+      std::vector<std::pair<int32_t, double>> e;
+      p.len.reserve((size_t)(b - a));
+      for (int64_t i = a; i < b; ++i) {
+        e.clear();
+        if (!row(i, e, p.err)) return;
+        merge_row(e);
+        p.len.push_back((int32_t)e.size());
+        for (auto& x : e) {
+          p.col.push_back(x.first);
+          p.val.push_back(x.second);
+        }
       }
+    } catch (const std::bad_alloc&) {
+      p.err = "host allocation failed while building a transfer";
+    } catch (...) {
+      p.err = "internal error while building a transfer";
     }
   };
   std::vector<std::thread> th;
-  for (int64_t t = 1; t < nt; ++t) th.emplace_back(work, t);
+  int64_t started = 1;
+  try {
+    for (int64_t t = 1; t < nt; ++t) {
+      th.emplace_back(work, t);
+      ++started;
+    }
+  } catch (...) {
+    // fewer threads than asked for: the remaining parts run here
+  }
+  for (int64_t t = started; t < nt; ++t) work(t);
   work(0);
   for (auto& x : th) x.join();
   for (auto& p : parts)
