@@ -448,7 +448,7 @@ def main():
                     help="uniform_l7: the benchmark line; adaptive: levels 5..--max-level band mesh solves; "
                          "bubble_steps: projection steps of the 3D rising bubble")
     ap.add_argument("--max-level", type=int, default=10)
-    ap.add_argument("--restart", type=int, default=16,
+    ap.add_argument("--restart", type=int, default=20,
                     help="bubble_steps: GMRES restart length (short cycles keep the Gram-Schmidt cost of the "
                          "large CH and momentum bases down)")
     ap.add_argument("--ch-pc", default="schur", choices=("block", "schur"),
