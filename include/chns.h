@@ -236,7 +236,13 @@ typedef struct chns_solve_stats {
  * A is singular (constants); b is projected to 1^T b = 0 first and x is
  * returned with 1^T x = 0.  b, x: device FP64, n_nodes; x holds x0 on entry
  * (use zeros for the standard start).  Synchronises `stream`.  ENOCONV if
- * rtol was not reached; x and stats then describe the last iterate.       */
+ * rtol was not reached; x and stats then describe the last iterate.  A CG
+ * breakdown (p.Ap <= 0 or r.z <= 0, e.g. a preconditioner output of zero)
+ * ends the iteration at the last iterate: with the learned preconditioner
+ * the solve then continues with Jacobi (stats->fallback = 1), otherwise it
+ * is ENOCONV.  EINVAL, with stats filled (0 iterations, rel_residual NaN)
+ * and x unchanged, when the phase field given to chns_set_phase_field or b
+ * holds a NaN or an infinity.                                             */
 int chns_solve_pressure(chns_ctx* ctx, const double* b, double* x, const chns_solve_opts* opts,
                         chns_solve_stats* stats, void* stream);
 
@@ -339,8 +345,12 @@ typedef struct chns_step_stats {
  * pressure Poisson (CG) and velocity
  * update (CG on the rho-weighted mass matrix), then
  * (u_prev, u, p, phi, mu) <- (u^k, u^{k+1}, p^{k+1}, phi^{k+1}, mu^{k+1}).
- * Synchronises `stream`.  ENOCONV if a solve or Newton stalls; the state is
- * then left at step k.                                                     */
+ * Synchronises `stream`.  On return the context's phase field is phi~ of
+ * the last block (later pressure applies and solves use it).  ENOCONV if a
+ * solve or Newton stalls, or if a residual is not finite (NaN or infinity in
+ * the state); the state is then left at step k, and the context's phase
+ * field is marked unset (pressure applies and solves return ESTATE until
+ * chns_set_phase_field).                                                   */
 int chns_advance_step(chns_ctx* ctx, chns_state* state, const chns_step_opts* opts, chns_step_stats* stats,
                       void* stream);
 
@@ -361,8 +371,10 @@ int chns_advance_step(chns_ctx* ctx, chns_state* state, const chns_step_opts* op
  * The paper preconditions with algebraic multigrid; this network is an
  * addition of this library.  Weights belong to the context.               */
 
-/* Deterministic He initialisation from `seed`; out_scale is K, smooth_omega
- * the damping (0 <= omega < 2).  Async.                                    */
+/* Deterministic He initialisation from `seed`; out_scale is K >= 0 (K = 0
+ * makes the network's output zero, which flexible CG detects as a breakdown:
+ * the solve then falls back to Jacobi), smooth_omega the damping
+ * (0 <= omega < 2).  EINVAL otherwise.  Async.                             */
 int chns_pc_init(chns_ctx* ctx, uint64_t seed, float out_scale, float smooth_omega, void* stream);
 /* Weight blob: "CHNSUNET", u32 version (1 or 2), u32 layers (14), f32 K,
  * [version 2: f32 omega], then per layer u32 ci, u32 co, f32 W[27][ci][co]
@@ -399,7 +411,7 @@ int chns_pc_forward(chns_ctx* ctx, const double* phi, const double* r, const int
  *   CHNS_PC_OBJ_CROP_MSE: on the crop (origin, flip, crop) the output is
  *     compared with e / (rms(r) K) by the mean squared error over the voxels
  *     inside the grid.
- * Synchronises `stream`.                                                   */
+ * EINVAL when the output scale K is 0.  Synchronises `stream`.             */
 enum { CHNS_PC_OBJ_CROP_MSE = 0, CHNS_PC_OBJ_ANORM = 1 };
 typedef struct chns_pc_batch {
   int n;                      /* samples                                      */

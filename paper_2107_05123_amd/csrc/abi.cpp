@@ -559,8 +559,8 @@ int chns_advance_step(chns_ctx* ctx, chns_state* state, const chns_step_opts* op
 
 int chns_pc_init(chns_ctx* ctx, uint64_t seed, float out_scale, float smooth_omega, void* stream) {
   CHNS_GUARD_BEGIN
-  if (!ctx || !(out_scale > 0.0f) || !(smooth_omega >= 0.0f && smooth_omega < 2.0f)) {
-    set_error("null context, non-positive output scale or damping outside [0, 2)");
+  if (!ctx || !(out_scale >= 0.0f) || !(smooth_omega >= 0.0f && smooth_omega < 2.0f)) {
+    set_error("null context, negative output scale or damping outside [0, 2)");
     return CHNS_EINVAL;
   }
   return unet_init(ctx->c, seed, out_scale, smooth_omega, (hipStream_t)stream);

@@ -57,7 +57,8 @@ struct DevMesh {
 struct DevScalars {
   double pq, rz, rz_old, rr, bb, alpha, beta, sum;
   double tol2;        // (rtol |b|)^2
-  int it, done, max_it, pad;
+  int it, done, max_it;
+  int phi_bad;  // set by chns_set_phase_field when phi~ holds a NaN or an infinity
 };
 
 // One coarse level of the geometric multigrid hierarchy (level 0 is the

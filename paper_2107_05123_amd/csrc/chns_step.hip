@@ -623,6 +623,10 @@ int gmres(Ctx& c, int op, const double* b, double* x, int pc, const double* pcd,
     CHNS_HIP(hipMemcpyAsync(S.gd_host, S.gd, 64, hipMemcpyDeviceToHost, s));
     CHNS_HIP(hipStreamSynchronize(s));
     *rel = S.gd_host->beta / bn;
+    if (!std::isfinite(*rel)) {
+      set_error("GMRES: the residual is not finite");
+      return CHNS_ENOCONV;
+    }
     if (S.gd_host->conv || total >= max_it) break;
     // Arnoldi steps until the device flags the end of the cycle
     for (int it = 0; it < m; ++it) {
@@ -753,10 +757,17 @@ int newton_ch_impl(Ctx& c, const double* phi0, const double* mu0, const double* 
   const double r0 = std::sqrt(rr);
   double rn = r0;
   int it = 0;
+  *newton_it = 0;
+  *rfinal = rn;
+  if (!std::isfinite(r0)) {
+    set_error("Cahn-Hilliard residual is not finite (NaN or infinity in the state)");
+    return CHNS_ENOCONV;
+  }
   if ((rc = ensure_coef(c, &c.coef_chj))) return rc;
   const bool schur = o.ch_pc == CHNS_CH_PC_SCHUR_GMG;
   if (schur && (rc = schur_setup(c, s))) return rc;
-  while (rn > std::max(o.newton_rtol * r0, o.newton_atol) && it < o.max_newton) {
+  const double ntol = std::max(o.newton_rtol * r0, o.newton_atol);
+  while (!(rn <= ntol) && it < o.max_newton) {
     // Jacobian coefficients [phi^{k+1}, phi^k, u~] and its 2x2 node blocks
     if ((rc = copy(c.coef_chj, S.X, n, s))) return rc;
     if ((rc = copy(c.coef_chj + n, phi0, n, s))) return rc;
@@ -788,7 +799,7 @@ int newton_ch_impl(Ctx& c, const double* phi0, const double* mu0, const double* 
   }
   *newton_it = it;
   *rfinal = rn;
-  if (rn > std::max(o.newton_rtol * r0, o.newton_atol)) {
+  if (!(rn <= ntol)) {
     set_error("Newton iteration for the Cahn-Hilliard system did not converge");
     return CHNS_ENOCONV;
   }
@@ -909,7 +920,28 @@ int initial_mu_impl(Ctx& c, const double* phi, double* mu, hipStream_t s) {
   return solve_spd_impl(c, CHNS_OP_MASS, S.R + n, mu, S.dm, 1e-13, 10000, false, s, &it, &rel);
 }
 
+int advance_step_body(Ctx& c, const chns_state& st, const chns_step_opts& o, chns_step_stats& stats,
+                      hipStream_t caller);
+
+// On an error return the step has replaced the context's phase field (and
+// possibly the operator behind the multigrid hierarchy) part way through:
+// the phase field is marked unset, so later pressure applies and solves
+// return CHNS_ESTATE until chns_set_phase_field, and every cached set-up is
+// invalidated.
 int advance_step_impl(Ctx& c, const chns_state& st, const chns_step_opts& o, chns_step_stats& stats,
+                      hipStream_t caller) {
+  const int rc = advance_step_body(c, st, o, stats, caller);
+  if (rc) {
+    c.phi_set = false;
+    c.pp_kind = 0;
+    c.pp_shift = 0.0;
+    c.diag_valid = false;
+    if (c.mg) c.mg->setup_valid = false;
+  }
+  return rc;
+}
+
+int advance_step_body(Ctx& c, const chns_state& st, const chns_step_opts& o, chns_step_stats& stats,
                       hipStream_t caller) {
   Clock clk;
   const int64_t n = c.dm.n;

@@ -90,7 +90,9 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const double* partials
     sc->rz = tot[0];
     sc->rr = tot[1];
     sc->it = 0;
-    sc->done = (tot[1] <= sc->tol2) ? 1 : 0;
+    // converged, or breakdown: a non-finite residual or r.z <= 0 (an
+    // indefinite or vanishing preconditioner output) ends the solve at x_0
+    sc->done = (tot[1] <= sc->tol2 || !(tot[1] == tot[1]) || !(tot[0] > 0.0)) ? 1 : 0;
   } else {
     // CG: beta = (r_new.z_new) / (r_old.z_old); flexible CG (Polak-Ribiere
     // form): beta = z_new.(r_new - r_old) / (r_old.z_old)
@@ -99,7 +101,13 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const double* partials
     sc->rr = tot[1];
     sc->beta = (mode == FIN_FCG_UPDATE ? tot[0] - tot[2] : tot[0]) / sc->rz_old;
     sc->it = sc->it + 1;
-    sc->done = (tot[1] <= sc->tol2 || sc->it >= sc->max_it || !(tot[1] == tot[1])) ? 1 : 0;
+    // the update kernel skipped this step when p.Ap <= 0 (see k_cg_update);
+    // r.z <= 0 would make the next step length meaningless: both end the solve
+    // at the last iterate, as does a non-finite residual
+    sc->done = (tot[1] <= sc->tol2 || sc->it >= sc->max_it || !(tot[1] == tot[1]) || !(sc->pq > 0.0) ||
+                !(tot[0] > 0.0))
+                   ? 1
+                   : 0;
   }
   if (flag_host && mode != FIN_STORE) {
     // vector stores with system scope into pinned host memory; visible to
@@ -142,15 +150,20 @@ __global__ void k_sub_mean(const T* x, T* y, int64_t n, const double* sum) {
     y[i] = (T)((double)x[i] - m);
 }
 
-__global__ void k_phase(const double* phi, const double* prev, double* p64, float* p32, int64_t n) {
+__global__ void k_clear_flag(int* f) { *f = 0; }
+__global__ void k_phase(const double* phi, const double* prev, double* p64, float* p32, int64_t n, int* bad) {
+  bool ok = true;
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
     double v = prev ? 0.5 * (phi[i] + prev[i]) : phi[i];
+    ok = ok && __builtin_isfinite(v);
     p64[i] = v;
     // FP32 copy holds 1 + phi: near phi = -1 (the light phase) this keeps the
     // relative accuracy of rho = (beta - alpha) + alpha (1 + phi) at high
     // density ratios, where alpha phi + beta would cancel.
     p32[i] = (float)(1.0 + v);
   }
+  // the pull back would map a NaN to a pure phase; flag it instead
+  if (!ok) *bad = 1;
 }
 
 template <typename T>
@@ -191,7 +204,8 @@ __global__ __launch_bounds__(kThreads) void k_cg_update(T* x, T* r, T* z, const 
                                                         int64_t n, DevScalars* sc, double* partials,
                                                         unsigned* counter) {
   if (sc->done) return;
-  const double alpha = sc->rz / sc->pq;
+  // p.Ap <= 0 (breakdown of a non-SPD preconditioner, or p = 0): no step
+  const double alpha = sc->pq > 0.0 ? sc->rz / sc->pq : 0.0;
   const T a = (T)alpha;
   double v[2] = {0.0, 0.0};
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
@@ -232,7 +246,7 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_cg_update_nopc(T* x, T* r, T* r_old, const T* p, const T* q, int64_t n,
                                                              const DevScalars* sc, double* partials) {
   if (sc->done) return;
-  const T a = (T)(sc->rz / sc->pq);
+  const T a = (T)(sc->pq > 0.0 ? sc->rz / sc->pq : 0.0);
   double v[2] = {0.0, 0.0};
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
     const T ri = r[i];
@@ -514,7 +528,8 @@ int pcg(Ctx& c, int op, const T* b, T* x, int pc, const T* dinv, bool flexible, 
 }  // namespace
 
 int launch_set_phase(Ctx& c, const double* phi, const double* prev, hipStream_t s) {
-  k_phase<<<grid_for(c.dm.n), kThreads, 0, s>>>(phi, prev, c.phi64, c.phi32, c.dm.n);
+  k_clear_flag<<<1, 1, 0, s>>>(&c.sc->phi_bad);
+  k_phase<<<grid_for(c.dm.n), kThreads, 0, s>>>(phi, prev, c.phi64, c.phi32, c.dm.n, &c.sc->phi_bad);
   CHNS_HIP(hipGetLastError());
   c.phi_set = true;
   c.diag_valid = false;
@@ -602,6 +617,18 @@ int solve_pressure_impl(Ctx& c, const double* b_in, double* x_out, const chns_so
   st.iterations = 0;
   st.outer_iterations = 0;
   st.fallback = 0;
+  if (c.sc_host->phi_bad) {
+    st.rel_residual = NAN;
+    st.ms_solve = 0.0;
+    set_error("the phase field holds a NaN or an infinity");
+    return CHNS_EINVAL;
+  }
+  if (!std::isfinite(bb)) {
+    st.rel_residual = NAN;
+    st.ms_solve = 0.0;
+    set_error("the right-hand side holds a NaN or an infinity");
+    return CHNS_EINVAL;
+  }
   if (bb == 0.0) {
     k_fill<double><<<g, kThreads, 0, s>>>(x_out, 0.0, n);
     CHNS_HIP(hipStreamSynchronize(s));

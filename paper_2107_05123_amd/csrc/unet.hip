@@ -1202,7 +1202,7 @@ int unet_load(Ctx& c, const void* blob, size_t n, hipStream_t s) {
   float K = 1.0f, omega = 0.0f;
   if (!blob || !take(magic, 8) || std::memcmp(magic, "CHNSUNET", 8) != 0 || !take(&ver, 4) ||
       (ver != 1 && ver != 2) || !take(&nl, 4) || nl != kLayers || !take(&K, 4) || (ver == 2 && !take(&omega, 4)) ||
-      !(K > 0.0f) || !(omega >= 0.0f && omega < 2.0f)) {
+      !(K >= 0.0f) || !(omega >= 0.0f && omega < 2.0f)) {
     set_error("not a U-Net weight blob of this library");
     return CHNS_EINVAL;
   }
@@ -1454,6 +1454,10 @@ int unet_train_step(Ctx& c, const chns_pc_batch& b, float lr, float* loss, hipSt
   if (!c.unet || !c.unet->ready) {
     set_error("no U-Net weights in this context");
     return CHNS_ESTATE;
+  }
+  if (!(c.unet->K > 0.0f)) {
+    set_error("training needs a positive output scale K");
+    return CHNS_EINVAL;
   }
   if (b.objective == CHNS_PC_OBJ_ANORM) {
     if (b.n < 1 || !b.phi || !b.r || !b.e) {

@@ -12,16 +12,16 @@ from oracle import mesh as om
 
 
 class Pair:
-    def __init__(self, kind, dim, lmin, lmax, centre=(0.5, 0.3, 0.5), radius=0.15, band=0.03):
+    def __init__(self, kind, dim, lmin, lmax, centre=(0.5, 0.3, 0.5), radius=0.15, band=0.03, brick_max=0):
         from paper_2107_05123_amd import Mesh
         self.kind, self.dim = kind, dim
         c = tuple(centre[:dim])
         if kind == "uniform":
-            self.lib = Mesh(dim=dim, min_level=lmax, max_level=lmax, rule="uniform")
+            self.lib = Mesh(dim=dim, min_level=lmax, max_level=lmax, rule="uniform", brick_max=brick_max)
             self.orc = om.uniform(dim, lmax)
         elif kind == "band":
             self.lib = Mesh(dim=dim, min_level=lmin, max_level=lmax, rule="sphere_band", centres=[c],
-                            radii=[radius], band=band)
+                            radii=[radius], band=band, brick_max=brick_max)
             self.orc = om.sphere_band(dim, lmin, lmax, c, radius, band)
         else:
             raise ValueError(kind)
