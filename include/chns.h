@@ -197,6 +197,22 @@ enum { CHNS_FP64 = 0, CHNS_FP32 = 1 };
  * FP64 only (CHNS_EINVAL).  Async.                                          */
 int chns_apply_operator(chns_ctx* ctx, int op, int prec, const void* x, void* y, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * y = Op x as chns_apply_operator, same kernels and bitwise the same result,
+ * but the brick-boundary partial sums live in a static per-GPU scratch array
+ * of 32 MiB (held by each GPU the library runs on until the process ends)
+ * instead of the context's slot buffer.  The call allocates nothing.
+ * Arguments as chns_apply_operator; the current device must be the
+ * context's.  EINVAL when the mesh needs more scratch than 32 MiB for this
+ * operator and precision (fields * brick-boundary slots * element size; a
+ * 128^3 mesh of 8^3 bricks has 1.58 M slots and fits for every operator but
+ * the three-field FP64 momentum operator), or while profiling is enabled.  Every call on one GPU
+ * (any context, any stream) uses the same array and overwrites it: calls
+ * that overlap in time on one GPU race and give wrong results; calls ordered
+ * on one stream, or separated by synchronisation, are safe.  Async.        */
+int chns_apply_operator_noalloc(chns_ctx* ctx, int op, int prec, const void* x, void* y, void* stream);
+
 /* Exact diagonal of the constrained operator diag(P^T (sum_e K_e) P),
  * including the cross terms that hanging nodes create.  d: device,
  * n_fields * n_nodes.  Async.                                              */

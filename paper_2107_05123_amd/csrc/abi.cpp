@@ -397,6 +397,7 @@ int chns_context_create(chns_mesh* mesh, const chns_params* params, chns_ctx** o
     rc = hip_fail(hipErrorUnknown, "hipStreamCreateWithFlags");
   if (!rc && hipEventCreateWithFlags(&c.ev_in, hipEventDisableTiming) != hipSuccess)
     rc = hip_fail(hipErrorUnknown, "hipEventCreateWithFlags");
+  if (!rc) rc = scratch_address(&c.scratch);
   if (rc) {
     delete h;
     return rc;
@@ -434,6 +435,29 @@ int chns_apply_operator(chns_ctx* ctx, int op, int prec, const void* x, void* y,
   }
   ApplyOut o{};
   return launch_apply(ctx->c, op, prec, x, y, (hipStream_t)stream, o);
+  CHNS_GUARD_END
+}
+
+int chns_apply_operator_noalloc(chns_ctx* ctx, int op, int prec, const void* x, void* y, void* stream) {
+  CHNS_GUARD_BEGIN
+  if (!ctx || !x || !y) {
+    set_error("null argument");
+    return CHNS_EINVAL;
+  }
+  if (x == y) {
+    set_error("x and y must not alias");
+    return CHNS_EINVAL;
+  }
+  if (ctx->c.prof) {
+    set_error("the allocation-free apply does not run with profiling enabled");
+    return CHNS_EINVAL;
+  }
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != ctx->c.device) {
+    set_error("the current device is not the context's device");
+    return CHNS_EINVAL;
+  }
+  return launch_apply_noalloc(ctx->c, op, prec, x, y, (hipStream_t)stream);
   CHNS_GUARD_END
 }
 

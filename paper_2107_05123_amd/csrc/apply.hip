@@ -14,12 +14,19 @@
 //     buffer, and a second pass (k_combine) adds the slots of every shared
 //     node in a fixed order, applying P^T for hanging entries.  No atomics:
 //     the result is bitwise reproducible.
+#include <mutex>
+
 #include "brick_geom.h"
 #include "chns_internal.h"
 #include "elem_chns.h"
 
 namespace chns {
 namespace {
+
+// Slot buffer of the allocation-free apply (chns_apply_operator_noalloc):
+// one per GPU, held until the process ends.  In host code `scratch` names a
+// host-side stand-in; kernels get the device address from scratch_address().
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 constexpr double kGauss = 0.57735026918962576451;  // 1/sqrt(3)
 
@@ -1182,6 +1189,46 @@ int op_fields(int op, int dim) {
 }
 
 LevelView fine_view(Ctx& c) { return LevelView{&c.dm, c.phi64, c.phi32, c.slots}; }
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept for the process.
+int scratch_address(void** out) {
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = -1;
+  CHNS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("device index beyond the library's limit");
+    return CHNS_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    CHNS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return CHNS_OK;
+}
+
+int launch_apply_noalloc(Ctx& c, int op, int prec, const void* x, void* y, hipStream_t s) {
+  if (!c.scratch) {
+    set_error("context has no scratch address");
+    return CHNS_ESTATE;
+  }
+  const size_t es = prec == CHNS_FP64 ? sizeof(double) : sizeof(float);
+  const int nf = op_fields(op, c.dm.dim);
+  const size_t need = es * (size_t)nf * (size_t)(c.dm.n_slots > 0 ? c.dm.n_slots : 1);
+  if (nf > 0 && need > kScratchBytes) {
+    set_error("mesh needs " + std::to_string(need) + " bytes of slot scratch for this operator, more than the " +
+              std::to_string(kScratchBytes) + " the allocation-free apply has");
+    return CHNS_EINVAL;
+  }
+  LevelView L = fine_view(c);
+  L.slots = c.scratch;
+  ApplyOut o{};
+  return launch_apply_lv(c, L, op, prec, x, y, s, o);
+}
 
 int launch_apply_lv(Ctx& c, const LevelView& L, int op, int prec, const void* x, void* y, hipStream_t s,
                     const ApplyOut& o) {

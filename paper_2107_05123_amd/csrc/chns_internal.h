@@ -139,6 +139,8 @@ struct Ctx {
   // slot buffers (largest field count * n_slots), both precisions share storage
   void* slots = nullptr;
   size_t slots_bytes = 0;
+  // device address of the per-GPU slot scratch of the allocation-free apply
+  void* scratch = nullptr;
 
   // reduction scratch
   double* partials = nullptr;   // kMaxPartials
@@ -212,6 +214,9 @@ struct Ctx {
   ~Ctx();
 };
 
+// slot scratch of the allocation-free apply, per GPU (apply.hip)
+constexpr size_t kScratchBytes = size_t(32) << 20;
+constexpr int kMaxDevices = 64;
 constexpr int kMaxPartials = 1 << 20;  // per-block reduction partials (bricks + combine blocks of the largest meshes)
 constexpr int kMaxCoefFields = 16;  // coefficient fields one element form may read
 
@@ -245,6 +250,10 @@ int launch_diagonal_lv(Ctx& c, const LevelView& L, int op, int prec, void* d, bo
                        hipStream_t s);
 LevelView fine_view(Ctx& c);
 int op_fields(int op, int dim);
+// address of the per-GPU static slot scratch on the current device (looked
+// up once per device); the apply below uses it instead of the context's slots
+int scratch_address(void** out);
+int launch_apply_noalloc(Ctx& c, int op, int prec, const void* x, void* y, hipStream_t s);
 
 // Run `enqueue(stream)` through a HIP graph captured on first use and cached
 // in *cache (eagerly when profiling).  The enqueued work must be kernels only.
