@@ -141,27 +141,3 @@ def rho_mass_matrix(mesh: OracleMesh, phi_indep: np.ndarray, rho_plus: float, rh
     alpha, beta = rho_coeffs(rho_plus, rho_minus)
     rq = alpha * pull_back(qp_values(mesh, phi_indep)) + beta
     return mass_matrix(mesh, rq)
-
-
-def pp_rows_uniform(mesh: OracleMesh, phi_indep: np.ndarray, x_indep: np.ndarray, rows: np.ndarray,
-                    rho_plus: float, rho_minus: float) -> np.ndarray:
-    """(A x)_i for selected independent nodes of a mesh without hanging nodes,
-    summing the element matrices of the leaves around each node one by one."""
-    assert not mesh.hanging.any()
-    node_all = mesh.indep[rows]
-    out = np.zeros(rows.shape[0])
-    # leaves incident to each node (brute force over the element-node table, via a sort)
-    en = mesh.elem_nodes
-    flat = en.ravel()
-    order = np.argsort(flat, kind="stable")
-    sorted_nodes = flat[order]
-    for k, n in enumerate(node_all):
-        lo = np.searchsorted(sorted_nodes, n, side="left")
-        hi = np.searchsorted(sorted_nodes, n, side="right")
-        pos = order[lo:hi]
-        elems = pos // en.shape[1]
-        local = pos % en.shape[1]
-        Ke = pp_element_matrices(mesh, phi_indep, rho_plus, rho_minus, elems=elems)
-        xa = x_indep[np.searchsorted(mesh.indep, en[elems])]  # P = I
-        out[k] = sum(Ke[i, local[i], :] @ xa[i] for i in range(elems.shape[0]))
-    return out
