@@ -112,10 +112,43 @@ def solve_once(torch, ctx, phi_d, b, **kw):
     return x, st
 
 
+class RowSplit:
+    """A CSR matrix whose products run as row blocks on a thread pool (scipy
+    releases the GIL in its CSR kernels), so the oracle's own CG runs with a
+    T-thread sparse product."""
+
+    def __init__(self, A, threads):
+        from concurrent.futures import ThreadPoolExecutor
+        self.A, self.T = A, threads
+        cuts = np.linspace(0, A.shape[0], threads + 1).astype(np.int64)
+        self.blocks = [(int(cuts[i]), int(cuts[i + 1]), A[cuts[i]:cuts[i + 1]]) for i in range(threads)]
+        self.pool = ThreadPoolExecutor(threads)
+        self.shape = A.shape
+
+    def __matmul__(self, v):
+        out = np.empty(self.A.shape[0])
+
+        def part(blk):
+            lo, hi, Ab = blk
+            out[lo:hi] = Ab @ v
+        list(self.pool.map(part, self.blocks))
+        return out
+
+    def diagonal(self):
+        return self.A.diagonal()
+
+
+def host_threads():
+    """Threads of this process's CPU share (at most 16, the share of one GPU on the pool's boxes)."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
 def cpu_baseline(phi_nodes_lex, f_nodes_lex, pcg_iters):
     """Oracle timed on this host: mesh + CSR assembly + a bounded number of
     Jacobi-PCG iterations (the oracle's solver) on the same 128^3 problem,
-    scaled to the iteration count that solver needs to reach 1e-8."""
+    scaled to the iteration count that solver needs to reach 1e-8; once as it
+    stands (one thread) and once with its CSR products split over the host's
+    threads."""
     from oracle import fem, krylov, mesh as om
     t0 = time.time()
     m = om.uniform(3, LEVEL)
@@ -138,6 +171,17 @@ def cpu_baseline(phi_nodes_lex, f_nodes_lex, pcg_iters):
         A @ b
     t_spmv = (time.time() - t_spmv0) / 5
     est = t_asm + t_it * pcg_iters
+    T = host_threads()
+    At = RowSplit(A, T)
+    At @ b
+    t1 = time.time()
+    krylov.pcg(At, b, rtol=1e-30, max_it=k_it, M_inv_diag=dinv, singular=True)
+    t_it_T = (time.time() - t1) / k_it
+    t_spmv0 = time.time()
+    for _ in range(5):
+        At @ b
+    t_spmv_T = (time.time() - t_spmv0) / 5
+    At.pool.shutdown()
     return {
         "value": est, "unit": "s", "cores": 1, "kind": "oracle",
         "sample": (f"oracle mesh + CSR assembly ({t_asm:.1f} s) and {k_it} Jacobi-PCG iterations "
@@ -146,10 +190,15 @@ def cpu_baseline(phi_nodes_lex, f_nodes_lex, pcg_iters):
         "spmv_gdof_s": m.n_indep / t_spmv / 1e9,
         "assembly_s": t_asm,
         "pcg_iter_s": t_it,
+        "threads": {"value": t_asm + t_it_T * pcg_iters, "unit": "s", "cores": T,
+                    "kind": "oracle, CSR products split over the host threads",
+                    "sample": f"same assembly and {k_it} Jacobi-PCG iterations ({t_it_T * 1e3:.0f} ms each) with "
+                              f"the CSR product in {T} row blocks on {T} threads, scaled to {pcg_iters} iterations",
+                    "spmv_gdof_s": m.n_indep / t_spmv_T / 1e9, "pcg_iter_s": t_it_T},
     }
 
 
-def load_traffic(tag, launches_ms):
+def load_traffic(tag):
     """HBM traffic per launch from a stored rocprofv3 PMC summary, only if it
     was taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", f"{tag}_pmc.json")
@@ -160,6 +209,38 @@ def load_traffic(tag, launches_ms):
     if d.get("src_hash") != src_hash():
         return None
     return d.get("bytes_per_launch")
+
+
+def apply_roofline(n_elems, n_dof, brick_ms, combine_ms, es=8):
+    """Roofline entry of one whole pressure apply (brick kernel + combine,
+    their average durations from the library's HIP events): algorithmic
+    bytes (x, phi~ read, y written once: 24 B/DoF in FP64, 12 in FP32) and
+    flops per launch over the apply's time, against HBM and the vector ALU.
+    The brick kernel alone is kept as an extra entry."""
+    flops = PP_FLOPS_PER_LEAF * n_elems
+    nbytes = PP_BYTES_PER_DOF[es] * n_dof
+    ms = brick_ms + combine_ms
+    ach_flops = flops / (ms * 1e-3) / 1e12
+    ach_gbs = nbytes / (ms * 1e-3) / 1e9
+    peak_alu = FP64_PEAK_TFLOPS if es == 8 else FP32_PEAK_TFLOPS
+    frac_alu = ach_flops / peak_alu
+    frac_hbm = ach_gbs / HBM_PEAK_GBS
+    traffic = load_traffic("pp_apply_fp64_l7" if es == 8 else "pp_apply_fp32_l7")
+    # the bound is the resource whose roofline is lower at this intensity
+    ridge = peak_alu * 1e12 / (HBM_PEAK_GBS * 1e9)
+    if flops / nbytes >= ridge:
+        roof = {"bound": "alu", "achieved": ach_flops, "peak": peak_alu, "unit": "TFLOP/s", "frac": frac_alu,
+                "traffic": traffic}
+    else:
+        roof = {"bound": "hbm", "achieved": ach_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": frac_hbm,
+                "traffic": traffic}
+    prec = "double" if es == 8 else "float"
+    roof.update({"kernel": f"k_brick_o4<3,8,{prec},PP> + k_combine<{prec},1,0> (one apply)", "kernel_ms": ms,
+                 "algorithmic_bytes_per_launch": nbytes, "algorithmic_flops_per_launch": flops,
+                 "hbm_frac_algorithmic": frac_hbm, "alu_frac": frac_alu, "gdof_s": n_dof / (ms * 1e-3) / 1e9,
+                 "brick_only": {"kernel_ms": brick_ms, "alu_frac": flops / (brick_ms * 1e-3) / 1e12 / peak_alu,
+                                "hbm_frac_algorithmic": nbytes / (brick_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}})
+    return roof
 
 
 def summarize_stats(db, out_md, title, command, note, limit=30):
@@ -178,34 +259,36 @@ def summarize_stats(db, out_md, title, command, note, limit=30):
         fh.write("\n".join(lines) + "\n")
 
 
-def summarize_pmc(fetch_csv, write_csv, out_json, commands):
-    """HBM bytes per launch of the FP64 pressure brick kernel (and the
-    combine) from FETCH_SIZE / WRITE_SIZE passes, calibrated on the 256 MiB
-    device copy of the same run (copy reads and writes 262144 KiB)."""
+def summarize_pmc(fetch_csv, write_csv, out_prefix, commands):
+    """HBM bytes per pressure apply (brick kernel + combine), FP64 and FP32,
+    from FETCH_SIZE / WRITE_SIZE passes, calibrated on the 256 MiB device copy
+    of the same run (the copy reads and writes 262144 KiB)."""
     import csv
 
     def per_kernel(path, key):
         with open(path) as fh:
             return [float(r["Counter_Value"]) for r in csv.DictReader(fh) if key in r["Kernel_Name"]]
-    avg = lambda v: sum(v) / len(v)
+    avg = lambda v: sum(v) / len(v) if v else 0.0
     ff = 262144.0 / max(per_kernel(fetch_csv, "copyBuffer"))
     fw = 262144.0 / max(per_kernel(write_csv, "copyBuffer"))
-    fb = per_kernel(fetch_csv, "k_brick_o4<3, 8, double, 0")
-    wb = per_kernel(write_csv, "k_brick_o4<3, 8, double, 0")
-    fc = per_kernel(fetch_csv, "k_combine<double, 1, 0>")
-    wc = per_kernel(write_csv, "k_combine<double, 1, 0>")
-    fetch, write = avg(fb) * ff * 1024, avg(wb) * fw * 1024
-    d = {"kernel": "k_brick_o4<3,8,double,PP> (pressure-Poisson apply, FP64, 128^3)", "src_hash": src_hash(),
-         "fetch_size_kib_per_dispatch": avg(fb), "write_size_kib_per_dispatch": avg(wb), "dispatches": len(fb),
-         "fetch_factor": ff, "write_factor": fw,
-         "calibration": "256 MiB device copy: FETCH_SIZE x fetch_factor and WRITE_SIZE x write_factor give "
-                        "262144 KiB each",
-         "bytes_per_launch": fetch + write, "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
-         "combine_fetch_bytes_per_launch": avg(fc) * ff * 1024,
-         "combine_write_bytes_per_launch": avg(wc) * fw * 1024, "commands": commands}
-    with open(out_json, "w") as fh:
-        json.dump(d, fh, indent=1)
-    return d
+    out = {}
+    for prec, es in (("double", 8), ("float", 4)):
+        kb, kc = f"k_brick_o4<3, 8, {prec}, 0", f"k_combine<{prec}, 1, 0>"
+        fb, wb = avg(per_kernel(fetch_csv, kb)) * ff * 1024, avg(per_kernel(write_csv, kb)) * fw * 1024
+        fc, wc = avg(per_kernel(fetch_csv, kc)) * ff * 1024, avg(per_kernel(write_csv, kc)) * fw * 1024
+        d = {"kernel": f"k_brick_o4<3,8,{prec},PP> + k_combine<{prec},1,0> (pressure-Poisson apply, 128^3)",
+             "src_hash": src_hash(), "dispatches": len(per_kernel(fetch_csv, kb)),
+             "fetch_factor": ff, "write_factor": fw,
+             "calibration": "256 MiB device copy: FETCH_SIZE x fetch_factor and WRITE_SIZE x write_factor give "
+                            "262144 KiB each",
+             "bytes_per_launch": fb + wb + fc + wc,
+             "brick_fetch_bytes": fb, "brick_write_bytes": wb, "combine_fetch_bytes": fc,
+             "combine_write_bytes": wc, "commands": commands}
+        name = f"{out_prefix}_fp{8 * es}_l7_pmc.json"
+        with open(name, "w") as fh:
+            json.dump(d, fh, indent=1)
+        out[prec] = d
+    return out
 
 
 def profile_run(torch, with_solve=True, pc="jacobi"):
@@ -441,6 +524,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adaptive", action="store_true", help="leave out the adaptive (levels 5-10) key")
+    ap.add_argument("--adaptive-level", type=int, default=10, help="finest level of the adaptive key")
     ap.add_argument("--profile-run", nargs="?", const="full", default=None,
                     help="fixed sequence for rocprofv3; 'applies' skips the solve (for counter passes), "
                          "'gmg' solves with multigrid CG, 'chns' runs the CHNS applies, steps and network passes")
@@ -463,8 +548,8 @@ def main():
                     help="bubble_steps: pressure solve modes to step with, in order (comma-separated)")
     ap.add_argument("--summarize-stats", nargs=5, metavar=("DB", "OUT_MD", "TITLE", "COMMAND", "NOTE"),
                     help="write the kernel-statistics table of a rocprofv3 database (no GPU needed)")
-    ap.add_argument("--summarize-pmc", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON", "CMD1", "CMD2"),
-                    help="write the HBM-traffic summary of the pressure brick kernel (no GPU needed)")
+    ap.add_argument("--summarize-pmc", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_PREFIX", "CMD1", "CMD2"),
+                    help="write the HBM-traffic summaries of the FP64 and FP32 pressure applies (no GPU needed)")
     args = ap.parse_args()
     if args.summarize_stats:
         db, out, title, cmd, note = args.summarize_stats
@@ -549,23 +634,9 @@ def main():
     ms32 = time_applies(torch, ctx, xr.float())
     k64, comb64 = kernel_avg_ms(torch, ctx, xr, "pp_brick_fp64")
     k32, comb32 = kernel_avg_ms(torch, ctx, xr.float(), "pp_brick_fp32")
+    roof = apply_roofline(mesh.n_elems, n, k64, comb64)
+    roof32 = apply_roofline(mesh.n_elems, n, k32, comb32, es=4)
     E = mesh.n_elems
-    flops = PP_FLOPS_PER_LEAF * E
-    bytes64 = PP_BYTES_PER_DOF[8] * n
-    ach_flops = flops / (k64 * 1e-3) / 1e12
-    ach_gbs = bytes64 / (k64 * 1e-3) / 1e9
-    frac_alu = ach_flops / FP64_PEAK_TFLOPS
-    frac_hbm = ach_gbs / HBM_PEAK_GBS
-    traffic = load_traffic("pp_brick_fp64_l7", k64)
-    if frac_alu >= frac_hbm:
-        roof = {"bound": "alu", "achieved": ach_flops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": frac_alu, "traffic": traffic}
-    else:
-        roof = {"bound": "hbm", "achieved": ach_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": frac_hbm, "traffic": traffic}
-    roof.update({"kernel": "k_brick_o4<3,8,double,PP>", "kernel_ms": k64,
-                 "algorithmic_bytes_per_launch": bytes64, "algorithmic_flops_per_launch": flops,
-                 "hbm_frac_algorithmic": frac_hbm, "alu_frac": frac_alu})
 
     out = {
         "metric": METRIC,
@@ -589,12 +660,15 @@ def main():
                          "brick_fp64_ms": k64, "combine_fp64_ms": comb64,
                          "brick_fp32_ms": k32, "combine_fp32_ms": comb32},
         "roofline": roof,
+        "roofline_fp32": roof32,
         "variants": variants,
         "iterations": st.iterations,
         "rel_residual": st.rel_residual,
         "host_mesh_build_s": t_mesh,
         "chns": chns_measure(torch, mesh, ctx, phi_d),
     }
+    if not args.no_adaptive:
+        out["adaptive"] = adaptive_workload(torch, args.adaptive_level)
     if not args.no_cpu_baseline:
         lex = np.arange(n)  # uniform meshes are numbered lexicographically, x fastest
         out["cpu_baseline"] = cpu_baseline(phi[lex], f[lex], variants["jacobi_pcg_fp64"]["iterations"])

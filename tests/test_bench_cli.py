@@ -56,12 +56,14 @@ def test_traffic_summary_scales_by_the_copy_calibration(tmp_path):
     write(wr, [{"Kernel_Name": "__amd_rocclr_copyBuffer", "Counter_Value": 262144.0},
                {"Kernel_Name": brick, "Counter_Value": 50.0}, {"Kernel_Name": brick, "Counter_Value": 50.0},
                {"Kernel_Name": comb, "Counter_Value": 5.0}])
-    out = tmp_path / "p.json"
+    prefix = tmp_path / "pp_apply"
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--summarize-pmc", str(fetch), str(wr),
-                        str(out), "c1", "c2"], capture_output=True, text=True, timeout=120)
+                        str(prefix), "c1", "c2"], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stderr
-    d = json.loads(out.read_text())
+    d = json.loads((tmp_path / "pp_apply_fp64_l7_pmc.json").read_text())
     assert d["fetch_factor"] == 2.0 and d["write_factor"] == 1.0
-    assert d["fetch_bytes_per_launch"] == 200.0 * 2.0 * 1024
-    assert d["write_bytes_per_launch"] == 50.0 * 1024
-    assert d["bytes_per_launch"] == (400.0 + 50.0) * 1024
+    assert d["brick_fetch_bytes"] == 200.0 * 2.0 * 1024
+    assert d["brick_write_bytes"] == 50.0 * 1024
+    assert d["combine_fetch_bytes"] == 10.0 * 2.0 * 1024 and d["combine_write_bytes"] == 5.0 * 1024
+    assert d["bytes_per_launch"] == (400.0 + 50.0 + 20.0 + 5.0) * 1024
+    assert (tmp_path / "pp_apply_fp32_l7_pmc.json").exists()
