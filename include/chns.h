@@ -283,7 +283,8 @@ enum {
                                 -> (R_phi, R_mu), 2n (Def. 6)                   */
   CHNS_FORM_VP_RHS = 1,      /* fields {phi~, mu~, u^, u^k, p^k} -> dim n, wall rows 0
                                 (Def. 3 right-hand side incl. gravity, Korteweg
-                                and the known part of the VMS fine scales)     */
+                                and the known part of the VMS fine scales; no
+                                body force: see chns_step_opts.force_v)        */
   CHNS_FORM_PP_RHS = 2,      /* fields {.. as VP_RHS .., v} -> n (Def. 4, including
                                 the fine-scale term of the predicted velocity)  */
   CHNS_FORM_VU_RHS = 3,      /* fields {.. as PP_RHS .., p^{k+1}} -> dim n, wall rows 0
@@ -331,6 +332,18 @@ typedef struct chns_step_opts {
                         * V-cycle of CHNS_OP_MOMENTUM_SCALAR per velocity
                         * component on the interior rows, identity on the wall
                         * rows; needs a mesh of max_level >= 2)                 */
+  /* Body forces for manufactured solutions (paper Sec. 5.1: the residual of
+   * the continuous equations for a prescribed solution is added as a body
+   * force), nodal values at the step's mid time t^k + dt/2, device FP64,
+   * each nullable (NULL = zero): force_v (dim * n, component-blocked) is the
+   * known right-hand side of the momentum equation, (w, f_v) in the
+   * velocity prediction and -f_v inside the fine-scale residual R_m of the
+   * prediction, the pressure Poisson and the velocity update; force_phi (n)
+   * enters the phase-field equation as -(q, f_phi), force_mu (n) the
+   * chemical-potential equation as +(q, f_mu).                            */
+  const double* force_v;
+  const double* force_phi;
+  const double* force_mu;
 } chns_step_opts;
 
 enum { CHNS_CH_PC_BLOCK_JACOBI = 0, CHNS_CH_PC_SCHUR_GMG = 1 };

@@ -157,8 +157,11 @@ class Elems:
 
 
 # ----------------------------------------------------------------- Cahn-Hilliard
-def ch_residual(el: Elems, prm: Params, phi1, mu1, phi0, mu0, ut):
-    """(R_phi, R_mu) of the discrete CH system; ut: (d, n) advecting velocity."""
+def ch_residual(el: Elems, prm: Params, phi1, mu1, phi0, mu0, ut, f_phi=None, f_mu=None):
+    """(R_phi, R_mu) of the discrete CH system; ut: (d, n) advecting velocity.
+
+    Optional body forces (nodal values at the step's mid time, manufactured
+    solutions): R_phi -= (q, f_phi), R_mu += (q, f_mu)."""
     pt = 0.5 * (phi1 + phi0)
     mt = 0.5 * (mu1 + mu0)
     w = el.detJ[:, None]
@@ -173,6 +176,10 @@ def ch_residual(el: Elems, prm: Params, phi1, mu1, phi0, mu0, ut):
             + np.einsum("eqad,eqd->ea", el.dN, w[..., None] * gmt) / (prm.pe * prm.Cn))
     Rmu = (np.einsum("eq,qa->ea", w * (dpsi(ptq) - el.val(mt)), N)
            + prm.Cn ** 2 * np.einsum("eqad,eqd->ea", el.dN, w[..., None] * gpt))
+    if f_phi is not None:
+        Rphi = Rphi - np.einsum("eq,qa->ea", w * el.val(f_phi), N)
+    if f_mu is not None:
+        Rmu = Rmu + np.einsum("eq,qa->ea", w * el.val(f_mu), N)
     return el.load(Rphi), el.load(Rmu)
 
 
@@ -195,12 +202,12 @@ def ch_jacobian(el: Elems, prm: Params, phi1, phi0, ut):
 
 
 def ch_solve(el: Elems, prm: Params, phi0, mu0, ut, phi_guess=None, mu_guess=None, rtol=1e-8, atol=1e-12,
-             max_newton=20):
+             max_newton=20, f_phi=None, f_mu=None):
     """Newton iteration x <- x - J^{-1} R until |R| <= max(rtol |R0|, atol)."""
     n = phi0.shape[0]
     phi = (phi0 if phi_guess is None else phi_guess).copy()
     mu = (mu0 if mu_guess is None else mu_guess).copy()
-    Rp, Rm = ch_residual(el, prm, phi, mu, phi0, mu0, ut)
+    Rp, Rm = ch_residual(el, prm, phi, mu, phi0, mu0, ut, f_phi, f_mu)
     r0 = np.linalg.norm(np.concatenate([Rp, Rm]))
     hist = [r0]
     it = 0
@@ -209,7 +216,7 @@ def ch_solve(el: Elems, prm: Params, phi0, mu0, ut, phi_guess=None, mu_guess=Non
         d = spla.spsolve(J.tocsc(), -np.concatenate([Rp, Rm]))
         phi = phi + d[:n]
         mu = mu + d[n:]
-        Rp, Rm = ch_residual(el, prm, phi, mu, phi0, mu0, ut)
+        Rp, Rm = ch_residual(el, prm, phi, mu, phi0, mu0, ut, f_phi, f_mu)
         hist.append(np.linalg.norm(np.concatenate([Rp, Rm])))
         it += 1
     return phi, mu, it, hist
@@ -229,8 +236,12 @@ class QPState:
     """Gauss-point coefficients shared by the velocity prediction, the
     pressure right-hand side and the velocity update."""
 
-    def __init__(self, el: Elems, prm: Params, phit, mut, uhat, uk, pk):
+    def __init__(self, el: Elems, prm: Params, phit, mut, uhat, uk, pk, f_v=None):
+        """f_v: optional body force (d, n) at the step's mid time; it is the
+        known right-hand side of the momentum equation, so it enters R_m
+        with a minus sign (and the velocity-prediction right-hand side)."""
         d = el.dim
+        self.fvq = None if f_v is None else [el.val(f_v[i]) for i in range(d)]
         self.ptq = el.val(phit)
         self.rho = prm.rho(self.ptq)
         self.eta = prm.eta(self.ptq)
@@ -257,11 +268,14 @@ class QPState:
             kort = sum(H[..., i, j] * self.gphi[..., j] for j in range(d) if j != i)
             gp = el.grad(pk)[..., i]
             grav = -1.0 if i == prm.gravity_axis else 0.0
-            self.Rk.append(-self.rho * ui / prm.dt
-                           + 0.5 * self.rho * (self.uh * gui).sum(-1)
-                           + (self.J * gui).sum(-1) / (2.0 * prm.pe)
-                           - (self.geta * gui).sum(-1) / (2.0 * prm.Re)
-                           + prm.Cn / prm.We * kort + gp - self.rho * grav / prm.Fr)
+            rk = (-self.rho * ui / prm.dt
+                  + 0.5 * self.rho * (self.uh * gui).sum(-1)
+                  + (self.J * gui).sum(-1) / (2.0 * prm.pe)
+                  - (self.geta * gui).sum(-1) / (2.0 * prm.Re)
+                  + prm.Cn / prm.We * kort + gp - self.rho * grav / prm.Fr)
+            if self.fvq is not None:
+                rk = rk - self.fvq[i]
+            self.Rk.append(rk)
 
     def rlin_of(self, el, prm, v):
         """R_lin(v) at the Gauss points for a nodal field v."""
@@ -309,6 +323,8 @@ def vp_rhs(el: Elems, prm: Params, S: QPState, uk, pk, phit):
         grav = -1.0 if i == prm.gravity_axis else 0.0
         f_N = (S.rho * ui / prm.dt - 0.5 * S.rho * (S.uh * gui).sum(-1) - (S.J * gui).sum(-1) / (2.0 * prm.pe)
                - gp + S.rho * grav / prm.Fr)
+        if S.fvq is not None:
+            f_N = f_N + S.fvq[i]
         b = (np.einsum("eq,qa->ea", w * f_N, N)
              - np.einsum("eqad,eqd->ea", el.dN, w[..., None] * S.eta[..., None] * gui) / (2.0 * prm.Re)
              + prm.Cn / prm.We * np.einsum("eqad,eqd->ea", el.dN,
@@ -390,9 +406,14 @@ def solve_singular(A, b):
     return x - x.mean()
 
 
-def step(el: Elems, prm: Params, st: State, blocks=2):
-    """One projection time step: `blocks` passes of CH -> VP -> PP -> VU."""
+def step(el: Elems, prm: Params, st: State, blocks=2, forcing=None):
+    """One projection time step: `blocks` passes of CH -> VP -> PP -> VU.
+
+    forcing: optional body forces (f_v (d, n), f_phi, f_mu), nodal values at
+    the step's mid time t^k + dt/2 (the time the scheme's averages are
+    centred on), used by manufactured solutions."""
     d = el.dim
+    f_v, f_phi, f_mu = forcing if forcing is not None else (None, None, None)
     uhat = 1.5 * st.u - 0.5 * st.u_prev
     u_new = st.u.copy()
     phi1, mu1 = st.phi.copy(), st.mu.copy()
@@ -400,11 +421,11 @@ def step(el: Elems, prm: Params, st: State, blocks=2):
     info = {"newton": []}
     for _ in range(blocks):
         ut = 0.5 * (st.u + u_new)
-        phi1, mu1, nit, hist = ch_solve(el, prm, st.phi, st.mu, ut, phi1, mu1)
+        phi1, mu1, nit, hist = ch_solve(el, prm, st.phi, st.mu, ut, phi1, mu1, f_phi=f_phi, f_mu=f_mu)
         info["newton"].append(nit)
         phit = 0.5 * (phi1 + st.phi)
         mut = 0.5 * (mu1 + st.mu)
-        S = QPState(el, prm, phit, mut, uhat, st.u, st.p)
+        S = QPState(el, prm, phit, mut, uhat, st.u, st.p, f_v)
         A = vp_matrix(el, prm, S).tocsc()
         v = np.stack([spla.spsolve(A, b) for b in vp_rhs(el, prm, S, st.u, st.p, phit)])
         p_new = solve_singular(pp_matrix_rhot(el, prm, S), pp_rhs(el, prm, S, v, st.p))

@@ -314,10 +314,14 @@ class Context:
 
     def advance_step(self, state: dict, blocks=2, newton_rtol=1e-8, newton_atol=1e-12, max_newton=20,
                      lin_rtol=1e-8, max_it=5000, restart=64, pp_pc="jacobi", pp_mode="fp64", graphs=True,
-                     ch_pc="block", vp_pc="jacobi", stream=None):
-        """state: dict of device FP64 tensors u, u_prev (dim*n), p, phi, mu (n), updated in place."""
+                     ch_pc="block", vp_pc="jacobi", forcing=None, stream=None):
+        """state: dict of device FP64 tensors u, u_prev (dim*n), p, phi, mu (n), updated in place;
+        forcing: optional (f_v (dim*n), f_phi (n), f_mu (n)) device tensors (None entries allowed),
+        nodal body forces at the step's mid time."""
         import torch
         d = self.dim * self.n
+        fv, fp, fm = forcing if forcing is not None else (None, None, None)
+        fptr = lambda t, k: _dev_ptr(t, torch.float64, k) if t is not None else C.c_void_p()
         st = L.State(_dev_ptr(state["u"], torch.float64, d), _dev_ptr(state["u_prev"], torch.float64, d),
                      _dev_ptr(state["p"], torch.float64, self.n), _dev_ptr(state["phi"], torch.float64, self.n),
                      _dev_ptr(state["mu"], torch.float64, self.n))
@@ -325,7 +329,8 @@ class Context:
                        {"jacobi": L.PC_JACOBI, "gmg": L.PC_GMG}[pp_pc],
                        {"fp64": L.MODE_FP64, "mixed": L.MODE_MIXED_IR}[pp_mode], 0 if graphs else 1,
                        {"block": L.CH_PC_BLOCK_JACOBI, "schur": L.CH_PC_SCHUR_GMG}[ch_pc],
-                       {"jacobi": L.VP_PC_JACOBI, "gmg": L.VP_PC_GMG}[vp_pc])
+                       {"jacobi": L.VP_PC_JACOBI, "gmg": L.VP_PC_GMG}[vp_pc],
+                       fptr(fv, d), fptr(fp, self.n), fptr(fm, self.n))
         ss = L.StepStats()
         L.check(L.lib().chns_advance_step(self._h, C.byref(st), C.byref(o), C.byref(ss), _stream_ptr(stream)))
         return {"newton": list(ss.newton_iterations)[:blocks], "ch_iterations": ss.ch_iterations,

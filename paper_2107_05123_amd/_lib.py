@@ -70,6 +70,7 @@ class StepOpts(C.Structure):
         ("blocks", C.c_int), ("newton_rtol", C.c_double), ("newton_atol", C.c_double), ("max_newton", C.c_int),
         ("lin_rtol", C.c_double), ("max_it", C.c_int), ("restart", C.c_int), ("pp_pc", C.c_int),
         ("pp_mode", C.c_int), ("no_graphs", C.c_int), ("ch_pc", C.c_int), ("vp_pc", C.c_int),
+        ("force_v", C.c_void_p), ("force_phi", C.c_void_p), ("force_mu", C.c_void_p),
     ]
 
 

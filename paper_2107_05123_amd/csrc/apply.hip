@@ -168,9 +168,9 @@ CHNS_TRAITS(K_MASS_RHO, DIM, 1, DIM, true, 1)
 CHNS_TRAITS(K_CH_RES, 2, 2 + DIM, 2, false, 0)
 CHNS_TRAITS(K_CH_JAC, 2, 2 + DIM, 2, false, 0)
 CHNS_TRAITS(K_VP, DIM, 2 + DIM, DIM, true, 1)
-CHNS_TRAITS(K_VP_RHS, 0, 2 * DIM + 3, DIM, false, 2)
-CHNS_TRAITS(K_PP_RHS, 0, 3 * DIM + 3, 1, false, 0)
-CHNS_TRAITS(K_VU_RHS, 0, 3 * DIM + 4, DIM, false, 2)
+CHNS_TRAITS(K_VP_RHS, 0, 3 * DIM + 3, DIM, false, 2)
+CHNS_TRAITS(K_PP_RHS, 0, 4 * DIM + 3, 1, false, 0)
+CHNS_TRAITS(K_VU_RHS, 0, 4 * DIM + 4, DIM, false, 2)
 CHNS_TRAITS(K_ENERGY, 0, 2 + DIM, 1, false, 0)
 CHNS_TRAITS(K_PPS, 1, 1, 1, false, 0)  // pressure operator + shift * mass
 CHNS_TRAITS(K_VPS, 1, 1, 1, false, 0)  // scalar momentum: K_{eta/(2 Re)} + M_{rho/dt}
@@ -334,7 +334,9 @@ __device__ __forceinline__ void el_vp(const double (*x)[1 << DIM], const double 
 }
 
 // right-hand sides: coefficient layout phi~, mu~, u^ (DIM), u^k (DIM), p^k,
-// then v (DIM) and p^{k+1}
+// then v (DIM) and p^{k+1}, and last the body force f_v (DIM; zero except for
+// manufactured solutions), which is the known right-hand side of the momentum
+// equation: (w, f_v) in the velocity prediction and -f_v inside R_m
 template <int DIM>
 __device__ __forceinline__ void el_vp_rhs(const double (*c)[1 << DIM], const Phys& P, double gs, double w,
                                           double (*y)[1 << DIM]) {
@@ -343,6 +345,7 @@ __device__ __forceinline__ void el_vp_rhs(const double (*c)[1 << DIM], const Phy
 #pragma unroll
   for (int d = 0; d < DIM; ++d) uh[d] = c[2 + d];
   const double* pk = c[2 + 2 * DIM];
+  constexpr int FV = 3 + 2 * DIM;  // first body-force row
 #pragma unroll
   for (int f = 0; f < DIM; ++f)
 #pragma unroll
@@ -360,10 +363,11 @@ __device__ __forceinline__ void el_vp_rhs(const double (*c)[1 << DIM], const Phy
       double gui[DIM];
       QP<DIM>::grad(uk, q, gs, gui);
       const double kort = kort_i<DIM>(c[0], q, i, gs, M.gphi);
-      const double rk = M.rknown(P, i, ui, gui, gp, kort);
+      const double fvi = QP<DIM>::val(c[FV + i], q);
+      const double rk = M.rknown(P, i, ui, gui, gp, kort) - fvi;
       const double g = i == P.gaxis ? -1.0 : 0.0;
       const double fN = w * (M.rho * ui / P.dt - 0.5 * M.rho * M.dot(M.uh, gui) - M.dot(M.J, gui) / (2.0 * P.Pe) -
-                             gp[i] + M.rho * g / P.Fr);
+                             gp[i] + M.rho * g / P.Fr + fvi);
       double fG[DIM];
 #pragma unroll
       for (int d = 0; d < DIM; ++d) fG[d] = w * (-M.eta * gui[d] / (2.0 * P.Re) + P.Cn / P.We * M.gphi[i] * M.gphi[d]);
@@ -386,6 +390,7 @@ __device__ __forceinline__ void el_pp_rhs(const double (*c)[1 << DIM], const Phy
 #pragma unroll
   for (int d = 0; d < DIM; ++d) uh[d] = c[2 + d];
   const double* pk = c[2 + 2 * DIM];
+  constexpr int FV = 3 + 3 * DIM;  // first body-force row
 #pragma unroll
   for (int a = 0; a < NC; ++a) y[0][a] = 0.0;
 #pragma unroll
@@ -404,7 +409,8 @@ __device__ __forceinline__ void el_pp_rhs(const double (*c)[1 << DIM], const Phy
       QP<DIM>::grad(uk, q, gs, gui);
       div += gv[i];
       const double rl = M.rlin(P, QP<DIM>::val(v, q), gv);
-      const double rk = M.rknown(P, i, QP<DIM>::val(uk, q), gui, gp, kort_i<DIM>(c[0], q, i, gs, M.gphi));
+      const double rk = M.rknown(P, i, QP<DIM>::val(uk, q), gui, gp, kort_i<DIM>(c[0], q, i, gs, M.gphi)) -
+                        QP<DIM>::val(c[FV + i], q);
       fG[i] = w * (-(2.0 / P.dt) * M.tau * (rl + rk) / M.rho + gp[i] / M.rho);
     }
     const double fN = -w * (2.0 / P.dt) * div;
@@ -426,6 +432,7 @@ __device__ __forceinline__ void el_vu_rhs(const double (*c)[1 << DIM], const Phy
   for (int d = 0; d < DIM; ++d) uh[d] = c[2 + d];
   const double* pk = c[2 + 2 * DIM];
   const double* pn = c[3 + 3 * DIM];
+  constexpr int FV = 4 + 3 * DIM;  // first body-force row
 #pragma unroll
   for (int f = 0; f < DIM; ++f)
 #pragma unroll
@@ -446,7 +453,8 @@ __device__ __forceinline__ void el_vu_rhs(const double (*c)[1 << DIM], const Phy
       QP<DIM>::grad(uk, q, gs, gui);
       const double vq = QP<DIM>::val(v, q);
       const double rl = M.rlin(P, vq, gv);
-      const double rk = M.rknown(P, i, QP<DIM>::val(uk, q), gui, gp, kort_i<DIM>(c[0], q, i, gs, M.gphi));
+      const double rk = M.rknown(P, i, QP<DIM>::val(uk, q), gui, gp, kort_i<DIM>(c[0], q, i, gs, M.gphi)) -
+                        QP<DIM>::val(c[FV + i], q);
       const double f = w * (M.rho * vq - M.tau * (rl + rk) - 0.5 * P.dt * (gpn[i] - gp[i]));
 #pragma unroll
       for (int a = 0; a < NC; ++a) y[i][a] += refN<DIM>(q, a) * f;

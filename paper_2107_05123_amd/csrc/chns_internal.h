@@ -282,9 +282,10 @@ int run_captured(Ctx& c, hipGraphExec_t* cache, hipStream_t s, F&& enqueue) {
 //   CH_RES  x = [phi^{k+1}, mu^{k+1}], cf = [phi^k, mu^k, u~_0..]    -> 2 fields
 //   CH_JAC  x = [dphi, dmu],           cf = [phi^{k+1}, phi^k, u~]   -> 2 fields
 //   VP      x = v (dim),               cf = [phi~, mu~, u^]          -> dim fields
-//   VP_RHS  cf = [phi~, mu~, u^, u^k, p^k]                          -> dim fields
-//   PP_RHS  cf = [phi~, mu~, u^, u^k, p^k, v]                       -> 1 field
-//   VU_RHS  cf = [phi~, mu~, u^, u^k, p^k, v, p^{k+1}]              -> dim fields
+//   VP_RHS  cf = [phi~, mu~, u^, u^k, p^k, f_v]                     -> dim fields
+//   PP_RHS  cf = [phi~, mu~, u^, u^k, p^k, v, f_v]                  -> 1 field
+//   VU_RHS  cf = [phi~, mu~, u^, u^k, p^k, v, p^{k+1}, f_v]         -> dim fields
+//   (f_v: body force of the momentum equation, dim fields; zeros without one)
 //   ENERGY  cf = [phi, vertical coordinate, u]                       -> 1 field
 enum Form { FORM_CH_RES = 3, FORM_CH_JAC = 4, FORM_VP = 5, FORM_VP_RHS = 6, FORM_PP_RHS = 7, FORM_VU_RHS = 8,
             FORM_ENERGY = 9 };

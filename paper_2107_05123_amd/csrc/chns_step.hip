@@ -71,6 +71,7 @@ struct Stepper {
          *pj = nullptr;
   double *dMinv = nullptr, *cx = nullptr, *cr = nullptr, *cd = nullptr;  // Chebyshev solve with M
   double* vmask = nullptr;  // momentum multigrid preconditioner: masked input component
+  double* fch = nullptr;    // Cahn-Hilliard body-force vector [-M f_phi; M f_mu]
   double sc_scale = 0.0;  // dt / b of the Schur approximation
   double m_lmax = 0.0;    // Gershgorin bound of eig(D_M^-1 M)
 };
@@ -724,13 +725,13 @@ int schur_setup(Ctx& c, hipStream_t s) {
   return rc;
 }
 
-int newton_ch_impl(Ctx& c, const double* phi0, const double* mu0, const double* ut, const chns_step_opts& o,
-                   bool graphs, hipStream_t s, int* newton_it, int* lin_it, double* rfinal);
+int newton_ch_impl(Ctx& c, const double* phi0, const double* mu0, const double* ut, const double* fch,
+                   const chns_step_opts& o, bool graphs, hipStream_t s, int* newton_it, int* lin_it, double* rfinal);
 
 // the mass shift is the pressure operator's only while the Newton solve runs
-int newton_ch(Ctx& c, const double* phi0, const double* mu0, const double* ut, const chns_step_opts& o, bool graphs,
-              hipStream_t s, int* newton_it, int* lin_it, double* rfinal) {
-  const int rc = newton_ch_impl(c, phi0, mu0, ut, o, graphs, s, newton_it, lin_it, rfinal);
+int newton_ch(Ctx& c, const double* phi0, const double* mu0, const double* ut, const double* fch,
+              const chns_step_opts& o, bool graphs, hipStream_t s, int* newton_it, int* lin_it, double* rfinal) {
+  const int rc = newton_ch_impl(c, phi0, mu0, ut, fch, o, graphs, s, newton_it, lin_it, rfinal);
   if (c.pp_shift != 0.0) {
     c.pp_shift = 0.0;
     c.diag_valid = false;
@@ -739,8 +740,9 @@ int newton_ch(Ctx& c, const double* phi0, const double* mu0, const double* ut, c
   return rc;
 }
 
-int newton_ch_impl(Ctx& c, const double* phi0, const double* mu0, const double* ut, const chns_step_opts& o,
-                   bool graphs, hipStream_t s, int* newton_it, int* lin_it, double* rfinal) {
+// fch (nullable): body-force vector added to every residual (2n)
+int newton_ch_impl(Ctx& c, const double* phi0, const double* mu0, const double* ut, const double* fch,
+                   const chns_step_opts& o, bool graphs, hipStream_t s, int* newton_it, int* lin_it, double* rfinal) {
   Stepper& S = *c.step;
   const int64_t n = c.dm.n;
   const int dim = c.dm.dim;
@@ -753,6 +755,7 @@ int newton_ch_impl(Ctx& c, const double* phi0, const double* mu0, const double* 
   int rc;
   double rr = 0.0;
   if ((rc = launch_form(c, FORM_CH_RES, S.X, cf, S.R, s, plain))) return rc;
+  if (fch) k_add<<<g2, kT, 0, s>>>(S.R, fch, 2 * n);
   if ((rc = dot_sync(c, S.R, S.R, 2 * n, s, &rr))) return rc;
   const double r0 = std::sqrt(rr);
   double rn = r0;
@@ -793,6 +796,7 @@ int newton_ch_impl(Ctx& c, const double* phi0, const double* mu0, const double* 
     k_add<<<g2, kT, 0, s>>>(S.X, S.dX, 2 * n);
     CHNS_HIP(hipGetLastError());
     if ((rc = launch_form(c, FORM_CH_RES, S.X, cf, S.R, s, plain))) return rc;
+  if (fch) k_add<<<g2, kT, 0, s>>>(S.R, fch, 2 * n);
     if ((rc = dot_sync(c, S.R, S.R, 2 * n, s, &rr))) return rc;
     rn = std::sqrt(rr);
     ++it;
@@ -890,6 +894,7 @@ int assemble_impl(Ctx& c, int form, const double* const* fields, double* out, hi
   if (form >= CHNS_FORM_PP_RHS)
     for (int d = 0; d < dim; ++d) cf[k++] = fields[5] + d * n;
   if (form == CHNS_FORM_VU_RHS) cf[k++] = fields[6];
+  for (int d = 0; d < dim; ++d) cf[k++] = c.step->zero;  // no body force
   const int f = form == CHNS_FORM_VP_RHS ? FORM_VP_RHS : (form == CHNS_FORM_PP_RHS ? FORM_PP_RHS : FORM_VU_RHS);
   return launch_form(c, f, nullptr, cf, out, s, plain);
 }
@@ -968,13 +973,27 @@ int advance_step_body(Ctx& c, const chns_state& st, const chns_step_opts& o, chn
   if ((rc = copy(S.X + n, st.mu, n, s))) return rc;
   if ((rc = copy(S.pnew, st.p, n, s))) return rc;
   stats = chns_step_stats{};
+  // body forces of the Cahn-Hilliard system: R_phi -= M f_phi, R_mu += M f_mu
+  const double* fch = nullptr;
+  if (o.force_phi || o.force_mu) {
+    if (!S.fch && !(S.fch = (double*)c.dalloc(sizeof(double) * 2 * (size_t)n))) return CHNS_ENOMEM;
+    k_fill0<<<blocks_for(2 * n), kT, 0, s>>>(S.fch, 2 * n);
+    CHNS_HIP(hipGetLastError());
+    if (o.force_phi) {
+      if ((rc = launch_apply(c, CHNS_OP_MASS, CHNS_FP64, o.force_phi, S.tmp, s, plain))) return rc;
+      k_axpby<<<g1, kT, 0, s>>>(S.fch, -1.0, S.tmp, 0.0, S.tmp, n);
+    }
+    if (o.force_mu && (rc = launch_apply(c, CHNS_OP_MASS, CHNS_FP64, o.force_mu, S.fch + n, s, plain))) return rc;
+    CHNS_HIP(hipGetLastError());
+    fch = S.fch;
+  }
   for (int blk = 0; blk < o.blocks; ++blk) {
     // ---- Cahn-Hilliard with u~ = (u^k + u^{k+1}) / 2
     k_axpby<<<gv, kT, 0, s>>>(S.ut, 0.5, st.u, 0.5, S.unew, dim * n);
     CHNS_HIP(hipGetLastError());
     int nit = 0;
     double rfin = 0.0;
-    rc = newton_ch(c, st.phi, st.mu, S.ut, o, graphs, s, &nit, &stats.ch_iterations, &rfin);
+    rc = newton_ch(c, st.phi, st.mu, S.ut, fch, o, graphs, s, &nit, &stats.ch_iterations, &rfin);
     if (blk < 4) stats.newton_iterations[blk] = nit;
     stats.ch_residual = rfin;
     if (rc) return rc;
@@ -990,6 +1009,11 @@ int advance_step_body(Ctx& c, const chns_state& st, const chns_step_opts& o, chn
     for (int d = 0; d < dim; ++d) cf[k++] = S.uhat + d * n;
     for (int d = 0; d < dim; ++d) cf[k++] = st.u + d * n;
     cf[k++] = st.p;
+    // body force of the momentum equation after each form's own fields
+    auto force_at = [&](int k0) {
+      for (int d = 0; d < dim; ++d) cf[k0 + d] = o.force_v ? o.force_v + d * n : S.zero;
+    };
+    force_at(k);
     if ((rc = launch_form(c, FORM_VP_RHS, nullptr, cf, S.rhs, s, plain))) return rc;
     if ((rc = ensure_coef(c, &c.coef_mom))) return rc;
     if ((rc = copy(c.coef_mom, S.phit, n, s))) return rc;
@@ -1021,6 +1045,7 @@ int advance_step_body(Ctx& c, const chns_state& st, const chns_step_opts& o, chn
     if (rc) return rc;
     // ---- pressure Poisson with 1/rho(phi~)
     for (int d = 0; d < dim; ++d) cf[k++] = S.v + d * n;
+    force_at(k);
     if ((rc = launch_form(c, FORM_PP_RHS, nullptr, cf, S.rhs, s, plain))) return rc;
     chns_solve_opts po{};
     po.rtol = o.lin_rtol;
@@ -1037,6 +1062,7 @@ int advance_step_body(Ctx& c, const chns_state& st, const chns_step_opts& o, chn
     if (rc) return rc;
     // ---- velocity update: M_rho u^{k+1} = ...
     cf[k++] = S.pnew;
+    force_at(k);
     if ((rc = launch_form(c, FORM_VU_RHS, nullptr, cf, S.rhs, s, plain))) return rc;
     if ((rc = launch_diagonal(c, CHNS_OP_MASS_RHO, CHNS_FP64, S.dvu, true, s))) return rc;
     if ((rc = copy(S.unew, S.v, dim * n, s))) return rc;
