@@ -192,9 +192,14 @@ enum { CHNS_FP64 = 0, CHNS_FP32 = 1 };
 /* y = Op x, matrix-free: per leaf, gather (with hanging-node interpolation),
  * 2-point Gauss quadrature, and a conflict-free deterministic scatter-add
  * (transpose interpolation).  x and y: device, n_fields * n_nodes of the
- * precision's type; x and y must not alias.  CHNS_FP32 is available for
- * PRESSURE, MASS, MASS_RHO and MOMENTUM_SCALAR; MOMENTUM and CH_JACOBIAN are
- * FP64 only (CHNS_EINVAL).  Async.                                          */
+ * precision's type; x and y must not alias.  Every operator is available in
+ * CHNS_FP64 and CHNS_FP32; in FP32 the arithmetic and the fields are single
+ * precision (the phase field kept as 1 + phi so that rho(phi) keeps its
+ * relative accuracy near phi = -1; MOMENTUM and CH_JACOBIAN use FP32 copies
+ * of their coefficient fields, made on the first FP32 apply after each
+ * chns_set_coefficients).  ESTATE before chns_set_phase_field (PRESSURE,
+ * MASS_RHO, MOMENTUM_SCALAR) or chns_set_coefficients (MOMENTUM,
+ * CH_JACOBIAN).  Async.                                                     */
 int chns_apply_operator(chns_ctx* ctx, int op, int prec, const void* x, void* y, void* stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph

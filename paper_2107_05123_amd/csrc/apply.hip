@@ -14,6 +14,7 @@
 //     buffer, and a second pass (k_combine) adds the slots of every shared
 //     node in a fixed order, applying P^T for hanging entries.  No atomics:
 //     the result is bitwise reproducible.
+#include <algorithm>
 #include <mutex>
 
 #include "brick_geom.h"
@@ -253,86 +254,6 @@ __device__ __forceinline__ void el_ch_res(const double (*x)[1 << DIM], const dou
   }
 }
 
-template <int DIM>
-__device__ __forceinline__ void el_ch_jac(const double (*x)[1 << DIM], const double (*c)[1 << DIM], const Phys& P,
-                                          double gs, double w, double (*y)[1 << DIM]) {
-  constexpr int NC = 1 << DIM;
-  double pt[NC];
-#pragma unroll
-  for (int a = 0; a < NC; ++a) {
-    pt[a] = 0.5 * (c[0][a] + c[1][a]);
-    y[0][a] = 0.0;
-    y[1][a] = 0.0;
-  }
-#pragma unroll
-  for (int q = 0; q < NC; ++q) {
-    const double ptq = QP<DIM>::val(pt, q), dph = QP<DIM>::val(x[0], q), dmu = QP<DIM>::val(x[1], q);
-    double gdph[DIM], gdmu[DIM], fl[DIM], fm[DIM];
-    QP<DIM>::grad(x[0], q, gs, gdph);
-    QP<DIM>::grad(x[1], q, gs, gdmu);
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      const double ut = QP<DIM>::val(c[2 + d], q);
-      fl[d] = w * (-0.5 * ut * dph + gdmu[d] / (2.0 * P.Pe * P.Cn));
-      fm[d] = w * 0.5 * P.Cn * P.Cn * gdph[d];
-    }
-    const double fphi = w * dph / P.dt, fmu = w * (0.5 * d2psi(ptq) * dph - 0.5 * dmu);
-#pragma unroll
-    for (int a = 0; a < NC; ++a) {
-      double s0 = refN<DIM>(q, a) * fphi, s1 = refN<DIM>(q, a) * fmu;
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) {
-        const double gN = gs * refD<DIM>(q, a, d);
-        s0 += gN * fl[d];
-        s1 += gN * fm[d];
-      }
-      y[0][a] += s0;
-      y[1][a] += s1;
-    }
-  }
-}
-
-// velocity prediction operator, all DIM components (identical scalar operator)
-template <int DIM>
-__device__ __forceinline__ void el_vp(const double (*x)[1 << DIM], const double (*c)[1 << DIM], const Phys& P,
-                                      double gs, double w, double (*y)[1 << DIM]) {
-  constexpr int NC = 1 << DIM;
-  const double* uh[DIM];
-#pragma unroll
-  for (int d = 0; d < DIM; ++d) uh[d] = c[2 + d];
-#pragma unroll
-  for (int f = 0; f < DIM; ++f)
-#pragma unroll
-    for (int a = 0; a < NC; ++a) y[f][a] = 0.0;
-#pragma unroll
-  for (int q = 0; q < NC; ++q) {
-    MomQ<DIM> M;
-    M.init(P, c[0], c[1], uh, q, gs);
-    double sN[NC];
-#pragma unroll
-    for (int a = 0; a < NC; ++a) {
-      double gN[DIM];
-      gradN<DIM>(q, a, gs, gN);
-      sN[a] = M.s(P, gN);
-    }
-#pragma unroll
-    for (int f = 0; f < DIM; ++f) {
-      const double vq = QP<DIM>::val(x[f], q);
-      double gv[DIM];
-      QP<DIM>::grad(x[f], q, gs, gv);
-      const double rl = M.rlin(P, vq, gv);
-      const double fN = w * (M.rho * vq / P.dt + 0.5 * M.rho * M.dot(M.uh, gv) + M.dot(M.J, gv) / (2.0 * P.Pe));
-      const double fst = w * M.tau * rl;
-#pragma unroll
-      for (int a = 0; a < NC; ++a) {
-        double gN[DIM];
-        gradN<DIM>(q, a, gs, gN);
-        y[f][a] += refN<DIM>(q, a) * fN + w * M.eta * M.dot(gN, gv) / (2.0 * P.Re) + sN[a] * fst;
-      }
-    }
-  }
-}
-
 // right-hand sides: coefficient layout phi~, mu~, u^ (DIM), u^k (DIM), p^k,
 // then v (DIM) and p^{k+1}, and last the body force f_v (DIM; zero except for
 // manufactured solutions), which is the known right-hand side of the momentum
@@ -489,6 +410,235 @@ __device__ __forceinline__ void el_energy(const double (*c)[1 << DIM], const Phy
   for (int a = 0; a < NC; ++a) y[0][a] = e / NC;
 }
 
+// ---------------------------------------- heavy forms, corners read on demand
+// The Cahn-Hilliard Jacobian and the VMS momentum operator read many fields;
+// their element routines take the corner values through an accessor cv(f, a)
+// (field f, corner a) that reads the brick's LDS node layers, so that no
+// field is held in registers longer than it is used.
+//
+// Phase-field storage: FP64 fields hold phi, FP32 fields hold 1 + phi (so
+// that rho = (beta - alpha) + alpha (1 + phi) keeps its relative accuracy
+// near phi = -1 at large density ratios); PhaseT gives the pull-back range
+// and the mixture laws in the stored variable.
+template <typename T>
+struct PhaseT {
+  T lo, hi;          // range of the stored variable (phi* in [-1, 1])
+  T ra, rb, ea, eb;  // rho = ra s + rb, eta = ea s + eb with s the stored value
+};
+template <typename T>
+__device__ __forceinline__ PhaseT<T> phase_of(const Phys& P) {
+  PhaseT<T> f;
+  const bool shifted = sizeof(T) == 4;
+  f.lo = shifted ? T(0) : T(-1);
+  f.hi = shifted ? T(2) : T(1);
+  f.ra = T(P.alpha);
+  f.rb = T(shifted ? P.beta - P.alpha : P.beta);
+  f.ea = T(P.gam);
+  f.eb = T(shifted ? P.xi - P.gam : P.xi);
+  return f;
+}
+
+// Newton Jacobian of the discrete Cahn-Hilliard system (Def. 6), fields
+// x = [dphi, dmu] and coefficients [phi^{k+1}, phi^k, u~]:
+//   y_phi = M dphi / dt - 1/2 (grad q, u~ dphi) + K dmu / (2 Pe Cn)
+//   y_mu  = 1/2 (q, psi''(phi~) dphi) + Cn^2/2 K dphi - 1/2 M dmu
+// sum-factorised: values at the Gauss points by the two-point transforms,
+// the constant-coefficient stiffness K in closed form (3D: the Q1 element
+// matrix is (h/12)(5 I - 1 1^T + edge adjacency); 2D: (4 I - edge adjacency
+// - 2 opposite corner)/6), the advection flux through the transposed
+// gradient.  cv(f, a): f = 0 dphi, 1 dmu, 2 phi^{k+1}, 3 phi^k, 4.. u~.
+template <int DIM, typename T, class CV>
+__device__ __forceinline__ void el_chj(const CV& cv, const Phys& P, int lev, T (*y)[1 << DIM]) {
+  constexpr int NC = 1 << DIM, H = NC / 2;
+  const double h = ldexp(1.0, -lev);
+  // (2^d scaling of each transform) x (2^d of the transpose) folded into w
+  const T w = T(ldexp(1.0, -(lev + 1) * DIM - 2 * DIM));
+  const T inv2d = T(ldexp(1.0, -DIM));
+  // stiffness parts, corner form
+  {
+    T xp[NC], xm[NC];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+      xp[a] = cv(0, a);
+      xm[a] = cv(1, a);
+    }
+    const T kphi = T((DIM == 3 ? h / 12.0 : 1.0 / 6.0) * P.Cn * P.Cn * 0.5);
+    const T kmu = T((DIM == 3 ? h / 12.0 : 1.0 / 6.0) / (2.0 * P.Pe * P.Cn));
+    T sp = T(0), sm = T(0);
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+      sp += xp[a];
+      sm += xm[a];
+    }
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+      T kp, km;
+      if constexpr (DIM == 3) {
+        kp = T(5) * xp[a] - sp + (xp[a ^ 1] + xp[a ^ 2] + xp[a ^ 4]);
+        km = T(5) * xm[a] - sm + (xm[a ^ 1] + xm[a ^ 2] + xm[a ^ 4]);
+      } else {
+        kp = T(4) * xp[a] - (xp[a ^ 1] + xp[a ^ 2]) - T(2) * xp[a ^ 3];
+        km = T(4) * xm[a] - (xm[a ^ 1] + xm[a ^ 2]) - T(2) * xm[a ^ 3];
+      }
+      y[0][a] = kmu * km;
+      y[1][a] = kphi * kp;
+    }
+    // mass parts at the Gauss points (values scaled by 2^d)
+    all_stages<DIM>(xp);
+    all_stages<DIM>(xm);
+    T pt[NC];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) pt[a] = T(0.5) * (cv(2, a) + cv(3, a));
+    all_stages<DIM>(pt);
+    T fa[NC], fb[NC];
+    const T idt = T(1.0 / P.dt);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const T p = pt[q] * inv2d;
+      const T d2 = T(3) * p * p - T(1);
+      fa[q] = w * idt * xp[q];
+      fb[q] = w * T(0.5) * (d2 * xp[q] - xm[q]);
+    }
+    all_stages<DIM>(fa);
+    all_stages<DIM>(fb);
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+      y[0][a] += fa[a];
+      y[1][a] += fb[a];
+    }
+    // advection -1/2 (grad q, u~ dphi): flux F_d = -1/2 det J u~_d dphi at
+    // each Gauss point, then the transposed gradient (constant along d)
+    const T wa = T(-0.5 * ldexp(1.0, -(lev + 1) * DIM) * ldexp(1.0, lev) * ldexp(1.0, -2 * DIM - (DIM - 1)));
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      T u[NC];
+#pragma unroll
+      for (int a = 0; a < NC; ++a) u[a] = cv(4 + d, a);
+      all_stages<DIM>(u);
+      T g[H];
+#pragma unroll
+      for (int r = 0; r < H; ++r) {
+        const int lo = insert0(r, d), hi = lo | (1 << d);
+        g[r] = u[lo] * xp[lo] + u[hi] * xp[hi];
+      }
+      stage<H, 1>(g);
+      if constexpr (H > 2) stage<H, 2>(g);
+#pragma unroll
+      for (int r = 0; r < H; ++r) {
+        const int lo = insert0(r, d), hi = lo | (1 << d);
+        const T v = wa * g[r];
+        y[0][hi] += v;
+        y[0][lo] -= v;
+      }
+    }
+  }
+}
+
+// VMS velocity prediction (Def. 3, tau_m and R_m of Sec. 3.1), the same
+// scalar operator for every component.  Per Gauss point, with
+// b = u^/2 + J/(2 Pe rho~), g = grad eta~/(2 Re) and k = eta~/(2 Re):
+//   R_lin(v) = rho~ (v/dt + b.grad v) - g.grad v,
+//   Galerkin part  N_a rho~ (v/dt + b.grad v) + k grad N_a . grad v,
+//   stabilisation  (b.grad N_a) tau_m R_lin(v);
+// the coefficients are formed once per Gauss point and applied to the
+// components in turn.  cv(f, a): f < DIM the velocity components, then
+// phi~ (stored as in PhaseT), mu~, u^.
+template <int DIM, typename T, class CV>
+__device__ __forceinline__ void el_vp2(const CV& cv, const Phys& P, int lev, T (*y)[1 << DIM]) {
+  constexpr int NC = 1 << DIM;
+  const PhaseT<T> ph = phase_of<T>(P);
+  const T gs = T(ldexp(1.0, lev + 1));
+  const T w = T(ldexp(1.0, -(lev + 1) * DIM));
+  const T idt = T(1.0 / P.dt);
+  const T i2re = T(1.0 / (2.0 * P.Re));
+  const T cJ = T(P.cJ);
+  const T i2pe = T(1.0 / (2.0 * P.Pe));
+  const T gs2 = gs * gs;
+  const T tau_c = T(4.0 / (P.dt * P.dt));
+  const T visc_c = T(P.C_I * DIM) * gs2 * gs2;
+  const T rhope = T(1.0 / P.Pe);
+  const T ire = T(1.0 / P.Re);
+#pragma unroll
+  for (int f = 0; f < DIM; ++f)
+#pragma unroll
+    for (int a = 0; a < NC; ++a) y[f][a] = T(0);
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    // keep the LDS reads of each Gauss point after the previous one's
+    // arithmetic (bounds the registers held at once)
+    asm volatile("" ::: "memory");
+    // coefficient fields at q
+    T s = T(0), gph[DIM], gmu[DIM], uh[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) gph[d] = gmu[d] = uh[d] = T(0);
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+      const T n = T(refN<DIM>(q, a));
+      const T cp = cv(DIM, a), cm = cv(DIM + 1, a);
+      s += n * cp;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const T dn = T(refD<DIM>(q, a, d));
+        gph[d] += dn * cp;
+        gmu[d] += dn * cm;
+        uh[d] += n * cv(DIM + 2 + d, a);
+      }
+    }
+    const T sc = fmin(fmax(s, ph.lo), ph.hi);
+    const T rho = ph.ra * sc + ph.rb;
+    const T eta = ph.ea * sc + ph.eb;
+    const T inside = (s > ph.lo && s < ph.hi) ? T(1) : T(0);
+    const T irho = T(1) / rho;
+    T b[DIM], g[DIM], uu = T(0), uJ = T(0);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const T J = cJ * gs * gmu[d];
+      uu += uh[d] * uh[d];
+      uJ += uh[d] * J;
+      b[d] = T(0.5) * uh[d] + J * i2pe * irho;
+      g[d] = ph.ea * gs * gph[d] * inside * i2re;
+    }
+    const T r = eta * irho * ire;
+    const T tau = T(1) / sqrt(tau_c + gs2 * uu + gs2 * uJ * irho * rhope + visc_c * r * r);
+    const T k = eta * i2re;
+    // the components in turn
+#pragma unroll
+    for (int f = 0; f < DIM; ++f) {
+      asm volatile("" ::: "memory");
+      T v = T(0), gv[DIM];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) gv[d] = T(0);
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        const T xa = cv(f, a);
+        v += T(refN<DIM>(q, a)) * xa;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) gv[d] += T(refD<DIM>(q, a, d)) * xa;
+      }
+      T bg = T(0), gg = T(0);
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        gv[d] *= gs;
+        bg += b[d] * gv[d];
+        gg += g[d] * gv[d];
+      }
+      const T G = rho * (v * idt + bg);
+      const T S = tau * (G - gg);
+      T F[DIM];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) F[d] = w * (k * gv[d] + b[d] * S);
+      const T wG = w * G;
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        T t = T(refN<DIM>(q, a)) * wG;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) t += T(refD<DIM>(q, a, d)) * gs * F[d];
+        y[f][a] += t;
+      }
+    }
+  }
+}
+
 template <typename T, bool MASK>
 __device__ __forceinline__ T fetch(const T* v, const uint8_t* wall, int32_t i) {
   if constexpr (MASK) return wall[i] ? T(0) : v[i];
@@ -528,7 +678,11 @@ __device__ __forceinline__ void brick_body(const BrickArgs<T>& a) {
   constexpr int NL = DIM == 3 ? (B + 1) * (B + 1) : (B + 1);  // nodes per layer
   constexpr int KL = (NL + LPB - 1) / LPB;   // layer nodes handled per lane
   constexpr int NC = 1 << DIM, NH = NC / 2;
-  constexpr int RING = WHOLE ? B + 1 : 3;
+  // heavy forms read corners from LDS on demand; a two-layer ring suffices
+  // for them (the layer two ahead is stored after the barrier that ends the
+  // reads of the layer it replaces) and leaves LDS for two waves per SIMD
+  constexpr bool HEAVY = OP == K_VP || OP == K_CH_JAC;
+  constexpr int RING = WHOLE ? B + 1 : (HEAVY ? 2 : 3);
   __shared__ T lay[RING][BPB][NV][NL];
   // per-corner-type leaf contributions, indexed by the node they land on
   // (zero where no leaf of the brick lands): a node sums NH entries
@@ -684,7 +838,7 @@ __device__ __forceinline__ void brick_body(const BrickArgs<T>& a) {
 #pragma unroll
         for (int f = 0; f < NO; ++f) {
           a.y[f * a.n + e] = v[f];
-          if constexpr (NI == NO) {
+          if constexpr (NI == NO && !HEAVY) {
             if (a.partials) dot += (double)lay[buf][bl][f][p] * (double)v[f];
           }
         }
@@ -765,22 +919,36 @@ __device__ __forceinline__ void brick_body(const BrickArgs<T>& a) {
       for (int f = 0; f < NCF; ++f) cc[f][c + half * NH] = lay[buf][bl][NI + f][p];
     }
   };
-  if (active) read_half(0, 1);
+  if constexpr (!HEAVY) {
+    if (active) read_half(0, 1);
+  }
   constexpr int kUnroll = (OP == K_PP || OP == K_PPS || OP == K_VPS || OP == K_MASS) ? B : 1;
 #pragma unroll kUnroll
   for (int ez = 0; ez < B; ++ez) {
     load_emit_entries(ez);
     if (active) {
       T ye[NO][NC];
+      if constexpr (!HEAVY) {
 #pragma unroll
-      for (int c = 0; c < NH; ++c) {
+        for (int c = 0; c < NH; ++c) {
 #pragma unroll
-        for (int f = 0; f < NI; ++f) xc[f][c] = xc[f][c + NH];
+          for (int f = 0; f < NI; ++f) xc[f][c] = xc[f][c + NH];
 #pragma unroll
-        for (int f = 0; f < NCF; ++f) cc[f][c] = cc[f][c + NH];
+          for (int f = 0; f < NCF; ++f) cc[f][c] = cc[f][c + NH];
+        }
+        read_half(ez + 1, 1);
       }
-      read_half(ez + 1, 1);
-      if constexpr (OP == K_PP || OP == K_PPS) {
+      // corner a of field f (inputs first, then coefficients) from LDS
+      auto cv = [&](int f, int ca) -> T {
+        const int bx = ca & 1, by = DIM == 3 ? (ca >> 1) & 1 : 0, bz = (ca >> (DIM - 1)) & 1;
+        const int p = (ix + bx) + (DIM == 3 ? (iy + by) * (B + 1) : 0);
+        return lay[(ez + bz) % RING][bl][f][p];
+      };
+      if constexpr (OP == K_CH_JAC) {
+        el_chj<DIM, T>(cv, a.phys, lev, ye);
+      } else if constexpr (OP == K_VP) {
+        el_vp2<DIM, T>(cv, a.phys, lev, ye);
+      } else if constexpr (OP == K_PP || OP == K_PPS) {
         elem_pp<DIM, T>(xc[0], cc[0], A, Bc, ye[0]);
         if constexpr (OP == K_PPS) {
           T r[NC], ym[NC];
@@ -804,10 +972,6 @@ __device__ __forceinline__ void brick_body(const BrickArgs<T>& a) {
         for (int f = 0; f < NI; ++f) elem_mass_apply<DIM, T>(xc[f], r, ye[f]);
       } else if constexpr (OP == K_CH_RES) {
         el_ch_res<DIM>(xc, cc, a.phys, gs, wdet, ye);
-      } else if constexpr (OP == K_CH_JAC) {
-        el_ch_jac<DIM>(xc, cc, a.phys, gs, wdet, ye);
-      } else if constexpr (OP == K_VP) {
-        el_vp<DIM>(xc, cc, a.phys, gs, wdet, ye);
       } else if constexpr (OP == K_VP_RHS) {
         el_vp_rhs<DIM>(cc, a.phys, gs, wdet, ye);
       } else if constexpr (OP == K_PP_RHS) {
@@ -946,6 +1110,13 @@ __global__ __launch_bounds__(1024) void k_sum_partials(const double* partials, i
 // Wall rows of masked operators that no brick writes (all go through the
 // combine, which handles them); nothing else is needed here.
 
+// FP32 copy of coefficient fields; entries below `shifted` (the phase field
+// of the momentum operator) are stored as 1 + value
+__global__ void k_coef32(const double* src, float* dst, int64_t n, int64_t shifted) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (float)(i < shifted ? 1.0 + src[i] : src[i]);
+}
+
 // Diagonal probing helpers.
 // x = indicator of colour c in field `field` (every field when field < 0)
 template <typename T>
@@ -1076,8 +1247,8 @@ int apply_t(Ctx& c, const LevelView& L, const T* x, T* y, const T* const* cf, hi
   using TR = Traits<OP, DIM>;
   static_assert(TR::NCF <= kMaxCoef, "too many coefficient fields");
   const DevMesh& dm = *L.dm;
-  if (o.fuse_dot && TR::NI != TR::NO) {
-    set_error("fused dot needs as many inputs as outputs");
+  if (o.fuse_dot && (TR::NI != TR::NO || OP == K_VP || OP == K_CH_JAC)) {
+    set_error("fused dot needs as many inputs as outputs and a scalar-form operator");
     return CHNS_EINVAL;
   }
   if (o.sm_r && ((OP != K_PP && OP != K_PPS && OP != K_VPS) || o.fuse_dot || x == y)) {
@@ -1171,8 +1342,29 @@ int apply_dispatch(Ctx& c, const LevelView& L, int op, const T* x, T* y, const T
     }
   } else {
     if (op == CHNS_OP_MOMENTUM || op == CHNS_OP_CH_JACOBIAN) {
-      set_error("the momentum and Cahn-Hilliard operators are FP64 only");
-      return CHNS_EINVAL;
+      const bool mom = op == CHNS_OP_MOMENTUM;
+      const double* base = mom ? c.coef_mom : c.coef_chj;
+      if (!base || !(mom ? c.coef_mom_set : c.coef_chj_set)) {
+        set_error("chns_set_coefficients must be called for this operator first");
+        return CHNS_ESTATE;
+      }
+      // FP32 copies of the coefficient fields, refreshed after every change
+      // of the FP64 ones (the momentum phase field as 1 + phi)
+      const int64_t n = L.dm->n;
+      const int nf = 2 + L.dm->dim;
+      float*& c32 = mom ? c.coef_mom32 : c.coef_chj32;
+      bool& ok = mom ? c.coef_mom32_ok : c.coef_chj32_ok;
+      if (!c32 && !(c32 = (float*)c.dalloc(sizeof(float) * (size_t)nf * (size_t)n))) return CHNS_ENOMEM;
+      if (!ok) {
+        const int64_t tot = nf * n;
+        k_coef32<<<(unsigned)std::min<int64_t>((tot + 255) / 256, 65535), 256, 0, s>>>(base, c32, tot,
+                                                                                      mom ? n : 0);
+        CHNS_HIP(hipGetLastError());
+        ok = true;
+      }
+      const float* cf[kMaxCoef] = {};
+      for (int k = 0; k < nf; ++k) cf[k] = c32 + k * n;
+      return mom ? apply_d<K_VP, float>(c, L, x, y, cf, s, o) : apply_d<K_CH_JAC, float>(c, L, x, y, cf, s, o);
     }
   }
   set_error("operator not available");

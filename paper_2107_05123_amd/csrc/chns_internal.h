@@ -174,6 +174,11 @@ struct Ctx {
   double* coef_mom = nullptr;
   double* coef_chj = nullptr;
   bool coef_mom_set = false, coef_chj_set = false;
+  // FP32 copies for the FP32 applies (momentum phase field as 1 + phi~),
+  // refreshed lazily after the FP64 fields change
+  float* coef_mom32 = nullptr;
+  float* coef_chj32 = nullptr;
+  bool coef_mom32_ok = false, coef_chj32_ok = false;
 
   struct Stepper* step = nullptr;  // time-step work arrays (chns_step.hip)
   struct UNet* unet = nullptr;     // learned preconditioner (unet.hip)

@@ -776,6 +776,7 @@ int newton_ch_impl(Ctx& c, const double* phi0, const double* mu0, const double* 
     if ((rc = copy(c.coef_chj + n, phi0, n, s))) return rc;
     if ((rc = copy(c.coef_chj + 2 * n, ut, dim * n, s))) return rc;
     c.coef_chj_set = true;
+    c.coef_chj32_ok = false;
     for (int k = 6; k < 8; ++k) {
       if (!c.w64[k]) c.w64[k] = (double*)c.dalloc(sizeof(double) * n * 3);
       if (!c.w64[k]) return CHNS_ENOMEM;
@@ -842,6 +843,7 @@ int set_coefficients_impl(Ctx& c, int op, const double* const* fields, hipStream
   if ((rc = copy(*buf + n, fields[1], n, s))) return rc;
   if ((rc = copy(*buf + 2 * n, fields[2], dim * n, s))) return rc;
   (op == CHNS_OP_MOMENTUM ? c.coef_mom_set : c.coef_chj_set) = true;
+  (op == CHNS_OP_MOMENTUM ? c.coef_mom32_ok : c.coef_chj32_ok) = false;
   return CHNS_OK;
 }
 
@@ -1020,6 +1022,7 @@ int advance_step_body(Ctx& c, const chns_state& st, const chns_step_opts& o, chn
     if ((rc = copy(c.coef_mom + n, S.mut, n, s))) return rc;
     if ((rc = copy(c.coef_mom + 2 * n, S.uhat, dim * n, s))) return rc;
     c.coef_mom_set = true;
+    c.coef_mom32_ok = false;
     // phase field phi~ of the pressure solve (and of the momentum multigrid)
     if ((rc = launch_set_phase(c, S.X, st.phi, s))) return rc;
     const bool vpmg = o.vp_pc == CHNS_VP_PC_GMG;

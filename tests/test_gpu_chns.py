@@ -113,6 +113,10 @@ def test_ch_jacobian_apply_and_diagonal_match_oracle(case):
     ref = (J @ np.concatenate([c.o(d[0]), c.o(d[1])])).reshape(2, -1)
     _close(y[0], c.lib(ref[0]))
     _close(y[1], c.lib(ref[1]))
+    # FP32 apply (FP32 copies of the coefficient fields): FP32 rounding only
+    y32 = c.ctx.apply(c.ctx.CH_JACOBIAN, _dev(d.reshape(-1)).float()).cpu().numpy().astype(np.float64)
+    for f, r in enumerate(y32.reshape(2, -1)):
+        assert np.abs(r - c.lib(ref[f])).max() <= 2e-5 * np.abs(ref[f]).max()
     dg = c.ctx.diagonal(c.ctx.CH_JACOBIAN).cpu().numpy().reshape(2, -1)
     dref = J.diagonal().reshape(2, -1)
     _close(dg[0], c.lib(dref[0]))
@@ -128,6 +132,10 @@ def test_momentum_apply_and_diagonal_match_oracle(case):
     A = chns.vp_matrix(c.el, c.prm, c.qpstate(phit, mut, uhat))
     for i in range(c.dim):
         _close(y[i], c.lib(A @ c.o(c.v[i])))
+    y32 = c.ctx.apply(c.ctx.MOMENTUM, _dev(c.v.reshape(-1)).float()).cpu().numpy().astype(np.float64)
+    for i, r in enumerate(y32.reshape(c.dim, -1)):
+        ref = c.lib(A @ c.o(c.v[i]))
+        assert np.abs(r - ref).max() <= 2e-5 * np.abs(ref).max()
     dg = c.ctx.diagonal(c.ctx.MOMENTUM).cpu().numpy().reshape(c.dim, -1)
     for i in range(c.dim):
         _close(dg[i], c.lib(A.diagonal()))
