@@ -96,3 +96,26 @@ def rhs_field(x: np.ndarray, amps: np.ndarray, waves: np.ndarray) -> np.ndarray:
 def unit_coords(ijk: np.ndarray, max_level: int) -> np.ndarray:
     """Integer node coordinates (units of 2^-max_level) to unit-domain floats."""
     return np.asarray(ijk, dtype=np.float64) / float(1 << max_level)
+
+
+# ---- incomplete (carved) octree: the paper's 3D Rayleigh-Taylor column
+# The 1 x 8 x 1 box is the part x < 1/8, z < 1/8 of the unit root cube
+# (carve level 3, extent (1, 8, 1)); physical lengths are 8 x unit ones.
+RT_CARVE_LEVEL = 3
+RT_EXTENT = (1, 8, 1)
+
+
+def phi_rt(x: np.ndarray, cn: float, l: float = 6.0, amp: float = 0.05) -> np.ndarray:
+    """phi = tanh(sqrt2 (x2 - l - g(x)) / Cn), g = amp (cos 2 pi x1 + cos 2 pi x3)
+    in physical units (unit coordinates x times 8); 2D: g = amp cos 2 pi x1."""
+    X = 8.0 * np.asarray(x, dtype=np.float64)
+    g = amp * np.cos(2 * np.pi * X[:, 0])
+    if X.shape[1] == 3:
+        g = g + amp * np.cos(2 * np.pi * X[:, 2])
+    return np.tanh(SQRT2 * (X[:, 1] - l - g) / cn)
+
+
+def rt_slab_meets(lo_y: float, hi_y: float, width: float, l: float = 6.0) -> bool:
+    """Refinement predicate of the Rayleigh-Taylor meshes: the octant's
+    vertical extent (unit coordinates) meets the slab |8 y - l| <= width."""
+    return 8.0 * lo_y <= l + width and 8.0 * hi_y >= l - width

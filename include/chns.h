@@ -70,6 +70,16 @@ typedef struct chns_mesh_spec {
   /* largest brick edge (8, 4, 2 or 1 leaves); 0 = automatic: the largest
    * edge that still gives >= 1024 bricks, so small meshes keep the GPU busy */
   int brick_max;
+  /* Incomplete (carved) octree (paper Sec. 4: traversals visit only the
+   * octants that exist, so the domain can be a union of octants; Sec. 5.4
+   * runs in a 1 x 8 x 1 box): carve_level = 0 keeps the whole unit cube;
+   * otherwise only the octants inside the box [0, extent[d] 2^-carve_level]
+   * per direction d exist (extent[2] unused in 2D).  Needs
+   * 1 <= carve_level <= min_level and 1 <= extent[d] <= 2^carve_level.  The
+   * velocity walls are the faces of the box; phi, mu and the pressure keep
+   * natural conditions there.                                              */
+  int carve_level;
+  int32_t extent[3];
 } chns_mesh_spec;
 
 typedef struct chns_mesh chns_mesh;
@@ -77,7 +87,8 @@ typedef struct chns_mesh chns_mesh;
 typedef struct chns_mesh_info {
   int dim, max_level;
   int node_order;        /* 0 = lexicographic (x fastest; uniform meshes), 1 = Morton */
-  int uniform;           /* 1 if every leaf has the same level               */
+  int uniform;           /* 1 if the mesh is the whole cube with every leaf at
+                            max_level                                         */
   int64_t n_elems;       /* leaves                                           */
   int64_t n_nodes;       /* independent nodes = vector length                */
   int64_t n_hanging;     /* hanging (constrained) nodes                      */
@@ -87,6 +98,8 @@ typedef struct chns_mesh_info {
   int64_t n_shared;      /* nodes completed by the deterministic combine pass */
   int n_colors;          /* node colours used to probe the exact diagonal    */
   int64_t level_counts[17];
+  int32_t box[3];        /* domain box in units of 2^-max_level (2^max_level
+                            per direction for the whole cube)                 */
 } chns_mesh_info;
 
 /* Build a 2:1 vertex-balanced octree on the unit cube/square, enumerate its

@@ -153,7 +153,7 @@ class Elems:
 
     def wall(self):
         c = self.m.indep_coords()
-        return np.any((c == 0) | (c == self.m.side), axis=1)
+        return np.any((c == 0) | (c == self.m.box[None, :]), axis=1)
 
 
 # ----------------------------------------------------------------- Cahn-Hilliard

@@ -49,6 +49,7 @@ class OracleMesh:
     indep: np.ndarray = None          # (N_ind,) indices into `nodes` of independent nodes
     P: sp.csr_matrix = None           # (N_all, N_ind) hanging interpolation
     extra: dict = field(default_factory=dict)
+    box_hi: np.ndarray = None         # (dim,) domain box in units of 2^-max_level; None: whole cube
 
     @property
     def n_elems(self) -> int:
@@ -69,6 +70,11 @@ class OracleMesh:
     def indep_coords(self) -> np.ndarray:
         return self.nodes[self.indep]
 
+    @property
+    def box(self) -> np.ndarray:
+        """Upper corner of the domain box (integer units of 2^-max_level)."""
+        return np.full(self.dim, self.side, dtype=np.int64) if self.box_hi is None else self.box_hi
+
 
 # ---------------------------------------------------------------- refinement
 def box_meets_shell(lo: np.ndarray, hi: np.ndarray, centre, r_in: float, r_out: float) -> bool:
@@ -88,15 +94,20 @@ def box_meets_shell(lo: np.ndarray, hi: np.ndarray, centre, r_in: float, r_out: 
     return True
 
 
-def refine_top_down(dim: int, min_level: int, max_level: int, predicate=None):
+def refine_top_down(dim: int, min_level: int, max_level: int, predicate=None, box=None):
     """Leaves of the tree refined to min_level everywhere and, where the
-    predicate(level, lo, hi) holds, further down to max_level."""
+    predicate(level, lo, hi) holds, further down to max_level.  box: the
+    domain of an incomplete (carved) octree in unit coordinates, a union of
+    octants no finer than min_level; octants whose lower corner lies outside
+    it do not exist (paper Sec. 4: traversals visit only existing octants)."""
     side = 1 << max_level
     out_level, out_anchor = [], []
     stack = [(0, (0,) * dim)]
     while stack:
         lev, anc = stack.pop()
         size = side >> lev
+        if box is not None and lev >= min_level and any(a / side >= b for a, b in zip(anc, box)):
+            continue
         refine = lev < min_level
         if not refine and lev < max_level and predicate is not None:
             lo = np.array(anc, dtype=np.float64) / side
@@ -140,10 +151,12 @@ class _Locator:
         return res
 
 
-def balance_2to1(level, anchor, max_level):
-    """Vertex 2:1 balance by repeated refinement of too-coarse neighbours."""
+def balance_2to1(level, anchor, max_level, box_hi=None):
+    """Vertex 2:1 balance by repeated refinement of too-coarse neighbours
+    (neighbours only inside the domain box, integer units)."""
     dim = anchor.shape[1]
     side = 1 << max_level
+    hi2 = 2 * (np.full(dim, side) if box_hi is None else np.asarray(box_hi))
     dirs = np.array([d for d in itertools.product((-1, 0, 1), repeat=dim) if any(d)], dtype=np.int64)
     while True:
         loc = _Locator(level, anchor, max_level)
@@ -152,7 +165,7 @@ def balance_2to1(level, anchor, max_level):
         for d in dirs:
             # centre of the same-size neighbour in direction d, doubled coordinates
             c2 = 2 * anchor + (2 * d[None, :] + 1) * size[:, None]
-            inside = np.all((c2 > 0) & (c2 < 2 * side), axis=1)
+            inside = np.all((c2 > 0) & (c2 < hi2[None, :]), axis=1)
             src = np.nonzero(inside)[0]
             nb = loc.locate(c2[src])
             too_coarse = level[nb] < level[src] - 1
@@ -202,9 +215,10 @@ def enumerate_nodes(mesh: OracleMesh) -> OracleMesh:
     loc = _Locator(mesh.level, mesh.anchor, L)
     n_all = nodes.shape[0]
     hang_leaf = np.full(n_all, -1, dtype=np.int64)
+    hi2 = 2 * mesh.box
     for o in itertools.product((-1, 1), repeat=dim):
         p2 = 2 * nodes + np.array(o)[None, :]
-        inside = np.all((p2 > 0) & (p2 < 2 * side), axis=1)
+        inside = np.all((p2 > 0) & (p2 < hi2[None, :]), axis=1)
         src = np.nonzero(inside)[0]
         leaf = loc.locate(p2[src])
         rel = nodes[src] - mesh.anchor[leaf]
@@ -251,21 +265,30 @@ def uniform(dim: int, level: int) -> OracleMesh:
     return enumerate_nodes(m)
 
 
-def from_predicate(dim: int, min_level: int, max_level: int, predicate) -> OracleMesh:
-    lev, anc = refine_top_down(dim, min_level, max_level, predicate)
-    lev, anc = balance_2to1(lev, anc, max_level)
-    m = OracleMesh(dim=dim, max_level=max_level, level=lev, anchor=anc)
+def from_predicate(dim: int, min_level: int, max_level: int, predicate, box=None) -> OracleMesh:
+    """box: optional carved domain [0, box[d]] (unit coordinates, a union of
+    octants no finer than min_level)."""
+    lev, anc = refine_top_down(dim, min_level, max_level, predicate, box)
+    box_hi = None if box is None else np.array([round(b * (1 << max_level)) for b in box], dtype=np.int64)
+    lev, anc = balance_2to1(lev, anc, max_level, box_hi)
+    m = OracleMesh(dim=dim, max_level=max_level, level=lev, anchor=anc, box_hi=box_hi)
     return enumerate_nodes(m)
 
 
-def sphere_band(dim: int, min_level: int, max_level: int, centre, radius: float, band: float) -> OracleMesh:
+def sphere_band(dim: int, min_level: int, max_level: int, centre, radius: float, band: float,
+                box=None) -> OracleMesh:
     """Refine to max_level every octant meeting radius-band <= |x-c| <= radius+band."""
     c = np.asarray(centre, dtype=np.float64)[:dim]
 
     def pred(lev, lo, hi):
         return box_meets_shell(lo, hi, c, radius - band, radius + band)
 
-    return from_predicate(dim, min_level, max_level, pred)
+    return from_predicate(dim, min_level, max_level, pred, box)
+
+
+def carved_uniform(dim: int, level: int, box) -> OracleMesh:
+    """Every leaf at `level` inside the box (an incomplete octree)."""
+    return from_predicate(dim, level, level, None, box)
 
 
 def from_leaves(dim: int, max_level: int, level, anchor) -> OracleMesh:

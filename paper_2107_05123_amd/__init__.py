@@ -42,7 +42,7 @@ class Mesh:
     nodes, hanging constraints and brick decomposition (built on the host)."""
 
     def __init__(self, dim=3, min_level=0, max_level=5, rule="uniform", centres=None, radii=None,
-                 band=0.0, refine=None, brick_max=0):
+                 band=0.0, refine=None, brick_max=0, carve_level=0, extent=(0, 0, 0)):
         lib = L.lib()
         spec = L.MeshSpec()
         spec.dim, spec.min_level, spec.max_level = dim, min_level, max_level
@@ -59,6 +59,9 @@ class Mesh:
             spec.radii = r.ctypes.data_as(C.POINTER(C.c_double))
         spec.band = band
         spec.brick_max = int(brick_max)
+        spec.carve_level = int(carve_level)
+        for d, e in enumerate(tuple(extent)[:3]):
+            spec.extent[d] = int(e)
         if refine is not None:
             def _cb(anchor, level, user):
                 return int(bool(refine([anchor[i] for i in range(3)], level)))
@@ -137,7 +140,8 @@ class Mesh:
         return {"dim": i.dim, "max_level": i.max_level, "uniform": bool(i.uniform), "n_elems": i.n_elems,
                 "n_nodes": i.n_nodes, "n_hanging": i.n_hanging, "n_bricks": list(i.n_bricks),
                 "elems_in_bricks": list(i.elems_in_bricks), "n_slots": i.n_slots, "n_shared": i.n_shared,
-                "n_colors": i.n_colors, "level_counts": {l: c for l, c in enumerate(i.level_counts) if c}}
+                "n_colors": i.n_colors, "level_counts": {l: c for l, c in enumerate(i.level_counts) if c},
+                "box": list(i.box)[:self.dim]}
 
     def __del__(self):
         # only attributes of the object itself: module globals may already be

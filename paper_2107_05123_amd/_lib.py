@@ -25,6 +25,7 @@ class MeshSpec(C.Structure):
         ("dim", C.c_int), ("min_level", C.c_int), ("max_level", C.c_int), ("rule", C.c_int),
         ("n_spheres", C.c_int), ("centres", C.POINTER(C.c_double)), ("radii", C.POINTER(C.c_double)),
         ("band", C.c_double), ("refine", REFINE_CB), ("user", C.c_void_p), ("brick_max", C.c_int),
+        ("carve_level", C.c_int), ("extent", C.c_int32 * 3),
     ]
 
 
@@ -34,6 +35,7 @@ class MeshInfo(C.Structure):
         ("n_elems", C.c_int64), ("n_nodes", C.c_int64), ("n_hanging", C.c_int64),
         ("n_bricks", C.c_int64 * 4), ("elems_in_bricks", C.c_int64 * 4), ("n_slots", C.c_int64),
         ("n_shared", C.c_int64), ("n_colors", C.c_int), ("level_counts", C.c_int64 * 17),
+        ("box", C.c_int32 * 3),
     ]
 
 

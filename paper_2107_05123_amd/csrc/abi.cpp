@@ -196,6 +196,7 @@ int chns_mesh_info_get(const chns_mesh* mesh, chns_mesh_info* out) {
   out->n_colors = m.n_colors;
   for (auto l : m.leaf_level)
     if (l >= 0 && l <= 16) out->level_counts[(int)l]++;
+  for (int d = 0; d < 3; ++d) out->box[d] = m.box_hi[d];
   return CHNS_OK;
 }
 

@@ -21,6 +21,7 @@
 // launch, a combine launch and an update launch: on levels of a few
 // thousand nodes every launch costs the same few microseconds, whatever its
 // size.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <utility>
@@ -965,7 +966,8 @@ void reference_tables(int dim, std::vector<double>& tg, std::vector<double>& tp,
 int mg_build(Ctx& c) {
   if (c.mg) return CHNS_OK;
   const HostMesh& f = *c.host;
-  const int coarsest = 1;
+  // a carved octree keeps its domain only down to the carve level
+  const int coarsest = std::max(1, f.carve_level);
   auto* mg = new Multigrid();
   mg->lv.resize(1);
   std::string msg;
@@ -975,7 +977,7 @@ int mg_build(Ctx& c) {
     std::vector<int8_t> lev;
     std::vector<int32_t> anc;
     truncate_leaves(*finer, k, lev, anc);
-    int rc = build_host_mesh_from_leaves(f.dim, k, lev, anc, L.host, msg);
+    int rc = build_host_mesh_from_leaves(f.dim, k, lev, anc, L.host, msg, &f);
     if (rc) {
       delete mg;
       set_error("multigrid level: " + msg);

@@ -166,8 +166,21 @@ struct Builder {
   int32_t side;
   int nc;  // corners per leaf
 
+  int32_t box_hi[3];  // domain box (units of 2^-L)
+  bool carved;
+
   Builder(const chns_mesh_spec& s, HostMesh& mm, std::string& e)
-      : sp(s), m(mm), msg(e), dim(s.dim), L(s.max_level), side(1 << s.max_level), nc(1 << s.dim) {}
+      : sp(s), m(mm), msg(e), dim(s.dim), L(s.max_level), side(1 << s.max_level), nc(1 << s.dim) {
+    carved = s.carve_level > 0;
+    for (int d = 0; d < 3; ++d)
+      box_hi[d] = (carved && d < dim && s.carve_level <= L) ? (s.extent[d] << (L - s.carve_level)) : side;
+  }
+  // octant (level lev, anchor a) lies outside the domain box
+  bool outside(const int32_t* a) const {
+    for (int d = 0; d < dim; ++d)
+      if (a[d] >= box_hi[d]) return true;
+    return false;
+  }
 
   int32_t size_at(int lev) const { return side >> lev; }
 
@@ -210,6 +223,9 @@ struct Builder {
     while (!stack.empty()) {
       Item it = stack.back();
       stack.pop_back();
+      // carved octree: octants at or below the carve level lie wholly inside
+      // or outside the box; the outside ones do not exist
+      if (carved && it.lev >= sp.carve_level && outside(it.a)) continue;
       if (predicate(it.lev, it.a)) {
         int32_t h = size_at(it.lev + 1);
         // push children in reverse Morton order so that they pop in Morton order
@@ -262,7 +278,7 @@ struct Builder {
             tt /= 3;
             if (dir[d]) zero = false;
             N[d] = P[d] + dir[d] * sP;
-            if (N[d] < 0 || N[d] >= side) inside = false;
+            if (N[d] < 0 || N[d] >= box_hi[d]) inside = false;
           }
           if (zero || !inside) continue;
           // exactly one leaf contains the point N: probe level l-1 first,
@@ -399,7 +415,7 @@ struct Builder {
         bool ok = true;
         for (int d = 0; d < dim; ++d) {
           if ((o >> d) & 1) {
-            if (c[d] >= side) ok = false;
+            if (c[d] >= box_hi[d]) ok = false;
             a[d] = (c[d] / S2) * S2;
           } else {
             if (c[d] <= 0) ok = false;
@@ -748,9 +764,24 @@ struct Builder {
       msg = "unknown rule";
       return CHNS_EINVAL;
     }
+    if (carved) {
+      bool ok = sp.carve_level <= sp.min_level && sp.carve_level <= L && sp.carve_level <= 16;
+      for (int d = 0; d < dim && ok; ++d) ok = sp.extent[d] >= 1 && sp.extent[d] <= (1 << sp.carve_level);
+      if (!ok) {
+        msg = "carved octree needs 1 <= carve_level <= min_level and 1 <= extent[d] <= 2^carve_level";
+        return CHNS_EINVAL;
+      }
+    } else if (sp.carve_level < 0) {
+      msg = "carve_level must not be negative";
+      return CHNS_EINVAL;
+    }
     m.dim = dim;
     m.max_level = L;
     refine(m.leaf_level, m.leaf_anchor);
+    if (m.leaf_level.empty()) {
+      msg = "no octant inside the domain";
+      return CHNS_EINVAL;
+    }
     return finish();
   }
 
@@ -772,7 +803,11 @@ struct Builder {
       lmin = std::min<int>(lmin, l);
       lmax = std::max<int>(lmax, l);
     }
-    m.uniform = lmin == lmax && lmax == L;
+    // "uniform" means the whole cube at one level: the structured kernels,
+    // the stencil multigrid levels and the network grid rely on it
+    m.uniform = lmin == lmax && lmax == L && !carved;
+    m.carve_level = carved ? sp.carve_level : 0;
+    for (int d = 0; d < 3; ++d) m.box_hi[d] = d < dim ? box_hi[d] : 0;
     m.node_order = m.uniform ? 0 : 1;
     std::vector<int32_t> elem_corner, all_entry, all_coords;
     int rc = nodes(elem_corner, all_entry, all_coords);
@@ -787,7 +822,7 @@ struct Builder {
     for (int64_t i = 0; i < m.n_indep; ++i)
       for (int d = 0; d < dim; ++d) {
         int32_t c = m.indep_coords[3 * i + d];
-        if (c == 0 || c == side) m.wall[i] = 1;
+        if (c == 0 || c == box_hi[d]) m.wall[i] = 1;
       }
     return CHNS_OK;
   }
@@ -796,13 +831,22 @@ struct Builder {
 }  // namespace
 
 int build_host_mesh_from_leaves(int dim, int max_level, const std::vector<int8_t>& level,
-                                const std::vector<int32_t>& anchor, HostMesh& m, std::string& msg) {
+                                const std::vector<int32_t>& anchor, HostMesh& m, std::string& msg,
+                                const HostMesh* like) {
   try {
     chns_mesh_spec sp{};
     sp.dim = dim;
     sp.min_level = 0;
     sp.max_level = max_level;
     sp.rule = CHNS_RULE_UNIFORM;
+    if (like && like->carve_level > 0) {
+      if (max_level < like->carve_level) {
+        msg = "a level of a carved octree must not be coarser than its carve level";
+        return CHNS_EINVAL;
+      }
+      sp.carve_level = like->carve_level;
+      for (int d = 0; d < dim; ++d) sp.extent[d] = like->box_hi[d] >> (like->max_level - like->carve_level);
+    }
     Builder b(sp, m, msg);
     m.leaf_level = level;
     m.leaf_anchor = anchor;
@@ -993,7 +1037,6 @@ int build_transfer(const HostMesh& fine, const HostMesh& coarse, Transfer& t, st
     return CHNS_EINVAL;
   }
   const int Lc = coarse.max_level;
-  const int32_t side_f = 1 << fine.max_level;
   const int nc = 1 << dim;
   KeySet leaves((size_t)coarse.n_elems() * 2);
   for (int64_t e = 0; e < coarse.n_elems(); ++e)
@@ -1010,7 +1053,7 @@ int build_transfer(const HostMesh& fine, const HostMesh& coarse, Transfer& t, st
         for (int mlev = Lc; mlev >= 0 && found < 0; --mlev) {
           sf = 1 << (fine.max_level - mlev);  // coarse octant edge in fine units
           for (int d = 0; d < dim; ++d) {
-            const int32_t q2 = 2 * x[d] + (x[d] < side_f ? 1 : -1);  // doubled, nudged inside
+            const int32_t q2 = 2 * x[d] + (x[d] < fine.box_hi[d] ? 1 : -1);  // doubled, nudged inside
             af[d] = (q2 / (2 * sf)) * sf;
             ac[d] = af[d] / 2;
           }
@@ -1154,6 +1197,14 @@ int build_host_mesh_remesh(const HostMesh& old, const double* phi, int min_level
     sp.dim = old.dim;
     sp.min_level = min_level;
     sp.max_level = old.max_level;
+    if (old.carve_level > 0) {
+      if (min_level < old.carve_level) {
+        msg = "remesh of a carved octree needs min_level >= its carve level";
+        return CHNS_EINVAL;
+      }
+      sp.carve_level = old.carve_level;
+      for (int d = 0; d < old.dim; ++d) sp.extent[d] = old.box_hi[d] >> (old.max_level - old.carve_level);
+    }
     sp.rule = CHNS_RULE_CALLBACK;
     sp.refine = band_refine;
     sp.user = &q;
@@ -1173,7 +1224,6 @@ int build_interp(const HostMesh& src, const HostMesh& dst, std::vector<int32_t>&
   }
   try {
     const int dim = src.dim, L = src.max_level;
-    const int32_t side = 1 << L;
     const int nc = 1 << dim;
     KeySet leaves((size_t)src.n_elems() * 2);
     for (int64_t e = 0; e < src.n_elems(); ++e)
@@ -1190,7 +1240,7 @@ int build_interp(const HostMesh& src, const HostMesh& dst, std::vector<int32_t>&
           for (int lev = L; lev >= 0 && found < 0; --lev) {
             sf = 1 << (L - lev);
             for (int d = 0; d < dim; ++d) {
-              const int32_t q2 = 2 * x[d] + (x[d] < side ? 1 : -1);
+              const int32_t q2 = 2 * x[d] + (x[d] < dst.box_hi[d] ? 1 : -1);
               af[d] = (q2 / (2 * sf)) * sf;
             }
             if (leaves.contains(leaf_key(dim, lev, af))) found = lev;

@@ -59,15 +59,22 @@ struct HostMesh {
   std::vector<uint8_t> color;  // n_indep
   // Dirichlet wall mask (1 on the domain boundary)
   std::vector<uint8_t> wall;   // n_indep
+  // domain: the box [0, box_hi[d]] (units of 2^-max_level); the whole cube
+  // unless the octree is carved (carve_level > 0: the box is a union of
+  // level-carve_level octants)
+  int carve_level = 0;
+  int32_t box_hi[3] = {0, 0, 0};
 
   int64_t n_elems() const { return (int64_t)leaf_level.size(); }
 };
 
 // Build everything from a spec; returns CHNS_OK or an error with msg set.
 int build_host_mesh(const chns_mesh_spec& spec, HostMesh& m, std::string& msg);
-// Build from an explicit leaf list (levels and anchors in units of 2^-max_level).
+// Build from an explicit leaf list (levels and anchors in units of 2^-max_level)
+// inside the domain of `like` (its carving, rescaled to this max_level).
 int build_host_mesh_from_leaves(int dim, int max_level, const std::vector<int8_t>& level,
-                                const std::vector<int32_t>& anchor, HostMesh& m, std::string& msg);
+                                const std::vector<int32_t>& anchor, HostMesh& m, std::string& msg,
+                                const HostMesh* like = nullptr);
 // Leaves of `fine` with every leaf deeper than k replaced by its level-k
 // ancestor, in units of 2^-k (truncation keeps 2:1 balance).
 void truncate_leaves(const HostMesh& fine, int k, std::vector<int8_t>& level, std::vector<int32_t>& anchor);
