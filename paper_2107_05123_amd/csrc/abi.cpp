@@ -80,51 +80,6 @@ Ctx::~Ctx() {
   if (flag_host) (void)hipHostFree(flag_host);
 }
 
-template <typename T>
-static int upload(Ctx& c, T** dst, const std::vector<T>& src) {
-  *dst = (T*)c.dalloc(sizeof(T) * (src.empty() ? 1 : src.size()));
-  if (!*dst) return CHNS_ENOMEM;
-  if (!src.empty()) CHNS_HIP(hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice));
-  return CHNS_OK;
-}
-
-static int upload_mesh(Ctx& c) {
-  const HostMesh& m = *c.host;
-  DevMesh& d = c.dm;
-  d.dim = m.dim;
-  d.max_level = m.max_level;
-  d.n = m.n_indep;
-  d.n_hanging = m.n_hanging;
-  d.n_slots = m.n_slots;
-  d.n_colors = m.n_colors;
-  d.side = 1 << m.max_level;
-  // structured kernels address nodes with 32-bit offsets
-  d.structured = m.uniform && m.node_order == 0 && m.n_hanging == 0 && m.n_indep < ((int64_t)1 << 31);
-  int rc;
-  for (int k = 0; k < kBrickClasses; ++k) {
-    const BrickClass& h = m.cls[k];
-    DevBrickClass& b = d.cls[k];
-    b.B = h.B;
-    b.count = h.count;
-    b.npb = h.nodes_per_brick;
-    b.nbnd = h.bnd_per_brick;
-    b.slot_base = h.slot_base;
-    if ((rc = upload(c, &b.table, h.table))) return rc;
-    if ((rc = upload(c, &b.level, h.level))) return rc;
-    std::vector<int16_t> r(h.rank.begin(), h.rank.end());
-    if ((rc = upload(c, &b.rank, r))) return rc;
-    if ((rc = upload(c, &b.anchor, h.anchor))) return rc;
-  }
-  if ((rc = upload(c, &d.hang_par, m.hang_parents))) return rc;
-  d.n_comb = (int64_t)m.comb_node.size();
-  if ((rc = upload(c, &d.comb_node, m.comb_node))) return rc;
-  if ((rc = upload(c, &d.comb_ptr, m.comb_ptr))) return rc;
-  if ((rc = upload(c, &d.comb_ent, m.comb_ent))) return rc;
-  if ((rc = upload(c, &d.color, m.color))) return rc;
-  if ((rc = upload(c, &d.wall, m.wall))) return rc;
-  return CHNS_OK;
-}
-
 }  // namespace chns
 
 using namespace chns;
@@ -375,7 +330,7 @@ int chns_context_create(chns_mesh* mesh, const chns_params* params, chns_ctx** o
     delete h;
     return CHNS_EHIP;
   }
-  rc = upload_mesh(c);
+  rc = upload_dm(c, *c.host, c.dm);
   const int64_t n = c.dm.n;
   if (!rc) {
     c.phi64 = (double*)c.dalloc(sizeof(double) * n);

@@ -661,6 +661,18 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// The hardware deals workgroups round-robin to the 8 XCDs (block b runs on
+// XCD b % 8), each with its own L2.  Bricks are numbered along the Morton
+// curve, so handing XCD x the contiguous run of brick groups
+// [start(x), start(x) + count(x)) keeps the node layers that neighbouring
+// bricks share in one L2.  A bijection for any grid size.
+__device__ __forceinline__ uint32_t xcd_block() {
+  constexpr uint32_t kXcd = 8;
+  const uint32_t g = gridDim.x, b = blockIdx.x;
+  const uint32_t per = g / kXcd, rem = g % kXcd, x = b % kXcd;
+  return x * per + (x < rem ? x : rem) + b / kXcd;
+}
+
 // One wavefront = BPB bricks; one lane = one leaf column of a brick, marching
 // along the last axis.  WHOLE: every node of the brick is gathered into LDS
 // up front (all loads in flight together); otherwise a three-layer LDS ring
@@ -689,7 +701,7 @@ __device__ __forceinline__ void brick_body(const BrickArgs<T>& a) {
   __shared__ T accn[BPB][NO][NH][NL];
   if (a.done && *a.done) return;
   const int lane = threadIdx.x, bl = lane / LPB, ll = lane % LPB;
-  const int64_t brick = (int64_t)blockIdx.x * BPB + bl;
+  const int64_t brick = (int64_t)xcd_block() * BPB + bl;
   const bool active = brick < a.count;
   const int ix = ll % B, iy = DIM == 3 ? ll / B : 0;
   const int32_t* tab = a.table + (active ? brick : 0) * (int64_t)(NL * (B + 1));
@@ -1058,24 +1070,43 @@ __global__ __launch_bounds__(256) void k_combine(const int32_t* __restrict__ nod
   if (row < nrows) {
     const int32_t i = node[row];
     const int32_t k0 = ptr[row], k1 = ptr[row + 1];
+    // a row's entries and then its slots are loaded CH at a time, every load
+    // of a group in flight together (a row holds 2 to 8 entries, more only
+    // next to hanging nodes); the sum keeps the entry order
+    constexpr int CH = 8;
+    T v[NO];
+#pragma unroll
+    for (int f = 0; f < NO; ++f) v[f] = T(0);
+    for (int32_t kb = k0; kb < k1; kb += CH) {
+      uint32_t e[CH];
+#pragma unroll
+      for (int j = 0; j < CH; ++j) e[j] = kb + j < k1 ? ent[kb + j] : 0u;
+#pragma unroll
+      for (int f = 0; f < NO; ++f) {
+        T sv[CH];
+#pragma unroll
+        for (int j = 0; j < CH; ++j) sv[j] = kb + j < k1 ? slots[f * n_slots + (e[j] & 0x3fffffffu)] : T(0);
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+          if (kb + j < k1) {
+            const uint32_t code = e[j] >> 30;
+            v[f] += code == 0 ? sv[j] : (code == 1 ? sv[j] * T(0.5) : sv[j] * T(0.25));
+          }
+        }
+      }
+    }
 #pragma unroll
     for (int f = 0; f < NO; ++f) {
-      T v = T(0);
-      for (int32_t k = k0; k < k1; ++k) {
-        const uint32_t e = ent[k];
-        const uint32_t code = e >> 30;
-        const T s = slots[f * n_slots + (e & 0x3fffffffu)];
-        v += code == 0 ? s : (code == 1 ? s * T(0.5) : s * T(0.25));
-      }
+      T w = v[f];
       // wall rows: identity (WALL 1) or zero (WALL 2)
       if constexpr (WALL == 1) {
-        if (wall[i]) v = x[f * n + i];
+        if (wall[i]) w = x[f * n + i];
       } else if constexpr (WALL == 2) {
-        if (wall[i]) v = T(0);
+        if (wall[i]) w = T(0);
       }
-      if (sm_r) v = x[i] + sm_w * sm_d[i] * (sm_r[i] - v);
-      y[f * n + i] = v;
-      if (partials) dot += (double)x[f * n + i] * (double)v;
+      if (sm_r) w = x[i] + sm_w * sm_d[i] * (sm_r[i] - w);
+      y[f * n + i] = w;
+      if (partials) dot += (double)x[f * n + i] * (double)w;
     }
   }
   if (!partials) return;

@@ -255,6 +255,8 @@ int launch_diagonal_lv(Ctx& c, const LevelView& L, int op, int prec, void* d, bo
                        hipStream_t s);
 LevelView fine_view(Ctx& c);
 int op_fields(int op, int dim);
+// device copy of a host mesh (brick tables, combine rows, colours, walls)
+int upload_dm(Ctx& c, const HostMesh& m, DevMesh& d);
 // address of the per-GPU static slot scratch on the current device (looked
 // up once per device); the apply below uses it instead of the context's slots
 int scratch_address(void** out);

@@ -637,6 +637,8 @@ int upload_as_float(Ctx& c, float** dst, const std::vector<T>& src) {
   return upload(c, dst, f);
 }
 
+}  // namespace
+
 int upload_dm(Ctx& c, const HostMesh& m, DevMesh& d) {
   d.dim = m.dim;
   d.max_level = m.max_level;
@@ -671,6 +673,8 @@ int upload_dm(Ctx& c, const HostMesh& m, DevMesh& d) {
   if ((rc = upload(c, &d.wall, m.wall))) return rc;
   return CHNS_OK;
 }
+
+namespace {
 
 LevelView view(MgLevel& L) { return LevelView{&L.dm, L.phi64, L.phi32, L.slots}; }
 
