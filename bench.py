@@ -446,6 +446,27 @@ def adaptive_workload(torch, lmax):
                                "outer": sv.outer_iterations, "rel_residual": sv.rel_residual,
                                "setup_ms": sv.ms_setup}
         print(f"# {name}: {out['solves'][name]}", file=sys.stderr, flush=True)
+    # learned preconditioner through the uniform level-7 grid (the shipped
+    # weights; the grid transfers are built on the host at the first solve)
+    wpath = os.path.join(ROOT, "paper_2107_05123_amd", "weights", "unet_uniform_l7_rho1000.bin")
+    with open(wpath, "rb") as fh:
+        ctx.pc_load(fh.read())
+    t1 = time.perf_counter()
+    solve_once(torch, ctx, phi_d, b, pc="learned", learned_every=8)
+    torch.cuda.synchronize()
+    out["learned_grid_setup_s"] = time.perf_counter() - t1
+    for name, kw in (("learned_fcg_every8_fp64", dict(pc="learned", learned_every=8, max_it=40000)),
+                     ("learned_fcg_every8_mixed_ir", dict(pc="learned", learned_every=8, mode="mixed",
+                                                          max_it=40000))):
+        solve_once(torch, ctx, phi_d, b, **kw)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, sv = solve_once(torch, ctx, phi_d, b, **kw)
+        torch.cuda.synchronize()
+        out["solves"][name] = {"s": time.perf_counter() - t1, "iterations": sv.iterations,
+                               "outer": sv.outer_iterations, "rel_residual": sv.rel_residual,
+                               "setup_ms": sv.ms_setup, "fallback_to_jacobi": sv.fallback}
+        print(f"# {name}: {out['solves'][name]}", file=sys.stderr, flush=True)
     return out
 
 

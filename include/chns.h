@@ -415,6 +415,13 @@ int chns_advance_step(chns_ctx* ctx, chns_state* state, const chns_step_opts* op
  * r1 = r - A z1, n = N(r1), z2 = z1 + beta n with the A-norm-optimal step
  * beta = n.r1 / n.A n along n (either sign; 0 if n.A n <= 0),
  * z = z2 + omega D^-1 (r - A z2); then 1^T z = 0.
+ * On an adaptive 3D octree of the whole cube (max_level >= 7) the network
+ * sees the uniform level-7 node grid (129^3 points): N(r) = P Net(R r) with
+ * P the Q1 interpolation of grid fields at the mesh's nodes, R = P^T, and
+ * phi~ sampled at the grid points by the mesh's Q1 field; the transfers are
+ * built on the host at the first learned solve of a context (EINVAL for 2D
+ * or carved meshes, or max_level < 7).  Training and chns_pc_forward need a
+ * uniform 3D mesh.
  * The paper preconditions with algebraic multigrid; this network is an
  * addition of this library.  Weights belong to the context.               */
 

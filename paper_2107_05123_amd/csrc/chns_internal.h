@@ -329,7 +329,7 @@ size_t unet_param_count(const Ctx& c);
 int unet_forward_crop(Ctx& c, const double* phi, const double* r, const int32_t* origin, int flip, int crop,
                       float* out, hipStream_t s);
 int unet_train_step(Ctx& c, const chns_pc_batch& b, float lr, float* loss, hipStream_t s);
-int unet_prepare(Ctx& c);
+int unet_prepare(Ctx& c, hipStream_t s);
 bool unet_ready(const Ctx& c);
 template <typename T>
 int unet_apply(Ctx& c, const T* r, T* z, hipStream_t s);

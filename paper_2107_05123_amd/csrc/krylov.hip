@@ -564,7 +564,7 @@ int solve_pressure_impl(Ctx& c, const double* b_in, double* x_out, const chns_so
       set_error("no learned preconditioner weights in this context (chns_pc_load or chns_pc_init)");
       return CHNS_ESTATE;
     }
-    int e = unet_prepare(c);
+    int e = unet_prepare(c, s);
     if (e) return e;
   }
   int pck = o.pc == CHNS_PC_JACOBI ? PCK_JACOBI

@@ -1216,6 +1216,49 @@ int build_host_mesh_remesh(const HostMesh& old, const double* phi, int min_level
   }
 }
 
+namespace {
+// The Q1 field of src (hanging constraints included) at the point x (units of
+// 2^-max_level, inside src's box): the trilinear weights of the corners of the
+// leaf whose box holds x, nudged inside at the box's far faces.
+bool field_at(const HostMesh& src, const KeySet& leaves, const NodeLookup& sl, const int32_t* x,
+              std::vector<std::pair<int32_t, double>>& row, std::string& err) {
+  const int dim = src.dim, L = src.max_level, nc = 1 << dim;
+  int32_t af[3] = {0, 0, 0};
+  int32_t sf = 0;
+  int found = -1;
+  for (int lev = L; lev >= 0 && found < 0; --lev) {
+    sf = 1 << (L - lev);
+    for (int d = 0; d < dim; ++d) {
+      const int32_t q2 = 2 * x[d] + (x[d] < src.box_hi[d] ? 1 : -1);
+      af[d] = (q2 / (2 * sf)) * sf;
+    }
+    if (leaves.contains(leaf_key(dim, lev, af))) found = lev;
+  }
+  if (found < 0) {
+    err = "node outside the source mesh";
+    return false;
+  }
+  for (int a = 0; a < nc; ++a) {
+    double w = 1.0;
+    int32_t cc[3] = {0, 0, 0};
+    for (int d = 0; d < dim; ++d) {
+      const int bit = (a >> d) & 1;
+      const double xi = (double)(x[d] - af[d]) / sf;
+      w *= bit ? xi : 1.0 - xi;
+      cc[d] = af[d] + bit * sf;
+    }
+    if (w == 0.0) continue;
+    int32_t ent;
+    if (!sl.find(cc, &ent)) {
+      err = "source leaf corner missing";
+      return false;
+    }
+    expand_entry(src, ent, w, row);
+  }
+  return true;
+}
+}  // namespace
+
 int build_interp(const HostMesh& src, const HostMesh& dst, std::vector<int32_t>& ptr, std::vector<int32_t>& col,
                  std::vector<double>& val, std::string& msg) {
   if (src.dim != dst.dim || src.max_level != dst.max_level) {
@@ -1223,55 +1266,73 @@ int build_interp(const HostMesh& src, const HostMesh& dst, std::vector<int32_t>&
     return CHNS_EINVAL;
   }
   try {
-    const int dim = src.dim, L = src.max_level;
-    const int nc = 1 << dim;
     KeySet leaves((size_t)src.n_elems() * 2);
     for (int64_t e = 0; e < src.n_elems(); ++e)
-      leaves.insert(leaf_key(dim, src.leaf_level[e], &src.leaf_anchor[3 * e]));
+      leaves.insert(leaf_key(src.dim, src.leaf_level[e], &src.leaf_anchor[3 * e]));
     NodeLookup sl(src);
     return build_rows(
         dst.n_indep,
         [&](int64_t i, std::vector<std::pair<int32_t, double>>& row, std::string& err) {
-          const int32_t* x = &dst.indep_coords[3 * i];
-          // the source leaf whose box holds x (nudged inside at the far faces)
-          int32_t af[3] = {0, 0, 0};
-          int32_t sf = 0;
-          int found = -1;
-          for (int lev = L; lev >= 0 && found < 0; --lev) {
-            sf = 1 << (L - lev);
-            for (int d = 0; d < dim; ++d) {
-              const int32_t q2 = 2 * x[d] + (x[d] < dst.box_hi[d] ? 1 : -1);
-              af[d] = (q2 / (2 * sf)) * sf;
-            }
-            if (leaves.contains(leaf_key(dim, lev, af))) found = lev;
-          }
-          if (found < 0) {
-            err = "node outside the source mesh";
-            return false;
-          }
-          // the source Q1 field at x: trilinear weights of the leaf's corners
-          for (int a = 0; a < nc; ++a) {
-            double w = 1.0;
-            int32_t cc[3] = {0, 0, 0};
-            for (int d = 0; d < dim; ++d) {
-              const int bit = (a >> d) & 1;
-              const double xi = (double)(x[d] - af[d]) / sf;
-              w *= bit ? xi : 1.0 - xi;
-              cc[d] = af[d] + bit * sf;
-            }
-            if (w == 0.0) continue;
-            int32_t ent;
-            if (!sl.find(cc, &ent)) {
-              err = "source leaf corner missing";
-              return false;
-            }
-            expand_entry(src, ent, w, row);
-          }
-          return true;
+          return field_at(src, leaves, sl, &dst.indep_coords[3 * i], row, err);
         },
         ptr, col, val, msg);
   } catch (const std::bad_alloc&) {
     msg = "host allocation failed while building the transfer";
+    return CHNS_ENOMEM;
+  }
+}
+
+int build_grid_transfer(const HostMesh& m, int g, GridTransfer& t, std::string& msg) {
+  if (m.dim != 3 || m.carve_level != 0 || g < 1 || g > m.max_level) {
+    msg = "grid transfers need a 3D octree on the whole cube whose max_level is at least the grid level";
+    return CHNS_EINVAL;
+  }
+  try {
+    const int L = m.max_level;
+    const int32_t s = 1 << (L - g), G = (1 << g) + 1, cmax = (1 << g) - 1;
+    t.level = g;
+    // P: the grid's Q1 field at every mesh node (trilinear in the grid cell
+    // that holds it; the last cell along an axis takes its far face)
+    int rc = build_rows(
+        m.n_indep,
+        [&](int64_t i, std::vector<std::pair<int32_t, double>>& row, std::string&) {
+          const int32_t* x = &m.indep_coords[3 * i];
+          int32_t c[3];
+          double xi[3];
+          for (int d = 0; d < 3; ++d) {
+            c[d] = std::min(x[d] / s, cmax);
+            xi[d] = (double)(x[d] - c[d] * s) / s;
+          }
+          for (int a = 0; a < 8; ++a) {
+            double w = 1.0;
+            int64_t k = 0, mul = 1;
+            for (int d = 0; d < 3; ++d) {
+              const int bit = (a >> d) & 1;
+              w *= bit ? xi[d] : 1.0 - xi[d];
+              k += (c[d] + bit) * mul;
+              mul *= G;
+            }
+            if (w != 0.0) row.push_back({(int32_t)k, w});
+          }
+          return true;
+        },
+        t.P_ptr, t.P_col, t.P_val, msg);
+    if (rc) return rc;
+    const int64_t ng = (int64_t)G * G * G;
+    csr_transpose(ng, t.P_ptr, t.P_col, t.P_val, t.R_ptr, t.R_col, t.R_val);
+    // Q: the mesh's Q1 field at every grid point
+    KeySet leaves((size_t)m.n_elems() * 2);
+    for (int64_t e = 0; e < m.n_elems(); ++e) leaves.insert(leaf_key(m.dim, m.leaf_level[e], &m.leaf_anchor[3 * e]));
+    NodeLookup sl(m);
+    return build_rows(
+        ng,
+        [&](int64_t j, std::vector<std::pair<int32_t, double>>& row, std::string& err) {
+          const int32_t x[3] = {(int32_t)(j % G) * s, (int32_t)((j / G) % G) * s, (int32_t)(j / ((int64_t)G * G)) * s};
+          return field_at(m, leaves, sl, x, row, err);
+        },
+        t.Q_ptr, t.Q_col, t.Q_val, msg);
+  } catch (const std::bad_alloc&) {
+    msg = "host allocation failed while building the grid transfers";
     return CHNS_ENOMEM;
   }
 }

@@ -105,4 +105,17 @@ int build_host_mesh_remesh(const HostMesh& old, const double* phi, int min_level
 int build_interp(const HostMesh& src, const HostMesh& dst, std::vector<int32_t>& ptr, std::vector<int32_t>& col,
                  std::vector<double>& val, std::string& msg);
 
+// Transfers between a 3D octree on the whole cube and the uniform node grid
+// of level g ((2^g + 1)^3 points in lexicographic order, x fastest):
+//   P (mesh nodes x grid points): the grid's Q1 field at every mesh node;
+//   R = P^T (grid points x mesh nodes);
+//   Q (grid points x mesh nodes): the mesh's Q1 field, hanging constraints
+//   included, at every grid point.
+struct GridTransfer {
+  int level = 0;
+  std::vector<int32_t> P_ptr, P_col, R_ptr, R_col, Q_ptr, Q_col;
+  std::vector<double> P_val, R_val, Q_val;
+};
+int build_grid_transfer(const HostMesh& m, int g, GridTransfer& t, std::string& msg);
+
 }  // namespace chns

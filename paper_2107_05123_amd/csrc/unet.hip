@@ -26,6 +26,8 @@
 
 #include <cmath>
 #include <cstring>
+#include <string>
+#include <type_traits>
 #include <vector>
 
 #include "chns_internal.h"
@@ -86,12 +88,25 @@ struct UNet {
   double* tb[10] = {};                  // training work vectors (smoothing)
   double* hb64[4] = {};                 // preconditioner work vectors
   float* hb32[4] = {};
+  // adaptive meshes: the network runs on the uniform node grid of level
+  // kGridLevel; P (mesh nodes <- grid), R = P^T and Q (grid <- mesh nodes)
+  bool grid_built = false;
+  int64_t n_grid = 0;
+  int32_t *gP_ptr = nullptr, *gP_col = nullptr, *gR_ptr = nullptr, *gR_col = nullptr, *gQ_ptr = nullptr,
+          *gQ_col = nullptr;
+  double *gP_val = nullptr, *gR_val = nullptr, *gQ_val = nullptr;
+  double* phig = nullptr;  // phi~ sampled at the grid points
+  double* xg64[2] = {};    // grid residual and network output
+  float* xg32[2] = {};
 };
 
 namespace {
 
 constexpr int kT = 256;
 constexpr int kRedBlocks = 1024;
+// level of the uniform node grid (129^3 points) the network sees on adaptive
+// meshes: the level it is trained on
+constexpr int kGridLevel = 7;
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
   uint32_t u = __float_as_uint(f);
@@ -628,6 +643,17 @@ __global__ __launch_bounds__(256) void k_rms(const double* part, int np, int64_t
   if (threadIdx.x == 0) scal[0] = s > 0.0 ? sqrt(s / (double)n) : 1.0;
 }
 
+// y = M x for a CSR matrix with FP64 values, summed in FP64 in row order
+template <typename T>
+__global__ void k_csr_apply(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                            const double* __restrict__ val, const T* __restrict__ x, T* __restrict__ y, int64_t rows) {
+  ULOOP(i, rows) {
+    double acc = 0.0;
+    for (int32_t k = ptr[i]; k < ptr[i + 1]; ++k) acc += val[k] * (double)x[col[k]];
+    y[i] = (T)acc;
+  }
+}
+
 struct PackGeo {
   int side;            // nodes per axis - 1
   int E;               // grid edge in voxels
@@ -1072,11 +1098,25 @@ void rho_ab(const Ctx& c, double* a, double* b) {
 
 int check_grid(const Ctx& c) {
   if (c.dm.dim != 3 || !c.dm.structured) {
-    set_error("the learned preconditioner needs a uniform 3D mesh");
+    set_error("training and crop passes of the network need a uniform 3D mesh");
     return CHNS_EINVAL;
   }
   return CHNS_OK;
 }
+
+// The preconditioner runs on uniform 3D meshes directly and on 3D octrees of
+// the whole cube refined to at least the grid level through the grid.
+int check_pc(const Ctx& c) {
+  if (c.dm.dim == 3 && c.dm.structured) return CHNS_OK;
+  if (c.dm.dim != 3 || !c.host || c.host->carve_level != 0 || c.host->max_level < kGridLevel) {
+    set_error("the learned preconditioner needs a 3D octree of the whole cube with max_level >= " +
+              std::to_string(kGridLevel));
+    return CHNS_EINVAL;
+  }
+  return CHNS_OK;
+}
+// nodes per axis - 1 of the grid the network sees
+int net_side(const Ctx& c) { return c.dm.structured ? c.dm.side : (1 << kGridLevel); }
 
 // splitmix64 -> two uniforms -> Box-Muller normal
 uint64_t splitmix(uint64_t& s) {
@@ -1339,11 +1379,10 @@ static int adam_update(UNet& u, float lr, hipStream_t s) {
 // network part of the preconditioner on a node vector x: rms(x) -> scal[0],
 // pack, forward, z = rms(x) K Net (no projection)
 template <typename T>
-static int net_nodes(Ctx& c, UActs& a, const double* phi, const T* x, T* z, hipStream_t s) {
+static int net_nodes(Ctx& c, UActs& a, int side, int64_t n, const double* phi, const T* x, T* z, hipStream_t s) {
   UNet& u = *c.unet;
-  const int64_t n = c.dm.n;
   const unsigned g = (unsigned)std::min<int64_t>(kRedBlocks, (n + kT - 1) / kT);
-  const PackGeo geo{c.dm.side, a.E, 0, 0, 0, 0};
+  const PackGeo geo{side, a.E, 0, 0, 0, 0};
   double al, be;
   rho_ab(c, &al, &be);
   const int64_t V = (int64_t)a.E * a.E * a.E;
@@ -1355,6 +1394,29 @@ static int net_nodes(Ctx& c, UActs& a, const double* phi, const T* x, T* z, hipS
   int rc = forward(u, a, s);
   if (rc) return rc;
   k_unpack<T><<<nblk(V), kT, 0, s>>>(geo, a.A13, u.W + u.wout_off, u.scal, u.K, z);
+  CHNS_HIP(hipGetLastError());
+  return CHNS_OK;
+}
+
+// network part of the preconditioner on a mesh vector: on a uniform mesh
+// the node grid is the mesh's own; otherwise z = P Net(R x) on the grid
+// (phi~ sampled there by Q when the solve is prepared)
+template <typename T>
+static int net_apply(Ctx& c, UActs& a, const T* x, T* z, hipStream_t s) {
+  if (c.dm.structured) return net_nodes<T>(c, a, c.dm.side, c.dm.n, c.phi64, x, z, s);
+  UNet& u = *c.unet;
+  constexpr bool f64 = sizeof(T) == 8;
+  T* xg = f64 ? (T*)u.xg64[0] : (T*)u.xg32[0];
+  T* zg = f64 ? (T*)u.xg64[1] : (T*)u.xg32[1];
+  if (!u.grid_built || !xg || !zg) {
+    set_error("grid transfers of the learned preconditioner are not prepared");
+    return CHNS_ESTATE;
+  }
+  k_csr_apply<T><<<nblk(u.n_grid), kT, 0, s>>>(u.gR_ptr, u.gR_col, u.gR_val, x, xg, u.n_grid);
+  CHNS_HIP(hipGetLastError());
+  int rc = net_nodes<T>(c, a, 1 << kGridLevel, u.n_grid, u.phig, xg, zg, s);
+  if (rc) return rc;
+  k_csr_apply<T><<<nblk(c.dm.n), kT, 0, s>>>(u.gP_ptr, u.gP_col, u.gP_val, zg, z, c.dm.n);
   CHNS_HIP(hipGetLastError());
   return CHNS_OK;
 }
@@ -1407,7 +1469,7 @@ static int train_energy(Ctx& c, const chns_pc_batch& b, float lr, float* loss, h
       CHNS_HIP(hipGetLastError());
       xin = r1;
     }
-    if ((rc = net_nodes<double>(c, *a, b.phi[k], xin, net, s))) return rc;
+    if ((rc = net_nodes<double>(c, *a, c.dm.side, c.dm.n, b.phi[k], xin, net, s))) return rc;
     const double* zz = net;
     if (w > 0.0) {
       if ((rc = launch_apply(c, CHNS_OP_PRESSURE, CHNS_FP64, net, an, s, plain))) return rc;
@@ -1511,19 +1573,52 @@ int unet_train_step(Ctx& c, const chns_pc_batch& b, float lr, float* loss, hipSt
 
 bool unet_ready(const Ctx& c) { return c.unet && c.unet->ready; }
 
-// activations of the full node grid and the smoothing work vectors,
-// allocated before any graph capture
-int unet_prepare(Ctx& c) {
+// activations of the network's grid and the smoothing work vectors,
+// allocated before any graph capture; on adaptive meshes the grid transfers
+// (built on the host once per context) and phi~ at the grid points
+int unet_prepare(Ctx& c, hipStream_t s) {
   int rc;
-  if ((rc = check_grid(c))) return rc;
+  if ((rc = check_pc(c))) return rc;
   UNet& u = *c.unet;
   for (int k = 0; k < 4; ++k) {
     if (!u.hb64[k]) u.hb64[k] = (double*)c.dalloc(sizeof(double) * c.dm.n);
     if (!u.hb32[k]) u.hb32[k] = (float*)c.dalloc(sizeof(float) * c.dm.n);
     if (!u.hb64[k] || !u.hb32[k]) return CHNS_ENOMEM;
   }
+  if (!c.dm.structured) {
+    if (!u.grid_built) {
+      GridTransfer t;
+      std::string msg;
+      if ((rc = build_grid_transfer(*c.host, kGridLevel, t, msg))) {
+        set_error(msg);
+        return rc;
+      }
+      u.n_grid = (int64_t)t.R_ptr.size() - 1;
+      auto up = [&](auto** dst, const auto& v) -> int {
+        using E = typename std::decay_t<decltype(v)>::value_type;
+        *dst = (E*)c.dalloc(sizeof(E) * std::max<size_t>(v.size(), 1));
+        if (!*dst) return CHNS_ENOMEM;
+        if (!v.empty()) CHNS_HIP(hipMemcpy(*dst, v.data(), sizeof(E) * v.size(), hipMemcpyHostToDevice));
+        return CHNS_OK;
+      };
+      if ((rc = up(&u.gP_ptr, t.P_ptr)) || (rc = up(&u.gP_col, t.P_col)) || (rc = up(&u.gP_val, t.P_val)) ||
+          (rc = up(&u.gR_ptr, t.R_ptr)) || (rc = up(&u.gR_col, t.R_col)) || (rc = up(&u.gR_val, t.R_val)) ||
+          (rc = up(&u.gQ_ptr, t.Q_ptr)) || (rc = up(&u.gQ_col, t.Q_col)) || (rc = up(&u.gQ_val, t.Q_val)))
+        return rc;
+      u.phig = (double*)c.dalloc(sizeof(double) * u.n_grid);
+      for (int k = 0; k < 2; ++k) {
+        u.xg64[k] = (double*)c.dalloc(sizeof(double) * u.n_grid);
+        u.xg32[k] = (float*)c.dalloc(sizeof(float) * u.n_grid);
+        if (!u.xg64[k] || !u.xg32[k]) return CHNS_ENOMEM;
+      }
+      if (!u.phig) return CHNS_ENOMEM;
+      u.grid_built = true;
+    }
+    k_csr_apply<double><<<nblk(u.n_grid), kT, 0, s>>>(u.gQ_ptr, u.gQ_col, u.gQ_val, c.phi64, u.phig, u.n_grid);
+    CHNS_HIP(hipGetLastError());
+  }
   UActs* a = nullptr;
-  return ensure_acts(c, ((c.dm.side + 1 + 7) / 8) * 8, false, &a);
+  return ensure_acts(c, ((net_side(c) + 1 + 7) / 8) * 8, false, &a);
 }
 
 // Preconditioner (kernels only, graph-capturable; the phase field is the
@@ -1534,9 +1629,9 @@ int unet_prepare(Ctx& c) {
 template <typename T>
 int unet_apply(Ctx& c, const T* r, T* z, hipStream_t s) {
   int rc;
-  if ((rc = check_grid(c))) return rc;
+  if ((rc = check_pc(c))) return rc;
   UNet& u = *c.unet;
-  const int E = ((c.dm.side + 1 + 7) / 8) * 8;
+  const int E = ((net_side(c) + 1 + 7) / 8) * 8;
   UActs* a = nullptr;
   if ((rc = ensure_acts(c, E, false, &a))) return rc;
   const int64_t n = c.dm.n;
@@ -1558,14 +1653,14 @@ int unet_apply(Ctx& c, const T* r, T* z, hipStream_t s) {
     if ((rc = launch_apply(c, CHNS_OP_PRESSURE, prec, z1, az1, s, plain))) return rc;
     k_diffv<T><<<gn, kT, 0, s>>>(r1, r, az1, n);
     CHNS_HIP(hipGetLastError());
-    if ((rc = net_nodes<T>(c, *a, c.phi64, r1, z, s))) return rc;
+    if ((rc = net_apply<T>(c, *a, r1, z, s))) return rc;
     if ((rc = launch_apply(c, CHNS_OP_PRESSURE, prec, z, an, s, plain))) return rc;
     k_dot2<T><<<g, kT, 0, s>>>(z, r1, an, n, u.red);
     k_beta<<<1, 256, 0, s>>>(u.red, (int)g, u.scal);
     k_comb<T><<<gn, kT, 0, s>>>(z, z1, u.scal, n);
     k_jcorr2<T><<<gn, kT, 0, s>>>(z, w, d, r, az1, an, u.scal, n);
     CHNS_HIP(hipGetLastError());
-  } else if ((rc = net_nodes<T>(c, *a, c.phi64, r, z, s))) {
+  } else if ((rc = net_apply<T>(c, *a, r, z, s))) {
     return rc;
   }
   k_sum_part<T><<<g, kT, 0, s>>>(z, n, u.red);

@@ -309,3 +309,78 @@ def test_trained_network_cuts_cg_iterations_on_the_128_cube_workload():
         assert st.rel_residual <= 1e-8
     print("gain", res, flush=True)
     assert res["learned_every8"][0] <= 0.5 * res["jacobi_flex"][0]
+
+
+def _shipped_blob():
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    with open(os.path.join(root, "paper_2107_05123_amd", "weights", "unet_uniform_l7_rho1000.bin"), "rb") as fh:
+        return fh.read()
+
+
+def _c2_instance(mesh, level):
+    import chns_inputs as ci
+    from paper_2107_05123_amd import Context
+    x = ci.unit_coords(mesh.node_coords(), level)
+    c, r = ci.drops(0)
+    ctx = Context(mesh, Cn=0.01, rho_plus=RHO_P, rho_minus=RHO_M)
+    ctx.set_phase_field(_dev(ci.phi_drops(x, c, r, 0.01)))
+    amps, waves = ci.rhs_modes(1)
+    b = ctx.apply(ctx.MASS, _dev(ci.rhs_field(x, amps, waves)))
+    ctx.pc_load(_shipped_blob())
+    return ctx, b
+
+
+def test_learned_preconditioner_through_the_grid_equals_the_uniform_path():
+    """The adaptive path (network on the uniform level-7 grid through P, R =
+    P^T and Q) on a mesh whose leaves are all level 7 but whose max_level is
+    8: the grid points are the mesh nodes (in another order), so P, R and Q
+    are permutations and the solve must behave as on the uniform level-7
+    mesh (same iteration counts; the operators differ only in rounding
+    order).  A misplaced or mis-weighted grid entry breaks the network's
+    gain."""
+    from paper_2107_05123_amd import Mesh
+    uni = Mesh(dim=3, min_level=7, max_level=7, rule="uniform")
+    as_tree = Mesh(dim=3, min_level=7, max_level=8, rule="callback", refine=lambda anchor, level: False)
+    assert as_tree.n_nodes == uni.n_nodes and as_tree.summary()["n_hanging"] == 0
+    out = {}
+    for name, mesh, level in (("uniform", uni, 7), ("tree", as_tree, 8)):
+        ctx, b = _c2_instance(mesh, level)
+        its = {}
+        for kw_name, kw in (("every8", dict(pc="learned", learned_every=8)),
+                            ("every8_mixed", dict(pc="learned", learned_every=8, mode="mixed"))):
+            _, st = ctx.solve_pressure(b, **kw)
+            assert st.rel_residual <= 1e-8 and st.fallback == 0, (name, kw_name, st)
+            its[kw_name] = st.iterations
+        out[name] = its
+        print(name, its, flush=True)
+    for k in out["uniform"]:
+        assert abs(out["tree"][k] - out["uniform"][k]) <= 2, out
+
+
+def test_learned_preconditioner_on_an_adaptive_mesh_reaches_tolerance():
+    """Adaptive band mesh (levels 4-7, hanging nodes): flexible CG with the
+    shipped network through the level-7 grid reaches 1e-8, measured with the
+    oracle's assembled operator, in FP64 and in mixed precision."""
+    from paper_2107_05123_amd import Context
+    pair = Pair("band", 3, 4, 7, centre=(0.5, 0.5, 0.5), radius=0.3, band=0.02)
+    ctx = Context(pair.lib, Cn=0.02, rho_plus=RHO_P, rho_minus=RHO_M)
+    phi = np.tanh((np.linalg.norm(pair.x_unit - 0.5, axis=1) - 0.3) / (np.sqrt(2) * 0.02))
+    ctx.set_phase_field(_dev(phi))
+    ctx.pc_load(_shipped_blob())
+    A = fem.pp_matrix(pair.orc, pair.to_orc(phi), RHO_P, RHO_M)
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal(pair.lib.n_nodes)
+    b -= b.mean()
+    print(f"n={pair.lib.n_nodes} hanging={pair.lib.summary()['n_hanging']}", flush=True)
+    its = {}
+    for name, kw in (("jacobi_flex", dict(pc="learned", learned_every=10 ** 6)),
+                     ("every8", dict(pc="learned", learned_every=8)),
+                     ("every8_mixed", dict(pc="learned", learned_every=8, mode="mixed"))):
+        x, st = ctx.solve_pressure(_dev(b), **kw)
+        bo = pair.to_orc(b)
+        res = np.linalg.norm(bo - A @ pair.to_orc(x.cpu().numpy())) / np.linalg.norm(bo)
+        print(name, st, res, flush=True)
+        assert res <= 1.05e-8 and st.rel_residual <= 1e-8
+        its[name] = st.iterations
+    print(its, flush=True)
