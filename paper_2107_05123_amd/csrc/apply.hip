@@ -46,6 +46,11 @@ __device__ __forceinline__ float rcp_t(float r) { return __builtin_amdgcn_rcpf(r
 __device__ __forceinline__ double clamp_t(double v, double lim) { return fmin(fmax(v, -lim), lim); }
 __device__ __forceinline__ float clamp_t(float v, float lim) { return __builtin_amdgcn_fmed3f(v, 0.0f, 2.0f * lim); }
 
+// fused multiply-add in the operands' own precision (__builtin_fma is the
+// double one: float operands would be widened and the result narrowed)
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // 1D two-node / two-Gauss-point transform, scaled by 2: (a, b) nodal values
 // -> values at xi = -1/sqrt3, +1/sqrt3.  The 2x2 matrix is symmetric, so the
 // same transform also applies the transpose.
@@ -53,8 +58,8 @@ template <typename T>
 __device__ __forceinline__ void pair_tf(T& a, T& b) {
   T t = a + b;
   T u = b - a;
-  a = __builtin_fma(T(-kGauss), u, t);
-  b = __builtin_fma(T(kGauss), u, t);
+  a = fma_t(T(-kGauss), u, t);
+  b = fma_t(T(kGauss), u, t);
 }
 template <int N, int BIT, typename T>
 __device__ __forceinline__ void stage(T* v) {
@@ -90,7 +95,7 @@ __device__ __forceinline__ void elem_pp(const T* x, const T* ph, T A, T Bc, T* y
 #pragma unroll
   for (int i = 0; i < NC; ++i) {
     // coefficient 1 / (A phi + B) (pressure) or A phi + B (viscosity)
-    const T lin = __builtin_fma(A, clamp_t(q[i], T(NC)), Bc);
+    const T lin = fma_t(A, clamp_t(q[i], T(NC)), Bc);
     c[i] = RCP ? rcp_t(lin) : lin;
   }
 #pragma unroll
@@ -130,7 +135,7 @@ __device__ __forceinline__ void elem_mass_coef(const T* ph, T A, T Bc, T* r) {
     for (int i = 0; i < NC; ++i) r[i] = ph[i];
     all_stages<DIM>(r);
 #pragma unroll
-    for (int i = 0; i < NC; ++i) r[i] = __builtin_fma(A, clamp_t(r[i], T(NC)), Bc);
+    for (int i = 0; i < NC; ++i) r[i] = fma_t(A, clamp_t(r[i], T(NC)), Bc);
   } else {
 #pragma unroll
     for (int i = 0; i < NC; ++i) r[i] = Bc;
