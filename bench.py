@@ -436,7 +436,8 @@ def adaptive_workload(torch, lmax):
            "solves": {}}
     for name, kw in (("gmg_pcg_fp64", dict(pc="gmg")), ("gmg_pcg_mixed_ir", dict(pc="gmg", mode="mixed")),
                      ("jacobi_pcg_fp64", dict(pc="jacobi", max_it=40000)),
-                     ("jacobi_pcg_mixed_ir", dict(pc="jacobi", mode="mixed", max_it=40000))):
+                     ("jacobi_pcg_mixed_ir", dict(pc="jacobi", mode="mixed", max_it=40000)),
+                     ("jacobi_pcg_mixed_ru", dict(pc="jacobi", mode="mixed_ru", inner_rtol=1e-2, max_it=40000))):
         solve_once(torch, ctx, phi_d, b, **kw)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -622,7 +623,8 @@ def main():
                                  "rel_residual": st.rel_residual, "setup_ms": st.ms_setup}}
     for name, kw in (("gmg_pcg_mixed_ir", dict(pc="gmg", mode="mixed", inner_rtol=1e-4)),
                      ("jacobi_pcg_fp64", dict(pc="jacobi")),
-                     ("jacobi_pcg_mixed_ir", dict(pc="jacobi", mode="mixed", inner_rtol=1e-4))):
+                     ("jacobi_pcg_mixed_ir", dict(pc="jacobi", mode="mixed", inner_rtol=1e-4)),
+                     ("jacobi_pcg_mixed_ru", dict(pc="jacobi", mode="mixed_ru", inner_rtol=1e-2))):
         solve_once(torch, ctx, phi_d, b, **kw)
         torch.cuda.synchronize()
         t1 = time.perf_counter()

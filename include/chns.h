@@ -239,16 +239,28 @@ int chns_operator_diagonal(chns_ctx* ctx, int op, int prec, void* d, void* strea
 /* ---------------------------------------------------------------- solves */
 
 enum { CHNS_PC_JACOBI = 0, CHNS_PC_GMG = 1, CHNS_PC_LEARNED = 2, CHNS_PC_NONE = 3 };
-enum { CHNS_MODE_FP64 = 0, CHNS_MODE_MIXED_IR = 1 };
+/* MIXED_IR: FP64 iterative refinement, r = b - A x in FP64, each inner CG
+ * (FP32 operator, vectors and preconditioner; FP64 dot products) solves
+ * A d = r / |r| to inner_rtol from a fresh start, then x += |r| d.
+ * MIXED_RU: the same refinement steps, but each inner CG continues the
+ * previous one's search direction (residual replacement, as in reliable-
+ * update CG): p = z + beta p with beta = (r.z)_new / (r.z)_old of the
+ * unnormalised residuals, so the Krylov process is not restarted when the
+ * FP64 residual replaces the FP32 one.  Flexible CG (the learned
+ * preconditioner) always restarts.                                         */
+enum { CHNS_MODE_FP64 = 0, CHNS_MODE_MIXED_IR = 1, CHNS_MODE_MIXED_RU = 2 };
 
 typedef struct chns_solve_opts {
   double rtol;        /* stop when |b - A x|_2 / |b|_2 <= rtol (FP64); default 1e-8 */
   int max_it;         /* Krylov iterations (inner ones in MIXED_IR); default 20000   */
   int pc;             /* CHNS_PC_*                                                   */
   int mode;           /* CHNS_MODE_*                                                 */
-  double inner_rtol;  /* MIXED_IR inner tolerance; default 1e-4                      */
+  double inner_rtol;  /* MIXED_IR inner tolerance; default 1e-4.  MIXED_RU: the
+                         factor by which the FP32 residual falls between two FP64
+                         replacements; about 1e-2 (below ~1e-3 FP32 rounding piles
+                         up in the continued directions and convergence stalls)    */
   int check_every;    /* host convergence poll period in iterations; default 16      */
-  int max_outer;      /* MIXED_IR refinement steps; default 30                       */
+  int max_outer;      /* MIXED_IR / MIXED_RU refinement steps; default 30            */
   int no_graphs;      /* 1: launch every kernel eagerly instead of replaying one HIP
                          graph per Krylov iteration (same arithmetic, same result)  */
   int learned_every;  /* CHNS_PC_LEARNED: 0 = network preconditioner in every
@@ -338,7 +350,7 @@ typedef struct chns_step_opts {
   int max_it;          /* iteration cap of each linear solve; default 5000      */
   int restart;         /* GMRES restart length, 1..128; default 64              */
   int pp_pc;           /* CHNS_PC_JACOBI (default) or CHNS_PC_GMG                */
-  int pp_mode;         /* CHNS_MODE_FP64 (default) or CHNS_MODE_MIXED_IR         */
+  int pp_mode;         /* CHNS_MODE_FP64 (default), _MIXED_IR or _MIXED_RU        */
   int no_graphs;       /* 1: no HIP graph replay of Krylov iterations           */
   int ch_pc;           /* preconditioner of the CH Newton GMRES: CHNS_CH_PC_BLOCK_JACOBI
                         * (default: 2x2 node blocks of the Jacobian) or

@@ -17,6 +17,10 @@ from ._lib import ChnsError  # noqa: F401
 
 __all__ = ["Mesh", "Context", "ChnsError", "octree_build"]
 
+# pressure solve modes: FP64, FP64 refinement around FP32 CG restarted at
+# every step, or continuing its search direction across the steps
+_MODES = {"fp64": L.MODE_FP64, "mixed": L.MODE_MIXED_IR, "mixed_ru": L.MODE_MIXED_RU}
+
 
 def _stream_ptr(stream=None):
     import torch
@@ -256,16 +260,17 @@ class Context:
         L.check(L.lib().chns_operator_diagonal(self._h, op, prec, _dev_ptr(d, want), _stream_ptr(stream)))
         return d
 
-    def solve_pressure(self, b, x=None, rtol=1e-8, max_it=20000, pc="jacobi", mode="fp64", inner_rtol=1e-4,
+    def solve_pressure(self, b, x=None, rtol=1e-8, max_it=20000, pc="jacobi", mode="fp64", inner_rtol=None,
                        check_every=16, max_outer=30, graphs=True, learned_every=0, stream=None,
                        raise_on_noconv=True):
         import torch
         if x is None:
             x = torch.zeros_like(b)
+        if inner_rtol is None:
+            inner_rtol = 1e-2 if mode == "mixed_ru" else 1e-4
         o = L.SolveOpts(rtol, max_it, {"jacobi": L.PC_JACOBI, "gmg": L.PC_GMG, "learned": L.PC_LEARNED,
                                        "none": L.PC_NONE}[pc],
-                        {"fp64": L.MODE_FP64, "mixed": L.MODE_MIXED_IR}[mode], inner_rtol, check_every, max_outer,
-                        0 if graphs else 1, int(learned_every))
+                        _MODES[mode], inner_rtol, check_every, max_outer, 0 if graphs else 1, int(learned_every))
         st = L.SolveStats()
         rc = L.lib().chns_solve_pressure(self._h, _dev_ptr(b, torch.float64, self.n),
                                          _dev_ptr(x, torch.float64, self.n), C.byref(o), C.byref(st),
@@ -331,7 +336,7 @@ class Context:
                      _dev_ptr(state["mu"], torch.float64, self.n))
         o = L.StepOpts(blocks, newton_rtol, newton_atol, max_newton, lin_rtol, max_it, restart,
                        {"jacobi": L.PC_JACOBI, "gmg": L.PC_GMG}[pp_pc],
-                       {"fp64": L.MODE_FP64, "mixed": L.MODE_MIXED_IR}[pp_mode], 0 if graphs else 1,
+                       _MODES[pp_mode], 0 if graphs else 1,
                        {"block": L.CH_PC_BLOCK_JACOBI, "schur": L.CH_PC_SCHUR_GMG}[ch_pc],
                        {"jacobi": L.VP_PC_JACOBI, "gmg": L.VP_PC_GMG}[vp_pc],
                        fptr(fv, d), fptr(fp, self.n), fptr(fm, self.n))

@@ -14,7 +14,7 @@ RULE_UNIFORM, RULE_SPHERE_BAND, RULE_MULTI_SPHERE_BAND, RULE_CALLBACK = 0, 1, 2,
 OP_PRESSURE, OP_MOMENTUM, OP_CH_JACOBIAN, OP_MASS_RHO, OP_MASS, OP_MOMENTUM_SCALAR = 0, 1, 2, 3, 4, 5
 FP64, FP32 = 0, 1
 PC_JACOBI, PC_GMG, PC_LEARNED, PC_NONE = 0, 1, 2, 3
-MODE_FP64, MODE_MIXED_IR = 0, 1
+MODE_FP64, MODE_MIXED_IR, MODE_MIXED_RU = 0, 1, 2
 FORM_CH_RESIDUAL, FORM_VP_RHS, FORM_PP_RHS, FORM_VU_RHS, FORM_ENERGY = 0, 1, 2, 3, 4
 
 REFINE_CB = C.CFUNCTYPE(C.c_int, C.POINTER(C.c_int64), C.c_int, C.c_void_p)

@@ -191,7 +191,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_init(const T* b, const T* q, T*
     T zi = dinv ? dinv[i] * ri : ri;
     r[i] = ri;
     z[i] = zi;
-    p[i] = zi;
+    if (p) p[i] = zi;
     v[0] += (double)ri * (double)zi;
     v[1] += (double)ri * (double)ri;
   }
@@ -225,6 +225,16 @@ template <typename T>
 __global__ void k_cg_p(T* p, const T* z, int64_t n, const DevScalars* sc, int check_done) {
   if (check_done && sc->done) return;
   const T beta = (T)sc->beta;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+    p[i] = z[i] + beta * p[i];
+}
+
+// continued search direction after a residual replacement:
+// p = z + coef (r.z) p, coef prepared on the host
+template <typename T>
+__global__ void k_cont_p(T* p, const T* z, int64_t n, const DevScalars* sc, double coef) {
+  if (sc->done) return;
+  const T beta = (T)(coef * sc->rz);
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
     p[i] = z[i] + beta * p[i];
 }
@@ -420,9 +430,13 @@ int apply_pc(Ctx& c, int pc, const T* r, T* z, hipStream_t s, const T* dinv = nu
 // CG convergent for a preconditioner that varies between iterations.  With
 // every > 0 (flexible only) the preconditioner `pc` is applied to r_0 and
 // after every `every`-th iteration, Jacobi after the others.
+//
+// cont_coef != 0 continues the search direction left in p by the previous
+// call instead of starting from p = z (residual replacement, see the mixed
+// solve): p = z + cont_coef (r.z) p.
 template <typename T>
 int pcg(Ctx& c, int op, const T* b, T* x, int pc, const T* dinv, bool flexible, double tol2, int max_it, int depth,
-        bool graphs, hipStream_t s, int* iters, double* rr_out, int every = 0) {
+        bool graphs, hipStream_t s, int* iters, double* rr_out, int every = 0, double cont_coef = 0.0) {
   // all fields of the operator form one vector (block-diagonal operators)
   const int64_t n = c.dm.n * op_fields(op, c.dm.dim);
   const int prec = sizeof(T) == 8 ? CHNS_FP64 : CHNS_FP32;
@@ -440,17 +454,22 @@ int pcg(Ctx& c, int op, const T* b, T* x, int pc, const T* dinv, bool flexible, 
   k_init_scalars<<<1, 1, 0, s>>>(c.sc, tol2, max_it);
   ApplyOut plain{};
   if ((rc = launch_apply(c, op, prec, x, q, s, plain))) return rc;
+  const bool cont = cont_coef != 0.0;
   if (fused_pc) {
-    k_cg_init<T><<<g, kThreads, 0, s>>>(b, q, r, z, p, pc == PCK_JACOBI ? dinv : nullptr, n, c.sc, c.partials,
-                                        c.counter);
+    k_cg_init<T><<<g, kThreads, 0, s>>>(b, q, r, z, cont ? nullptr : p, pc == PCK_JACOBI ? dinv : nullptr, n, c.sc,
+                                        c.partials, c.counter);
   } else {
     k_cg_init_nopc<T><<<g, kThreads, 0, s>>>(b, q, r, n, c.partials);
     if ((rc = apply_pc<T>(c, pc, r, z, s, dinv, n))) return rc;
     k_dot_rz<T><<<g, kThreads, 0, s>>>(r, z, nullptr, n, c.sc, c.partials, 0);
-    k_copy<T><<<g, kThreads, 0, s>>>(p, z, n);
+    if (!cont) k_copy<T><<<g, kThreads, 0, s>>>(p, z, n);
   }
   CHNS_HIP(hipGetLastError());
   if ((rc = fin(c, s, g, 2, FIN_CG_INIT, nullptr, 0))) return rc;
+  if (cont) {
+    k_cont_p<T><<<g, kThreads, 0, s>>>(p, z, n, c.sc, cont_coef);
+    CHNS_HIP(hipGetLastError());
+  }
   ApplyOut fused{};
   fused.fuse_dot = true;
   fused.done = &c.sc->done;
@@ -584,7 +603,12 @@ int solve_pressure_impl(Ctx& c, const double* b_in, double* x_out, const chns_so
   k_dot<double><<<g, kThreads, 0, s>>>(b, b, n, c.partials, c.counter, &c.sc->bb);
   if ((rc = fin(c, s, g, 1, FIN_STORE, &c.sc->bb, 0))) return rc;
   CHNS_HIP(hipGetLastError());
-  const bool mixed = o.mode == CHNS_MODE_MIXED_IR;
+  if (o.mode != CHNS_MODE_FP64 && o.mode != CHNS_MODE_MIXED_IR && o.mode != CHNS_MODE_MIXED_RU) {
+    set_error("unknown solve mode");
+    return CHNS_EINVAL;
+  }
+  const bool mixed = o.mode != CHNS_MODE_FP64;
+  const bool replace = o.mode == CHNS_MODE_MIXED_RU;
   if (o.pc == CHNS_PC_GMG) {
     if ((rc = mg_build(c))) return rc;
     if (!c.mg->setup_valid && (rc = mg_setup(c, s))) return rc;
@@ -669,6 +693,10 @@ int solve_pressure_impl(Ctx& c, const double* b_in, double* x_out, const chns_so
     float* r32 = c.w32[4];
     float* d32 = c.w32[5];
     int total = 0;
+    // residual replacement: the previous inner solve's |r| and its last
+    // r.z before convergence (normalised units), for continuing its direction
+    double rn_prev = 0.0, rz_prev = 0.0;
+    bool can_continue = false;
     for (int outer = 0; outer < o.max_outer; ++outer) {
       rc = launch_apply(c, CHNS_OP_PRESSURE, CHNS_FP64, x, q64, s, plain);
       if (rc) return rc;
@@ -694,10 +722,16 @@ int solve_pressure_impl(Ctx& c, const double* b_in, double* x_out, const chns_so
       const bool fcg = pck == PCK_LEARNED;
       const int every = fcg ? o.learned_every : 0;
       const int cap = fcg && every == 0 ? std::min(o.max_it - total, kLearnedCap) : o.max_it - total;
+      // continued direction: p = z + beta (rn_prev / rn) p with the CG beta
+      // of the unnormalised residuals, (rn^2 r.z) / (rn_prev^2 rz_prev)
+      const double coef = replace && can_continue && !fcg ? (rn / rn_prev) / rz_prev : 0.0;
       rc = pcg<float>(c, CHNS_OP_PRESSURE, r32, d32, pck, c.diag32, fcg, itol * itol, cap,
-                      every > 0 ? o.check_every : depth, graphs, s, &it, &rri, every);
+                      every > 0 ? o.check_every : depth, graphs, s, &it, &rri, every, coef);
       if (rc) return rc;
       total += it;
+      rn_prev = rn;
+      rz_prev = c.sc_host->rz_old;
+      can_continue = it > 0 && rz_prev > 0.0 && std::isfinite(rz_prev);
       if (fcg && !(rri <= itol * itol)) {
         // stagnation guard: the remaining refinement steps use Jacobi
         st.fallback = 1;

@@ -64,8 +64,9 @@ def test_full_cube_pp_apply_every_entry_matches_oracle(cube):
     assert np.abs(y32 - ref).max() <= 2e-5 * scale
 
 
-@pytest.mark.parametrize("pc,mode", [("jacobi", "fp64"), ("jacobi", "mixed"), ("gmg", "fp64"), ("gmg", "mixed"),
-                                     ("learned", "fp64"), ("learned", "mixed")])
+@pytest.mark.parametrize("pc,mode", [("jacobi", "fp64"), ("jacobi", "mixed"), ("jacobi", "mixed_ru"), ("gmg", "fp64"),
+                                     ("gmg", "mixed"), ("gmg", "mixed_ru"), ("learned", "fp64"),
+                                     ("learned", "mixed")])
 def test_full_cube_solves_reach_1e8_with_the_oracle_matrix(cube, pc, mode):
     pair, phi, A, ctx = cube
     kw = {}
@@ -135,7 +136,7 @@ def test_adaptive_level10_gmg_solve_reaches_1e8(band10):
     ctx.set_phase_field(_dev(ci.phi_bubble(xu, cn=0.01)))
     amps, waves = ci.rhs_modes(1)
     b = ctx.apply(ctx.MASS, _dev(ci.rhs_field(xu, amps, waves)))
-    for mode in ("fp64", "mixed"):
+    for mode in ("fp64", "mixed", "mixed_ru"):
         x, st = ctx.solve_pressure(b, rtol=1e-8, pc="gmg", mode=mode)
         bc = b - b.mean()
         rel = float((bc - ctx.apply(ctx.PRESSURE, x)).norm() / bc.norm())

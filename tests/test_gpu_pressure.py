@@ -139,7 +139,7 @@ def _rhs(pair, seed=1):
 
 
 @pytest.mark.parametrize("pc", ["jacobi", "gmg"])
-@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+@pytest.mark.parametrize("mode", ["fp64", "mixed", "mixed_ru"])
 def test_solve_pressure_reaches_1e8(case, mode, pc):
     pair, phi, A = case
     ctx = _ctx(pair)
@@ -185,7 +185,7 @@ def test_gmg_cuts_iterations_and_is_reused_across_phase_fields():
     assert rel <= 1.05e-8
 
 
-@pytest.mark.parametrize("pc,mode", [("jacobi", "fp64"), ("gmg", "fp64"), ("gmg", "mixed")])
+@pytest.mark.parametrize("pc,mode", [("jacobi", "fp64"), ("gmg", "fp64"), ("gmg", "mixed"), ("jacobi", "mixed_ru")])
 def test_graph_replays_match_eager_launches(pc, mode):
     # every Krylov iteration replays one captured HIP graph; the same solve
     # launched eagerly must give the bitwise identical iterate, on repeated
