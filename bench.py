@@ -368,6 +368,22 @@ def chns_measure(torch, mesh, ctx, phi_d):
     return out
 
 
+def profile_unet(torch):
+    """Fixed sequence for rocprofv3: 20 forward passes of the shipped network
+    on the 128^3 node grid (after one warm-up)."""
+    mesh, ctx, phi_d, b, *_ = setup(torch)
+    with open(os.path.join(ROOT, "paper_2107_05123_amd", "weights", "unet_uniform_l7_rho1000.bin"), "rb") as fh:
+        ctx.pc_load(fh.read())
+    r = b - b.mean()
+    out = ctx.pc_forward(phi_d, r, crop=128)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        ctx.pc_forward(phi_d, r, crop=128, out=out)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_run": "unet done", "forward_ms": (time.perf_counter() - t0) / 20 * 1e3}))
+
+
 def profile_chns(torch):
     """Fixed sequence for rocprofv3: CHNS applies on 128^3, three steps of the
     2D 64x64 drop, three U-Net forward passes on a 128^3 crop."""
@@ -471,6 +487,42 @@ def adaptive_workload(torch, lmax):
     return out
 
 
+# held-out instance seeds timed in the benchmark line (the full 0-99
+# evaluation is train_pc.py --eval-only ... --eval-seeds 0-99)
+LEARNED_SEEDS = 10
+
+
+def learned_distribution(torch, ctx, x_unit, seeds):
+    """Jacobi-PCG against flexible CG with the network every 8th iteration on
+    held-out instances of the 128^3 drop family (phase field and right-hand
+    side of each seed evaluated on the GPU), each solve timed after a warm-up
+    of the same instance."""
+    from paper_2107_05123_amd.train_pc import GpuInputs, instance_gpu
+    gin = GpuInputs(torch, x_unit)
+    rows = []
+    for seed in seeds:
+        _, b_s = instance_gpu(gin, ctx, seed)
+        row = {"seed": seed}
+        for name, kw in (("jacobi_pcg_fp64", dict(pc="jacobi")),
+                         ("learned_fcg_every8_fp64", dict(pc="learned", learned_every=8))):
+            ctx.solve_pressure(b_s, **kw)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, st = ctx.solve_pressure(b_s, **kw)
+            torch.cuda.synchronize()
+            row[name] = (time.perf_counter() - t1, st.iterations)
+        rows.append(row)
+    out = {"seeds": f"{seeds[0]}-{seeds[-1]}", "note": "seeds 0-99: profiles/learned_pc_uniform_l7_seeds0-99.md"}
+    for name in ("jacobi_pcg_fp64", "learned_fcg_every8_fp64"):
+        ms = np.array([r[name][0] for r in rows]) * 1e3
+        it = np.array([r[name][1] for r in rows])
+        out[name] = {"ms_median": float(np.median(ms)), "ms_min": float(ms.min()), "ms_max": float(ms.max()),
+                     "iterations_median": float(np.median(it)), "iterations_min": int(it.min()),
+                     "iterations_max": int(it.max())}
+    out["learned_faster_on"] = int(sum(r["learned_fcg_every8_fp64"][0] < r["jacobi_pcg_fp64"][0] for r in rows))
+    return out
+
+
 def bubble_steps(torch, lmax, nsteps, ch_pc="block", restart=16, vp_pc="jacobi", modes=("fp64", "mixed"),
                  remesh_every=0):
     """Projection time steps of the 3D rising bubble (density ratio 1000,
@@ -550,7 +602,8 @@ def main():
     ap.add_argument("--adaptive-level", type=int, default=10, help="finest level of the adaptive key")
     ap.add_argument("--profile-run", nargs="?", const="full", default=None,
                     help="fixed sequence for rocprofv3; 'applies' skips the solve (for counter passes), "
-                         "'gmg' solves with multigrid CG, 'chns' runs the CHNS applies, steps and network passes")
+                         "'gmg' solves with multigrid CG, 'chns' runs the CHNS applies, steps and network passes, "
+                         "'unet' 20 network forward passes")
     ap.add_argument("--workload", default="uniform_l7", choices=("uniform_l7", "adaptive", "bubble_steps"),
                     help="uniform_l7: the benchmark line; adaptive: levels 5..--max-level band mesh solves; "
                          "bubble_steps: projection steps of the 3D rising bubble")
@@ -596,6 +649,9 @@ def main():
         return
     if args.profile_run == "chns":
         profile_chns(torch)
+        return
+    if args.profile_run == "unet":
+        profile_unet(torch)
         return
     if args.profile_run:
         profile_run(torch, with_solve=args.profile_run != "applies",
@@ -650,6 +706,8 @@ def main():
         variants[name] = {"s": time.perf_counter() - t1, "iterations": sv.iterations,
                           "outer": sv.outer_iterations, "rel_residual": sv.rel_residual,
                           "setup_ms": sv.ms_setup, "fallback_to_jacobi": sv.fallback}
+    learned_seeds = learned_distribution(torch, ctx, x_unit, range(LEARNED_SEEDS))
+    ctx.set_phase_field(phi_d)
 
     # ---- apply throughput and the dominant kernel's roofline
     xr = torch.tensor(ci.normal_vector(0, n), dtype=torch.float64, device="cuda")
@@ -684,7 +742,7 @@ def main():
                          "brick_fp32_ms": k32, "combine_fp32_ms": comb32},
         "roofline": roof,
         "roofline_fp32": roof32,
-        "variants": variants,
+        "variants": variants, "learned_seeds": learned_seeds,
         "iterations": st.iterations,
         "rel_residual": st.rel_residual,
         "host_mesh_build_s": t_mesh,

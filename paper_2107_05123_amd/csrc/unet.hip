@@ -150,6 +150,21 @@ inline unsigned nblk(int64_t n) {
 // Wave w computes the z-slice w of the tile: four 16-voxel rows (one per y)
 // times NB 16-channel column blocks.
 constexpr int kTX = 16, kTY = 4, kTZ = 4;
+
+// Output tile of a convolution workgroup.  Workgroups are dealt round-robin
+// to the 8 XCDs (linear id b on XCD b % 8, each XCD with its own L2); the
+// linear id is remapped so that each XCD runs a contiguous run of tiles (a
+// slab of the grid), whose overlapping halos then meet in one L2.
+__device__ __forceinline__ void conv_tile(int& ox, int& oy, int& oz) {
+  constexpr uint32_t kXcd = 8;
+  const uint32_t gx = gridDim.x, gy = gridDim.y, g = gx * gy * gridDim.z;
+  const uint32_t b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const uint32_t per = g / kXcd, rem = g % kXcd, x = b % kXcd;
+  const uint32_t t = x * per + (x < rem ? x : rem) + b / kXcd;
+  ox = (int)(t % gx) * kTX;
+  oy = (int)((t / gx) % gy) * kTY;
+  oz = (int)(t / (gx * gy)) * kTZ;
+}
 constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2;
 constexpr int kHRow = 40;  // bf16 per halo voxel: 32 channels + 8 padding (bank spread)
 template <int NB>
@@ -160,7 +175,8 @@ __global__ __launch_bounds__(256) void k_conv3_tile(const uint16_t* __restrict__
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r16 = lane & 15, g = lane >> 4;
   const int co = NB * 16;
-  const int ox = blockIdx.x * kTX, oy = blockIdx.y * kTY, oz = blockIdx.z * kTZ;
+  int ox, oy, oz;
+  conv_tile(ox, oy, oz);
   f32x4 acc[4][NB];
 #pragma unroll
   for (int mb = 0; mb < 4; ++mb)
@@ -168,23 +184,72 @@ __global__ __launch_bounds__(256) void k_conv3_tile(const uint16_t* __restrict__
     for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int nchunk = (ci + 31) >> 5;
   for (int c = 0; c < nchunk; ++c) {
-    // stage the halo of this channel chunk: 4 rows of 16 bytes per voxel
-    for (int i = tid; i < kHZ * kHY * kHX * 4; i += 256) {
+    // stage the halo of this channel chunk: 4 rows of 16 bytes per voxel;
+    // a thread issues all its loads before its first LDS store
+    constexpr int NS = kHZ * kHY * kHX * 4, NJ = (NS + 255) / 256;
+    u32x4 t[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int i = tid + j * 256;
       const int hv = i >> 2, part = i & 3;
       const int hx = hv % kHX, hy = (hv / kHX) % kHY, hz = hv / (kHX * kHY);
       const int x = ox + hx - 1, y = oy + hy - 1, z = oz + hz - 1;
       const int k = c * 32 + part * 8;
-      u32x4 t = {0u, 0u, 0u, 0u};
-      if (k < ci && x >= 0 && x < E && y >= 0 && y < E && z >= 0 && z < E)
-        t = *(const u32x4*)(in + ((int64_t)(z * E + y) * E + x) * cs_in + k);
-      *(u32x4*)&H[hv * kHRow + part * 8] = t;
+      t[j] = u32x4{0u, 0u, 0u, 0u};
+      if (i < NS && k < ci && x >= 0 && x < E && y >= 0 && y < E && z >= 0 && z < E)
+        t[j] = *(const u32x4*)(in + ((int64_t)(z * E + y) * E + x) * cs_in + k);
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int i = tid + j * 256;
+      if (i < NS) *(u32x4*)&H[(i >> 2) * kHRow + (i & 3) * 8] = t[j];
     }
     __syncthreads();
     const int k0 = c * 32 + g * 8;
     const bool kin = k0 < ci;
+    if constexpr (NB <= 2) {
+      // few output channels: an activation fragment feeds only NB MFMAs, so
+      // LDS bandwidth bounds the loop.  Per dz, the 9 taps' weights stay in
+      // registers and each halo row (hy, dx) is read once for the up to
+      // three output rows it serves (mb = hy - 1 - dy): 18 LDS reads for 36
+      // MFMAs per NB instead of 36
+#pragma unroll 1
+      for (int dz = -1; dz <= 1; ++dz) {
+        u32x4 w[9][NB];
+#pragma unroll
+        for (int t = 0; t < 9; ++t)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            w[t][nb] = u32x4{0u, 0u, 0u, 0u};
+            if (kin) w[t][nb] = *(const u32x4*)(wt + ((int64_t)((dz + 1) * 9 + t) * co + nb * 16 + r16) * ci + k0);
+          }
+        const int hz = wave + 1 + dz;
+#pragma unroll
+        for (int hy = 0; hy < kTY + 2; ++hy) {
+          // one halo row's reads at a time (bounds the registers in flight)
+          asm volatile("" ::: "memory");
+#pragma unroll
+          for (int dx = -1; dx <= 1; ++dx) {
+            const u32x4 ta = *(const u32x4*)&H[((hz * kHY + hy) * kHX + r16 + 1 + dx) * kHRow + g * 8];
+            const bf16x8 av = as_bf(ta);
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy) {
+              const int mb = hy - 1 - dy;
+              if (mb < 0 || mb >= kTY) continue;
+#pragma unroll
+              for (int nb = 0; nb < NB; ++nb)
+                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, as_bf(w[(dy + 1) * 3 + dx + 1][nb]),
+                                                                     acc[mb][nb], 0, 0, 0);
+            }
+          }
+        }
+      }
+      __syncthreads();
+      continue;
+    }
     // weight fragments of a group of taps are loaded together (one latency
     // per group instead of one per tap)
-    constexpr int TG = NB <= 2 ? 9 : 3;
+    constexpr int TG = 3;
     for (int t0 = 0; t0 < 27; t0 += TG) {
       u32x4 w[TG][NB];
 #pragma unroll
@@ -250,15 +315,40 @@ __global__ __launch_bounds__(256) void k_conv3_flat(const uint16_t* __restrict__
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r16 = lane & 15, g = lane >> 4;
   const int co = NB * 16;
-  const int ox = blockIdx.x * kTX, oy = blockIdx.y * kTY, oz = blockIdx.z * kTZ;
-  for (int i = tid; i < kHZ * kHY * kHX * PARTS; i += 256) {
-    const int hv = i / PARTS, part = i % PARTS;
-    const int hx = hv % kHX, hy = (hv / kHX) % kHY, hz = hv / (kHX * kHY);
-    const int x = ox + hx - 1, y = oy + hy - 1, z = oz + hz - 1;
-    u32x4 t = {0u, 0u, 0u, 0u};
-    if (x >= 0 && x < E && y >= 0 && y < E && z >= 0 && z < E)
-      t = *(const u32x4*)(in + ((int64_t)(z * E + y) * E + x) * cs_in + part * 8);
-    *(u32x4*)&H[hv * ROW + part * 8] = t;
+  int ox, oy, oz;
+  conv_tile(ox, oy, oz);
+  if constexpr (CI >= 32) {
+    // all loads of a thread before its first LDS store (measured faster
+    // for 32 and 48 channels; for 16 the unrolled loads cost occupancy); the
+    // fence keeps the weight loads below out of this phase
+    constexpr int NS = kHZ * kHY * kHX * PARTS, NJ = (NS + 255) / 256;
+    u32x4 t[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int i = tid + j * 256;
+      const int hv = i / PARTS, part = i % PARTS;
+      const int hx = hv % kHX, hy = (hv / kHX) % kHY, hz = hv / (kHX * kHY);
+      const int x = ox + hx - 1, y = oy + hy - 1, z = oz + hz - 1;
+      t[j] = u32x4{0u, 0u, 0u, 0u};
+      if (i < NS && x >= 0 && x < E && y >= 0 && y < E && z >= 0 && z < E)
+        t[j] = *(const u32x4*)(in + ((int64_t)(z * E + y) * E + x) * cs_in + part * 8);
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int i = tid + j * 256;
+      if (i < NS) *(u32x4*)&H[(i / PARTS) * ROW + (i % PARTS) * 8] = t[j];
+    }
+    asm volatile("" ::: "memory");
+  } else {
+    for (int i = tid; i < kHZ * kHY * kHX * PARTS; i += 256) {
+      const int hv = i / PARTS, part = i % PARTS;
+      const int hx = hv % kHX, hy = (hv / kHX) % kHY, hz = hv / (kHX * kHY);
+      const int x = ox + hx - 1, y = oy + hy - 1, z = oz + hz - 1;
+      u32x4 t = {0u, 0u, 0u, 0u};
+      if (x >= 0 && x < E && y >= 0 && y < E && z >= 0 && z < E)
+        t = *(const u32x4*)(in + ((int64_t)(z * E + y) * E + x) * cs_in + part * 8);
+      *(u32x4*)&H[hv * ROW + part * 8] = t;
+    }
   }
   __syncthreads();
   f32x4 acc[4][NB];
