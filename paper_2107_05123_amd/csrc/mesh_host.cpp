@@ -139,20 +139,66 @@ bool box_meets_shell(const double* lo, const double* hi, const double* c, int di
 }
 
 // LSD radix sort of (key, payload) pairs.
-void radix_sort_pairs(std::vector<uint64_t>& key, std::vector<uint32_t>& val, int key_bits) {
-  const size_t n = key.size();
-  std::vector<uint64_t> k2(n);
-  std::vector<uint32_t> v2(n);
-  const int R = 11, NB = 1 << R;
-  for (int shift = 0; shift < key_bits; shift += R) {
-    std::vector<size_t> cnt(NB + 1, 0);
-    for (size_t i = 0; i < n; ++i) ++cnt[((key[i] >> shift) & (NB - 1)) + 1];
-    for (int b = 0; b < NB; ++b) cnt[b + 1] += cnt[b];
-    for (size_t i = 0; i < n; ++i) {
-      size_t p = cnt[(key[i] >> shift) & (NB - 1)]++;
-      k2[p] = key[i];
-      v2[p] = val[i];
+// Run f(t, begin, end) over T contiguous chunks of [0, n) on up to 16 host
+// threads (fewer for small n); chunk t is always [n t / T, n (t + 1) / T),
+// so work split this way and merged in chunk order is deterministic.  f must
+// not throw.
+template <typename F>
+void parallel_chunks(int64_t n, int64_t min_per_thread, F f) {
+  int64_t T = std::min<int64_t>(16, std::max<int64_t>(1, (int64_t)std::thread::hardware_concurrency()));
+  T = std::max<int64_t>(1, std::min<int64_t>(T, n / std::max<int64_t>(1, min_per_thread)));
+  std::vector<std::thread> th;
+  int64_t started = 1;
+  try {
+    for (int64_t t = 1; t < T; ++t) {
+      th.emplace_back([&f, t, T, n] { f(t, n * t / T, n * (t + 1) / T); });
+      ++started;
     }
+  } catch (...) {
+    // fewer threads than asked for: the remaining chunks run here
+  }
+  for (int64_t t = started; t < T; ++t) f(t, n * t / T, n * (t + 1) / T);
+  f(0, 0, n / T);
+  for (auto& x : th) x.join();
+}
+inline int64_t chunk_count(int64_t n, int64_t min_per_thread) {
+  int64_t T = std::min<int64_t>(16, std::max<int64_t>(1, (int64_t)std::thread::hardware_concurrency()));
+  return std::max<int64_t>(1, std::min<int64_t>(T, n / std::max<int64_t>(1, min_per_thread)));
+}
+
+// Stable LSD radix sort of (key, val) pairs by the low key_bits of key:
+// per-chunk digit histograms, then each chunk scatters its elements in order
+// to offsets that put chunk t's elements of a digit after chunk t-1's.
+void radix_sort_pairs(std::vector<uint64_t>& key, std::vector<uint32_t>& val, int key_bits) {
+  const int64_t n = (int64_t)key.size();
+  std::vector<uint64_t> k2((size_t)n);
+  std::vector<uint32_t> v2((size_t)n);
+  const int R = 11, NB = 1 << R;
+  constexpr int64_t kMin = 1 << 16;
+  const int64_t T = chunk_count(n, kMin);
+  std::vector<int64_t> hist((size_t)(T * NB));
+  for (int shift = 0; shift < key_bits; shift += R) {
+    std::fill(hist.begin(), hist.end(), 0);
+    parallel_chunks(n, kMin, [&](int64_t t, int64_t a, int64_t b) {
+      int64_t* h = &hist[(size_t)(t * NB)];
+      for (int64_t i = a; i < b; ++i) ++h[(key[(size_t)i] >> shift) & (NB - 1)];
+    });
+    // exclusive offsets in (digit, chunk) order
+    int64_t run = 0;
+    for (int d = 0; d < NB; ++d)
+      for (int64_t t = 0; t < T; ++t) {
+        const int64_t c = hist[(size_t)(t * NB + d)];
+        hist[(size_t)(t * NB + d)] = run;
+        run += c;
+      }
+    parallel_chunks(n, kMin, [&](int64_t t, int64_t a, int64_t b) {
+      int64_t* h = &hist[(size_t)(t * NB)];
+      for (int64_t i = a; i < b; ++i) {
+        const int64_t p = h[(key[(size_t)i] >> shift) & (NB - 1)]++;
+        k2[(size_t)p] = key[(size_t)i];
+        v2[(size_t)p] = val[(size_t)i];
+      }
+    });
     key.swap(k2);
     val.swap(v2);
   }
@@ -256,51 +302,83 @@ struct Builder {
     };
     int ndir = 1;
     for (int d = 0; d < dim; ++d) ndir *= 3;
+    // the leaf holding the point N (level < l-1 returned for a coarser leaf,
+    // -1 when a leaf of level l-1 or finer holds it: no action)
+    auto coarse_cover = [&](const int32_t* N, int l) -> int {
+      int32_t am[3];
+      for (int mlev = l - 1; mlev <= L; ++mlev) {
+        align(N, mlev, am);
+        if (S.contains(leaf_key(dim, mlev, am))) return -1;
+      }
+      for (int mlev = l - 2; mlev >= 0; --mlev) {
+        align(N, mlev, am);
+        if (S.contains(leaf_key(dim, mlev, am))) return mlev;
+      }
+      return -1;
+    };
+    struct Req {
+      int32_t N[3];
+    };
     for (int l = L; l >= 2; --l) {
-      // the neighbour checks depend only on the parent block: once per parent
-      KeySet parents(bylev[l].size() / 4 + 1);
-      for (size_t idx = 0; idx < bylev[l].size(); ++idx) {
-        std::array<int32_t, 3> a = bylev[l][idx];
-        if (!S.contains(leaf_key(dim, l, a.data()))) continue;
-        int32_t P[3];
-        align(a.data(), l - 1, P);
-        const uint64_t pk = leaf_key(dim, l - 1, P);
-        if (parents.contains(pk)) continue;
-        parents.insert(pk);
-        int32_t sP = size_at(l - 1);
-        for (int t = 0; t < ndir; ++t) {
-          int dir[3] = {0, 0, 0};
-          int tt = t;
-          bool zero = true, inside = true;
-          int32_t N[3] = {0, 0, 0};
-          for (int d = 0; d < dim; ++d) {
-            dir[d] = tt % 3 - 1;
-            tt /= 3;
-            if (dir[d]) zero = false;
-            N[d] = P[d] + dir[d] * sP;
-            if (N[d] < 0 || N[d] >= box_hi[d]) inside = false;
-          }
-          if (zero || !inside) continue;
-          // exactly one leaf contains the point N: probe level l-1 first,
-          // then finer levels (the neighbour block is already refined: no
-          // action), then coarser ones (the leaf to split)
-          int cover = -1;
-          int32_t am[3];
-          bool finer = false;
-          for (int mlev = l - 1; mlev <= L && cover < 0 && !finer; ++mlev) {
-            align(N, mlev, am);
-            if (S.contains(leaf_key(dim, mlev, am))) {
-              if (mlev == l - 1) cover = mlev;
-              else finer = true;
+      // the neighbour checks depend only on the parent block: the level-l
+      // leaves' parents, each once (sorted by Morton key, first leaf kept)
+      const int64_t nl = (int64_t)bylev[l].size();
+      if (nl == 0) continue;
+      std::vector<uint64_t> pk((size_t)nl);
+      parallel_chunks(nl, 1 << 14, [&](int64_t, int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i) {
+          const auto& a = bylev[l][(size_t)i];
+          int32_t P[3];
+          align(a.data(), l - 1, P);
+          pk[(size_t)i] = S.contains(leaf_key(dim, l, a.data())) ? morton(dim, P) : ~0ull;
+        }
+      });
+      std::vector<uint64_t> keys;
+      std::vector<uint32_t> ids;
+      for (int64_t i = 0; i < nl; ++i)
+        if (pk[(size_t)i] != ~0ull) {
+          keys.push_back(pk[(size_t)i]);
+          ids.push_back((uint32_t)i);
+        }
+      radix_sort_pairs(keys, ids, dim * (L + 1));
+      std::vector<uint32_t> par;
+      for (size_t i = 0; i < keys.size(); ++i)
+        if (i == 0 || keys[i] != keys[i - 1]) par.push_back(ids[i]);
+      // read-only checks in parallel: the neighbour points of every parent
+      // that a leaf coarser than l-1 holds, per chunk in parent order
+      const int64_t np = (int64_t)par.size();
+      const int64_t T = chunk_count(np, 1 << 12);
+      std::vector<std::vector<Req>> req((size_t)T);
+      const int32_t sP = size_at(l - 1);
+      parallel_chunks(np, 1 << 12, [&](int64_t t, int64_t j0, int64_t j1) {
+        for (int64_t j = j0; j < j1; ++j) {
+          int32_t P[3];
+          align(bylev[l][par[(size_t)j]].data(), l - 1, P);
+          for (int tt0 = 0; tt0 < ndir; ++tt0) {
+            int tt = tt0;
+            bool zero = true, inside = true;
+            Req r{{0, 0, 0}};
+            for (int d = 0; d < dim; ++d) {
+              const int dir = tt % 3 - 1;
+              tt /= 3;
+              if (dir) zero = false;
+              r.N[d] = P[d] + dir * sP;
+              if (r.N[d] < 0 || r.N[d] >= box_hi[d]) inside = false;
             }
+            if (zero || !inside) continue;
+            if (coarse_cover(r.N, l) >= 0) req[(size_t)t].push_back(r);
           }
-          for (int mlev = l - 2; mlev >= 0 && cover < 0 && !finer; --mlev) {
-            align(N, mlev, am);
-            if (S.contains(leaf_key(dim, mlev, am))) cover = mlev;
-          }
-          if (cover < 0 || cover >= l - 1) continue;
+        }
+      });
+      // splits in that order, each checked again against the leaves as split
+      // so far: the leaf holding N is refined down to level l-1
+      for (auto& rv : req)
+        for (const Req& r : rv) {
+          const int cover = coarse_cover(r.N, l);
+          if (cover < 0) continue;
+          int32_t am[3];
           for (int mlev = cover; mlev < l - 1; ++mlev) {
-            align(N, mlev, am);
+            align(r.N, mlev, am);
             S.erase(leaf_key(dim, mlev, am));
             int32_t h = size_at(mlev + 1);
             for (int c = 0; c < nc; ++c) {
@@ -311,7 +389,6 @@ struct Builder {
             }
           }
         }
-      }
     }
     // collect and sort by Morton key of the anchor (= depth-first order)
     std::vector<uint64_t> keys;
@@ -359,15 +436,17 @@ struct Builder {
     }
     std::vector<uint64_t> key((size_t)E * nc);
     std::vector<uint32_t> pay((size_t)E * nc);
-    for (int64_t e = 0; e < E; ++e) {
-      int32_t s = size_at(m.leaf_level[e]);
-      for (int a = 0; a < nc; ++a) {
-        int32_t c[3] = {0, 0, 0};
-        for (int d = 0; d < dim; ++d) c[d] = m.leaf_anchor[3 * e + d] + ((a >> d) & 1) * s;
-        key[e * nc + a] = node_key(c);
-        pay[e * nc + a] = (uint32_t)(e * nc + a);
+    parallel_chunks(E, 1 << 14, [&](int64_t, int64_t e0, int64_t e1) {
+      for (int64_t e = e0; e < e1; ++e) {
+        int32_t s = size_at(m.leaf_level[e]);
+        for (int a = 0; a < nc; ++a) {
+          int32_t c[3] = {0, 0, 0};
+          for (int d = 0; d < dim; ++d) c[d] = m.leaf_anchor[3 * e + d] + ((a >> d) & 1) * s;
+          key[e * nc + a] = node_key(c);
+          pay[e * nc + a] = (uint32_t)(e * nc + a);
+        }
       }
-    }
+    });
     radix_sort_pairs(key, pay, node_key_bits());
     elem_corner.assign((size_t)E * nc, -1);
     std::vector<uint64_t> ukey;
@@ -398,38 +477,54 @@ struct Builder {
     // that sits on the boundary of a level-(lmax-1) leaf is hanging.
     KeySet S((size_t)E * 2);
     for (int64_t e = 0; e < E; ++e) S.insert(leaf_key(dim, m.leaf_level[e], &m.leaf_anchor[3 * e]));
+    // the octant (corner direction o) of the coarse leaf holding each node,
+    // found in parallel (read-only lookups), then numbered in node order
+    auto coarse_anchor = [&](const int32_t* c, int o, int32_t S2, int32_t* a) {
+      bool ok = true;
+      for (int d = 0; d < 3; ++d) a[d] = 0;
+      for (int d = 0; d < dim; ++d) {
+        if ((o >> d) & 1) {
+          if (c[d] >= box_hi[d]) ok = false;
+          a[d] = (c[d] / S2) * S2;
+        } else {
+          if (c[d] <= 0) ok = false;
+          a[d] = ((c[d] - 1) / S2) * S2;
+        }
+      }
+      return ok;
+    };
+    std::vector<int8_t> hang_o(NA, -1);
+    parallel_chunks(NA, 1 << 14, [&](int64_t, int64_t n0, int64_t n1) {
+      for (int64_t n = n0; n < n1; ++n) {
+        int lm = maxlev[n];
+        if (lm < 1) continue;
+        const int32_t* c = &all_coords[3 * n];
+        int32_t S2 = size_at(lm - 1);
+        bool odd = false;
+        for (int d = 0; d < dim; ++d)
+          if (c[d] % S2) odd = true;
+        if (!odd) continue;
+        for (int o = 0; o < nc; ++o) {
+          int32_t a[3];
+          if (!coarse_anchor(c, o, S2, a)) continue;
+          if (S.contains(leaf_key(dim, lm - 1, a))) {
+            hang_o[n] = (int8_t)o;
+            break;
+          }
+        }
+      }
+    });
     std::vector<int32_t> hang_of(NA, -1);
     std::vector<std::array<int32_t, 3>> hang_leaf_anchor;
     std::vector<int8_t> hang_leaf_level;
     for (int64_t n = 0; n < NA; ++n) {
-      int lm = maxlev[n];
-      if (lm < 1) continue;
-      const int32_t* c = &all_coords[3 * n];
-      int32_t S2 = size_at(lm - 1);
-      bool odd = false;
-      for (int d = 0; d < dim; ++d)
-        if (c[d] % S2) odd = true;
-      if (!odd) continue;
-      for (int o = 0; o < nc; ++o) {
-        int32_t a[3] = {0, 0, 0};
-        bool ok = true;
-        for (int d = 0; d < dim; ++d) {
-          if ((o >> d) & 1) {
-            if (c[d] >= box_hi[d]) ok = false;
-            a[d] = (c[d] / S2) * S2;
-          } else {
-            if (c[d] <= 0) ok = false;
-            a[d] = ((c[d] - 1) / S2) * S2;
-          }
-        }
-        if (!ok) continue;
-        if (S.contains(leaf_key(dim, lm - 1, a))) {
-          hang_of[n] = (int32_t)hang_leaf_level.size();
-          hang_leaf_level.push_back((int8_t)(lm - 1));
-          hang_leaf_anchor.push_back({a[0], a[1], a[2]});
-          break;
-        }
-      }
+      if (hang_o[n] < 0) continue;
+      const int lm = maxlev[n];
+      int32_t a[3];
+      coarse_anchor(&all_coords[3 * n], hang_o[n], size_at(lm - 1), a);
+      hang_of[n] = (int32_t)hang_leaf_level.size();
+      hang_leaf_level.push_back((int8_t)(lm - 1));
+      hang_leaf_anchor.push_back({a[0], a[1], a[2]});
     }
     // independent numbering in key order
     all_entry.assign(NA, 0);
@@ -704,27 +799,40 @@ struct Builder {
       std::sort(out, out + k);
       return (int)(std::unique(out, out + k) - out);
     };
+    // every leaf's coupled independent nodes (hanging corners replaced by
+    // their parents), sorted and unique: lengths, then the lists, in parallel
+    std::vector<int64_t> eptr(E + 1, 0);
+    parallel_chunks(E, 1 << 14, [&](int64_t, int64_t e0, int64_t e1) {
+      int32_t buf[64];
+      for (int64_t e = e0; e < e1; ++e) eptr[e + 1] = expand(e, buf);
+    });
+    for (int64_t e = 0; e < E; ++e) eptr[e + 1] += eptr[e];
+    std::vector<int32_t> eent((size_t)eptr[E]);
+    parallel_chunks(E, 1 << 14, [&](int64_t, int64_t e0, int64_t e1) {
+      // the raw list (before removing duplicates) may be longer than the
+      // leaf's slot: expand into a buffer, copy the unique entries
+      int32_t buf[64];
+      for (int64_t e = e0; e < e1; ++e) {
+        const int k = expand(e, buf);
+        std::copy(buf, buf + k, &eent[(size_t)eptr[e]]);
+      }
+    });
     std::vector<int32_t> cnt(N + 1, 0);
-    int32_t buf[64];
-    for (int64_t e = 0; e < E; ++e) {
-      int k = expand(e, buf);
-      for (int j = 0; j < k; ++j) ++cnt[buf[j] + 1];
-    }
+    for (int32_t v : eent) ++cnt[v + 1];
     for (int64_t i = 0; i < N; ++i) cnt[i + 1] += cnt[i];
     std::vector<int32_t> inc(cnt[N]);
     std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
-    for (int64_t e = 0; e < E; ++e) {
-      int k = expand(e, buf);
-      for (int j = 0; j < k; ++j) inc[fill[buf[j]]++] = (int32_t)e;
-    }
+    for (int64_t e = 0; e < E; ++e)
+      for (int64_t j = eptr[e]; j < eptr[e + 1]; ++j) inc[fill[eent[(size_t)j]]++] = (int32_t)e;
+    // greedy colouring in node order
     std::vector<int16_t> col(N, -1);
     int maxc = 0;
     for (int64_t i = 0; i < N; ++i) {
       uint64_t used[4] = {0, 0, 0, 0};
       for (int32_t t = cnt[i]; t < cnt[i + 1]; ++t) {
-        int k = expand(inc[t], buf);
-        for (int j = 0; j < k; ++j) {
-          int16_t cj = col[buf[j]];
+        const int64_t e = inc[t];
+        for (int64_t j = eptr[e]; j < eptr[e + 1]; ++j) {
+          int16_t cj = col[eent[(size_t)j]];
           if (cj >= 0) used[cj >> 6] |= 1ull << (cj & 63);
         }
       }
