@@ -420,6 +420,27 @@ def profile_chns(torch):
     print(json.dumps({"profile_run": "chns done"}))
 
 
+def uniform_apply(torch, level):
+    """Pressure apply on a finer uniform octree (level 8: 256^3 leaves, eight
+    waves per SIMD slot in turn): FP64 and FP32 throughput and the brick /
+    combine split by the library's HIP events."""
+    from paper_2107_05123_amd import Context, Mesh
+    mesh = Mesh(dim=3, min_level=level, max_level=level, rule="uniform")
+    x = ci.unit_coords(mesh.node_coords(), level)
+    ctx = Context(mesh, Cn=CN, rho_plus=RHO_P, rho_minus=RHO_M)
+    c, r = ci.drops(0)
+    ctx.set_phase_field(torch.tensor(ci.phi_drops(x, c, r, CN), dtype=torch.float64, device="cuda"))
+    n = mesh.n_nodes
+    xr = torch.tensor(ci.normal_vector(0, n), dtype=torch.float64, device="cuda")
+    out = {"workload": f"3D uniform octree level {level} ({1 << level}^3 Q1 hex, {n:,} nodes), 8 seeded drops, "
+                       "density ratio 1000", "n_elems": mesh.n_elems, "n_dof": n}
+    for prec, v in (("fp64", xr), ("fp32", xr.float())):
+        ms = time_applies(torch, ctx, v)
+        k, comb = kernel_avg_ms(torch, ctx, v, "pp_brick_" + prec)
+        out[prec] = {"gdof_s": n / (ms * 1e-3) / 1e9, "ms": ms, "brick_ms": k, "combine_ms": comb}
+    return out
+
+
 def adaptive_workload(torch, lmax):
     """Adaptive octree, levels 5..lmax refined within 3 Cn of the rising-bubble
     interface (R 0.15, centre (0.5, 0.3, 0.5), Cn 0.01), density ratio 1000:
@@ -748,6 +769,7 @@ def main():
         "host_mesh_build_s": t_mesh,
         "chns": chns_measure(torch, mesh, ctx, phi_d),
     }
+    out["apply_uniform_l8"] = uniform_apply(torch, 8)
     if not args.no_adaptive:
         out["adaptive"] = adaptive_workload(torch, args.adaptive_level)
     if not args.no_cpu_baseline:
