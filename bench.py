@@ -718,6 +718,8 @@ def main():
     for name, kw in (("learned_fcg_every8_fp64", dict(pc="learned", learned_every=8)),
                      ("learned_fcg_every8_mixed_ir", dict(pc="learned", learned_every=8, mode="mixed",
                                                           inner_rtol=1e-4)),
+                     ("learned_fcg_every8_mixed_ru", dict(pc="learned", learned_every=8, mode="mixed_ru",
+                                                          inner_rtol=1e-2)),
                      ("learned_fcg_every_iteration_fp64", dict(pc="learned"))):
         solve_once(torch, ctx, phi_d, b, **kw)
         torch.cuda.synchronize()

@@ -246,8 +246,9 @@ enum { CHNS_PC_JACOBI = 0, CHNS_PC_GMG = 1, CHNS_PC_LEARNED = 2, CHNS_PC_NONE = 
  * previous one's search direction (residual replacement, as in reliable-
  * update CG): p = z + beta p with beta = (r.z)_new / (r.z)_old of the
  * unnormalised residuals, so the Krylov process is not restarted when the
- * FP64 residual replaces the FP32 one.  Flexible CG (the learned
- * preconditioner) always restarts.                                         */
+ * FP64 residual replaces the FP32 one (flexible CG with the learned
+ * preconditioner: the Polak-Ribiere beta, z.(r_new - r_prev) / (r.z)_prev,
+ * with the previous inner system's vectors rescaled to the new one).       */
 enum { CHNS_MODE_FP64 = 0, CHNS_MODE_MIXED_IR = 1, CHNS_MODE_MIXED_RU = 2 };
 
 typedef struct chns_solve_opts {

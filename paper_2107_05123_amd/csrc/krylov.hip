@@ -49,7 +49,7 @@ __device__ void block_partials(double (&v)[NV], double* partials) {
   }
 }
 
-enum FinMode { FIN_STORE = 0, FIN_CG_INIT = 1, FIN_CG_UPDATE = 2, FIN_FCG_UPDATE = 3 };
+enum FinMode { FIN_STORE = 0, FIN_CG_INIT = 1, FIN_CG_UPDATE = 2, FIN_FCG_UPDATE = 3, FIN_FCG_CONT = 4 };
 
 // Fixed-order totals of nv partial arrays, then the scalar update of `mode`.
 // 1024 threads, each with four independent running sums, so the few thousand
@@ -86,10 +86,13 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const double* partials
   if (threadIdx.x != 0) return;
   if (mode == FIN_STORE) {
     *out = tot[0];
-  } else if (mode == FIN_CG_INIT) {
+  } else if (mode == FIN_CG_INIT || mode == FIN_FCG_CONT) {
     sc->rz = tot[0];
     sc->rr = tot[1];
     sc->it = 0;
+    // flexible CG continued across a residual replacement: z.r_old for the
+    // continued direction (see k_cont_p_flex)
+    if (mode == FIN_FCG_CONT) sc->beta = tot[2];
     // converged, or breakdown: a non-finite residual or r.z <= 0 (an
     // indefinite or vanishing preconditioner output) ends the solve at x_0
     sc->done = (tot[1] <= sc->tol2 || !(tot[1] == tot[1]) || !(tot[0] > 0.0)) ? 1 : 0;
@@ -229,12 +232,17 @@ __global__ void k_cg_p(T* p, const T* z, int64_t n, const DevScalars* sc, int ch
     p[i] = z[i] + beta * p[i];
 }
 
-// continued search direction after a residual replacement:
-// p = z + coef (r.z) p, coef prepared on the host
+// continued search direction after a residual replacement, in the units of
+// the new inner system (right-hand side r / |r_new|; the previous one's was
+// r / |r_old|, scale = |r_new| / |r_old|): CG p = z + scale (r.z) / rz_prev p;
+// flexible CG (Polak-Ribiere) p = z + (scale (r.z) - z.r_prev) / rz_prev p
+// with r_prev the previous inner system's last residual but one (z.r_prev in
+// sc->beta) and rz_prev its r.z
 template <typename T>
-__global__ void k_cont_p(T* p, const T* z, int64_t n, const DevScalars* sc, double coef) {
+__global__ void k_cont_p(T* p, const T* z, int64_t n, const DevScalars* sc, double scale, double inv_rz_prev,
+                         int flexible) {
   if (sc->done) return;
-  const T beta = (T)(coef * sc->rz);
+  const T beta = (T)((scale * sc->rz - (flexible ? sc->beta : 0.0)) * inv_rz_prev);
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
     p[i] = z[i] + beta * p[i];
 }
@@ -431,12 +439,16 @@ int apply_pc(Ctx& c, int pc, const T* r, T* z, hipStream_t s, const T* dinv = nu
 // every > 0 (flexible only) the preconditioner `pc` is applied to r_0 and
 // after every `every`-th iteration, Jacobi after the others.
 //
-// cont_coef != 0 continues the search direction left in p by the previous
-// call instead of starting from p = z (residual replacement, see the mixed
-// solve): p = z + cont_coef (r.z) p.
+// cont_scale != 0 continues the search direction left in p (and, flexible,
+// the residual left in r_old) by the previous call instead of starting from
+// p = z (residual replacement, see the mixed solve); cont_scale is the ratio
+// of the new to the previous normalisation of the right-hand side and
+// cont_inv_rz the reciprocal of the previous call's last r.z but one; the
+// schedule of `every` then counts on from sched_offset iterations.
 template <typename T>
 int pcg(Ctx& c, int op, const T* b, T* x, int pc, const T* dinv, bool flexible, double tol2, int max_it, int depth,
-        bool graphs, hipStream_t s, int* iters, double* rr_out, int every = 0, double cont_coef = 0.0) {
+        bool graphs, hipStream_t s, int* iters, double* rr_out, int every = 0, double cont_scale = 0.0,
+        double cont_inv_rz = 0.0, int sched_offset = 0) {
   // all fields of the operator form one vector (block-diagonal operators)
   const int64_t n = c.dm.n * op_fields(op, c.dm.dim);
   const int prec = sizeof(T) == 8 ? CHNS_FP64 : CHNS_FP32;
@@ -454,20 +466,23 @@ int pcg(Ctx& c, int op, const T* b, T* x, int pc, const T* dinv, bool flexible, 
   k_init_scalars<<<1, 1, 0, s>>>(c.sc, tol2, max_it);
   ApplyOut plain{};
   if ((rc = launch_apply(c, op, prec, x, q, s, plain))) return rc;
-  const bool cont = cont_coef != 0.0;
+  const bool cont = cont_scale != 0.0;
+  const bool cont_flex = cont && flexible && !fused_pc;
   if (fused_pc) {
     k_cg_init<T><<<g, kThreads, 0, s>>>(b, q, r, z, cont ? nullptr : p, pc == PCK_JACOBI ? dinv : nullptr, n, c.sc,
                                         c.partials, c.counter);
   } else {
     k_cg_init_nopc<T><<<g, kThreads, 0, s>>>(b, q, r, n, c.partials);
-    if ((rc = apply_pc<T>(c, pc, r, z, s, dinv, n))) return rc;
-    k_dot_rz<T><<<g, kThreads, 0, s>>>(r, z, nullptr, n, c.sc, c.partials, 0);
+    // on a schedule, r_0 gets `pc` unless a continued solve is between turns
+    const int pc0 = flexible && every > 0 && sched_offset % every != 0 ? PCK_JACOBI_FLEX : pc;
+    if ((rc = apply_pc<T>(c, pc0, r, z, s, dinv, n))) return rc;
+    k_dot_rz<T><<<g, kThreads, 0, s>>>(r, z, cont_flex ? r_old : nullptr, n, c.sc, c.partials, 0);
     if (!cont) k_copy<T><<<g, kThreads, 0, s>>>(p, z, n);
   }
   CHNS_HIP(hipGetLastError());
-  if ((rc = fin(c, s, g, 2, FIN_CG_INIT, nullptr, 0))) return rc;
+  if ((rc = fin(c, s, g, cont_flex ? 3 : 2, cont_flex ? FIN_FCG_CONT : FIN_CG_INIT, nullptr, 0))) return rc;
   if (cont) {
-    k_cont_p<T><<<g, kThreads, 0, s>>>(p, z, n, c.sc, cont_coef);
+    k_cont_p<T><<<g, kThreads, 0, s>>>(p, z, n, c.sc, cont_scale, cont_inv_rz, cont_flex ? 1 : 0);
     CHNS_HIP(hipGetLastError());
   }
   ApplyOut fused{};
@@ -522,7 +537,7 @@ int pcg(Ctx& c, int op, const T* b, T* x, int pc, const T* dinv, bool flexible, 
   bool done = false;
   int it = 0;
   while (true) {
-    const bool jac = sched && (it + 1) % every != 0;
+    const bool jac = sched && (sched_offset + it + 1) % every != 0;
     hipGraphExec_t ex = jac ? exec_j : exec;
     if (ex) {
       CHNS_HIP(hipGraphLaunch(ex, s));
@@ -722,11 +737,12 @@ int solve_pressure_impl(Ctx& c, const double* b_in, double* x_out, const chns_so
       const bool fcg = pck == PCK_LEARNED;
       const int every = fcg ? o.learned_every : 0;
       const int cap = fcg && every == 0 ? std::min(o.max_it - total, kLearnedCap) : o.max_it - total;
-      // continued direction: p = z + beta (rn_prev / rn) p with the CG beta
-      // of the unnormalised residuals, (rn^2 r.z) / (rn_prev^2 rz_prev)
-      const double coef = replace && can_continue && !fcg ? (rn / rn_prev) / rz_prev : 0.0;
+      // continued direction: this inner system is normalised by rn, the
+      // previous one by rn_prev
+      const bool cont = replace && can_continue;
       rc = pcg<float>(c, CHNS_OP_PRESSURE, r32, d32, pck, c.diag32, fcg, itol * itol, cap,
-                      every > 0 ? o.check_every : depth, graphs, s, &it, &rri, every, coef);
+                      every > 0 ? o.check_every : depth, graphs, s, &it, &rri, every,
+                      cont ? rn / rn_prev : 0.0, cont ? 1.0 / rz_prev : 0.0, cont ? total : 0);
       if (rc) return rc;
       total += it;
       rn_prev = rn;
@@ -736,6 +752,7 @@ int solve_pressure_impl(Ctx& c, const double* b_in, double* x_out, const chns_so
         // stagnation guard: the remaining refinement steps use Jacobi
         st.fallback = 1;
         pck = PCK_JACOBI;
+        can_continue = false;
       }
       k_ir_correct<<<g, kThreads, 0, s>>>(x, d32, rn, n);
       CHNS_HIP(hipGetLastError());
