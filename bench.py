@@ -545,12 +545,14 @@ def learned_distribution(torch, ctx, x_unit, seeds):
 
 
 def bubble_steps(torch, lmax, nsteps, ch_pc="block", restart=16, vp_pc="jacobi", modes=("fp64", "mixed"),
-                 remesh_every=0):
+                 remesh_every=0, max_seconds=0.0):
     """Projection time steps of the 3D rising bubble (density ratio 1000,
     viscosity ratio 100, Re 35, We 10, Cn 0.005, dt 5e-4) on the adaptive
     octree of levels 5..lmax refined within 3 Cn of the interface; with
     remesh_every = K > 0 the mesh is rebuilt around |phi| <= 0.95 after every
-    K steps and the state carried over by the intergrid transfer."""
+    K steps and the state carried over by the intergrid transfer.  With
+    max_seconds > 0 no new step starts after that much wall time since the
+    start (the steps taken are reported)."""
     from paper_2107_05123_amd import Context, Mesh, Transfer
     cn = 0.005
     t0 = time.time()
@@ -575,6 +577,9 @@ def bubble_steps(torch, lmax, nsteps, ch_pc="block", restart=16, vp_pc="jacobi",
            "n_elems": mesh.n_elems, "n_nodes": n, "host_mesh_build_s": t_mesh, "steps": [], "remesh": []}
     for mode in modes:
         for k in range(nsteps):
+            if max_seconds > 0 and time.time() - t0 > max_seconds:
+                out["stopped_at_time_limit"] = {"mode": mode, "steps_done": k}
+                break
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             s = ctx.advance_step(st, pp_pc="gmg", pp_mode=mode, ch_pc=ch_pc, restart=restart, vp_pc=vp_pc)
@@ -629,6 +634,8 @@ def main():
                     help="uniform_l7: the benchmark line; adaptive: levels 5..--max-level band mesh solves; "
                          "bubble_steps: projection steps of the 3D rising bubble")
     ap.add_argument("--max-level", type=int, default=10)
+    ap.add_argument("--max-seconds", type=float, default=0.0,
+                    help="bubble_steps: start no step after this much wall time (0: no limit)")
     ap.add_argument("--restart", type=int, default=20,
                     help="bubble_steps: GMRES restart length (short cycles keep the Gram-Schmidt cost of the "
                          "large CH and momentum bases down)")
@@ -666,7 +673,7 @@ def main():
         return
     if args.workload == "bubble_steps":
         print(json.dumps(bubble_steps(torch, args.max_level, args.steps, args.ch_pc, args.restart, args.vp_pc,
-                                      tuple(args.pp_modes.split(",")), args.remesh_every)))
+                                      tuple(args.pp_modes.split(",")), args.remesh_every, args.max_seconds)))
         return
     if args.profile_run == "chns":
         profile_chns(torch)
