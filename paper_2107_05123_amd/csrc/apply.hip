@@ -41,6 +41,16 @@ __device__ __forceinline__ double rcp_t(double r) {
   return __builtin_fma(y, e, y);
 }
 __device__ __forceinline__ float rcp_t(float r) { return __builtin_amdgcn_rcpf(r); }
+// 1/sqrt(x) for x > 0: hardware estimate refined by two Newton steps
+// y <- y + y (1 - x y^2) / 2 (FP64), the hardware value alone in FP32
+__device__ __forceinline__ double rsqrt_t(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = __builtin_fma(-x * y, y, 1.0);
+  y = __builtin_fma(0.5 * y, e, y);
+  e = __builtin_fma(-x * y, y, 1.0);
+  return __builtin_fma(0.5 * y, e, y);
+}
+__device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
 // Pull back of the (scaled) phase field to its physical range.  FP64 fields
 // hold phi in [-lim, lim]; FP32 fields hold 1 + phi in [0, 2 lim].
 __device__ __forceinline__ double clamp_t(double v, double lim) { return fmin(fmax(v, -lim), lim); }
@@ -593,7 +603,7 @@ __device__ __forceinline__ void el_vp2(const CV& cv, const Phys& P, int lev, T (
     const T rho = ph.ra * sc + ph.rb;
     const T eta = ph.ea * sc + ph.eb;
     const T inside = (s > ph.lo && s < ph.hi) ? T(1) : T(0);
-    const T irho = T(1) / rho;
+    const T irho = rcp_t(rho);
     T b[DIM], g[DIM], uu = T(0), uJ = T(0);
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
@@ -604,7 +614,7 @@ __device__ __forceinline__ void el_vp2(const CV& cv, const Phys& P, int lev, T (
       g[d] = ph.ea * gs * gph[d] * inside * i2re;
     }
     const T r = eta * irho * ire;
-    const T tau = T(1) / sqrt(tau_c + gs2 * uu + gs2 * uJ * irho * rhope + visc_c * r * r);
+    const T tau = rsqrt_t(tau_c + gs2 * uu + gs2 * uJ * irho * rhope + visc_c * r * r);
     const T k = eta * i2re;
     // the components in turn
 #pragma unroll
