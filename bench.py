@@ -37,6 +37,7 @@ METRIC = "pressure-solve time to 1e-8 rel. residual & GDoF/s apply, plain vs lea
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (fma) x 2.4 GHz
 FP32_PEAK_TFLOPS = 78.6   # same lane count without packed FP32 (packed math is not used)
+FP32_PACKED_PEAK_TFLOPS = 157.3  # the published FP32 vector peak (packed FP32)
 # algorithmic work of one trilinear-hex pressure-Poisson leaf, sum-factorised:
 # phase field to 8 Gauss points (72), 8 x (clamp 2 + fma 2 + reciprocal 9),
 # 3 x (differences 4 + 2 transforms 24 + coefficient sums/products 8 + 2
@@ -240,6 +241,12 @@ def apply_roofline(n_elems, n_dof, brick_ms, combine_ms, es=8):
                  "hbm_frac_algorithmic": frac_hbm, "alu_frac": frac_alu, "gdof_s": n_dof / (ms * 1e-3) / 1e9,
                  "brick_only": {"kernel_ms": brick_ms, "alu_frac": flops / (brick_ms * 1e-3) / 1e12 / peak_alu,
                                 "hbm_frac_algorithmic": nbytes / (brick_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}})
+    if es == 4:
+        # the published FP32 vector peak counts packed FP32 (two per lane),
+        # which this build does not use
+        roof["alu_frac_vs_packed_peak"] = ach_flops / FP32_PACKED_PEAK_TFLOPS
+    if traffic:
+        roof["traffic_over_algorithmic"] = traffic / nbytes
     return roof
 
 
