@@ -554,103 +554,167 @@ __device__ __forceinline__ void el_chj(const CV& cv, const Phys& P, int lev, T (
 // b = u^/2 + J/(2 Pe rho~), g = grad eta~/(2 Re) and k = eta~/(2 Re):
 //   R_lin(v) = rho~ (v/dt + b.grad v) - g.grad v,
 //   Galerkin part  N_a rho~ (v/dt + b.grad v) + k grad N_a . grad v,
-//   stabilisation  (b.grad N_a) tau_m R_lin(v);
-// the coefficients are formed once per Gauss point and applied to the
-// components in turn.  cv(f, a): f < DIM the velocity components, then
-// phi~ (stored as in PhaseT), mu~, u^.
-template <int DIM, typename T, class CV>
-__device__ __forceinline__ void el_vp2(const CV& cv, const Phys& P, int lev, T (*y)[1 << DIM]) {
-  constexpr int NC = 1 << DIM;
+//   stabilisation  (b.grad N_a) tau_m R_lin(v).
+// Sum-factorised: every field's values at the Gauss points come from the
+// two-point transforms (scaled by S = 2^d), its gradient along d from the
+// differences along d carried through the transforms of the other
+// directions (constant along d, so shared by the two Gauss points of a
+// column); the test functions are applied by the same transforms
+// transposed.  The coefficients are formed once per Gauss point (the phase
+// field clamped, tau_m, b scaled by 2/h, grad phi~ per column with the
+// pull-back mask per point), then each component is transformed, combined
+// and handed to out(f, y) in turn.  cv(f, a): f < DIM the velocity
+// components, then phi~ (stored as in PhaseT), mu~, u^.
+template <int DIM, typename T, class CV, class OUT>
+__device__ __forceinline__ void el_vp(const CV& cv, const Phys& P, int lev, const OUT& out) {
+  constexpr int NC = 1 << DIM, H = NC / 2;
   const PhaseT<T> ph = phase_of<T>(P);
-  const T gs = T(ldexp(1.0, lev + 1));
-  const T w = T(ldexp(1.0, -(lev + 1) * DIM));
+  // powers of two (2/h = 2^e1, det J = 2^-d e1, S = 2^d) are applied with
+  // ldexp: exact, and no per-level constants held in registers
+  const int e1 = lev + 1;
+  const double iS = ldexp(1.0, -DIM);  // 1/S
   const T idt = T(1.0 / P.dt);
-  const T i2re = T(1.0 / (2.0 * P.Re));
-  const T cJ = T(P.cJ);
-  const T i2pe = T(1.0 / (2.0 * P.Pe));
-  const T gs2 = gs * gs;
+  // k (2/h)^2 = (ea s + eb) / (2 Re) (2/h)^2; grad eta~ / (2 Re) (2/h) per
+  // transformed column; J / (2 Pe) per transformed column
+  const T kea = T(P.gam / (2.0 * P.Re)), keb = T(ph.eb / (2.0 * P.Re));
+  const T cgp = T(P.gam / (2.0 * P.Re) * iS);
+  const T cJ = T(P.cJ * iS / (2.0 * P.Pe));
   const T tau_c = T(4.0 / (P.dt * P.dt));
-  const T visc_c = T(P.C_I * DIM) * gs2 * gs2;
-  const T rhope = T(1.0 / P.Pe);
+  const T visc_c = T(P.C_I * DIM);
   const T ire = T(1.0 / P.Re);
+  const T iSt = T(iS);
+
+  // ---- coefficients at the Gauss points
+  T sc[NC], tau[NC], bs[DIM][NC], gp[DIM][H];
+  unsigned inside = 0;
+  {
+    T v[NC];
 #pragma unroll
-  for (int f = 0; f < DIM; ++f)
-#pragma unroll
-    for (int a = 0; a < NC; ++a) y[f][a] = T(0);
-#pragma unroll
-  for (int q = 0; q < NC; ++q) {
-    // keep the LDS reads of each Gauss point after the previous one's
-    // arithmetic (bounds the registers held at once)
-    asm volatile("" ::: "memory");
-    // coefficient fields at q
-    T s = T(0), gph[DIM], gmu[DIM], uh[DIM];
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) gph[d] = gmu[d] = uh[d] = T(0);
-#pragma unroll
-    for (int a = 0; a < NC; ++a) {
-      const T n = T(refN<DIM>(q, a));
-      const T cp = cv(DIM, a), cm = cv(DIM + 1, a);
-      s += n * cp;
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) {
-        const T dn = T(refD<DIM>(q, a, d));
-        gph[d] += dn * cp;
-        gmu[d] += dn * cm;
-        uh[d] += n * cv(DIM + 2 + d, a);
-      }
-    }
-    const T sc = fmin(fmax(s, ph.lo), ph.hi);
-    const T rho = ph.ra * sc + ph.rb;
-    const T eta = ph.ea * sc + ph.eb;
-    const T inside = (s > ph.lo && s < ph.hi) ? T(1) : T(0);
-    const T irho = rcp_t(rho);
-    T b[DIM], g[DIM], uu = T(0), uJ = T(0);
+    for (int a = 0; a < NC; ++a) v[a] = cv(DIM, a);
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-      const T J = cJ * gs * gmu[d];
-      uu += uh[d] * uh[d];
-      uJ += uh[d] * J;
-      b[d] = T(0.5) * uh[d] + J * i2pe * irho;
-      g[d] = ph.ea * gs * gph[d] * inside * i2re;
-    }
-    const T r = eta * irho * ire;
-    const T tau = rsqrt_t(tau_c + gs2 * uu + gs2 * uJ * irho * rhope + visc_c * r * r);
-    const T k = eta * i2re;
-    // the components in turn
 #pragma unroll
-    for (int f = 0; f < DIM; ++f) {
-      asm volatile("" ::: "memory");
-      T v = T(0), gv[DIM];
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) gv[d] = T(0);
-#pragma unroll
-      for (int a = 0; a < NC; ++a) {
-        const T xa = cv(f, a);
-        v += T(refN<DIM>(q, a)) * xa;
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) gv[d] += T(refD<DIM>(q, a, d)) * xa;
+      for (int r = 0; r < H; ++r) {
+        const int lo = insert0(r, d), hi = lo | (1 << d);
+        gp[d][r] = v[hi] - v[lo];
       }
-      T bg = T(0), gg = T(0);
+      stage<H, 1>(gp[d]);
+      if constexpr (H > 2) stage<H, 2>(gp[d]);
+#pragma unroll
+      for (int r = 0; r < H; ++r) gp[d][r] = ldexp(gp[d][r] * cgp, 2 * e1);
+    }
+    all_stages<DIM>(v);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const T s = v[q] * iSt;
+      sc[q] = fmin(fmax(s, ph.lo), ph.hi);
+      if (s > ph.lo && s < ph.hi) inside |= 1u << q;
+    }
+  }
+  asm volatile("" ::: "memory");
+  {
+    T J[DIM][H];
+    {
+      T m[NC];
+#pragma unroll
+      for (int a = 0; a < NC; ++a) m[a] = cv(DIM + 1, a);
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
-        gv[d] *= gs;
-        bg += b[d] * gv[d];
-        gg += g[d] * gv[d];
-      }
-      const T G = rho * (v * idt + bg);
-      const T S = tau * (G - gg);
-      T F[DIM];
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) F[d] = w * (k * gv[d] + b[d] * S);
-      const T wG = w * G;
+        for (int r = 0; r < H; ++r) {
+          const int lo = insert0(r, d), hi = lo | (1 << d);
+          J[d][r] = m[hi] - m[lo];
+        }
+        stage<H, 1>(J[d]);
+        if constexpr (H > 2) stage<H, 2>(J[d]);
 #pragma unroll
-      for (int a = 0; a < NC; ++a) {
-        T t = T(refN<DIM>(q, a)) * wG;
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) t += T(refD<DIM>(q, a, d)) * gs * F[d];
-        y[f][a] += t;
+        for (int r = 0; r < H; ++r) J[d][r] = ldexp(J[d][r] * cJ, e1);
       }
     }
+    T irho[NC], uu[NC], uJ[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      irho[q] = rcp_t(ph.ra * sc[q] + ph.rb);
+      uu[q] = uJ[q] = T(0);
+    }
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      asm volatile("" ::: "memory");
+      T u[NC];
+#pragma unroll
+      for (int a = 0; a < NC; ++a) u[a] = cv(DIM + 2 + d, a);
+      all_stages<DIM>(u);
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        const int r = (q & ((1 << d) - 1)) | ((q >> (d + 1)) << d);
+        const T uh = u[q] * iSt;
+        const T j2 = J[d][r];  // J / (2 Pe)
+        uu[q] = fma_t(uh, uh, uu[q]);
+        uJ[q] = fma_t(uh, j2, uJ[q]);
+        bs[d][q] = ldexp(fma_t(j2, irho[q], T(0.5) * uh), e1);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const T r = (ph.ea * sc[q] + ph.eb) * irho[q] * ire;
+      // u^.J / (Pe rho~) = 2 u^.(J / (2 Pe)) / rho~
+      tau[q] = rsqrt_t(tau_c + ldexp(fma_t(T(2) * uJ[q], irho[q], uu[q]), 2 * e1) + ldexp(visc_c * r * r, 4 * e1));
+    }
+  }
+  // ---- the components in turn
+#pragma unroll
+  for (int f = 0; f < DIM; ++f) {
+    asm volatile("" ::: "memory");
+    T v[NC], g[DIM][H], fs[DIM][H];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) v[a] = cv(f, a);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+#pragma unroll
+      for (int r = 0; r < H; ++r) {
+        const int lo = insert0(r, d), hi = lo | (1 << d);
+        g[d][r] = v[hi] - v[lo];
+        fs[d][r] = T(0);
+      }
+      stage<H, 1>(g[d]);
+      if constexpr (H > 2) stage<H, 2>(g[d]);
+    }
+    all_stages<DIM>(v);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const T rho = ph.ra * sc[q] + ph.rb;
+      const T kg = ldexp(fma_t(kea, sc[q], keb), 2 * e1);
+      T Gh = idt * v[q], gg = T(0);
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const int r = (q & ((1 << d) - 1)) | ((q >> (d + 1)) << d);
+        Gh = fma_t(bs[d][q], g[d][r], Gh);
+        gg = fma_t(gp[d][r], g[d][r], gg);
+      }
+      const T A = rho * Gh;
+      const T Tq = tau[q] * (((inside >> q) & 1u) ? A - gg : A);
+      v[q] = A;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const int r = (q & ((1 << d) - 1)) | ((q >> (d + 1)) << d);
+        fs[d][r] = fma_t(kg, g[d][r], fma_t(bs[d][q], Tq, fs[d][r]));
+      }
+    }
+    all_stages<DIM>(v);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      stage<H, 1>(fs[d]);
+      if constexpr (H > 2) stage<H, 2>(fs[d]);
+#pragma unroll
+      for (int r = 0; r < H; ++r) {
+        const int lo = insert0(r, d), hi = lo | (1 << d);
+        v[hi] += fs[d][r];
+        v[lo] -= fs[d][r];
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < NC; ++a) v[a] = ldexp(v[a], -(e1 + 2) * DIM);  // det J / S^2
+    out(f, v);
   }
 }
 
@@ -974,7 +1038,16 @@ __device__ __forceinline__ void brick_body(const BrickArgs<T>& a) {
       if constexpr (OP == K_CH_JAC) {
         el_chj<DIM, T>(cv, a.phys, lev, ye);
       } else if constexpr (OP == K_VP) {
-        el_vp2<DIM, T>(cv, a.phys, lev, ye);
+        // each component's corner values go to the node accumulators as
+        // soon as they are formed
+        el_vp<DIM, T>(cv, a.phys, lev, [&](int f, const T* yf) {
+#pragma unroll
+          for (int c = 0; c < NH; ++c) {
+            const int p = (ix + (c & 1)) + (DIM == 3 ? (iy + ((c >> 1) & 1)) * (B + 1) : 0);
+            accn[bl][f][c][p] = yf[c] + carry[f][c];
+            carry[f][c] = yf[c + NH];
+          }
+        });
       } else if constexpr (OP == K_PP || OP == K_PPS) {
         elem_pp<DIM, T>(xc[0], cc[0], A, Bc, ye[0]);
         if constexpr (OP == K_PPS) {
@@ -1008,14 +1081,16 @@ __device__ __forceinline__ void brick_body(const BrickArgs<T>& a) {
       } else {
         el_energy<DIM>(cc, a.phys, gs, wdet, ye);
       }
+      if constexpr (OP != K_VP) {
 #pragma unroll
-      for (int f = 0; f < NO; ++f)
+        for (int f = 0; f < NO; ++f)
 #pragma unroll
-        for (int c = 0; c < NH; ++c) {
-          const int p = (ix + (c & 1)) + (DIM == 3 ? (iy + ((c >> 1) & 1)) * (B + 1) : 0);
-          accn[bl][f][c][p] = ye[f][c] + carry[f][c];
-          carry[f][c] = ye[f][c + NH];
-        }
+          for (int c = 0; c < NH; ++c) {
+            const int p = (ix + (c & 1)) + (DIM == 3 ? (iy + ((c >> 1) & 1)) * (B + 1) : 0);
+            accn[bl][f][c][p] = ye[f][c] + carry[f][c];
+            carry[f][c] = ye[f][c + NH];
+          }
+      }
     }
     __syncthreads();
     // values of layer ez + 2 (loads in flight since the previous layer) go to
