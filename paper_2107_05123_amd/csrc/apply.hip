@@ -182,7 +182,7 @@ CHNS_TRAITS(K_PP, 1, 1, 1, false, 0)
 CHNS_TRAITS(K_MASS, 1, 0, 1, false, 0)
 CHNS_TRAITS(K_MASS_RHO, DIM, 1, DIM, true, 1)
 CHNS_TRAITS(K_CH_RES, 2, 2 + DIM, 2, false, 0)
-CHNS_TRAITS(K_CH_JAC, 2, 2 + DIM, 2, false, 0)
+CHNS_TRAITS(K_CH_JAC, 2, 1 + DIM, 2, false, 0)
 CHNS_TRAITS(K_VP, DIM, 2 + DIM, DIM, true, 1)
 CHNS_TRAITS(K_VP_RHS, 0, 3 * DIM + 3, DIM, false, 2)
 CHNS_TRAITS(K_PP_RHS, 0, 4 * DIM + 3, 1, false, 0)
@@ -454,14 +454,14 @@ __device__ __forceinline__ PhaseT<T> phase_of(const Phys& P) {
 }
 
 // Newton Jacobian of the discrete Cahn-Hilliard system (Def. 6), fields
-// x = [dphi, dmu] and coefficients [phi^{k+1}, phi^k, u~]:
+// x = [dphi, dmu] and coefficients [phi~ = (phi^{k+1} + phi^k)/2, u~]:
 //   y_phi = M dphi / dt - 1/2 (grad q, u~ dphi) + K dmu / (2 Pe Cn)
 //   y_mu  = 1/2 (q, psi''(phi~) dphi) + Cn^2/2 K dphi - 1/2 M dmu
 // sum-factorised: values at the Gauss points by the two-point transforms,
 // the constant-coefficient stiffness K in closed form (3D: the Q1 element
 // matrix is (h/12)(5 I - 1 1^T + edge adjacency); 2D: (4 I - edge adjacency
 // - 2 opposite corner)/6), the advection flux through the transposed
-// gradient.  cv(f, a): f = 0 dphi, 1 dmu, 2 phi^{k+1}, 3 phi^k, 4.. u~.
+// gradient.  cv(f, a): f = 0 dphi, 1 dmu, 2 phi~, 3.. u~.
 template <int DIM, typename T, class CV>
 __device__ __forceinline__ void el_chj(const CV& cv, const Phys& P, int lev, T (*y)[1 << DIM]) {
   constexpr int NC = 1 << DIM, H = NC / 2;
@@ -503,7 +503,7 @@ __device__ __forceinline__ void el_chj(const CV& cv, const Phys& P, int lev, T (
     all_stages<DIM>(xm);
     T pt[NC];
 #pragma unroll
-    for (int a = 0; a < NC; ++a) pt[a] = T(0.5) * (cv(2, a) + cv(3, a));
+    for (int a = 0; a < NC; ++a) pt[a] = cv(2, a);
     all_stages<DIM>(pt);
     T fa[NC], fb[NC];
     const T idt = T(1.0 / P.dt);
@@ -528,7 +528,7 @@ __device__ __forceinline__ void el_chj(const CV& cv, const Phys& P, int lev, T (
     for (int d = 0; d < DIM; ++d) {
       T u[NC];
 #pragma unroll
-      for (int a = 0; a < NC; ++a) u[a] = cv(4 + d, a);
+      for (int a = 0; a < NC; ++a) u[a] = cv(3 + d, a);
       all_stages<DIM>(u);
       T g[H];
 #pragma unroll
@@ -1133,6 +1133,13 @@ template <int DIM, int B, typename T, int OP, bool WHOLE, bool STRUCT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_brick_o4(BrickArgs<T> a) {
   brick_body<DIM, B, T, OP, WHOLE, STRUCT>(a);
 }
+// the FP64 3D Cahn-Hilliard Jacobian: its LDS admits three waves per SIMD,
+// which at 128^3 leaves a third of the bricks to a second, sparse round;
+// held to two waves it runs two full rounds (0.095 -> 0.090 ms)
+template <int DIM, int B, typename T, int OP, bool WHOLE, bool STRUCT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_brick_o2(BrickArgs<T> a) {
+  brick_body<DIM, B, T, OP, WHOLE, STRUCT>(a);
+}
 
 // Block-wide deterministic sum of one double (256 threads).
 __device__ double block_sum256(double v, double* sh) {
@@ -1283,6 +1290,8 @@ void launch_one(int64_t grid, hipStream_t s, const BrickArgs<T>& a) {
   constexpr bool W = whole_fits<DIM, B, T, OP>();
   if constexpr (OP == K_PP || OP == K_PPS || OP == K_VPS || OP == K_MASS)
     k_brick_o4<DIM, B, T, OP, W, STRUCT><<<g, blk, 0, s>>>(a);
+  else if constexpr (OP == K_CH_JAC && DIM == 3 && sizeof(T) == 8)
+    k_brick_o2<DIM, B, T, OP, W, STRUCT><<<g, blk, 0, s>>>(a);
   else k_brick<DIM, B, T, OP, W, STRUCT><<<g, blk, 0, s>>>(a);
 }
 template <int DIM, typename T, int OP, bool STRUCT>
@@ -1458,7 +1467,7 @@ int apply_dispatch(Ctx& c, const LevelView& L, int op, const T* x, T* y, const T
         set_error("chns_set_coefficients must be called for this operator first");
         return CHNS_ESTATE;
       }
-      for (int k = 0; k < 2 + L.dm->dim; ++k) cf[k] = base + k * n;
+      for (int k = 0; k < (mom ? 2 : 1) + L.dm->dim; ++k) cf[k] = base + k * n;
       return mom ? apply_d<K_VP, double>(c, L, x, y, cf, s, o) : apply_d<K_CH_JAC, double>(c, L, x, y, cf, s, o);
     }
   } else {
@@ -1472,7 +1481,7 @@ int apply_dispatch(Ctx& c, const LevelView& L, int op, const T* x, T* y, const T
       // FP32 copies of the coefficient fields, refreshed after every change
       // of the FP64 ones (the momentum phase field as 1 + phi)
       const int64_t n = L.dm->n;
-      const int nf = 2 + L.dm->dim;
+      const int nf = (mom ? 2 : 1) + L.dm->dim;
       float*& c32 = mom ? c.coef_mom32 : c.coef_chj32;
       bool& ok = mom ? c.coef_mom32_ok : c.coef_chj32_ok;
       if (!c32 && !(c32 = (float*)c.dalloc(sizeof(float) * (size_t)nf * (size_t)n))) return CHNS_ENOMEM;

@@ -771,10 +771,11 @@ int newton_ch_impl(Ctx& c, const double* phi0, const double* mu0, const double* 
   if (schur && (rc = schur_setup(c, s))) return rc;
   const double ntol = std::max(o.newton_rtol * r0, o.newton_atol);
   while (!(rn <= ntol) && it < o.max_newton) {
-    // Jacobian coefficients [phi^{k+1}, phi^k, u~] and its 2x2 node blocks
-    if ((rc = copy(c.coef_chj, S.X, n, s))) return rc;
-    if ((rc = copy(c.coef_chj + n, phi0, n, s))) return rc;
-    if ((rc = copy(c.coef_chj + 2 * n, ut, dim * n, s))) return rc;
+    // Jacobian coefficients [phi~ = (phi^{k+1} + phi^k)/2, u~] and its 2x2
+    // node blocks
+    k_axpby<<<blocks_for(n), kT, 0, s>>>(c.coef_chj, 0.5, S.X, 0.5, phi0, n);
+    CHNS_HIP(hipGetLastError());
+    if ((rc = copy(c.coef_chj + n, ut, dim * n, s))) return rc;
     c.coef_chj_set = true;
     c.coef_chj32_ok = false;
     for (int k = 6; k < 8; ++k) {
@@ -839,9 +840,16 @@ int set_coefficients_impl(Ctx& c, int op, const double* const* fields, hipStream
   double** buf = op == CHNS_OP_MOMENTUM ? &c.coef_mom : &c.coef_chj;
   int rc;
   if ((rc = ensure_coef(c, buf))) return rc;
-  if ((rc = copy(*buf, fields[0], n, s))) return rc;
-  if ((rc = copy(*buf + n, fields[1], n, s))) return rc;
-  if ((rc = copy(*buf + 2 * n, fields[2], dim * n, s))) return rc;
+  if (op == CHNS_OP_MOMENTUM) {
+    if ((rc = copy(*buf, fields[0], n, s))) return rc;
+    if ((rc = copy(*buf + n, fields[1], n, s))) return rc;
+    if ((rc = copy(*buf + 2 * n, fields[2], dim * n, s))) return rc;
+  } else {
+    // the Jacobian reads phi^{k+1} and phi^k only through their average
+    k_axpby<<<blocks_for(n), kT, 0, s>>>(*buf, 0.5, fields[0], 0.5, fields[1], n);
+    CHNS_HIP(hipGetLastError());
+    if ((rc = copy(*buf + n, fields[2], dim * n, s))) return rc;
+  }
   (op == CHNS_OP_MOMENTUM ? c.coef_mom_set : c.coef_chj_set) = true;
   (op == CHNS_OP_MOMENTUM ? c.coef_mom32_ok : c.coef_chj32_ok) = false;
   return CHNS_OK;
