@@ -86,7 +86,10 @@ typedef struct chns_mesh chns_mesh;
 
 typedef struct chns_mesh_info {
   int dim, max_level;
-  int node_order;        /* 0 = lexicographic (x fastest; uniform meshes), 1 = Morton */
+  int node_order;        /* 0 = lexicographic (x fastest; uniform meshes),
+                            1 = Morton, 2 = blocked: aligned 8^d blocks of
+                            the finest grid in Morton order, lexicographic
+                            (x fastest) inside a block (other meshes)       */
   int uniform;           /* 1 if the mesh is the whole cube with every leaf at
                             max_level                                         */
   int64_t n_elems;       /* leaves                                           */

@@ -823,6 +823,41 @@ __device__ __forceinline__ void brick_body(const BrickArgs<T>& a) {
       return gather<T, false>(a.cf[f - NI], nullptr, a.hang, (int32_t)e);
     }
   };
+  // Table meshes, every field of node entry e in two passes: first one load
+  // per field with no branch (a hanging node reads node 0 as a placeholder),
+  // so that all of them are in flight together; then, only in waves that
+  // hold a hanging node, its fields replaced by the mean of its parents (the
+  // same sums as gather()).
+  auto table_vals = [&](int32_t e, T* v) {
+    const int32_t i = e >= 0 ? e : 0;
+#pragma unroll
+    for (int f = 0; f < NV; ++f) v[f] = f < NI ? fetch<T, TR::MASK>(a.x + f * a.n, a.wall, i) : a.cf[f - NI][i];
+  };
+  auto table_hang = [&](int32_t e, T* v) {
+    const int32_t* hp = a.hang + 4 * (int64_t)(-e - 1);
+    const int32_t p0 = hp[0], p1 = hp[1], p2 = hp[2], p3 = hp[3];
+    const bool four = p2 >= 0;
+    const int32_t q2 = four ? p2 : p0, q3 = four ? p3 : p1;
+#pragma unroll
+    for (int f = 0; f < NV; ++f) {
+      T v0, v1, v2, v3;
+      if (f < NI) {
+        const T* src = a.x + f * a.n;
+        v0 = fetch<T, TR::MASK>(src, a.wall, p0);
+        v1 = fetch<T, TR::MASK>(src, a.wall, p1);
+        v2 = fetch<T, TR::MASK>(src, a.wall, q2);
+        v3 = fetch<T, TR::MASK>(src, a.wall, q3);
+      } else {
+        const T* src = a.cf[f - NI];
+        v0 = src[p0];
+        v1 = src[p1];
+        v2 = src[q2];
+        v3 = src[q3];
+      }
+      const T s01 = v0 + v1;
+      v[f] = four ? (s01 + (v2 + v3)) * T(0.25) : s01 * T(0.5);
+    }
+  };
   // per-level folded constants (powers of two are exact); FP32 fields carry
   // 1 + phi, so rho = (beta - alpha) + alpha (1 + phi)
   const double beta0 = sizeof(T) == 8 ? a.beta : a.beta - a.alpha;
@@ -869,13 +904,26 @@ __device__ __forceinline__ void brick_body(const BrickArgs<T>& a) {
     }
   };
   auto gather_vals = [&](int z) {
+    if constexpr (STRUCT) {
 #pragma unroll
-    for (int k = 0; k < KL; ++k) {
-      const int p = ll + k * LPB;
-      if (active && z <= B && p < NL) {
-        const int64_t e = STRUCT ? entry(z, p) : ent[k];
+      for (int k = 0; k < KL; ++k) {
+        const int p = ll + k * LPB;
+        if (active && z <= B && p < NL) {
+          const int64_t e = entry(z, p);
 #pragma unroll
-        for (int f = 0; f < NV; ++f) val[k][f] = value(f, e, z, p);
+          for (int f = 0; f < NV; ++f) val[k][f] = value(f, e, z, p);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < KL; ++k) {
+        const int p = ll + k * LPB;
+        if (active && z <= B && p < NL) table_vals((int32_t)ent[k], val[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < KL; ++k) {
+        const int p = ll + k * LPB;
+        if (active && z <= B && p < NL && ent[k] < 0) table_hang((int32_t)ent[k], val[k]);
       }
     }
   };
@@ -964,15 +1012,30 @@ __device__ __forceinline__ void brick_body(const BrickArgs<T>& a) {
     constexpr int KW = (NPB + LPB - 1) / LPB;
     if (active) {
       T w[KW][NV];
+      if constexpr (STRUCT) {
 #pragma unroll
-      for (int k = 0; k < KW; ++k) {
-        const int q = ll + k * LPB;
-        if (q < NPB) {
-          const int z = q / NL, p = q % NL;
-          const int64_t e = entry(z, p);
+        for (int k = 0; k < KW; ++k) {
+          const int q = ll + k * LPB;
+          if (q < NPB) {
+            const int z = q / NL, p = q % NL;
+            const int64_t e = entry(z, p);
 #pragma unroll
-          for (int f = 0; f < NV; ++f) w[k][f] = value(f, e, z, p);
+            for (int f = 0; f < NV; ++f) w[k][f] = value(f, e, z, p);
+          }
         }
+      } else {
+        int32_t ew[KW];
+#pragma unroll
+        for (int k = 0; k < KW; ++k) {
+          const int q = ll + k * LPB;
+          ew[k] = q < NPB ? tab[q] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < KW; ++k)
+          if (ll + k * LPB < NPB) table_vals(ew[k], w[k]);
+#pragma unroll
+        for (int k = 0; k < KW; ++k)
+          if (ll + k * LPB < NPB && ew[k] < 0) table_hang(ew[k], w[k]);
       }
 #pragma unroll
       for (int k = 0; k < KW; ++k) {
@@ -1133,9 +1196,10 @@ template <int DIM, int B, typename T, int OP, bool WHOLE, bool STRUCT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_brick_o4(BrickArgs<T> a) {
   brick_body<DIM, B, T, OP, WHOLE, STRUCT>(a);
 }
-// the FP64 3D Cahn-Hilliard Jacobian: its LDS admits three waves per SIMD,
-// which at 128^3 leaves a third of the bricks to a second, sparse round;
-// held to two waves it runs two full rounds (0.095 -> 0.090 ms)
+// the FP64 3D Cahn-Hilliard Jacobian on structured 8^3 bricks: its LDS
+// admits three waves per SIMD, which at 128^3 leaves a third of the bricks
+// to a second, sparse round; held to two waves it runs two full rounds
+// (0.095 -> 0.090 ms; equal at 256^3; on adaptive meshes three are faster)
 template <int DIM, int B, typename T, int OP, bool WHOLE, bool STRUCT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_brick_o2(BrickArgs<T> a) {
   brick_body<DIM, B, T, OP, WHOLE, STRUCT>(a);
@@ -1290,7 +1354,7 @@ void launch_one(int64_t grid, hipStream_t s, const BrickArgs<T>& a) {
   constexpr bool W = whole_fits<DIM, B, T, OP>();
   if constexpr (OP == K_PP || OP == K_PPS || OP == K_VPS || OP == K_MASS)
     k_brick_o4<DIM, B, T, OP, W, STRUCT><<<g, blk, 0, s>>>(a);
-  else if constexpr (OP == K_CH_JAC && DIM == 3 && sizeof(T) == 8)
+  else if constexpr (OP == K_CH_JAC && DIM == 3 && B == 8 && STRUCT && sizeof(T) == 8)
     k_brick_o2<DIM, B, T, OP, W, STRUCT><<<g, blk, 0, s>>>(a);
   else k_brick<DIM, B, T, OP, W, STRUCT><<<g, blk, 0, s>>>(a);
 }

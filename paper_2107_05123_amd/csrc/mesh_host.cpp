@@ -415,6 +415,17 @@ struct Builder {
 
   uint64_t node_key(const int32_t* c) const {
     if (m.node_order == 1) return morton(dim, c);
+    if (m.node_order == 2) {
+      // aligned blocks of 8^d finest-grid points in Morton order, x fastest
+      // inside a block
+      int32_t b[3] = {0, 0, 0};
+      uint64_t in = 0;
+      for (int d = dim - 1; d >= 0; --d) {
+        b[d] = c[d] >> 3;
+        in = in * 8 + (uint64_t)(c[d] & 7);
+      }
+      return morton(dim, b) << (3 * dim) | in;
+    }
     uint64_t s1 = (uint64_t)side + 1;
     uint64_t k = 0;
     for (int d = dim - 1; d >= 0; --d) k = k * s1 + (uint64_t)c[d];
@@ -422,6 +433,7 @@ struct Builder {
   }
   int node_key_bits() const {
     if (m.node_order == 1) return dim * (L + 1);
+    if (m.node_order == 2) return dim * (L > 2 ? L + 1 : 3);
     double b = dim * std::log2((double)side + 1.0);
     return (int)std::ceil(b) + 1;
   }
@@ -916,7 +928,10 @@ struct Builder {
     m.uniform = lmin == lmax && lmax == L && !carved;
     m.carve_level = carved ? sp.carve_level : 0;
     for (int d = 0; d < 3; ++d) m.box_hi[d] = d < dim ? box_hi[d] : 0;
-    m.node_order = m.uniform ? 0 : 1;
+    // uniform meshes: lexicographic (the structured kernels index nodes by
+    // coordinates); otherwise blocked, so that a brick's node rows are
+    // mostly contiguous and its gathers touch few cache lines
+    m.node_order = m.uniform ? 0 : 2;
     std::vector<int32_t> elem_corner, all_entry, all_coords;
     int rc = nodes(elem_corner, all_entry, all_coords);
     if (rc) return rc;

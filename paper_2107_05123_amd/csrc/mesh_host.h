@@ -30,7 +30,7 @@ struct HostMesh {
   int dim = 3;
   int max_level = 0;
   bool uniform = false;
-  int node_order = 0;  // 0 lexicographic, 1 Morton
+  int node_order = 0;  // 0 lexicographic, 1 Morton, 2 blocked (8^d blocks in Morton order)
 
   // leaves in Morton order
   std::vector<int8_t> leaf_level;
