@@ -163,10 +163,30 @@ __global__ __launch_bounds__(kT) void k_gm_multidot(const double* V, int64_t nv,
   __shared__ double sh[4][4];
   if (gd->done) return;
   const int j = gd->j;
+  const int64_t i0 = (int64_t)blockIdx.x * kT + threadIdx.x, st = (int64_t)gridDim.x * kT;
   for (int k0 = 0; k0 <= j; k0 += 4) {
     double a[4] = {0.0, 0.0, 0.0, 0.0};
     const int nk = min(4, j + 1 - k0);
-    GRID_LOOP(i, nv) {
+    // two elements per trip, every load of the trip in flight together; each
+    // thread still adds its elements in grid-stride order
+    int64_t i = i0;
+    for (; i + st < nv; i += 2 * st) {
+      const double wa = w[i], wb = w[i + st];
+      double va[4], vb[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (q < nk) {
+          va[q] = V[(int64_t)(k0 + q) * nv + i];
+          vb[q] = V[(int64_t)(k0 + q) * nv + i + st];
+        }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (q < nk) {
+          a[q] += va[q] * wa;
+          a[q] += vb[q] * wb;
+        }
+    }
+    if (i < nv) {
       const double wi = w[i];
 #pragma unroll
       for (int q = 0; q < 4; ++q)
@@ -195,17 +215,31 @@ __global__ __launch_bounds__(kT) void k_gm_fin(const double* part, int np, GmDev
   v = bsum(v, sh);
   if (threadIdx.x == 0) (which == 1 ? gd->h1 : gd->h2)[k] = v;
 }
-// w -= sum_k h[k] V_k; with `norm`, partial w.w into part[block]
+// w -= sum_k h[k] V_k; with `norm`, partial w.w into part[block].  The
+// coefficients are staged in LDS and four basis loads issued per trip (the
+// subtractions keep the order k = 0, 1, ..., j).
 __global__ __launch_bounds__(kT) void k_gm_orth(const double* V, int64_t nv, double* w, const GmDev* gd, int which,
                                                 double* part) {
   __shared__ double sh[4];
+  __shared__ double hs[kGmMax + 1];
   if (gd->done) return;
   const int j = gd->j;
   const double* h = which == 1 ? gd->h1 : gd->h2;
+  if (threadIdx.x <= j) hs[threadIdx.x] = h[threadIdx.x];
+  __syncthreads();
   double ww = 0.0;
   GRID_LOOP(i, nv) {
     double t = w[i];
-    for (int k = 0; k <= j; ++k) t -= h[k] * V[(int64_t)k * nv + i];
+    int k = 0;
+    for (; k + 3 <= j; k += 4) {
+      const double v0 = V[(int64_t)k * nv + i], v1 = V[(int64_t)(k + 1) * nv + i];
+      const double v2 = V[(int64_t)(k + 2) * nv + i], v3 = V[(int64_t)(k + 3) * nv + i];
+      t -= hs[k] * v0;
+      t -= hs[k + 1] * v1;
+      t -= hs[k + 2] * v2;
+      t -= hs[k + 3] * v3;
+    }
+    for (; k <= j; ++k) t -= hs[k] * V[(int64_t)k * nv + i];
     w[i] = t;
     ww += t * t;
   }
