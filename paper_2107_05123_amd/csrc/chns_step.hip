@@ -97,6 +97,13 @@ inline unsigned blocks_for(int64_t n) {
   int64_t g = (n + kT - 1) / kT;
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, kMaxBlocks));
 }
+// elementwise kernels (no reduction, so the grid does not change any result):
+// enough blocks to fill every SIMD with waves, which keeps their streams'
+// loads in flight
+inline unsigned blocks_ew(int64_t n) {
+  int64_t g = (n + kT - 1) / kT;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 8192));
+}
 
 #define GRID_LOOP(i, n) for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < (n); i += (int64_t)gridDim.x * kT)
 
@@ -504,7 +511,7 @@ constexpr int kMassCheb = 12;  // Chebyshev degree of the mass solve
 int ch_schur_apply(Ctx& c, const double* in, double* out, hipStream_t s) {
   Stepper& S = *c.step;
   const int64_t n = c.dm.n;
-  const unsigned g = blocks_for(n);
+  const unsigned g = blocks_ew(n);
   int rc;
   ApplyOut plain{};
   if ((rc = mg_vcycle64(c, in, S.pt1, s))) return rc;
@@ -609,11 +616,11 @@ int gmres(Ctx& c, int op, const double* b, double* x, int pc, const double* pcd,
   auto step = [&](hipStream_t st) -> int {
     int e;
     if (pc == GPC_SCHUR || pc == GPC_VPMG) {
-      k_gm_copyj<<<g, kT, 0, st>>>(S.V, nv, S.pin, S.gd);
+      k_gm_copyj<<<blocks_ew(nv), kT, 0, st>>>(S.V, nv, S.pin, S.gd);
       CHNS_HIP(hipGetLastError());
       if ((e = pc == GPC_SCHUR ? ch_schur_apply(c, S.pin, S.z, st) : vp_mg_apply(c, S.pin, S.z, st))) return e;
     } else {
-      k_gm_pc<<<pc == GPC_BLOCK2 ? gn : g, kT, 0, st>>>(S.V, nv, n, S.z, S.gd, pc, pcd);
+      k_gm_pc<<<blocks_ew(pc == GPC_BLOCK2 ? n : nv), kT, 0, st>>>(S.V, nv, n, S.z, S.gd, pc, pcd);
       CHNS_HIP(hipGetLastError());
     }
     e = launch_apply(c, op, CHNS_FP64, S.z, S.w, st, gated);
@@ -625,7 +632,7 @@ int gmres(Ctx& c, int op, const double* b, double* x, int pc, const double* pcd,
       CHNS_HIP(hipGetLastError());
     }
     k_gm_givens<<<1, kT, 0, st>>>(S.part, (int)g, S.gd);
-    k_gm_scale<<<g, kT, 0, st>>>(S.V, nv, S.w, S.gd);
+    k_gm_scale<<<blocks_ew(nv), kT, 0, st>>>(S.V, nv, S.w, S.gd);
     CHNS_HIP(hipGetLastError());
     return CHNS_OK;
   };
