@@ -104,6 +104,9 @@ class KeySet {
       i = (i + 1) & mask_;
     }
   }
+  // n keys inserted from several threads at once (insert_parallel below)
+  template <typename F>
+  void insert_parallel(int64_t n, F key_of);
 
  private:
   static constexpr uint64_t kEmpty = ~0ull;
@@ -138,7 +141,6 @@ bool box_meets_shell(const double* lo, const double* hi, const double* c, int di
   return true;
 }
 
-// LSD radix sort of (key, payload) pairs.
 // Run f(t, begin, end) over T contiguous chunks of [0, n) on up to 16 host
 // threads (fewer for small n); chunk t is always [n t / T, n (t + 1) / T),
 // so work split this way and merged in chunk order is deterministic.  f must
@@ -164,6 +166,40 @@ void parallel_chunks(int64_t n, int64_t min_per_thread, F f) {
 inline int64_t chunk_count(int64_t n, int64_t min_per_thread) {
   int64_t T = std::min<int64_t>(16, std::max<int64_t>(1, (int64_t)std::thread::hardware_concurrency()));
   return std::max<int64_t>(1, std::min<int64_t>(T, n / std::max<int64_t>(1, min_per_thread)));
+}
+
+// Lock-free linear probing: a thread claims an empty slot by compare-and-swap
+// and, when another key took it first, probes on.  The set's contents do not
+// depend on the threads' order (only where a key sits in the table does),
+// and the table is sized first, so no rehash runs meanwhile.
+template <typename F>
+void KeySet::insert_parallel(int64_t n, F key_of) {
+  while ((used_ + (size_t)n + 1) * 2 > slots_.size()) rehash(slots_.size() * 2);
+  uint64_t* sl = slots_.data();
+  const size_t mask = mask_;
+  std::vector<int64_t> added((size_t)chunk_count(n, 1 << 14), 0);
+  parallel_chunks(n, 1 << 14, [&](int64_t t, int64_t a, int64_t b) {
+    int64_t add = 0;
+    for (int64_t e = a; e < b; ++e) {
+      const uint64_t k = key_of(e);
+      size_t i = mix(k) & mask;
+      while (true) {
+        const uint64_t v = __atomic_load_n(&sl[i], __ATOMIC_RELAXED);
+        if (v == k) break;
+        if (v == kEmpty) {
+          uint64_t expect = kEmpty;
+          if (__atomic_compare_exchange_n(&sl[i], &expect, k, false, __ATOMIC_RELAXED, __ATOMIC_RELAXED)) {
+            ++add;
+            break;
+          }
+          if (expect == k) break;
+        }
+        i = (i + 1) & mask;
+      }
+    }
+    added[(size_t)t] = add;
+  });
+  for (int64_t a : added) used_ += (size_t)a;
 }
 
 // Stable LSD radix sort of (key, val) pairs by the low key_bits of key:
@@ -291,10 +327,29 @@ struct Builder {
   void balance(std::vector<int8_t>& lev, std::vector<int32_t>& anc) {
     const size_t n0 = lev.size();
     KeySet S(n0 * 2);
+    S.insert_parallel((int64_t)n0, [&](int64_t i) { return leaf_key(dim, lev[i], &anc[3 * i]); });
+    // the leaves of each level in leaf order: per-chunk counts, then each
+    // chunk writes its leaves after the previous chunks'
     std::vector<std::vector<std::array<int32_t, 3>>> bylev(L + 1);
-    for (size_t i = 0; i < n0; ++i) {
-      S.insert(leaf_key(dim, lev[i], &anc[3 * i]));
-      bylev[lev[i]].push_back({anc[3 * i], anc[3 * i + 1], anc[3 * i + 2]});
+    {
+      const int64_t T = chunk_count((int64_t)n0, 1 << 14);
+      std::vector<std::vector<int64_t>> cnt((size_t)T, std::vector<int64_t>(L + 1, 0));
+      parallel_chunks((int64_t)n0, 1 << 14, [&](int64_t t, int64_t a, int64_t b) {
+        for (int64_t i = a; i < b; ++i) ++cnt[(size_t)t][lev[i]];
+      });
+      for (int l = 0; l <= L; ++l) {
+        int64_t off = 0;
+        for (int64_t t = 0; t < T; ++t) {
+          const int64_t c = cnt[(size_t)t][l];
+          cnt[(size_t)t][l] = off;
+          off += c;
+        }
+        bylev[l].resize((size_t)off);
+      }
+      parallel_chunks((int64_t)n0, 1 << 14, [&](int64_t t, int64_t a, int64_t b) {
+        std::vector<int64_t>& at = cnt[(size_t)t];
+        for (int64_t i = a; i < b; ++i) bylev[lev[i]][(size_t)at[lev[i]]++] = {anc[3 * i], anc[3 * i + 1], anc[3 * i + 2]};
+      });
     }
     auto align = [&](const int32_t* p, int l, int32_t* out) {
       int32_t s = size_at(l);
@@ -390,27 +445,53 @@ struct Builder {
           }
         }
     }
-    // collect and sort by Morton key of the anchor (= depth-first order)
-    std::vector<uint64_t> keys;
-    std::vector<uint32_t> ids;
-    std::vector<int8_t> lv;
-    std::vector<int32_t> an;
+    // collect the leaves that remain (level by level, in list order) and sort
+    // them by the Morton key of the anchor (= depth-first order)
+    std::vector<int64_t> base(L + 2, 0);
+    for (int l = 0; l <= L; ++l) base[l + 1] = base[l] + (int64_t)bylev[l].size();
+    const int64_t NT = base[L + 1];
+    std::vector<int64_t> pos((size_t)NT + 1, 0);
     for (int l = 0; l <= L; ++l)
-      for (auto& a : bylev[l])
-        if (S.contains(leaf_key(dim, l, a.data()))) {
-          S.erase(leaf_key(dim, l, a.data()));  // guards against duplicates
-          keys.push_back(morton(dim, a.data()));
-          ids.push_back((uint32_t)lv.size());
-          lv.push_back((int8_t)l);
-          an.insert(an.end(), a.begin(), a.end());
+      parallel_chunks((int64_t)bylev[l].size(), 1 << 14, [&](int64_t, int64_t a, int64_t b) {
+        for (int64_t i = a; i < b; ++i)
+          pos[(size_t)(base[l] + i) + 1] = S.contains(leaf_key(dim, l, bylev[l][(size_t)i].data())) ? 1 : 0;
+      });
+    for (int64_t g = 0; g < NT; ++g) pos[(size_t)g + 1] += pos[(size_t)g];
+    const int64_t NL = pos[(size_t)NT];
+    std::vector<uint64_t> keys((size_t)NL);
+    std::vector<uint32_t> ids((size_t)NL);
+    std::vector<int8_t> lv((size_t)NL);
+    std::vector<int32_t> an((size_t)NL * 3);
+    for (int l = 0; l <= L; ++l)
+      parallel_chunks((int64_t)bylev[l].size(), 1 << 14, [&](int64_t, int64_t a, int64_t b) {
+        for (int64_t i = a; i < b; ++i) {
+          const size_t g = (size_t)(base[l] + i);
+          if (pos[g + 1] == pos[g]) continue;
+          const size_t k = (size_t)pos[g];
+          const auto& A = bylev[l][(size_t)i];
+          keys[k] = morton(dim, A.data());
+          ids[k] = (uint32_t)k;
+          lv[k] = (int8_t)l;
+          std::memcpy(&an[3 * k], A.data(), 3 * sizeof(int32_t));
         }
+      });
     radix_sort_pairs(keys, ids, dim * (L + 1));
-    lev.resize(lv.size());
-    anc.resize(an.size());
-    for (size_t i = 0; i < ids.size(); ++i) {
-      lev[i] = lv[ids[i]];
-      std::memcpy(&anc[3 * i], &an[3 * (size_t)ids[i]], 3 * sizeof(int32_t));
+    // a leaf listed twice (same level and anchor) is kept once; the stable
+    // sort leaves the copies next to each other
+    std::vector<uint32_t> keep;
+    keep.reserve((size_t)NL);
+    for (int64_t i = 0; i < NL; ++i) {
+      if (i > 0 && keys[(size_t)i] == keys[(size_t)i - 1] && lv[ids[(size_t)i]] == lv[ids[(size_t)i - 1]]) continue;
+      keep.push_back(ids[(size_t)i]);
     }
+    lev.resize(keep.size());
+    anc.resize(keep.size() * 3);
+    parallel_chunks((int64_t)keep.size(), 1 << 14, [&](int64_t, int64_t a, int64_t b) {
+      for (int64_t i = a; i < b; ++i) {
+        lev[(size_t)i] = lv[keep[(size_t)i]];
+        std::memcpy(&anc[3 * (size_t)i], &an[3 * (size_t)keep[(size_t)i]], 3 * sizeof(int32_t));
+      }
+    });
   }
 
   uint64_t node_key(const int32_t* c) const {
@@ -460,35 +541,54 @@ struct Builder {
       }
     });
     radix_sort_pairs(key, pay, node_key_bits());
-    elem_corner.assign((size_t)E * nc, -1);
-    std::vector<uint64_t> ukey;
-    std::vector<int8_t> maxlev;
-    for (size_t i = 0; i < key.size(); ++i) {
-      if (i == 0 || key[i] != key[i - 1]) {
-        ukey.push_back(key[i]);
-        uint32_t p = pay[i];
-        int64_t e = p / nc;
-        int a = p % nc;
-        int32_t s = size_at(m.leaf_level[e]);
-        for (int d = 0; d < 3; ++d)
-          all_coords.push_back(d < dim ? m.leaf_anchor[3 * e + d] + ((a >> d) & 1) * s : 0);
-        maxlev.push_back(m.leaf_level[e]);
+    // distinct keys = nodes, numbered in key order: a run of equal keys is
+    // one node (its coordinates from the run's first corner, its finest
+    // touching level the largest over the run); runs are found per chunk and
+    // numbered by prefix counts
+    const int64_t NK = (int64_t)key.size();
+    elem_corner.assign((size_t)NK, -1);
+    const int64_t T = chunk_count(NK, 1 << 16);
+    std::vector<int64_t> first((size_t)T + 1, 0);
+    parallel_chunks(NK, 1 << 16, [&](int64_t t, int64_t a, int64_t b) {
+      int64_t c = 0;
+      for (int64_t i = a; i < b; ++i) c += (i == 0 || key[(size_t)i] != key[(size_t)i - 1]) ? 1 : 0;
+      first[(size_t)t + 1] = c;
+    });
+    for (int64_t t = 0; t < T; ++t) first[(size_t)t + 1] += first[(size_t)t];
+    const int64_t NA = first[(size_t)T];
+    std::vector<uint64_t> ukey((size_t)NA);
+    std::vector<int8_t> maxlev((size_t)NA);
+    all_coords.assign((size_t)NA * 3, 0);
+    parallel_chunks(NK, 1 << 16, [&](int64_t t, int64_t a, int64_t b) {
+      int64_t id = first[(size_t)t] - 1;
+      for (int64_t i = a; i < b; ++i) {
+        if (i == 0 || key[(size_t)i] != key[(size_t)i - 1]) {
+          ++id;
+          ukey[(size_t)id] = key[(size_t)i];
+          const uint32_t p = pay[(size_t)i];
+          const int64_t e = p / nc;
+          const int a2 = p % nc;
+          const int32_t s = size_at(m.leaf_level[e]);
+          for (int d = 0; d < dim; ++d)
+            all_coords[3 * (size_t)id + d] = m.leaf_anchor[3 * e + d] + ((a2 >> d) & 1) * s;
+          // the finest level over the run, which may continue past this chunk
+          int8_t lm = m.leaf_level[e];
+          for (int64_t j = i + 1; j < NK && key[(size_t)j] == key[(size_t)i]; ++j)
+            lm = std::max(lm, m.leaf_level[pay[(size_t)j] / nc]);
+          maxlev[(size_t)id] = lm;
+        }
+        elem_corner[pay[(size_t)i]] = (int32_t)id;
       }
-      int64_t id = (int64_t)ukey.size() - 1;
-      elem_corner[pay[i]] = (int32_t)id;
-      int8_t lv = m.leaf_level[pay[i] / nc];
-      if (lv > maxlev[id]) maxlev[id] = lv;
-    }
+    });
     key.clear();
     key.shrink_to_fit();
     pay.clear();
     pay.shrink_to_fit();
-    const int64_t NA = (int64_t)ukey.size();
 
     // hanging detection: a corner that is not on the level-(lmax-1) grid and
     // that sits on the boundary of a level-(lmax-1) leaf is hanging.
     KeySet S((size_t)E * 2);
-    for (int64_t e = 0; e < E; ++e) S.insert(leaf_key(dim, m.leaf_level[e], &m.leaf_anchor[3 * e]));
+    S.insert_parallel(E, [&](int64_t e) { return leaf_key(dim, m.leaf_level[e], &m.leaf_anchor[3 * e]); });
     // the octant (corner direction o) of the coarse leaf holding each node,
     // found in parallel (read-only lookups), then numbered in node order
     auto coarse_anchor = [&](const int32_t* c, int o, int32_t S2, int32_t* a) {
