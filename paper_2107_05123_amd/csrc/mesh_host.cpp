@@ -929,13 +929,21 @@ struct Builder {
         std::copy(buf, buf + k, &eent[(size_t)eptr[e]]);
       }
     });
+    // the leaves around each node (counted and placed by atomic increments
+    // from several threads: the order inside a node's list varies, the
+    // colouring below only forms the union of their nodes' colours)
     std::vector<int32_t> cnt(N + 1, 0);
-    for (int32_t v : eent) ++cnt[v + 1];
+    parallel_chunks((int64_t)eent.size(), 1 << 16, [&](int64_t, int64_t a, int64_t b) {
+      for (int64_t j = a; j < b; ++j) __atomic_fetch_add(&cnt[(size_t)eent[(size_t)j] + 1], 1, __ATOMIC_RELAXED);
+    });
     for (int64_t i = 0; i < N; ++i) cnt[i + 1] += cnt[i];
     std::vector<int32_t> inc(cnt[N]);
     std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
-    for (int64_t e = 0; e < E; ++e)
-      for (int64_t j = eptr[e]; j < eptr[e + 1]; ++j) inc[fill[eent[(size_t)j]]++] = (int32_t)e;
+    parallel_chunks(E, 1 << 14, [&](int64_t, int64_t e0, int64_t e1) {
+      for (int64_t e = e0; e < e1; ++e)
+        for (int64_t j = eptr[e]; j < eptr[e + 1]; ++j)
+          inc[(size_t)__atomic_fetch_add(&fill[(size_t)eent[(size_t)j]], 1, __ATOMIC_RELAXED)] = (int32_t)e;
+    });
     // greedy colouring in node order
     std::vector<int16_t> col(N, -1);
     int maxc = 0;
