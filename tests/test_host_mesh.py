@@ -94,6 +94,28 @@ def test_sphere_band_matches_oracle(dim, lmin, lmax, band):
     assert om.is_balanced(*m.leaves(), lmax) if m.n_elems < 3000 else True
 
 
+def _blocked_key(c, dim):
+    # aligned 8^d blocks of the finest grid in Morton order (bit b of
+    # coordinate d at position dim b + d), x fastest inside a block
+    c = np.asarray(c, dtype=np.int64)
+    blk, low = c >> 3, c & 7
+    key = np.zeros(c.shape[0], dtype=np.int64)
+    for b in range(20):
+        for d in range(dim):
+            key |= ((blk[:, d] >> b) & 1) << (dim * b + d)
+    inner = sum(low[:, d] << (3 * d) for d in range(dim))
+    return (key << (3 * dim)) | inner
+
+
+@pytest.mark.parametrize("dim,lmax", [(3, 6), (2, 7)])
+def test_adaptive_node_order_is_blocked(dim, lmax):
+    c = (0.5, 0.3, 0.5)[:dim]
+    m = _lib_mesh(dim=dim, min_level=2, max_level=lmax, rule="sphere_band", centres=[c], radii=[0.15], band=0.03)
+    assert m.info.node_order == 2 and not m.summary()["uniform"]
+    k = _blocked_key(m.node_coords()[:, :dim], dim)
+    assert np.all(np.diff(k) > 0)
+
+
 def test_multi_sphere_and_callback_rules():
     cs = [(0.3, 0.3, 0.3), (0.7, 0.6, 0.5)]
     rs = [0.1, 0.15]
