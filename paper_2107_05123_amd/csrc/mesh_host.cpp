@@ -750,52 +750,58 @@ struct Builder {
         if (brick_rank(dim, B, jx, jy, z) != bc.rank[p]) throw std::logic_error("brick rank formula");
       }
       std::vector<int32_t>& elist = brick_elems[c];
-      int64_t i = 0;
-      while (i < E) {
-        if (taken[i]) {
-          ++i;
-          continue;
-        }
-        int l = m.leaf_level[i];
-        if (c == kBrickClasses - 1) {
-          elist.push_back((int32_t)i);
-          taken[i] = 1;
-          ++bc.count;
-          ++i;
-          continue;
-        }
-        int32_t s = size_at(l);
-        bool ok = B <= bmax && l >= b && i + n <= E;
-        for (int d = 0; ok && d < dim; ++d)
-          if (m.leaf_anchor[3 * i + d] % (B * s)) ok = false;
-        for (int64_t j = i; ok && j < i + n; ++j)
-          if (taken[j] || m.leaf_level[j] != l) ok = false;
-        for (int d = 0; ok && d < dim; ++d)
-          if (m.leaf_anchor[3 * (i + n - 1) + d] != m.leaf_anchor[3 * i + d] + (B - 1) * s) ok = false;
-        if (!ok) {
-          ++i;
-          continue;
-        }
-        // record the brick's leaves ordered by local lexicographic position
-        std::vector<int32_t> loc(n, -1);
-        for (int64_t j = i; j < i + n; ++j) {
-          int lp = 0, mul = 1;
-          for (int d = 0; d < dim; ++d) {
-            lp += ((m.leaf_anchor[3 * j + d] - m.leaf_anchor[3 * i + d]) / s) * mul;
-            mul *= B;
+      // a leaf starts a brick of this class when it is free, aligned to the
+      // brick edge, and the n leaves from it on are free, of its level and end
+      // at the brick's far corner; same-level aligned blocks never overlap,
+      // so the starts are found independently (per chunk, in leaf order) and
+      // give what a scan that skips each found brick gives
+      const int64_t T = chunk_count(E, 1 << 14);
+      std::vector<std::vector<int32_t>> found((size_t)T);
+      parallel_chunks(E, 1 << 14, [&](int64_t t, int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i) {
+          if (taken[i]) continue;
+          if (c == kBrickClasses - 1) {
+            found[(size_t)t].push_back((int32_t)i);
+            continue;
           }
-          loc[lp] = (int32_t)j;
-          taken[j] = 1;
+          const int l = m.leaf_level[i];
+          const int32_t s = size_at(l);
+          bool ok = B <= bmax && l >= b && i + n <= E;
+          for (int d = 0; ok && d < dim; ++d)
+            if (m.leaf_anchor[3 * i + d] % (B * s)) ok = false;
+          for (int64_t j = i; ok && j < i + n; ++j)
+            if (taken[j] || m.leaf_level[j] != l) ok = false;
+          for (int d = 0; ok && d < dim; ++d)
+            if (m.leaf_anchor[3 * (i + n - 1) + d] != m.leaf_anchor[3 * i + d] + (B - 1) * s) ok = false;
+          if (ok) found[(size_t)t].push_back((int32_t)i);
         }
-        elist.insert(elist.end(), loc.begin(), loc.end());
-        ++bc.count;
-        i += n;
-      }
+      });
+      std::vector<int32_t> first;
+      for (auto& f : found) first.insert(first.end(), f.begin(), f.end());
+      bc.count = (int64_t)first.size();
+      // each brick's leaves ordered by local lexicographic position
+      elist.assign((size_t)bc.count * n, -1);
+      parallel_chunks(bc.count, 1 << 10, [&](int64_t, int64_t k0, int64_t k1) {
+        for (int64_t k = k0; k < k1; ++k) {
+          const int64_t i = first[(size_t)k];
+          const int32_t s = size_at(m.leaf_level[i]);
+          for (int64_t j = i; j < i + n; ++j) {
+            int lp = 0, mul = 1;
+            for (int d = 0; d < dim; ++d) {
+              lp += ((m.leaf_anchor[3 * j + d] - m.leaf_anchor[3 * i + d]) / s) * mul;
+              mul *= B;
+            }
+            elist[(size_t)k * n + lp] = (int32_t)j;
+            taken[j] = 1;
+          }
+        }
+      });
       // tables
       bc.table.resize((size_t)bc.count * np);
       bc.level.resize(bc.count);
       bc.anchor.resize((size_t)bc.count * 3);
-      for (int64_t k = 0; k < bc.count; ++k) {
+      parallel_chunks(bc.count, 1 << 10, [&](int64_t, int64_t k0, int64_t k1) {
+      for (int64_t k = k0; k < k1; ++k) {
         const int32_t* els = &elist[(size_t)k * n];
         bc.level[k] = m.leaf_level[els[0]];
         for (int d = 0; d < 3; ++d) bc.anchor[3 * k + d] = m.leaf_anchor[3 * (size_t)els[0] + d];
@@ -812,6 +818,7 @@ struct Builder {
           bc.table[(size_t)k * np + p] = all_entry[elem_corner[(size_t)els[le] * nc + a]];
         }
       }
+      });
     }
     int64_t base = 0;
     for (int c = 0; c < kBrickClasses; ++c) {
@@ -827,40 +834,60 @@ struct Builder {
       msg = "too many brick-boundary slots";
       return CHNS_EINVAL;
     }
+    // every brick-boundary slot names the independent nodes it lands on (a
+    // hanging node's parents, with its weight code in the top bits), in
+    // (class, brick, position) order: per chunk of bricks, merged in chunk
+    // order; interior nodes are counted (each must be interior to one brick)
     std::vector<int32_t> interior(N, 0);
-    std::vector<int32_t> cnt(N + 1, 0);
-    struct Push {
-      int32_t node;
-      uint32_t ent;
-    };
-    std::vector<Push> pushes;
+    std::vector<uint64_t> key;
+    std::vector<uint32_t> val;
+    int bad = 0;
     for (int c = 0; c < kBrickClasses; ++c) {
-      BrickClass& bc = m.cls[c];
-      for (int64_t k = 0; k < bc.count; ++k) {
-        for (int p = 0; p < bc.nodes_per_brick; ++p) {
-          int32_t e = bc.table[(size_t)k * bc.nodes_per_brick + p];
-          int r = bc.rank[p];
-          if (r < 0) {
-            if (e < 0) {
-              msg = "hanging node inside a brick";
-              return CHNS_EINVAL;
+      const BrickClass& bc = m.cls[c];
+      const int64_t T = chunk_count(bc.count, 1 << 10);
+      std::vector<std::vector<uint64_t>> kp((size_t)T);
+      std::vector<std::vector<uint32_t>> vp((size_t)T);
+      parallel_chunks(bc.count, 1 << 10, [&](int64_t t, int64_t k0, int64_t k1) {
+        for (int64_t k = k0; k < k1; ++k)
+          for (int p = 0; p < bc.nodes_per_brick; ++p) {
+            const int32_t e = bc.table[(size_t)k * bc.nodes_per_brick + p];
+            const int r = bc.rank[p];
+            if (r < 0) {
+              if (e < 0) __atomic_store_n(&bad, 1, __ATOMIC_RELAXED);
+              else __atomic_fetch_add(&interior[e], 1, __ATOMIC_RELAXED);
+              continue;
             }
-            ++interior[e];
-            continue;
+            const uint32_t slot = (uint32_t)(bc.slot_base + k * bc.bnd_per_brick + r);
+            if (e >= 0) {
+              kp[(size_t)t].push_back((uint64_t)e);
+              vp[(size_t)t].push_back(slot);
+            } else {
+              const int64_t h = -e - 1;
+              const int np = m.hang_npar[h];
+              const uint32_t code = np == 2 ? 1u : (np == 4 ? 2u : 0u);
+              for (int q = 0; q < np; ++q) {
+                kp[(size_t)t].push_back((uint64_t)m.hang_parents[4 * h + q]);
+                vp[(size_t)t].push_back(slot | (code << 30));
+              }
+            }
           }
-          uint32_t slot = (uint32_t)(bc.slot_base + k * bc.bnd_per_brick + r);
-          if (e >= 0) {
-            pushes.push_back({e, slot});
-          } else {
-            int64_t h = -e - 1;
-            int np = m.hang_npar[h];
-            uint32_t code = np == 2 ? 1u : (np == 4 ? 2u : 0u);
-            for (int q = 0; q < np; ++q) pushes.push_back({m.hang_parents[4 * h + q], slot | (code << 30)});
-          }
-        }
+      });
+      for (int64_t t = 0; t < T; ++t) {
+        key.insert(key.end(), kp[(size_t)t].begin(), kp[(size_t)t].end());
+        val.insert(val.end(), vp[(size_t)t].begin(), vp[(size_t)t].end());
       }
     }
-    for (auto& p : pushes) ++cnt[p.node + 1];
+    if (bad) {
+      msg = "hanging node inside a brick";
+      return CHNS_EINVAL;
+    }
+    // grouped by node, each node's entries in that order (stable sort)
+    int bits = 1;
+    while (bits < 63 && (1ll << bits) <= N) ++bits;
+    radix_sort_pairs(key, val, bits);
+    const int64_t P = (int64_t)key.size();
+    std::vector<int32_t> cnt(N + 1, 0);
+    for (int64_t j = 0; j < P; ++j) ++cnt[(size_t)key[(size_t)j] + 1];
     for (int64_t i = 0; i < N; ++i) {
       bool in = interior[i] > 0, sh = cnt[i + 1] > 0;
       if (interior[i] > 1 || in == sh) {
@@ -868,17 +895,12 @@ struct Builder {
         return CHNS_EINVAL;
       }
     }
-    std::vector<int32_t> start(N + 1, 0);
-    for (int64_t i = 0; i < N; ++i) start[i + 1] = start[i] + cnt[i + 1];
-    std::vector<uint32_t> ent(pushes.size());
-    std::vector<int32_t> fill(start.begin(), start.end() - 1);
-    for (auto& p : pushes) ent[fill[p.node]++] = p.ent;  // stable: push order kept
+    m.comb_ent.assign(val.begin(), val.end());
     m.comb_ptr.push_back(0);
     for (int64_t i = 0; i < N; ++i) {
       if (cnt[i + 1] == 0) continue;
       m.comb_node.push_back((int32_t)i);
-      for (int32_t j = start[i]; j < start[i + 1]; ++j) m.comb_ent.push_back(ent[j]);
-      m.comb_ptr.push_back((int32_t)m.comb_ent.size());
+      m.comb_ptr.push_back(m.comb_ptr.back() + cnt[i + 1]);
     }
     return CHNS_OK;
   }
