@@ -626,75 +626,90 @@ struct Builder {
         }
       }
     });
-    std::vector<int32_t> hang_of(NA, -1);
-    std::vector<std::array<int32_t, 3>> hang_leaf_anchor;
-    std::vector<int8_t> hang_leaf_level;
-    for (int64_t n = 0; n < NA; ++n) {
-      if (hang_o[n] < 0) continue;
-      const int lm = maxlev[n];
-      int32_t a[3];
-      coarse_anchor(&all_coords[3 * n], hang_o[n], size_at(lm - 1), a);
-      hang_of[n] = (int32_t)hang_leaf_level.size();
-      hang_leaf_level.push_back((int8_t)(lm - 1));
-      hang_leaf_anchor.push_back({a[0], a[1], a[2]});
-    }
-    // independent numbering in key order
+    // independent and hanging nodes numbered in key order (per-chunk counts)
+    const int64_t TC = chunk_count(NA, 1 << 14);
+    std::vector<int64_t> hc((size_t)TC + 1, 0);
+    parallel_chunks(NA, 1 << 14, [&](int64_t t, int64_t a, int64_t b) {
+      int64_t c = 0;
+      for (int64_t n = a; n < b; ++n) c += hang_o[n] >= 0 ? 1 : 0;
+      hc[(size_t)t + 1] = c;
+    });
+    for (int64_t t = 0; t < TC; ++t) hc[(size_t)t + 1] += hc[(size_t)t];
+    const int64_t nh = hc[(size_t)TC], ni = NA - nh;
     all_entry.assign(NA, 0);
-    int64_t ni = 0, nh = 0;
-    for (int64_t n = 0; n < NA; ++n) {
-      if (hang_of[n] >= 0) {
-        all_entry[n] = -(int32_t)(++nh);
-      } else {
-        all_entry[n] = (int32_t)ni++;
-        for (int d = 0; d < 3; ++d) m.indep_coords.push_back(all_coords[3 * n + d]);
+    m.indep_coords.assign((size_t)ni * 3, 0);
+    parallel_chunks(NA, 1 << 14, [&](int64_t t, int64_t a, int64_t b) {
+      int64_t h = hc[(size_t)t], i = a - hc[(size_t)t];
+      for (int64_t n = a; n < b; ++n) {
+        if (hang_o[n] >= 0) {
+          all_entry[n] = -(int32_t)(++h);
+        } else {
+          all_entry[n] = (int32_t)i;
+          for (int d = 0; d < 3; ++d) m.indep_coords[3 * (size_t)i + d] = all_coords[3 * n + d];
+          ++i;
+        }
       }
-    }
+    });
     m.n_indep = ni;
     m.n_hanging = nh;
     m.hang_parents.assign(nh * 4, -1);
     m.hang_npar.assign(nh, 0);
     m.hang_coords.resize(nh * 3);
-    for (int64_t n = 0; n < NA; ++n) {
-      if (hang_of[n] < 0) continue;
-      int64_t h = -all_entry[n] - 1;
-      const int32_t* c = &all_coords[3 * n];
-      for (int d = 0; d < 3; ++d) m.hang_coords[3 * h + d] = c[d];
-      auto& A = hang_leaf_anchor[hang_of[n]];
-      int32_t s = size_at(hang_leaf_level[hang_of[n]]);
-      int nfree = 0;
-      int fixedbit[3] = {0, 0, 0};
-      bool isfree[3] = {false, false, false};
-      for (int d = 0; d < dim; ++d) {
-        int32_t r = c[d] - A[d];
-        if (r == 0) fixedbit[d] = 0;
-        else if (r == s) fixedbit[d] = 1;
-        else {
-          isfree[d] = true;
-          ++nfree;
-        }
-      }
-      int np = 0;
-      for (int comb = 0; comb < (1 << nfree); ++comb) {
-        int32_t pc[3] = {0, 0, 0};
-        int k = 0;
+    // a hanging node's parents: the corners of the coarse leaf's face or edge
+    // that holds it (read-only lookups, one hanging node per iteration)
+    int err = 0;
+    parallel_chunks(NA, 1 << 14, [&](int64_t, int64_t a0, int64_t a1) {
+      for (int64_t n = a0; n < a1; ++n) {
+        if (hang_o[n] < 0) continue;
+        const int64_t h = -all_entry[n] - 1;
+        const int32_t* c = &all_coords[3 * n];
+        for (int d = 0; d < 3; ++d) m.hang_coords[3 * h + d] = c[d];
+        const int32_t s = size_at(maxlev[n] - 1);
+        int32_t A[3];
+        coarse_anchor(c, hang_o[n], s, A);
+        int nfree = 0;
+        int fixedbit[3] = {0, 0, 0};
+        bool isfree[3] = {false, false, false};
         for (int d = 0; d < dim; ++d) {
-          int bit = isfree[d] ? ((comb >> k++) & 1) : fixedbit[d];
-          pc[d] = A[d] + bit * s;
+          const int32_t r = c[d] - A[d];
+          if (r == 0) fixedbit[d] = 0;
+          else if (r == s) fixedbit[d] = 1;
+          else {
+            isfree[d] = true;
+            ++nfree;
+          }
         }
-        uint64_t pk = node_key(pc);
-        auto it = std::lower_bound(ukey.begin(), ukey.end(), pk);
-        if (it == ukey.end() || *it != pk) {
-          msg = "hanging-node parent is not a leaf corner";
-          return CHNS_EINVAL;
+        int np = 0;
+        for (int comb = 0; comb < (1 << nfree); ++comb) {
+          int32_t pc[3] = {0, 0, 0};
+          int k = 0;
+          for (int d = 0; d < dim; ++d) {
+            const int bit = isfree[d] ? ((comb >> k++) & 1) : fixedbit[d];
+            pc[d] = A[d] + bit * s;
+          }
+          const uint64_t pk = node_key(pc);
+          const auto it = std::lower_bound(ukey.begin(), ukey.end(), pk);
+          if (it == ukey.end() || *it != pk) {
+            __atomic_fetch_or(&err, 1, __ATOMIC_RELAXED);
+            break;
+          }
+          const int32_t pe = all_entry[it - ukey.begin()];
+          if (pe < 0) {
+            __atomic_fetch_or(&err, 2, __ATOMIC_RELAXED);
+            break;
+          }
+          m.hang_parents[4 * h + np++] = pe;
         }
-        int32_t pe = all_entry[it - ukey.begin()];
-        if (pe < 0) {
-          msg = "hanging-node parent is itself hanging (tree not 2:1 balanced)";
-          return CHNS_EINVAL;
-        }
-        m.hang_parents[4 * h + np++] = pe;
+        m.hang_npar[h] = (int8_t)np;
       }
-      m.hang_npar[h] = (int8_t)np;
+    });
+    if (err & 1) {
+      msg = "hanging-node parent is not a leaf corner";
+      return CHNS_EINVAL;
+    }
+    if (err & 2) {
+      msg = "hanging-node parent is itself hanging (tree not 2:1 balanced)";
+      return CHNS_EINVAL;
     }
     return CHNS_OK;
   }
