@@ -859,10 +859,26 @@ struct Builder {
     int bad = 0;
     for (int c = 0; c < kBrickClasses; ++c) {
       const BrickClass& bc = m.cls[c];
+      // pushes per chunk of bricks (counted first, then written in place)
+      auto pushes_of = [&](int64_t k, int p) -> int {
+        const int32_t e = bc.table[(size_t)k * bc.nodes_per_brick + p];
+        if (bc.rank[p] < 0) return 0;
+        return e >= 0 ? 1 : m.hang_npar[-e - 1];
+      };
       const int64_t T = chunk_count(bc.count, 1 << 10);
-      std::vector<std::vector<uint64_t>> kp((size_t)T);
-      std::vector<std::vector<uint32_t>> vp((size_t)T);
+      std::vector<int64_t> off((size_t)T + 1, 0);
       parallel_chunks(bc.count, 1 << 10, [&](int64_t t, int64_t k0, int64_t k1) {
+        int64_t cnt = 0;
+        for (int64_t k = k0; k < k1; ++k)
+          for (int p = 0; p < bc.nodes_per_brick; ++p) cnt += pushes_of(k, p);
+        off[(size_t)t + 1] = cnt;
+      });
+      off[0] = (int64_t)key.size();
+      for (int64_t t = 0; t < T; ++t) off[(size_t)t + 1] += off[(size_t)t];
+      key.resize((size_t)off[(size_t)T]);
+      val.resize((size_t)off[(size_t)T]);
+      parallel_chunks(bc.count, 1 << 10, [&](int64_t t, int64_t k0, int64_t k1) {
+        size_t w = (size_t)off[(size_t)t];
         for (int64_t k = k0; k < k1; ++k)
           for (int p = 0; p < bc.nodes_per_brick; ++p) {
             const int32_t e = bc.table[(size_t)k * bc.nodes_per_brick + p];
@@ -874,23 +890,19 @@ struct Builder {
             }
             const uint32_t slot = (uint32_t)(bc.slot_base + k * bc.bnd_per_brick + r);
             if (e >= 0) {
-              kp[(size_t)t].push_back((uint64_t)e);
-              vp[(size_t)t].push_back(slot);
+              key[w] = (uint64_t)e;
+              val[w++] = slot;
             } else {
               const int64_t h = -e - 1;
               const int np = m.hang_npar[h];
               const uint32_t code = np == 2 ? 1u : (np == 4 ? 2u : 0u);
               for (int q = 0; q < np; ++q) {
-                kp[(size_t)t].push_back((uint64_t)m.hang_parents[4 * h + q]);
-                vp[(size_t)t].push_back(slot | (code << 30));
+                key[w] = (uint64_t)m.hang_parents[4 * h + q];
+                val[w++] = slot | (code << 30);
               }
             }
           }
       });
-      for (int64_t t = 0; t < T; ++t) {
-        key.insert(key.end(), kp[(size_t)t].begin(), kp[(size_t)t].end());
-        val.insert(val.end(), vp[(size_t)t].begin(), vp[(size_t)t].end());
-      }
     }
     if (bad) {
       msg = "hanging node inside a brick";
