@@ -723,17 +723,6 @@ __device__ __forceinline__ T fetch(const T* v, const uint8_t* wall, int32_t i) {
   if constexpr (MASK) return wall[i] ? T(0) : v[i];
   return v[i];
 }
-template <typename T, bool MASK>
-__device__ __forceinline__ T gather(const T* v, const uint8_t* wall, const int32_t* hang, int32_t e) {
-  if (e >= 0) return fetch<T, MASK>(v, wall, e);
-  const int32_t* p = hang + 4 * (int64_t)(-e - 1);
-  const int32_t p0 = p[0], p1 = p[1], p2 = p[2], p3 = p[3];
-  if (p2 < 0) return (fetch<T, MASK>(v, wall, p0) + fetch<T, MASK>(v, wall, p1)) * T(0.5);
-  return ((fetch<T, MASK>(v, wall, p0) + fetch<T, MASK>(v, wall, p1)) +
-          (fetch<T, MASK>(v, wall, p2) + fetch<T, MASK>(v, wall, p3))) *
-         T(0.25);
-}
-
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -809,25 +798,22 @@ __device__ __forceinline__ void brick_body(const BrickArgs<T>& a) {
     const int cx = ax + jx, cy = DIM == 3 ? ay + jy : ay + z, cz = az + z;
     return cx == 0 || cx == a.side || cy == 0 || cy == a.side || (DIM == 3 && (cz == 0 || cz == a.side));
   };
+  // structured meshes: field f of the node with index e at layer z, layer
+  // position p (inputs read as zero on the walls when MASK)
   auto value = [&](int f, int64_t e, int z, int p) -> T {
-    if constexpr (STRUCT) {
-      if (f < NI) {
-        if constexpr (TR::MASK) {
-          if (on_wall(z, p)) return T(0);
-        }
-        return (a.x + f * a.n)[(int32_t)e];
+    if (f < NI) {
+      if constexpr (TR::MASK) {
+        if (on_wall(z, p)) return T(0);
       }
-      return a.cf[f - NI][(int32_t)e];
-    } else {
-      if (f < NI) return gather<T, TR::MASK>(a.x + f * a.n, a.wall, a.hang, (int32_t)e);
-      return gather<T, false>(a.cf[f - NI], nullptr, a.hang, (int32_t)e);
+      return (a.x + f * a.n)[(int32_t)e];
     }
+    return a.cf[f - NI][(int32_t)e];
   };
   // Table meshes, every field of node entry e in two passes: first one load
   // per field with no branch (a hanging node reads node 0 as a placeholder),
   // so that all of them are in flight together; then, only in waves that
-  // hold a hanging node, its fields replaced by the mean of its parents (the
-  // same sums as gather()).
+  // hold a hanging node, its fields replaced by the mean of its parents
+  // (edge: (a + b) / 2, face: ((a + b) + (c + d)) / 4).
   auto table_vals = [&](int32_t e, T* v) {
     const int32_t i = e >= 0 ? e : 0;
 #pragma unroll
