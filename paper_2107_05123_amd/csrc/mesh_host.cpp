@@ -1410,23 +1410,33 @@ struct BandQuery {
   std::vector<double> v, bmin, bmax;
 
   BandQuery(const HostMesh& m, const double* phi, double t) : dim(m.dim), L(m.max_level), thr(t) {
-    std::vector<std::pair<uint64_t, double>> kv;
-    kv.reserve((size_t)(m.n_indep + m.n_hanging));
-    for (int64_t i = 0; i < m.n_indep; ++i) kv.push_back({morton(dim, &m.indep_coords[3 * i]), phi[i]});
-    for (int64_t h = 0; h < m.n_hanging; ++h) {
-      // a hanging node's value: the mean of its parents (its constraint)
-      const int np = m.hang_npar[h];
-      double s = 0.0;
-      for (int q = 0; q < np; ++q) s += phi[m.hang_parents[4 * h + q]];
-      kv.push_back({morton(dim, &m.hang_coords[3 * h]), s / np});
-    }
-    std::sort(kv.begin(), kv.end());
-    key.resize(kv.size());
-    v.resize(kv.size());
-    for (size_t i = 0; i < kv.size(); ++i) {
-      key[i] = kv[i].first;
-      v[i] = kv[i].second;
-    }
+    const int64_t ni = m.n_indep, nt = m.n_indep + m.n_hanging;
+    std::vector<double> val((size_t)nt);
+    std::vector<uint32_t> ids((size_t)nt);
+    key.resize((size_t)nt);
+    parallel_chunks(nt, 1 << 14, [&](int64_t, int64_t a, int64_t b) {
+      for (int64_t i = a; i < b; ++i) {
+        ids[(size_t)i] = (uint32_t)i;
+        if (i < ni) {
+          key[(size_t)i] = morton(dim, &m.indep_coords[3 * i]);
+          val[(size_t)i] = phi[i];
+        } else {
+          // a hanging node's value: the mean of its parents (its constraint)
+          const int64_t h = i - ni;
+          const int np = m.hang_npar[h];
+          double s = 0.0;
+          for (int q = 0; q < np; ++q) s += phi[m.hang_parents[4 * h + q]];
+          key[(size_t)i] = morton(dim, &m.hang_coords[3 * h]);
+          val[(size_t)i] = s / np;
+        }
+      }
+    });
+    // node keys are distinct, so the order is that of the keys alone
+    radix_sort_pairs(key, ids, dim * (L + 1));
+    v.resize((size_t)nt);
+    parallel_chunks(nt, 1 << 14, [&](int64_t, int64_t a, int64_t b) {
+      for (int64_t i = a; i < b; ++i) v[(size_t)i] = val[ids[(size_t)i]];
+    });
     const int64_t nb = ((int64_t)v.size() + kBlk - 1) / kBlk;
     bmin.assign((size_t)nb, INFINITY);
     bmax.assign((size_t)nb, -INFINITY);
