@@ -1170,15 +1170,32 @@ struct NodeLookup {
   uint64_t s1;
   int dim;
   explicit NodeLookup(const HostMesh& m) : s1((uint64_t)(1 << m.max_level) + 1), dim(m.dim) {
-    std::vector<std::pair<uint64_t, int32_t>> kv;
-    kv.reserve(m.n_indep + m.n_hanging);
-    for (int64_t i = 0; i < m.n_indep; ++i) kv.push_back({enc(&m.indep_coords[3 * i]), (int32_t)i});
-    for (int64_t h = 0; h < m.n_hanging; ++h) kv.push_back({enc(&m.hang_coords[3 * h]), -(int32_t)(h + 1)});
-    std::sort(kv.begin(), kv.end());
-    for (auto& p : kv) {
-      key.push_back(p.first);
-      val.push_back(p.second);
-    }
+    // keys of every node (distinct coordinates, so distinct keys), sorted
+    // with their entries on several threads
+    const int64_t ni = m.n_indep, nt = m.n_indep + m.n_hanging;
+    key.resize((size_t)nt);
+    std::vector<uint32_t> ids((size_t)nt);
+    parallel_chunks(nt, 1 << 14, [&](int64_t, int64_t a, int64_t b) {
+      for (int64_t i = a; i < b; ++i) {
+        key[(size_t)i] = enc(i < ni ? &m.indep_coords[3 * i] : &m.hang_coords[3 * (i - ni)]);
+        ids[(size_t)i] = (uint32_t)i;
+      }
+    });
+    int bits = 1;
+    while (bits < 63 && (uint64_t)1 << bits <= enc_max()) ++bits;
+    radix_sort_pairs(key, ids, bits);
+    val.resize((size_t)nt);
+    parallel_chunks(nt, 1 << 14, [&](int64_t, int64_t a, int64_t b) {
+      for (int64_t i = a; i < b; ++i) {
+        const int64_t j = ids[(size_t)i];
+        val[(size_t)i] = j < ni ? (int32_t)j : -(int32_t)(j - ni + 1);
+      }
+    });
+  }
+  uint64_t enc_max() const {
+    uint64_t k = 0;
+    for (int d = 0; d < dim; ++d) k = k * s1 + (s1 - 1);
+    return k;
   }
   uint64_t enc(const int32_t* c) const {
     uint64_t k = 0;
@@ -1319,8 +1336,8 @@ int build_transfer(const HostMesh& fine, const HostMesh& coarse, Transfer& t, st
   const int Lc = coarse.max_level;
   const int nc = 1 << dim;
   KeySet leaves((size_t)coarse.n_elems() * 2);
-  for (int64_t e = 0; e < coarse.n_elems(); ++e)
-    leaves.insert(leaf_key(dim, coarse.leaf_level[e], &coarse.leaf_anchor[3 * e]));
+  leaves.insert_parallel(coarse.n_elems(),
+                         [&](int64_t e) { return leaf_key(dim, coarse.leaf_level[e], &coarse.leaf_anchor[3 * e]); });
   NodeLookup cl(coarse), fl(fine);
   // prolongation rows: fine independent node <- coarse Q1 field at its position
   int rc = build_rows(
@@ -1557,8 +1574,8 @@ int build_interp(const HostMesh& src, const HostMesh& dst, std::vector<int32_t>&
   }
   try {
     KeySet leaves((size_t)src.n_elems() * 2);
-    for (int64_t e = 0; e < src.n_elems(); ++e)
-      leaves.insert(leaf_key(src.dim, src.leaf_level[e], &src.leaf_anchor[3 * e]));
+    leaves.insert_parallel(src.n_elems(),
+                           [&](int64_t e) { return leaf_key(src.dim, src.leaf_level[e], &src.leaf_anchor[3 * e]); });
     NodeLookup sl(src);
     return build_rows(
         dst.n_indep,
@@ -1612,7 +1629,7 @@ int build_grid_transfer(const HostMesh& m, int g, GridTransfer& t, std::string& 
     csr_transpose(ng, t.P_ptr, t.P_col, t.P_val, t.R_ptr, t.R_col, t.R_val);
     // Q: the mesh's Q1 field at every grid point
     KeySet leaves((size_t)m.n_elems() * 2);
-    for (int64_t e = 0; e < m.n_elems(); ++e) leaves.insert(leaf_key(m.dim, m.leaf_level[e], &m.leaf_anchor[3 * e]));
+    leaves.insert_parallel(m.n_elems(), [&](int64_t e) { return leaf_key(m.dim, m.leaf_level[e], &m.leaf_anchor[3 * e]); });
     NodeLookup sl(m);
     return build_rows(
         ng,
