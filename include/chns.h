@@ -306,7 +306,9 @@ int chns_solve_pressure(chns_ctx* ctx, const double* b, double* x, const chns_so
  *                        u^ = (3 u^k - u^{k-1})/2 (Sec. 3, Def. 3; the
  *                        mixture current J is built from grad mu~)
  *   CHNS_OP_CH_JACOBIAN: fields = {phi^{k+1} (Newton iterate), phi^k, u~}
- *                        (Def. 6)
+ *                        (Def. 6); the Jacobian reads the two phase fields
+ *                        only through their average, which the context
+ *                        stores in their place
  * EINVAL for any other op.                                                 */
 int chns_set_coefficients(chns_ctx* ctx, int op, const double* const* fields, void* stream);
 
