@@ -224,6 +224,9 @@ struct BrickArgs {
   const int32_t* anchor;  // 3 per brick, integer node coordinates
   int64_t sy, sz;         // index strides of y and z
   int32_t side;           // nodes per edge - 1
+  // table meshes, 3D 8^3 bricks: eight block bases per brick (base[0] < 0:
+  // use the table), from which the node numbers are computed
+  const int32_t* abase;
 };
 
 // -------------------------------------------------- CHNS element routines
@@ -784,12 +787,36 @@ __device__ __forceinline__ void brick_body(const BrickArgs<T>& a) {
     }
     base = DIM == 3 ? ax + ay * (int32_t)a.sy + az * (int32_t)a.sz : ax + ay * (int32_t)a.sy;
   }
+  // 8^3 bricks of a blocked node order whose numbers follow their 2x2x2
+  // point blocks: node (jx, jy, z) is the base of its block plus its
+  // lexicographic place in the block (the host checked this against the
+  // table); the brick is one wavefront, so the choice is uniform
+  int32_t ab[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  bool affine = false;
+  if constexpr (!STRUCT && DIM == 3 && B == 8) {
+    if (a.abase && active) {
+      const int32_t* q = a.abase + brick * 8;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) ab[i] = q[i];
+      affine = ab[0] >= 0;
+    }
+  }
+  auto affine_id = [&](int z, int p) -> int32_t {
+    const int jx = p % (B + 1), jy = p / (B + 1);
+    const bool zb = (z >> 3) != 0, yb = (jy >> 3) != 0, xb = (jx >> 3) != 0;
+    const int32_t b0 = zb ? ab[4] : ab[0], b1 = zb ? ab[5] : ab[1], b2 = zb ? ab[6] : ab[2], b3 = zb ? ab[7] : ab[3];
+    const int32_t bb = yb ? (xb ? b3 : b2) : (xb ? b1 : b0);
+    return bb + (jx & 7) + 8 * (jy & 7) + 64 * (z & 7);
+  };
   // index of layer-z node p (STRUCT) or its table entry
   auto entry = [&](int z, int p) -> int64_t {
     if constexpr (STRUCT) {
       const int jx = p % (B + 1), jy = DIM == 3 ? p / (B + 1) : 0;
       return DIM == 3 ? base + jx + jy * (int32_t)a.sy + z * (int32_t)a.sz : base + jx + z * (int32_t)a.sy;
     } else {
+      if constexpr (DIM == 3 && B == 8) {
+        if (affine) return affine_id(z, p);
+      }
       return tab[z * NL + p];
     }
   };
@@ -932,7 +959,7 @@ __device__ __forceinline__ void brick_body(const BrickArgs<T>& a) {
 #pragma unroll
       for (int k = 0; k < KL; ++k) {
         const int p = ll + k * LPB;
-        eo[k] = (active && p < NL) ? tab[z * NL + p] : 0;
+        eo[k] = (active && p < NL) ? entry(z, p) : 0;
       }
     }
   };
@@ -1360,6 +1387,7 @@ int launch_bricks(const DevMesh& dm, BrickArgs<T> a, hipStream_t s, int& part_of
     const DevBrickClass& bc = dm.cls[k];
     if (bc.count == 0) continue;
     a.table = bc.table;
+    a.abase = bc.abase;
     a.level = bc.level;
     a.rank = bc.rank;
     a.count = bc.count;

@@ -32,6 +32,7 @@ struct DevBrickClass {
   int8_t* level = nullptr;
   int16_t* rank = nullptr;  // npb entries
   int32_t* anchor = nullptr;  // 3 per brick (integer node coordinates)
+  int32_t* abase = nullptr;   // 8 per brick, or null (see BrickClass::abase)
 };
 
 struct DevMesh {

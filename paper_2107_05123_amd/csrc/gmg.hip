@@ -663,6 +663,7 @@ int upload_dm(Ctx& c, const HostMesh& m, DevMesh& d) {
     std::vector<int16_t> r(h.rank.begin(), h.rank.end());
     if ((rc = upload(c, &b.rank, r))) return rc;
     if ((rc = upload(c, &b.anchor, h.anchor))) return rc;
+    if (!h.abase.empty() && (rc = upload(c, &b.abase, h.abase))) return rc;
   }
   if ((rc = upload(c, &d.hang_par, m.hang_parents))) return rc;
   d.n_comb = (int64_t)m.comb_node.size();

@@ -834,6 +834,32 @@ struct Builder {
         }
       }
       });
+      // finest-level 8^3 bricks whose nodes are numbered block by block
+      // (every point of the blocks they touch is an independent node): node
+      // numbers from eight block bases, checked against the table
+      bc.abase.clear();
+      if (dim == 3 && B == 8 && m.node_order == 2) {
+        bc.abase.assign((size_t)bc.count * 8, -1);
+        parallel_chunks(bc.count, 1 << 10, [&](int64_t, int64_t k0, int64_t k1) {
+          for (int64_t k = k0; k < k1; ++k) {
+            if (bc.level[k] != L) continue;
+            const int32_t* t = &bc.table[(size_t)k * np];
+            int32_t base[8];
+            bool ok = true;
+            for (int q = 0; q < 8 && ok; ++q) {
+              base[q] = t[8 * (q & 1) + 9 * 8 * ((q >> 1) & 1) + 81 * 8 * ((q >> 2) & 1)];
+              ok = base[q] >= 0;
+            }
+            for (int p = 0; p < np && ok; ++p) {
+              const int jx = p % 9, jy = (p / 9) % 9, jz = p / 81;
+              const int q = (jx >> 3) | ((jy >> 3) << 1) | ((jz >> 3) << 2);
+              ok = t[p] == base[q] + (jx & 7) + 8 * (jy & 7) + 64 * (jz & 7);
+            }
+            if (ok)
+              for (int q = 0; q < 8; ++q) bc.abase[(size_t)k * 8 + q] = base[q];
+          }
+        });
+      }
     }
     int64_t base = 0;
     for (int c = 0; c < kBrickClasses; ++c) {

@@ -24,6 +24,12 @@ struct BrickClass {
   std::vector<int8_t> level;    // count
   std::vector<int32_t> anchor;  // count * 3 (integer lower corner)
   std::vector<int32_t> rank;    // nodes_per_brick: boundary rank or -1 (interior)
+  // 3D 8^3 bricks of a blocked node order: per brick the node numbers of the
+  // 2x2x2 aligned 8^3 point blocks it touches, such that its node at
+  // (jx, jy, jz) is base[(jx>>3) | (jy>>3)<<1 | (jz>>3)<<2] + (jx&7) +
+  // 8 (jy&7) + 64 (jz&7) for all 9^3 of them; base[0] = -1 where that does
+  // not hold (the table is used); empty for other classes
+  std::vector<int32_t> abase;   // count * 8
 };
 
 struct HostMesh {
