@@ -790,10 +790,14 @@ __device__ __forceinline__ void brick_body(const BrickArgs<T>& a) {
   // 8^3 bricks of a blocked node order whose numbers follow their 2x2x2
   // point blocks: node (jx, jy, z) is the base of its block plus its
   // lexicographic place in the block (the host checked this against the
-  // table); the brick is one wavefront, so the choice is uniform
+  // table); the brick is one wavefront, so the choice is uniform.  Used by
+  // the pressure and momentum forms only: in the others the extra registers
+  // cost more (spills under the four-wave cap, a wave less for the CH
+  // Jacobian) than the table loads they save
+  constexpr bool AFF = !STRUCT && DIM == 3 && B == 8 && (OP == K_PP || OP == K_VP);
   int32_t ab[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   bool affine = false;
-  if constexpr (!STRUCT && DIM == 3 && B == 8) {
+  if constexpr (AFF) {
     if (a.abase && active) {
       const int32_t* q = a.abase + brick * 8;
 #pragma unroll
@@ -814,7 +818,7 @@ __device__ __forceinline__ void brick_body(const BrickArgs<T>& a) {
       const int jx = p % (B + 1), jy = DIM == 3 ? p / (B + 1) : 0;
       return DIM == 3 ? base + jx + jy * (int32_t)a.sy + z * (int32_t)a.sz : base + jx + z * (int32_t)a.sy;
     } else {
-      if constexpr (DIM == 3 && B == 8) {
+      if constexpr (AFF) {
         if (affine) return affine_id(z, p);
       }
       return tab[z * NL + p];
