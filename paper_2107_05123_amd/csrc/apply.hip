@@ -1369,7 +1369,10 @@ template <int DIM, int B, typename T, int OP, bool STRUCT>
 void launch_one(int64_t grid, hipStream_t s, const BrickArgs<T>& a) {
   const dim3 g((unsigned)grid), blk(64);
   constexpr bool W = whole_fits<DIM, B, T, OP>();
-  if constexpr (OP == K_PP || OP == K_PPS || OP == K_VPS || OP == K_MASS)
+  // the scalar momentum form (viscous stiffness and density mass together)
+  // needs ~140 registers: capped at four waves it spilled (88 bytes per lane
+  // on table bricks), uncapped it runs three without
+  if constexpr (OP == K_PP || OP == K_PPS || OP == K_MASS)
     k_brick_o4<DIM, B, T, OP, W, STRUCT><<<g, blk, 0, s>>>(a);
   else if constexpr (OP == K_CH_JAC && DIM == 3 && B == 8 && STRUCT && sizeof(T) == 8)
     k_brick_o2<DIM, B, T, OP, W, STRUCT><<<g, blk, 0, s>>>(a);
