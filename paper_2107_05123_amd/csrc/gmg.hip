@@ -87,12 +87,14 @@ __global__ void k_resid(const T* r, T* t, int64_t n) {
 }
 // z = M r with a dense n x n row-major M
 template <typename T>
+__device__ __forceinline__ T dense_row(const T* M, const T* r, int i, int n) {
+  T acc = T(0);
+  for (int j = 0; j < n; ++j) acc += M[(int64_t)i * n + j] * r[j];
+  return acc;
+}
+template <typename T>
 __global__ void k_dense(const T* M, const T* r, T* z, int n) {
-  for (int i = blockIdx.x * kT + threadIdx.x; i < n; i += gridDim.x * kT) {
-    T acc = T(0);
-    for (int j = 0; j < n; ++j) acc += M[(int64_t)i * n + j] * r[j];
-    z[i] = acc;
-  }
+  for (int i = blockIdx.x * kT + threadIdx.x; i < n; i += gridDim.x * kT) z[i] = dense_row<T>(M, r, i, n);
 }
 // Structured transfers between uniform lexicographically numbered levels
 // (fine side nf = 2 nc nodes per edge minus one): the Q1 embedding has weight
@@ -558,70 +560,226 @@ __device__ __forceinline__ void node_ijk(int64_t node, int s, int& I, int& J, in
   J = (int)((node / s1) % s1);
   K = DIM == 3 ? (int)(node / (s1 * s1)) : 0;
 }
+// Per-node bodies of the stencil smoothers, shared by the per-level kernels
+// below and the fused coarse tail (the same arithmetic in both).
+// (A w D^-1 r)(i): the image of the first damped-Jacobi sweep from z = 0
+template <typename T, int DIM, typename ST>
+__device__ __forceinline__ T first_sweep_image(const ST* __restrict__ S, const T* __restrict__ dinv,
+                                               const T* __restrict__ r, T w, int64_t i, int s, int64_t n) {
+  const int64_t s1 = s + 1;
+  T az = T(0);
+#pragma unroll
+  for (int oz = (DIM == 3 ? -1 : 0); oz <= (DIM == 3 ? 1 : 0); ++oz) {
+#pragma unroll
+    for (int oy = -1; oy <= 1; ++oy) {
+#pragma unroll
+      for (int ox = -1; ox <= 1; ++ox) {
+        const int o = (ox + 1) + 3 * (oy + 1) + (DIM == 3 ? 9 * (oz + 1) : 0);
+        const int64_t j = nbr<DIM>(i, ox, oy, oz, s1, n);
+        az += (T)S[o * n + i] * (w * dinv[j] * r[j]);
+      }
+    }
+  }
+  return az;
+}
+// two sweeps from z = 0 at node i: z1 + w D^-1 (r - A z1) with z1 = w D^-1 r
+template <typename T, int DIM, typename ST>
+__device__ __forceinline__ T pre2_at(const ST* __restrict__ S, const T* __restrict__ dinv, const T* __restrict__ r,
+                                     T w, int64_t i, int s, int64_t n) {
+  const T az = first_sweep_image<T, DIM, ST>(S, dinv, r, w, i, s, n);
+  const T z1 = w * dinv[i] * r[i];
+  return z1 + w * dinv[i] * (r[i] - az);
+}
+// one sweep from zi at node i: zi + w D^-1 (r - A zi)
+template <typename T, int DIM, typename ST>
+__device__ __forceinline__ T sweep_at(const ST* __restrict__ S, const T* __restrict__ dinv, const T* __restrict__ r,
+                                      const T* __restrict__ zi, T w, int64_t i, int s, int64_t n) {
+  int I, J, K;
+  node_ijk<DIM>(i, s, I, J, K);
+  return zi[i] + w * dinv[i] * (r[i] - stencil_row<T, DIM, ST>(S, zi, i, n, I, J, K, s));
+}
+template <typename T, int DIM, typename ST>
+__device__ __forceinline__ T row_at(const ST* __restrict__ S, const T* __restrict__ z, int64_t i, int s, int64_t n) {
+  int I, J, K;
+  node_ijk<DIM>(i, s, I, J, K);
+  return stencil_row<T, DIM, ST>(S, z, i, n, I, J, K, s);
+}
 // two damped-Jacobi sweeps from z = 0: z1 = w D^-1 r, z2 = z1 + w D^-1 (r - A z1)
 template <typename T, int DIM, typename ST>
 __global__ void k_st_pre2(const ST* __restrict__ S, const T* __restrict__ dinv, const T* __restrict__ r,
                           T* __restrict__ z, T w, int s, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
-    const int64_t s1 = s + 1;
-    T az = T(0);
-#pragma unroll
-    for (int oz = (DIM == 3 ? -1 : 0); oz <= (DIM == 3 ? 1 : 0); ++oz) {
-#pragma unroll
-      for (int oy = -1; oy <= 1; ++oy) {
-#pragma unroll
-        for (int ox = -1; ox <= 1; ++ox) {
-          const int o = (ox + 1) + 3 * (oy + 1) + (DIM == 3 ? 9 * (oz + 1) : 0);
-          const int64_t j = nbr<DIM>(i, ox, oy, oz, s1, n);
-          az += (T)S[o * n + i] * (w * dinv[j] * r[j]);
-        }
-      }
-    }
-    const T z1 = w * dinv[i] * r[i];
-    z[i] = z1 + w * dinv[i] * (r[i] - az);
-  }
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
+    z[i] = pre2_at<T, DIM, ST>(S, dinv, r, w, i, s, n);
 }
 // one damped-Jacobi sweep from z = 0 and its image: z = w D^-1 r, t = A z
 template <typename T, int DIM, typename ST>
 __global__ void k_st_pre1(const ST* __restrict__ S, const T* __restrict__ dinv, const T* __restrict__ r,
                           T* __restrict__ z, T* __restrict__ t, T w, int s, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
-    const int64_t s1 = s + 1;
-    T az = T(0);
-#pragma unroll
-    for (int oz = (DIM == 3 ? -1 : 0); oz <= (DIM == 3 ? 1 : 0); ++oz) {
-#pragma unroll
-      for (int oy = -1; oy <= 1; ++oy) {
-#pragma unroll
-        for (int ox = -1; ox <= 1; ++ox) {
-          const int o = (ox + 1) + 3 * (oy + 1) + (DIM == 3 ? 9 * (oz + 1) : 0);
-          const int64_t j = nbr<DIM>(i, ox, oy, oz, s1, n);
-          az += (T)S[o * n + i] * (w * dinv[j] * r[j]);
-        }
-      }
-    }
     z[i] = w * dinv[i] * r[i];
-    t[i] = az;
+    t[i] = first_sweep_image<T, DIM, ST>(S, dinv, r, w, i, s, n);
   }
 }
 // zo = zi + w D^-1 (r - A zi)
 template <typename T, int DIM, typename ST>
 __global__ void k_st_sweep(const ST* __restrict__ S, const T* __restrict__ dinv, const T* __restrict__ r,
                            const T* __restrict__ zi, T* __restrict__ zo, T w, int s, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
-    int I, J, K;
-    node_ijk<DIM>(i, s, I, J, K);
-    zo[i] = zi[i] + w * dinv[i] * (r[i] - stencil_row<T, DIM, ST>(S, zi, i, n, I, J, K, s));
-  }
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
+    zo[i] = sweep_at<T, DIM, ST>(S, dinv, r, zi, w, i, s, n);
 }
 // t = A z
 template <typename T, int DIM, typename ST>
 __global__ void k_st_apply(const ST* __restrict__ S, const T* __restrict__ z, T* __restrict__ t, int s, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
-    int I, J, K;
-    node_ijk<DIM>(i, s, I, J, K);
-    t[i] = stencil_row<T, DIM, ST>(S, z, i, n, I, J, K, s);
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
+    t[i] = row_at<T, DIM, ST>(S, z, i, s, n);
+}
+
+// The coarse tail of the stencil V-cycle in one workgroup, held in LDS: the
+// levels at the bottom of the hierarchy (9^3 nodes and coarser in 3D) and
+// the dense coarsest level fit in one CU's 160 KiB of LDS together with
+// their stencils.  One launch stages the stencils, diagonals, coarsest
+// inverse and the first level's right-hand side into LDS, runs every phase
+// of the cycle from there down and back up (one loop over a level's nodes
+// per phase, a workgroup barrier between phases) and writes the first
+// level's correction back.  The per-level kernels above take one launch per
+// phase instead (ten for this part of the level-7 pressure cycle, each a few
+// microseconds of launch and memory latency over a few hundred nodes).
+// Same per-node arithmetic in the same order, so the same results.
+constexpr int kTailT = 1024;
+constexpr int kTailLevels = 8;
+constexpr int kTailLds = 160 * 1024;  // bytes
+template <typename T>
+struct TailLevel {
+  const float* S;  // global: stencil, diagonal, and for the first level the correction
+  const T* dinv;
+  T* z;
+  int side, n;
+  int oS, od, orr, oz, ot, oz2;  // byte offsets of the LDS copies
+};
+// one staged region: bytes (a multiple of 4) from global src to LDS offset
+// dst; chunk0 = its first 16-byte chunk in the staging order
+struct TailSeg {
+  const char* src;
+  int dst, bytes, chunk0;
+};
+constexpr int kTailSegs = 2 * kTailLevels + 2;
+constexpr int kTailU = 8;  // 16-byte chunks per thread per staging trip
+template <typename T>
+struct TailArgs {
+  TailSeg seg[kTailSegs];
+  int nseg, nchunk;
+  TailLevel<T> lv[kTailLevels];
+  int nl;        // stencil levels
+  const T* inv;  // coarsest level: dense inverse (global)
+  int sideK, nK;
+  int oinv, orK, ozK;
+  int nu;
+  T w;
+};
+template <typename T, int DIM>
+__global__ __launch_bounds__(kTailT) void k_vcycle_tail(const TailArgs<T> a) {
+  __shared__ double lds[kTailLds / sizeof(double)];
+  char* base = reinterpret_cast<char*>(lds);
+  const int tid = threadIdx.x;
+  constexpr int NS = DIM == 3 ? 27 : 9;
+  auto F = [&](int off) { return reinterpret_cast<float*>(base + off); };
+  auto V = [&](int off) { return reinterpret_cast<T*>(base + off); };
+  // staging: the whole 16-byte chunks of every region, kTailU per thread
+  // with all loads in flight before the stores, then the last 4-byte words
+  for (int c0 = tid; c0 < a.nchunk; c0 += kTailU * kTailT) {
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    v4i v[kTailU];
+    int dst[kTailU];
+#pragma unroll
+    for (int u = 0; u < kTailU; ++u) {
+      const int ch = c0 + u * kTailT;
+      dst[u] = -1;
+      if (ch < a.nchunk) {
+        int g = 0;  // the last region starting at or before chunk ch
+#pragma unroll
+        for (int q = 1; q < kTailSegs; ++q) g += (q < a.nseg && a.seg[q].chunk0 <= ch) ? 1 : 0;
+        const int k = ch - a.seg[g].chunk0;
+        v[u] = reinterpret_cast<const v4i*>(a.seg[g].src)[k];
+        dst[u] = a.seg[g].dst + 16 * k;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kTailU; ++u)
+      if (dst[u] >= 0) *reinterpret_cast<v4i*>(base + dst[u]) = v[u];
   }
+  for (int g = 0; g < a.nseg; ++g) {
+    const int whole = a.seg[g].bytes / 16 * 16;
+    if (tid < (a.seg[g].bytes - whole) / 4)
+      reinterpret_cast<int*>(base + a.seg[g].dst + whole)[tid] =
+          reinterpret_cast<const int*>(a.seg[g].src + whole)[tid];
+  }
+  __syncthreads();
+  for (int l = 0; l < a.nl; ++l) {
+    const TailLevel<T>& L = a.lv[l];
+    const float* S = F(L.oS);
+    const T* dinv = V(L.od);
+    const T* r = V(L.orr);
+    T* z = V(L.oz);
+    T* t = V(L.ot);
+    T* z2 = V(L.oz2);
+    const int64_t n = L.n;
+    if (a.nu == 1) {
+      for (int64_t i = tid; i < n; i += kTailT) {
+        z[i] = a.w * dinv[i] * r[i];
+        t[i] = first_sweep_image<T, DIM, float>(S, dinv, r, a.w, i, L.side, n);
+      }
+    } else {
+      for (int64_t i = tid; i < n; i += kTailT) z[i] = pre2_at<T, DIM, float>(S, dinv, r, a.w, i, L.side, n);
+      for (int it = 2; it < a.nu; ++it) {
+        __syncthreads();
+        for (int64_t i = tid; i < n; i += kTailT) z2[i] = sweep_at<T, DIM, float>(S, dinv, r, z, a.w, i, L.side, n);
+        __syncthreads();
+        for (int64_t i = tid; i < n; i += kTailT) z[i] = z2[i];
+      }
+      __syncthreads();
+      for (int64_t i = tid; i < n; i += kTailT) t[i] = row_at<T, DIM, float>(S, z, i, L.side, n);
+    }
+    __syncthreads();
+    const bool last = l + 1 == a.nl;
+    T* rc = V(last ? a.orK : a.lv[l + 1].orr);
+    const int sc = last ? a.sideK : a.lv[l + 1].side;
+    const int64_t nc = last ? a.nK : a.lv[l + 1].n;
+    for (int64_t c = tid; c < nc; c += kTailT) rc[c] = restrict_at<T, DIM>(r, t, c, sc);
+    __syncthreads();
+  }
+  {
+    const T* M = V(a.oinv);
+    const T* rK = V(a.orK);
+    T* zK = V(a.ozK);
+    for (int i = tid; i < a.nK; i += kTailT) zK[i] = dense_row<T>(M, rK, i, a.nK);
+  }
+  __syncthreads();
+  const bool odd = a.nu % 2 == 1;
+  for (int l = a.nl - 1; l >= 0; --l) {
+    const TailLevel<T>& L = a.lv[l];
+    const float* S = F(L.oS);
+    const T* dinv = V(L.od);
+    const T* r = V(L.orr);
+    T* z = V(L.oz);
+    const int64_t n = L.n;
+    const bool last = l + 1 == a.nl;
+    const T* zc = V(last ? a.ozK : a.lv[l + 1].oz);
+    const int sc = last ? a.sideK : a.lv[l + 1].side;
+    // for odd nu the prolongation writes to z2, so the sweeps end in z
+    T* cur = odd ? V(L.oz2) : z;
+    T* oth = odd ? z : V(L.oz2);
+    for (int64_t f = tid; f < n; f += kTailT) cur[f] = z[f] + prolong_at<T>(zc, f, sc, DIM);
+    for (int it = 0; it < a.nu; ++it) {
+      __syncthreads();
+      for (int64_t i = tid; i < n; i += kTailT) oth[i] = sweep_at<T, DIM, float>(S, dinv, r, cur, a.w, i, L.side, n);
+      T* x = cur;
+      cur = oth;
+      oth = x;
+    }
+    __syncthreads();
+  }
+  const T* z0 = V(a.lv[0].oz);
+  for (int i = tid; i < a.lv[0].n; i += kTailT) a.lv[0].z[i] = z0[i];
 }
 
 template <typename T>
@@ -761,15 +919,96 @@ void transfer(const Multigrid& mg, const int32_t* ptr, const int32_t* col, const
     k_spmv_g<T, T, L><<<g, kT, 0, s>>>(ptr, col, val, x, y, rows, yin);
 }
 
+// The rest of the cycle from stencil level k as one k_vcycle_tail launch,
+// when every level from k down is a lexicographic stencil level and all of
+// them fit in the tail's LDS (false: the per-level launches run instead).
+template <typename T>
+bool launch_tail(Ctx& c, int k, const T* r, T* z, hipStream_t s) {
+  using PR = Prec<T>;
+  Multigrid& mg = *c.mg;
+  const int K = (int)mg.lv.size() - 1;
+  if (k >= K || K - k > kTailLevels) return false;
+  auto lex = [](const DevMesh& d) {
+    const int64_t s1 = d.side + 1;
+    return d.n == (d.dim == 3 ? s1 * s1 * s1 : s1 * s1);
+  };
+  TailArgs<T> a{};
+  const int dim = mg.lv[k].dm.dim;
+  const int64_t ns = dim == 3 ? 27 : 9;
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) {
+    const int64_t o = off;
+    off += (bytes + 15) / 16 * 16;
+    return (int)std::min<int64_t>(o, kTailLds);
+  };
+  for (int j = k; j < K; ++j) {
+    MgLevel& L = mg.lv[j];
+    if (!L.S64 || !L.S32 || L.dm.dim != dim || !lex(L.dm) || mg.lv[j + 1].dm.side * 2 != L.dm.side ||
+        L.dm.n > kTailLds)
+      return false;
+    const int64_t n = L.dm.n;
+    TailLevel<T>& t = a.lv[j - k];
+    t.S = L.S32;
+    t.dinv = PR::dinv(L);
+    t.z = z;
+    t.side = L.dm.side;
+    t.n = (int)n;
+    t.oS = take(sizeof(float) * ns * n);
+    t.od = take(sizeof(T) * n);
+    t.orr = take(sizeof(T) * n);
+    t.oz = take(sizeof(T) * n);
+    t.ot = take(sizeof(T) * n);
+    t.oz2 = take(sizeof(T) * n);
+  }
+  MgLevel& B = mg.lv[K];
+  if (B.dm.dim != dim || !lex(B.dm) || B.dm.n > kTailLds) return false;
+  a.nl = K - k;
+  a.inv = PR::inv(B);
+  a.sideK = B.dm.side;
+  a.nK = (int)B.dm.n;
+  a.oinv = take(sizeof(T) * B.dm.n * B.dm.n);
+  a.orK = take(sizeof(T) * B.dm.n);
+  a.ozK = take(sizeof(T) * B.dm.n);
+  if (off > kTailLds) return false;
+  auto seg = [&](const void* src, int dst, int64_t bytes) {
+    TailSeg& g = a.seg[a.nseg++];
+    g.src = static_cast<const char*>(src);
+    g.dst = dst;
+    g.bytes = (int)bytes;
+    g.chunk0 = a.nchunk;
+    a.nchunk += (int)(bytes / 16);
+    return reinterpret_cast<uintptr_t>(src) % 16 == 0;
+  };
+  bool aligned = true;
+  for (int l = 0; l < a.nl; ++l) {
+    const TailLevel<T>& t = a.lv[l];
+    aligned &= seg(t.S, t.oS, sizeof(float) * ns * t.n);
+    aligned &= seg(t.dinv, t.od, sizeof(T) * t.n);
+  }
+  aligned &= seg(r, a.lv[0].orr, sizeof(T) * a.lv[0].n);
+  aligned &= seg(a.inv, a.oinv, sizeof(T) * a.nK * a.nK);
+  if (!aligned) return false;
+  a.nu = mg.nu;
+  a.w = (T)mg.omega;
+  if (dim == 3) k_vcycle_tail<T, 3><<<1, kTailT, 0, s>>>(a);
+  else k_vcycle_tail<T, 2><<<1, kTailT, 0, s>>>(a);
+  return true;
+}
+
 // V-cycle from a uniform coarse level k > 0 with an assembled stencil: the
 // same damped-Jacobi sweeps and transfers as the matrix-free levels, six
 // launches per level (two-sweep pre-smoothing, A z, restriction,
-// prolongation, two post-smoothing sweeps)
+// prolongation, two post-smoothing sweeps); the small levels at the bottom
+// run fused in one launch
 template <typename T>
 int vcycle_stencil(Ctx& c, int k, const T* r, T* z, hipStream_t s) {
   using PR = Prec<T>;
   Multigrid& mg = *c.mg;
   MgLevel& L = mg.lv[k];
+  if (launch_tail<T>(c, k, r, z, s)) {
+    CHNS_HIP(hipGetLastError());
+    return CHNS_OK;
+  }
   MgLevel& C = mg.lv[k + 1];
   const int64_t n = L.dm.n;
   const int side = L.dm.side, dim = L.dm.dim;
