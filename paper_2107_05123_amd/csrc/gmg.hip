@@ -264,6 +264,16 @@ __global__ __launch_bounds__(64) void k_el_rediscr(const double* __restrict__ ph
   }
 }
 
+// Order the LDS traffic between the lanes of a one-wave workgroup: a wave's
+// LDS operations complete in issue order, so fences at wavefront scope
+// around a compiler-level wave barrier suffice; unlike __syncthreads this
+// does not wait for the wave's global loads and stores still in flight.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Galerkin element matrices of a uniform level (sc cells per edge) straight
 // from the phase field of the uniform level above (sf = 2 sc).  One wave
 // handles kGalPerWave coarse elements; lane t keeps column t of H (the 64
@@ -287,7 +297,7 @@ __global__ __launch_bounds__(64) void k_gal_phi(const double* __restrict__ phi, 
                                                 const double* __restrict__ Gt, const double* __restrict__ Mq,
                                                 double fmscale, double* DP) {
   constexpr int NC = 1 << DIM, NE = NC * NC, NB = DIM == 3 ? 27 : 9;
-  __shared__ double cq[NE], cm[NE], hm[VARM ? NE * NE : 1], dd[NE];
+  __shared__ double cq[NE], cm[NE], hm[VARM ? NE * NE : 1], dd[NE], pv[kGalPerWave * NB];
   const int sc = sf / 2;
   const int64_t f1 = sf + 1;
   const int t = threadIdx.x;
@@ -298,11 +308,17 @@ __global__ __launch_bounds__(64) void k_gal_phi(const double* __restrict__ phi, 
   // Galerkin product (Q1 spaces are nested, 2-point Gauss is exact for it)
   const double m = t < NE ? mconst * Mt[t] : 0.0;
   if constexpr (VARM) {
-    for (int k = t; k < NE * NE; k += 64) hm[k] = Hm[k];
+    // eight loads in flight at a time
+    for (int k0 = 0; k0 < NE * NE; k0 += 8 * 64) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = k0 + 64 * u + t < NE * NE ? Hm[k0 + 64 * u + t] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (k0 + 64 * u + t < NE * NE) hm[k0 + 64 * u + t] = v[u];
+    }
   }
-  // lane t: child c = t / NC, Gauss point q = t % NC of that child; the
-  // child's corner phase values of the next element are loaded while the
-  // current one is reduced
+  // lane t: child c = t / NC, Gauss point q = t % NC of that child
   const int c = t / NC, q = t % NC;
   // diagonal tables of corner u = t % NC (lane t = (child, corner) in the
   // diagonal pass)
@@ -312,28 +328,14 @@ __global__ __launch_bounds__(64) void k_gal_phi(const double* __restrict__ phi, 
     gd[k] = t < NE ? Gt[k * NE + q * NC + q] : 0.0;
     md[k] = t < NE ? Mq[k * NE + q * NC + q] : 0.0;
   }
-  auto load = [&](int64_t e, double* ph) {
-    const int X = (int)(e % sc), Y = (int)((e / sc) % sc), Z = DIM == 3 ? (int)(e / ((int64_t)sc * sc)) : 0;
-    const int cx = 2 * X + (c & 1), cy = 2 * Y + ((c >> 1) & 1), cz = DIM == 3 ? 2 * Z + ((c >> 2) & 1) : 0;
-#pragma unroll
-    for (int b = 0; b < NC; ++b)
-      ph[b] = phi[((int64_t)(cz + ((b >> 2) & 1)) * f1 + (cy + ((b >> 1) & 1))) * f1 + (cx + (b & 1))];
-  };
-  const int64_t e0 = (int64_t)blockIdx.x * kGalPerWave;
-  const int64_t e1 = e0 + kGalPerWave < ne ? e0 + kGalPerWave : ne;
-  double nx[NC];
-  if (t < NE && e0 < e1) load(e0, nx);
-  for (int64_t e = e0; e < e1; ++e) {
-    double ph[NC];
-#pragma unroll
-    for (int b = 0; b < NC; ++b) ph[b] = nx[b];
-    if (t < NE && e + 1 < e1) load(e + 1, nx);
+  // one element with the phase values ph of its children's corners
+  auto element = [&](int64_t e, const double* ph) {
     if (t < NE) {
       const double v = phase_at(ph, q, DIM);
       cq[t] = cf.k(v);
       cm[t] = cf.m(v);
     }
-    __syncthreads();
+    wave_sync();
     if (t < NE) {
       // child c = t / NC, corner u = t % NC: that child's diagonal entry there
       double a = 0.0, b = 0.0;
@@ -344,7 +346,7 @@ __global__ __launch_bounds__(64) void k_gal_phi(const double* __restrict__ phi, 
       }
       dd[t] = scale * a + fmscale * b;
     }
-    __syncthreads();
+    wave_sync();
     if (t < NB) {
       // local fine node (i, j, k) in {0, 1, 2}^d: children and corners with
       // c_d + u_d = i_d (child c spans fine cells c_d .. c_d + 1), in a
@@ -375,7 +377,45 @@ __global__ __launch_bounds__(64) void k_gal_phi(const double* __restrict__ phi, 
         E[e * NE + t] = scale * acc + m;
       }
     }
-    __syncthreads();
+    wave_sync();
+  };
+  // the phase values at the 3^d fine nodes of each of the wave's elements,
+  // staged in LDS with all loads in flight at once; the element loop then
+  // issues no global loads (a register prefetch of the next element made the
+  // wave wait for its loads at once)
+  const int64_t e0 = (int64_t)blockIdx.x * kGalPerWave;
+  const int64_t e1 = e0 + kGalPerWave < ne ? e0 + kGalPerWave : ne;
+  const int nel = (int)(e1 - e0);
+  {
+    // sc = 2^ls (a uniform level): element coordinates by shifts
+    const int ls = __builtin_ctz((unsigned)sc);
+    double v[NB];
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+      const int idx = t + 64 * r;
+      v[r] = 0.0;
+      if (idx < nel * NB) {
+        const int64_t e = e0 + idx / NB;
+        const int nd = idx % NB;
+        const int X = (int)(e & (sc - 1)), Y = (int)((e >> ls) & (sc - 1)), Z = DIM == 3 ? (int)(e >> (2 * ls)) : 0;
+        const int lx = nd % 3, ly = (nd / 3) % 3, lz = DIM == 3 ? nd / 9 : 0;
+        v[r] = phi[((int64_t)(2 * Z + lz) * f1 + (2 * Y + ly)) * f1 + (2 * X + lx)];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NB; ++r)
+      if (t + 64 * r < nel * NB) pv[t + 64 * r] = v[r];
+  }
+  wave_sync();
+  for (int64_t e = e0; e < e1; ++e) {
+    // child c's corner b is fine node (c_d + b_d)_d of the element's 3^d
+    const double* pe = pv + (e - e0) * NB;
+    double ph[NC];
+#pragma unroll
+    for (int b = 0; b < NC; ++b)
+      ph[b] = pe[((c & 1) + (b & 1)) + 3 * (((c >> 1) & 1) + ((b >> 1) & 1)) +
+                 (DIM == 3 ? 9 * (((c >> 2) & 1) + ((b >> 2) & 1)) : 0)];
+    element(e, ph);
   }
 }
 
@@ -1382,6 +1422,11 @@ int mg_setup(Ctx& c, hipStream_t s) {
       const int64_t ncoarse = (int64_t)1 << (dim * (c.dm.max_level - 1));
       const unsigned gl = (unsigned)((ncoarse + kGalPerWave - 1) / kGalPerWave);
       const int sf = c.dm.side;
+      // k_gal_phi takes element coordinates by shifts: a power-of-two side
+      if (sf < 2 || (sf & (sf - 1)) != 0 || ncoarse != std::pow((double)(sf / 2), dim)) {
+        set_error("multigrid: uniform fine level with a side that is not a power of two");
+        return CHNS_EINVAL;
+      }
       const double mc = cf.mb * mscale(sf / 2);
       const double fm = mscale(sf);
       if (dim == 3) {
