@@ -883,8 +883,11 @@ LevelView view(MgLevel& L) { return LevelView{&L.dm, L.phi64, L.phi32, L.slots};
 int dense_inverse(std::vector<double>& A, int n, bool regularise) {
   double scale = 0.0;
   for (int i = 0; i < n; ++i) scale = std::max(scale, A[(size_t)i * n + i]);
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) A[(size_t)i * n + j] = 0.5 * (A[(size_t)i * n + j] + A[(size_t)j * n + i]);
+  {
+    const std::vector<double> A0(A);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) A[(size_t)i * n + j] = 0.5 * (A0[(size_t)i * n + j] + A0[(size_t)j * n + i]);
+  }
   if (regularise)
     for (int i = 0; i < n; ++i)
       for (int j = 0; j < n; ++j) A[(size_t)i * n + j] += scale / n;
@@ -917,6 +920,67 @@ int dense_inverse(std::vector<double>& A, int n, bool regularise) {
   }
   A.swap(inv);
   return CHNS_OK;
+}
+
+// The same inverse on the device for a coarsest level of at most
+// kDenseDev nodes, in one wave: the host routine's steps in its order with
+// fused multiply-adds off (division and square root are correctly rounded),
+// so the inverse is the host's bit for bit without the round trip through
+// host memory.  Cholesky: column by column, lane i forms the entry of row i;
+// inverse: lane j forms column j by forward and back substitution.  A
+// non-positive pivot makes the inverse NaN, and a solve that uses it stops
+// on its non-finite residual.
+constexpr int kDenseDev = 64;
+__global__ __launch_bounds__(64) void k_dense_inverse(const double* __restrict__ A0, double* __restrict__ inv64,
+                                                      float* __restrict__ inv32, int n, int regularise) {
+#pragma clang fp contract(off)
+  __shared__ double A[kDenseDev * kDenseDev], Lc[kDenseDev * kDenseDev], Y[kDenseDev * kDenseDev];
+  const int t = threadIdx.x;
+  double scale = 0.0;
+  for (int i = 0; i < n; ++i) scale = scale < A0[i * n + i] ? A0[i * n + i] : scale;
+  for (int q = t; q < n * n; q += 64) {
+    const int i = q / n, j = q % n;
+    double a = 0.5 * (A0[i * n + j] + A0[j * n + i]);
+    if (regularise) a += scale / n;
+    A[q] = a;
+    Lc[q] = 0.0;
+  }
+  wave_sync();
+  bool bad = false;
+  for (int j = 0; j < n; ++j) {
+    double d = A[j * n + j];
+    for (int k = 0; k < j; ++k) d -= Lc[j * n + k] * Lc[j * n + k];
+    bad = bad || !(d > 0.0);
+    d = sqrt(d);
+    if (t == 0) Lc[j * n + j] = d;
+    if (t > j && t < n) {
+      double v = A[t * n + j];
+      for (int k = 0; k < j; ++k) v -= Lc[t * n + k] * Lc[j * n + k];
+      Lc[t * n + j] = v / d;
+    }
+    wave_sync();
+  }
+  if (t < n) {
+    const int j = t;
+    for (int i = 0; i < n; ++i) {
+      double v = (i == j) ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) v -= Lc[i * n + k] * Y[k * kDenseDev + j];
+      Y[i * kDenseDev + j] = v / Lc[i * n + i];
+    }
+    // column j of the inverse into A (row i at A[i * kDenseDev + j])
+    for (int i = n - 1; i >= 0; --i) {
+      double v = Y[i * kDenseDev + j];
+      for (int k = i + 1; k < n; ++k) v -= Lc[k * n + i] * A[k * kDenseDev + j];
+      A[i * kDenseDev + j] = v / Lc[i * n + i];
+    }
+  }
+  wave_sync();
+  for (int q = t; q < n * n; q += 64) {
+    const int i = q / n, j = q % n;
+    const double v = bad ? __builtin_nan("") : A[i * kDenseDev + j];
+    inv64[q] = v;
+    inv32[q] = (float)v;
+  }
 }
 
 template <typename T>
@@ -1540,17 +1604,22 @@ int mg_setup(Ctx& c, hipStream_t s) {
     }
   }
   if ((rc = run_captured(c, exec, s, device_part))) return rc;
-  std::vector<double> A((size_t)n * n);
-  CHNS_HIP(hipMemcpyAsync(A.data(), B.dense, sizeof(double) * A.size(), hipMemcpyDeviceToHost, s));
-  CHNS_HIP(hipStreamSynchronize(s));
   // a shifted operator or one with a mass term is definite: no rank-one
   // regularisation
-  if ((rc = dense_inverse(A, n, c.pp_shift == 0.0 && c.pp_kind == 0))) {
-    set_error("coarsest multigrid operator is not positive semi-definite");
-    return rc;
+  const bool regularise = c.pp_shift == 0.0 && c.pp_kind == 0;
+  if (n <= kDenseDev) {
+    k_dense_inverse<<<1, 64, 0, s>>>(B.dense, B.inv64, B.inv32, n, regularise ? 1 : 0);
+  } else {
+    std::vector<double> A((size_t)n * n);
+    CHNS_HIP(hipMemcpyAsync(A.data(), B.dense, sizeof(double) * A.size(), hipMemcpyDeviceToHost, s));
+    CHNS_HIP(hipStreamSynchronize(s));
+    if ((rc = dense_inverse(A, n, regularise))) {
+      set_error("coarsest multigrid operator is not positive semi-definite");
+      return rc;
+    }
+    CHNS_HIP(hipMemcpy(B.inv64, A.data(), sizeof(double) * A.size(), hipMemcpyHostToDevice));
+    k_to32<<<blocks((int64_t)n * n), kT, 0, s>>>(B.inv64, B.inv32, (int64_t)n * n);
   }
-  CHNS_HIP(hipMemcpy(B.inv64, A.data(), sizeof(double) * A.size(), hipMemcpyHostToDevice));
-  k_to32<<<blocks((int64_t)n * n), kT, 0, s>>>(B.inv64, B.inv32, (int64_t)n * n);
   CHNS_HIP(hipGetLastError());
   mg.setup_valid = true;
   return CHNS_OK;
